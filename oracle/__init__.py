@@ -1,0 +1,313 @@
+"""Python view of the CPU FP64 oracle (oracle/orc.c).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package.  It shares no code with the GPU
+library and never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# CAMG_ORACLE_LIB lets the mutation tests load a deliberately broken build
+_LIBPATH = os.environ.get("CAMG_ORACLE_LIB") or os.path.join(HERE, "liborc.so")
+_lib = None
+
+OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -2, -3, -4, -5, -6
+F, U, CPT = -1, 0, 1
+X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS = range(10)
+
+
+class Params(C.Structure):
+    _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("omega", C.c_double), ("max_levels", C.c_int32),
+                ("max_coarse", C.c_int32), ("max_iter", C.c_int32)]
+
+
+class CsrOut(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("rp", C.POINTER(C.c_int32)),
+                ("ci", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIBPATH)
+        vp = C.c_void_p
+        i32, u64, dbl = C.c_int32, C.c_uint64, C.c_double
+        L.orc_params_default.argtypes = [C.POINTER(Params)]
+        L.orc_validate.argtypes = [i32, vp, vp, vp]
+        L.orc_strength.argtypes = [i32, vp, vp, vp, dbl, vp, vp]
+        L.orc_splitmix64.argtypes = [u64, u64]; L.orc_splitmix64.restype = u64
+        L.orc_pmis_rand.argtypes = [u64, i32, i32]; L.orc_pmis_rand.restype = u64
+        L.orc_pmis.argtypes = [i32, vp, vp, vp, vp, u64, i32, vp, vp]
+        L.orc_interp_direct.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(CsrOut)]
+        L.orc_transpose.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
+        L.orc_spgemm.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.POINTER(CsrOut)]
+        L.orc_cholesky.argtypes = [i32, vp]
+        L.orc_chol_solve.argtypes = [i32, vp, vp, vp]
+        L.orc_gershgorin_omega.argtypes = [i32, vp, vp, vp]; L.orc_gershgorin_omega.restype = dbl
+        L.orc_csr_free.argtypes = [C.POINTER(CsrOut)]
+        L.orc_setup.argtypes = [i32, vp, vp, vp, C.POINTER(Params), C.POINTER(vp)]
+        L.orc_num_levels.argtypes = [vp]
+        L.orc_level_sizes.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.orc_export.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.orc_vcycle.argtypes = [vp, vp, vp]
+        L.orc_solve.argtypes = [vp, vp, dbl, i32, i32, vp, vp, vp, i32, vp]
+        L.orc_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _csr_arrays(A):
+    """Accept problems.CSR, a (nrows, ncols, rp, ci, val) tuple, or a scipy CSR matrix."""
+    if hasattr(A, "row_ptr"):
+        return A.n, A.n, A.row_ptr, A.col_idx, A.val
+    if hasattr(A, "indptr"):
+        return A.shape[0], A.shape[1], A.indptr, A.indices, A.data
+    nr, nc, rp, ci, v = A
+    return nr, nc, rp, ci, v
+
+
+def _to_out(n, nc, rp, ci, v):
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    o = CsrOut(n, nc, rp.ctypes.data_as(C.POINTER(C.c_int32)), ci.ctypes.data_as(C.POINTER(C.c_int32)),
+               v.ctypes.data_as(C.POINTER(C.c_double)))
+    return o, (rp, ci, v)
+
+
+def _from_out(o):
+    nnz = o.rp[o.nrows] if o.nrows > 0 else 0
+    rp = np.ctypeslib.as_array(o.rp, shape=(o.nrows + 1,)).copy()
+    ci = np.ctypeslib.as_array(o.ci, shape=(max(nnz, 1),))[:nnz].copy() if nnz else np.zeros(0, np.int32)
+    v = np.ctypeslib.as_array(o.val, shape=(max(nnz, 1),))[:nnz].copy() if nnz else np.zeros(0)
+    res = (int(o.nrows), int(o.ncols), rp, ci, v)
+    lib().orc_csr_free(C.byref(o))
+    return res
+
+
+def params(**kw) -> Params:
+    p = Params()
+    lib().orc_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def validate(A) -> int:
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    return lib().orc_validate(n, _p(rp), _p(ci), _p(v))
+
+
+def strength(A, theta=0.25):
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    s = np.zeros(len(ci), np.uint8)
+    cnt = np.zeros(n, np.int32)
+    lib().orc_strength(n, _p(rp), _p(ci), _p(v), theta, _p(s), _p(cnt))
+    return s, cnt
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    return int(lib().orc_splitmix64(seed, counter))
+
+
+def pmis_rand(seed: int, level: int, i: int) -> int:
+    return int(lib().orc_pmis_rand(seed, level, i))
+
+
+def pmis(A, strong, st_count, seed=0, level=0):
+    n, _, rp, ci, _ = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    strong = np.ascontiguousarray(strong, np.uint8); st_count = np.ascontiguousarray(st_count, np.int32)
+    cf = np.zeros(n, np.int8)
+    rounds = np.zeros(1, np.int32)
+    st = lib().orc_pmis(n, _p(rp), _p(ci), _p(strong), _p(st_count), seed, level, _p(cf), _p(rounds))
+    assert st == OK
+    return cf, int(rounds[0])
+
+
+def interp_direct(A, strong, cf):
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    strong = np.ascontiguousarray(strong, np.uint8); cf = np.ascontiguousarray(cf, np.int8)
+    o = CsrOut()
+    st = lib().orc_interp_direct(n, _p(rp), _p(ci), _p(v), _p(strong), _p(cf), C.byref(o))
+    assert st == OK
+    return _from_out(o)
+
+
+def transpose(X):
+    o, keep = _to_out(*_csr_arrays(X))
+    r = CsrOut()
+    assert lib().orc_transpose(C.byref(o), C.byref(r)) == OK
+    return _from_out(r)
+
+
+def spgemm(X, Y):
+    ox, kx = _to_out(*_csr_arrays(X))
+    oy, ky = _to_out(*_csr_arrays(Y))
+    r = CsrOut()
+    assert lib().orc_spgemm(C.byref(ox), C.byref(oy), C.byref(r)) == OK
+    return _from_out(r)
+
+
+def galerkin(A, P):
+    """A_c = P^T (A P) as the oracle forms it."""
+    R = transpose(P)
+    AP = spgemm(A, P)
+    return spgemm(R, AP)
+
+
+def cholesky(a: np.ndarray):
+    a = np.array(a, dtype=np.float64, order="C", copy=True)
+    st = lib().orc_cholesky(a.shape[0], _p(a))
+    return st, a
+
+
+def chol_solve(L: np.ndarray, y: np.ndarray) -> np.ndarray:
+    L = np.ascontiguousarray(L, np.float64); y = np.ascontiguousarray(y, np.float64)
+    z = np.zeros_like(y)
+    lib().orc_chol_solve(L.shape[0], _p(L), _p(y), _p(z))
+    return z
+
+
+def gershgorin_omega(A) -> float:
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    return float(lib().orc_gershgorin_omega(n, _p(rp), _p(ci), _p(v)))
+
+
+class Hierarchy:
+    """Oracle AMG hierarchy (setup) plus V-cycle and PCG."""
+
+    def __init__(self, A, **kw):
+        n, _, rp, ci, v = _csr_arrays(A)
+        self._keep = (np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+                      np.ascontiguousarray(v, np.float64))
+        self.n = n
+        self.params = params(**kw)
+        h = C.c_void_p()
+        st = lib().orc_setup(n, _p(self._keep[0]), _p(self._keep[1]), _p(self._keep[2]),
+                             C.byref(self.params), C.byref(h))
+        self.status = st
+        self.h = h if st == OK else None
+        if st != OK:
+            raise OracleError(st)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    @property
+    def nlev(self) -> int:
+        return lib().orc_num_levels(self.h)
+
+    def sizes(self, l):
+        a = [np.zeros(1, np.int32) for _ in range(4)]
+        assert lib().orc_level_sizes(self.h, l, *[_p(x) for x in a]) == OK
+        return tuple(int(x[0]) for x in a)  # n, nnzA, nnzP, nc
+
+    def A(self, l):
+        n, nnz, _, _ = self.sizes(l)
+        rp = np.zeros(n + 1, np.int32); ci = np.zeros(nnz, np.int32); v = np.zeros(nnz)
+        assert lib().orc_export(self.h, l, X_A, _p(rp), _p(ci), _p(v)) == OK
+        return (n, n, rp, ci, v)
+
+    def _pr(self, l, what):
+        n, _, nnzp, nc = self.sizes(l)
+        rows = n if what == X_P else nc
+        cols = nc if what == X_P else n
+        rp = np.zeros(rows + 1, np.int32); ci = np.zeros(nnzp, np.int32); v = np.zeros(nnzp)
+        assert lib().orc_export(self.h, l, what, _p(rp), _p(ci), _p(v)) == OK
+        return (rows, cols, rp, ci, v)
+
+    def P(self, l):
+        return self._pr(l, X_P)
+
+    def R(self, l):
+        return self._pr(l, X_R)
+
+    def cf(self, l):
+        n = self.sizes(l)[0]
+        a = np.zeros(n, np.int8)
+        assert lib().orc_export(self.h, l, X_CF, _p(a), None, None) == OK
+        return a
+
+    def strong(self, l):
+        nnz = self.sizes(l)[1]
+        a = np.zeros(nnz, np.uint8)
+        assert lib().orc_export(self.h, l, X_STRONG, _p(a), None, None) == OK
+        return a
+
+    def dinv(self, l):
+        a = np.zeros(self.sizes(l)[0])
+        assert lib().orc_export(self.h, l, X_DINV, _p(a), None, None) == OK
+        return a
+
+    def omega(self, l):
+        a = np.zeros(1)
+        assert lib().orc_export(self.h, l, X_OMEGA, _p(a), None, None) == OK
+        return float(a[0])
+
+    def chol(self):
+        l = self.nlev - 1
+        n = self.sizes(l)[0]
+        a = np.zeros((n, n))
+        assert lib().orc_export(self.h, l, X_CHOL, _p(a), None, None) == OK
+        return a
+
+    def vcycle(self, y):
+        y = np.ascontiguousarray(y, np.float64)
+        z = np.zeros_like(y)
+        lib().orc_vcycle(self.h, _p(y), _p(z))
+        return z
+
+    def solve(self, b, rtol=1e-8, max_iter=None, precond=True):
+        b = np.ascontiguousarray(b, np.float64)
+        mi = self.params.max_iter if max_iter is None else max_iter
+        x = np.zeros_like(b)
+        it = np.zeros(1, np.int32)
+        hist = np.zeros(mi + 1)
+        rel = np.zeros(1)
+        st = lib().orc_solve(self.h, _p(b), rtol, mi, 1 if precond else 0, _p(x), _p(it), _p(hist),
+                             mi + 1, _p(rel))
+        k = int(it[0])
+        return SolveResult(st, x, k, hist[:k + 1].copy(), float(rel[0]))
+
+    def complexities(self):
+        ns = [self.sizes(l)[0] for l in range(self.nlev)]
+        nz = [self.sizes(l)[1] for l in range(self.nlev)]
+        return sum(ns) / ns[0], sum(nz) / nz[0]
+
+
+class SolveResult:
+    def __init__(self, status, x, iters, hist, true_relres):
+        self.status, self.x, self.iters, self.hist, self.true_relres = status, x, iters, hist, true_relres
+
+    def __repr__(self):
+        return f"SolveResult(status={self.status}, iters={self.iters}, true_relres={self.true_relres:.3e})"
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__(f"oracle status {status}")
+        self.status = status

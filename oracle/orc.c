@@ -1,0 +1,703 @@
+/*
+ * Plain CPU FP64 oracle for classical-AMG-preconditioned CG.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the GPU library.  Written from
+ * the paper "Chronos: a general purpose classical AMG solver for High
+ * Performance Computing" (Isotton, Frigo, Spiezia, Janna; arXiv 2102.07417)
+ * and the textbook definitions it cites.  Readings of passages the paper
+ * leaves open are stated beside the code that takes them.
+ *
+ * Every loop runs in the plain index order written here; the file is built
+ * with -ffp-contract=off so a*b+c is a rounded multiply then a rounded add.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+void orc_free(void *p) { free(p); }
+
+void orc_csr_free(orc_csr *m) {
+    if (!m) return;
+    free(m->rp); free(m->ci); free(m->val);
+    m->rp = NULL; m->ci = NULL; m->val = NULL;
+    m->nrows = m->ncols = 0;
+}
+
+void orc_params_default(orc_params *p) {
+    p->theta = 0.25;
+    p->seed = 0;
+    p->nu_pre = 1;
+    p->nu_post = 1;
+    p->omega = 0.0;
+    p->max_levels = 25;
+    p->max_coarse = 256;
+    p->max_iter = 1000;
+}
+
+/* Position of column j in row i, or -1 (rows are sorted). */
+static int32_t find_in_row(const int32_t *rp, const int32_t *ci, int32_t i, int32_t j) {
+    int32_t lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo <= hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (ci[mid] == j) return mid;
+        if (ci[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/*
+ * Input check.  The paper's problem is A x = b with A sparse SPD
+ * (Section 1, eq. linSys), stored in CSR (Section 3, CSRMAT).  Checks, in
+ * this order: row pointer shape, column range and strict ordering, finite
+ * values, diagonal present, structural and numerical symmetry
+ * (|a_ij - a_ji| <= 1e-12 max|a|), positive diagonal.
+ */
+int orc_validate(int32_t n, const int32_t *rp, const int32_t *ci, const double *v) {
+    if (n < 1 || !rp || !ci || !v) return ORC_E_ARG;
+    if (rp[0] != 0) return ORC_E_CSR;
+    for (int32_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return ORC_E_CSR;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (ci[e] < 0 || ci[e] >= n) return ORC_E_CSR;
+            if (e > rp[i] && ci[e] <= ci[e - 1]) return ORC_E_CSR;
+        }
+    double amax = 0.0;
+    for (int32_t e = 0; e < rp[n]; ++e) {
+        if (!isfinite(v[e])) return ORC_E_CSR;
+        if (fabs(v[e]) > amax) amax = fabs(v[e]);
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (find_in_row(rp, ci, i, i) < 0) return ORC_E_CSR;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int32_t j = ci[e];
+            int32_t t = find_in_row(rp, ci, j, i);
+            if (t < 0) return ORC_E_CSR;
+            if (fabs(v[e] - v[t]) > 1e-12 * amax) return ORC_E_CSR;
+        }
+    for (int32_t i = 0; i < n; ++i)
+        if (!(v[find_in_row(rp, ci, i, i)] > 0.0)) return ORC_E_NOT_SPD;
+    return ORC_OK;
+}
+
+/*
+ * Classical strength of connection (Section 2, Strength of Connection,
+ * eq. cla) filtered by a threshold theta.  The printed formula is garbled
+ * (its denominator is a minimum of raw entries and is negative for an
+ * M-matrix); the reading taken is the Ruge-Stueben measure it stands for:
+ *   m_i = max_{k != i} (-a_ik),
+ *   j in S_i  <=>  j != i, m_i > 0 and -a_ij >= theta * m_i.
+ * theta * m_i is one rounded product; the test is a comparison, not a
+ * division.  A row with no negative off-diagonal has no strong connection.
+ * strong[e] flags entry e of A (aligned with col_idx); st_count[j] = |S_j^T|,
+ * the number of rows that depend strongly on j.
+ */
+void orc_strength(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                  double theta, uint8_t *strong, int32_t *st_count) {
+    for (int32_t i = 0; i < n; ++i) st_count[i] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int have = 0;
+        double m = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (ci[e] == i) continue;
+            double neg = -v[e];
+            if (!have || neg > m) { m = neg; have = 1; }
+        }
+        double thr = theta * m;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int s = 0;
+            if (ci[e] != i && have && m > 0.0 && -v[e] >= thr) s = 1;
+            strong[e] = (uint8_t)s;
+            if (s) st_count[ci[e]] += 1;
+        }
+    }
+}
+
+/*
+ * splitmix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the generator's state advances by the golden
+ * gamma 0x9E3779B97F4A7C15 per draw and each output is the state passed
+ * through the variant-13 finaliser.  orc_splitmix64(seed, c) is draw number
+ * c (from 0) of a generator seeded with `seed`.
+ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t counter) {
+    uint64_t z = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* The random part of the PMIS measure of point i on level l: the top 53 bits
+ * of draw ((l << 40) + i). */
+uint64_t orc_pmis_rand(uint64_t seed, int32_t level, int32_t i) {
+    uint64_t c = ((uint64_t)(uint32_t)level << 40) + (uint64_t)(uint32_t)i;
+    return orc_splitmix64(seed, c) >> 11;
+}
+
+/* key(a) > key(b) for the PMIS measure (|S^T|, random, index) compared
+ * lexicographically. */
+static int key_greater(const int32_t *cnt, const uint64_t *u, int32_t a, int32_t b) {
+    if (cnt[a] != cnt[b]) return cnt[a] > cnt[b];
+    if (u[a] != u[b]) return u[a] > u[b];
+    return a > b;
+}
+
+/*
+ * PMIS coarsening (Section 2, Strength of Connection, last paragraph; the
+ * algorithm is the one of De Sterck, Yang and Heys, which the paper cites
+ * but does not print).  Measure of i: |S_i^T| plus a random number in
+ * [0, 1); here the tuple (|S_i^T|, 53-bit random, i) compared as integers,
+ * which orders points the same way with a deterministic tie break.
+ *   - points with |S_i^T| = 0 start as F, the rest undecided (U);
+ *   - each round, every undecided i whose measure beats that of every
+ *     undecided j in S_i u S_i^T becomes C (all selections of a round are
+ *     made against the round's starting state);
+ *   - then every undecided point that depends strongly on a new C point
+ *     becomes F;
+ *   - rounds repeat until no point is undecided.
+ * cf[i] is ORC_C or ORC_F on return.
+ */
+int orc_pmis(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+             const int32_t *st_count, uint64_t seed, int32_t level, int8_t *cf, int32_t *rounds) {
+    uint64_t *u = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    int8_t *newc = (int8_t *)malloc((size_t)n);
+    int8_t *next = (int8_t *)malloc((size_t)n);
+    if (!u || !newc || !next) { free(u); free(newc); free(next); return ORC_E_NOMEM; }
+    int32_t und = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        u[i] = orc_pmis_rand(seed, level, i);
+        cf[i] = (st_count[i] == 0) ? ORC_F : ORC_U;
+        if (cf[i] == ORC_U) ++und;
+    }
+    int32_t r = 0;
+    while (und > 0) {
+        ++r;
+        for (int32_t i = 0; i < n; ++i) {
+            newc[i] = 0;
+            if (cf[i] != ORC_U) continue;
+            int sel = 1;
+            for (int32_t e = rp[i]; e < rp[i + 1] && sel; ++e) {
+                int32_t j = ci[e];
+                if (j == i || cf[j] != ORC_U) continue;
+                int32_t t = find_in_row(rp, ci, j, i);
+                int sym = strong[e] || (t >= 0 && strong[t]);
+                if (sym && key_greater(st_count, u, j, i)) sel = 0;
+            }
+            newc[i] = (int8_t)sel;
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            next[i] = cf[i];
+            if (cf[i] != ORC_U) continue;
+            if (newc[i]) { next[i] = ORC_C; continue; }
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (strong[e] && newc[ci[e]]) { next[i] = ORC_F; break; }
+        }
+        und = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            cf[i] = next[i];
+            if (cf[i] == ORC_U) ++und;
+        }
+    }
+    if (rounds) *rounds = r;
+    free(u); free(newc); free(next);
+    return ORC_OK;
+}
+
+/*
+ * Direct (distance-one) interpolation, P = [W; I] in the paper's F/C block
+ * form (Section 2, eq. prolOperator), kept in the original ordering
+ * (the F/C reordering of eq. blk_FC is notational).  Coarse index of a C
+ * point: the number of C points before it.
+ *   C row i: a single 1 in column cmap(i).
+ *   F row i, C_i^S = S_i n C (neighbour sets of Section 2, Interpolation):
+ *     d_i     = a_ii + sum of the positive off-diagonals of row i
+ *               (positive couplings are never strong, so they are lumped),
+ *     alpha_i = (sum of the negative off-diagonals) / (sum_{j in C_i^S} a_ij),
+ *     w_ij    = -(alpha_i a_ij) / d_i  for j in C_i^S.
+ *   This is the direct formula of the multigrid literature the paper cites
+ *   (Stueben; Trottenberg, Oosterlee, Schueller).  An F row with no strong
+ *   C neighbour is empty.  Sums run in CSR order, d_i starting from a_ii.
+ */
+int orc_interp_direct(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                      const uint8_t *strong, const int8_t *cf, orc_csr *P) {
+    int32_t *cmap = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!cmap) return ORC_E_NOMEM;
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i) { cmap[i] = nc; if (cf[i] == ORC_C) ++nc; }
+    int32_t *prp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    if (!prp) { free(cmap); return ORC_E_NOMEM; }
+    prp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t c = 0;
+        if (cf[i] == ORC_C) c = 1;
+        else
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (strong[e] && cf[ci[e]] == ORC_C) ++c;
+        prp[i + 1] = prp[i] + c;
+    }
+    int32_t nnz = prp[n];
+    int32_t *pci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *pv = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!pci || !pv) { free(cmap); free(prp); free(pci); free(pv); return ORC_E_NOMEM; }
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t o = prp[i];
+        if (cf[i] == ORC_C) { pci[o] = cmap[i]; pv[o] = 1.0; continue; }
+        if (prp[i + 1] == o) continue;
+        double d = 0.0, num = 0.0, den = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] == i) d = v[e];
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (ci[e] == i) continue;
+            if (v[e] > 0.0) d = d + v[e];
+            else if (v[e] < 0.0) num = num + v[e];
+        }
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (strong[e] && cf[ci[e]] == ORC_C) den = den + v[e];
+        double alpha = num / den;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (strong[e] && cf[ci[e]] == ORC_C) {
+                pci[o] = cmap[ci[e]];
+                pv[o] = -(alpha * v[e]) / d;
+                ++o;
+            }
+    }
+    free(cmap);
+    P->nrows = n; P->ncols = nc; P->rp = prp; P->ci = pci; P->val = pv;
+    return ORC_OK;
+}
+
+/* X^T by counting sort on the column index; rows of the result list their
+ * columns in ascending order.  The restriction is R = P^T (eq. AcDef). */
+int orc_transpose(const orc_csr *X, orc_csr *XT) {
+    int32_t m = X->nrows, nc = X->ncols, nnz = X->rp[m];
+    int32_t *rp = (int32_t *)calloc((size_t)nc + 1, sizeof(int32_t));
+    int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc + 1));
+    if (!rp || !ci || !val || !fill) { free(rp); free(ci); free(val); free(fill); return ORC_E_NOMEM; }
+    for (int32_t e = 0; e < nnz; ++e) rp[X->ci[e] + 1] += 1;
+    for (int32_t c = 0; c < nc; ++c) rp[c + 1] += rp[c];
+    for (int32_t c = 0; c <= nc; ++c) fill[c] = rp[c];
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t e = X->rp[i]; e < X->rp[i + 1]; ++e) {
+            int32_t c = X->ci[e];
+            ci[fill[c]] = i;
+            val[fill[c]] = X->val[e];
+            fill[c] += 1;
+        }
+    free(fill);
+    XT->nrows = nc; XT->ncols = m; XT->rp = rp; XT->ci = ci; XT->val = val;
+    return ORC_OK;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Z = X Y, row by row with a dense accumulator (Gustavson).  The pattern is
+ * the full symbolic product: every column reached by a product is kept,
+ * even when the values cancel.  For each output entry the products are
+ * added in ascending order of the inner index k, starting from 0.0.
+ * Used twice to form the Galerkin operator A_c = P^T (A P) (eq. AcDef).
+ */
+int orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z) {
+    int32_t m = X->nrows, nc = Y->ncols;
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+    if (!mark || !acc || !cols || !rp) { free(mark); free(acc); free(cols); free(rp); return ORC_E_NOMEM; }
+    for (int32_t j = 0; j < nc; ++j) mark[j] = -1;
+    /* symbolic */
+    int64_t total = 0;
+    rp[0] = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t cnt = 0;
+        for (int32_t e = X->rp[i]; e < X->rp[i + 1]; ++e) {
+            int32_t k = X->ci[e];
+            for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t) {
+                int32_t j = Y->ci[t];
+                if (mark[j] != i) { mark[j] = i; ++cnt; }
+            }
+        }
+        total += cnt;
+        if (total > 2147483647LL) { free(mark); free(acc); free(cols); free(rp); return ORC_E_NOMEM; }
+        rp[i + 1] = (int32_t)total;
+    }
+    int32_t nnz = rp[m];
+    int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!ci || !val) { free(mark); free(acc); free(cols); free(rp); free(ci); free(val); return ORC_E_NOMEM; }
+    for (int32_t j = 0; j < nc; ++j) mark[j] = -1;
+    /* numeric */
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t cnt = 0;
+        for (int32_t e = X->rp[i]; e < X->rp[i + 1]; ++e) {
+            int32_t k = X->ci[e];
+            double x = X->val[e];
+            for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t) {
+                int32_t j = Y->ci[t];
+                if (mark[j] != i) { mark[j] = i; acc[j] = 0.0; cols[cnt++] = j; }
+                acc[j] = acc[j] + x * Y->val[t];
+            }
+        }
+        qsort(cols, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        for (int32_t q = 0; q < cnt; ++q) {
+            ci[rp[i] + q] = cols[q];
+            val[rp[i] + q] = acc[cols[q]];
+        }
+    }
+    free(mark); free(acc); free(cols);
+    Z->nrows = m; Z->ncols = nc; Z->rp = rp; Z->ci = ci; Z->val = val;
+    return ORC_OK;
+}
+
+/*
+ * Dense Cholesky A = L L^T for the last level (Alg. AMG Set-up: a direct
+ * factorisation once the level is small).  Column-oriented: for each column
+ * j, the pivot a_jj - sum_k L_jk^2, then the entries below it.  Row-major
+ * storage; L overwrites the lower triangle and the strict upper triangle is
+ * zeroed.  Returns -(j+1) if pivot j is not positive.
+ */
+int orc_cholesky(int32_t n, double *a) {
+    for (int32_t j = 0; j < n; ++j) {
+        double s = a[(size_t)j * n + j];
+        for (int32_t k = 0; k < j; ++k) s = s - a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        if (!(s > 0.0)) return -(j + 1);
+        double ljj = sqrt(s);
+        a[(size_t)j * n + j] = ljj;
+        for (int32_t i = j + 1; i < n; ++i) {
+            double t = a[(size_t)i * n + j];
+            for (int32_t k = 0; k < j; ++k) t = t - a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            a[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) a[(size_t)i * n + j] = 0.0;
+    return 0;
+}
+
+/* z = (L L^T)^{-1} y by forward then backward substitution (Alg. AMG
+ * application in a V-cycle, last level). */
+void orc_chol_solve(int32_t n, const double *L, const double *y, double *z) {
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t i = 0; i < n; ++i) {
+        double t = y[i];
+        for (int32_t k = 0; k < i; ++k) t = t - L[(size_t)i * n + k] * w[k];
+        w[i] = t / L[(size_t)i * n + i];
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        double t = w[i];
+        for (int32_t k = i + 1; k < n; ++k) t = t - L[(size_t)k * n + i] * z[k];
+        z[i] = t / L[(size_t)i * n + i];
+    }
+    free(w);
+}
+
+/*
+ * Relaxation weight of the Jacobi smoother S = I - omega D^{-1} A
+ * (Section 2, eq. smoother), which needs omega rho(D^{-1} A) < 2.  The paper
+ * gives no value; the reading taken is omega = (4/3) / rho_hat with the
+ * Gershgorin bound rho_hat = max_i (sum_j |a_ij|) / a_ii >= rho(D^{-1} A),
+ * so omega rho <= 4/3.  Row sums in CSR order from 0.0.
+ */
+double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, const double *v) {
+    double rho = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0, d = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            s = s + fabs(v[e]);
+            if (ci[e] == i) d = v[e];
+        }
+        double q = s / d;
+        if (q > rho) rho = q;
+    }
+    return (4.0 / 3.0) / rho;
+}
+
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    orc_csr A, P, R;
+    uint8_t *strong;
+    int32_t *stcnt;
+    int8_t *cf;
+    double *dinv;
+    double omega;
+    int32_t rounds;
+} orc_level;
+
+#define ORC_MAXLEV 64
+
+struct orc_hier {
+    orc_params prm;
+    int32_t nlev;            /* levels 0..nlev-1; the last one is solved directly */
+    orc_level lev[ORC_MAXLEV];
+    double *L;               /* dense Cholesky factor of the last level */
+};
+
+static int copy_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, orc_csr *o) {
+    int32_t nnz = rp[n];
+    o->nrows = n; o->ncols = n;
+    o->rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    o->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    o->val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!o->rp || !o->ci || !o->val) return ORC_E_NOMEM;
+    memcpy(o->rp, rp, sizeof(int32_t) * ((size_t)n + 1));
+    memcpy(o->ci, ci, sizeof(int32_t) * (size_t)nnz);
+    memcpy(o->val, v, sizeof(double) * (size_t)nnz);
+    return ORC_OK;
+}
+
+void orc_destroy(orc_hier *h) {
+    if (!h) return;
+    for (int32_t l = 0; l < ORC_MAXLEV; ++l) {
+        orc_level *L = &h->lev[l];
+        orc_csr_free(&L->A); orc_csr_free(&L->P); orc_csr_free(&L->R);
+        free(L->strong); free(L->stcnt); free(L->cf); free(L->dinv);
+    }
+    free(h->L);
+    free(h);
+}
+
+/*
+ * Hierarchy construction, Alg. AMG Set-up, level by level from A_0 = A:
+ *   - level l is the last one when n_l <= max_coarse or l = max_levels - 1
+ *     (the paper's "small enough for a direct factorisation", read as a
+ *     size threshold); it is also the last one when coarsening stalls
+ *     (no C point, or every point C);
+ *   - otherwise: Jacobi smoother (D^{-1}, omega), strength, PMIS, direct
+ *     interpolation, R = P^T, A_{l+1} = R (A_l P)  (eq. AcDef);
+ *   - the last level is factorised densely (more than 8192 unknowns there
+ *     is reported as a stalled coarsening).
+ */
+int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              const orc_params *prm, orc_hier **out) {
+    *out = NULL;
+    int st = orc_validate(n, rp, ci, v);
+    if (st != ORC_OK) return st;
+    orc_hier *h = (orc_hier *)calloc(1, sizeof(orc_hier));
+    if (!h) return ORC_E_NOMEM;
+    if (prm) h->prm = *prm; else orc_params_default(&h->prm);
+    if (h->prm.max_levels > ORC_MAXLEV) h->prm.max_levels = ORC_MAXLEV;
+    if (h->prm.max_levels < 1) h->prm.max_levels = 1;
+    st = copy_csr(n, rp, ci, v, &h->lev[0].A);
+    if (st) { orc_destroy(h); return st; }
+    int32_t l = 0;
+    for (;;) {
+        orc_level *L = &h->lev[l];
+        int32_t nl = L->A.nrows;
+        if (nl <= h->prm.max_coarse || l == h->prm.max_levels - 1) break;
+        const int32_t *arp = L->A.rp, *aci = L->A.ci;
+        const double *av = L->A.val;
+        int32_t nnz = arp[nl];
+        L->dinv = (double *)malloc(sizeof(double) * (size_t)nl);
+        L->strong = (uint8_t *)malloc((size_t)(nnz > 0 ? nnz : 1));
+        L->stcnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)nl);
+        L->cf = (int8_t *)malloc((size_t)nl);
+        if (!L->dinv || !L->strong || !L->stcnt || !L->cf) { orc_destroy(h); return ORC_E_NOMEM; }
+        for (int32_t i = 0; i < nl; ++i) {
+            int32_t d = find_in_row(arp, aci, i, i);
+            if (d < 0 || !(av[d] > 0.0)) { orc_destroy(h); return ORC_E_NOT_SPD; }
+            L->dinv[i] = 1.0 / av[d];
+        }
+        L->omega = h->prm.omega > 0.0 ? h->prm.omega : orc_gershgorin_omega(nl, arp, aci, av);
+        orc_strength(nl, arp, aci, av, h->prm.theta, L->strong, L->stcnt);
+        st = orc_pmis(nl, arp, aci, L->strong, L->stcnt, h->prm.seed, l, L->cf, &L->rounds);
+        if (st) { orc_destroy(h); return st; }
+        int32_t nc = 0;
+        for (int32_t i = 0; i < nl; ++i) if (L->cf[i] == ORC_C) ++nc;
+        if (nc == 0 || nc == nl) break;
+        st = orc_interp_direct(nl, arp, aci, av, L->strong, L->cf, &L->P);
+        if (!st) st = orc_transpose(&L->P, &L->R);
+        orc_csr AP = {0, 0, NULL, NULL, NULL};
+        if (!st) st = orc_spgemm(&L->A, &L->P, &AP);
+        if (!st) st = orc_spgemm(&L->R, &AP, &h->lev[l + 1].A);
+        orc_csr_free(&AP);
+        if (st) { orc_destroy(h); return st; }
+        ++l;
+    }
+    /* last level: discard any coarsening data computed before a stall */
+    orc_level *Lc = &h->lev[l];
+    orc_csr_free(&Lc->P); orc_csr_free(&Lc->R);
+    h->nlev = l + 1;
+    int32_t nL = Lc->A.nrows;
+    if (nL > 8192) { orc_destroy(h); return ORC_E_COARSE; }
+    h->L = (double *)calloc((size_t)nL * (size_t)nL, sizeof(double));
+    if (!h->L) { orc_destroy(h); return ORC_E_NOMEM; }
+    for (int32_t i = 0; i < nL; ++i)
+        for (int32_t e = Lc->A.rp[i]; e < Lc->A.rp[i + 1]; ++e)
+            h->L[(size_t)i * nL + Lc->A.ci[e]] = Lc->A.val[e];
+    if (orc_cholesky(nL, h->L) != 0) { orc_destroy(h); return ORC_E_NOT_SPD; }
+    *out = h;
+    return ORC_OK;
+}
+
+int orc_num_levels(const orc_hier *h) { return h ? h->nlev : 0; }
+
+int orc_level_sizes(const orc_hier *h, int32_t l, int32_t *n, int32_t *nnzA, int32_t *nnzP, int32_t *nc) {
+    if (!h || l < 0 || l >= h->nlev) return ORC_E_ARG;
+    const orc_level *L = &h->lev[l];
+    *n = L->A.nrows;
+    *nnzA = L->A.rp[L->A.nrows];
+    *nnzP = (l < h->nlev - 1) ? L->P.rp[L->P.nrows] : 0;
+    *nc = (l < h->nlev - 1) ? L->P.ncols : 0;
+    return ORC_OK;
+}
+
+static void copy_out_csr(const orc_csr *m, void *a, void *b, void *c) {
+    int32_t nnz = m->rp[m->nrows];
+    if (a) memcpy(a, m->rp, sizeof(int32_t) * ((size_t)m->nrows + 1));
+    if (b) memcpy(b, m->ci, sizeof(int32_t) * (size_t)nnz);
+    if (c) memcpy(c, m->val, sizeof(double) * (size_t)nnz);
+}
+
+int orc_export(const orc_hier *h, int32_t l, int32_t what, void *a, void *b, void *c) {
+    if (!h || l < 0 || l >= h->nlev) return ORC_E_ARG;
+    const orc_level *L = &h->lev[l];
+    int last = (l == h->nlev - 1);
+    int32_t n = L->A.nrows;
+    switch (what) {
+    case ORC_X_A: copy_out_csr(&L->A, a, b, c); return ORC_OK;
+    case ORC_X_P: if (last) return ORC_E_ARG; copy_out_csr(&L->P, a, b, c); return ORC_OK;
+    case ORC_X_R: if (last) return ORC_E_ARG; copy_out_csr(&L->R, a, b, c); return ORC_OK;
+    case ORC_X_CF: if (last) return ORC_E_ARG; memcpy(a, L->cf, (size_t)n); return ORC_OK;
+    case ORC_X_STRONG: if (last) return ORC_E_ARG; memcpy(a, L->strong, (size_t)L->A.rp[n]); return ORC_OK;
+    case ORC_X_DINV: if (last) return ORC_E_ARG; memcpy(a, L->dinv, sizeof(double) * (size_t)n); return ORC_OK;
+    case ORC_X_OMEGA: if (last) return ORC_E_ARG; memcpy(a, &L->omega, sizeof(double)); return ORC_OK;
+    case ORC_X_STCNT: if (last) return ORC_E_ARG; memcpy(a, L->stcnt, sizeof(int32_t) * (size_t)n); return ORC_OK;
+    case ORC_X_ROUNDS: if (last) return ORC_E_ARG; memcpy(a, &L->rounds, sizeof(int32_t)); return ORC_OK;
+    case ORC_X_CHOL: if (!last) return ORC_E_ARG; memcpy(a, h->L, sizeof(double) * (size_t)n * (size_t)n); return ORC_OK;
+    default: return ORC_E_ARG;
+    }
+}
+
+/* t = A s, each row summed in CSR order from 0.0 */
+static void spmv(const orc_csr *A, const double *s, double *t) {
+    for (int32_t i = 0; i < A->nrows; ++i) {
+        double acc = 0.0;
+        for (int32_t e = A->rp[i]; e < A->rp[i + 1]; ++e) acc = acc + A->val[e] * s[A->ci[e]];
+        t[i] = acc;
+    }
+}
+
+/*
+ * One V-cycle z = M_l y (Alg. AMG application in a V-cycle) with Jacobi
+ * smoothing s <- s + omega D^{-1} (y - A s) (eq. smoother, M = D).
+ * nu_pre steps from s = 0 (the first of them is s = omega D^{-1} y, since
+ * A 0 = 0), residual, restriction by R = P^T, recursion, prolongation and
+ * correction, nu_post steps.  On the last level, z = L^{-T} L^{-1} y.
+ * The scaled inverse diagonal is formed as (omega * dinv_i).
+ */
+static void vcycle_level(const orc_hier *h, int32_t l, const double *y, double *z) {
+    const orc_level *L = &h->lev[l];
+    int32_t n = L->A.nrows;
+    if (l == h->nlev - 1) { orc_chol_solve(n, h->L, y, z); return; }
+    int32_t nc = L->P.ncols;
+    double *s = z;   /* the smoothed iterate lives in the output */
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *yc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double *dc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    for (int32_t i = 0; i < n; ++i) s[i] = 0.0;
+    for (int32_t it = 0; it < h->prm.nu_pre; ++it) {
+        if (it == 0) {
+            for (int32_t i = 0; i < n; ++i) s[i] = (L->omega * L->dinv[i]) * y[i];
+        } else {
+            spmv(&L->A, s, t);
+            for (int32_t i = 0; i < n; ++i) s[i] = s[i] + (L->omega * L->dinv[i]) * (y[i] - t[i]);
+        }
+    }
+    spmv(&L->A, s, t);
+    for (int32_t i = 0; i < n; ++i) t[i] = y[i] - t[i];      /* r = y - A s */
+    spmv(&L->R, t, yc);                                       /* y_{l+1} = P^T r */
+    vcycle_level(h, l + 1, yc, dc);
+    spmv(&L->P, dc, t);                                       /* d_l = P d_{l+1} */
+    for (int32_t i = 0; i < n; ++i) s[i] = s[i] + t[i];
+    for (int32_t it = 0; it < h->prm.nu_post; ++it) {
+        spmv(&L->A, s, t);
+        for (int32_t i = 0; i < n; ++i) s[i] = s[i] + (L->omega * L->dinv[i]) * (y[i] - t[i]);
+    }
+    free(t); free(yc); free(dc);
+}
+
+void orc_vcycle(const orc_hier *h, const double *y, double *z) { vcycle_level(h, 0, y, z); }
+
+static double norm2(int32_t n, const double *x) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s = s + x[i] * x[i];
+    return sqrt(s);
+}
+
+static double dot(int32_t n, const double *x, const double *y) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s = s + x[i] * y[i];
+    return s;
+}
+
+/*
+ * Preconditioned CG (the paper's Krylov solver, Section 3 LinSolver/PCG),
+ * in the standard Hestenes-Stiefel form, started from x_0 = 0 and stopped
+ * when the recursively updated residual satisfies ||r_k|| < rtol ||b||
+ * (Section 4: the iterative residual's norm smaller than 1e-8 ||b||).
+ *   z = M r_k, rho_k = r_k . z, p = z (k = 0) or z + (rho_k / rho_{k-1}) p,
+ *   q = A p, sigma = p . q, alpha = rho_k / sigma, x += alpha p, r -= alpha q.
+ * sigma <= 0 or rho_k <= 0 is a breakdown.  rtol <= 0 runs exactly
+ * max_iter iterations.  hist[k] = ||r_k|| for k <= iters (up to hist_cap).
+ * b = 0 returns x = 0 after 0 iterations.
+ */
+int orc_solve(const orc_hier *h, const double *b, double rtol, int32_t max_iter, int32_t precond,
+              double *x, int32_t *iters, double *hist, int32_t hist_cap, double *true_relres) {
+    const orc_csr *A = &h->lev[0].A;
+    int32_t n = A->nrows;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!r || !z || !p || !q) { free(r); free(z); free(p); free(q); return ORC_E_NOMEM; }
+    for (int32_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    double bn = norm2(n, b);
+    if (hist && hist_cap > 0) hist[0] = bn;
+    int status = ORC_OK;
+    int32_t k = 0;
+    if (bn == 0.0) {
+        *iters = 0;
+        if (true_relres) *true_relres = 0.0;
+        free(r); free(z); free(p); free(q);
+        return ORC_OK;
+    }
+    double rn = bn, rho_old = 0.0;
+    for (k = 0;; ++k) {
+        if (rtol > 0.0 && rn < rtol * bn) break;
+        if (k == max_iter) { status = ORC_MAXIT; break; }
+        if (precond) orc_vcycle(h, r, z);
+        else for (int32_t i = 0; i < n; ++i) z[i] = r[i];
+        double rho = dot(n, r, z);
+        if (k == 0) for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+        else {
+            double beta = rho / rho_old;
+            for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        }
+        spmv(A, p, q);
+        double sigma = dot(n, p, q);
+        if (!(sigma > 0.0) || !(rho > 0.0)) { status = ORC_E_BREAKDOWN; break; }
+        double alpha = rho / sigma;
+        for (int32_t i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+        rho_old = rho;
+        rn = norm2(n, r);
+        if (hist && k + 1 < hist_cap) hist[k + 1] = rn;
+    }
+    *iters = k;
+    if (true_relres) {
+        spmv(A, x, q);
+        for (int32_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
+        *true_relres = norm2(n, q) / bn;
+    }
+    free(r); free(z); free(p); free(q);
+    return status;
+}

@@ -1,0 +1,90 @@
+/*
+ * Plain CPU FP64 oracle for classical-AMG-preconditioned CG.
+ *
+ * TEST INFRASTRUCTURE.  This library exists only to check the GPU library
+ * against an independent, slow, obviously-correct implementation written
+ * from the paper (Isotton, Frigo, Spiezia, Janna, "Chronos: a general
+ * purpose classical AMG solver for High Performance Computing").  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no source with the GPU library.
+ *
+ * Single-threaded, compiled with -O2 -ffp-contract=off so every multiply and
+ * add is rounded separately in the order written.
+ *
+ * Status codes (same meaning as the GPU library's, defined independently):
+ *   0 OK, 1 MAXIT (outputs valid), -1 bad argument, -2 malformed CSR,
+ *   -3 not SPD (non-positive diagonal or Cholesky pivot), -4 CG breakdown,
+ *   -5 coarsest level too large, -6 out of memory.
+ */
+#ifndef CAMG_ORACLE_H
+#define CAMG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_MAXIT = 1, ORC_E_ARG = -1, ORC_E_CSR = -2, ORC_E_NOT_SPD = -3,
+       ORC_E_BREAKDOWN = -4, ORC_E_COARSE = -5, ORC_E_NOMEM = -6 };
+
+/* C/F markers */
+enum { ORC_F = -1, ORC_U = 0, ORC_C = 1 };
+
+typedef struct {
+    int32_t nrows, ncols;
+    int32_t *rp;     /* nrows+1 */
+    int32_t *ci;     /* nnz, ascending per row */
+    double  *val;    /* nnz */
+} orc_csr;
+
+typedef struct {
+    double   theta;       /* strength threshold (0.25) */
+    uint64_t seed;        /* PMIS random seed */
+    int32_t  nu_pre, nu_post;
+    double   omega;       /* <= 0: (4/3)/Gershgorin bound per level */
+    int32_t  max_levels;
+    int32_t  max_coarse;
+    int32_t  max_iter;
+} orc_params;
+
+void orc_params_default(orc_params *p);
+
+/* ---- single steps (each on caller buffers unless it returns a CSR) ---- */
+int  orc_validate(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
+void orc_strength(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                  double theta, uint8_t *strong, int32_t *st_count);
+uint64_t orc_splitmix64(uint64_t seed, uint64_t counter);
+uint64_t orc_pmis_rand(uint64_t seed, int32_t level, int32_t i);
+int  orc_pmis(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+              const int32_t *st_count, uint64_t seed, int32_t level, int8_t *cf, int32_t *rounds);
+int  orc_interp_direct(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                       const uint8_t *strong, const int8_t *cf, orc_csr *P);
+int  orc_transpose(const orc_csr *X, orc_csr *XT);
+int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
+int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */
+void orc_chol_solve(int32_t n, const double *L, const double *y, double *z);
+double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
+void orc_csr_free(orc_csr *m);
+void orc_free(void *p);
+
+/* ---- hierarchy and solver ---- */
+typedef struct orc_hier orc_hier;
+int  orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+               const orc_params *prm, orc_hier **out);
+int  orc_num_levels(const orc_hier *h);
+/* sizes of level l: n, nnz(A), nnz(P) (0 on the coarsest), n of level l+1 (0 on the coarsest) */
+int  orc_level_sizes(const orc_hier *h, int32_t l, int32_t *n, int32_t *nnzA, int32_t *nnzP, int32_t *nc);
+enum { ORC_X_A = 0, ORC_X_P = 1, ORC_X_R = 2, ORC_X_CF = 3, ORC_X_STRONG = 4, ORC_X_DINV = 5,
+       ORC_X_OMEGA = 6, ORC_X_CHOL = 7, ORC_X_STCNT = 8, ORC_X_ROUNDS = 9 };
+int  orc_export(const orc_hier *h, int32_t l, int32_t what, void *a, void *b, void *c);
+/* z = M y : one V-cycle */
+void orc_vcycle(const orc_hier *h, const double *y, double *z);
+/* PCG from x0 = 0; precond: 1 = AMG V-cycle, 0 = identity */
+int  orc_solve(const orc_hier *h, const double *b, double rtol, int32_t max_iter, int32_t precond,
+               double *x, int32_t *iters, double *hist, int32_t hist_cap, double *true_relres);
+void orc_destroy(orc_hier *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

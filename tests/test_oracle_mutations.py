@@ -1,0 +1,64 @@
+"""Plant plausible mistakes in a copy of the oracle source and check that
+the pins in test_oracle.py catch every one of them (CPU only)."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "orc.c")
+
+# (name, exact text in orc.c, replacement)
+MUTATIONS = [
+    ("strength_strict", "-v[e] >= thr", "-v[e] > thr"),
+    ("strength_count_transposed", "if (s) st_count[ci[e]] += 1;", "if (s) st_count[i] += 1;"),
+    ("strength_sign", "double neg = -v[e];", "double neg = v[e];"),
+    ("pmis_compare_flipped", "if (sym && key_greater(st_count, u, j, i)) sel = 0;",
+     "if (sym && key_greater(st_count, u, i, j)) sel = 0;"),
+    ("pmis_only_S", "int sym = strong[e] || (t >= 0 && strong[t]);", "int sym = strong[e]; (void)t;"),
+    ("pmis_F_any_neighbour", "if (strong[e] && newc[ci[e]]) { next[i] = ORC_F; break; }",
+     "if (newc[ci[e]]) { next[i] = ORC_F; break; }"),
+    ("pmis_rand_low_bits", "return orc_splitmix64(seed, c) >> 11;", "return orc_splitmix64(seed, c) & ((1ull << 53) - 1);"),
+    ("interp_no_lumping", "if (v[e] > 0.0) d = d + v[e];", "if (v[e] > 0.0) d = d;"),
+    ("interp_sign", "pv[o] = -(alpha * v[e]) / d;", "pv[o] = (alpha * v[e]) / d;"),
+    ("interp_alpha_inverted", "double alpha = num / den;", "double alpha = den / num;"),
+    ("transpose_index", "ci[fill[c]] = i;", "ci[fill[c]] = c;"),
+    ("spgemm_no_accumulate", "acc[j] = acc[j] + x * Y->val[t];", "acc[j] = x * Y->val[t];"),
+    ("spgemm_wrong_operand", "acc[j] = acc[j] + x * Y->val[t];", "acc[j] = acc[j] + x * Y->val[e];"),
+    ("chol_sign", "for (int32_t k = 0; k < j; ++k) t = t - a[(size_t)i * n + k] * a[(size_t)j * n + k];",
+     "for (int32_t k = 0; k < j; ++k) t = t + a[(size_t)i * n + k] * a[(size_t)j * n + k];"),
+    ("chol_solve_transposed", "for (int32_t k = i + 1; k < n; ++k) t = t - L[(size_t)k * n + i] * z[k];",
+     "for (int32_t k = i + 1; k < n; ++k) t = t - L[(size_t)i * n + k] * z[k];"),
+    ("omega_inverted", "return (4.0 / 3.0) / rho;", "return (4.0 / 3.0) * rho / 4.0;"),
+    ("vcycle_restrict_wrong_vector", "spmv(&L->R, t, yc);", "spmv(&L->R, y, yc);"),
+    ("vcycle_no_correction", "for (int32_t i = 0; i < n; ++i) s[i] = s[i] + t[i];",
+     "for (int32_t i = 0; i < n; ++i) s[i] = s[i];"),
+    ("vcycle_residual_sign", "for (int32_t i = 0; i < n; ++i) t[i] = y[i] - t[i];      /* r = y - A s */",
+     "for (int32_t i = 0; i < n; ++i) t[i] = t[i] - y[i];"),
+    ("pcg_beta_sign", "p[i] = z[i] + beta * p[i];", "p[i] = z[i] - beta * p[i];"),
+    ("pcg_stop_nonstrict", "if (rtol > 0.0 && rn < rtol * bn) break;", "if (rtol > 0.0 && rn <= 10 * rtol * bn) break;"),
+]
+
+
+def _run_pins(libpath):
+    env = dict(os.environ, CAMG_ORACLE_LIB=libpath)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique/found"
+    mutated = src.replace(old, new)
+    cfile = tmp_path / "orc.c"
+    cfile.write_text(mutated)
+    hdr = os.path.join(ROOT, "oracle")
+    lib = tmp_path / "liborc_mut.so"
+    subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-I", hdr, "-o", str(lib), str(cfile), "-lm"])
+    assert _run_pins(str(lib)) != 0, f"the pins did not catch mutation {name}"
