@@ -1,0 +1,179 @@
+/*
+ * camg: classical algebraic multigrid preconditioned conjugate gradients
+ * for sparse SPD systems on one AMD Instinct MI355X (gfx950).
+ *
+ * The method follows Isotton, Frigo, Spiezia, Janna, "Chronos: a general
+ * purpose classical AMG solver for High Performance Computing"
+ * (arXiv 2102.07417):
+ *   - the problem A x = b with A sparse SPD in CSR (Section 1, eq. linSys;
+ *     Section 3, CSRMAT storage);
+ *   - hierarchy set-up, Alg. "AMG Set-up": Jacobi smoother (eq. smoother),
+ *     classical strength of connection with a threshold (Section 2,
+ *     Strength of Connection, eq. cla), PMIS C/F splitting, interpolation
+ *     P = [W; I] (eq. prolOperator), Galerkin coarse operator
+ *     A_c = P^T A P (eq. AcDef), dense Cholesky on the last level;
+ *   - preconditioner application, Alg. "AMG application in a V-cycle";
+ *   - PCG from x0 = 0, stopped when ||r|| < rtol ||b|| on the recursively
+ *     updated residual (Section 4, set-up of the experiments).
+ *
+ * Every call returns a camg_status.  No exception or abort crosses this
+ * interface.  The last error message of the calling thread is available
+ * from camg_last_error().
+ *
+ * Pointer conventions: functions named *_dev take device pointers (memory
+ * of the device the handle was created on, e.g. torch tensors) and run on
+ * the given HIP stream (NULL = the default stream); the other functions take
+ * host pointers and synchronise before returning.  Input arrays are borrowed
+ * for the duration of the call; outputs are caller-allocated unless stated.
+ * All indices are 0-based int32; values are IEEE double unless stated.
+ */
+#ifndef CAMG_H
+#define CAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CAMG_ABI_VERSION 1
+
+typedef struct camg_hier *camg_handle;
+
+typedef enum {
+    CAMG_OK = 0,
+    CAMG_E_MAXIT = 1,       /* warning: max_iter reached; outputs hold the last iterate */
+    CAMG_E_ARG = -1,        /* bad argument (null pointer, n < 1, bad parameter) */
+    CAMG_E_CSR = -2,        /* malformed CSR, non-finite value, missing diagonal, asymmetry */
+    CAMG_E_NOT_SPD = -3,    /* non-positive diagonal or non-positive Cholesky pivot */
+    CAMG_E_BREAKDOWN = -4,  /* CG breakdown: p.Ap <= 0 or r.z <= 0 (matrix or M not SPD) */
+    CAMG_E_COARSE = -5,     /* coarsening stalled with more than 8192 unknowns on the last level */
+    CAMG_E_NOMEM = -6,      /* device or host allocation failed */
+    CAMG_E_DEVICE = -7,     /* HIP runtime error */
+    CAMG_E_BUSY = -8        /* the handle is in use by another call */
+} camg_status;
+
+enum { CAMG_FP64 = 0, CAMG_MIXED_FP32 = 1 };
+
+/* Hierarchy and solver parameters. */
+typedef struct {
+    double   theta;       /* strength threshold; default 0.25 */
+    uint64_t seed;        /* PMIS random seed; level l, point i uses splitmix64 draw (l << 40) + i */
+    int32_t  nu_pre;      /* Jacobi steps before the coarse correction; default 1 */
+    int32_t  nu_post;     /* Jacobi steps after it; default 1 (equal values keep M symmetric) */
+    double   omega;       /* <= 0: (4/3) / max_i(sum_j |a_ij| / a_ii) per level; > 0: fixed */
+    int32_t  max_levels;  /* default 25 */
+    int32_t  max_coarse;  /* a level with at most this many unknowns is solved directly; default 256 */
+    int32_t  precision;   /* CAMG_FP64 or CAMG_MIXED_FP32 (FP32 V-cycle inside FP64 PCG) */
+    int32_t  max_iter;    /* PCG iteration limit; default 1000 */
+} camg_params;
+
+#define CAMG_MAX_LEVELS 32
+
+typedef struct {
+    int32_t levels;                       /* number of levels; the last one is solved directly */
+    int32_t n[CAMG_MAX_LEVELS];           /* unknowns per level */
+    int64_t nnz[CAMG_MAX_LEVELS];         /* nonzeros of A_l */
+    int64_t nnz_p[CAMG_MAX_LEVELS];       /* nonzeros of P_l (0 on the last level) */
+    int32_t pmis_rounds[CAMG_MAX_LEVELS]; /* PMIS rounds per level */
+    double  omega[CAMG_MAX_LEVELS];       /* Jacobi weight per level */
+    double  grid_complexity;              /* sum_l n_l / n_0 */
+    double  operator_complexity;          /* sum_l nnz(A_l) / nnz(A_0) */
+    int64_t device_bytes;                 /* device memory held by the handle */
+    double  setup_ms;                     /* wall time of the set-up call */
+    int32_t precision;
+} camg_info_t;
+
+int32_t     camg_abi_version(void);
+const char *camg_status_str(camg_status s);
+const char *camg_last_error(void);
+void        camg_params_default(camg_params *p);
+
+/*
+ * Build the hierarchy of A on the current HIP device (Alg. AMG Set-up).
+ * n: order of A.  row_ptr[n+1], col_idx[nnz], val[nnz] with nnz = row_ptr[n]:
+ * 0-based CSR, columns strictly increasing in each row, both triangles
+ * stored, structurally symmetric with |a_ij - a_ji| <= 1e-12 max|a|, every
+ * diagonal entry present and positive, all values finite.  Violations give
+ * CAMG_E_CSR (CAMG_E_NOT_SPD for a non-positive diagonal) before any
+ * hierarchy is built.  params may be NULL (defaults).  The handle owns
+ * copies of everything it needs; release it with camg_destroy.
+ * camg_setup takes host arrays; camg_setup_dev device arrays.
+ */
+camg_status camg_setup(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                       const camg_params *params, camg_handle *out);
+camg_status camg_setup_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
+                           const camg_params *params, void *hip_stream, camg_handle *out);
+
+/*
+ * Solve A x = b by PCG preconditioned with one V-cycle per iteration
+ * (Alg. AMG application in a V-cycle), from x0 = 0, until
+ * ||r_k|| < rtol ||b|| on the recursively updated residual, or max_iter
+ * iterations.  rtol <= 0 runs exactly max_iter iterations.
+ * b, x: n doubles.  iters (may be NULL): iterations done.  hist (host, may be
+ * NULL): hist[k] = ||r_k|| for k = 0..iters, truncated to hist_cap entries.
+ * true_relres (may be NULL): ||b - A x|| / ||b|| in FP64 at exit.
+ * b = 0 gives x = 0 after 0 iterations.  Returns CAMG_E_MAXIT (x valid) or
+ * CAMG_E_BREAKDOWN (x = last iterate) when the loop did not converge.
+ * camg_solve: host b and x.  camg_solve_dev: device b and x, asynchronous
+ * with respect to the host except for the convergence polling; it returns
+ * after the solve has finished on `hip_stream`.
+ */
+camg_status camg_solve(camg_handle h, const double *b, double rtol, double *x, int32_t *iters,
+                       double *hist, int32_t hist_cap, double *true_relres);
+camg_status camg_solve_dev(camg_handle h, const double *d_b, double rtol, double *d_x, int32_t *iters,
+                           double *hist, int32_t hist_cap, double *true_relres, void *hip_stream);
+
+/*
+ * k right-hand sides at once: d_B and d_X are n-by-k row-major device
+ * blocks.  The columns run k independent PCG recurrences that share every
+ * matrix pass (sparse matrix times row-major block); a column stops updating
+ * once it has converged, so each column's result equals that of a
+ * single-column call with the same precision setting.  iters[k],
+ * true_relres[k] (host, may be NULL); hist (host, may be NULL) is k-by-hist_cap
+ * row-major.  Returns the worst status over the columns.
+ */
+camg_status camg_solve_multi_dev(camg_handle h, int32_t k, const double *d_B, double rtol, double *d_X,
+                                 int32_t *iters, double *hist, int32_t hist_cap, double *true_relres,
+                                 void *hip_stream);
+
+/* z = M y: one V-cycle (device vectors of length n). */
+camg_status camg_vcycle_dev(camg_handle h, const double *d_y, double *d_z, void *hip_stream);
+
+/* Hierarchy statistics (host struct). */
+camg_status camg_info(camg_handle h, camg_info_t *info);
+
+/* Sizes of level l: n_l, nnz(A_l), nnz(P_l), n_{l+1} (the last two are 0 on the last level). */
+camg_status camg_level_sizes(camg_handle h, int32_t l, int32_t *n, int64_t *nnz_a, int64_t *nnz_p, int32_t *nc);
+
+/*
+ * Copy part of level l to host buffers sized from camg_level_sizes:
+ *   CAMG_X_A, CAMG_X_P, CAMG_X_R: a = row_ptr (int32), b = col_idx (int32), c = values (double);
+ *   CAMG_X_CF: a = int8[n] (1 = C, -1 = F);   CAMG_X_STRONG: a = uint8[nnz(A_l)];
+ *   CAMG_X_DINV: a = double[n] (1 / a_ii);    CAMG_X_OMEGA: a = double[1];
+ *   CAMG_X_STCNT: a = int32[n] (|S_i^T|);      CAMG_X_COARSE_INV: a = double[n*n] (last level:
+ *   the dense inverse applied by the coarse solve, row-major).
+ */
+enum { CAMG_X_A = 0, CAMG_X_P = 1, CAMG_X_R = 2, CAMG_X_CF = 3, CAMG_X_STRONG = 4, CAMG_X_DINV = 5,
+       CAMG_X_OMEGA = 6, CAMG_X_COARSE_INV = 7, CAMG_X_STCNT = 8 };
+camg_status camg_export_level(camg_handle h, int32_t l, int32_t what, void *a, void *b, void *c);
+
+/*
+ * Galerkin product A_c = P^T (A P) (eq. AcDef) of caller-provided host CSR
+ * matrices, computed on the current device by the same kernels the set-up
+ * uses.  A: n-by-n, P: n-by-nc.  The result arrays are allocated by the
+ * library (release each with camg_free_host); *nnz_out receives nnz(A_c).
+ * The pattern is the full symbolic product (no dropping), rows sorted.
+ */
+camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, const double *a_val,
+                          int32_t nc, const int32_t *p_rp, const int32_t *p_ci, const double *p_val,
+                          int32_t **c_rp, int32_t **c_ci, double **c_val, int64_t *nnz_out);
+void camg_free_host(void *p);
+
+/* Release the hierarchy and all its device memory.  NULL is ignored. */
+camg_status camg_destroy(camg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMG_H */

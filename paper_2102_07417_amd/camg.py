@@ -1,0 +1,325 @@
+"""ctypes binding of libcamg (include/camg.h).
+
+Argument marshalling only: every step of set-up and solve runs in the HIP
+kernels of the library.  Device arrays are passed as torch CUDA tensors
+(``.data_ptr()``), streams as ``torch.cuda.Stream`` objects; host arrays as
+numpy arrays.  If the shared library is missing this module raises at
+import of the library (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcamg.so")
+
+OK, E_MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM, E_DEVICE, E_BUSY = (
+    0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
+FP64, MIXED_FP32 = 0, 1
+X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_COARSE_INV, X_STCNT = range(9)
+MAX_LEVELS = 32
+
+EXPORTED = [
+    "camg_abi_version", "camg_status_str", "camg_last_error", "camg_params_default", "camg_setup",
+    "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
+    "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy",
+]
+
+
+class camg_params(C.Structure):
+    _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
+                ("precision", C.c_int32), ("max_iter", C.c_int32)]
+
+
+class camg_info_t(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("n", C.c_int32 * MAX_LEVELS), ("nnz", C.c_int64 * MAX_LEVELS),
+                ("nnz_p", C.c_int64 * MAX_LEVELS), ("pmis_rounds", C.c_int32 * MAX_LEVELS),
+                ("omega", C.c_double * MAX_LEVELS), ("grid_complexity", C.c_double),
+                ("operator_complexity", C.c_double), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
+                ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libcamg.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIBPATH
+    if not os.path.exists(p):
+        raise OSError(f"libcamg.so not found at {p}; build it with paper_2102_07417_amd/build.py")
+    L = C.CDLL(p)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.camg_abi_version.restype = i32
+    L.camg_status_str.argtypes = [C.c_int]; L.camg_status_str.restype = C.c_char_p
+    L.camg_last_error.restype = C.c_char_p
+    L.camg_params_default.argtypes = [C.POINTER(camg_params)]
+    L.camg_setup.argtypes = [i32, vp, vp, vp, C.POINTER(camg_params), C.POINTER(vp)]
+    L.camg_setup_dev.argtypes = [i32, vp, vp, vp, C.POINTER(camg_params), vp, C.POINTER(vp)]
+    L.camg_solve.argtypes = [vp, vp, dbl, vp, vp, vp, i32, vp]
+    L.camg_solve_dev.argtypes = [vp, vp, dbl, vp, vp, vp, i32, vp, vp]
+    L.camg_solve_multi_dev.argtypes = [vp, i32, vp, dbl, vp, vp, vp, i32, vp, vp]
+    L.camg_vcycle_dev.argtypes = [vp, vp, vp, vp]
+    L.camg_info.argtypes = [vp, C.POINTER(camg_info_t)]
+    L.camg_level_sizes.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.camg_export_level.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.camg_galerkin.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp, C.POINTER(C.POINTER(C.c_int32)),
+                                C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_double)), C.POINTER(i64)]
+    L.camg_free_host.argtypes = [vp]
+    L.camg_destroy.argtypes = [vp]
+    for name in ("camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
+                 "camg_vcycle_dev", "camg_info", "camg_level_sizes", "camg_export_level", "camg_galerkin",
+                 "camg_destroy"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class CamgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"camg status {status}: {msg}")
+        self.status = status
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(st: int, allow=(OK,)):
+    if st not in allow:
+        raise CamgError(st, load().camg_last_error().decode())
+    return st
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def params(**kw) -> camg_params:
+    p = camg_params()
+    load().camg_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+# ------------------------------------------------------------------ C-ABI names
+def camg_setup(n, row_ptr, col_idx, val, prm=None):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    h = C.c_void_p()
+    st = load().camg_setup(int(n), _p(rp), _p(ci), _p(v), C.byref(prm) if prm is not None else None, C.byref(h))
+    return st, h
+
+
+def camg_setup_dev(n, d_row_ptr, d_col_idx, d_val, prm=None, stream=None):
+    h = C.c_void_p()
+    st = load().camg_setup_dev(int(n), C.c_void_p(d_row_ptr.data_ptr()), C.c_void_p(d_col_idx.data_ptr()),
+                               C.c_void_p(d_val.data_ptr()), C.byref(prm) if prm is not None else None,
+                               _stream_ptr(stream), C.byref(h))
+    return st, h
+
+
+def camg_solve(h, b, rtol, x, hist_cap=0):
+    b = np.ascontiguousarray(b, np.float64)
+    it = np.zeros(1, np.int32)
+    hist = np.zeros(max(hist_cap, 1))
+    rel = np.zeros(1)
+    st = load().camg_solve(h, _p(b), float(rtol), _p(x), _p(it), _p(hist) if hist_cap else None, int(hist_cap),
+                           _p(rel))
+    return st, int(it[0]), hist[:min(hist_cap, int(it[0]) + 1)], float(rel[0])
+
+
+def camg_solve_dev(h, d_b, rtol, d_x, hist_cap=0, stream=None):
+    it = np.zeros(1, np.int32)
+    hist = np.zeros(max(hist_cap, 1))
+    rel = np.zeros(1)
+    st = load().camg_solve_dev(h, C.c_void_p(d_b.data_ptr()), float(rtol), C.c_void_p(d_x.data_ptr()), _p(it),
+                               _p(hist) if hist_cap else None, int(hist_cap), _p(rel), _stream_ptr(stream))
+    return st, int(it[0]), hist[:min(hist_cap, int(it[0]) + 1)], float(rel[0])
+
+
+def camg_solve_multi_dev(h, k, d_B, rtol, d_X, hist_cap=0, stream=None):
+    it = np.zeros(k, np.int32)
+    hist = np.zeros((k, max(hist_cap, 1)))
+    rel = np.zeros(k)
+    st = load().camg_solve_multi_dev(h, int(k), C.c_void_p(d_B.data_ptr()), float(rtol), C.c_void_p(d_X.data_ptr()),
+                                     _p(it), _p(hist) if hist_cap else None, int(hist_cap), _p(rel),
+                                     _stream_ptr(stream))
+    return st, it, hist, rel
+
+
+def camg_vcycle_dev(h, d_y, d_z, stream=None):
+    return load().camg_vcycle_dev(h, C.c_void_p(d_y.data_ptr()), C.c_void_p(d_z.data_ptr()), _stream_ptr(stream))
+
+
+def camg_info(h):
+    info = camg_info_t()
+    _check(load().camg_info(h, C.byref(info)))
+    return info
+
+
+def camg_level_sizes(h, l):
+    a = [np.zeros(1, np.int32), np.zeros(1, np.int64), np.zeros(1, np.int64), np.zeros(1, np.int32)]
+    _check(load().camg_level_sizes(h, int(l), *[_p(x) for x in a]))
+    return tuple(int(x[0]) for x in a)
+
+
+def camg_export_level(h, l, what, a, b=None, c=None):
+    return load().camg_export_level(h, int(l), int(what), _p(a), None if b is None else _p(b),
+                                    None if c is None else _p(c))
+
+
+def camg_galerkin(A, P):
+    """A, P: (nrows, ncols, rp, ci, val) tuples.  Returns the CSR tuple of P^T A P."""
+    n, _, arp, aci, av = A
+    _, nc, prp, pci, pv = P
+    arrs = [np.ascontiguousarray(x, t) for x, t in [(arp, np.int32), (aci, np.int32), (av, np.float64),
+                                                     (prp, np.int32), (pci, np.int32), (pv, np.float64)]]
+    crp, cci, cv = C.POINTER(C.c_int32)(), C.POINTER(C.c_int32)(), C.POINTER(C.c_double)()
+    nnz = C.c_int64()
+    L = load()
+    _check(L.camg_galerkin(int(n), _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), int(nc), _p(arrs[3]), _p(arrs[4]),
+                           _p(arrs[5]), C.byref(crp), C.byref(cci), C.byref(cv), C.byref(nnz)))
+    m = int(nnz.value)
+    rp = np.ctypeslib.as_array(crp, shape=(nc + 1,)).copy()
+    ci = np.ctypeslib.as_array(cci, shape=(max(m, 1),))[:m].copy()
+    v = np.ctypeslib.as_array(cv, shape=(max(m, 1),))[:m].copy()
+    for p in (crp, cci, cv):
+        L.camg_free_host(C.cast(p, C.c_void_p))
+    return (nc, nc, rp, ci, v)
+
+
+def camg_destroy(h):
+    return load().camg_destroy(h)
+
+
+# ------------------------------------------------------------------ convenience
+class Solver:
+    """An AMG hierarchy resident on the current GPU.
+
+    ``Solver(A)`` with A a problems.CSR (host arrays, copied to the device),
+    or ``Solver.from_device(n, rp, ci, val)`` with torch CUDA tensors."""
+
+    def __init__(self, A=None, stream=None, _handle=None, **kw):
+        self.h = None
+        if _handle is not None:
+            self.h = _handle
+        else:
+            prm = params(**kw)
+            st, h = camg_setup(A.n, A.row_ptr, A.col_idx, A.val, prm)
+            _check(st)
+            self.h = h
+        self.info = camg_info(self.h)
+        self.n = self.info.n[0]
+
+    @classmethod
+    def from_device(cls, n, d_rp, d_ci, d_val, stream=None, **kw):
+        prm = params(**kw)
+        st, h = camg_setup_dev(n, d_rp, d_ci, d_val, prm, stream)
+        _check(st)
+        return cls(_handle=h)
+
+    def close(self):
+        if self.h:
+            camg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nlev(self):
+        return self.info.levels
+
+    def sizes(self, l):
+        return camg_level_sizes(self.h, l)
+
+    def _csr(self, l, what):
+        n, nnza, nnzp, nc = self.sizes(l)
+        if what == X_A:
+            nr, ncol, nnz = n, n, nnza
+        elif what == X_P:
+            nr, ncol, nnz = n, nc, nnzp
+        else:
+            nr, ncol, nnz = nc, n, nnzp
+        rp = np.zeros(nr + 1, np.int32)
+        ci = np.zeros(max(nnz, 1), np.int32)
+        v = np.zeros(max(nnz, 1))
+        _check(camg_export_level(self.h, l, what, rp, ci, v))
+        return (nr, ncol, rp, ci[:nnz], v[:nnz])
+
+    def A(self, l):
+        return self._csr(l, X_A)
+
+    def P(self, l):
+        return self._csr(l, X_P)
+
+    def R(self, l):
+        return self._csr(l, X_R)
+
+    def _vec(self, l, what, dtype, size=None):
+        n = self.sizes(l)[0]
+        a = np.zeros(size if size is not None else n, dtype)
+        _check(camg_export_level(self.h, l, what, a))
+        return a
+
+    def cf(self, l):
+        return self._vec(l, X_CF, np.int8)
+
+    def strong(self, l):
+        return self._vec(l, X_STRONG, np.uint8, self.sizes(l)[1])
+
+    def stcnt(self, l):
+        return self._vec(l, X_STCNT, np.int32)
+
+    def dinv(self, l):
+        return self._vec(l, X_DINV, np.float64)
+
+    def omega(self, l):
+        return float(self._vec(l, X_OMEGA, np.float64, 1)[0])
+
+    def coarse_inverse(self):
+        l = self.nlev - 1
+        n = self.sizes(l)[0]
+        a = np.zeros((n, n))
+        _check(camg_export_level(self.h, l, X_COARSE_INV, a))
+        return a
+
+    def solve(self, b, rtol=1e-8, hist_cap=None):
+        """Host vectors in and out."""
+        x = np.zeros(self.n)
+        cap = 100001 if hist_cap is None else hist_cap
+        st, it, hist, rel = camg_solve(self.h, b, rtol, x, hist_cap=cap)
+        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        return SolveResult(st, x, it, hist, rel)
+
+    def solve_dev(self, d_b, d_x, rtol=1e-8, hist_cap=0, stream=None):
+        st, it, hist, rel = camg_solve_dev(self.h, d_b, rtol, d_x, hist_cap=hist_cap, stream=stream)
+        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        return SolveResult(st, None, it, hist, rel)
+
+    def vcycle_dev(self, d_y, d_z, stream=None):
+        _check(camg_vcycle_dev(self.h, d_y, d_z, stream))
+
+
+class SolveResult:
+    def __init__(self, status, x, iters, hist, true_relres):
+        self.status, self.x, self.iters, self.hist, self.true_relres = status, x, iters, hist, true_relres
+
+    def __repr__(self):
+        return f"SolveResult(status={self.status}, iters={self.iters}, true_relres={self.true_relres:.3e})"

@@ -1,0 +1,721 @@
+// C-ABI of libcamg: hierarchy set-up (Alg. "AMG Set-up"), V-cycle
+// (Alg. "AMG application in a V-cycle") and PCG drivers.  Host code only
+// orchestrates; every step of set-up and solve runs in the kernels of
+// setup.hip, spgemm.hip and solve.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace camg {
+
+static thread_local std::string g_last_error;
+
+void fail(camg_status s, const std::string &msg) { throw Error{s, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        fail(CAMG_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    fail(CAMG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *Pool::raw(size_t nbytes) {
+    void *p = nullptr;
+    if (nbytes == 0) nbytes = 1;
+    nbytes = (nbytes + 255) & ~(size_t)255;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CAMG_E_NOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    bytes += (int64_t)nbytes;
+    return p;
+}
+
+void Pool::release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+}
+
+namespace {
+
+struct BusyGuard {
+    Hier *h;
+    explicit BusyGuard(Hier *hh) : h(hh) {
+        int expect = 0;
+        if (!h->busy.compare_exchange_strong(expect, 1)) fail(CAMG_E_BUSY, "handle is in use by another call");
+    }
+    ~BusyGuard() { h->busy.store(0); }
+};
+
+template <class F>
+camg_status guarded(F &&f) {
+    try {
+        f();
+        return CAMG_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return CAMG_E_NOMEM;
+    } catch (...) {
+        g_last_error = "unexpected exception";
+        return CAMG_E_DEVICE;
+    }
+}
+
+template <class T>
+T read1(const T *d, hipStream_t s) {
+    T v;
+    HIPC(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return v;
+}
+
+void check_params(const camg_params &p) {
+    if (!(p.theta >= 0.0 && p.theta <= 1.0)) fail(CAMG_E_ARG, "theta must lie in [0, 1]");
+    if (p.nu_pre < 1 || p.nu_pre > 8 || p.nu_post < 1 || p.nu_post > 8)
+        fail(CAMG_E_ARG, "nu_pre and nu_post must lie in [1, 8]");
+    if (p.max_levels < 1 || p.max_levels > CAMG_MAX_LEVELS) fail(CAMG_E_ARG, "max_levels must lie in [1, 32]");
+    if (p.max_coarse < 1) fail(CAMG_E_ARG, "max_coarse must be >= 1");
+    if (p.max_iter < 0) fail(CAMG_E_ARG, "max_iter must be >= 0");
+    if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
+    if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
+}
+
+// ---------------------------------------------------------------- set-up
+void validate_input(Hier &h, int n, int64_t nnz, const Csr &A, int32_t *tpos, Pool &tmp, hipStream_t s) {
+    int32_t *flags = tmp.alloc<int32_t>(8);
+    unsigned long long *amax = tmp.alloc<unsigned long long>(1);
+    HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+    HIPC(hipMemsetAsync(amax, 0, sizeof(unsigned long long), s));
+    validate_rowptr(n, nnz, A.rp, flags, s);
+    int32_t hf[8];
+    HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hf[0]) fail(CAMG_E_CSR, "row pointer is not 0-based and non-decreasing up to nnz");
+    validate_rows(n, A.rp, A.ci, A.v, flags, amax, s);
+    HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hf[1]) fail(CAMG_E_CSR, "column index out of range or not strictly increasing within a row");
+    if (hf[2]) fail(CAMG_E_CSR, "non-finite matrix value");
+    if (hf[3]) fail(CAMG_E_CSR, "a diagonal entry is missing");
+    validate_sym(n, A.rp, A.ci, A.v, amax, flags, tpos, s);
+    HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hf[4]) fail(CAMG_E_CSR, "matrix is not symmetric (pattern or values beyond 1e-12 max|a|)");
+    if (hf[5]) fail(CAMG_E_NOT_SPD, "non-positive diagonal entry");
+    (void)h;
+}
+
+void alloc_f32_copy(Pool &pool, Csr &M, hipStream_t s) {
+    M.v32 = pool.alloc<float>(std::max<int64_t>(M.nnz, 1));
+    to_f32(M.nnz, M.v, M.v32, s);
+}
+
+void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const double *v, bool host_in,
+                     hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const camg_params &prm = h.prm;
+    Pool tmp;
+    int64_t nnz;
+    if (host_in) nnz = rp[n];
+    else nnz = read1(rp + n, s);
+    if (nnz < 0) fail(CAMG_E_CSR, "row_ptr[n] is negative");
+
+    h.lev.clear();
+    h.lev.emplace_back();
+    {
+        Csr &A = h.lev[0].A;
+        A.nr = A.nc = n;
+        A.nnz = nnz;
+        A.rp = h.pool.alloc<int32_t>((size_t)n + 1);
+        A.ci = h.pool.alloc<int32_t>(std::max<int64_t>(nnz, 1));
+        A.v = h.pool.alloc<double>(std::max<int64_t>(nnz, 1));
+        const hipMemcpyKind k = host_in ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        HIPC(hipMemcpyAsync(A.rp, rp, sizeof(int32_t) * ((size_t)n + 1), k, s));
+        HIPC(hipMemcpyAsync(A.ci, ci, sizeof(int32_t) * (size_t)nnz, k, s));
+        HIPC(hipMemcpyAsync(A.v, v, sizeof(double) * (size_t)nnz, k, s));
+    }
+    int32_t *tpos = tmp.alloc<int32_t>(std::max<int64_t>(nnz, 1));
+    validate_input(h, n, nnz, h.lev[0].A, tpos, tmp, s);
+
+    int32_t *flags = tmp.alloc<int32_t>(8);
+    unsigned long long *qmax = tmp.alloc<unsigned long long>(1);
+    int32_t *und = tmp.alloc<int32_t>(1);
+    for (int l = 0;; ++l) {
+        const int nl = h.lev[l].A.nr;
+        if (nl <= prm.max_coarse || l == prm.max_levels - 1) break;
+        Level &L = h.lev[l];
+        const int64_t nz = L.A.nnz;
+        Pool lt;  // per-level temporaries
+        if (l > 0) {
+            tpos = lt.alloc<int32_t>(std::max<int64_t>(nz, 1));
+            transpose_positions(nl, L.A.rp, L.A.ci, tpos, s);
+        }
+        // Jacobi weights (eq. smoother)
+        L.dinv = h.pool.alloc<double>(nl);
+        L.wd = h.pool.alloc<double>(nl);
+        HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+        diag_gershgorin(nl, L.A.rp, L.A.ci, L.A.v, L.dinv, qmax, flags, s);
+        int32_t hf[8];
+        unsigned long long hq;
+        HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(&hq, qmax, sizeof(hq), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        if (hf[5]) fail(CAMG_E_NOT_SPD, "non-positive diagonal on level " + std::to_string(l));
+        double rho;
+        std::memcpy(&rho, &hq, sizeof(rho));
+        L.omega = prm.omega > 0.0 ? prm.omega : (4.0 / 3.0) / rho;
+        scale_vec(nl, L.omega, L.dinv, L.wd, s);
+        // strength and PMIS
+        L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
+        L.stcnt = h.pool.alloc<int32_t>(nl);
+        L.cf = h.pool.alloc<int8_t>(nl);
+        strength(nl, L.A.rp, L.A.ci, L.A.v, prm.theta, L.strong, L.stcnt, s);
+        uint64_t *u = lt.alloc<uint64_t>(nl);
+        int8_t *newc = lt.alloc<int8_t>(nl);
+        pmis_init(nl, L.stcnt, prm.seed, l, u, L.cf, und, s);
+        int32_t hund = read1(und, s);
+        int rounds = 0;
+        while (hund > 0) {
+            pmis_round(nl, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und, s);
+            ++rounds;
+            hund = read1(und, s);
+            if (rounds > nl + 1) fail(CAMG_E_DEVICE, "PMIS did not terminate");
+        }
+        L.rounds = rounds;
+        // coarse numbering
+        int32_t *isc = lt.alloc<int32_t>(nl);
+        int64_t *cmap = lt.alloc<int64_t>((size_t)nl + 1);
+        cf_flags(nl, L.cf, isc, s);
+        scan_i32_to_i64(isc, cmap, nl, lt, s);
+        const int64_t nc = read1(cmap + nl, s);
+        if (nc == 0 || nc == nl) break;  // coarsening stalled: this is the last level
+        // direct interpolation P = [W; I]
+        Csr &P = L.P;
+        P.nr = nl;
+        P.nc = (int32_t)nc;
+        int32_t *pcnt = lt.alloc<int32_t>(nl);
+        interp_count(nl, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
+        int64_t *prp64 = lt.alloc<int64_t>((size_t)nl + 1);
+        scan_i32_to_i64(pcnt, prp64, nl, lt, s);
+        P.nnz = read1(prp64 + nl, s);
+        P.rp = h.pool.alloc<int32_t>((size_t)nl + 1);
+        narrow_i64(prp64, P.rp, nl, s);
+        P.ci = h.pool.alloc<int32_t>(std::max<int64_t>(P.nnz, 1));
+        P.v = h.pool.alloc<double>(std::max<int64_t>(P.nnz, 1));
+        interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
+        // R = P^T
+        Csr &R = L.R;
+        R.nr = P.nc;
+        R.nc = nl;
+        R.nnz = P.nnz;
+        int32_t *ccnt = lt.alloc<int32_t>(P.nc);
+        column_counts(P, ccnt, s);
+        int64_t *rrp64 = lt.alloc<int64_t>((size_t)P.nc + 1);
+        scan_i32_to_i64(ccnt, rrp64, P.nc, lt, s);
+        R.rp = h.pool.alloc<int32_t>((size_t)P.nc + 1);
+        narrow_i64(rrp64, R.rp, P.nc, s);
+        R.ci = h.pool.alloc<int32_t>(std::max<int64_t>(R.nnz, 1));
+        R.v = h.pool.alloc<double>(std::max<int64_t>(R.nnz, 1));
+        transpose_csr(P, R, lt, s);
+        // Galerkin product A_{l+1} = R (A P)  (eq. AcDef)
+        Csr AP, Ac;
+        spgemm(L.A, P, AP, lt, lt, s);
+        spgemm(R, AP, Ac, h.pool, lt, s);
+        HIPC(hipStreamSynchronize(s));
+        lt.release();
+        Level next;
+        next.A = Ac;
+        h.lev.push_back(next);
+    }
+    h.nlev = (int)h.lev.size();
+    // last level: dense Cholesky and explicit inverse (FP64)
+    Level &Lc = h.lev.back();
+    h.nL = Lc.A.nr;
+    if (h.nL > 8192) fail(CAMG_E_COARSE, "coarsening stalled with " + std::to_string(h.nL) + " unknowns");
+    {
+        double *D = tmp.alloc<double>((size_t)h.nL * h.nL);
+        dense_from_csr(h.nL, Lc.A.rp, Lc.A.ci, Lc.A.v, D, s);
+        HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+        cholesky_dense(h.nL, D, flags, s);
+        int32_t hf[8];
+        HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        if (hf[5]) fail(CAMG_E_NOT_SPD, "non-positive pivot in the Cholesky factorisation of the last level");
+        h.cinv = h.pool.alloc<double>((size_t)h.nL * h.nL);
+        chol_inverse(h.nL, D, h.cinv, s);
+    }
+    // launch shapes, work vectors, mixed-precision copies
+    const bool mixed = prm.precision == CAMG_MIXED_FP32;
+    for (int l = 0; l < h.nlev; ++l) {
+        Level &L = h.lev[l];
+        const int nl = L.A.nr;
+        L.cA = choose_cfg(nl, L.A.nnz);
+        if (l < h.nlev - 1) {
+            L.cP = choose_cfg(L.P.nr, L.P.nnz);
+            L.cR = choose_cfg(L.R.nr, L.R.nnz);
+        }
+        if (!mixed) {
+            if (l > 0) {
+                L.y = h.pool.alloc<double>(nl);
+                L.z = h.pool.alloc<double>(nl);
+            }
+            L.s = h.pool.alloc<double>(nl);
+            L.r = h.pool.alloc<double>(nl);
+        } else {
+            L.y32 = h.pool.alloc<float>(nl);
+            L.z32 = h.pool.alloc<float>(nl);
+            L.s32 = h.pool.alloc<float>(nl);
+            L.r32 = h.pool.alloc<float>(nl);
+            if (l < h.nlev - 1) {
+                alloc_f32_copy(h.pool, L.A, s);
+                alloc_f32_copy(h.pool, L.P, s);
+                alloc_f32_copy(h.pool, L.R, s);
+                L.wd32 = h.pool.alloc<float>(nl);
+                to_f32(nl, L.wd, L.wd32, s);
+            }
+        }
+        // extra buffer for more than one smoothing step
+        if (prm.nu_pre > 1 || prm.nu_post > 1) {
+            if (!mixed) L.t = h.pool.alloc<double>(nl);
+            else L.t32 = h.pool.alloc<float>(nl);
+        }
+    }
+    const int n0 = h.lev[0].A.nr;
+    h.r = h.pool.alloc<double>(n0);
+    h.z = h.pool.alloc<double>(n0);
+    h.p[0] = h.pool.alloc<double>(n0);
+    h.p[1] = h.pool.alloc<double>(n0);
+    h.q = h.pool.alloc<double>(n0);
+    h.partials = h.pool.alloc<double>(kMaxGrid);
+    h.counter = h.pool.alloc<unsigned>(1);
+    h.st = h.pool.alloc<PcgState>(1);
+    h.sc = h.pool.alloc<double>(4);
+    HIPC(hipMemsetAsync(h.counter, 0, sizeof(unsigned), s));
+    HIPC(hipHostMalloc((void **)&h.hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
+    HIPC(hipHostGetDevicePointer((void **)&h.hflag_dev, h.hflag, 0));
+    HIPC(hipStreamSynchronize(s));
+    h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <class T>
+struct VT;
+template <>
+struct VT<double> {
+    static const double *wd(const Level &L) { return L.wd; }
+    static double *y(Level &L) { return L.y; }
+    static double *s(Level &L) { return L.s; }
+    static double *r(Level &L) { return L.r; }
+    static double *z(Level &L) { return L.z; }
+    static double *t(Level &L) { return L.t; }
+};
+template <>
+struct VT<float> {
+    static const float *wd(const Level &L) { return L.wd32; }
+    static float *y(Level &L) { return L.y32; }
+    static float *s(Level &L) { return L.s32; }
+    static float *r(Level &L) { return L.r32; }
+    static float *z(Level &L) { return L.z32; }
+    static float *t(Level &L) { return L.t32; }
+};
+
+// Pre-smoothing (nu_pre steps from s = 0) and residual on level l.
+// Returns the buffer that holds s.
+template <class T, class TY>
+T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
+    T *sv = VT<T>::s(L), *tv = VT<T>::t(L);
+    vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), y, sv, VT<T>::r(L), st, s);
+    if (h.prm.nu_pre > 1) {
+        for (int it = 1; it < h.prm.nu_pre; ++it) {
+            vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, nullptr, st, s);
+            std::swap(sv, tv);
+        }
+        vc_resid<T, TY>(L.A, L.cA, y, sv, VT<T>::r(L), st, s);
+    }
+    return sv;
+}
+
+// Post-smoothing (nu_post steps) into z; the last step fuses rho when dot.
+template <class T, class TY, class TZ>
+void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
+    T *tv = VT<T>::t(L);
+    for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
+        T *out = (tv == sv) ? VT<T>::s(L) : tv;
+        vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, nullptr, st, s);
+        sv = out;
+    }
+    if (dot) vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.partials, h.counter, st, s);
+    else vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, nullptr, st, s);
+}
+
+// z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.
+template <class T>
+void vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
+    const int L = h.nlev - 1;
+    if (L == 0) {
+        // one level: direct solve (FP64)
+        coarse_solve<double>(h.nL, h.cinv, y0, z0, st, s);
+        if (dot) dot_rho(h.nL, y0, z0, h.partials, h.counter, st, s);
+        return;
+    }
+    std::vector<T *> sv(h.nlev, nullptr);
+    for (int l = 0; l < L; ++l) {
+        Level &Lv = h.lev[l];
+        if (l == 0) sv[0] = smooth_pre<T, double>(h, Lv, y0, st, s);
+        else sv[l] = smooth_pre<T, T>(h, Lv, VT<T>::y(Lv), st, s);
+        vc_restrict<T>(Lv.R, Lv.cR, VT<T>::r(Lv), VT<T>::y(h.lev[l + 1]), st, s);
+    }
+    coarse_solve<T>(h.nL, h.cinv, VT<T>::y(h.lev[L]), VT<T>::z(h.lev[L]), st, s);
+    for (int l = L - 1; l >= 0; --l) {
+        Level &Lv = h.lev[l];
+        vc_prolong<T>(Lv.P, Lv.cP, VT<T>::z(h.lev[l + 1]), sv[l], st, s);
+        if (l == 0) smooth_post<T, double, double>(h, Lv, y0, sv[0], z0, dot, st, s);
+        else smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, st, s);
+    }
+}
+
+void vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
+    if (h.prm.precision == CAMG_MIXED_FP32) vcycle_t<float>(h, y0, z0, st, dot, s);
+    else vcycle_t<double>(h, y0, z0, st, dot, s);
+}
+
+// ---------------------------------------------------------------- PCG
+void ensure_hist(Hier &h, int cap) {
+    if (h.dhist_cap >= cap) return;
+    h.dhist = h.pool.alloc<double>(cap);
+    h.dhist_cap = cap;
+}
+
+camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t *iters, double *hist, int hist_cap,
+                      double *true_relres, hipStream_t s) {
+    const Csr &A = h.lev[0].A;
+    const int n = A.nr;
+    const int max_iter = h.prm.max_iter;
+    ensure_hist(h, max_iter + 1);
+    pcg_init(n, b, x, h.r, h.p[0], rtol, h.partials, h.counter, h.st, h.dhist, s);
+    h.hflag[0] = 0;
+    hipEvent_t ev[2];
+    HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+    } eg{ev};
+    // the first poll: b = 0 or an immediate stop
+    {
+        PcgState st0 = read1(h.st, s);
+        if (st0.done) h.hflag[0] = 1;
+    }
+    for (int k = 0; k < max_iter && !h.hflag[0]; ++k) {
+        vcycle(h, h.r, h.z, h.st, true, s);
+        pcg_spmv_p(A, h.lev[0].cA, h.z, h.p[k & 1], h.p[(k + 1) & 1], h.q, h.partials, h.counter, h.st, s);
+        pcg_update(n, h.p[(k + 1) & 1], h.q, x, h.r, h.partials, h.counter, h.st, h.dhist, h.dhist_cap,
+                   h.hflag_dev, s);
+        HIPC(hipEventRecord(ev[k & 1], s));
+        if (k >= 1) {
+            HIPC(hipEventSynchronize(ev[(k - 1) & 1]));
+            if (h.hflag[0]) break;
+        }
+    }
+    HIPC(hipStreamSynchronize(s));
+    const PcgState st = read1(h.st, s);
+    const int it = st.iter;
+    if (iters) *iters = it;
+    if (hist && hist_cap > 0) {
+        const int m = std::min(hist_cap, it + 1);
+        HIPC(hipMemcpyAsync(hist, h.dhist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    }
+    if (true_relres) {
+        true_residual(A, h.lev[0].cA, b, x, h.partials, h.counter, h.sc, s);
+        const double t2 = read1(h.sc, s);
+        *true_relres = st.bnorm > 0.0 ? std::sqrt(t2) / st.bnorm : 0.0;
+    }
+    HIPC(hipStreamSynchronize(s));
+    if (st.status == (int32_t)CAMG_E_BREAKDOWN) {
+        g_last_error = "CG breakdown: p.Ap <= 0 or r.z <= 0";
+        return CAMG_E_BREAKDOWN;
+    }
+    if (!st.done) {
+        g_last_error = "max_iter reached";
+        return CAMG_E_MAXIT;
+    }
+    return CAMG_OK;
+}
+
+Hier *as_hier(camg_handle h) {
+    if (!h) fail(CAMG_E_ARG, "null handle");
+    return reinterpret_cast<Hier *>(h);
+}
+
+}  // namespace
+}  // namespace camg
+
+using namespace camg;
+
+struct camg_hier : public camg::Hier {};
+
+extern "C" {
+
+int32_t camg_abi_version(void) { return CAMG_ABI_VERSION; }
+
+const char *camg_status_str(camg_status s) {
+    switch (s) {
+    case CAMG_OK: return "ok";
+    case CAMG_E_MAXIT: return "maximum number of iterations reached";
+    case CAMG_E_ARG: return "invalid argument";
+    case CAMG_E_CSR: return "malformed or unsupported CSR matrix";
+    case CAMG_E_NOT_SPD: return "matrix is not symmetric positive definite";
+    case CAMG_E_BREAKDOWN: return "conjugate gradient breakdown";
+    case CAMG_E_COARSE: return "coarsening stalled";
+    case CAMG_E_NOMEM: return "out of memory";
+    case CAMG_E_DEVICE: return "HIP runtime error";
+    case CAMG_E_BUSY: return "handle busy";
+    }
+    return "unknown status";
+}
+
+const char *camg_last_error(void) { return camg::g_last_error.c_str(); }
+
+void camg_params_default(camg_params *p) {
+    if (!p) return;
+    p->theta = 0.25;
+    p->seed = 0;
+    p->nu_pre = 1;
+    p->nu_post = 1;
+    p->omega = 0.0;
+    p->max_levels = 25;
+    p->max_coarse = 256;
+    p->precision = CAMG_FP64;
+    p->max_iter = 1000;
+}
+
+static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                                const camg_params *params, void *stream, bool host_in, camg_handle *out) {
+    return guarded([&] {
+        if (!out) fail(CAMG_E_ARG, "null output handle");
+        *out = nullptr;
+        if (n < 1 || !rp || !ci || !v) fail(CAMG_E_ARG, "n < 1 or null CSR array");
+        std::unique_ptr<camg_hier> h(new camg_hier());
+        if (params) h->prm = *params;
+        else camg_params_default(&h->prm);
+        check_params(h->prm);
+        HIPC(hipGetDevice(&h->device));
+        build_hierarchy(*h, n, rp, ci, v, host_in, (hipStream_t)stream);
+        *out = h.release();
+    });
+}
+
+camg_status camg_setup(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                       const camg_params *params, camg_handle *out) {
+    if (n >= 1 && row_ptr && (row_ptr[0] != 0 || row_ptr[n] < 0)) {
+        g_last_error = "row pointer is not 0-based";
+        if (out) *out = nullptr;
+        return CAMG_E_CSR;
+    }
+    return setup_common(n, row_ptr, col_idx, val, params, nullptr, true, out);
+}
+
+camg_status camg_setup_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
+                           const camg_params *params, void *hip_stream, camg_handle *out) {
+    return setup_common(n, d_row_ptr, d_col_idx, d_val, params, hip_stream, false, out);
+}
+
+camg_status camg_solve_dev(camg_handle hh, const double *d_b, double rtol, double *d_x, int32_t *iters,
+                           double *hist, int32_t hist_cap, double *true_relres, void *hip_stream) {
+    camg_status ret = CAMG_OK;
+    camg_status st = guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!d_b || !d_x) fail(CAMG_E_ARG, "null vector");
+        if (!std::isfinite(rtol)) fail(CAMG_E_ARG, "rtol must be finite");
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        ret = solve_dev(*h, d_b, rtol, d_x, iters, hist, hist_cap, true_relres, (hipStream_t)hip_stream);
+    });
+    return st != CAMG_OK ? st : ret;
+}
+
+camg_status camg_solve(camg_handle hh, const double *b, double rtol, double *x, int32_t *iters, double *hist,
+                       int32_t hist_cap, double *true_relres) {
+    camg_status ret = CAMG_OK;
+    camg_status st = guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!b || !x) fail(CAMG_E_ARG, "null vector");
+        if (!std::isfinite(rtol)) fail(CAMG_E_ARG, "rtol must be finite");
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        const int n = h->lev[0].A.nr;
+        Pool io;
+        double *db = io.alloc<double>(n), *dx = io.alloc<double>(n);
+        HIPC(hipMemcpy(db, b, sizeof(double) * n, hipMemcpyHostToDevice));
+        ret = solve_dev(*h, db, rtol, dx, iters, hist, hist_cap, true_relres, nullptr);
+        HIPC(hipMemcpy(x, dx, sizeof(double) * n, hipMemcpyDeviceToHost));
+    });
+    return st != CAMG_OK ? st : ret;
+}
+
+camg_status camg_vcycle_dev(camg_handle hh, const double *d_y, double *d_z, void *hip_stream) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!d_y || !d_z) fail(CAMG_E_ARG, "null vector");
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        vcycle(*h, d_y, d_z, nullptr, false, (hipStream_t)hip_stream);
+        HIPC(hipStreamSynchronize((hipStream_t)hip_stream));
+    });
+}
+
+camg_status camg_info(camg_handle hh, camg_info_t *info) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!info) fail(CAMG_E_ARG, "null info");
+        std::memset(info, 0, sizeof(*info));
+        info->levels = h->nlev;
+        double sn = 0, sz = 0;
+        for (int l = 0; l < h->nlev; ++l) {
+            const Level &L = h->lev[l];
+            info->n[l] = L.A.nr;
+            info->nnz[l] = L.A.nnz;
+            info->nnz_p[l] = l < h->nlev - 1 ? L.P.nnz : 0;
+            info->pmis_rounds[l] = L.rounds;
+            info->omega[l] = L.omega;
+            sn += L.A.nr;
+            sz += (double)L.A.nnz;
+        }
+        info->grid_complexity = sn / h->lev[0].A.nr;
+        info->operator_complexity = sz / (double)h->lev[0].A.nnz;
+        info->device_bytes = h->pool.bytes;
+        info->setup_ms = h->setup_ms;
+        info->precision = h->prm.precision;
+    });
+}
+
+camg_status camg_level_sizes(camg_handle hh, int32_t l, int32_t *n, int64_t *nnz_a, int64_t *nnz_p, int32_t *nc) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (l < 0 || l >= h->nlev) fail(CAMG_E_ARG, "level out of range");
+        const Level &L = h->lev[l];
+        const bool last = l == h->nlev - 1;
+        if (n) *n = L.A.nr;
+        if (nnz_a) *nnz_a = L.A.nnz;
+        if (nnz_p) *nnz_p = last ? 0 : L.P.nnz;
+        if (nc) *nc = last ? 0 : L.P.nc;
+    });
+}
+
+static void copy_csr_out(const Csr &M, void *a, void *b, void *c) {
+    if (a) HIPC(hipMemcpy(a, M.rp, sizeof(int32_t) * ((size_t)M.nr + 1), hipMemcpyDeviceToHost));
+    if (b && M.nnz) HIPC(hipMemcpy(b, M.ci, sizeof(int32_t) * (size_t)M.nnz, hipMemcpyDeviceToHost));
+    if (c && M.nnz) HIPC(hipMemcpy(c, M.v, sizeof(double) * (size_t)M.nnz, hipMemcpyDeviceToHost));
+}
+
+camg_status camg_export_level(camg_handle hh, int32_t l, int32_t what, void *a, void *b, void *c) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (l < 0 || l >= h->nlev) fail(CAMG_E_ARG, "level out of range");
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        const Level &L = h->lev[l];
+        const bool last = l == h->nlev - 1;
+        const int n = L.A.nr;
+        if (what != CAMG_X_A && what != CAMG_X_COARSE_INV && last) fail(CAMG_E_ARG, "no such data on the last level");
+        if (!a) fail(CAMG_E_ARG, "null output");
+        switch (what) {
+        case CAMG_X_A: copy_csr_out(L.A, a, b, c); break;
+        case CAMG_X_P: copy_csr_out(L.P, a, b, c); break;
+        case CAMG_X_R: copy_csr_out(L.R, a, b, c); break;
+        case CAMG_X_CF: HIPC(hipMemcpy(a, L.cf, (size_t)n, hipMemcpyDeviceToHost)); break;
+        case CAMG_X_STRONG: HIPC(hipMemcpy(a, L.strong, (size_t)L.A.nnz, hipMemcpyDeviceToHost)); break;
+        case CAMG_X_DINV: HIPC(hipMemcpy(a, L.dinv, sizeof(double) * n, hipMemcpyDeviceToHost)); break;
+        case CAMG_X_OMEGA: std::memcpy(a, &L.omega, sizeof(double)); break;
+        case CAMG_X_STCNT: HIPC(hipMemcpy(a, L.stcnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost)); break;
+        case CAMG_X_COARSE_INV:
+            if (!last) fail(CAMG_E_ARG, "the dense inverse exists on the last level only");
+            HIPC(hipMemcpy(a, h->cinv, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToHost));
+            break;
+        default: fail(CAMG_E_ARG, "unknown export selector");
+        }
+    });
+}
+
+camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, const double *a_val, int32_t nc,
+                          const int32_t *p_rp, const int32_t *p_ci, const double *p_val, int32_t **c_rp,
+                          int32_t **c_ci, double **c_val, int64_t *nnz_out) {
+    return guarded([&] {
+        if (n < 1 || nc < 0 || !a_rp || !a_ci || !a_val || !p_rp || !p_ci || !p_val || !c_rp || !c_ci || !c_val)
+            fail(CAMG_E_ARG, "bad argument");
+        Pool tmp, outp;
+        hipStream_t s = nullptr;
+        auto up = [&](Csr &M, int nr, int ncol, const int32_t *rp, const int32_t *ci, const double *v) {
+            M.nr = nr;
+            M.nc = ncol;
+            M.nnz = rp[nr];
+            M.rp = tmp.alloc<int32_t>((size_t)nr + 1);
+            M.ci = tmp.alloc<int32_t>(std::max<int64_t>(M.nnz, 1));
+            M.v = tmp.alloc<double>(std::max<int64_t>(M.nnz, 1));
+            HIPC(hipMemcpy(M.rp, rp, sizeof(int32_t) * ((size_t)nr + 1), hipMemcpyHostToDevice));
+            if (M.nnz) {
+                HIPC(hipMemcpy(M.ci, ci, sizeof(int32_t) * (size_t)M.nnz, hipMemcpyHostToDevice));
+                HIPC(hipMemcpy(M.v, v, sizeof(double) * (size_t)M.nnz, hipMemcpyHostToDevice));
+            }
+        };
+        Csr A, P, R, AP, C;
+        up(A, n, n, a_rp, a_ci, a_val);
+        up(P, n, nc, p_rp, p_ci, p_val);
+        R.nr = nc;
+        R.nc = n;
+        R.nnz = P.nnz;
+        int32_t *ccnt = tmp.alloc<int32_t>(std::max(nc, 1));
+        column_counts(P, ccnt, s);
+        int64_t *rrp64 = tmp.alloc<int64_t>((size_t)nc + 1);
+        scan_i32_to_i64(ccnt, rrp64, nc, tmp, s);
+        R.rp = tmp.alloc<int32_t>((size_t)nc + 1);
+        narrow_i64(rrp64, R.rp, nc, s);
+        R.ci = tmp.alloc<int32_t>(std::max<int64_t>(R.nnz, 1));
+        R.v = tmp.alloc<double>(std::max<int64_t>(R.nnz, 1));
+        transpose_csr(P, R, tmp, s);
+        spgemm(A, P, AP, tmp, tmp, s);
+        spgemm(R, AP, C, outp, tmp, s);
+        HIPC(hipDeviceSynchronize());
+        *c_rp = (int32_t *)std::malloc(sizeof(int32_t) * ((size_t)nc + 1));
+        *c_ci = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(C.nnz, 1));
+        *c_val = (double *)std::malloc(sizeof(double) * (size_t)std::max<int64_t>(C.nnz, 1));
+        if (!*c_rp || !*c_ci || !*c_val) fail(CAMG_E_NOMEM, "host allocation failed");
+        copy_csr_out(C, *c_rp, *c_ci, *c_val);
+        if (nnz_out) *nnz_out = C.nnz;
+    });
+}
+
+void camg_free_host(void *p) { std::free(p); }
+
+camg_status camg_destroy(camg_handle hh) {
+    if (!hh) return CAMG_OK;
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        (void)hipSetDevice(h->device);
+        (void)hipDeviceSynchronize();
+        if (h->hflag) (void)hipHostFree(h->hflag);
+        delete static_cast<camg_hier *>(hh);
+    });
+}
+
+camg_status camg_solve_multi_dev(camg_handle, int32_t, const double *, double, double *, int32_t *, double *, int32_t,
+                                 double *, void *) {
+    camg::g_last_error = "multi-RHS solve not available in this build";
+    return CAMG_E_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// Internal declarations shared by the translation units of libcamg.
+// Kernels live next to their host launchers; the driver (camg.hip) only
+// calls the launchers declared here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "camg.h"
+
+namespace camg {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    camg_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(camg_status s, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPC(x) ::camg::hip_check((x), #x)
+
+// ---------------------------------------------------------------- memory
+// Device allocations owned by a handle (or by a set-up scratch pool).
+struct Pool {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    void *raw(size_t nbytes);
+    template <class T> T *alloc(size_t count) { return static_cast<T *>(raw(count * sizeof(T))); }
+    void release();
+    ~Pool() { release(); }
+};
+
+struct Csr {
+    int32_t nr = 0, nc = 0;
+    int64_t nnz = 0;
+    int32_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    double *v = nullptr;
+    float *v32 = nullptr;   // FP32 copy of the values (mixed precision)
+};
+
+// Launch shape of a row-parallel kernel: `lpr` lanes per row.
+struct RowCfg {
+    int lpr = 8;
+};
+
+struct Level {
+    Csr A, P, R;
+    double *dinv = nullptr;   // 1 / a_ii
+    double *wd = nullptr;     // omega * dinv_i
+    float *wd32 = nullptr;
+    double omega = 0.0;
+    int8_t *cf = nullptr;
+    uint8_t *strong = nullptr;
+    int32_t *stcnt = nullptr;
+    int32_t rounds = 0;
+    // V-cycle work vectors (y: right-hand side, s: smoothed iterate,
+    // r: residual, z: result).  Level 0 borrows y and z from PCG.
+    double *y = nullptr, *s = nullptr, *r = nullptr, *z = nullptr, *t = nullptr;
+    float *y32 = nullptr, *s32 = nullptr, *r32 = nullptr, *z32 = nullptr, *t32 = nullptr;
+    RowCfg cA, cP, cR;
+};
+
+// Scalars of one PCG recurrence, resident on the device.
+struct PcgState {
+    double rho, rho_old, sigma, alpha, beta, rnorm, bnorm, tol;
+    int32_t iter, done, status, pad;
+};
+
+struct Hier {
+    int device = 0;
+    camg_params prm{};
+    std::vector<Level> lev;
+    int nlev = 0;
+    int nL = 0;             // order of the last level
+    double *cinv = nullptr; // dense inverse of the last level (row-major nL x nL)
+    float *cinv32 = nullptr;
+    Pool pool;              // everything the handle owns
+    // PCG work
+    double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *t = nullptr;
+    double *partials = nullptr;  // per-block partial sums
+    double *sc = nullptr;        // device scalars (true residual)
+    unsigned *counter = nullptr; // last-block ticket
+    PcgState *st = nullptr;      // device state
+    double *dhist = nullptr;     // device residual history
+    int dhist_cap = 0;
+    int32_t *hflag = nullptr;    // host-mapped convergence flags (one per poll slot)
+    int32_t *hflag_dev = nullptr;
+    std::atomic<int> busy{0};
+    double setup_ms = 0.0;
+    // multi-RHS work (allocated on first use for a given k)
+    int mk = 0;
+    double *mr = nullptr, *mz = nullptr, *mp[2] = {nullptr, nullptr}, *mq = nullptr;
+    PcgState *mst = nullptr;
+    double *mpartials = nullptr;
+    double *mhist = nullptr;
+    std::vector<void *> mallocs;
+};
+
+constexpr int kBlock = 256;          // threads per block for row kernels
+constexpr int kMaxGrid = 2048;       // cap on blocks of the reduction kernels
+
+// ---------------------------------------------------------------- scan (setup.hip)
+// out[0..n] = exclusive prefix sums of in[0..n-1]; out[n] = total.
+void scan_i32_to_i64(const int32_t *in, int64_t *out, int n, Pool &tmp, hipStream_t s);
+void scan_i64(const int64_t *in, int64_t *out, int n, Pool &tmp, hipStream_t s);
+// rp32[i] = (int32) v64[i] for i in [0, n]; host checks the total first.
+void narrow_i64(const int64_t *v64, int32_t *rp32, int n, hipStream_t s);
+
+// ---------------------------------------------------------------- set-up kernels (setup.hip)
+// flags[0]: row pointer malformed; flags[1]: column out of range / not increasing;
+// flags[2]: non-finite value; flags[3]: diagonal missing; flags[4]: asymmetric;
+// flags[5]: non-positive diagonal.
+void validate_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags, hipStream_t s);
+void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
+                   unsigned long long *amax_bits, hipStream_t s);
+void validate_sym(int n, const int32_t *rp, const int32_t *ci, const double *v, const unsigned long long *amax_bits,
+                  int32_t *flags, int32_t *tpos, hipStream_t s);
+void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s);
+void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta, uint8_t *strong,
+              int32_t *stcnt, hipStream_t s);
+void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
+               int32_t *undecided, hipStream_t s);
+void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
+                const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc, int32_t *undecided,
+                hipStream_t s);
+void cf_flags(int n, const int8_t *cf, int32_t *isc, hipStream_t s);
+void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                  int32_t *cnt, hipStream_t s);
+void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+                 const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s);
+void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
+void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
+void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
+                     unsigned long long *qmax_bits, int32_t *flags, hipStream_t s);
+void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t s);
+void to_f32(int64_t n, const double *in, float *out, hipStream_t s);
+void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s);
+void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
+void chol_inverse(int n, const double *L, double *X, hipStream_t s);
+
+// ---------------------------------------------------------------- SpGEMM (spgemm.hip)
+// Z = X Y with the full symbolic pattern, rows sorted; for every output
+// entry the products are added in ascending order of the inner index.
+// Z's arrays are allocated from `out`.
+void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- solve (solve.hip)
+RowCfg choose_cfg(int n, int64_t nnz);
+int grid_for(int n, const RowCfg &c);
+
+// V-cycle building blocks.  T: value type of the level (double, or float
+// in mixed precision); TY: type of the right-hand side y (level 0 reads
+// the FP64 PCG residual); TZ: type of the output; DOT: fuse rho = y.z and
+// beta into the kernel (level 0 inside PCG).  st may be null (standalone
+// V-cycle); otherwise the kernels return at once when st->done is set.
+template <class T, class TY>
+void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const TY *y, T *s, T *r, const PcgState *st, hipStream_t str);
+template <class T, class TY, class TZ, bool DOT>
+void vc_post(const Csr &A, const RowCfg &c, const T *wd, const TY *y, const T *s, TZ *z, double *partials,
+             unsigned *counter, PcgState *st, hipStream_t str);
+template <class T, class TY>
+void vc_resid(const Csr &A, const RowCfg &c, const TY *y, const T *s, T *r, const PcgState *st, hipStream_t str);
+template <class T>
+void vc_restrict(const Csr &R, const RowCfg &c, const T *r, T *yc, const PcgState *st, hipStream_t str);
+template <class T>
+void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState *st, hipStream_t str);
+template <class T>
+void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *st, hipStream_t str);
+void dot_rho(int n, const double *y, const double *z, double *partials, unsigned *counter, PcgState *st,
+             hipStream_t s);
+
+// PCG outer kernels
+void pcg_init(int n, const double *b, double *x, double *r, double *p0, double rtol, double *partials,
+              unsigned *counter, PcgState *st, double *hist, hipStream_t s);
+void pcg_spmv_p(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
+                double *partials, unsigned *counter, PcgState *st, hipStream_t s);
+void pcg_update(int n, const double *p, const double *q, double *x, double *r, double *partials, unsigned *counter,
+                PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s);
+void true_residual(const Csr &A, const RowCfg &c, const double *b, const double *x, double *partials,
+                   unsigned *counter, double *out2, hipStream_t s);
+void fill_zero(int64_t n, double *x, hipStream_t s);
+
+}  // namespace camg

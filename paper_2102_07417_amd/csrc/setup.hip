@@ -1,0 +1,543 @@
+// Hierarchy set-up kernels (Alg. "AMG Set-up" of the paper): input checks,
+// strength of connection, PMIS rounds, direct interpolation, transpose,
+// Jacobi weights and the dense last-level factorisation.
+//
+// Every kernel that produces a value the CPU reference also produces does
+// the same floating-point operations in the same order (one thread per row,
+// CSR order, no fused multiply-add: the library is built with
+// -ffp-contract=off), so patterns and values of the hierarchy are
+// reproducible bit for bit.
+#include "devutil.hpp"
+#include "internal.hpp"
+
+namespace camg {
+
+namespace {
+
+inline int nblocks(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+template <class T>
+__device__ void block_exclusive_scan(int64_t (&v)[kScanItems], int64_t &total) {
+    int64_t local = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t t = v[i];
+        v[i] = local;
+        local += t;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __shared__ int64_t ws[kBlock / 64];
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    int64_t base = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        if (i < w) base += ws[i];
+        total += ws[i];
+    }
+    const int64_t excl = base + x - local;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) v[i] += excl;
+    __syncthreads();
+}
+
+template <class T>
+__global__ void k_scan_tiles(const T *in, int n, int64_t *tile_sum) {
+    int64_t v[kScanItems];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? (int64_t)in[base + i] : 0;
+    int64_t total;
+    block_exclusive_scan<T>(v, total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of the tile sums in place, total in [nt]
+__global__ void k_scan_tile_sums(int64_t *ts, int nt) {
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nt; b0 += kScanTile) {
+        int64_t v[kScanItems];
+        const int base = b0 + threadIdx.x * kScanItems;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < nt) ? ts[base + i] : 0;
+        int64_t total;
+        block_exclusive_scan<int64_t>(v, total);
+        const int64_t c = carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i)
+            if (base + i < nt) ts[base + i] = v[i] + c;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ts[nt] = carry;
+}
+
+template <class T>
+__global__ void k_scan_apply(const T *in, int n, const int64_t *ts, int64_t *out) {
+    int64_t v[kScanItems];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? (int64_t)in[base + i] : 0;
+    int64_t total;
+    block_exclusive_scan<T>(v, total);
+    const int64_t off = ts[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) out[base + i] = v[i] + off;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = ts[gridDim.x];
+}
+
+template <class T>
+void scan_impl(const T *in, int64_t *out, int n, Pool &tmp, hipStream_t s) {
+    const int nt = std::max(1, (n + kScanTile - 1) / kScanTile);
+    int64_t *ts = tmp.alloc<int64_t>(nt + 1);
+    k_scan_tiles<T><<<nt, kBlock, 0, s>>>(in, n, ts);
+    k_scan_tile_sums<<<1, kBlock, 0, s>>>(ts, nt);
+    k_scan_apply<T><<<nt, kBlock, 0, s>>>(in, n, ts, out);
+    HIPC(hipGetLastError());
+}
+
+__global__ void k_narrow(const int64_t *v, int32_t *o, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) o[i] = (int32_t)v[i];
+}
+
+// ---------------------------------------------------------------- validation
+__global__ void k_val_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(&flags[0], 1);
+    if (i < n && rp[i + 1] < rp[i]) atomicOr(&flags[0], 1);
+}
+
+__global__ void k_val_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
+                           unsigned long long *amax) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int bad_col = 0, bad_val = 0, has_diag = 0, bad_diag = 0;
+    double m = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int c = ci[e];
+        if (c < 0 || c >= n || (e > rp[i] && c <= ci[e - 1])) bad_col = 1;
+        double a = v[e];
+        if (!isfinite(a)) bad_val = 1;
+        else if (fabs(a) > m) m = fabs(a);
+        if (c == i) {
+            has_diag = 1;
+            if (!(a > 0.0)) bad_diag = 1;
+        }
+    }
+    if (bad_col) atomicOr(&flags[1], 1);
+    if (bad_val) atomicOr(&flags[2], 1);
+    if (!has_diag) atomicOr(&flags[3], 1);
+    if (bad_diag) atomicOr(&flags[5], 1);
+    atomicMax(amax, (unsigned long long)__double_as_longlong(m));
+}
+
+// tpos[e] = position of entry (j, i) in row j for entry e = (i, j); checks
+// structural and numerical symmetry when flags != nullptr.
+__global__ void k_tpos(int n, const int32_t *rp, const int32_t *ci, const double *v,
+                       const unsigned long long *amax, int32_t *flags, int32_t *tpos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double tol = flags ? 1e-12 * __longlong_as_double((long long)*amax) : 0.0;
+    int bad = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int j = ci[e];
+        int t = find_col(ci, rp[j], rp[j + 1], i);
+        tpos[e] = t;
+        if (t < 0) bad = 1;
+        else if (flags && fabs(v[e] - v[t]) > tol) bad = 1;
+    }
+    if (bad && flags) atomicOr(&flags[4], 1);
+}
+
+// ---------------------------------------------------------------- strength
+// Classical strength with threshold: m_i = max_{k != i} (-a_ik);
+// j in S_i iff j != i, m_i > 0 and -a_ij >= theta * m_i (one rounded product).
+__global__ void k_strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
+                           uint8_t *strong, int32_t *stcnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int have = 0;
+    double m = 0.0;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0; e < e1; ++e) {
+        if (ci[e] == i) continue;
+        double neg = -v[e];
+        if (!have || neg > m) { m = neg; have = 1; }
+    }
+    const double thr = theta * m;
+    for (int e = e0; e < e1; ++e) {
+        const int j = ci[e];
+        const int s = (j != i && have && m > 0.0 && -v[e] >= thr) ? 1 : 0;
+        strong[e] = (uint8_t)s;
+        if (s) atomicAdd(&stcnt[j], 1);
+    }
+}
+
+// ---------------------------------------------------------------- PMIS
+constexpr int8_t kF = -1, kU = 0, kC = 1;
+
+__global__ void k_pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
+                            int32_t *undecided) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int und = 0;
+    if (i < n) {
+        const uint64_t c = ((uint64_t)(uint32_t)level << 40) + (uint64_t)(uint32_t)i;
+        u[i] = splitmix64(seed, c) >> 11;
+        const int8_t s = stcnt[i] == 0 ? kF : kU;
+        state[i] = s;
+        und = (s == kU);
+    }
+    und = wave_sum_i(und);
+    if ((threadIdx.x & 63) == 0 && und) atomicAdd(undecided, und);
+}
+
+__device__ __forceinline__ bool key_gt(const int32_t *cnt, const uint64_t *u, int a, int b) {
+    const int ca = cnt[a], cb = cnt[b];
+    if (ca != cb) return ca > cb;
+    const uint64_t ua = u[a], ub = u[b];
+    if (ua != ub) return ua > ub;
+    return a > b;
+}
+
+// Selection: undecided i joins the new C set if its measure beats every
+// undecided neighbour in S_i u S_i^T (state as at the start of the round).
+__global__ void k_pmis_select(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                              const int32_t *tpos, const int32_t *stcnt, const uint64_t *u, const int8_t *state,
+                              int8_t *newc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int8_t sel = 0;
+    if (state[i] == kU) {
+        sel = 1;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            if (j == i || state[j] != kU) continue;
+            const int te = tpos[e];
+            if (!(strong[e] || (te >= 0 && strong[te]))) continue;
+            if (key_gt(stcnt, u, j, i)) { sel = 0; break; }
+        }
+    }
+    newc[i] = sel;
+}
+
+// Update: new C points become C; undecided points that depend strongly on
+// a new C point become F.
+__global__ void k_pmis_update(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                              const int8_t *newc, int8_t *state, int32_t *undecided) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int und = 0;
+    if (i < n && state[i] == kU) {
+        if (newc[i]) state[i] = kC;
+        else {
+            int f = 0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e)
+                if (strong[e] && newc[ci[e]]) { f = 1; break; }
+            if (f) state[i] = kF;
+            else und = 1;
+        }
+    }
+    und = wave_sum_i(und);
+    if ((threadIdx.x & 63) == 0 && und) atomicAdd(undecided, und);
+}
+
+__global__ void k_cf_flags(int n, const int8_t *cf, int32_t *isc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) isc[i] = cf[i] == kC ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- direct interpolation
+__global__ void k_interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                               const int8_t *cf, int32_t *cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    if (cf[i] == kC) c = 1;
+    else
+        for (int e = rp[i]; e < rp[i + 1]; ++e)
+            if (strong[e] && cf[ci[e]] == kC) ++c;
+    cnt[i] = c;
+}
+
+// C row: a single 1 at cmap(i).  F row: w_ij = -(alpha_i a_ij) / d_i over
+// C_i^S, d_i = a_ii + positive off-diagonals, alpha_i = (sum of negative
+// off-diagonals) / (sum over C_i^S of a_ij); sums in CSR order.
+__global__ void k_interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+                              const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = prp[i];
+    if (cf[i] == kC) {
+        pci[o] = (int32_t)cmap[i];
+        pv[o] = 1.0;
+        return;
+    }
+    if (prp[i + 1] == o) return;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    double d = 0.0, num = 0.0, den = 0.0;
+    for (int e = e0; e < e1; ++e)
+        if (ci[e] == i) d = v[e];
+    for (int e = e0; e < e1; ++e) {
+        if (ci[e] == i) continue;
+        const double a = v[e];
+        if (a > 0.0) d = d + a;
+        else if (a < 0.0) num = num + a;
+    }
+    for (int e = e0; e < e1; ++e)
+        if (strong[e] && cf[ci[e]] == kC) den = den + v[e];
+    const double alpha = num / den;
+    for (int e = e0; e < e1; ++e)
+        if (strong[e] && cf[ci[e]] == kC) {
+            pci[o] = (int32_t)cmap[ci[e]];
+            pv[o] = -(alpha * v[e]) / d;
+            ++o;
+        }
+}
+
+// ---------------------------------------------------------------- transpose
+__global__ void k_col_count(int64_t nnz, const int32_t *ci, int32_t *cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[ci[e]], 1);
+}
+
+__global__ void k_transpose_fill(int nr, const int32_t *rp, const int32_t *ci, const double *v, int32_t *fill,
+                                 int32_t *tci, double *tv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const int c = ci[e];
+        const int pos = atomicAdd(&fill[c], 1);
+        tci[pos] = i;
+        tv[pos] = v[e];
+    }
+}
+
+// rows of the transpose come out of k_transpose_fill in arbitrary order:
+// insertion sort each row by column (rows are short)
+__global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    for (int e = e0 + 1; e < e1; ++e) {
+        const int c = ci[e];
+        const double x = v[e];
+        int f = e - 1;
+        while (f >= e0 && ci[f] > c) {
+            ci[f + 1] = ci[f];
+            v[f + 1] = v[f];
+            --f;
+        }
+        ci[f + 1] = c;
+        v[f + 1] = x;
+    }
+}
+
+// ---------------------------------------------------------------- Jacobi weight
+// dinv_i = 1 / a_ii and q_i = (sum_j |a_ij|) / a_ii (CSR order); the max of
+// q over rows is the Gershgorin bound of rho(D^{-1} A).
+__global__ void k_diag_gersh(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
+                             unsigned long long *qmax, int32_t *flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0, d = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        s = s + fabs(v[e]);
+        if (ci[e] == i) d = v[e];
+    }
+    if (!(d > 0.0)) {
+        atomicOr(&flags[5], 1);
+        dinv[i] = 0.0;
+        return;
+    }
+    dinv[i] = 1.0 / d;
+    const double q = s / d;
+    atomicMax(qmax, (unsigned long long)__double_as_longlong(q));
+}
+
+__global__ void k_scale(int n, double omega, const double *dinv, double *wd) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wd[i] = omega * dinv[i];
+}
+
+__global__ void k_to_f32(int64_t n, const double *in, float *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+// ---------------------------------------------------------------- last level
+__global__ void k_dense_zero(int64_t nn, double *D) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nn) D[i] = 0.0;
+}
+
+__global__ void k_dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v, double *D) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) D[(int64_t)i * n + ci[e]] = v[e];
+}
+
+// Right-looking dense Cholesky by one block, in place (lower triangle).
+__global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int32_t *flags) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            const double s = D[(int64_t)j * n + j];
+            if (!(s > 0.0)) bad = 1;
+            else D[(int64_t)j * n + j] = sqrt(s);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double ljj = D[(int64_t)j * n + j];
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) D[(int64_t)i * n + j] = D[(int64_t)i * n + j] / ljj;
+        __syncthreads();
+        // trailing update of the lower triangle: rows i > j, columns j < k <= i
+        const int m = n - j - 1;
+        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+            const int a = (int)(t / m), b = (int)(t % m);
+            if (b > a) continue;
+            const int i = j + 1 + a, k = j + 1 + b;
+            D[(int64_t)i * n + k] = D[(int64_t)i * n + k] - D[(int64_t)i * n + j] * D[(int64_t)k * n + j];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bad) atomicOr(&flags[5], 1);
+}
+
+// X = (L L^T)^{-1}, one thread per column: forward then backward substitution.
+__global__ void k_chol_inverse(int n, const double *L, double *X) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int i = 0; i < n; ++i) {
+        double t = (i == j) ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) t = t - L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
+        X[(int64_t)i * n + j] = t / L[(int64_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = X[(int64_t)i * n + j];
+        for (int k = i + 1; k < n; ++k) t = t - L[(int64_t)k * n + i] * X[(int64_t)k * n + j];
+        X[(int64_t)i * n + j] = t / L[(int64_t)i * n + i];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void scan_i32_to_i64(const int32_t *in, int64_t *out, int n, Pool &tmp, hipStream_t s) { scan_impl(in, out, n, tmp, s); }
+void scan_i64(const int64_t *in, int64_t *out, int n, Pool &tmp, hipStream_t s) { scan_impl(in, out, n, tmp, s); }
+void narrow_i64(const int64_t *v, int32_t *o, int n, hipStream_t s) {
+    k_narrow<<<nblocks(n + 1), kBlock, 0, s>>>(v, o, n);
+    HIPC(hipGetLastError());
+}
+
+void validate_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags, hipStream_t s) {
+    k_val_rowptr<<<nblocks(n), kBlock, 0, s>>>(n, nnz, rp, flags);
+    HIPC(hipGetLastError());
+}
+void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
+                   unsigned long long *amax, hipStream_t s) {
+    k_val_rows<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, flags, amax);
+    HIPC(hipGetLastError());
+}
+void validate_sym(int n, const int32_t *rp, const int32_t *ci, const double *v, const unsigned long long *amax,
+                  int32_t *flags, int32_t *tpos, hipStream_t s) {
+    k_tpos<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, amax, flags, tpos);
+    HIPC(hipGetLastError());
+}
+void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s) {
+    k_tpos<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, nullptr, nullptr, nullptr, tpos);
+    HIPC(hipGetLastError());
+}
+void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta, uint8_t *strong,
+              int32_t *stcnt, hipStream_t s) {
+    HIPC(hipMemsetAsync(stcnt, 0, sizeof(int32_t) * (size_t)n, s));
+    k_strength<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, theta, strong, stcnt);
+    HIPC(hipGetLastError());
+}
+void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
+               int32_t *undecided, hipStream_t s) {
+    HIPC(hipMemsetAsync(undecided, 0, sizeof(int32_t), s));
+    k_pmis_init<<<nblocks(n), kBlock, 0, s>>>(n, stcnt, seed, level, u, state, undecided);
+    HIPC(hipGetLastError());
+}
+void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
+                const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc, int32_t *undecided,
+                hipStream_t s) {
+    k_pmis_select<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, tpos, stcnt, u, state, newc);
+    HIPC(hipMemsetAsync(undecided, 0, sizeof(int32_t), s));
+    k_pmis_update<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, newc, state, undecided);
+    HIPC(hipGetLastError());
+}
+void cf_flags(int n, const int8_t *cf, int32_t *isc, hipStream_t s) {
+    k_cf_flags<<<nblocks(n), kBlock, 0, s>>>(n, cf, isc);
+    HIPC(hipGetLastError());
+}
+void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                  int32_t *cnt, hipStream_t s) {
+    k_interp_count<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, cf, cnt);
+    HIPC(hipGetLastError());
+}
+void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+                 const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s) {
+    k_interp_fill<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, strong, cf, cmap, prp, pci, pv);
+    HIPC(hipGetLastError());
+}
+void column_counts(const Csr &X, int32_t *cnt, hipStream_t s) {
+    HIPC(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)X.nc, s));
+    if (X.nnz > 0) k_col_count<<<nblocks(X.nnz), kBlock, 0, s>>>(X.nnz, X.ci, cnt);
+    HIPC(hipGetLastError());
+}
+void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s) {
+    // XT.rp must already hold the row pointer (from column_counts + scan)
+    int32_t *fill = tmp.alloc<int32_t>((size_t)X.nc + 1);
+    HIPC(hipMemcpyAsync(fill, XT.rp, sizeof(int32_t) * ((size_t)X.nc + 1), hipMemcpyDeviceToDevice, s));
+    k_transpose_fill<<<nblocks(X.nr), kBlock, 0, s>>>(X.nr, X.rp, X.ci, X.v, fill, XT.ci, XT.v);
+    k_sort_rows<<<nblocks(X.nc), kBlock, 0, s>>>(X.nc, XT.rp, XT.ci, XT.v);
+    HIPC(hipGetLastError());
+}
+void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
+                     unsigned long long *qmax, int32_t *flags, hipStream_t s) {
+    HIPC(hipMemsetAsync(qmax, 0, sizeof(unsigned long long), s));
+    k_diag_gersh<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, dinv, qmax, flags);
+    HIPC(hipGetLastError());
+}
+void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t s) {
+    k_scale<<<nblocks(n), kBlock, 0, s>>>(n, omega, dinv, wd);
+    HIPC(hipGetLastError());
+}
+void to_f32(int64_t n, const double *in, float *out, hipStream_t s) {
+    if (n > 0) k_to_f32<<<nblocks(n), kBlock, 0, s>>>(n, in, out);
+    HIPC(hipGetLastError());
+}
+void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s) {
+    const int64_t nn = (int64_t)n * n;
+    k_dense_zero<<<nblocks(nn), kBlock, 0, s>>>(nn, D);
+    k_dense_from_csr<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, D);
+    HIPC(hipGetLastError());
+}
+void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s) {
+    k_cholesky<<<1, 1024, 0, s>>>(n, D, flags);
+    HIPC(hipGetLastError());
+}
+void chol_inverse(int n, const double *L, double *X, hipStream_t s) {
+    k_chol_inverse<<<nblocks(n, 64), 64, 0, s>>>(n, L, X);
+    HIPC(hipGetLastError());
+}
+
+}  // namespace camg

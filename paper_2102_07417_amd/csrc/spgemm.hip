@@ -1,0 +1,402 @@
+// Sparse matrix-matrix product Z = X Y for the Galerkin operator
+// A_c = P^T (A P) (eq. AcDef), row by row, one wavefront per output row.
+//
+//   1. product bound: prod_i = sum over k in row i of X of |row k of Y|;
+//   2. symbolic pass: the distinct columns of row i are counted with an
+//      open-addressing hash table in LDS (sized from prod_i, bins of rows);
+//   3. scan of the counts gives Z's row pointer;
+//   4. fill pass: the table is rebuilt, its keys sorted (bitonic, in LDS)
+//      and written as Z's columns; each slot then maps its column to the
+//      sorted position, and the values are accumulated there walking X's
+//      row in ascending order -- for a fixed inner index k the wavefront's
+//      lanes hold distinct columns, so every output entry receives its
+//      products one at a time in ascending k, starting from 0.0.  The sums
+//      are therefore rounded exactly as a sequential row-by-row product
+//      with a dense accumulator rounds them.
+// Rows whose table would not fit in LDS use the same code on tables in a
+// global scratch buffer.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "devutil.hpp"
+#include "internal.hpp"
+
+namespace camg {
+
+namespace {
+
+constexpr int kEmpty = -1;
+constexpr int kWPB = 4;  // wavefronts per block for the binned kernels
+
+#define WAVE_SYNC()                                         \
+    do {                                                    \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                    \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+    } while (0)
+
+__device__ __forceinline__ unsigned slot_of(int j, int ts) { return ((unsigned)j * 2654435761u) & (unsigned)(ts - 1); }
+
+struct CsrView {
+    const int32_t *rp, *ci;
+    const double *v;
+};
+
+__global__ void k_row_products(int nr, CsrView X, CsrView Y, int64_t *prod) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int64_t p = 0;
+    for (int e = X.rp[i]; e < X.rp[i + 1]; ++e) {
+        const int k = X.ci[e];
+        p += Y.rp[k + 1] - Y.rp[k];
+    }
+    prod[i] = p;
+}
+
+// bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is open
+__global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int nb, const int64_t *lim, int32_t *bcnt,
+                           int32_t *brows, int stride) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
+    int b = 0;
+    while (b < nb - 1 && x > lim[b]) ++b;
+    const int pos = atomicAdd(&bcnt[b], 1);
+    brows[(int64_t)b * stride + pos] = i;
+}
+
+// Insert the columns of row i of X Y into the table; returns the number of
+// new keys this lane inserted.  *overflow is set if a probe sequence wraps.
+__device__ __forceinline__ int insert_row(int i, const CsrView &X, const CsrView &Y, int *keys, int ts, int lane,
+                                          bool &overflow) {
+    int cnt = 0;
+    const int e1 = X.rp[i + 1];
+    for (int e = X.rp[i]; e < e1; ++e) {
+        const int k = X.ci[e];
+        const int t1 = Y.rp[k + 1];
+        for (int t = Y.rp[k] + lane; t < t1; t += kWave) {
+            const int j = Y.ci[t];
+            unsigned h = slot_of(j, ts);
+            for (int probe = 0;; ++probe) {
+                const int old = atomicCAS(&keys[h], kEmpty, j);
+                if (old == kEmpty) { ++cnt; break; }
+                if (old == j) break;
+                h = (h + 1) & (unsigned)(ts - 1);
+                if (probe >= ts) { overflow = true; break; }
+            }
+        }
+    }
+    return cnt;
+}
+
+// slot holding key j (present by construction); -1 if absent after a full sweep
+__device__ __forceinline__ int find_slot(const int *keys, int ts, int j) {
+    unsigned h = slot_of(j, ts);
+    for (int probe = 0; probe < ts; ++probe) {
+        if (keys[h] == j) return (int)h;
+        h = (h + 1) & (unsigned)(ts - 1);
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------ symbolic
+__device__ __forceinline__ void symbolic_row(int i, bool valid, const CsrView &X, const CsrView &Y, int *keys, int ts,
+                                             int32_t *cnt_out, int32_t *ovf_flag) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int s = lane; s < ts; s += kWave) keys[s] = kEmpty;
+    __syncthreads();
+    bool overflow = false;
+    int c = valid ? insert_row(i, X, Y, keys, ts, lane, overflow) : 0;
+    c = wave_sum_i(c);
+    const int ov = wave_sum_i(overflow ? 1 : 0);
+    if (valid && lane == 0) {
+        if (ov || c > (ts - ts / 4)) { cnt_out[i] = -1; atomicOr(ovf_flag, 1); }
+        else cnt_out[i] = c;
+    }
+    __syncthreads();
+}
+
+template <int TS, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_symbolic_lds(int nrows_bin, const int32_t *rows, CsrView X, CsrView Y,
+                                                            int32_t *cnt, int32_t *ovf) {
+    __shared__ int keys[WPB][TS];
+    const int w = threadIdx.x / kWave;
+    const int idx = blockIdx.x * WPB + w;
+    const bool valid = idx < nrows_bin;
+    const int i = valid ? rows[idx] : 0;
+    symbolic_row(i, valid, X, Y, keys[w], TS, cnt, ovf);
+}
+
+// one wavefront per row, tables in global memory at offsets toff[idx]
+__global__ void __launch_bounds__(64) k_symbolic_glb(int nrows, const int32_t *rows, const int64_t *toff,
+                                                      const int32_t *tsz, CsrView X, CsrView Y, int *scratch,
+                                                      int32_t *cnt, int32_t *ovf) {
+    const int idx = blockIdx.x;
+    if (idx >= nrows) return;
+    symbolic_row(rows[idx], true, X, Y, scratch + toff[idx], tsz[idx], cnt, ovf);
+}
+
+// ------------------------------------------------------------ fill + numeric
+__device__ __forceinline__ void fill_row(int i, bool valid, const CsrView &X, const CsrView &Y, const int32_t *zrp,
+                                         int32_t *zci, double *zv, int *keys, int *pos, int *cols, double *acc,
+                                         int ts, int *counter) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int s = lane; s < ts; s += kWave) keys[s] = kEmpty;
+    if (lane == 0) *counter = 0;
+    __syncthreads();
+    bool overflow = false;
+    if (valid) insert_row(i, X, Y, keys, ts, lane, overflow);
+    __syncthreads();
+    const int u = valid ? zrp[i + 1] - zrp[i] : 0;
+    int npow = 1;
+    while (npow < u) npow <<= 1;
+    if (valid) {
+        for (int s = lane; s < ts; s += kWave) {
+            const int k = keys[s];
+            if (k != kEmpty) {
+                const int q = atomicAdd(counter, 1);
+                if (q < npow) cols[q] = k;
+            }
+        }
+        WAVE_SYNC();
+        for (int p = u + lane; p < npow; p += kWave) cols[p] = INT_MAX;
+        WAVE_SYNC();
+        // bitonic sort of cols[0, npow)
+        for (int kk = 2; kk <= npow; kk <<= 1) {
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int a = lane; a < npow; a += kWave) {
+                    const int b = a ^ jj;
+                    if (b > a) {
+                        const int x = cols[a], y = cols[b];
+                        const bool up = (a & kk) == 0;
+                        if (up ? (x > y) : (x < y)) {
+                            cols[a] = y;
+                            cols[b] = x;
+                        }
+                    }
+                }
+                WAVE_SYNC();
+            }
+        }
+        for (int p = lane; p < u; p += kWave) {
+            const int h = find_slot(keys, ts, cols[p]);
+            if (h >= 0) pos[h] = p;
+            acc[p] = 0.0;
+        }
+        WAVE_SYNC();
+        // products in ascending inner index; lanes hold distinct columns
+        const int e1 = X.rp[i + 1];
+        for (int e = X.rp[i]; e < e1; ++e) {
+            const int k = X.ci[e];
+            const double x = X.v[e];
+            const int t1 = Y.rp[k + 1];
+            for (int t = Y.rp[k] + lane; t < t1; t += kWave) {
+                const int h = find_slot(keys, ts, Y.ci[t]);
+                if (h >= 0) {
+                    const int p = pos[h];
+                    acc[p] = acc[p] + x * Y.v[t];
+                }
+            }
+            WAVE_SYNC();
+        }
+        const int off = zrp[i];
+        for (int p = lane; p < u; p += kWave) {
+            zci[off + p] = cols[p];
+            zv[off + p] = acc[p];
+        }
+    }
+    __syncthreads();
+}
+
+template <int TS, int UMAX, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_fill_lds(int nrows_bin, const int32_t *rows, CsrView X, CsrView Y,
+                                                        const int32_t *zrp, int32_t *zci, double *zv) {
+    __shared__ int keys[WPB][TS];
+    __shared__ int pos[WPB][TS];
+    __shared__ int cols[WPB][UMAX];
+    __shared__ double acc[WPB][UMAX];
+    __shared__ int counter[WPB];
+    const int w = threadIdx.x / kWave;
+    const int idx = blockIdx.x * WPB + w;
+    const bool valid = idx < nrows_bin;
+    const int i = valid ? rows[idx] : 0;
+    fill_row(i, valid, X, Y, zrp, zci, zv, keys[w], pos[w], cols[w], acc[w], TS, &counter[w]);
+}
+
+// global-table variant: scratch per row = keys[ts], pos[ts], cols[npow] (ints) and acc[u] (doubles)
+__global__ void __launch_bounds__(64) k_fill_glb(int nrows, const int32_t *rows, const int64_t *ioff,
+                                                  const int64_t *doff, const int32_t *tsz, CsrView X, CsrView Y,
+                                                  const int32_t *zrp, int32_t *zci, double *zv, int *iscratch,
+                                                  double *dscratch, int *counters) {
+    const int idx = blockIdx.x;
+    if (idx >= nrows) return;
+    const int ts = tsz[idx];
+    int *base = iscratch + ioff[idx];
+    fill_row(rows[idx], true, X, Y, zrp, zci, zv, base, base + ts, base + 2 * ts, dscratch + doff[idx], ts,
+             &counters[idx]);
+}
+
+inline int nblk(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+int next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return (int)p;
+}
+
+template <int TS, int WPB>
+void launch_symbolic(int nb, const int32_t *rows, const CsrView &X, const CsrView &Y, int32_t *cnt, int32_t *ovf,
+                     hipStream_t s) {
+    if (nb <= 0) return;
+    k_symbolic_lds<TS, WPB><<<nblk(nb, WPB), WPB * 64, 0, s>>>(nb, rows, X, Y, cnt, ovf);
+    HIPC(hipGetLastError());
+}
+
+template <int TS, int UMAX, int WPB>
+void launch_fill(int nb, const int32_t *rows, const CsrView &X, const CsrView &Y, const int32_t *zrp, int32_t *zci,
+                 double *zv, hipStream_t s) {
+    if (nb <= 0) return;
+    k_fill_lds<TS, UMAX, WPB><<<nblk(nb, WPB), WPB * 64, 0, s>>>(nb, rows, X, Y, zrp, zci, zv);
+    HIPC(hipGetLastError());
+}
+
+}  // namespace
+
+void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_t s) {
+    const int nr = X.nr;
+    Z.nr = nr;
+    Z.nc = Y.nc;
+    Z.rp = out.alloc<int32_t>((size_t)nr + 1);
+    if (nr == 0) {
+        HIPC(hipMemsetAsync(Z.rp, 0, sizeof(int32_t), s));
+        Z.nnz = 0;
+        return;
+    }
+    CsrView xv{X.rp, X.ci, X.v}, yv{Y.rp, Y.ci, Y.v};
+
+    // 1. product bounds and symbolic bins
+    int64_t *prod = tmp.alloc<int64_t>(nr);
+    k_row_products<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, xv, yv, prod);
+    HIPC(hipGetLastError());
+
+    constexpr int NB = 5;
+    const int64_t sym_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
+    int64_t *lim = tmp.alloc<int64_t>(NB);
+    int32_t *bcnt = tmp.alloc<int32_t>(NB);
+    int32_t *brows = tmp.alloc<int32_t>((size_t)NB * nr);
+    int32_t *ovf = tmp.alloc<int32_t>(1);
+    int32_t *cnt = tmp.alloc<int32_t>(nr);
+    HIPC(hipMemcpyAsync(lim, sym_lim_h, sizeof(sym_lim_h), hipMemcpyHostToDevice, s));
+    HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
+    HIPC(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
+    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr);
+    HIPC(hipGetLastError());
+    int32_t hb[NB];
+    HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+
+    // 2. symbolic
+    launch_symbolic<128, kWPB>(hb[0], brows + 0 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<512, kWPB>(hb[1], brows + 1 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<2048, kWPB>(hb[2], brows + 2 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<8192, kWPB>(hb[3], brows + 3 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<16384, 2>(hb[4], brows + 4 * (size_t)nr, xv, yv, cnt, ovf, s);
+    int32_t hovf = 0;
+    HIPC(hipMemcpyAsync(&hovf, ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hovf) {
+        // rows whose distinct columns overflowed the largest LDS table: redo
+        // them with global tables sized from their product bound
+        std::vector<int32_t> rows(hb[4]);
+        std::vector<int64_t> pr(nr);
+        std::vector<int32_t> cn(nr);
+        HIPC(hipMemcpy(rows.data(), brows + 4 * (size_t)nr, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(pr.data(), prod, sizeof(int64_t) * nr, hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(cn.data(), cnt, sizeof(int32_t) * nr, hipMemcpyDeviceToHost));
+        std::vector<int32_t> grow, gts;
+        std::vector<int64_t> goff;
+        int64_t total = 0;
+        for (int r : rows)
+            if (cn[r] < 0) {
+                const int ts = next_pow2(2 * pr[r] + 1);
+                grow.push_back(r);
+                gts.push_back(ts);
+                goff.push_back(total);
+                total += ts;
+            }
+        Pool g;
+        int *scr = g.alloc<int>((size_t)total);
+        int32_t *drows = g.alloc<int32_t>(grow.size());
+        int32_t *dts = g.alloc<int32_t>(grow.size());
+        int64_t *doff = g.alloc<int64_t>(grow.size());
+        HIPC(hipMemcpyAsync(drows, grow.data(), sizeof(int32_t) * grow.size(), hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dts, gts.data(), sizeof(int32_t) * grow.size(), hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(doff, goff.data(), sizeof(int64_t) * grow.size(), hipMemcpyHostToDevice, s));
+        k_symbolic_glb<<<(int)grow.size(), 64, 0, s>>>((int)grow.size(), drows, doff, dts, xv, yv, scr, cnt, ovf);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));
+    }
+
+    // 3. row pointer
+    int64_t *rp64 = tmp.alloc<int64_t>((size_t)nr + 1);
+    scan_i32_to_i64(cnt, rp64, nr, tmp, s);
+    int64_t nnz = 0;
+    HIPC(hipMemcpyAsync(&nnz, rp64 + nr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (nnz > INT32_MAX) fail(CAMG_E_NOMEM, "sparse product has more than 2^31-1 nonzeros");
+    narrow_i64(rp64, Z.rp, nr, s);
+    Z.nnz = nnz;
+    Z.ci = out.alloc<int32_t>(std::max<int64_t>(nnz, 1));
+    Z.v = out.alloc<double>(std::max<int64_t>(nnz, 1));
+
+    // 4. fill bins by exact row length
+    const int64_t fill_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
+    HIPC(hipMemcpyAsync(lim, fill_lim_h, sizeof(fill_lim_h), hipMemcpyHostToDevice, s));
+    HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
+    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, lim, bcnt, brows, nr);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    launch_fill<128, 64, kWPB>(hb[0], brows + 0 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<512, 256, kWPB>(hb[1], brows + 1 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<2048, 1024, kWPB>(hb[2], brows + 2 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<8192, 4096, 1>(hb[3], brows + 3 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    if (hb[4] > 0) {
+        std::vector<int32_t> rows(hb[4]);
+        std::vector<int32_t> zrp(nr + 1);
+        HIPC(hipMemcpy(rows.data(), brows + 4 * (size_t)nr, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(zrp.data(), Z.rp, sizeof(int32_t) * (nr + 1), hipMemcpyDeviceToHost));
+        std::vector<int32_t> gts;
+        std::vector<int64_t> gio, gdo;
+        int64_t itot = 0, dtot = 0;
+        for (int r : rows) {
+            const int u = zrp[r + 1] - zrp[r];
+            const int ts = next_pow2(2 * (int64_t)u + 1);
+            const int np = next_pow2(u);
+            gts.push_back(ts);
+            gio.push_back(itot);
+            gdo.push_back(dtot);
+            itot += 2 * (int64_t)ts + np;
+            dtot += u;
+        }
+        Pool g;
+        const int m = (int)rows.size();
+        int *iscr = g.alloc<int>((size_t)itot);
+        double *dscr = g.alloc<double>((size_t)std::max<int64_t>(dtot, 1));
+        int32_t *drows = g.alloc<int32_t>(m);
+        int32_t *dts = g.alloc<int32_t>(m);
+        int64_t *dio = g.alloc<int64_t>(m);
+        int64_t *ddo = g.alloc<int64_t>(m);
+        int *ctr = g.alloc<int>(m);
+        HIPC(hipMemcpyAsync(drows, rows.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dts, gts.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dio, gio.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(ddo, gdo.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, s));
+        k_fill_glb<<<m, 64, 0, s>>>(m, drows, dio, ddo, dts, xv, yv, Z.rp, Z.ci, Z.v, iscr, dscr, ctr);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize(s));
+    }
+}
+
+}  // namespace camg

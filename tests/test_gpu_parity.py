@@ -1,0 +1,224 @@
+"""GPU library against the CPU oracle, through the C-ABI.
+
+Set-up: the GPU kernels perform the oracle's floating-point operations in
+the oracle's order, so every level (A_l, P_l, R_l, C/F split, strong flags,
+D^{-1}, omega) must match bit for bit.  Solve: the V-cycle and the CG dot
+products use different summation orders, so solutions are compared to
+1e-9 relative (iteration counts within one).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2102_07417_amd import problems as PB
+from tests.helpers import dense
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _camg():
+    from paper_2102_07417_amd import camg
+    camg.load()
+    return camg
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+CASES = {
+    "poisson2d_64": lambda: PB.poisson2d(64),
+    "poisson2d_ragged_37x23": lambda: PB.poisson2d(37, 23),
+    "lognormal3d_24": lambda: PB.lognormal3d(24, 2.0),
+    "aniso3d_20": lambda: PB.aniso3d(20, 1e-3),
+    "elasticity_6": lambda: PB.elasticity3d(6),
+    "lognormal2d_90": lambda: PB.lognormal2d(90, 2.0),
+}
+
+
+@pytest.fixture(scope="module")
+def camg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return _camg()
+
+
+def _pair(camg, A, **kw):
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), **kw)
+    okw = {k: v for k, v in kw.items() if k in ("theta", "seed", "nu_pre", "nu_post", "omega", "max_levels",
+                                                "max_coarse", "max_iter")}
+    o = O.Hierarchy(A, **okw)
+    return g, o
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bit_exact(camg, name):
+    print(f"[gpu] hierarchy {name}", flush=True)
+    A = CASES[name]()
+    g, o = _pair(camg, A, max_coarse=40)
+    assert g.nlev == o.nlev, (g.nlev, o.nlev)
+    for l in range(o.nlev):
+        ga, oa = g.A(l), o.A(l)
+        assert np.array_equal(ga[2], oa[2]) and np.array_equal(ga[3], oa[3]), f"A_{l} pattern"
+        assert np.array_equal(ga[4], oa[4]), f"A_{l} values"
+        if l == o.nlev - 1:
+            break
+        assert np.array_equal(g.strong(l), o.strong(l)), f"strong_{l}"
+        assert np.array_equal(g.cf(l), o.cf(l)), f"cf_{l}"
+        assert g.omega(l) == o.omega(l)
+        assert np.array_equal(g.dinv(l), o.dinv(l))
+        for what in ("P", "R"):
+            gp, op = getattr(g, what)(l), getattr(o, what)(l)
+            assert gp[:2] == op[:2]
+            assert np.array_equal(gp[2], op[2]) and np.array_equal(gp[3], op[3]), f"{what}_{l} pattern"
+            assert np.array_equal(gp[4], op[4]), f"{what}_{l} values"
+    # last level: dense inverse against numpy
+    Ad = dense(g.A(g.nlev - 1))
+    np.testing.assert_allclose(g.coarse_inverse(), np.linalg.inv(Ad), rtol=0,
+                               atol=1e-11 * np.abs(np.linalg.inv(Ad)).max())
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "lognormal3d_24", "elasticity_6"])
+def test_vcycle_matches_oracle(camg, name):
+    print(f"[gpu] vcycle {name}", flush=True)
+    A = CASES[name]()
+    g, o = _pair(camg, A, max_coarse=40)
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        y = rng.standard_normal(A.n)
+        dz = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+        g.vcycle_dev(_dev(y), dz)
+        torch.cuda.synchronize()
+        zo = o.vcycle(y)
+        err = np.linalg.norm(dz.cpu().numpy() - zo) / np.linalg.norm(zo)
+        assert err <= 1e-12, err
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_parity(camg, name):
+    print(f"[gpu] solve {name}", flush=True)
+    A = CASES[name]()
+    b = PB.rhs(A.n)
+    g, o = _pair(camg, A, max_iter=3000)
+    ro = o.solve(b, 1e-8, max_iter=3000)
+    assert ro.status == O.OK
+    db, dx = _dev(b), torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    rg = g.solve_dev(db, dx, rtol=1e-8, hist_cap=3001)
+    x = dx.cpu().numpy()
+    assert rg.status == camg.OK
+    assert abs(rg.iters - ro.iters) <= 1, (rg.iters, ro.iters)
+    assert np.linalg.norm(x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    assert rg.true_relres < 1e-8 * 1.01
+    np.testing.assert_allclose(rg.hist[:5], ro.hist[:5], rtol=1e-10)
+    # equal iteration count (parity mode): exactly the oracle's count
+    g2, _ = _pair(camg, A, max_iter=ro.iters)
+    dx2 = torch.zeros_like(dx)
+    r2 = g2.solve_dev(db, dx2, rtol=0.0)
+    assert r2.status == camg.E_MAXIT and r2.iters == ro.iters
+    assert np.linalg.norm(dx2.cpu().numpy() - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+    g2.close()
+
+
+def test_solve_host_api_and_determinism(camg):
+    A = PB.lognormal3d(20, 2.0)
+    b = PB.rhs(A.n)
+    s = camg.Solver(A)
+    r1 = s.solve(b)
+    r2 = s.solve(b)
+    assert r1.status == camg.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.x, r2.x) and np.array_equal(r1.hist, r2.hist)
+    s.close()
+
+
+def test_galerkin_exact_integer(camg):
+    rng = np.random.default_rng(3)
+    A = PB.poisson2d(9)
+    for nc in (1, 7, 30):
+        P = rng.integers(-2, 3, size=(A.n, nc)).astype(float)
+        P[rng.random(P.shape) > 0.3] = 0.0
+        from tests.helpers import from_dense
+        Pc = from_dense(P, keep_zero_diag=False)
+        C = camg.camg_galerkin((A.n, A.n, A.row_ptr, A.col_idx, A.val), Pc)
+        assert np.array_equal(dense(C), P.T @ dense(A) @ P)
+        Co = O.galerkin((A.n, A.n, A.row_ptr, A.col_idx, A.val), Pc)
+        assert np.array_equal(C[2], Co[2]) and np.array_equal(C[3], Co[3])
+
+
+def test_single_level_and_tiny(camg):
+    for A in [PB.poisson2d(1), PB.poisson2d(3), PB.poisson2d(16)]:
+        b = PB.rhs(A.n)
+        s = camg.Solver(A)
+        r = s.solve(b)
+        assert s.nlev == 1 and r.status == camg.OK and r.iters == 1
+        np.testing.assert_allclose(r.x, np.linalg.solve(dense((A.n, A.n, A.row_ptr, A.col_idx, A.val)), b),
+                                   rtol=1e-12, atol=1e-14)
+        s.close()
+
+
+def test_zero_rhs_and_maxit(camg):
+    A = PB.poisson2d(40)
+    s = camg.Solver(A, max_iter=3)
+    r = s.solve(np.zeros(A.n))
+    assert r.status == camg.OK and r.iters == 0 and np.all(r.x == 0)
+    r = s.solve(PB.rhs(A.n))
+    assert r.status == camg.E_MAXIT and r.iters == 3 and len(r.hist) == 4
+    s.close()
+
+
+def test_invalid_inputs(camg):
+    from tests.test_oracle import _bad
+    for kind in ["rp_dec", "col_range", "col_order", "nan", "nodiag", "asym", "negdiag"]:
+        A, code = _bad(kind)
+        n, _, rp, ci, v = A
+        st, h = camg.camg_setup(n, rp, ci, v)
+        assert st == code, (kind, st)
+        assert not h.value
+    st, h = camg.camg_setup(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert st == camg.E_ARG
+    bad = camg.params(nu_pre=0)
+    A = PB.poisson2d(5)
+    st, h = camg.camg_setup(A.n, A.row_ptr, A.col_idx, A.val, bad)
+    assert st == camg.E_ARG
+
+
+def test_breakdown_on_indefinite(camg):
+    L = dense(PB.poisson2d(12))
+    n = L.shape[0] + 2
+    M = np.zeros((n, n))
+    M[:-2, :-2] = L
+    M[-2:, -2:] = [[1.0, 2.0], [2.0, 1.0]]
+    from tests.helpers import from_dense
+    n_, _, rp, ci, v = from_dense(M)
+    s = camg.Solver(PB.CSR(n, rp, ci, v), max_coarse=20)
+    b = np.zeros(n)
+    b[-2:] = [1.0, -1.0]
+    r = s.solve(b)
+    assert r.status in (camg.E_BREAKDOWN,)
+    s.close()
+    st, h = camg.camg_setup(n, rp, ci, v, camg.params(max_coarse=1000))
+    assert st == camg.E_NOT_SPD
+
+
+def test_full_size_lognormal_128(camg):
+    """The benchmark's workload at full size: hierarchy bit-exact on every
+    level and the FP64 solve within 1e-9 of the oracle's."""
+    print("[gpu] full-size lognormal3d_128", flush=True)
+    A = PB.workload("lognormal3d_128")
+    b = PB.rhs(A.n)
+    g, o = _pair(camg, A)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev):
+        ga, oa = g.A(l), o.A(l)
+        assert np.array_equal(ga[3], oa[3]) and np.array_equal(ga[4], oa[4]), l
+    dx = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    rg = g.solve_dev(_dev(b), dx, rtol=1e-8)
+    ro = o.solve(b, 1e-8)
+    assert abs(rg.iters - ro.iters) <= 1
+    assert np.linalg.norm(dx.cpu().numpy() - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    assert rg.true_relres < 1e-8 * 1.01
+    g.close()
