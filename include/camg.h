@@ -170,6 +170,17 @@ camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, c
                           int32_t **c_rp, int32_t **c_ci, double **c_val, int64_t *nnz_out);
 void camg_free_host(void *p);
 
+/*
+ * Kernel timing for benchmarks: while enabled, every solve on the handle
+ * brackets the level-0 post-smoothing kernel (the fine-level Jacobi step
+ * z = s + omega D^{-1} (y - A s) fused with the r.z partial sums) with HIP
+ * events on the solve's stream and accumulates the durations of the
+ * launches that did work.  Each call returns (and resets) the totals
+ * gathered since the previous call, then enables or disables timing.
+ * total_ms and launches may be NULL.
+ */
+camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_t *launches);
+
 /* Release the hierarchy and all its device memory.  NULL is ignored. */
 camg_status camg_destroy(camg_handle h);
 

@@ -25,7 +25,7 @@ MAX_LEVELS = 32
 EXPORTED = [
     "camg_abi_version", "camg_status_str", "camg_last_error", "camg_params_default", "camg_setup",
     "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
-    "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy",
+    "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
 ]
 
 
@@ -73,7 +73,8 @@ def load(path: str | None = None):
                                 C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_double)), C.POINTER(i64)]
     L.camg_free_host.argtypes = [vp]
     L.camg_destroy.argtypes = [vp]
-    for name in ("camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
+    L.camg_profile.argtypes = [vp, i32, vp, vp]
+    for name in ("camg_profile", "camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
                  "camg_vcycle_dev", "camg_info", "camg_level_sizes", "camg_export_level", "camg_galerkin",
                  "camg_destroy"):
         getattr(L, name).restype = C.c_int
@@ -199,6 +200,15 @@ def camg_galerkin(A, P):
     for p in (crp, cci, cv):
         L.camg_free_host(C.cast(p, C.c_void_p))
     return (nc, nc, rp, ci, v)
+
+
+def camg_profile(h, enable):
+    """Returns (total_ms, launches) of the timed level-0 post-smoothing kernel
+    since the last call, then enables/disables timing."""
+    t = np.zeros(1)
+    n = np.zeros(1, np.int64)
+    _check(load().camg_profile(h, int(enable), _p(t), _p(n)))
+    return float(t[0]), int(n[0])
 
 
 def camg_destroy(h):

@@ -263,10 +263,10 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     for (int l = 0; l < h.nlev; ++l) {
         Level &L = h.lev[l];
         const int nl = L.A.nr;
-        L.cA = choose_cfg(nl, L.A.nnz);
+        L.cA = choose_cfg(nl, L.A.nnz, max_row_length(nl, L.A.rp, tmp, s));
         if (l < h.nlev - 1) {
-            L.cP = choose_cfg(L.P.nr, L.P.nnz);
-            L.cR = choose_cfg(L.R.nr, L.R.nnz);
+            L.cP = choose_cfg(L.P.nr, L.P.nnz, max_row_length(L.P.nr, L.P.rp, tmp, s));
+            L.cR = choose_cfg(L.R.nr, L.R.nnz, max_row_length(L.R.nr, L.R.rp, tmp, s));
         }
         if (!mixed) {
             if (l > 0) {
@@ -300,11 +300,12 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     h.p[0] = h.pool.alloc<double>(n0);
     h.p[1] = h.pool.alloc<double>(n0);
     h.q = h.pool.alloc<double>(n0);
-    h.partials = h.pool.alloc<double>(kMaxGrid);
-    h.counter = h.pool.alloc<unsigned>(1);
+    h.pr2 = h.pool.alloc<double>(kMaxGrid);
+    h.prz = h.pool.alloc<double>(kMaxGrid);
+    h.ppq = h.pool.alloc<double>(kMaxGrid);
+    h.ptmp = h.pool.alloc<double>(kMaxGrid);
     h.st = h.pool.alloc<PcgState>(1);
     h.sc = h.pool.alloc<double>(4);
-    HIPC(hipMemsetAsync(h.counter, 0, sizeof(unsigned), s));
     HIPC(hipHostMalloc((void **)&h.hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
     HIPC(hipHostGetDevicePointer((void **)&h.hflag_dev, h.hflag, 0));
     HIPC(hipStreamSynchronize(s));
@@ -341,7 +342,7 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
     vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), y, sv, VT<T>::r(L), st, s);
     if (h.prm.nu_pre > 1) {
         for (int it = 1; it < h.prm.nu_pre; ++it) {
-            vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, nullptr, st, s);
+            vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, st, s);
             std::swap(sv, tv);
         }
         vc_resid<T, TY>(L.A, L.cA, y, sv, VT<T>::r(L), st, s);
@@ -349,28 +350,36 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
     return sv;
 }
 
-// Post-smoothing (nu_post steps) into z; the last step fuses rho when dot.
+// Post-smoothing (nu_post steps) into z; with dot the last step also writes
+// the partials of y.z into h.prz.
 template <class T, class TY, class TZ>
 void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
     T *tv = VT<T>::t(L);
     for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
         T *out = (tv == sv) ? VT<T>::s(L) : tv;
-        vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, nullptr, st, s);
+        vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, st, s);
         sv = out;
     }
-    if (dot) vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.partials, h.counter, st, s);
-    else vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, nullptr, st, s);
+    if (dot) {
+        const bool p = h.prof && h.pcount + 1 < (int)h.pev.size() / 2;
+        if (p) HIPC(hipEventRecord(h.pev[2 * h.pcount], s));
+        vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.prz, st, s);
+        if (p) HIPC(hipEventRecord(h.pev[2 * h.pcount + 1], s));
+        if (p) ++h.pcount;
+    } else {
+        vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, st, s);
+    }
 }
 
-// z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.
+// z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.  With
+// dot, the partials of y0.z0 land in h.prz; returns their number.
 template <class T>
-void vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
+int vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
     const int L = h.nlev - 1;
     if (L == 0) {
         // one level: direct solve (FP64)
         coarse_solve<double>(h.nL, h.cinv, y0, z0, st, s);
-        if (dot) dot_rho(h.nL, y0, z0, h.partials, h.counter, st, s);
-        return;
+        return dot ? dot_partials(h.nL, y0, z0, h.prz, st, s) : 0;
     }
     std::vector<T *> sv(h.nlev, nullptr);
     for (int l = 0; l < L; ++l) {
@@ -386,11 +395,12 @@ void vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hip
         if (l == 0) smooth_post<T, double, double>(h, Lv, y0, sv[0], z0, dot, st, s);
         else smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, st, s);
     }
+    return dot ? h.lev[0].cA.grid : 0;
 }
 
-void vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
-    if (h.prm.precision == CAMG_MIXED_FP32) vcycle_t<float>(h, y0, z0, st, dot, s);
-    else vcycle_t<double>(h, y0, z0, st, dot, s);
+int vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
+    if (h.prm.precision == CAMG_MIXED_FP32) return vcycle_t<float>(h, y0, z0, st, dot, s);
+    return vcycle_t<double>(h, y0, z0, st, dot, s);
 }
 
 // ---------------------------------------------------------------- PCG
@@ -400,14 +410,14 @@ void ensure_hist(Hier &h, int cap) {
     h.dhist_cap = cap;
 }
 
-camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t *iters, double *hist, int hist_cap,
-                      double *true_relres, hipStream_t s) {
+// PCG iterations k = k0 .. max_iter-1 (fewer if the stopping test or a
+// breakdown ends them).  The host polls a host-mapped flag one iteration
+// behind the device, so the queue never runs dry.
+void run_iterations(Hier &h, const double *b, double *x, int k0, int &npr2, hipStream_t s) {
+    (void)b;
     const Csr &A = h.lev[0].A;
     const int n = A.nr;
     const int max_iter = h.prm.max_iter;
-    ensure_hist(h, max_iter + 1);
-    pcg_init(n, b, x, h.r, h.p[0], rtol, h.partials, h.counter, h.st, h.dhist, s);
-    h.hflag[0] = 0;
     hipEvent_t ev[2];
     HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -415,35 +425,74 @@ camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t 
         hipEvent_t *e;
         ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
     } eg{ev};
-    // the first poll: b = 0 or an immediate stop
-    {
-        PcgState st0 = read1(h.st, s);
-        if (st0.done) h.hflag[0] = 1;
-    }
-    for (int k = 0; k < max_iter && !h.hflag[0]; ++k) {
-        vcycle(h, h.r, h.z, h.st, true, s);
-        pcg_spmv_p(A, h.lev[0].cA, h.z, h.p[k & 1], h.p[(k + 1) & 1], h.q, h.partials, h.counter, h.st, s);
-        pcg_update(n, h.p[(k + 1) & 1], h.q, x, h.r, h.partials, h.counter, h.st, h.dhist, h.dhist_cap,
-                   h.hflag_dev, s);
+    volatile int32_t *flag = h.hflag;
+    flag[0] = 0;
+    for (int k = k0; k < max_iter; ++k) {
+        pcg_check(h.pr2, npr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
+        const int nprz = vcycle(h, h.r, h.z, h.st, true, s);
+        const int nppq = pcg_dir(A, h.lev[0].cA, h.z, h.p[k & 1], h.p[(k + 1) & 1], h.q, h.prz, nprz, h.ppq, h.st, s);
+        npr2 = pcg_update(n, h.p[(k + 1) & 1], h.q, x, h.r, h.ppq, nppq, h.pr2, h.st, h.hflag_dev, s);
         HIPC(hipEventRecord(ev[k & 1], s));
-        if (k >= 1) {
+        if (k > k0) {
             HIPC(hipEventSynchronize(ev[(k - 1) & 1]));
-            if (h.hflag[0]) break;
+            if (flag[0]) break;
         }
     }
+    // the stopping test for the last residual formed
+    pcg_check(h.pr2, npr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
     HIPC(hipStreamSynchronize(s));
-    const PcgState st = read1(h.st, s);
+}
+
+double true_relres_of(Hier &h, const double *b, const double *x, double bnorm, double *r_out, int *npr2, hipStream_t s) {
+    const Csr &A = h.lev[0].A;
+    double *part = r_out ? h.pr2 : h.ptmp;
+    const int np = residual_norm(A, h.lev[0].cA, b, x, r_out, part, s);
+    if (npr2) *npr2 = np;
+    sum_to(part, np, h.sc, s);
+    const double t2 = read1(h.sc, s);
+    return bnorm > 0.0 ? std::sqrt(t2) / bnorm : 0.0;
+}
+
+camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t *iters, double *hist, int hist_cap,
+                      double *true_relres, hipStream_t s) {
+    const Csr &A = h.lev[0].A;
+    const int n = A.nr;
+    ensure_hist(h, h.prm.max_iter + 2);
+    int npr2 = pcg_init(n, b, x, h.r, h.p[0], rtol, h.pr2, h.st, s);
+    run_iterations(h, b, x, 0, npr2, s);
+    PcgState st = read1(h.st, s);
+    double rel = -1.0;
+    // mixed precision: if the recursive residual met the test but the true
+    // one does not, restart from r = b - A x (at most twice)
+    if (h.prm.precision == CAMG_MIXED_FP32 && rtol > 0.0) {
+        for (int rep = 0; rep < 2 && st.done && st.status == 0; ++rep) {
+            rel = true_relres_of(h, b, x, st.bnorm, nullptr, nullptr, s);
+            if (rel < rtol || st.iter >= h.prm.max_iter) break;
+            true_relres_of(h, b, x, st.bnorm, h.r, &npr2, s);
+            pcg_restart(h.st, s);
+            run_iterations(h, b, x, st.iter, npr2, s);
+            st = read1(h.st, s);
+            rel = -1.0;
+        }
+    }
+    if (h.prof) {
+        // launches after convergence return at once: keep only those that ran
+        for (int i = 0; i < h.pcount; ++i) {
+            if (i >= st.iter) break;
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, h.pev[2 * i], h.pev[2 * i + 1]));
+            h.prof_ms += ms;
+            h.prof_launches += 1;
+        }
+        h.pcount = 0;
+    }
     const int it = st.iter;
     if (iters) *iters = it;
     if (hist && hist_cap > 0) {
         const int m = std::min(hist_cap, it + 1);
         HIPC(hipMemcpyAsync(hist, h.dhist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     }
-    if (true_relres) {
-        true_residual(A, h.lev[0].cA, b, x, h.partials, h.counter, h.sc, s);
-        const double t2 = read1(h.sc, s);
-        *true_relres = st.bnorm > 0.0 ? std::sqrt(t2) / st.bnorm : 0.0;
-    }
+    if (true_relres) *true_relres = rel >= 0.0 ? rel : true_relres_of(h, b, x, st.bnorm, nullptr, nullptr, s);
     HIPC(hipStreamSynchronize(s));
     if (st.status == (int32_t)CAMG_E_BREAKDOWN) {
         g_last_error = "CG breakdown: p.Ap <= 0 or r.z <= 0";
@@ -708,7 +757,26 @@ camg_status camg_destroy(camg_handle hh) {
         (void)hipSetDevice(h->device);
         (void)hipDeviceSynchronize();
         if (h->hflag) (void)hipHostFree(h->hflag);
+        for (auto &e : h->pev) (void)hipEventDestroy(e);
         delete static_cast<camg_hier *>(hh);
+    });
+}
+
+camg_status camg_profile(camg_handle hh, int32_t enable, double *total_ms, int64_t *launches) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        if (total_ms) *total_ms = h->prof_ms;
+        if (launches) *launches = h->prof_launches;
+        h->prof_ms = 0.0;
+        h->prof_launches = 0;
+        h->pcount = 0;
+        h->prof = enable != 0;
+        if (h->prof && h->pev.empty()) {
+            h->pev.resize(2 * ((size_t)h->prm.max_iter + 2));
+            for (auto &e : h->pev) HIPC(hipEventCreate(&e));
+        }
     });
 }
 

@@ -44,9 +44,20 @@ struct Csr {
     float *v32 = nullptr;   // FP32 copy of the values (mixed precision)
 };
 
-// Launch shape of a row-parallel kernel: `lpr` lanes per row.
+// Launch shape of the row kernels of one matrix (chosen at set-up).
+//   tile: rows are processed in LDS tiles of `rpt` rows (at most tile_nnz
+//         nonzeros), `lpr` lanes summing each row; `grid` blocks take `tpb`
+//         consecutive tiles each.
+//   vector (tile == false): `lpr` lanes walk each row, `rpt` rows per block.
 struct RowCfg {
+    bool tile = false;
     int lpr = 8;
+    int rpt = 0;
+    int tile_nnz = 0;
+    int ntiles = 0;
+    int grid = 8;
+    int tpb = 0;
+    int maxrow = 0;
 };
 
 struct Level {
@@ -68,8 +79,8 @@ struct Level {
 
 // Scalars of one PCG recurrence, resident on the device.
 struct PcgState {
-    double rho, rho_old, sigma, alpha, beta, rnorm, bnorm, tol;
-    int32_t iter, done, status, pad;
+    double rho, rho_old, sigma, alpha, beta, rnorm, bnorm, tol, rtol;
+    int32_t iter, done, status, restart;
 };
 
 struct Hier {
@@ -83,9 +94,11 @@ struct Hier {
     Pool pool;              // everything the handle owns
     // PCG work
     double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *t = nullptr;
-    double *partials = nullptr;  // per-block partial sums
-    double *sc = nullptr;        // device scalars (true residual)
-    unsigned *counter = nullptr; // last-block ticket
+    double *pr2 = nullptr;       // per-block partials of ||r||^2
+    double *prz = nullptr;       // per-block partials of r.z
+    double *ppq = nullptr;       // per-block partials of p.q
+    double *ptmp = nullptr;      // per-block partials (true residual)
+    double *sc = nullptr;        // device scalars
     PcgState *st = nullptr;      // device state
     double *dhist = nullptr;     // device residual history
     int dhist_cap = 0;
@@ -93,6 +106,12 @@ struct Hier {
     int32_t *hflag_dev = nullptr;
     std::atomic<int> busy{0};
     double setup_ms = 0.0;
+    // optional timing of the level-0 post-smoothing kernel inside solves
+    bool prof = false;
+    std::vector<hipEvent_t> pev;  // start/end pairs
+    int pcount = 0;               // pairs recorded since the last read
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
     // multi-RHS work (allocated on first use for a given k)
     int mk = 0;
     double *mr = nullptr, *mz = nullptr, *mp[2] = {nullptr, nullptr}, *mq = nullptr;
@@ -143,6 +162,7 @@ void to_f32(int64_t n, const double *in, float *out, hipStream_t s);
 void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s);
 void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
+int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
 
 // ---------------------------------------------------------------- SpGEMM (spgemm.hip)
 // Z = X Y with the full symbolic pattern, rows sorted; for every output
@@ -151,19 +171,18 @@ void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_t s);
 
 // ---------------------------------------------------------------- solve (solve.hip)
-RowCfg choose_cfg(int n, int64_t nnz);
-int grid_for(int n, const RowCfg &c);
+RowCfg choose_cfg(int n, int64_t nnz, int maxrow);
 
 // V-cycle building blocks.  T: value type of the level (double, or float
 // in mixed precision); TY: type of the right-hand side y (level 0 reads
-// the FP64 PCG residual); TZ: type of the output; DOT: fuse rho = y.z and
-// beta into the kernel (level 0 inside PCG).  st may be null (standalone
+// the FP64 PCG residual); TZ: type of the output; DOT: write per-block
+// partials of y.z (level 0 inside PCG).  st may be null (standalone
 // V-cycle); otherwise the kernels return at once when st->done is set.
 template <class T, class TY>
 void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const TY *y, T *s, T *r, const PcgState *st, hipStream_t str);
 template <class T, class TY, class TZ, bool DOT>
 void vc_post(const Csr &A, const RowCfg &c, const T *wd, const TY *y, const T *s, TZ *z, double *partials,
-             unsigned *counter, PcgState *st, hipStream_t str);
+             const PcgState *st, hipStream_t str);
 template <class T, class TY>
 void vc_resid(const Csr &A, const RowCfg &c, const TY *y, const T *s, T *r, const PcgState *st, hipStream_t str);
 template <class T>
@@ -172,18 +191,21 @@ template <class T>
 void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState *st, hipStream_t str);
 template <class T>
 void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *st, hipStream_t str);
-void dot_rho(int n, const double *y, const double *z, double *partials, unsigned *counter, PcgState *st,
-             hipStream_t s);
+// partial sums of y.z; returns the number of partials
+int dot_partials(int n, const double *y, const double *z, double *partials, const PcgState *st, hipStream_t s);
 
-// PCG outer kernels
-void pcg_init(int n, const double *b, double *x, double *r, double *p0, double rtol, double *partials,
-              unsigned *counter, PcgState *st, double *hist, hipStream_t s);
-void pcg_spmv_p(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
-                double *partials, unsigned *counter, PcgState *st, hipStream_t s);
-void pcg_update(int n, const double *p, const double *q, double *x, double *r, double *partials, unsigned *counter,
-                PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s);
-void true_residual(const Csr &A, const RowCfg &c, const double *b, const double *x, double *partials,
-                   unsigned *counter, double *out2, hipStream_t s);
-void fill_zero(int64_t n, double *x, hipStream_t s);
+// PCG.  Each producer returns how many per-block partials it wrote.
+int pcg_init(int n, const double *b, double *x, double *r, double *p0, double rtol, double *pr2, PcgState *st,
+             hipStream_t s);
+void pcg_check(const double *pr2, int npr2, PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s);
+int pcg_dir(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
+            const double *prz, int nprz, double *ppq, PcgState *st, hipStream_t s);
+int pcg_update(int n, const double *p, const double *q, double *x, double *r, const double *ppq, int nppq, double *pr2,
+               PcgState *st, int32_t *hflag, hipStream_t s);
+void pcg_restart(PcgState *st, hipStream_t s);
+// partials of ||b - A x||^2 (and out = b - A x when out != null)
+int residual_norm(const Csr &A, const RowCfg &c, const double *b, const double *x, double *out, double *partials,
+                  hipStream_t s);
+void sum_to(const double *partials, int n, double *out, hipStream_t s);
 
 }  // namespace camg

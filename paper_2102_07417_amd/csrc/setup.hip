@@ -420,20 +420,34 @@ __global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int32_t *fl
     if (threadIdx.x == 0 && bad) atomicOr(&flags[5], 1);
 }
 
-// X = (L L^T)^{-1}, one thread per column: forward then backward substitution.
-__global__ void k_chol_inverse(int n, const double *L, double *X) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+// X = (L L^T)^{-1}: one wavefront per column j, forward then backward
+// substitution with the inner products split over the 64 lanes.
+__global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, double *X) {
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
     if (j >= n) return;
     for (int i = 0; i < n; ++i) {
-        double t = (i == j) ? 1.0 : 0.0;
-        for (int k = 0; k < i; ++k) t = t - L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
-        X[(int64_t)i * n + j] = t / L[(int64_t)i * n + i];
+        double t = 0.0;
+        for (int k = lane; k < i; k += 64) t += L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
+        t = wave_sum(t);
+        if (lane == 0) X[(int64_t)i * n + j] = ((i == j ? 1.0 : 0.0) - t) / L[(int64_t)i * n + i];
+        __syncthreads();
     }
     for (int i = n - 1; i >= 0; --i) {
-        double t = X[(int64_t)i * n + j];
-        for (int k = i + 1; k < n; ++k) t = t - L[(int64_t)k * n + i] * X[(int64_t)k * n + j];
-        X[(int64_t)i * n + j] = t / L[(int64_t)i * n + i];
+        double t = 0.0;
+        for (int k = i + 1 + lane; k < n; k += 64) t += L[(int64_t)k * n + i] * X[(int64_t)k * n + j];
+        t = wave_sum(t);
+        if (lane == 0) X[(int64_t)i * n + j] = (X[(int64_t)i * n + j] - t) / L[(int64_t)i * n + i];
+        __syncthreads();
     }
+}
+
+__global__ void k_max_row(int n, const int32_t *rp, int32_t *out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int len = i < n ? rp[i + 1] - rp[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, len);
 }
 
 }  // namespace
@@ -536,8 +550,18 @@ void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s) {
     HIPC(hipGetLastError());
 }
 void chol_inverse(int n, const double *L, double *X, hipStream_t s) {
-    k_chol_inverse<<<nblocks(n, 64), 64, 0, s>>>(n, L, X);
+    k_chol_inverse<<<n, 64, 0, s>>>(n, L, X);
     HIPC(hipGetLastError());
+}
+int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s) {
+    int32_t *d = tmp.alloc<int32_t>(1);
+    HIPC(hipMemsetAsync(d, 0, sizeof(int32_t), s));
+    k_max_row<<<nblocks(n), kBlock, 0, s>>>(n, rp, d);
+    HIPC(hipGetLastError());
+    int32_t h = 0;
+    HIPC(hipMemcpyAsync(&h, d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return h;
 }
 
 }  // namespace camg

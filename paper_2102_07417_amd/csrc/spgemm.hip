@@ -54,16 +54,31 @@ __global__ void k_row_products(int nr, CsrView X, CsrView Y, int64_t *prod) {
     prod[i] = p;
 }
 
-// bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is open
+// bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is
+// open.  One atomic per wavefront and bin: lanes of a bin take consecutive
+// slots after the wavefront's base.
 __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int nb, const int64_t *lim, int32_t *bcnt,
                            int32_t *brows, int stride) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
-    int b = 0;
-    while (b < nb - 1 && x > lim[b]) ++b;
-    const int pos = atomicAdd(&bcnt[b], 1);
-    brows[(int64_t)b * stride + pos] = i;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int b = -1;
+    if (i < nr) {
+        const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
+        b = 0;
+        while (b < nb - 1 && x > lim[b]) ++b;
+    }
+    for (int bb = 0; bb < nb; ++bb) {
+        const unsigned long long m = __ballot(b == bb);
+        if (m == 0ull) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bcnt[bb], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (b == bb) {
+            const int off = __popcll(m & ((1ull << lane) - 1ull));
+            brows[(int64_t)bb * stride + base + off] = i;
+        }
+    }
 }
 
 // Insert the columns of row i of X Y into the table; returns the number of
