@@ -129,6 +129,20 @@ def main():
         mixed = [one_step(camg.MIXED_FP32) for _ in range(args.steps)]
         xm = dx.cpu().numpy().copy()
 
+    # streaming-copy calibration of the HBM roof (1 GiB device-to-device)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     info = fp64[-1]["info"]
     solve_ms = statistics.median(r["solve_ms"] for r in fp64)
     setup_ms = statistics.median(r["setup_ms"] for r in fp64)
@@ -165,7 +179,7 @@ def main():
                      "achieved": round(k_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "alg_bytes_per_launch": k_bytes, "avg_launch_us": round(k_ms * 1e3, 3),
-                     "launches": launches},
+                     "launches": launches, "copy_kernel_gbs": round(copy_gbs, 1)},
     }
     if mixed:
         m_ms = statistics.median(r["solve_ms"] for r in mixed)

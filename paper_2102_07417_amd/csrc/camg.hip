@@ -124,6 +124,15 @@ void alloc_f32_copy(Pool &pool, Csr &M, hipStream_t s) {
     to_f32(M.nnz, M.v, M.v32, s);
 }
 
+RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
+    RowCfg c = choose_cfg(M.nr, M.nnz, max_row_length(M.nr, M.rp, tmp, s));
+    if (c.tile) {
+        c.tstart = h.pool.alloc<int32_t>((size_t)c.ntiles + 1);
+        tile_starts(M.nr, M.rp, c.W, c.ntiles, c.tstart, s);
+    }
+    return c;
+}
+
 void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const double *v, bool host_in,
                      hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -179,11 +188,13 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         std::memcpy(&rho, &hq, sizeof(rho));
         L.omega = prm.omega > 0.0 ? prm.omega : (4.0 / 3.0) / rho;
         scale_vec(nl, L.omega, L.dinv, L.wd, s);
+        L.awd = h.pool.alloc<double>(std::max<int64_t>(nz, 1));
+        scale_columns(L.A, L.wd, L.awd, s);
         // strength and PMIS
         L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
         L.stcnt = h.pool.alloc<int32_t>(nl);
         L.cf = h.pool.alloc<int8_t>(nl);
-        strength(nl, L.A.rp, L.A.ci, L.A.v, prm.theta, L.strong, L.stcnt, s);
+        strength(nl, L.A.rp, L.A.ci, L.A.v, tpos, prm.theta, L.strong, L.stcnt, s);
         uint64_t *u = lt.alloc<uint64_t>(nl);
         int8_t *newc = lt.alloc<int8_t>(nl);
         pmis_init(nl, L.stcnt, prm.seed, l, u, L.cf, und, s);
@@ -263,10 +274,10 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     for (int l = 0; l < h.nlev; ++l) {
         Level &L = h.lev[l];
         const int nl = L.A.nr;
-        L.cA = choose_cfg(nl, L.A.nnz, max_row_length(nl, L.A.rp, tmp, s));
+        L.cA = make_cfg(h, L.A, tmp, s);
         if (l < h.nlev - 1) {
-            L.cP = choose_cfg(L.P.nr, L.P.nnz, max_row_length(L.P.nr, L.P.rp, tmp, s));
-            L.cR = choose_cfg(L.R.nr, L.R.nnz, max_row_length(L.R.nr, L.R.rp, tmp, s));
+            L.cP = make_cfg(h, L.P, tmp, s);
+            L.cR = make_cfg(h, L.R, tmp, s);
         }
         if (!mixed) {
             if (l > 0) {
@@ -286,6 +297,8 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                 alloc_f32_copy(h.pool, L.R, s);
                 L.wd32 = h.pool.alloc<float>(nl);
                 to_f32(nl, L.wd, L.wd32, s);
+                L.awd32 = h.pool.alloc<float>(std::max<int64_t>(L.A.nnz, 1));
+                to_f32(L.A.nnz, L.awd, L.awd32, s);
             }
         }
         // extra buffer for more than one smoothing step
@@ -318,6 +331,7 @@ struct VT;
 template <>
 struct VT<double> {
     static const double *wd(const Level &L) { return L.wd; }
+    static const double *awd(const Level &L) { return L.awd; }
     static double *y(Level &L) { return L.y; }
     static double *s(Level &L) { return L.s; }
     static double *r(Level &L) { return L.r; }
@@ -327,6 +341,7 @@ struct VT<double> {
 template <>
 struct VT<float> {
     static const float *wd(const Level &L) { return L.wd32; }
+    static const float *awd(const Level &L) { return L.awd32; }
     static float *y(Level &L) { return L.y32; }
     static float *s(Level &L) { return L.s32; }
     static float *r(Level &L) { return L.r32; }
@@ -339,7 +354,7 @@ struct VT<float> {
 template <class T, class TY>
 T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
     T *sv = VT<T>::s(L), *tv = VT<T>::t(L);
-    vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), y, sv, VT<T>::r(L), st, s);
+    vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), VT<T>::awd(L), y, sv, VT<T>::r(L), st, s);
     if (h.prm.nu_pre > 1) {
         for (int it = 1; it < h.prm.nu_pre; ++it) {
             vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, st, s);

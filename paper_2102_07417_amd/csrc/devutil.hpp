@@ -61,6 +61,40 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
+// Block-wide integer sum / unsigned max; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ long long block_sum_ll(long long v) {
+    __shared__ long long ws[NT / kWave];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) ws[w] = v;
+    __syncthreads();
+    long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / kWave; ++i) t += ws[i];
+    __syncthreads();
+    return t;
+}
+
+template <int NT>
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v) {
+    __shared__ unsigned long long ws[NT / kWave];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long x = __shfl_xor(v, o, kWave);
+        v = x > v ? x : v;
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) ws[w] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / kWave; ++i) t = ws[i] > t ? ws[i] : t;
+    __syncthreads();
+    return t;
+}
+
 // Ticket for the "last block finishes the reduction" pattern.  Every block
 // calls it once after writing its partial; it returns true in exactly one
 // block, which then sees every other block's partial.

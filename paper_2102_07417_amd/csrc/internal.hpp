@@ -45,19 +45,21 @@ struct Csr {
 };
 
 // Launch shape of the row kernels of one matrix (chosen at set-up).
-//   tile: rows are processed in LDS tiles of `rpt` rows (at most tile_nnz
-//         nonzeros), `lpr` lanes summing each row; `grid` blocks take `tpb`
-//         consecutive tiles each.
+//   tile: tile t holds the rows whose first nonzero lies in [t W, (t+1) W);
+//         its products are staged in LDS and `lpr` lanes sum each row;
+//         `grid` blocks take `tpb` consecutive tiles each.
 //   vector (tile == false): `lpr` lanes walk each row, `rpt` rows per block.
 struct RowCfg {
     bool tile = false;
     int lpr = 8;
-    int rpt = 0;
-    int tile_nnz = 0;
+    int rpt = 0;          // vector mode: rows per block
+    int W = 0;            // tile mode: nominal nonzeros per tile
+    int tile_nnz = 0;     // LDS entries reserved per block
     int ntiles = 0;
     int grid = 8;
-    int tpb = 0;
+    int tpb = 0;          // consecutive tiles per block
     int maxrow = 0;
+    int32_t *tstart = nullptr;  // device: first row of each tile
 };
 
 struct Level {
@@ -65,6 +67,8 @@ struct Level {
     double *dinv = nullptr;   // 1 / a_ii
     double *wd = nullptr;     // omega * dinv_i
     float *wd32 = nullptr;
+    double *awd = nullptr;    // a_ij * wd_j (pre-smoothing values)
+    float *awd32 = nullptr;
     double omega = 0.0;
     int8_t *cf = nullptr;
     uint8_t *strong = nullptr;
@@ -141,8 +145,8 @@ void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v,
 void validate_sym(int n, const int32_t *rp, const int32_t *ci, const double *v, const unsigned long long *amax_bits,
                   int32_t *flags, int32_t *tpos, hipStream_t s);
 void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s);
-void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta, uint8_t *strong,
-              int32_t *stcnt, hipStream_t s);
+void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos, double theta,
+              uint8_t *strong, int32_t *stcnt, hipStream_t s);
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
                int32_t *undecided, hipStream_t s);
 void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
@@ -158,11 +162,13 @@ void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
 void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax_bits, int32_t *flags, hipStream_t s);
 void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t s);
+void scale_columns(const Csr &A, const double *wd, double *awd, hipStream_t s);
 void to_f32(int64_t n, const double *in, float *out, hipStream_t s);
 void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v, double *D, hipStream_t s);
 void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
+void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s);
 
 // ---------------------------------------------------------------- SpGEMM (spgemm.hip)
 // Z = X Y with the full symbolic pattern, rows sorted; for every output
@@ -178,8 +184,11 @@ RowCfg choose_cfg(int n, int64_t nnz, int maxrow);
 // the FP64 PCG residual); TZ: type of the output; DOT: write per-block
 // partials of y.z (level 0 inside PCG).  st may be null (standalone
 // V-cycle); otherwise the kernels return at once when st->done is set.
+// awd (may be null): A's values scaled by wd of their column, so the first
+// Jacobi step s_j = wd_j y_j needs one gather per nonzero instead of two.
 template <class T, class TY>
-void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const TY *y, T *s, T *r, const PcgState *st, hipStream_t str);
+void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const T *awd, const TY *y, T *s, T *r, const PcgState *st,
+            hipStream_t str);
 template <class T, class TY, class TZ, bool DOT>
 void vc_post(const Csr &A, const RowCfg &c, const T *wd, const TY *y, const T *s, TZ *z, double *partials,
              const PcgState *st, hipStream_t str);

@@ -125,26 +125,29 @@ __global__ void k_val_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *fla
 
 __global__ void k_val_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
                            unsigned long long *amax) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int bad_col = 0, bad_val = 0, has_diag = 0, bad_diag = 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int bad_col = 0, bad_val = 0, has_diag = 1, bad_diag = 0;
     double m = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        int c = ci[e];
-        if (c < 0 || c >= n || (e > rp[i] && c <= ci[e - 1])) bad_col = 1;
-        double a = v[e];
-        if (!isfinite(a)) bad_val = 1;
-        else if (fabs(a) > m) m = fabs(a);
-        if (c == i) {
-            has_diag = 1;
-            if (!(a > 0.0)) bad_diag = 1;
+    if (i < n) {
+        has_diag = 0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int c = ci[e];
+            if (c < 0 || c >= n || (e > rp[i] && c <= ci[e - 1])) bad_col = 1;
+            const double a = v[e];
+            if (!isfinite(a)) bad_val = 1;
+            else if (fabs(a) > m) m = fabs(a);
+            if (c == i) {
+                has_diag = 1;
+                if (!(a > 0.0)) bad_diag = 1;
+            }
         }
     }
     if (bad_col) atomicOr(&flags[1], 1);
     if (bad_val) atomicOr(&flags[2], 1);
     if (!has_diag) atomicOr(&flags[3], 1);
     if (bad_diag) atomicOr(&flags[5], 1);
-    atomicMax(amax, (unsigned long long)__double_as_longlong(m));
+    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) atomicMax(amax, bm);
 }
 
 // tpos[e] = position of entry (j, i) in row j for entry e = (i, j); checks
@@ -169,7 +172,7 @@ __global__ void k_tpos(int n, const int32_t *rp, const int32_t *ci, const double
 // Classical strength with threshold: m_i = max_{k != i} (-a_ik);
 // j in S_i iff j != i, m_i > 0 and -a_ij >= theta * m_i (one rounded product).
 __global__ void k_strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
-                           uint8_t *strong, int32_t *stcnt) {
+                           uint8_t *strong) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int have = 0;
@@ -183,10 +186,18 @@ __global__ void k_strength(int n, const int32_t *rp, const int32_t *ci, const do
     const double thr = theta * m;
     for (int e = e0; e < e1; ++e) {
         const int j = ci[e];
-        const int s = (j != i && have && m > 0.0 && -v[e] >= thr) ? 1 : 0;
-        strong[e] = (uint8_t)s;
-        if (s) atomicAdd(&stcnt[j], 1);
+        strong[e] = (j != i && have && m > 0.0 && -v[e] >= thr) ? 1 : 0;
     }
+}
+
+// |S_i^T| = number of rows j with i in S_j = sum over row i of the strong
+// flags at the transposed positions (the pattern is symmetric)
+__global__ void k_stcount(int n, const int32_t *rp, const int32_t *tpos, const uint8_t *strong, int32_t *stcnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) c += strong[tpos[e]];
+    stcnt[i] = c;
 }
 
 // ---------------------------------------------------------------- PMIS
@@ -203,8 +214,8 @@ __global__ void k_pmis_init(int n, const int32_t *stcnt, uint64_t seed, int leve
         state[i] = s;
         und = (s == kU);
     }
-    und = wave_sum_i(und);
-    if ((threadIdx.x & 63) == 0 && und) atomicAdd(undecided, und);
+    const long long bu = block_sum_ll<kBlock>(und);
+    if (threadIdx.x == 0 && bu) atomicAdd(undecided, (int32_t)bu);
 }
 
 __device__ __forceinline__ bool key_gt(const int32_t *cnt, const uint64_t *u, int a, int b) {
@@ -240,7 +251,7 @@ __global__ void k_pmis_select(int n, const int32_t *rp, const int32_t *ci, const
 // a new C point become F.
 __global__ void k_pmis_update(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
                               const int8_t *newc, int8_t *state, int32_t *undecided) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int und = 0;
     if (i < n && state[i] == kU) {
         if (newc[i]) state[i] = kC;
@@ -252,8 +263,8 @@ __global__ void k_pmis_update(int n, const int32_t *rp, const int32_t *ci, const
             else und = 1;
         }
     }
-    und = wave_sum_i(und);
-    if ((threadIdx.x & 63) == 0 && und) atomicAdd(undecided, und);
+    const long long bu = block_sum_ll<kBlock>(und);
+    if (threadIdx.x == 0 && bu) atomicAdd(undecided, (int32_t)bu);
 }
 
 __global__ void k_cf_flags(int n, const int8_t *cf, int32_t *isc) {
@@ -352,26 +363,36 @@ __global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
 // q over rows is the Gershgorin bound of rho(D^{-1} A).
 __global__ void k_diag_gersh(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                              unsigned long long *qmax, int32_t *flags) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0, d = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        s = s + fabs(v[e]);
-        if (ci[e] == i) d = v[e];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double q = 0.0;
+    if (i < n) {
+        double s = 0.0, d = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            s = s + fabs(v[e]);
+            if (ci[e] == i) d = v[e];
+        }
+        if (!(d > 0.0)) {
+            atomicOr(&flags[5], 1);
+            dinv[i] = 0.0;
+        } else {
+            dinv[i] = 1.0 / d;
+            q = s / d;
+        }
     }
-    if (!(d > 0.0)) {
-        atomicOr(&flags[5], 1);
-        dinv[i] = 0.0;
-        return;
-    }
-    dinv[i] = 1.0 / d;
-    const double q = s / d;
-    atomicMax(qmax, (unsigned long long)__double_as_longlong(q));
+    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
+    if (threadIdx.x == 0) atomicMax(qmax, bm);
 }
 
 __global__ void k_scale(int n, double omega, const double *dinv, double *wd) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) wd[i] = omega * dinv[i];
+}
+
+__global__ void k_scale_cols(int n, const int32_t *rp, const int32_t *ci, const double *v, const double *wd,
+                             double *awd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) awd[e] = v[e] * wd[ci[e]];
 }
 
 __global__ void k_to_f32(int64_t n, const double *in, float *out) {
@@ -443,11 +464,25 @@ __global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, dou
 }
 
 __global__ void k_max_row(int n, const int32_t *rp, int32_t *out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int len = i < n ? rp[i + 1] - rp[i] : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, len);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int len = i < n ? rp[i + 1] - rp[i] : 0;
+    const unsigned long long m = block_max_u64<kBlock>((unsigned long long)len);
+    if (threadIdx.x == 0) atomicMax(out, (int32_t)m);
+}
+
+// Tiles of the row kernels: tile t holds the rows whose first nonzero lies
+// in [t W, (t+1) W).  tstart[t] = first row of tile t; tstart[ntiles] = n.
+__global__ void k_tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        const int tp = rp[n - 1] / W;
+        for (int t = tp + 1; t <= ntiles; ++t) tstart[t] = n;
+        return;
+    }
+    const int ti = rp[i] / W;
+    const int tp = i == 0 ? -1 : rp[i - 1] / W;
+    for (int t = tp + 1; t <= ti && t < ntiles; ++t) tstart[t] = i;
 }
 
 }  // namespace
@@ -478,10 +513,10 @@ void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *t
     k_tpos<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, nullptr, nullptr, nullptr, tpos);
     HIPC(hipGetLastError());
 }
-void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta, uint8_t *strong,
-              int32_t *stcnt, hipStream_t s) {
-    HIPC(hipMemsetAsync(stcnt, 0, sizeof(int32_t) * (size_t)n, s));
-    k_strength<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, theta, strong, stcnt);
+void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos, double theta,
+              uint8_t *strong, int32_t *stcnt, hipStream_t s) {
+    k_strength<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, theta, strong);
+    k_stcount<<<nblocks(n), kBlock, 0, s>>>(n, rp, tpos, strong, stcnt);
     HIPC(hipGetLastError());
 }
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
@@ -535,6 +570,11 @@ void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t 
     k_scale<<<nblocks(n), kBlock, 0, s>>>(n, omega, dinv, wd);
     HIPC(hipGetLastError());
 }
+void scale_columns(const Csr &A, const double *wd, double *awd, hipStream_t s) {
+    k_scale_cols<<<nblocks(A.nr), kBlock, 0, s>>>(A.nr, A.rp, A.ci, A.v, wd, awd);
+    HIPC(hipGetLastError());
+}
+
 void to_f32(int64_t n, const double *in, float *out, hipStream_t s) {
     if (n > 0) k_to_f32<<<nblocks(n), kBlock, 0, s>>>(n, in, out);
     HIPC(hipGetLastError());
@@ -553,6 +593,11 @@ void chol_inverse(int n, const double *L, double *X, hipStream_t s) {
     k_chol_inverse<<<n, 64, 0, s>>>(n, L, X);
     HIPC(hipGetLastError());
 }
+void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s) {
+    k_tile_starts<<<nblocks(n + 1), kBlock, 0, s>>>(n, rp, W, ntiles, tstart);
+    HIPC(hipGetLastError());
+}
+
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s) {
     int32_t *d = tmp.alloc<int32_t>(1);
     HIPC(hipMemsetAsync(d, 0, sizeof(int32_t), s));

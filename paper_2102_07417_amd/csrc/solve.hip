@@ -2,12 +2,14 @@
 // with Jacobi smoothing (eq. smoother, M = D) and the PCG recurrence.
 //
 // Row kernels come in two shapes, chosen per matrix at set-up:
-//  - tile: a block takes `rpt` consecutive rows whose nonzeros fit an LDS
-//    tile; phase 1 streams the tile's column indices and values with
-//    coalesced loads, forms a_ij * g(x_j) for every nonzero (many gathers in
-//    flight per thread) and parks the products in LDS; phase 2 lets `lpr`
-//    lanes per row add them up and runs the row's epilogue.  Used whenever
-//    the longest row fits the tile (every matrix of the workloads here).
+//  - tile: tile t holds the rows whose first nonzero lies in [t W, (t+1) W)
+//    (W ~ 256 mean rows, at most 4096), so every tile carries about the same
+//    number of nonzeros;
+//    phase 1 streams the tile's column indices and values with coalesced
+//    loads, forms a_ij * g(x_j) for every nonzero (eight gathers in flight
+//    per thread) and parks the products in LDS; phase 2 lets `lpr` lanes per
+//    row add them up and runs the row's epilogue.  Used whenever the longest
+//    row fits the LDS reserve (every matrix of the workloads here).
 //  - vector: `lpr` lanes walk each row directly (rows too long for a tile).
 // Blocks are renumbered so that each XCD owns one contiguous slab of rows
 // (its L2 then serves the gathered vector entries those rows share).
@@ -24,15 +26,17 @@ namespace camg {
 
 namespace {
 
-constexpr int kTileNnz = 2048;  // LDS tile capacity (nonzeros)
+constexpr int kTileW = 4096;      // largest nominal nonzeros per tile
+constexpr int kTileMaxRow = 4096; // longest row a tile can hold (LDS <= 8192 entries)
 
 template <class T>
 struct MatArg {
     const int32_t *__restrict__ rp;
     const int32_t *__restrict__ ci;
     const T *__restrict__ v;
+    const int32_t *__restrict__ tstart;  // tile mode: first row of each tile (ntiles + 1)
     int n;
-    int rpt;     // tile: rows per tile; vector: rows per block
+    int rpt;     // vector mode: rows per block
     int ntiles;  // tile mode
     int tpb;     // tiles per block
 };
@@ -45,8 +49,8 @@ template <>
 const float *vals<float>(const Csr &A) { return A.v32; }
 
 template <class T>
-MatArg<T> mat_arg(const Csr &A, const RowCfg &c) {
-    return MatArg<T>{A.rp, A.ci, vals<T>(A), A.nr, c.rpt, c.ntiles, c.tpb};
+MatArg<T> mat_arg(const Csr &A, const RowCfg &c, const T *v = nullptr) {
+    return MatArg<T>{A.rp, A.ci, v ? v : vals<T>(A), c.tstart, A.nr, c.rpt, c.ntiles, c.tpb};
 }
 
 // Sum of partials[0..n) in index order, result in every thread of the block.
@@ -60,48 +64,78 @@ __device__ __forceinline__ double sum_all(const double *partials, int n) {
     return r;
 }
 
-// Walk this block's rows; for each row call epi(i, sum_j a_ij g(j), dot).
+// Walk this block's rows; for each row i call
+//   epi.finish(i, sum_j a_ij g(j), epi.load(i), dot).
+// In tile mode the first row a lane group owns has its row pointers and its
+// epilogue operands loaded before phase 1, so those loads overlap the
+// streaming of the tile; phase 2 then only touches LDS and the output.
 template <class T, int LPR, bool TILE, class G, class E>
 __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E &epi, T *prod, double &dot) {
     const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
     constexpr int RPP = kBlock / LPR;  // rows per pass
+    using Pre = typename E::Pre;
     if (TILE) {
         const int b = xcd_block();
-        const int t0 = b * M.tpb, t1 = min(M.ntiles, t0 + M.tpb);
+        const int t0 = (int)((int64_t)b * M.ntiles / gridDim.x);
+        const int t1 = (int)((int64_t)(b + 1) * M.ntiles / gridDim.x);
         for (int t = t0; t < t1; ++t) {
-            const int r0 = t * M.rpt, r1 = min(M.n, r0 + M.rpt);
+            const int r0 = M.tstart[t], r1 = M.tstart[t + 1];
+            if (r0 == r1) continue;
             const int e0 = M.rp[r0], m = M.rp[r1] - e0;
+            const int i = r0 + grp;
+            const bool has = i < r1;
+            int qa = 0, qz = 0;
+            Pre pre{};
+            if (has) {
+                qa = M.rp[i] - e0;
+                qz = M.rp[i + 1] - e0;
+                if (sl == 0) pre = epi.load(i);
+            }
             int k = threadIdx.x;
+            for (; k + 7 * kBlock < m; k += 8 * kBlock) {
+                int j[8];
+                T a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) j[u] = M.ci[e0 + k + u * kBlock];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = M.v[e0 + k + u * kBlock];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
+            }
             for (; k + 3 * kBlock < m; k += 4 * kBlock) {
-                const int e = e0 + k;
-                const int j0 = M.ci[e], j1 = M.ci[e + kBlock], j2 = M.ci[e + 2 * kBlock], j3 = M.ci[e + 3 * kBlock];
-                const T a0 = M.v[e], a1 = M.v[e + kBlock], a2 = M.v[e + 2 * kBlock], a3 = M.v[e + 3 * kBlock];
-                const T g0 = g(j0), g1 = g(j1), g2 = g(j2), g3 = g(j3);
-                prod[k] = a0 * g0;
-                prod[k + kBlock] = a1 * g1;
-                prod[k + 2 * kBlock] = a2 * g2;
-                prod[k + 3 * kBlock] = a3 * g3;
+                int j[4];
+                T a[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) j[u] = M.ci[e0 + k + u * kBlock];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = M.v[e0 + k + u * kBlock];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
             }
-            for (; k < m; k += kBlock) {
-                const int e = e0 + k;
-                prod[k] = M.v[e] * g(M.ci[e]);
-            }
+            for (; k < m; k += kBlock) prod[k] = M.v[e0 + k] * g(M.ci[e0 + k]);
             __syncthreads();
-            for (int ib = r0; ib < r1; ib += RPP) {
-                const int i = ib + grp;
+            {
                 T acc = 0;
-                if (i < r1) {
-                    const int a = M.rp[i] - e0, z = M.rp[i + 1] - e0;
-                    for (int q = a + sl; q < z; q += LPR) acc += prod[q];
+                for (int q = qa + sl; q < qz; q += LPR) acc += prod[q];
+                acc = group_sum<LPR>(acc);
+                if (has && sl == 0) epi.finish(i, acc, pre, dot);
+            }
+            for (int ib = r0 + RPP; ib < r1; ib += RPP) {
+                const int i2 = ib + grp;
+                T acc = 0;
+                if (i2 < r1) {
+                    const int a2 = M.rp[i2] - e0, z2 = M.rp[i2 + 1] - e0;
+                    for (int q = a2 + sl; q < z2; q += LPR) acc += prod[q];
                 }
                 acc = group_sum<LPR>(acc);
-                if (i < r1 && sl == 0) epi(i, acc, dot);
+                if (i2 < r1 && sl == 0) epi.finish(i2, acc, epi.load(i2), dot);
             }
             __syncthreads();
         }
     } else {
         const int b = xcd_block();
-        const int r0 = min(M.n, b * M.rpt), r1 = min(M.n, r0 + M.rpt);
+        const int r0 = (int)((int64_t)b * M.n / gridDim.x);
+        const int r1 = (int)((int64_t)(b + 1) * M.n / gridDim.x);
         for (int ib = r0; ib < r1; ib += RPP) {
             const int i = ib + grp;
             T acc = 0;
@@ -110,7 +144,7 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
                 for (int e = M.rp[i] + sl; e < e1; e += LPR) acc += M.v[e] * g(M.ci[e]);
             }
             acc = group_sum<LPR>(acc);
-            if (i < r1 && sl == 0) epi(i, acc, dot);
+            if (i < r1 && sl == 0) epi.finish(i, acc, epi.load(i), dot);
         }
     }
 }
@@ -122,10 +156,10 @@ struct GPre {  // s_j of the first Jacobi step from s = 0
     const TY *y;
     __device__ T operator()(int j) const { return wd[j] * (T)y[j]; }
 };
-template <class T>
+template <class T, class TX = T>
 struct GVec {
-    const T *x;
-    __device__ T operator()(int j) const { return x[j]; }
+    const TX *x;
+    __device__ T operator()(int j) const { return (T)x[j]; }
 };
 struct GDir {  // the new search direction, formed on the fly
     const double *z, *p;
@@ -139,10 +173,13 @@ struct EPre {  // s = wd y, r = y - A s
     const T *wd;
     const TY *y;
     T *s, *r;
-    __device__ void operator()(int i, T acc, double &) const {
-        const T yi = (T)y[i];
-        s[i] = wd[i] * yi;
-        r[i] = yi - acc;
+    struct Pre {
+        T yi, wdi;
+    };
+    __device__ Pre load(int i) const { return Pre{(T)y[i], wd[i]}; }
+    __device__ void finish(int i, T acc, const Pre &p, double &) const {
+        s[i] = p.wdi * p.yi;
+        r[i] = p.yi - acc;
     }
 };
 template <class T, class TY, class TZ>
@@ -151,42 +188,61 @@ struct EPost {  // z = s + wd (y - A s); dot += y.z
     const TY *y;
     const T *s;
     TZ *z;
-    __device__ void operator()(int i, T acc, double &dot) const {
-        const T yi = (T)y[i];
-        const T zi = s[i] + wd[i] * (yi - acc);
+    struct Pre {
+        TY yo;
+        T wdi, si;
+    };
+    __device__ Pre load(int i) const { return Pre{y[i], wd[i], s[i]}; }
+    __device__ void finish(int i, T acc, const Pre &p, double &dot) const {
+        const T zi = p.si + p.wdi * ((T)p.yo - acc);
         const TZ zo = (TZ)zi;
         z[i] = zo;
-        dot += (double)y[i] * (double)zo;
+        dot += (double)p.yo * (double)zo;
     }
 };
 template <class T, class TY>
 struct EResid {  // r = y - A s
     const TY *y;
     T *r;
-    __device__ void operator()(int i, T acc, double &) const { r[i] = (T)y[i] - acc; }
+    struct Pre {
+        T yi;
+    };
+    __device__ Pre load(int i) const { return Pre{(T)y[i]}; }
+    __device__ void finish(int i, T acc, const Pre &p, double &) const { r[i] = p.yi - acc; }
 };
 template <class T, bool ADD>
 struct ESpmv {
     T *out;
-    __device__ void operator()(int i, T acc, double &) const { out[i] = ADD ? out[i] + acc : acc; }
+    struct Pre {
+        T o;
+    };
+    __device__ Pre load(int i) const { return Pre{ADD ? out[i] : T(0)}; }
+    __device__ void finish(int i, T acc, const Pre &p, double &) const { out[i] = ADD ? p.o + acc : acc; }
 };
 struct EDir {  // p_new, q = A p_new, dot += p.q
     const double *z, *pold;
     double beta;
     bool first;
     double *pnew, *q;
-    __device__ void operator()(int i, double acc, double &dot) const {
-        const double pi = first ? z[i] : z[i] + beta * pold[i];
-        pnew[i] = pi;
+    struct Pre {
+        double pi;
+    };
+    __device__ Pre load(int i) const { return Pre{first ? z[i] : z[i] + beta * pold[i]}; }
+    __device__ void finish(int i, double acc, const Pre &p, double &dot) const {
+        pnew[i] = p.pi;
         q[i] = acc;
-        dot += pi * acc;
+        dot += p.pi * acc;
     }
 };
 struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
     const double *b;
     double *out;
-    __device__ void operator()(int i, double acc, double &dot) const {
-        const double d = b[i] - acc;
+    struct Pre {
+        double bi;
+    };
+    __device__ Pre load(int i) const { return Pre{b[i]}; }
+    __device__ void finish(int i, double acc, const Pre &p, double &dot) const {
+        const double d = p.bi - acc;
         if (out) out[i] = d;
         dot += d * d;
     }
@@ -368,8 +424,8 @@ __global__ void __launch_bounds__(kBlock) k_sum_to(const double *partials, int n
 
 template <class T, bool DOT, class G, class E>
 void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *partials, const PcgState *st,
-                 hipStream_t s) {
-    const MatArg<T> M = mat_arg<T>(A, c);
+                 hipStream_t s, const T *values = nullptr) {
+    const MatArg<T> M = mat_arg<T>(A, c, values);
     const size_t smem = c.tile ? (size_t)c.tile_nnz * sizeof(T) : 0;
     if (c.tile) {
         CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, st)));
@@ -389,19 +445,25 @@ int pow2_ceil(double x) {
 
 RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
     RowCfg c;
-    const double mean = n > 0 ? (double)nnz / n : 1.0;
-    if (maxrow <= kTileNnz) {
+    const double mean = n > 0 ? std::max(1.0, (double)nnz / n) : 1.0;
+    c.maxrow = maxrow;
+    if (maxrow <= kTileMaxRow) {
+        // about kBlock rows per tile, at most kTileW nonzeros
+        int W = (int)std::min<double>(kTileW, std::max(256.0, kBlock * mean));
+        W = (W + 63) / 64 * 64;
         c.tile = true;
-        int rpt = 1;
-        while (rpt * 2 <= 1024 && (int64_t)rpt * 2 * std::max(maxrow, 1) <= kTileNnz) rpt *= 2;
-        c.rpt = rpt;
-        c.tile_nnz = rpt * std::max(maxrow, 1);
-        c.lpr = std::max(1, pow2_ceil(mean) / 2);
-        c.ntiles = (n + rpt - 1) / rpt;
+        c.W = W;
+        c.tile_nnz = W + std::max(maxrow, 1);
+        const double rows = W / mean;
+        int l = 1;
+        while (l * 2 <= 64 && l * 2 * rows <= kBlock) l *= 2;
+        c.lpr = l;
+        c.ntiles = (int)std::max<int64_t>(1, (nnz + W - 1) / W);
         int g = std::min(c.ntiles, kMaxGrid);
         g = std::max(8, (g + 7) / 8 * 8);
         c.grid = g;
         c.tpb = (c.ntiles + g - 1) / g;
+        c.rpt = 0;
     } else {
         c.tile = false;
         c.lpr = 64;
@@ -416,7 +478,6 @@ RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
         c.tpb = 0;
         c.tile_nnz = 0;
     }
-    c.maxrow = maxrow;
     return c;
 }
 
@@ -426,9 +487,12 @@ int vec_grid(int n) {
 }
 
 template <class T, class TY>
-void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const TY *y, T *s, T *r, const PcgState *st,
+void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const T *awd, const TY *y, T *s, T *r, const PcgState *st,
             hipStream_t str) {
-    launch_rows<T, false>(A, c, GPre<T, TY>{wd, y}, EPre<T, TY>{wd, y, s, r}, nullptr, st, str);
+    if (awd)  // values pre-scaled by wd_j: one gather per nonzero
+        launch_rows<T, false>(A, c, GVec<T, TY>{y}, EPre<T, TY>{wd, y, s, r}, nullptr, st, str, awd);
+    else
+        launch_rows<T, false>(A, c, GPre<T, TY>{wd, y}, EPre<T, TY>{wd, y, s, r}, nullptr, st, str);
 }
 
 template <class T, class TY, class TZ, bool DOT>
@@ -458,8 +522,8 @@ void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *s
     HIPC(hipGetLastError());
 }
 
-#define INST_PRE(T, TY) template void vc_pre<T, TY>(const Csr &, const RowCfg &, const T *, const TY *, T *, T *, \
-                                                     const PcgState *, hipStream_t);
+#define INST_PRE(T, TY) template void vc_pre<T, TY>(const Csr &, const RowCfg &, const T *, const T *, const TY *, T *, \
+                                                     T *, const PcgState *, hipStream_t);
 INST_PRE(double, double)
 INST_PRE(float, float)
 INST_PRE(float, double)

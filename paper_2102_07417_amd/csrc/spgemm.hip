@@ -55,30 +55,25 @@ __global__ void k_row_products(int nr, CsrView X, CsrView Y, int64_t *prod) {
 }
 
 // bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is
-// open.  One atomic per wavefront and bin: lanes of a bin take consecutive
-// slots after the wavefront's base.
+// open.  Slots are taken per block: LDS counters first, then one global
+// atomic per block and bin.
 __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int nb, const int64_t *lim, int32_t *bcnt,
                            int32_t *brows, int stride) {
+    __shared__ int lcnt[8], lbase[8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    int b = -1;
+    if (threadIdx.x < 8) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int b = -1, off = 0;
     if (i < nr) {
         const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
         b = 0;
         while (b < nb - 1 && x > lim[b]) ++b;
+        off = atomicAdd(&lcnt[b], 1);
     }
-    for (int bb = 0; bb < nb; ++bb) {
-        const unsigned long long m = __ballot(b == bb);
-        if (m == 0ull) continue;
-        const int leader = __ffsll((long long)m) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&bcnt[bb], __popcll(m));
-        base = __shfl(base, leader, 64);
-        if (b == bb) {
-            const int off = __popcll(m & ((1ull << lane) - 1ull));
-            brows[(int64_t)bb * stride + base + off] = i;
-        }
-    }
+    __syncthreads();
+    if (threadIdx.x < nb) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&bcnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
+    __syncthreads();
+    if (b >= 0) brows[(int64_t)b * stride + lbase[b] + off] = i;
 }
 
 // Insert the columns of row i of X Y into the table; returns the number of
