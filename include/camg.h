@@ -181,6 +181,14 @@ void camg_free_host(void *p);
  */
 camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_t *launches);
 
+/*
+ * Options of a handle.  CAMG_OPT_GRAPH (default 1): run each PCG iteration
+ * as a captured HIP graph (0: launch the kernels one by one; the results
+ * are bitwise the same).
+ */
+enum { CAMG_OPT_GRAPH = 1 };
+camg_status camg_set_option(camg_handle h, int32_t option, int64_t value);
+
 /* Release the hierarchy and all its device memory.  NULL is ignored. */
 camg_status camg_destroy(camg_handle h);
 

@@ -26,7 +26,9 @@ EXPORTED = [
     "camg_abi_version", "camg_status_str", "camg_last_error", "camg_params_default", "camg_setup",
     "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
     "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
+    "camg_set_option",
 ]
+OPT_GRAPH = 1
 
 
 class camg_params(C.Structure):
@@ -74,7 +76,8 @@ def load(path: str | None = None):
     L.camg_free_host.argtypes = [vp]
     L.camg_destroy.argtypes = [vp]
     L.camg_profile.argtypes = [vp, i32, vp, vp]
-    for name in ("camg_profile", "camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
+    L.camg_set_option.argtypes = [vp, i32, i64]
+    for name in ("camg_profile", "camg_set_option", "camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
                  "camg_vcycle_dev", "camg_info", "camg_level_sizes", "camg_export_level", "camg_galerkin",
                  "camg_destroy"):
         getattr(L, name).restype = C.c_int
@@ -209,6 +212,10 @@ def camg_profile(h, enable):
     n = np.zeros(1, np.int64)
     _check(load().camg_profile(h, int(enable), _p(t), _p(n)))
     return float(t[0]), int(n[0])
+
+
+def camg_set_option(h, option, value):
+    return load().camg_set_option(h, int(option), int(value))
 
 
 def camg_destroy(h):

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -308,6 +309,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         }
     }
     const int n0 = h.lev[0].A.nr;
+    h.x = h.pool.alloc<double>(n0);
     h.r = h.pool.alloc<double>(n0);
     h.z = h.pool.alloc<double>(n0);
     h.p[0] = h.pool.alloc<double>(n0);
@@ -349,6 +351,8 @@ struct VT<float> {
     static float *t(Level &L) { return L.t32; }
 };
 
+int32_t *st_count(PcgState *st, size_t off) { return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(st) + off); }
+
 // Pre-smoothing (nu_pre steps from s = 0) and residual on level l.
 // Returns the buffer that holds s.
 template <class T, class TY>
@@ -357,7 +361,7 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
     vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), VT<T>::awd(L), y, sv, VT<T>::r(L), st, s);
     if (h.prm.nu_pre > 1) {
         for (int it = 1; it < h.prm.nu_pre; ++it) {
-            vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, st, s);
+            vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, tv, nullptr, nullptr, st, s);
             std::swap(sv, tv);
         }
         vc_resid<T, TY>(L.A, L.cA, y, sv, VT<T>::r(L), st, s);
@@ -366,37 +370,38 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
 }
 
 // Post-smoothing (nu_post steps) into z; with dot the last step also writes
-// the partials of y.z into h.prz.
+// the partials of y.z into h.prz (bracketed by the timing events of parity
+// `par` when timing is on).
 template <class T, class TY, class TZ>
-void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
+void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, int par, PcgState *st, hipStream_t s) {
     T *tv = VT<T>::t(L);
     for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
         T *out = (tv == sv) ? VT<T>::s(L) : tv;
-        vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, st, s);
+        vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, nullptr, st, s);
         sv = out;
     }
     if (dot) {
-        const bool p = h.prof && h.pcount + 1 < (int)h.pev.size() / 2;
-        if (p) HIPC(hipEventRecord(h.pev[2 * h.pcount], s));
-        vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.prz, st, s);
-        if (p) HIPC(hipEventRecord(h.pev[2 * h.pcount + 1], s));
-        if (p) ++h.pcount;
+        if (h.prof) HIPC(hipEventRecord(h.pev[par][0], s));
+        vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.prz, st_count(st, offsetof(PcgState, n_rz)),
+                                 st, s);
+        if (h.prof) HIPC(hipEventRecord(h.pev[par][1], s));
     } else {
-        vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, st, s);
+        vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, nullptr, st, s);
     }
 }
 
 // z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.  With
-// dot, the partials of y0.z0 land in h.prz; returns their number.
+// dot, the partials of y0.z0 land in h.prz and their count in st->n_rz.
 template <class T>
-int vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
+void vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, int par, hipStream_t s) {
     const int L = h.nlev - 1;
     if (L == 0) {
         // one level: direct solve (FP64)
         coarse_solve<double>(h.nL, h.cinv, y0, z0, st, s);
-        return dot ? dot_partials(h.nL, y0, z0, h.prz, st, s) : 0;
+        if (dot) dot_partials(h.nL, y0, z0, h.prz, st_count(st, offsetof(PcgState, n_rz)), st, s);
+        return;
     }
-    std::vector<T *> sv(h.nlev, nullptr);
+    T *sv[CAMG_MAX_LEVELS] = {};
     for (int l = 0; l < L; ++l) {
         Level &Lv = h.lev[l];
         if (l == 0) sv[0] = smooth_pre<T, double>(h, Lv, y0, st, s);
@@ -407,15 +412,14 @@ int vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipS
     for (int l = L - 1; l >= 0; --l) {
         Level &Lv = h.lev[l];
         vc_prolong<T>(Lv.P, Lv.cP, VT<T>::z(h.lev[l + 1]), sv[l], st, s);
-        if (l == 0) smooth_post<T, double, double>(h, Lv, y0, sv[0], z0, dot, st, s);
-        else smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, st, s);
+        if (l == 0) smooth_post<T, double, double>(h, Lv, y0, sv[0], z0, dot, par, st, s);
+        else smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, par, st, s);
     }
-    return dot ? h.lev[0].cA.grid : 0;
 }
 
-int vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, hipStream_t s) {
-    if (h.prm.precision == CAMG_MIXED_FP32) return vcycle_t<float>(h, y0, z0, st, dot, s);
-    return vcycle_t<double>(h, y0, z0, st, dot, s);
+void vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, int par, hipStream_t s) {
+    if (h.prm.precision == CAMG_MIXED_FP32) vcycle_t<float>(h, y0, z0, st, dot, par, s);
+    else vcycle_t<double>(h, y0, z0, st, dot, par, s);
 }
 
 // ---------------------------------------------------------------- PCG
@@ -423,16 +427,65 @@ void ensure_hist(Hier &h, int cap) {
     if (h.dhist_cap >= cap) return;
     h.dhist = h.pool.alloc<double>(cap);
     h.dhist_cap = cap;
+    h.graph_ok = false;
+}
+
+// One PCG iteration of parity `par` (p[par] holds the previous direction):
+// stopping test, V-cycle, new direction with q = A p, x/r update.
+void enqueue_iteration(Hier &h, int par, hipStream_t s) {
+    const Csr &A = h.lev[0].A;
+    pcg_check(h.pr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
+    vcycle(h, h.r, h.z, h.st, true, par, s);
+    pcg_dir(A, h.lev[0].cA, h.z, h.p[par], h.p[1 - par], h.q, h.prz, h.ppq, h.st, s);
+    pcg_update(A.nr, h.p[1 - par], h.q, h.x, h.r, h.ppq, h.pr2, h.st, h.hflag_dev, s);
+}
+
+void destroy_graphs(Hier &h) {
+    for (int p = 0; p < 2; ++p) {
+        if (h.gexec[p]) (void)hipGraphExecDestroy(h.gexec[p]);
+        if (h.graph[p]) (void)hipGraphDestroy(h.graph[p]);
+        h.gexec[p] = nullptr;
+        h.graph[p] = nullptr;
+    }
+    h.graph_ok = false;
+}
+
+// Capture the two iteration parities as graphs (their kernel arguments only
+// name buffers the handle owns, so they stay valid across solves).  Any
+// failure falls back to direct launches.
+void build_graphs(Hier &h) {
+    destroy_graphs(h);
+    if (!h.cap_stream) HIPC(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+    for (int p = 0; p < 2; ++p) {
+        HIPC(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_iteration(h, p, h.cap_stream);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(h.cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        HIPC(hipStreamEndCapture(h.cap_stream, &h.graph[p]));
+        HIPC(hipGraphInstantiate(&h.gexec[p], h.graph[p], nullptr, nullptr, 0));
+    }
+    h.graph_ok = true;
 }
 
 // PCG iterations k = k0 .. max_iter-1 (fewer if the stopping test or a
 // breakdown ends them).  The host polls a host-mapped flag one iteration
-// behind the device, so the queue never runs dry.
-void run_iterations(Hier &h, const double *b, double *x, int k0, int &npr2, hipStream_t s) {
-    (void)b;
-    const Csr &A = h.lev[0].A;
-    const int n = A.nr;
+// behind the device, so the queue never runs dry.  With timing on, the
+// kernel time of iteration k is appended to `times` as (k, ms).
+void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, hipStream_t s) {
     const int max_iter = h.prm.max_iter;
+    if (h.use_graph && !h.graph_ok) {
+        try {
+            build_graphs(h);
+        } catch (const Error &) {
+            destroy_graphs(h);
+            h.use_graph = false;
+        }
+    }
     hipEvent_t ev[2];
     HIPC(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPC(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -440,29 +493,38 @@ void run_iterations(Hier &h, const double *b, double *x, int k0, int &npr2, hipS
         hipEvent_t *e;
         ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
     } eg{ev};
+    auto collect = [&](int k) {
+        if (!h.prof) return;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h.pev[k & 1][0], h.pev[k & 1][1]) == hipSuccess) times.emplace_back(k, ms);
+        else (void)hipGetLastError();
+    };
     volatile int32_t *flag = h.hflag;
     flag[0] = 0;
+    int last = -1;
     for (int k = k0; k < max_iter; ++k) {
-        pcg_check(h.pr2, npr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
-        const int nprz = vcycle(h, h.r, h.z, h.st, true, s);
-        const int nppq = pcg_dir(A, h.lev[0].cA, h.z, h.p[k & 1], h.p[(k + 1) & 1], h.q, h.prz, nprz, h.ppq, h.st, s);
-        npr2 = pcg_update(n, h.p[(k + 1) & 1], h.q, x, h.r, h.ppq, nppq, h.pr2, h.st, h.hflag_dev, s);
-        HIPC(hipEventRecord(ev[k & 1], s));
+        const int par = k & 1;
+        if (h.use_graph && h.graph_ok) HIPC(hipGraphLaunch(h.gexec[par], s));
+        else enqueue_iteration(h, par, s);
+        HIPC(hipEventRecord(ev[par], s));
+        last = k;
         if (k > k0) {
-            HIPC(hipEventSynchronize(ev[(k - 1) & 1]));
+            HIPC(hipEventSynchronize(ev[1 - par]));
+            collect(k - 1);
             if (flag[0]) break;
         }
     }
     // the stopping test for the last residual formed
-    pcg_check(h.pr2, npr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
+    pcg_check(h.pr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
     HIPC(hipStreamSynchronize(s));
+    if (last >= 0) collect(last);
 }
 
-double true_relres_of(Hier &h, const double *b, const double *x, double bnorm, double *r_out, int *npr2, hipStream_t s) {
+double true_relres_of(Hier &h, const double *b, const double *x, double bnorm, double *r_out, hipStream_t s) {
     const Csr &A = h.lev[0].A;
     double *part = r_out ? h.pr2 : h.ptmp;
-    const int np = residual_norm(A, h.lev[0].cA, b, x, r_out, part, s);
-    if (npr2) *npr2 = np;
+    int32_t *nout = r_out ? st_count(h.st, offsetof(PcgState, n_r2)) : nullptr;
+    const int np = residual_norm(A, h.lev[0].cA, b, x, r_out, part, nout, s);
     sum_to(part, np, h.sc, s);
     const double t2 = read1(h.sc, s);
     return bnorm > 0.0 ? std::sqrt(t2) / bnorm : 0.0;
@@ -473,41 +535,38 @@ camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t 
     const Csr &A = h.lev[0].A;
     const int n = A.nr;
     ensure_hist(h, h.prm.max_iter + 2);
-    int npr2 = pcg_init(n, b, x, h.r, h.p[0], rtol, h.pr2, h.st, s);
-    run_iterations(h, b, x, 0, npr2, s);
+    std::vector<std::pair<int, float>> times;
+    pcg_init(n, b, h.x, h.r, h.p[0], rtol, h.pr2, h.st, s);
+    run_iterations(h, 0, times, s);
     PcgState st = read1(h.st, s);
     double rel = -1.0;
     // mixed precision: if the recursive residual met the test but the true
     // one does not, restart from r = b - A x (at most twice)
     if (h.prm.precision == CAMG_MIXED_FP32 && rtol > 0.0) {
         for (int rep = 0; rep < 2 && st.done && st.status == 0; ++rep) {
-            rel = true_relres_of(h, b, x, st.bnorm, nullptr, nullptr, s);
+            rel = true_relres_of(h, b, h.x, st.bnorm, nullptr, s);
             if (rel < rtol || st.iter >= h.prm.max_iter) break;
-            true_relres_of(h, b, x, st.bnorm, h.r, &npr2, s);
+            true_relres_of(h, b, h.x, st.bnorm, h.r, s);
             pcg_restart(h.st, s);
-            run_iterations(h, b, x, st.iter, npr2, s);
+            run_iterations(h, st.iter, times, s);
             st = read1(h.st, s);
             rel = -1.0;
         }
     }
-    if (h.prof) {
-        // launches after convergence return at once: keep only those that ran
-        for (int i = 0; i < h.pcount; ++i) {
-            if (i >= st.iter) break;
-            float ms = 0.f;
-            HIPC(hipEventElapsedTime(&ms, h.pev[2 * i], h.pev[2 * i + 1]));
-            h.prof_ms += ms;
+    // launches after convergence return at once: keep the iterations that ran
+    for (const auto &t : times)
+        if (t.first < st.iter) {
+            h.prof_ms += t.second;
             h.prof_launches += 1;
         }
-        h.pcount = 0;
-    }
+    HIPC(hipMemcpyAsync(x, h.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
     const int it = st.iter;
     if (iters) *iters = it;
     if (hist && hist_cap > 0) {
         const int m = std::min(hist_cap, it + 1);
         HIPC(hipMemcpyAsync(hist, h.dhist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     }
-    if (true_relres) *true_relres = rel >= 0.0 ? rel : true_relres_of(h, b, x, st.bnorm, nullptr, nullptr, s);
+    if (true_relres) *true_relres = rel >= 0.0 ? rel : true_relres_of(h, b, h.x, st.bnorm, nullptr, s);
     HIPC(hipStreamSynchronize(s));
     if (st.status == (int32_t)CAMG_E_BREAKDOWN) {
         g_last_error = "CG breakdown: p.Ap <= 0 or r.z <= 0";
@@ -637,7 +696,7 @@ camg_status camg_vcycle_dev(camg_handle hh, const double *d_y, double *d_z, void
         if (!d_y || !d_z) fail(CAMG_E_ARG, "null vector");
         BusyGuard g(h);
         HIPC(hipSetDevice(h->device));
-        vcycle(*h, d_y, d_z, nullptr, false, (hipStream_t)hip_stream);
+        vcycle(*h, d_y, d_z, nullptr, false, 0, (hipStream_t)hip_stream);
         HIPC(hipStreamSynchronize((hipStream_t)hip_stream));
     });
 }
@@ -772,7 +831,11 @@ camg_status camg_destroy(camg_handle hh) {
         (void)hipSetDevice(h->device);
         (void)hipDeviceSynchronize();
         if (h->hflag) (void)hipHostFree(h->hflag);
-        for (auto &e : h->pev) (void)hipEventDestroy(e);
+        for (auto &pp : h->pev)
+            for (auto &e : pp)
+                if (e) (void)hipEventDestroy(e);
+        destroy_graphs(*h);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         delete static_cast<camg_hier *>(hh);
     });
 }
@@ -786,11 +849,25 @@ camg_status camg_profile(camg_handle hh, int32_t enable, double *total_ms, int64
         if (launches) *launches = h->prof_launches;
         h->prof_ms = 0.0;
         h->prof_launches = 0;
-        h->pcount = 0;
-        h->prof = enable != 0;
-        if (h->prof && h->pev.empty()) {
-            h->pev.resize(2 * ((size_t)h->prm.max_iter + 2));
-            for (auto &e : h->pev) HIPC(hipEventCreate(&e));
+        const bool on = enable != 0;
+        if (on && !h->pev[0][0])
+            for (auto &pp : h->pev)
+                for (auto &e : pp) HIPC(hipEventCreate(&e));
+        if (on != h->prof) h->graph_ok = false;  // the graphs carry the timing events or not
+        h->prof = on;
+    });
+}
+
+camg_status camg_set_option(camg_handle hh, int32_t option, int64_t value) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        BusyGuard g(h);
+        switch (option) {
+        case CAMG_OPT_GRAPH:
+            h->use_graph = value != 0;
+            h->graph_ok = false;
+            break;
+        default: fail(CAMG_E_ARG, "unknown option");
         }
     });
 }

@@ -82,9 +82,12 @@ struct Level {
 };
 
 // Scalars of one PCG recurrence, resident on the device.
+// n_r2, n_rz, n_pq: how many per-block partials the last producer of each
+// sum wrote (read by the consumer, so launches need no host knowledge).
 struct PcgState {
     double rho, rho_old, sigma, alpha, beta, rnorm, bnorm, tol, rtol;
     int32_t iter, done, status, restart;
+    int32_t n_r2, n_rz, n_pq, pad;
 };
 
 struct Hier {
@@ -97,7 +100,7 @@ struct Hier {
     float *cinv32 = nullptr;
     Pool pool;              // everything the handle owns
     // PCG work
-    double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *t = nullptr;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     double *pr2 = nullptr;       // per-block partials of ||r||^2
     double *prz = nullptr;       // per-block partials of r.z
     double *ppq = nullptr;       // per-block partials of p.q
@@ -112,10 +115,15 @@ struct Hier {
     double setup_ms = 0.0;
     // optional timing of the level-0 post-smoothing kernel inside solves
     bool prof = false;
-    std::vector<hipEvent_t> pev;  // start/end pairs
-    int pcount = 0;               // pairs recorded since the last read
+    hipEvent_t pev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][start/end]
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
+    // one PCG iteration captured as a graph, per parity of the iteration
+    bool use_graph = true;
+    bool graph_ok = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;
     // multi-RHS work (allocated on first use for a given k)
     int mk = 0;
     double *mr = nullptr, *mz = nullptr, *mp[2] = {nullptr, nullptr}, *mq = nullptr;
@@ -191,7 +199,7 @@ void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const T *awd, const TY *
             hipStream_t str);
 template <class T, class TY, class TZ, bool DOT>
 void vc_post(const Csr &A, const RowCfg &c, const T *wd, const TY *y, const T *s, TZ *z, double *partials,
-             const PcgState *st, hipStream_t str);
+             int32_t *nout, const PcgState *st, hipStream_t str);
 template <class T, class TY>
 void vc_resid(const Csr &A, const RowCfg &c, const TY *y, const T *s, T *r, const PcgState *st, hipStream_t str);
 template <class T>
@@ -201,20 +209,21 @@ void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState 
 template <class T>
 void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *st, hipStream_t str);
 // partial sums of y.z; returns the number of partials
-int dot_partials(int n, const double *y, const double *z, double *partials, const PcgState *st, hipStream_t s);
+int dot_partials(int n, const double *y, const double *z, double *partials, int32_t *nout, const PcgState *st,
+                 hipStream_t s);
 
 // PCG.  Each producer returns how many per-block partials it wrote.
 int pcg_init(int n, const double *b, double *x, double *r, double *p0, double rtol, double *pr2, PcgState *st,
              hipStream_t s);
-void pcg_check(const double *pr2, int npr2, PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s);
+void pcg_check(const double *pr2, PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s);
 int pcg_dir(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
-            const double *prz, int nprz, double *ppq, PcgState *st, hipStream_t s);
-int pcg_update(int n, const double *p, const double *q, double *x, double *r, const double *ppq, int nppq, double *pr2,
+            const double *prz, double *ppq, PcgState *st, hipStream_t s);
+int pcg_update(int n, const double *p, const double *q, double *x, double *r, const double *ppq, double *pr2,
                PcgState *st, int32_t *hflag, hipStream_t s);
 void pcg_restart(PcgState *st, hipStream_t s);
 // partials of ||b - A x||^2 (and out = b - A x when out != null)
 int residual_norm(const Csr &A, const RowCfg &c, const double *b, const double *x, double *out, double *partials,
-                  hipStream_t s);
+                  int32_t *nout, hipStream_t s);
 void sum_to(const double *partials, int n, double *out, hipStream_t s);
 
 }  // namespace camg

@@ -250,7 +250,8 @@ struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
 
 // ------------------------------------------------------------------ kernels
 template <class T, int LPR, bool TILE, bool DOT, class G, class E>
-__global__ void __launch_bounds__(kBlock) k_rows(MatArg<T> M, G g, E e, double *partials, const PcgState *st) {
+__global__ void __launch_bounds__(kBlock) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
+                                                 const PcgState *st) {
     if (st && st->done) return;
     extern __shared__ double smem_d[];
     T *prod = reinterpret_cast<T *>(smem_d);
@@ -258,7 +259,10 @@ __global__ void __launch_bounds__(kBlock) k_rows(MatArg<T> M, G g, E e, double *
     run_rows<T, LPR, TILE>(M, g, e, prod, dot);
     if (DOT) {
         const double b = block_sum<kBlock>(dot);
-        if (threadIdx.x == 0) partials[blockIdx.x] = b;
+        if (threadIdx.x == 0) {
+            partials[blockIdx.x] = b;
+            if (nout && blockIdx.x == 0) *nout = gridDim.x;
+        }
     }
 }
 
@@ -278,12 +282,15 @@ __global__ void __launch_bounds__(kBlock) k_coarse(int n, const double *__restri
 
 // partial sums of y.z (one-level hierarchy: nothing to fuse into)
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const double *__restrict__ y, const double *__restrict__ z,
-                                                double *partials, const PcgState *st) {
+                                                double *partials, int32_t *nout, const PcgState *st) {
     if (st && st->done) return;
     double acc = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc += y[i] * z[i];
     const double b = block_sum<kBlock>(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = b;
+        if (nout && blockIdx.x == 0) *nout = gridDim.x;
+    }
 }
 
 // x = 0, r = b, p = 0; partials of ||b||^2; state reset
@@ -303,6 +310,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const double *__rest
     if (threadIdx.x == 0) {
         pr2[blockIdx.x] = bs;
         if (blockIdx.x == 0) {
+            st->n_r2 = gridDim.x;
+            st->n_rz = 0;
+            st->n_pq = 0;
             st->rho = st->rho_old = st->sigma = st->alpha = st->beta = 0.0;
             st->rnorm = 0.0;
             st->bnorm = -1.0;
@@ -318,10 +328,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const double *__rest
 
 // Stopping test at the start of an iteration (and once after the last):
 // ||r_k|| from the partials of the kernel that formed r_k.
-__global__ void __launch_bounds__(kBlock) k_pcg_check(const double *pr2, int npr2, PcgState *st, double *hist,
-                                                      int hist_cap, int32_t *hflag) {
+__global__ void __launch_bounds__(kBlock) k_pcg_check(const double *pr2, PcgState *st, double *hist, int hist_cap,
+                                                      int32_t *hflag) {
     if (st->done) return;
-    const double rn = sqrt(sum_all(pr2, npr2));
+    const double rn = sqrt(sum_all(pr2, st->n_r2));
     if (threadIdx.x == 0) {
         if (st->bnorm < 0.0) {
             st->bnorm = rn;
@@ -342,11 +352,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_check(const double *pr2, int npr
 template <int LPR, bool TILE>
 __global__ void __launch_bounds__(kBlock) k_pcg_dir(MatArg<double> M, const double *__restrict__ z,
                                                     const double *__restrict__ pold, double *__restrict__ pnew,
-                                                    double *__restrict__ q, const double *prz, int nprz, double *ppq,
+                                                    double *__restrict__ q, const double *prz, double *ppq,
                                                     PcgState *st) {
     if (st->done) return;
     extern __shared__ double smem_d[];
-    const double rho = sum_all(prz, nprz);
+    const double rho = sum_all(prz, st->n_rz);
     const bool first = st->iter == st->restart;
     const double beta = first ? 0.0 : rho / st->rho_old;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -356,17 +366,20 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(MatArg<double> M, const doub
     double dot = 0.0;
     run_rows<double, LPR, TILE>(M, GDir{z, pold, beta, first}, EDir{z, pold, beta, first, pnew, q}, smem_d, dot);
     const double b = block_sum<kBlock>(dot);
-    if (threadIdx.x == 0) ppq[blockIdx.x] = b;
+    if (threadIdx.x == 0) {
+        ppq[blockIdx.x] = b;
+        if (blockIdx.x == 0) st->n_pq = gridDim.x;
+    }
 }
 
 // sigma = sum of the p.q partials; breakdown test; alpha = rho / sigma;
 // x += alpha p, r -= alpha q; partials of ||r||^2
 __global__ void __launch_bounds__(kBlock) k_pcg_update(int n, const double *__restrict__ p,
                                                        const double *__restrict__ q, double *__restrict__ x,
-                                                       double *__restrict__ r, const double *ppq, int nppq,
-                                                       double *pr2, PcgState *st, int32_t *hflag) {
+                                                       double *__restrict__ r, const double *ppq, double *pr2,
+                                                       PcgState *st, int32_t *hflag) {
     if (st->done) return;
-    const double sigma = sum_all(ppq, nppq);
+    const double sigma = sum_all(ppq, st->n_pq);
     const double rho = st->rho;
     if (!(sigma > 0.0) || !(rho > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -394,6 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int n, const double *__re
             st->alpha = alpha;
             st->rho_old = rho;
             st->iter = st->iter + 1;
+            st->n_r2 = gridDim.x;
         }
     }
 }
@@ -423,14 +437,14 @@ __global__ void __launch_bounds__(kBlock) k_sum_to(const double *partials, int n
     }
 
 template <class T, bool DOT, class G, class E>
-void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *partials, const PcgState *st,
-                 hipStream_t s, const T *values = nullptr) {
+void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *partials, int32_t *nout,
+                 const PcgState *st, hipStream_t s, const T *values = nullptr) {
     const MatArg<T> M = mat_arg<T>(A, c, values);
     const size_t smem = c.tile ? (size_t)c.tile_nnz * sizeof(T) : 0;
     if (c.tile) {
-        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, st)));
+        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
     } else {
-        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, false, DOT, G, E><<<c.grid, kBlock, 0, s>>>(M, g, e, partials, st)));
+        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, false, DOT, G, E><<<c.grid, kBlock, 0, s>>>(M, g, e, partials, nout, st)));
     }
     HIPC(hipGetLastError());
 }
@@ -490,30 +504,30 @@ template <class T, class TY>
 void vc_pre(const Csr &A, const RowCfg &c, const T *wd, const T *awd, const TY *y, T *s, T *r, const PcgState *st,
             hipStream_t str) {
     if (awd)  // values pre-scaled by wd_j: one gather per nonzero
-        launch_rows<T, false>(A, c, GVec<T, TY>{y}, EPre<T, TY>{wd, y, s, r}, nullptr, st, str, awd);
+        launch_rows<T, false>(A, c, GVec<T, TY>{y}, EPre<T, TY>{wd, y, s, r}, nullptr, nullptr, st, str, awd);
     else
-        launch_rows<T, false>(A, c, GPre<T, TY>{wd, y}, EPre<T, TY>{wd, y, s, r}, nullptr, st, str);
+        launch_rows<T, false>(A, c, GPre<T, TY>{wd, y}, EPre<T, TY>{wd, y, s, r}, nullptr, nullptr, st, str);
 }
 
 template <class T, class TY, class TZ, bool DOT>
 void vc_post(const Csr &A, const RowCfg &c, const T *wd, const TY *y, const T *s, TZ *z, double *partials,
-             const PcgState *st, hipStream_t str) {
-    launch_rows<T, DOT>(A, c, GVec<T>{s}, EPost<T, TY, TZ>{wd, y, s, z}, partials, st, str);
+             int32_t *nout, const PcgState *st, hipStream_t str) {
+    launch_rows<T, DOT>(A, c, GVec<T>{s}, EPost<T, TY, TZ>{wd, y, s, z}, partials, nout, st, str);
 }
 
 template <class T, class TY>
 void vc_resid(const Csr &A, const RowCfg &c, const TY *y, const T *s, T *r, const PcgState *st, hipStream_t str) {
-    launch_rows<T, false>(A, c, GVec<T>{s}, EResid<T, TY>{y, r}, nullptr, st, str);
+    launch_rows<T, false>(A, c, GVec<T>{s}, EResid<T, TY>{y, r}, nullptr, nullptr, st, str);
 }
 
 template <class T>
 void vc_restrict(const Csr &R, const RowCfg &c, const T *r, T *yc, const PcgState *st, hipStream_t str) {
-    launch_rows<T, false>(R, c, GVec<T>{r}, ESpmv<T, false>{yc}, nullptr, st, str);
+    launch_rows<T, false>(R, c, GVec<T>{r}, ESpmv<T, false>{yc}, nullptr, nullptr, st, str);
 }
 
 template <class T>
 void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState *st, hipStream_t str) {
-    launch_rows<T, false>(P, c, GVec<T>{d}, ESpmv<T, true>{s}, nullptr, st, str);
+    launch_rows<T, false>(P, c, GVec<T>{d}, ESpmv<T, true>{s}, nullptr, nullptr, st, str);
 }
 
 template <class T>
@@ -533,7 +547,8 @@ INST_RES(double, double)
 INST_RES(float, float)
 INST_RES(float, double)
 #define INST_POST(T, TY, TZ, D) template void vc_post<T, TY, TZ, D>(const Csr &, const RowCfg &, const T *, const TY *, \
-                                                                     const T *, TZ *, double *, const PcgState *, hipStream_t);
+                                                                     const T *, TZ *, double *, int32_t *, const PcgState *, \
+                                                                     hipStream_t);
 INST_POST(double, double, double, false)
 INST_POST(double, double, double, true)
 INST_POST(float, float, float, false)
@@ -549,9 +564,10 @@ template void vc_prolong<float>(const Csr &, const RowCfg &, const float *, floa
 template void coarse_solve<double>(int, const double *, const double *, double *, const PcgState *, hipStream_t);
 template void coarse_solve<float>(int, const double *, const float *, float *, const PcgState *, hipStream_t);
 
-int dot_partials(int n, const double *y, const double *z, double *partials, const PcgState *st, hipStream_t s) {
+int dot_partials(int n, const double *y, const double *z, double *partials, int32_t *nout, const PcgState *st,
+                 hipStream_t s) {
     const int g = std::min(kMaxGrid, std::max(1, (n + kBlock - 1) / kBlock));
-    k_dot<<<g, kBlock, 0, s>>>(n, y, z, partials, st);
+    k_dot<<<g, kBlock, 0, s>>>(n, y, z, partials, nout, st);
     HIPC(hipGetLastError());
     return g;
 }
@@ -564,28 +580,28 @@ int pcg_init(int n, const double *b, double *x, double *r, double *p0, double rt
     return g;
 }
 
-void pcg_check(const double *pr2, int npr2, PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s) {
-    k_pcg_check<<<1, kBlock, 0, s>>>(pr2, npr2, st, hist, hist_cap, hflag);
+void pcg_check(const double *pr2, PcgState *st, double *hist, int hist_cap, int32_t *hflag, hipStream_t s) {
+    k_pcg_check<<<1, kBlock, 0, s>>>(pr2, st, hist, hist_cap, hflag);
     HIPC(hipGetLastError());
 }
 
 int pcg_dir(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
-            const double *prz, int nprz, double *ppq, PcgState *st, hipStream_t s) {
+            const double *prz, double *ppq, PcgState *st, hipStream_t s) {
     const MatArg<double> M = mat_arg<double>(A, c);
     const size_t smem = c.tile ? (size_t)c.tile_nnz * sizeof(double) : 0;
     if (c.tile) {
-        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, true><<<c.grid, kBlock, smem, s>>>(M, z, pold, pnew, q, prz, nprz, ppq, st)));
+        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, true><<<c.grid, kBlock, smem, s>>>(M, z, pold, pnew, q, prz, ppq, st)));
     } else {
-        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, false><<<c.grid, kBlock, 0, s>>>(M, z, pold, pnew, q, prz, nprz, ppq, st)));
+        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, false><<<c.grid, kBlock, 0, s>>>(M, z, pold, pnew, q, prz, ppq, st)));
     }
     HIPC(hipGetLastError());
     return c.grid;
 }
 
-int pcg_update(int n, const double *p, const double *q, double *x, double *r, const double *ppq, int nppq, double *pr2,
+int pcg_update(int n, const double *p, const double *q, double *x, double *r, const double *ppq, double *pr2,
                PcgState *st, int32_t *hflag, hipStream_t s) {
     const int g = vec_grid(n);
-    k_pcg_update<<<g, kBlock, 0, s>>>(n, p, q, x, r, ppq, nppq, pr2, st, hflag);
+    k_pcg_update<<<g, kBlock, 0, s>>>(n, p, q, x, r, ppq, pr2, st, hflag);
     HIPC(hipGetLastError());
     return g;
 }
@@ -596,8 +612,8 @@ void pcg_restart(PcgState *st, hipStream_t s) {
 }
 
 int residual_norm(const Csr &A, const RowCfg &c, const double *b, const double *x, double *out, double *partials,
-                  hipStream_t s) {
-    launch_rows<double, true>(A, c, GVec<double>{x}, EResNorm{b, out}, partials, nullptr, s);
+                  int32_t *nout, hipStream_t s) {
+    launch_rows<double, true>(A, c, GVec<double>{x}, EResNorm{b, out}, partials, nout, nullptr, s);
     return c.grid;
 }
 

@@ -222,3 +222,55 @@ def test_full_size_lognormal_128(camg):
     assert np.linalg.norm(dx.cpu().numpy() - ro.x) / np.linalg.norm(ro.x) <= 1e-9
     assert rg.true_relres < 1e-8 * 1.01
     g.close()
+
+
+def test_graph_replays_match_direct_launches(camg):
+    """Each PCG iteration runs as a captured graph; replays across several
+    solves, with unrelated eager GPU work in between, must give bitwise the
+    same iterates as launching the kernels one by one."""
+    A = PB.lognormal3d(20, 2.0)
+    b1, b2 = PB.rhs(A.n, 1), PB.rhs(A.n, 2)
+    s = camg.Solver(A)
+    assert camg.camg_set_option(s.h, camg.OPT_GRAPH, 0) == camg.OK
+    d1, d2 = s.solve(b1), s.solve(b2)
+    assert camg.camg_set_option(s.h, camg.OPT_GRAPH, 1) == camg.OK
+    g1 = s.solve(b1)
+    t = torch.randn(1 << 20, device="cuda:0")
+    float(t.sum())
+    torch.cuda.synchronize()
+    g2 = s.solve(b2)
+    g1b = s.solve(b1)
+    for d, g in [(d1, g1), (d2, g2), (d1, g1b)]:
+        assert d.iters == g.iters and np.array_equal(d.x, g.x) and np.array_equal(d.hist, g.hist)
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["lognormal3d_24", "elasticity_6", "aniso3d_20"])
+def test_mixed_precision_reaches_fp64_tolerance(camg, name):
+    """FP32 V-cycle inside FP64 PCG: the true residual still drops below
+    rtol; the error against the FP64 oracle solution is reported."""
+    print(f"[gpu] mixed {name}", flush=True)
+    A = CASES[name]()
+    b = PB.rhs(A.n)
+    o = O.Hierarchy(A, max_iter=3000)
+    ro = o.solve(b, 1e-8, max_iter=3000)
+    s = camg.Solver(A, precision=camg.MIXED_FP32, max_iter=3000)
+    r = s.solve(b, rtol=1e-8)
+    err = np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x)
+    print(f"[gpu] mixed {name}: iters {r.iters} (fp64 oracle {ro.iters}) true_relres {r.true_relres:.2e} "
+          f"err_vs_oracle {err:.2e}", flush=True)
+    assert r.status == camg.OK and r.true_relres < 1e-8
+    assert r.iters <= ro.iters + 5
+    assert err < 1e-6
+    s.close()
+
+
+def test_kernel_timing_hook(camg):
+    A = PB.lognormal3d(24, 2.0)
+    b = PB.rhs(A.n)
+    s = camg.Solver(A)
+    camg.camg_profile(s.h, 1)
+    r = s.solve(b)
+    ms, launches = camg.camg_profile(s.h, 0)
+    assert launches == r.iters and ms > 0
+    s.close()
