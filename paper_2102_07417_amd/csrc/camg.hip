@@ -121,7 +121,7 @@ void validate_input(Hier &h, int n, int64_t nnz, const Csr &A, int32_t *tpos, Po
 }
 
 void alloc_f32_copy(Pool &pool, Csr &M, hipStream_t s) {
-    M.v32 = pool.alloc<float>(std::max<int64_t>(M.nnz, 1));
+    M.v32 = pool.alloc<float>(padded(M.nnz));
     to_f32(M.nnz, M.v, M.v32, s);
 }
 
@@ -151,8 +151,8 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         A.nr = A.nc = n;
         A.nnz = nnz;
         A.rp = h.pool.alloc<int32_t>((size_t)n + 1);
-        A.ci = h.pool.alloc<int32_t>(std::max<int64_t>(nnz, 1));
-        A.v = h.pool.alloc<double>(std::max<int64_t>(nnz, 1));
+        A.ci = h.pool.alloc<int32_t>(padded(nnz));
+        A.v = h.pool.alloc<double>(padded(nnz));
         const hipMemcpyKind k = host_in ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
         HIPC(hipMemcpyAsync(A.rp, rp, sizeof(int32_t) * ((size_t)n + 1), k, s));
         HIPC(hipMemcpyAsync(A.ci, ci, sizeof(int32_t) * (size_t)nnz, k, s));
@@ -189,7 +189,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         std::memcpy(&rho, &hq, sizeof(rho));
         L.omega = prm.omega > 0.0 ? prm.omega : (4.0 / 3.0) / rho;
         scale_vec(nl, L.omega, L.dinv, L.wd, s);
-        L.awd = h.pool.alloc<double>(std::max<int64_t>(nz, 1));
+        L.awd = h.pool.alloc<double>(padded(nz));
         scale_columns(L.A, L.wd, L.awd, s);
         // strength and PMIS
         L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
@@ -226,8 +226,8 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         P.nnz = read1(prp64 + nl, s);
         P.rp = h.pool.alloc<int32_t>((size_t)nl + 1);
         narrow_i64(prp64, P.rp, nl, s);
-        P.ci = h.pool.alloc<int32_t>(std::max<int64_t>(P.nnz, 1));
-        P.v = h.pool.alloc<double>(std::max<int64_t>(P.nnz, 1));
+        P.ci = h.pool.alloc<int32_t>(padded(P.nnz));
+        P.v = h.pool.alloc<double>(padded(P.nnz));
         interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
         // R = P^T
         Csr &R = L.R;
@@ -240,8 +240,8 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         scan_i32_to_i64(ccnt, rrp64, P.nc, lt, s);
         R.rp = h.pool.alloc<int32_t>((size_t)P.nc + 1);
         narrow_i64(rrp64, R.rp, P.nc, s);
-        R.ci = h.pool.alloc<int32_t>(std::max<int64_t>(R.nnz, 1));
-        R.v = h.pool.alloc<double>(std::max<int64_t>(R.nnz, 1));
+        R.ci = h.pool.alloc<int32_t>(padded(R.nnz));
+        R.v = h.pool.alloc<double>(padded(R.nnz));
         transpose_csr(P, R, lt, s);
         // Galerkin product A_{l+1} = R (A P)  (eq. AcDef)
         Csr AP, Ac;
@@ -298,7 +298,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                 alloc_f32_copy(h.pool, L.R, s);
                 L.wd32 = h.pool.alloc<float>(nl);
                 to_f32(nl, L.wd, L.wd32, s);
-                L.awd32 = h.pool.alloc<float>(std::max<int64_t>(L.A.nnz, 1));
+                L.awd32 = h.pool.alloc<float>(padded(L.A.nnz));
                 to_f32(L.A.nnz, L.awd, L.awd32, s);
             }
         }
@@ -370,56 +370,58 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
 }
 
 // Post-smoothing (nu_post steps) into z; with dot the last step also writes
-// the partials of y.z into h.prz (bracketed by the timing events of parity
-// `par` when timing is on).
+// the partials of y.z into h.prz and their count into st->n_rz.
 template <class T, class TY, class TZ>
-void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, int par, PcgState *st, hipStream_t s) {
+void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
     T *tv = VT<T>::t(L);
     for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
         T *out = (tv == sv) ? VT<T>::s(L) : tv;
         vc_post<T, TY, T, false>(L.A, L.cA, VT<T>::wd(L), y, sv, out, nullptr, nullptr, st, s);
         sv = out;
     }
-    if (dot) {
-        if (h.prof) HIPC(hipEventRecord(h.pev[par][0], s));
+    if (dot)
         vc_post<T, TY, TZ, true>(L.A, L.cA, VT<T>::wd(L), y, sv, z, h.prz, st_count(st, offsetof(PcgState, n_rz)),
                                  st, s);
-        if (h.prof) HIPC(hipEventRecord(h.pev[par][1], s));
-    } else {
+    else
         vc_post<T, TY, TZ, false>(L.A, L.cA, VT<T>::wd(L), y, sv, z, nullptr, nullptr, st, s);
-    }
 }
 
-// z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.  With
-// dot, the partials of y0.z0 land in h.prz and their count in st->n_rz.
+// z0 = M y0 with T-valued levels; y0, z0 are FP64 level-0 vectors.  The
+// cycle is split in two parts: `head` runs everything up to and including
+// the level-0 prolongation, `tail` the level-0 post-smoothing (with dot, the
+// partials of y0.z0 land in h.prz and their count in st->n_rz).
 template <class T>
-void vcycle_t(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, int par, hipStream_t s) {
+void vcycle_part(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, bool head, bool tail, hipStream_t s) {
     const int L = h.nlev - 1;
-    if (L == 0) {
-        // one level: direct solve (FP64)
-        coarse_solve<double>(h.nL, h.cinv, y0, z0, st, s);
-        if (dot) dot_partials(h.nL, y0, z0, h.prz, st_count(st, offsetof(PcgState, n_rz)), st, s);
+    if (L == 0) {  // one level: direct solve (FP64)
+        if (head) coarse_solve<double>(h.nL, h.cinv, y0, z0, st, s);
+        if (tail && dot) dot_partials(h.nL, y0, z0, h.prz, st_count(st, offsetof(PcgState, n_rz)), st, s);
         return;
     }
-    T *sv[CAMG_MAX_LEVELS] = {};
-    for (int l = 0; l < L; ++l) {
-        Level &Lv = h.lev[l];
-        if (l == 0) sv[0] = smooth_pre<T, double>(h, Lv, y0, st, s);
-        else sv[l] = smooth_pre<T, T>(h, Lv, VT<T>::y(Lv), st, s);
-        vc_restrict<T>(Lv.R, Lv.cR, VT<T>::r(Lv), VT<T>::y(h.lev[l + 1]), st, s);
+    // the level-0 iterate ends up in s or t depending on nu_pre
+    T *s0 = (h.prm.nu_pre % 2 == 1) ? VT<T>::s(h.lev[0]) : VT<T>::t(h.lev[0]);
+    if (head) {
+        T *sv[CAMG_MAX_LEVELS] = {};
+        for (int l = 0; l < L; ++l) {
+            Level &Lv = h.lev[l];
+            if (l == 0) sv[0] = smooth_pre<T, double>(h, Lv, y0, st, s);
+            else sv[l] = smooth_pre<T, T>(h, Lv, VT<T>::y(Lv), st, s);
+            vc_restrict<T>(Lv.R, Lv.cR, VT<T>::r(Lv), VT<T>::y(h.lev[l + 1]), st, s);
+        }
+        coarse_solve<T>(h.nL, h.cinv, VT<T>::y(h.lev[L]), VT<T>::z(h.lev[L]), st, s);
+        for (int l = L - 1; l >= 0; --l) {
+            Level &Lv = h.lev[l];
+            vc_prolong<T>(Lv.P, Lv.cP, VT<T>::z(h.lev[l + 1]), sv[l], st, s);
+            if (l > 0) smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, st, s);
+        }
+        if (sv[0] != s0) fail(CAMG_E_DEVICE, "internal: unexpected smoothing buffer");
     }
-    coarse_solve<T>(h.nL, h.cinv, VT<T>::y(h.lev[L]), VT<T>::z(h.lev[L]), st, s);
-    for (int l = L - 1; l >= 0; --l) {
-        Level &Lv = h.lev[l];
-        vc_prolong<T>(Lv.P, Lv.cP, VT<T>::z(h.lev[l + 1]), sv[l], st, s);
-        if (l == 0) smooth_post<T, double, double>(h, Lv, y0, sv[0], z0, dot, par, st, s);
-        else smooth_post<T, T, T>(h, Lv, VT<T>::y(Lv), sv[l], VT<T>::z(Lv), false, par, st, s);
-    }
+    if (tail) smooth_post<T, double, double>(h, h.lev[0], y0, s0, z0, dot, st, s);
 }
 
-void vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, int par, hipStream_t s) {
-    if (h.prm.precision == CAMG_MIXED_FP32) vcycle_t<float>(h, y0, z0, st, dot, par, s);
-    else vcycle_t<double>(h, y0, z0, st, dot, par, s);
+void vcycle(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, bool head, bool tail, hipStream_t s) {
+    if (h.prm.precision == CAMG_MIXED_FP32) vcycle_part<float>(h, y0, z0, st, dot, head, tail, s);
+    else vcycle_part<double>(h, y0, z0, st, dot, head, tail, s);
 }
 
 // ---------------------------------------------------------------- PCG
@@ -430,55 +432,88 @@ void ensure_hist(Hier &h, int cap) {
     h.graph_ok = false;
 }
 
-// One PCG iteration of parity `par` (p[par] holds the previous direction):
-// stopping test, V-cycle, new direction with q = A p, x/r update.
-void enqueue_iteration(Hier &h, int par, hipStream_t s) {
+// One PCG iteration of parity `par` (p[par] holds the previous direction)
+// in three segments: (0) stopping test and the V-cycle up to the level-0
+// prolongation, (1) level-0 post-smoothing with the r.z partials, (2) new
+// direction with q = A p, then the x / r update.
+void enqueue_segment(Hier &h, int par, int seg, hipStream_t s) {
     const Csr &A = h.lev[0].A;
-    pcg_check(h.pr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
-    vcycle(h, h.r, h.z, h.st, true, par, s);
-    pcg_dir(A, h.lev[0].cA, h.z, h.p[par], h.p[1 - par], h.q, h.prz, h.ppq, h.st, s);
-    pcg_update(A.nr, h.p[1 - par], h.q, h.x, h.r, h.ppq, h.pr2, h.st, h.hflag_dev, s);
+    if (seg == 0) {
+        pcg_check(h.pr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
+        vcycle(h, h.r, h.z, h.st, true, true, false, s);
+    } else if (seg == 1) {
+        vcycle(h, h.r, h.z, h.st, true, false, true, s);
+    } else {
+        pcg_dir(A, h.lev[0].cA, h.z, h.p[par], h.p[1 - par], h.q, h.prz, h.ppq, h.st, s);
+        pcg_update(A.nr, h.p[1 - par], h.q, h.x, h.r, h.ppq, h.pr2, h.st, h.hflag_dev, s);
+    }
 }
 
 void destroy_graphs(Hier &h) {
-    for (int p = 0; p < 2; ++p) {
-        if (h.gexec[p]) (void)hipGraphExecDestroy(h.gexec[p]);
-        if (h.graph[p]) (void)hipGraphDestroy(h.graph[p]);
-        h.gexec[p] = nullptr;
-        h.graph[p] = nullptr;
-    }
+    for (int k = 0; k < 3; ++k)
+        for (int p = 0; p < 2; ++p) {
+            if (h.gexec[k][p]) (void)hipGraphExecDestroy(h.gexec[k][p]);
+            if (h.graph[k][p]) (void)hipGraphDestroy(h.graph[k][p]);
+            h.gexec[k][p] = nullptr;
+            h.graph[k][p] = nullptr;
+        }
     h.graph_ok = false;
 }
 
-// Capture the two iteration parities as graphs (their kernel arguments only
-// name buffers the handle owns, so they stay valid across solves).  Any
-// failure falls back to direct launches.
+// Capture graphs of the iteration (their kernel arguments only name buffers
+// the handle owns, so they stay valid across solves): without timing one
+// graph per parity; with timing, segments 0 and 2 as graphs, so that the
+// level-0 post-smoothing kernel can be launched between two stream events.
 void build_graphs(Hier &h) {
     destroy_graphs(h);
     if (!h.cap_stream) HIPC(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
-    for (int p = 0; p < 2; ++p) {
+    auto capture = [&](int slot, int par, int s0, int s1) {
         HIPC(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_iteration(h, p, h.cap_stream);
+            for (int seg = s0; seg <= s1; ++seg) enqueue_segment(h, par, seg, h.cap_stream);
         } catch (...) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h.cap_stream, &g);
             if (g) (void)hipGraphDestroy(g);
             throw;
         }
-        HIPC(hipStreamEndCapture(h.cap_stream, &h.graph[p]));
-        HIPC(hipGraphInstantiate(&h.gexec[p], h.graph[p], nullptr, nullptr, 0));
+        HIPC(hipStreamEndCapture(h.cap_stream, &h.graph[slot][par]));
+        HIPC(hipGraphInstantiate(&h.gexec[slot][par], h.graph[slot][par], nullptr, nullptr, 0));
+    };
+    for (int p = 0; p < 2; ++p) {
+        if (h.prof) {
+            capture(1, p, 0, 0);
+            capture(2, p, 2, 2);
+        } else {
+            capture(0, p, 0, 2);
+        }
     }
     h.graph_ok = true;
+    h.graph_prof = h.prof;
+}
+
+void launch_iteration(Hier &h, int par, hipStream_t s) {
+    const bool g = h.use_graph && h.graph_ok;
+    if (g && !h.prof) {
+        HIPC(hipGraphLaunch(h.gexec[0][par], s));
+        return;
+    }
+    if (g) HIPC(hipGraphLaunch(h.gexec[1][par], s));
+    else enqueue_segment(h, par, 0, s);
+    if (h.prof) HIPC(hipEventRecord(h.pev[par][0], s));
+    enqueue_segment(h, par, 1, s);
+    if (h.prof) HIPC(hipEventRecord(h.pev[par][1], s));
+    if (g) HIPC(hipGraphLaunch(h.gexec[2][par], s));
+    else enqueue_segment(h, par, 2, s);
 }
 
 // PCG iterations k = k0 .. max_iter-1 (fewer if the stopping test or a
 // breakdown ends them).  The host polls a host-mapped flag one iteration
 // behind the device, so the queue never runs dry.  With timing on, the
-// kernel time of iteration k is appended to `times` as (k, ms).
+// level-0 post-smoothing time of iteration k is appended to `times`.
 void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, hipStream_t s) {
     const int max_iter = h.prm.max_iter;
-    if (h.use_graph && !h.graph_ok) {
+    if (h.use_graph && (!h.graph_ok || h.graph_prof != h.prof)) {
         try {
             build_graphs(h);
         } catch (const Error &) {
@@ -496,16 +531,15 @@ void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, 
     auto collect = [&](int k) {
         if (!h.prof) return;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, h.pev[k & 1][0], h.pev[k & 1][1]) == hipSuccess) times.emplace_back(k, ms);
-        else (void)hipGetLastError();
+        HIPC(hipEventElapsedTime(&ms, h.pev[k & 1][0], h.pev[k & 1][1]));
+        times.emplace_back(k, ms);
     };
     volatile int32_t *flag = h.hflag;
     flag[0] = 0;
     int last = -1;
     for (int k = k0; k < max_iter; ++k) {
         const int par = k & 1;
-        if (h.use_graph && h.graph_ok) HIPC(hipGraphLaunch(h.gexec[par], s));
-        else enqueue_iteration(h, par, s);
+        launch_iteration(h, par, s);
         HIPC(hipEventRecord(ev[par], s));
         last = k;
         if (k > k0) {
@@ -696,7 +730,7 @@ camg_status camg_vcycle_dev(camg_handle hh, const double *d_y, double *d_z, void
         if (!d_y || !d_z) fail(CAMG_E_ARG, "null vector");
         BusyGuard g(h);
         HIPC(hipSetDevice(h->device));
-        vcycle(*h, d_y, d_z, nullptr, false, 0, (hipStream_t)hip_stream);
+        vcycle(*h, d_y, d_z, nullptr, false, true, true, (hipStream_t)hip_stream);
         HIPC(hipStreamSynchronize((hipStream_t)hip_stream));
     });
 }
@@ -787,8 +821,8 @@ camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, c
             M.nc = ncol;
             M.nnz = rp[nr];
             M.rp = tmp.alloc<int32_t>((size_t)nr + 1);
-            M.ci = tmp.alloc<int32_t>(std::max<int64_t>(M.nnz, 1));
-            M.v = tmp.alloc<double>(std::max<int64_t>(M.nnz, 1));
+            M.ci = tmp.alloc<int32_t>(padded(M.nnz));
+            M.v = tmp.alloc<double>(padded(M.nnz));
             HIPC(hipMemcpy(M.rp, rp, sizeof(int32_t) * ((size_t)nr + 1), hipMemcpyHostToDevice));
             if (M.nnz) {
                 HIPC(hipMemcpy(M.ci, ci, sizeof(int32_t) * (size_t)M.nnz, hipMemcpyHostToDevice));
@@ -807,8 +841,8 @@ camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, c
         scan_i32_to_i64(ccnt, rrp64, nc, tmp, s);
         R.rp = tmp.alloc<int32_t>((size_t)nc + 1);
         narrow_i64(rrp64, R.rp, nc, s);
-        R.ci = tmp.alloc<int32_t>(std::max<int64_t>(R.nnz, 1));
-        R.v = tmp.alloc<double>(std::max<int64_t>(R.nnz, 1));
+        R.ci = tmp.alloc<int32_t>(padded(R.nnz));
+        R.v = tmp.alloc<double>(padded(R.nnz));
         transpose_csr(P, R, tmp, s);
         spgemm(A, P, AP, tmp, tmp, s);
         spgemm(R, AP, C, outp, tmp, s);
@@ -853,7 +887,6 @@ camg_status camg_profile(camg_handle hh, int32_t enable, double *total_ms, int64
         if (on && !h->pev[0][0])
             for (auto &pp : h->pev)
                 for (auto &e : pp) HIPC(hipEventCreate(&e));
-        if (on != h->prof) h->graph_ok = false;  // the graphs carry the timing events or not
         h->prof = on;
     });
 }

@@ -35,6 +35,12 @@ struct Pool {
     ~Pool() { release(); }
 };
 
+// Column-index and value arrays carry this many elements of padding past
+// nnz, so aligned 16-byte vector loads that straddle the end stay inside
+// the allocation.
+constexpr int64_t kPad = 8;
+inline size_t padded(int64_t nnz) { return (size_t)(nnz + kPad); }
+
 struct Csr {
     int32_t nr = 0, nc = 0;
     int64_t nnz = 0;
@@ -118,11 +124,14 @@ struct Hier {
     hipEvent_t pev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][start/end]
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
-    // one PCG iteration captured as a graph, per parity of the iteration
+    // PCG iterations captured as graphs, per parity of the iteration:
+    // slot 0 the whole iteration, slots 1 and 2 the parts before and after
+    // the level-0 post-smoothing (used while kernel timing is on)
     bool use_graph = true;
     bool graph_ok = false;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    bool graph_prof = false;
+    hipGraphExec_t gexec[3][2] = {};
+    hipGraph_t graph[3][2] = {};
     hipStream_t cap_stream = nullptr;
     // multi-RHS work (allocated on first use for a given k)
     int mk = 0;

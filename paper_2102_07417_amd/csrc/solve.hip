@@ -26,7 +26,7 @@ namespace camg {
 
 namespace {
 
-constexpr int kTileW = 4096;      // largest nominal nonzeros per tile
+constexpr int kTileW = 2048;      // largest nominal nonzeros per tile
 constexpr int kTileMaxRow = 4096; // longest row a tile can hold (LDS <= 8192 entries)
 
 template <class T>
@@ -39,6 +39,7 @@ struct MatArg {
     int rpt;     // vector mode: rows per block
     int ntiles;  // tile mode
     int tpb;     // tiles per block
+    int junk;    // tile mode: spare LDS slot after the tile
 };
 
 template <class T>
@@ -50,7 +51,7 @@ const float *vals<float>(const Csr &A) { return A.v32; }
 
 template <class T>
 MatArg<T> mat_arg(const Csr &A, const RowCfg &c, const T *v = nullptr) {
-    return MatArg<T>{A.rp, A.ci, v ? v : vals<T>(A), c.tstart, A.nr, c.rpt, c.ntiles, c.tpb};
+    return MatArg<T>{A.rp, A.ci, v ? v : vals<T>(A), c.tstart, A.nr, c.rpt, c.ntiles, c.tpb, c.tile_nnz};
 }
 
 // Sum of partials[0..n) in index order, result in every thread of the block.
@@ -62,6 +63,101 @@ __device__ __forceinline__ double sum_all(const double *partials, int n) {
     const double r = tot;
     __syncthreads();
     return r;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Four consecutive values starting at a 16-byte aligned index.
+__device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
+    const v2d a = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
+    const v2d b = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p + 2));
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
+    const v4f a = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+}
+
+// Phase 1 of a tile: prod[e - e0] = a_e * g(col_e) for e in [e0, e0 + m).
+// Column indices and values are streamed as aligned 16-byte vectors from
+// e0 rounded down to a multiple of 4 (the arrays carry 8 elements of
+// padding, so the last vector stays inside the allocation).  Entries outside
+// the tile gather column 0 instead and store into the spare LDS slot
+// prod[junk] (no branch anywhere, so all the loads stay in flight).
+template <class T, class G>
+__device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m) {
+    const int junk = M.junk;
+    const int a0 = e0 & ~3;
+    const int span = e0 + m - a0;
+    constexpr int STEP = 4 * kBlock;
+    int k = 4 * threadIdx.x;
+    for (; k + STEP < span; k += 2 * STEP) {
+        const v4i c0 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k));
+        const v4i c1 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k + STEP));
+        T v0[4], v1[4];
+        load4(M.v + a0 + k, v0);
+        load4(M.v + a0 + k + STEP, v1);
+        const int cc[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+        const int qb = a0 + k - e0;
+        T gv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = qb + (u & 3) + (u >> 2) * STEP;
+            const bool in = q >= 0 && q < m;
+            gv[u] = g(in ? cc[u] : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = qb + (u & 3) + (u >> 2) * STEP;
+            const T a = u < 4 ? v0[u & 3] : v1[u & 3];
+            prod[(q >= 0 && q < m) ? q : junk] = a * gv[u];
+        }
+    }
+    for (; k < span; k += STEP) {
+        const v4i c0 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k));
+        T v0[4];
+        load4(M.v + a0 + k, v0);
+        const int cc[4] = {c0.x, c0.y, c0.z, c0.w};
+        const int qb = a0 + k - e0;
+        T gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = qb + u >= 0 && qb + u < m;
+            gv[u] = g(in ? cc[u] : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) prod[(qb + u >= 0 && qb + u < m) ? qb + u : junk] = v0[u] * gv[u];
+    }
+}
+
+// Scalar variant of phase 1 for gathers that read two vectors per nonzero
+// (fewer registers than the vector variant, so more waves stay resident).
+template <class T, class G>
+__device__ __forceinline__ void stream_tile_scalar(const MatArg<T> &M, const G &g, T *prod, int e0, int m) {
+    int k = threadIdx.x;
+    for (; k + 7 * kBlock < m; k += 8 * kBlock) {
+        int j[8];
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) j[u] = M.ci[e0 + k + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = M.v[e0 + k + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
+    }
+    for (; k + 3 * kBlock < m; k += 4 * kBlock) {
+        int j[4];
+        T a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = M.ci[e0 + k + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = M.v[e0 + k + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
+    }
+    for (; k < m; k += kBlock) prod[k] = M.v[e0 + k] * g(M.ci[e0 + k]);
 }
 
 // Walk this block's rows; for each row i call
@@ -91,28 +187,8 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
                 qz = M.rp[i + 1] - e0;
                 if (sl == 0) pre = epi.load(i);
             }
-            int k = threadIdx.x;
-            for (; k + 7 * kBlock < m; k += 8 * kBlock) {
-                int j[8];
-                T a[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) j[u] = M.ci[e0 + k + u * kBlock];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] = M.v[e0 + k + u * kBlock];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
-            }
-            for (; k + 3 * kBlock < m; k += 4 * kBlock) {
-                int j[4];
-                T a[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) j[u] = M.ci[e0 + k + u * kBlock];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) a[u] = M.v[e0 + k + u * kBlock];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) prod[k + u * kBlock] = a[u] * g(j[u]);
-            }
-            for (; k < m; k += kBlock) prod[k] = M.v[e0 + k] * g(M.ci[e0 + k]);
+            if constexpr (G::kLoads > 1) stream_tile_scalar(M, g, prod, e0, m);
+            else stream_tile(M, g, prod, e0, m);
             __syncthreads();
             {
                 T acc = 0;
@@ -152,20 +228,25 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
 // ------------------------------------------------------------------ gathers and epilogues
 template <class T, class TY>
 struct GPre {  // s_j of the first Jacobi step from s = 0
+    static constexpr int kLoads = 2;
     const T *wd;
     const TY *y;
     __device__ T operator()(int j) const { return wd[j] * (T)y[j]; }
 };
 template <class T, class TX = T>
 struct GVec {
+    static constexpr int kLoads = 1;
     const TX *x;
     __device__ T operator()(int j) const { return (T)x[j]; }
 };
-struct GDir {  // the new search direction, formed on the fly
+// The new search direction p = z + beta p_old, formed on the fly.  On the
+// first iteration (and after a restart) beta = 0 and p_old is finite, so
+// z + 0 * p_old is exactly z: no branch is needed.
+struct GDir {
+    static constexpr int kLoads = 2;
     const double *z, *p;
     double beta;
-    bool first;
-    __device__ double operator()(int j) const { return first ? z[j] : z[j] + beta * p[j]; }
+    __device__ double operator()(int j) const { return z[j] + beta * p[j]; }
 };
 
 template <class T, class TY>
@@ -222,12 +303,11 @@ struct ESpmv {
 struct EDir {  // p_new, q = A p_new, dot += p.q
     const double *z, *pold;
     double beta;
-    bool first;
     double *pnew, *q;
     struct Pre {
         double pi;
     };
-    __device__ Pre load(int i) const { return Pre{first ? z[i] : z[i] + beta * pold[i]}; }
+    __device__ Pre load(int i) const { return Pre{z[i] + beta * pold[i]}; }
     __device__ void finish(int i, double acc, const Pre &p, double &dot) const {
         pnew[i] = p.pi;
         q[i] = acc;
@@ -364,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(MatArg<double> M, const doub
         st->beta = beta;
     }
     double dot = 0.0;
-    run_rows<double, LPR, TILE>(M, GDir{z, pold, beta, first}, EDir{z, pold, beta, first, pnew, q}, smem_d, dot);
+    run_rows<double, LPR, TILE>(M, GDir{z, pold, beta}, EDir{z, pold, beta, pnew, q}, smem_d, dot);
     const double b = block_sum<kBlock>(dot);
     if (threadIdx.x == 0) {
         ppq[blockIdx.x] = b;
@@ -440,7 +520,7 @@ template <class T, bool DOT, class G, class E>
 void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *partials, int32_t *nout,
                  const PcgState *st, hipStream_t s, const T *values = nullptr) {
     const MatArg<T> M = mat_arg<T>(A, c, values);
-    const size_t smem = c.tile ? (size_t)c.tile_nnz * sizeof(T) : 0;
+    const size_t smem = c.tile ? (size_t)(c.tile_nnz + 1) * sizeof(T) : 0;
     if (c.tile) {
         CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
     } else {
@@ -588,7 +668,7 @@ void pcg_check(const double *pr2, PcgState *st, double *hist, int hist_cap, int3
 int pcg_dir(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
             const double *prz, double *ppq, PcgState *st, hipStream_t s) {
     const MatArg<double> M = mat_arg<double>(A, c);
-    const size_t smem = c.tile ? (size_t)c.tile_nnz * sizeof(double) : 0;
+    const size_t smem = c.tile ? (size_t)(c.tile_nnz + 1) * sizeof(double) : 0;
     if (c.tile) {
         CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, true><<<c.grid, kBlock, smem, s>>>(M, z, pold, pnew, q, prz, ppq, st)));
     } else {

@@ -357,8 +357,8 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     if (nnz > INT32_MAX) fail(CAMG_E_NOMEM, "sparse product has more than 2^31-1 nonzeros");
     narrow_i64(rp64, Z.rp, nr, s);
     Z.nnz = nnz;
-    Z.ci = out.alloc<int32_t>(std::max<int64_t>(nnz, 1));
-    Z.v = out.alloc<double>(std::max<int64_t>(nnz, 1));
+    Z.ci = out.alloc<int32_t>(padded(nnz));
+    Z.v = out.alloc<double>(padded(nnz));
 
     // 4. fill bins by exact row length
     const int64_t fill_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
