@@ -65,6 +65,30 @@ def post0_bytes(n, nnz, fp32=False):
     return 4 * (n + 1) + 12 * nnz + 32 * n
 
 
+def committed_traffic():
+    """HBM bytes per launch of the level-0 post-smoothing kernel from the
+    committed rocprofv3 counter summary, or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "post0_lognormal3d_128_pmc.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "-", "|")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for s in fields["sources"].split(", "):
+            h.update(open(os.path.join(ROOT, s), "rb").read())
+        if h.hexdigest() != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +177,7 @@ def main():
     k_ms = tot_ms / max(launches, 1)
     k_bytes = post0_bytes(A.n, A.nnz)
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9 if launches else 0.0
+    traffic = committed_traffic() if args.workload == "lognormal3d_128" else None
     vb = vcycle_bytes(info)
     per_iter_ms = solve_ms / max(iters, 1)
 
@@ -177,7 +202,7 @@ def main():
                  "vcycle_alg_bytes": vb},
         "roofline": {"bound": "hbm", "kernel": "level-0 post-smoothing (k_rows<EPost, DOT>)",
                      "achieved": round(k_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": k_bytes, "avg_launch_us": round(k_ms * 1e3, 3),
                      "launches": launches, "copy_kernel_gbs": round(copy_gbs, 1)},
     }
