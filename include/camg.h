@@ -127,15 +127,49 @@ camg_status camg_solve_dev(camg_handle h, const double *d_b, double rtol, double
 /*
  * k right-hand sides at once: d_B and d_X are n-by-k row-major device
  * blocks.  The columns run k independent PCG recurrences that share every
- * matrix pass (sparse matrix times row-major block); a column stops updating
- * once it has converged, so each column's result equals that of a
- * single-column call with the same precision setting.  iters[k],
- * true_relres[k] (host, may be NULL); hist (host, may be NULL) is k-by-hist_cap
- * row-major.  Returns the worst status over the columns.
+ * matrix pass (sparse matrix times row-major block, K = the next power of
+ * two >= k columns, at most 64 per pass); a column stops updating once it
+ * has converged.  Each column's result does not depend on the other columns
+ * (bitwise, for a given K) and agrees with a single-vector solve to
+ * rounding.  iters[k], true_relres[k] (host, may be NULL); hist (host, may
+ * be NULL) is k-by-hist_cap row-major.  Returns the worst status over the
+ * columns (breakdown before max_iter before ok).
  */
 camg_status camg_solve_multi_dev(camg_handle h, int32_t k, const double *d_B, double rtol, double *d_X,
                                  int32_t *iters, double *hist, int32_t hist_cap, double *true_relres,
                                  void *hip_stream);
+
+/*
+ * Slot engine (continuous batching).  An engine holds `slots` columns (a
+ * power of two, at most 64) of row-major n-by-slots work blocks on the
+ * handle's hierarchy and runs one PCG recurrence per busy column, all
+ * columns sharing every matrix pass.  Columns can be started while others
+ * run; a finished column stops updating.  A column's iterates do not depend
+ * on the other columns or on its slot (bitwise), for a given slot count.
+ * The handle must outlive its engines; one engine is driven by one host
+ * thread; engines of one handle may run concurrently on different streams.
+ *   camg_engine_footprint: device bytes an engine of `slots` columns needs.
+ *   camg_engine_create: allocate it (hist_cap entries of residual history per column).
+ *   camg_engine_start: start columns [slot0, slot0+m) from the device block
+ *     d_B (n-by-m row-major, row stride ldb), x0 = 0, rtol, max_iter.
+ *   camg_engine_step: run up to max_steps iterations (fewer once no column is
+ *     running); *running receives the number of columns still running.
+ *   camg_engine_state: host arrays of `slots` entries: iterations done, done
+ *     flag (1 done, 0 running, -1 free), status (camg_status of the column).
+ *   camg_engine_finish: copy columns [slot0, slot0+m) of x into d_X (n-by-m
+ *     row-major, row stride ldx), true relative residuals into true_relres
+ *     (host, may be NULL), and free the slots.
+ */
+typedef struct camg_engine *camg_engine_t;
+camg_status camg_engine_footprint(camg_handle h, int32_t slots, int64_t *bytes);
+camg_status camg_engine_create(camg_handle h, int32_t slots, int32_t hist_cap, void *hip_stream, camg_engine_t *out);
+camg_status camg_engine_start(camg_engine_t e, int32_t slot0, int32_t m, const double *d_B, int32_t ldb, double rtol,
+                              int32_t max_iter);
+camg_status camg_engine_step(camg_engine_t e, int32_t max_steps, int32_t *running);
+camg_status camg_engine_state(camg_engine_t e, int32_t *iters, int32_t *done, int32_t *status);
+camg_status camg_engine_finish(camg_engine_t e, int32_t slot0, int32_t m, double *d_X, int32_t ldx,
+                               double *true_relres);
+camg_status camg_engine_destroy(camg_engine_t e);
 
 /* z = M y: one V-cycle (device vectors of length n). */
 camg_status camg_vcycle_dev(camg_handle h, const double *d_y, double *d_z, void *hip_stream);

@@ -26,7 +26,8 @@ EXPORTED = [
     "camg_abi_version", "camg_status_str", "camg_last_error", "camg_params_default", "camg_setup",
     "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
     "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
-    "camg_set_option",
+    "camg_set_option", "camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
+    "camg_engine_state", "camg_engine_finish", "camg_engine_destroy",
 ]
 OPT_GRAPH = 1
 
@@ -77,6 +78,16 @@ def load(path: str | None = None):
     L.camg_destroy.argtypes = [vp]
     L.camg_profile.argtypes = [vp, i32, vp, vp]
     L.camg_set_option.argtypes = [vp, i32, i64]
+    L.camg_engine_footprint.argtypes = [vp, i32, vp]
+    L.camg_engine_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
+    L.camg_engine_start.argtypes = [vp, i32, i32, vp, i32, dbl, i32]
+    L.camg_engine_step.argtypes = [vp, i32, vp]
+    L.camg_engine_state.argtypes = [vp, vp, vp, vp]
+    L.camg_engine_finish.argtypes = [vp, i32, i32, vp, i32, vp]
+    L.camg_engine_destroy.argtypes = [vp]
+    for name in ("camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
+                 "camg_engine_state", "camg_engine_finish", "camg_engine_destroy"):
+        getattr(L, name).restype = C.c_int
     for name in ("camg_profile", "camg_set_option", "camg_setup", "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev",
                  "camg_vcycle_dev", "camg_info", "camg_level_sizes", "camg_export_level", "camg_galerkin",
                  "camg_destroy"):
@@ -218,6 +229,61 @@ def camg_set_option(h, option, value):
     return load().camg_set_option(h, int(option), int(value))
 
 
+def camg_engine_footprint(h, slots):
+    out = np.zeros(1, np.int64)
+    _check(load().camg_engine_footprint(h, int(slots), _p(out)))
+    return int(out[0])
+
+
+class Engine:
+    """Slot engine of a Solver: columns start, run and finish independently
+    (continuous batching).  Device blocks are torch CUDA tensors."""
+
+    def __init__(self, solver, slots, hist_cap=1, stream=None):
+        self.solver = solver
+        self.slots = slots
+        e = C.c_void_p()
+        _check(load().camg_engine_create(solver.h, int(slots), int(hist_cap), _stream_ptr(stream), C.byref(e)))
+        self.e = e
+
+    def start(self, slot0, d_B, rtol=1e-8, max_iter=1000):
+        """d_B: n-by-m row-major (or length-n) float64 CUDA tensor."""
+        m = 1 if d_B.dim() == 1 else d_B.shape[1]
+        ldb = d_B.stride(0) if d_B.dim() > 1 else 1
+        _check(load().camg_engine_start(self.e, int(slot0), int(m), C.c_void_p(d_B.data_ptr()), int(ldb),
+                                        float(rtol), int(max_iter)))
+
+    def step(self, max_steps=1):
+        r = np.zeros(1, np.int32)
+        _check(load().camg_engine_step(self.e, int(max_steps), _p(r)))
+        return int(r[0])
+
+    def state(self):
+        it = np.zeros(self.slots, np.int32)
+        dn = np.zeros(self.slots, np.int32)
+        st = np.zeros(self.slots, np.int32)
+        _check(load().camg_engine_state(self.e, _p(it), _p(dn), _p(st)))
+        return it, dn, st
+
+    def finish(self, slot0, d_X):
+        m = 1 if d_X.dim() == 1 else d_X.shape[1]
+        ldx = d_X.stride(0) if d_X.dim() > 1 else 1
+        rel = np.zeros(m)
+        _check(load().camg_engine_finish(self.e, int(slot0), int(m), C.c_void_p(d_X.data_ptr()), int(ldx), _p(rel)))
+        return rel
+
+    def close(self):
+        if self.e:
+            load().camg_engine_destroy(self.e)
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def camg_destroy(h):
     return load().camg_destroy(h)
 
@@ -332,6 +398,18 @@ class Solver:
 
     def vcycle_dev(self, d_y, d_z, stream=None):
         _check(camg_vcycle_dev(self.h, d_y, d_z, stream))
+
+    def solve_multi_dev(self, d_B, d_X, rtol=1e-8, hist_cap=0, stream=None):
+        """d_B, d_X: n-by-k row-major float64 CUDA tensors."""
+        k = d_B.shape[1]
+        st, it, hist, rel = camg_solve_multi_dev(self.h, k, d_B, rtol, d_X, hist_cap=hist_cap, stream=stream)
+        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        return MultiResult(st, it, hist, rel)
+
+
+class MultiResult:
+    def __init__(self, status, iters, hist, true_relres):
+        self.status, self.iters, self.hist, self.true_relres = status, iters, hist, true_relres
 
 
 class SolveResult:

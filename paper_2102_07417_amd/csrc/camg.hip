@@ -870,6 +870,8 @@ camg_status camg_destroy(camg_handle hh) {
                 if (e) (void)hipEventDestroy(e);
         destroy_graphs(*h);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        for (Engine *e : h->engines) engine_destroy(e);
+        h->engines.clear();
         delete static_cast<camg_hier *>(hh);
     });
 }
@@ -905,10 +907,153 @@ camg_status camg_set_option(camg_handle hh, int32_t option, int64_t value) {
     });
 }
 
-camg_status camg_solve_multi_dev(camg_handle, int32_t, const double *, double, double *, int32_t *, double *, int32_t,
-                                 double *, void *) {
-    camg::g_last_error = "multi-RHS solve not available in this build";
-    return CAMG_E_ARG;
+static int pow2_at_least(int k) {
+    int K = 1;
+    while (K < k) K <<= 1;
+    return K;
+}
+
+static Engine *engine_for(Hier *h, int K, hipStream_t s) {
+    for (Engine *e : h->engines)
+        if (engine_slots(*e) == K) return e;
+    Engine *e = engine_create(*h, K, h->prm.max_iter + 2, s);
+    h->engines.push_back(e);
+    return e;
+}
+
+camg_status camg_solve_multi_dev(camg_handle hh, int32_t k, const double *d_B, double rtol, double *d_X,
+                                 int32_t *iters, double *hist, int32_t hist_cap, double *true_relres,
+                                 void *hip_stream) {
+    camg_status worst = CAMG_OK;
+    camg_status st = guarded([&] {
+        Hier *h = as_hier(hh);
+        if (k < 1 || !d_B || !d_X) fail(CAMG_E_ARG, "k < 1 or null block");
+        if (!std::isfinite(rtol)) fail(CAMG_E_ARG, "rtol must be finite");
+        BusyGuard g(h);
+        HIPC(hipSetDevice(h->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        const int K = pow2_at_least(std::min<int>(k, kMaxSlots));
+        Engine *E = engine_for(h, K, s);
+        std::vector<int32_t> it(K), dn(K), stt(K);
+        std::vector<double> rel(K);
+        for (int c0 = 0; c0 < k; c0 += K) {
+            const int m = std::min(K, k - c0);
+            engine_start(*E, 0, m, d_B + c0, k, rtol, h->prm.max_iter, s);
+            engine_step(*E, h->prm.max_iter + 1, s);
+            engine_slot_state(*E, it.data(), dn.data(), stt.data(), s);
+            if (h->prm.precision == CAMG_MIXED_FP32 && rtol > 0.0) {
+                for (int rep = 0; rep < 2; ++rep) {
+                    engine_true_res(*E, rel.data(), s);
+                    unsigned long long mask = 0;
+                    for (int c = 0; c < m; ++c)
+                        if (stt[c] == 0 && rel[c] >= rtol && it[c] < h->prm.max_iter) mask |= 1ull << c;
+                    if (!mask) break;
+                    engine_replace(*E, mask, s);
+                    engine_step(*E, h->prm.max_iter + 1, s);
+                    engine_slot_state(*E, it.data(), dn.data(), stt.data(), s);
+                }
+            }
+            engine_true_res(*E, rel.data(), s);
+            engine_copy_x(*E, 0, m, d_X + c0, k, s);
+            for (int c = 0; c < m; ++c) {
+                if (iters) iters[c0 + c] = it[c];
+                if (true_relres) true_relres[c0 + c] = rel[c];
+                if (hist && hist_cap > 0) engine_hist(*E, c, hist + (size_t)(c0 + c) * hist_cap, hist_cap, it[c] + 1, s);
+                const camg_status cs = (camg_status)stt[c];
+                if (cs == CAMG_E_BREAKDOWN) worst = CAMG_E_BREAKDOWN;
+                else if (cs == CAMG_E_MAXIT && worst == CAMG_OK) worst = CAMG_E_MAXIT;
+            }
+            engine_release(*E, 0, m, s);
+        }
+        HIPC(hipStreamSynchronize(s));
+    });
+    if (st != CAMG_OK) return st;
+    if (worst == CAMG_E_BREAKDOWN) camg::g_last_error = "CG breakdown in at least one column";
+    if (worst == CAMG_E_MAXIT) camg::g_last_error = "max_iter reached in at least one column";
+    return worst;
+}
+
+// ---------------------------------------------------------------- engine (serving) API
+struct camg_engine {
+    Engine *e = nullptr;
+    Hier *h = nullptr;
+    hipStream_t s = nullptr;
+};
+
+camg_status camg_engine_footprint(camg_handle hh, int32_t slots, int64_t *bytes) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!bytes || slots < 1 || slots > kMaxSlots) fail(CAMG_E_ARG, "bad argument");
+        *bytes = engine_footprint(*h, pow2_at_least(slots));
+    });
+}
+
+camg_status camg_engine_create(camg_handle hh, int32_t slots, int32_t hist_cap, void *hip_stream, camg_engine_t *out) {
+    return guarded([&] {
+        Hier *h = as_hier(hh);
+        if (!out) fail(CAMG_E_ARG, "null output");
+        *out = nullptr;
+        if (slots < 1 || slots > kMaxSlots || (slots & (slots - 1)))
+            fail(CAMG_E_ARG, "slots must be a power of two in [1, 64]");
+        HIPC(hipSetDevice(h->device));
+        std::unique_ptr<camg_engine> ce(new camg_engine());
+        ce->h = h;
+        ce->s = (hipStream_t)hip_stream;
+        ce->e = engine_create(*h, slots, std::max(hist_cap, 1), ce->s);
+        *out = ce.release();
+    });
+}
+
+camg_status camg_engine_start(camg_engine_t ce, int32_t slot0, int32_t m, const double *d_B, int32_t ldb, double rtol,
+                              int32_t max_iter) {
+    return guarded([&] {
+        if (!ce || !d_B || ldb < m) fail(CAMG_E_ARG, "bad argument");
+        HIPC(hipSetDevice(ce->h->device));
+        engine_start(*ce->e, slot0, m, d_B, ldb, rtol, max_iter, ce->s);
+    });
+}
+
+camg_status camg_engine_step(camg_engine_t ce, int32_t max_steps, int32_t *running) {
+    return guarded([&] {
+        if (!ce || max_steps < 1) fail(CAMG_E_ARG, "bad argument");
+        HIPC(hipSetDevice(ce->h->device));
+        const int r = engine_step(*ce->e, max_steps, ce->s);
+        if (running) *running = r;
+    });
+}
+
+camg_status camg_engine_state(camg_engine_t ce, int32_t *iters, int32_t *done, int32_t *status) {
+    return guarded([&] {
+        if (!ce) fail(CAMG_E_ARG, "null engine");
+        HIPC(hipSetDevice(ce->h->device));
+        engine_slot_state(*ce->e, iters, done, status, ce->s);
+    });
+}
+
+camg_status camg_engine_finish(camg_engine_t ce, int32_t slot0, int32_t m, double *d_X, int32_t ldx,
+                               double *true_relres) {
+    return guarded([&] {
+        if (!ce || !d_X || ldx < m || slot0 < 0 || m < 1 || slot0 + m > engine_slots(*ce->e))
+            fail(CAMG_E_ARG, "bad argument");
+        HIPC(hipSetDevice(ce->h->device));
+        if (true_relres) {
+            double rel[kMaxSlots];
+            engine_true_res(*ce->e, rel, ce->s);
+            for (int c = 0; c < m; ++c) true_relres[c] = rel[slot0 + c];
+        }
+        engine_copy_x(*ce->e, slot0, m, d_X, ldx, ce->s);
+        engine_release(*ce->e, slot0, m, ce->s);
+    });
+}
+
+camg_status camg_engine_destroy(camg_engine_t ce) {
+    if (!ce) return CAMG_OK;
+    return guarded([&] {
+        (void)hipSetDevice(ce->h->device);
+        (void)hipStreamSynchronize(ce->s);
+        engine_destroy(ce->e);
+        delete ce;
+    });
 }
 
 }  // extern "C"

@@ -133,16 +133,12 @@ struct Hier {
     hipGraphExec_t gexec[3][2] = {};
     hipGraph_t graph[3][2] = {};
     hipStream_t cap_stream = nullptr;
-    // multi-RHS work (allocated on first use for a given k)
-    int mk = 0;
-    double *mr = nullptr, *mz = nullptr, *mp[2] = {nullptr, nullptr}, *mq = nullptr;
-    PcgState *mst = nullptr;
-    double *mpartials = nullptr;
-    double *mhist = nullptr;
-    std::vector<void *> mallocs;
+    // engines used by camg_solve_multi_dev, by slot count (owned)
+    std::vector<struct Engine *> engines;
 };
 
 constexpr int kBlock = 256;          // threads per block for row kernels
+constexpr int kMaxSlots = 64;        // columns of a multi-RHS engine
 constexpr int kMaxGrid = 2048;       // cap on blocks of the reduction kernels
 
 // ---------------------------------------------------------------- scan (setup.hip)
@@ -234,5 +230,22 @@ void pcg_restart(PcgState *st, hipStream_t s);
 int residual_norm(const Csr &A, const RowCfg &c, const double *b, const double *x, double *out, double *partials,
                   int32_t *nout, hipStream_t s);
 void sum_to(const double *partials, int n, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- multi-RHS engine (multi.hip)
+struct Engine;
+int64_t engine_footprint(const Hier &h, int K);
+Engine *engine_create(Hier &h, int K, int cap, hipStream_t s);
+void engine_destroy(Engine *e);
+int engine_slots(const Engine &E);
+// start columns [c0, c0+m) from the n-by-m row-major device block B (row stride ldb)
+void engine_start(Engine &E, int c0, int m, const double *B, int ldb, double rtol, int max_iter, hipStream_t s);
+// up to `iters` iterations; returns the number of columns still running
+int engine_step(Engine &E, int iters, hipStream_t s);
+void engine_slot_state(Engine &E, int32_t *iters, int32_t *done, int32_t *status, hipStream_t s);
+void engine_true_res(Engine &E, double *rel, hipStream_t s);
+void engine_copy_x(Engine &E, int c0, int m, double *X, int ldx, hipStream_t s);
+void engine_release(Engine &E, int c0, int m, hipStream_t s);
+void engine_replace(Engine &E, unsigned long long mask, hipStream_t s);
+void engine_hist(Engine &E, int c, double *host, int cap_out, int count, hipStream_t s);
 
 }  // namespace camg

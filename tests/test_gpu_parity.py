@@ -274,3 +274,95 @@ def test_kernel_timing_hook(camg):
     ms, launches = camg.camg_profile(s.h, 0)
     assert launches == r.iters and ms > 0
     s.close()
+
+
+# ----------------------------------------------------------------- multi-RHS
+@pytest.mark.parametrize("name,k", [("lognormal3d_24", 5), ("poisson2d_64", 32), ("elasticity_6", 3)])
+def test_multi_rhs_matches_oracle(camg, name, k):
+    print(f"[gpu] multi {name} k={k}", flush=True)
+    A = CASES[name]()
+    B = PB.rhs_block(A.n, k)
+    o = O.Hierarchy(A, max_iter=3000)
+    s = camg.Solver(A, max_iter=3000)
+    dB = torch.from_numpy(B).to("cuda:0")
+    dX = torch.zeros_like(dB)
+    r = s.solve_multi_dev(dB, dX, rtol=1e-8)
+    X = dX.cpu().numpy()
+    assert r.status == camg.OK
+    for c in range(k):
+        ro = o.solve(B[:, c], 1e-8, max_iter=3000)
+        assert abs(int(r.iters[c]) - ro.iters) <= 1, (c, r.iters[c], ro.iters)
+        assert np.linalg.norm(X[:, c] - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+        assert r.true_relres[c] < 1e-8 * 1.01
+    # agrees with the single-vector path to rounding
+    rs = s.solve(B[:, 0])
+    assert np.linalg.norm(X[:, 0] - rs.x) / np.linalg.norm(rs.x) <= 1e-9
+    s.close()
+
+
+def test_multi_rhs_edge_cases(camg):
+    """More columns than slots (chunks of 64), a zero column, one level."""
+    for A, k in [(PB.poisson2d(16), 70), (PB.poisson2d(3), 5)]:
+        print(f"[gpu] multi edge n={A.n} k={k}", flush=True)
+        B = PB.rhs_block(A.n, k)
+        B[:, 2] = 0.0
+        s = camg.Solver(A)
+        o = O.Hierarchy(A)
+        dB = torch.from_numpy(B).to("cuda:0")
+        dX = torch.full_like(dB, 7.0)
+        r = s.solve_multi_dev(dB, dX, rtol=1e-8)
+        X = dX.cpu().numpy()
+        assert r.status == camg.OK
+        assert r.iters[2] == 0 and np.all(X[:, 2] == 0.0)
+        for c in (0, 1, k - 1):
+            ro = o.solve(B[:, c], 1e-8)
+            assert abs(int(r.iters[c]) - ro.iters) <= 1
+            assert np.linalg.norm(X[:, c] - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+        s.close()
+
+
+def test_multi_rhs_mixed_precision(camg):
+    A = PB.lognormal3d(24, 2.0)
+    B = PB.rhs_block(A.n, 8)
+    s = camg.Solver(A, precision=camg.MIXED_FP32)
+    dB = torch.from_numpy(B).to("cuda:0")
+    dX = torch.zeros_like(dB)
+    r = s.solve_multi_dev(dB, dX, rtol=1e-8)
+    assert r.status == camg.OK and np.all(r.true_relres < 1e-8)
+    o = O.Hierarchy(A)
+    X = dX.cpu().numpy()
+    for c in (0, 7):
+        ro = o.solve(B[:, c], 1e-8)
+        assert np.linalg.norm(X[:, c] - ro.x) / np.linalg.norm(ro.x) < 1e-6
+    s.close()
+
+
+def test_engine_column_alone_equals_in_mix(camg):
+    """Continuous batching: a column's result is bitwise the same alone and
+    among other columns started before and after it, in another slot."""
+    A = PB.lognormal3d(20, 2.0)
+    s = camg.Solver(A)
+    b = torch.from_numpy(PB.rhs(A.n, 99)).to("cuda:0")
+    others = torch.from_numpy(PB.rhs_block(A.n, 7, 5)).to("cuda:0")
+    e = camg.Engine(s, 8, hist_cap=200)
+    e.start(3, b)
+    while e.step(4):
+        pass
+    xa = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    it_a = e.state()[0][3]
+    e.finish(3, xa)
+    # now: four columns first, b joins later in slot 6, more join after
+    e.start(0, others[:, :4])
+    e.step(3)
+    e.start(6, b)
+    e.step(2)
+    e.start(4, others[:, 4:6])
+    while e.step(5):
+        pass
+    it, dn, st = e.state()
+    assert dn[6] == 1 and st[6] == 0 and it[6] == it_a
+    xb = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    e.finish(6, xb)
+    assert torch.equal(xa, xb)
+    e.close()
+    s.close()
