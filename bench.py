@@ -97,6 +97,13 @@ def main():
     ap.add_argument("--workload", default="lognormal3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--batched", type=int, default=32,
+                    help="right-hand sides of the batched (block) run on aniso3d_160; 0 skips it")
+    ap.add_argument("--only-batched", action="store_true", help="print only the batched run")
+    ap.add_argument("--serve", action="store_true",
+                    help="print only the serving sweep (8 resident systems, Poisson arrivals)")
+    ap.add_argument("--rates", default="5,10,20,50,100,200", help="request rates (1/s) of the serving sweep")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -111,6 +118,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     camg.load()
     dev = torch.device("cuda:0")
+    if args.only_batched:
+        print(json.dumps({"batched": batched_run(args.batched or 32, args.steps)}), flush=True)
+        return
+    if args.serve:
+        print(json.dumps({"serving": serve_run([float(r) for r in args.rates.split(",")], args.serve_seconds)}),
+              flush=True)
+        return
     A = problems.workload(args.workload)
     b = problems.rhs(A.n)
     rp = torch.from_numpy(A.row_ptr).to(dev)
@@ -212,9 +226,174 @@ def main():
         out["mixed"] = {"solve_ms": round(m_ms, 4), "setup_ms": round(statistics.median(r["setup_ms"] for r in mixed), 4),
                         "iters": mixed[-1]["iters"], "true_relres": mixed[-1]["true_relres"],
                         "speedup_vs_fp64": round(solve_ms / m_ms, 4), "rel_err_vs_fp64_gpu": err}
+    if args.batched:
+        out["batched"] = batched_run(args.batched, max(1, min(args.steps, 3)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, x64, iters)
     print(json.dumps(out), flush=True)
+
+
+def batched_run(k, steps):
+    """Block of k right-hand sides on the 160^3 anisotropic problem: one
+    FP32-V-cycle / FP64-PCG block solve (all columns to rtol 1e-8) against k
+    sequential FP64 single-vector solves on the same GPU code.  Hierarchies
+    are set up before the timed regions (both reuse one hierarchy for all
+    columns); the block engine is warm (created by an untimed first call)."""
+    import numpy as np
+    import torch
+
+    from paper_2102_07417_amd import camg, problems
+
+    dev = torch.device("cuda:0")
+    A = problems.workload("aniso3d_160")
+    B = problems.rhs_block(A.n, k)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    va = torch.from_numpy(A.val).to(dev)
+    dB = torch.from_numpy(B).to(dev)
+    stream = torch.cuda.current_stream()
+
+    s64 = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, max_iter=5000)
+    cols = [dB[:, j].contiguous() for j in range(k)]
+    X64 = torch.zeros((A.n, k), dtype=torch.float64, device=dev)
+    xs = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    s64.solve_dev(cols[0], xs, rtol=1e-8, stream=stream)  # warm (graphs)
+    seq = []
+    seq_iters = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(k):
+            r = s64.solve_dev(cols[j], xs, rtol=1e-8, stream=stream)
+            X64[:, j].copy_(xs)
+            seq_iters.append(r.iters)
+        torch.cuda.synchronize()
+        seq.append((time.perf_counter() - t0) * 1e3)
+
+    def block(solver):
+        dX = torch.zeros_like(dB)
+        solver.solve_multi_dev(dB, dX, rtol=1e-8, stream=stream)  # warm: engine + graphs
+        ts = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = solver.solve_multi_dev(dB, dX, rtol=1e-8, stream=stream)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        err = ((dX - X64).norm(dim=0) / X64.norm(dim=0)).max().item()
+        return statistics.median(ts), r, err
+
+    b64_ms, r64, e64 = block(s64)
+    s64.close()
+    smx = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, max_iter=5000, precision=camg.MIXED_FP32)
+    bmx_ms, rmx, emx = block(smx)
+    info = smx.info
+    smx.close()
+    seq_ms = statistics.median(seq)
+    return {"workload": "aniso3d_160", "n": A.n, "nnz": A.nnz, "rhs": k, "levels": info.levels,
+            "sequential_fp64_ms": round(seq_ms, 3),
+            "sequential_iters": [int(min(seq_iters)), int(max(seq_iters))],
+            "block_fp64_ms": round(b64_ms, 3), "block_fp64_speedup": round(seq_ms / b64_ms, 3),
+            "block_fp64_iters": [int(r64.iters.min()), int(r64.iters.max())],
+            "block_fp64_max_true_relres": float(r64.true_relres.max()),
+            "block_fp64_max_rel_err_vs_sequential": e64,
+            "block_mixed_ms": round(bmx_ms, 3), "block_mixed_speedup": round(seq_ms / bmx_ms, 3),
+            "block_mixed_iters": [int(rmx.iters.min()), int(rmx.iters.max())],
+            "block_mixed_max_true_relres": float(rmx.true_relres.max()),
+            "block_mixed_max_rel_err_vs_sequential_fp64": emx}
+
+
+def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
+    """Serving sweep: the 8 resident systems (mixed-precision hierarchies,
+    one slot engine of `slots` columns and one stream each), Poisson
+    arrivals at each rate for `seconds`, system uniform, 1-16 right-hand
+    sides per request (uniform), rtol 1e-8, device-resident request
+    buffers.  Latency is from the scheduled arrival to the poll that
+    returned the completion."""
+    import numpy as np
+    import torch
+
+    from paper_2102_07417_amd import camg, problems
+
+    dev = torch.device("cuda:0")
+    systems = []
+    t0 = time.perf_counter()
+    for name, make in problems.SERVING_SYSTEMS:
+        A = make()
+        s = camg.Solver.from_device(A.n, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col_idx).to(dev),
+                                    torch.from_numpy(A.val).to(dev), precision=camg.MIXED_FP32, max_iter=2000)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed + len(systems))
+        B = torch.rand((A.n, 16), generator=gen, dtype=torch.float64, device=dev) * 2.0 - 1.0
+        systems.append((name, A.n, s, B))
+    setup_s = time.perf_counter() - t0
+    budget = int(budget_gb * (1 << 30))
+    out = {"systems": [{"name": nm, "n": n} for nm, n, _, _ in systems], "slots": slots,
+           "budget_bytes": budget, "rtol": 1e-8, "precision": "mixed (FP32 V-cycle, FP64 PCG)",
+           "generation_and_setup_s": round(setup_s, 2), "rates": []}
+    for lam in rates:
+        srv = camg.Server(budget)
+        for _, _, s, _ in systems:
+            srv.add(s, slots)
+        rng = np.random.default_rng(int(seed + 1000 * lam))
+        count = max(20, int(lam * seconds))
+        arr = np.cumsum(rng.exponential(1.0 / lam, count))
+        sys_of = rng.integers(0, len(systems), count)
+        k_of = rng.integers(1, 17, count)
+        # warm every engine (graph capture) before the clock starts
+        for si, (_, n, _, B) in enumerate(systems):
+            X = torch.empty((n, 1), dtype=torch.float64, device=dev)
+            srv.submit(si, B[:, :1], X, rtol=1e-8, max_iter=2000, tag=-1 - si)
+        warm = 0
+        while warm < len(systems):
+            warm += len(srv.poll())
+        torch.cuda.synchronize()
+        done_t = {}
+        res = {}
+        bufs = {}
+        nxt = 0
+        T0 = time.perf_counter()
+        while len(done_t) < count:
+            now = time.perf_counter() - T0
+            if now > seconds + 60.0:  # far past saturation: stop draining
+                break
+            while nxt < count and arr[nxt] <= now:
+                si, k = int(sys_of[nxt]), int(k_of[nxt])
+                _, n, _, B = systems[si]
+                X = torch.empty((n, k), dtype=torch.float64, device=dev)
+                bufs[nxt] = X
+                srv.submit(si, B[:, :k], X, rtol=1e-8, max_iter=2000, tag=nxt)
+                nxt += 1
+            for c in srv.poll():
+                done_t[c["tag"]] = time.perf_counter() - T0
+                res[c["tag"]] = c
+                bufs.pop(c["tag"], None)
+        T1 = time.perf_counter() - T0
+        srv.close()
+        got = np.array(sorted(done_t))
+        lat = np.array([done_t[i] - arr[i] for i in got]) * 1e3
+        sys_of, k_of = sys_of[got], k_of[got]
+        rhs = int(k_of.sum())
+        worst = max(r["true_relres"] for r in res.values())
+        bad = sum(1 for r in res.values() if r["status"] != camg.OK)
+        per_sys = {}
+        for si, (nm, _, _, _) in enumerate(systems):
+            m = sys_of == si
+            if m.any():
+                per_sys[nm] = {"p50_ms": round(float(np.percentile(lat[m], 50)), 2),
+                               "p99_ms": round(float(np.percentile(lat[m], 99)), 2), "requests": int(m.sum())}
+        out["rates"].append({"rate_per_s": lam, "requests": count, "completed": int(len(got)), "rhs": rhs,
+                             "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                             "mean_queue_ms": round(float(np.mean([r["queue_ms"] for r in res.values()])), 2),
+                             "requests_per_s": round(len(got) / T1, 2), "solves_per_s": round(rhs / T1, 2),
+                             "wall_s": round(T1, 3), "max_true_relres": worst, "not_ok": bad,
+                             "per_system": per_sys})
+        print(f"[serve] rate {lam}: p50 {out['rates'][-1]['p50_ms']} ms p99 {out['rates'][-1]['p99_ms']} ms "
+              f"{out['rates'][-1]['solves_per_s']} solves/s", file=sys.stderr, flush=True)
+    for _, _, s, _ in systems:
+        s.close()
+    return out
 
 
 def cpu_baseline(A, b, x_gpu, gpu_iters):

@@ -171,6 +171,58 @@ camg_status camg_engine_finish(camg_engine_t e, int32_t slot0, int32_t m, double
                                double *true_relres);
 camg_status camg_engine_destroy(camg_engine_t e);
 
+/*
+ * Server: resident hierarchies answering solve requests (the paper reuses
+ * one hierarchy for many solves; here every system added keeps its
+ * hierarchy and a slot engine on a stream of its own, so the systems' work
+ * overlaps on the device).
+ *   camg_server_create: a server whose device memory (engines plus request
+ *     arena) stays within budget_bytes.
+ *   camg_server_add: add the system of handle h with an engine of `slots`
+ *     columns (power of two, at most 64) and iters_per_batch iterations per
+ *     batch (0: chosen from n); *system receives its index.  CAMG_E_NOMEM if
+ *     the engine does not fit the budget; CAMG_E_BUSY after the first
+ *     request.  The handle must outlive the server.
+ *   camg_server_submit: queue a request of k right-hand sides of one system:
+ *     B (n-by-k row-major, row stride ldb) and X (solutions, row stride ldx)
+ *     are host or device pointers (pinned host memory keeps the copies
+ *     asynchronous) that stay valid until the request completes; x0 = 0.
+ *     A request is admitted, in arrival order per system, when k slots are
+ *     free and its n*k*8-byte staging block fits in the arena (the budget
+ *     left after the engines).  CAMG_E_NOMEM if it can never fit.
+ *   camg_server_poll: advance every system without waiting for the device
+ *     (retire finished batches, check true residuals, copy results out,
+ *     admit, launch); completed requests are appended to `out` (at most
+ *     cap, the rest stay for the next call) and *n_out receives their
+ *     number.  Each completion has the worst column status, the largest
+ *     iteration count and true relative residual of the request, the time
+ *     from submission to admission and to completion (ms).
+ *   camg_server_stats: arena bytes in use and its size, requests waiting,
+ *     slots busy (any pointer may be NULL).
+ *   camg_server_destroy: wait for the device and release everything; the
+ *     outcome of requests not yet completed is undefined.
+ * One host thread drives a server.  A request's solutions are bitwise the
+ * same whatever else runs beside it (per-column arithmetic, slot count
+ * fixed per system).
+ */
+typedef struct camg_server *camg_server_t;
+typedef struct {
+    int64_t tag;
+    int32_t status;
+    int32_t iters;
+    double true_relres;
+    double queue_ms;
+    double latency_ms;
+} camg_completion;
+camg_status camg_server_create(int64_t budget_bytes, camg_server_t *out);
+camg_status camg_server_add(camg_server_t s, camg_handle h, int32_t slots, int32_t iters_per_batch, int32_t *system);
+camg_status camg_server_submit(camg_server_t s, int32_t system, int32_t k, const double *B, int32_t ldb, double *X,
+                               int32_t ldx, double rtol, int32_t max_iter, int64_t tag);
+camg_status camg_server_poll(camg_server_t s, camg_completion *out, int32_t cap, int32_t *n_out);
+camg_status camg_server_stats(camg_server_t s, int64_t *arena_used, int64_t *arena_size, int32_t *queued,
+                              int32_t *busy_slots);
+camg_status camg_server_destroy(camg_server_t s);
+
 /* z = M y: one V-cycle (device vectors of length n). */
 camg_status camg_vcycle_dev(camg_handle h, const double *d_y, double *d_z, void *hip_stream);
 

@@ -27,7 +27,8 @@ EXPORTED = [
     "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
     "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
     "camg_set_option", "camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
-    "camg_engine_state", "camg_engine_finish", "camg_engine_destroy",
+    "camg_engine_state", "camg_engine_finish", "camg_engine_destroy", "camg_server_create", "camg_server_add",
+    "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy",
 ]
 OPT_GRAPH = 1
 
@@ -85,6 +86,15 @@ def load(path: str | None = None):
     L.camg_engine_state.argtypes = [vp, vp, vp, vp]
     L.camg_engine_finish.argtypes = [vp, i32, i32, vp, i32, vp]
     L.camg_engine_destroy.argtypes = [vp]
+    L.camg_server_create.argtypes = [i64, C.POINTER(vp)]
+    L.camg_server_add.argtypes = [vp, vp, i32, i32, vp]
+    L.camg_server_submit.argtypes = [vp, i32, i32, vp, i32, vp, i32, dbl, i32, i64]
+    L.camg_server_poll.argtypes = [vp, vp, i32, vp]
+    L.camg_server_stats.argtypes = [vp, vp, vp, vp, vp]
+    L.camg_server_destroy.argtypes = [vp]
+    for name in ("camg_server_create", "camg_server_add", "camg_server_submit", "camg_server_poll",
+                 "camg_server_stats", "camg_server_destroy"):
+        getattr(L, name).restype = C.c_int
     for name in ("camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
                  "camg_engine_state", "camg_engine_finish", "camg_engine_destroy"):
         getattr(L, name).restype = C.c_int
@@ -276,6 +286,88 @@ class Engine:
         if self.e:
             load().camg_engine_destroy(self.e)
             self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def torch_float64():
+    import torch
+    return torch.float64
+
+
+class camg_completion(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("iters", C.c_int32), ("true_relres", C.c_double),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+def _buf_ptr(a):
+    """Pointer and row stride (elements) of a row-major 2D (or 1D) block: a
+    torch tensor (CUDA or host) or a numpy array."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or a.strides[-1] != 8:
+            raise ValueError("float64 block with contiguous rows expected")
+        ld = a.strides[0] // 8 if a.ndim == 2 else 1
+        return C.c_void_p(a.ctypes.data), ld
+    if a.dtype != torch_float64() or a.stride(-1) != 1:
+        raise ValueError("float64 block with contiguous rows expected")
+    ld = a.stride(0) if a.dim() == 2 else 1
+    return C.c_void_p(a.data_ptr()), ld
+
+
+class Server:
+    """Resident hierarchies serving solve requests (continuous batching).
+    Buffers passed to submit() are kept referenced until their request
+    completes."""
+
+    def __init__(self, budget_bytes):
+        s = C.c_void_p()
+        _check(load().camg_server_create(int(budget_bytes), C.byref(s)))
+        self.s = s
+        self.solvers = []
+        self.live = {}
+        self._out = (camg_completion * 512)()
+
+    def add(self, solver, slots, iters_per_batch=0):
+        sid = np.zeros(1, np.int32)
+        _check(load().camg_server_add(self.s, solver.h, int(slots), int(iters_per_batch), _p(sid)))
+        self.solvers.append(solver)
+        return int(sid[0])
+
+    def submit(self, system, B, X, rtol=1e-8, max_iter=1000, tag=0):
+        k = 1 if B.ndim == 1 else B.shape[1]
+        pb, ldb = _buf_ptr(B)
+        px, ldx = _buf_ptr(X)
+        _check(load().camg_server_submit(self.s, int(system), int(k), pb, int(ldb), px, int(ldx), float(rtol),
+                                         int(max_iter), int(tag)))
+        self.live[int(tag)] = (B, X)
+
+    def poll(self):
+        n = np.zeros(1, np.int32)
+        _check(load().camg_server_poll(self.s, C.cast(self._out, C.c_void_p), len(self._out), _p(n)))
+        res = []
+        for i in range(int(n[0])):
+            c = self._out[i]
+            self.live.pop(int(c.tag), None)
+            res.append({"tag": int(c.tag), "status": int(c.status), "iters": int(c.iters),
+                        "true_relres": float(c.true_relres), "queue_ms": float(c.queue_ms),
+                        "latency_ms": float(c.latency_ms)})
+        return res
+
+    def stats(self):
+        u = np.zeros(2, np.int64)
+        q = np.zeros(2, np.int32)
+        _check(load().camg_server_stats(self.s, _p(u[0:1]), _p(u[1:2]), _p(q[0:1]), _p(q[1:2])))
+        return {"arena_used": int(u[0]), "arena_size": int(u[1]), "queued": int(q[0]), "busy_slots": int(q[1])}
+
+    def close(self):
+        if self.s:
+            load().camg_server_destroy(self.s)
+            self.s = None
+        self.live.clear()
 
     def __del__(self):
         try:

@@ -1056,4 +1056,69 @@ camg_status camg_engine_destroy(camg_engine_t ce) {
     });
 }
 
+// ---------------------------------------------------------------- server API
+struct camg_server {
+    Server *s = nullptr;
+    int device = 0;
+};
+
+camg_status camg_server_create(int64_t budget_bytes, camg_server_t *out) {
+    return guarded([&] {
+        if (!out) fail(CAMG_E_ARG, "null output");
+        *out = nullptr;
+        std::unique_ptr<camg_server> cs(new camg_server());
+        HIPC(hipGetDevice(&cs->device));
+        cs->s = server_create(budget_bytes);
+        *out = cs.release();
+    });
+}
+
+camg_status camg_server_add(camg_server_t cs, camg_handle hh, int32_t slots, int32_t iters_per_batch,
+                            int32_t *system) {
+    return guarded([&] {
+        if (!cs) fail(CAMG_E_ARG, "null server");
+        Hier *h = as_hier(hh);
+        if (h->device != cs->device) fail(CAMG_E_ARG, "handle lives on another device");
+        HIPC(hipSetDevice(cs->device));
+        const int id = server_add(*cs->s, *h, slots, iters_per_batch);
+        if (system) *system = id;
+    });
+}
+
+camg_status camg_server_submit(camg_server_t cs, int32_t system, int32_t k, const double *B, int32_t ldb, double *X,
+                               int32_t ldx, double rtol, int32_t max_iter, int64_t tag) {
+    return guarded([&] {
+        if (!cs) fail(CAMG_E_ARG, "null server");
+        HIPC(hipSetDevice(cs->device));
+        server_submit(*cs->s, system, k, B, ldb, X, ldx, rtol, max_iter, tag);
+    });
+}
+
+camg_status camg_server_poll(camg_server_t cs, camg_completion *out, int32_t cap, int32_t *n_out) {
+    return guarded([&] {
+        if (!cs || cap < 0 || (cap > 0 && !out)) fail(CAMG_E_ARG, "bad argument");
+        HIPC(hipSetDevice(cs->device));
+        server_poll(*cs->s);
+        const int m = server_take(*cs->s, out, cap);
+        if (n_out) *n_out = m;
+    });
+}
+
+camg_status camg_server_stats(camg_server_t cs, int64_t *arena_used, int64_t *arena_size, int32_t *queued,
+                              int32_t *busy_slots) {
+    return guarded([&] {
+        if (!cs) fail(CAMG_E_ARG, "null server");
+        server_stats(*cs->s, arena_used, arena_size, queued, busy_slots);
+    });
+}
+
+camg_status camg_server_destroy(camg_server_t cs) {
+    if (!cs) return CAMG_OK;
+    return guarded([&] {
+        (void)hipSetDevice(cs->device);
+        server_destroy(cs->s);
+        delete cs;
+    });
+}
+
 }  // extern "C"

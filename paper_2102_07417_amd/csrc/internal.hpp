@@ -233,6 +233,15 @@ void sum_to(const double *partials, int n, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- multi-RHS engine (multi.hip)
 struct Engine;
+// slot -> column of a right-hand-side block (-1: not involved); passed by value
+struct SlotMap {
+    int8_t q[kMaxSlots];
+};
+// per-column state copied out for the host (plain layout)
+struct EngineSnap {
+    int32_t iter[kMaxSlots], done[kMaxSlots], status[kMaxSlots], active[kMaxSlots];
+    double rnorm[kMaxSlots], bnorm[kMaxSlots], tres2[kMaxSlots];
+};
 int64_t engine_footprint(const Hier &h, int K);
 Engine *engine_create(Hier &h, int K, int cap, hipStream_t s);
 void engine_destroy(Engine *e);
@@ -247,5 +256,23 @@ void engine_copy_x(Engine &E, int c0, int m, double *X, int ldx, hipStream_t s);
 void engine_release(Engine &E, int c0, int m, hipStream_t s);
 void engine_replace(Engine &E, unsigned long long mask, hipStream_t s);
 void engine_hist(Engine &E, int c, double *host, int cap_out, int count, hipStream_t s);
+void engine_start_slots(Engine &E, const SlotMap &q, const double *B, int ldb, double rtol, int max_iter,
+                        hipStream_t s);
+void engine_launch(Engine &E, int iters, hipStream_t s);
+void engine_snapshot(Engine &E, bool true_res, EngineSnap *snap, hipStream_t s);
+void engine_release_mask(Engine &E, unsigned long long mask, hipStream_t s);
+void engine_gather_x(Engine &E, const SlotMap &q, int k, double *out, hipStream_t s);
+int engine_n(const Engine &E);
+
+// ---------------------------------------------------------------- server (serve.hip)
+struct Server;
+Server *server_create(int64_t budget);
+int server_add(Server &S, Hier &h, int slots, int ipb);
+void server_submit(Server &S, int sys, int k, const double *B, int ldb, double *X, int ldx, double rtol,
+                   int max_iter, int64_t tag);
+int server_poll(Server &S);
+int server_take(Server &S, camg_completion *out, int cap);
+void server_stats(const Server &S, int64_t *arena_used, int64_t *arena_size, int32_t *queued, int32_t *active);
+void server_destroy(Server *S);
 
 }  // namespace camg

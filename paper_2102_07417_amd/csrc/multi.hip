@@ -36,6 +36,9 @@ struct MState;
 struct Engine;
 namespace {
 
+constexpr int kRed = 1024;       // threads of the one-block reductions
+constexpr int kMGridMax = 2048;  // most blocks of a block-row kernel (partials per column)
+
 struct MState {
     double rho[kMaxSlots], rho_old[kMaxSlots], sigma[kMaxSlots], alpha[kMaxSlots], beta[kMaxSlots];
     double rnorm[kMaxSlots], bnorm[kMaxSlots], tol[kMaxSlots], rtol[kMaxSlots];
@@ -69,55 +72,69 @@ __device__ __forceinline__ void block_col_sum(double v, double *partials, unsign
     __syncthreads();
 }
 
-// Sum over blocks of partials[b * K + c] for every column; result of column
-// c in out[c] (shared).  Fixed order: thread t adds blocks t/K, t/K + T/K,
-// ... then the T/K per-column sums are added in index order.
+// Sum over blocks of partials[b * K + c] for every column, by one block of
+// kRed threads; result of column c in out[c] (shared).  Fixed order: thread
+// (g, c) adds blocks g, g + per, ... into four running sums, then the per
+// group sums are added pairwise in a fixed tree.
 template <int K>
 __device__ __forceinline__ void sum_cols(const double *partials, int nb, double *out) {
-    __shared__ double sh[kBlock];
-    constexpr int per = kBlock / K;
+    __shared__ double sh[kRed];
+    constexpr int per = kRed / K;
     const int c = threadIdx.x % K, g = threadIdx.x / K;
-    double t = 0.0;
-    for (int b = g; b < nb; b += per) t += partials[(size_t)b * K + c];
-    sh[threadIdx.x] = t;
-    __syncthreads();
-    if (threadIdx.x < K) {
-        double u = 0.0;
-        for (int q = 0; q < per; ++q) u += sh[q * K + threadIdx.x];
-        out[threadIdx.x] = u;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int b = g;
+    for (; b + 3 * per < nb; b += 4 * per) {
+        t0 += partials[(size_t)b * K + c];
+        t1 += partials[(size_t)(b + per) * K + c];
+        t2 += partials[(size_t)(b + 2 * per) * K + c];
+        t3 += partials[(size_t)(b + 3 * per) * K + c];
     }
+    for (; b < nb; b += per) t0 += partials[(size_t)b * K + c];
+    sh[threadIdx.x] = (t0 + t1) + (t2 + t3);
+    __syncthreads();
+    for (int s = per / 2; s >= 1; s >>= 1) {
+        if (g < s) sh[threadIdx.x] += sh[threadIdx.x + s * K];
+        __syncthreads();
+    }
+    if (threadIdx.x < K) out[threadIdx.x] = sh[threadIdx.x];
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ row kernel
-// out(i, c) = sum_j a_ij g(j, c); epi(i, c, acc, dot)
+// out(i, c) = sum_j a_ij g(j, c); epi(i, c, acc, dot).  The row's entries
+// are taken eight at a time: the lanes of a group read the same index and
+// value (one cache line per group), clamped to the row so every load and
+// gather is unconditional and all are in flight together; the products are
+// added in CSR order, the padding ones skipped.
 template <class T, int K, bool DOT, class G, class E>
 __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const T *__restrict__ av, G g, E epi, double *partials,
                                                   unsigned long long pmask) {
     constexpr int RPP = kBlock / K;
+    constexpr int U = 8;
     const int c = threadIdx.x % K, grp = threadIdx.x / K;
     int r0, r1;
     block_rows(n, r0, r1);
     double dot = 0.0;
-    for (int ib = r0; ib < r1; ib += RPP) {
-        const int i = ib + grp;
+    for (int i = r0 + grp; i < r1; i += RPP) {
+        const int e0 = rp[i], e1 = rp[i + 1];
         T acc = 0;
-        if (i < r1) {
-            const int e0 = rp[i], e1 = rp[i + 1];
-            for (int eb = e0; eb < e1; eb += K) {
-                const int e = eb + c;
-                const int jl = e < e1 ? ci[e] : 0;
-                const T al = e < e1 ? av[e] : T(0);
-                const int cnt = min(K, e1 - eb);
-                for (int t = 0; t < cnt; ++t) {
-                    const int j = __shfl(jl, t, K);
-                    const T a = __shfl(al, t, K);
-                    acc += a * g(j, c);
-                }
+        for (int eb = e0; eb < e1; eb += U) {
+            int j[U];
+            T a[U], x[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const int e = min(eb + t, e1 - 1);
+                j[t] = ci[e];
+                a[t] = av[e];
             }
-            epi(i, c, acc, dot);
+#pragma unroll
+            for (int t = 0; t < U; ++t) x[t] = g(j[t], c);
+#pragma unroll
+            for (int t = 0; t < U; ++t)
+                if (eb + t < e1) acc += a[t] * x[t];
         }
+        epi(i, c, acc, dot);
     }
     if (DOT) block_col_sum<K>(dot, partials, pmask);
 }
@@ -207,22 +224,24 @@ struct MERes {  // d = B - A X; dot += d^2; R = d for the columns of `mask`
 };
 
 // ------------------------------------------------------------------ elementwise / state kernels
-// Start columns [c0, c0 + m): X = 0, R = B (B is n-by-m row-major with row
-// stride ldb), both P = 0; state reset; partials of ||b||^2 for them.
+// Start the columns c with q.q[c] >= 0 from column q.q[c] of B (n-by-m
+// row-major, row stride ldb): X = 0, R = B, both P = 0; state reset;
+// partials of ||b||^2 for them.
 template <int K>
-__global__ void __launch_bounds__(kBlock) mk_start(int n, int c0, int m, const double *__restrict__ B, int ldb,
+__global__ void __launch_bounds__(kBlock) mk_start(int n, SlotMap q, const double *__restrict__ B, int ldb,
                                                    double *X, double *R, double *B0, double *P0, double *P1,
                                                    double rtol, int max_iter, double *pr2, MState *st) {
     constexpr int RPP = kBlock / K;
     const int c = threadIdx.x % K, grp = threadIdx.x / K;
-    const bool mine = c >= c0 && c < c0 + m;
+    const int qc = q.q[c];
+    const bool mine = qc >= 0;
     int r0, r1;
     block_rows(n, r0, r1);
     double acc = 0.0;
     if (mine)
         for (int i = r0 + grp; i < r1; i += RPP) {
             const size_t o = (size_t)i * K + c;
-            const double bi = B[(size_t)i * ldb + (c - c0)];
+            const double bi = B[(size_t)i * ldb + qc];
             X[o] = 0.0;
             R[o] = bi;
             B0[o] = bi;
@@ -253,9 +272,44 @@ __global__ void __launch_bounds__(kBlock) mk_start(int n, int c0, int m, const d
     }
 }
 
+// free the slots of `mask`
+template <int K>
+__global__ void mk_release(MState *st, unsigned long long mask) {
+    const int c = threadIdx.x;
+    if (c < K && ((mask >> c) & 1ull)) st->active[c] = 0;
+}
+
+// per-column state (and, when sq is given, the true ||b - A x||^2 sums)
+// into a plain snapshot for the host
+template <int K>
+__global__ void mk_snap(const MState *st, const double *sq, EngineSnap *out) {
+    const int c = threadIdx.x;
+    if (c < K) {
+        out->iter[c] = st->iter[c];
+        out->done[c] = st->done[c];
+        out->status[c] = st->status[c];
+        out->active[c] = st->active[c];
+        out->rnorm[c] = st->rnorm[c];
+        out->bnorm[c] = st->bnorm[c];
+        out->tres2[c] = sq ? sq[c] : -1.0;
+    }
+}
+
+// out (n-by-k row-major) = the columns q.q[0..k) of X
+template <int K>
+__global__ void __launch_bounds__(kBlock) mk_gather_cols(int n, int k, SlotMap q, const double *__restrict__ X,
+                                                         double *__restrict__ out) {
+    const int64_t tot = (int64_t)n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / k;
+        const int j = (int)(t - i * k);
+        out[t] = X[i * K + q.q[j]];
+    }
+}
+
 // Stopping test of every running column (one block); hist is K-by-cap.
 template <int K>
-__global__ void __launch_bounds__(kBlock) mk_check(const double *pr2, int nb, MState *st, double *hist, int cap,
+__global__ void __launch_bounds__(kRed) mk_check(const double *pr2, int nb, MState *st, double *hist, int cap,
                                                    int32_t *hflag) {
     __shared__ double tot[K];
     sum_cols<K>(pr2, nb, tot);
@@ -289,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) mk_check(const double *pr2, int nb, MS
 
 // rho_c and beta_c of every running column (one block)
 template <int K>
-__global__ void __launch_bounds__(kBlock) mk_fin_rz(const double *prz, int nb, MState *st) {
+__global__ void __launch_bounds__(kRed) mk_fin_rz(const double *prz, int nb, MState *st) {
     __shared__ double tot[K];
     sum_cols<K>(prz, nb, tot);
     if (threadIdx.x < K) {
@@ -306,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) mk_fin_rz(const double *prz, int nb, M
 
 // sigma_c, breakdown test, alpha_c; iteration count (one block)
 template <int K>
-__global__ void __launch_bounds__(kBlock) mk_fin_pq(const double *ppq, int nb, MState *st) {
+__global__ void __launch_bounds__(kRed) mk_fin_pq(const double *ppq, int nb, MState *st) {
     __shared__ double tot[K];
     sum_cols<K>(ppq, nb, tot);
     if (threadIdx.x < K) {
@@ -377,13 +431,14 @@ __global__ void mk_restart(MState *st, unsigned long long mask) {
 }
 
 template <int K>
-__global__ void __launch_bounds__(kBlock) mk_sum(const double *partials, int nb, double *out) {
+__global__ void __launch_bounds__(kRed) mk_sum(const double *partials, int nb, double *out) {
     __shared__ double tot[K];
     sum_cols<K>(partials, nb, tot);
     if (threadIdx.x < K) out[threadIdx.x] = tot[threadIdx.x];
 }
 
-// last level: Z = Ainv Y for a K-column block (FP64 arithmetic), K lanes per row
+// last level: Z = Ainv Y for a K-column block (FP64 arithmetic), K lanes
+// per row; eight loads in flight, products added in column order
 template <class T, int K>
 __global__ void __launch_bounds__(kBlock) mk_coarse(int n, const double *__restrict__ cinv, const T *__restrict__ y,
                                                     T *__restrict__ z) {
@@ -391,15 +446,27 @@ __global__ void __launch_bounds__(kBlock) mk_coarse(int n, const double *__restr
     const int c = threadIdx.x % K;
     const int i = blockIdx.x * RPP + threadIdx.x / K;
     if (i >= n) return;
+    const double *row = cinv + (size_t)i * n;
     double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += cinv[(size_t)i * n + j] * (double)y[(size_t)j * K + c];
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        double a[8], v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            a[t] = row[j + t];
+            v[t] = (double)y[(size_t)(j + t) * K + c];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc += a[t] * v[t];
+    }
+    for (; j < n; ++j) acc += row[j] * (double)y[(size_t)j * K + c];
     z[(size_t)i * K + c] = (T)acc;
 }
 
 int mgrid(int n, int K) {
     const int rpp = kBlock / K;
     int g = (n + rpp - 1) / rpp;
-    g = std::min(g, 1024);
+    g = std::min(g, kMGridMax);
     return std::max(8, (g + 7) / 8 * 8);
 }
 
@@ -543,17 +610,17 @@ template <int K>
 void miteration(Engine &E, int par, hipStream_t s) {
     Hier &h = *E.h;
     const Csr &A = h.lev[0].A;
-    mk_check<K><<<1, kBlock, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev);
+    mk_check<K><<<1, kRed, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev);
     HIPC(hipGetLastError());
     if (E.mixed) mvcycle<float, K>(E, true, s);
     else mvcycle<double, K>(E, true, s);
     // the r.z partials come from a kernel on the n_0 rows: lv[0].grid == nb_vec blocks
-    mk_fin_rz<K><<<1, kBlock, 0, s>>>(E.prz, E.nb_vec, E.st);
+    mk_fin_rz<K><<<1, kRed, 0, s>>>(E.prz, E.nb_vec, E.st);
     const double *beta =
         reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
     launch_mrows_any<double, K>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s, MGDir<K>{E.Z, E.P[par], beta},
                                 MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true);
-    mk_fin_pq<K><<<1, kBlock, 0, s>>>(E.ppq, E.lv[0].grid, E.st);
+    mk_fin_pq<K><<<1, kRed, 0, s>>>(E.ppq, E.lv[0].grid, E.st);
     mk_update<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.P[1 - par], E.Q, E.X, E.R, E.pr2, E.st);
     HIPC(hipGetLastError());
 }
@@ -625,7 +692,7 @@ int64_t engine_footprint(const Hier &h, int K) {
     const bool mixed = h.prm.precision == CAMG_MIXED_FP32;
     int64_t b = 7 * n * K * 8;  // X, R, B, Z, P0, P1, Q
     for (int l = 0; l < h.nlev; ++l) b += 5 * (int64_t)h.lev[l].A.nr * K * (mixed ? 4 : 8);
-    b += 4 * (int64_t)1024 * K * 8 + sizeof(MState);
+    b += 4 * (int64_t)kMGridMax * K * 8 + sizeof(MState);
     return b;
 }
 
@@ -665,10 +732,10 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
         }
     }
     E->nb_vec = mgrid(E->n, K);
-    E->pr2 = E->pool.alloc<double>((size_t)1024 * K);
-    E->prz = E->pool.alloc<double>((size_t)1024 * K);
-    E->ppq = E->pool.alloc<double>((size_t)1024 * K);
-    E->ptmp = E->pool.alloc<double>((size_t)1024 * K);
+    E->pr2 = E->pool.alloc<double>((size_t)kMGridMax * K);
+    E->prz = E->pool.alloc<double>((size_t)kMGridMax * K);
+    E->ppq = E->pool.alloc<double>((size_t)kMGridMax * K);
+    E->ptmp = E->pool.alloc<double>((size_t)kMGridMax * K);
     E->sc = E->pool.alloc<double>(kMaxSlots);
     E->st = E->pool.alloc<MState>(1);
     E->cap = cap;
@@ -680,7 +747,7 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     for (auto &B : E->lv)
         for (void *p : {B.y, B.s, B.t, B.r, B.z})
             if (p) HIPC(hipMemsetAsync(p, 0, (size_t)h.lev[&B - &E->lv[0]].A.nr * K * vb, s));
-    HIPC(hipMemsetAsync(E->pr2, 0, (size_t)1024 * K * 8, s));
+    HIPC(hipMemsetAsync(E->pr2, 0, (size_t)kMGridMax * K * 8, s));
     HIPC(hipHostMalloc((void **)&E->hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
     HIPC(hipHostGetDevicePointer((void **)&E->hflag_dev, E->hflag, 0));
     E->hflag[0] = 0;
@@ -688,13 +755,56 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     return E.release();
 }
 
-void engine_start(Engine &E, int c0, int m, const double *B, int ldb, double rtol, int max_iter, hipStream_t s) {
-    if (c0 < 0 || m < 1 || c0 + m > E.K) fail(CAMG_E_ARG, "slot range out of bounds");
-    CAMG_K_SWITCH(E.K, (mk_start<KK><<<E.nb_vec, kBlock, 0, s>>>(E.n, c0, m, B, ldb, E.X, E.R, E.Bk, E.P[0], E.P[1],
-                                                                  rtol, max_iter, E.pr2, E.st)));
+void engine_start_slots(Engine &E, const SlotMap &q, const double *B, int ldb, double rtol, int max_iter,
+                        hipStream_t s) {
+    CAMG_K_SWITCH(E.K, (mk_start<KK><<<E.nb_vec, kBlock, 0, s>>>(E.n, q, B, ldb, E.X, E.R, E.Bk, E.P[0], E.P[1], rtol,
+                                                                  max_iter, E.pr2, E.st)));
     HIPC(hipGetLastError());
     E.hflag[0] = 1;
 }
+
+void engine_start(Engine &E, int c0, int m, const double *B, int ldb, double rtol, int max_iter, hipStream_t s) {
+    if (c0 < 0 || m < 1 || c0 + m > E.K) fail(CAMG_E_ARG, "slot range out of bounds");
+    SlotMap q;
+    for (int c = 0; c < kMaxSlots; ++c) q.q[c] = (c >= c0 && c < c0 + m) ? (int8_t)(c - c0) : (int8_t)-1;
+    engine_start_slots(E, q, B, ldb, rtol, max_iter, s);
+}
+
+// Enqueue `iters` iterations and a stopping test; no wait.
+void engine_launch(Engine &E, int iters, hipStream_t s) {
+    for (int k = 0; k < iters; ++k) m_launch_iteration(E, s);
+    CAMG_K_SWITCH(E.K, (mk_check<KK><<<1, kRed, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev)));
+    HIPC(hipGetLastError());
+}
+
+// Enqueue the per-column snapshot into the device buffer `snap` (with the
+// true residual sums when true_res); no wait.
+void engine_snapshot(Engine &E, bool true_res, EngineSnap *snap, hipStream_t s) {
+    if (true_res) {
+        const Csr &A = E.h->lev[0].A;
+        CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s,
+                                                           MGather<double, KK>{E.X}, MERes<KK>{E.Bk, nullptr, 0ull},
+                                                           E.ptmp, true)));
+        CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, E.lv[0].grid, E.sc)));
+    }
+    CAMG_K_SWITCH(E.K, (mk_snap<KK><<<1, 64, 0, s>>>(E.st, true_res ? E.sc : nullptr, snap)));
+    HIPC(hipGetLastError());
+}
+
+void engine_release_mask(Engine &E, unsigned long long mask, hipStream_t s) {
+    if (!mask) return;
+    CAMG_K_SWITCH(E.K, (mk_release<KK><<<1, 64, 0, s>>>(E.st, mask)));
+    HIPC(hipGetLastError());
+}
+
+void engine_gather_x(Engine &E, const SlotMap &q, int k, double *out, hipStream_t s) {
+    const int64_t tot = (int64_t)E.n * k;
+    const int grid = (int)std::min<int64_t>((tot + kBlock - 1) / kBlock, 4096);
+    CAMG_K_SWITCH(E.K, (mk_gather_cols<KK><<<std::max(grid, 1), kBlock, 0, s>>>(E.n, k, q, E.X, out)));
+    HIPC(hipGetLastError());
+}
+
+int engine_n(const Engine &E) { return E.n; }
 
 // Run up to `iters` iterations (or until no column is running); polls one
 // iteration behind.  Returns the number of running columns at the end.
@@ -716,7 +826,7 @@ int engine_step(Engine &E, int iters, hipStream_t s) {
         }
     }
     // stopping test for the residuals just formed
-    CAMG_K_SWITCH(E.K, (mk_check<KK><<<1, kBlock, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev)));
+    CAMG_K_SWITCH(E.K, (mk_check<KK><<<1, kRed, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev)));
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));
     return flag[0];
@@ -739,7 +849,7 @@ void engine_true_res(Engine &E, double *rel, hipStream_t s) {
     CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s, MGather<double, KK>{E.X},
                                                        MERes<KK>{E.Bk, nullptr, 0ull}, E.ptmp, true)));
     double *part = E.ptmp;
-    CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kBlock, 0, s>>>(part, E.lv[0].grid, E.sc)));
+    CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(part, E.lv[0].grid, E.sc)));
     HIPC(hipGetLastError());
     double t2[kMaxSlots];
     MState st;
@@ -757,9 +867,9 @@ void engine_copy_x(Engine &E, int c0, int m, double *X, int ldx, hipStream_t s) 
 
 // mark columns [c0, c0+m) free
 void engine_release(Engine &E, int c0, int m, hipStream_t s) {
-    std::vector<int32_t> zero(m, 0);
-    HIPC(hipMemcpyAsync(reinterpret_cast<char *>(E.st) + offsetof(MState, active) + sizeof(int32_t) * c0, zero.data(),
-                        sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+    unsigned long long mask = 0;
+    for (int c = c0; c < c0 + m; ++c) mask |= 1ull << c;
+    engine_release_mask(E, mask, s);
     HIPC(hipStreamSynchronize(s));
 }
 

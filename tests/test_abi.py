@@ -1,0 +1,91 @@
+"""The C-ABI library on the CPU: it loads, exports every function the
+header declares, the Python binding lists the same set, and the binding's
+structures have the header's layout (checked against a C program compiled
+from the header).  No call here touches a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2102_07417_amd import camg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "camg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(camg_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return camg.load()
+    except OSError as e:
+        pytest.fail(f"libcamg.so missing or not loadable (run the build first): {e}")
+
+
+def test_header_declares_functions():
+    names = _declared()
+    assert len(names) >= 30
+    for must in ("camg_setup", "camg_solve", "camg_solve_dev", "camg_vcycle_dev", "camg_galerkin",
+                 "camg_solve_multi_dev", "camg_server_poll", "camg_destroy"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding knows the same set
+    assert sorted(camg.EXPORTED) == _declared()
+
+
+def test_pure_host_calls(lib):
+    assert lib.camg_abi_version() == 1
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
+        s = lib.camg_status_str(code)
+        assert isinstance(s, bytes) and len(s) > 0
+    p = camg.camg_params()
+    lib.camg_params_default(C.byref(p))
+    assert p.theta == 0.25 and p.nu_pre == 1 and p.nu_post == 1 and p.max_coarse == 256 and p.max_levels == 25
+    assert p.precision == camg.FP64 and p.omega == 0.0
+
+
+def test_argument_errors_without_device(lib):
+    # null handles and pointers are rejected before any device work
+    assert lib.camg_info(None, None) == camg.E_ARG
+    assert lib.camg_destroy(None) == camg.OK
+    assert lib.camg_engine_destroy(None) == camg.OK
+    assert lib.camg_server_destroy(None) == camg.OK
+    assert len(lib.camg_last_error()) >= 0
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "camg.h"
+int main(void) {
+  printf("params %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
+         offsetof(camg_params, precision), offsetof(camg_params, max_iter));
+  printf("info %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p));
+  printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
+         offsetof(camg_completion, latency_ms));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    out = dict((l.split()[0], [int(v) for v in l.split()[1:]])
+               for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    P = camg.camg_params
+    assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset]
+    I = camg.camg_info_t
+    assert out["info"] == [C.sizeof(I), I.nnz_p.offset]
+    Q = camg.camg_completion
+    assert out["completion"] == [C.sizeof(Q), Q.true_relres.offset, Q.latency_ms.offset]
