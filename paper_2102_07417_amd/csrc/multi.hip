@@ -101,100 +101,276 @@ __device__ __forceinline__ void sum_cols(const double *partials, int nb, double 
 }
 
 // ------------------------------------------------------------------ row kernel
-// out(i, c) = sum_j a_ij g(j, c); epi(i, c, acc, dot).  The row's entries
-// are taken eight at a time: the lanes of a group read the same index and
-// value (one cache line per group), clamped to the row so every load and
-// gather is unconditional and all are in flight together; the products are
-// added in CSR order, the padding ones skipped.
+// A lane owns V consecutive columns of its row (V * sizeof(T) = 16 bytes
+// where K allows), so a gather of row j is one 16-byte load per lane and
+// LPR = K / V lanes cover the row.
+template <class T, int K>
+struct Lay {
+    static constexpr int V = (K * (int)sizeof(T) >= 16) ? 16 / (int)sizeof(T) : K;
+    static constexpr int LPR = K / V;
+    static constexpr int RPP = kBlock / LPR;  // rows per pass of a block
+};
+
+// V consecutive elements (16, 8 or 4k bytes, aligned to their size)
+template <class X, int V>
+__device__ __forceinline__ void vload(const X *p, X (&o)[V]) {
+    constexpr int B = V * (int)sizeof(X);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int w = 0; w < B / 16; ++w) {
+            const uint4 u = reinterpret_cast<const uint4 *>(p)[w];
+            __builtin_memcpy(reinterpret_cast<char *>(o) + 16 * w, &u, 16);
+        }
+    } else if constexpr (B == 8) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(o, &u, 8);
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = p[v];
+    }
+}
+template <class X, int V>
+__device__ __forceinline__ void vstore(X *p, const X (&o)[V]) {
+    constexpr int B = V * (int)sizeof(X);
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int w = 0; w < B / 16; ++w) {
+            uint4 u;
+            __builtin_memcpy(&u, reinterpret_cast<const char *>(o) + 16 * w, 16);
+            reinterpret_cast<uint4 *>(p)[w] = u;
+        }
+    } else if constexpr (B == 8) {
+        uint2 u;
+        __builtin_memcpy(&u, o, 8);
+        *reinterpret_cast<uint2 *>(p) = u;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) p[v] = o[v];
+    }
+}
+
+// Per-column sums over the block of the V accumulators of each lane:
+// partials[blockIdx.x * K + c], lanes of the same column added in group order.
+template <int K, int V>
+__device__ __forceinline__ void block_col_sum_v(const double (&d)[V], double *partials, unsigned long long mask) {
+    __shared__ double sh[kBlock * V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) sh[threadIdx.x * V + v] = d[v];
+    __syncthreads();
+    constexpr int G = kBlock * V / K;
+    if (threadIdx.x < K && ((mask >> threadIdx.x) & 1ull)) {
+        double t = 0.0;
+        for (int g = 0; g < G; ++g) t += sh[g * K + threadIdx.x];
+        partials[(size_t)blockIdx.x * K + threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+constexpr int kStage = 1024;  // CSR entries staged in LDS per chunk
+constexpr int kChunkRowsMax = 512;
+
+// One row: acc(c0 .. c0+V) = sum_j a_ij g(j, .).  Entries G::kU at a time,
+// clamped to the row so all loads and gathers are unconditional and in
+// flight together; products added in CSR order, padding skipped.
+template <class T, int V, class CI, class AV, class G>
+__device__ __forceinline__ void row_acc(int e0, int e1, const CI *ci, const AV *av, const G &g, int c0, T (&acc)[V]) {
+    constexpr int U = G::kU;
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = T(0);
+    for (int eb = e0; eb < e1; eb += U) {
+        int j[U];
+        T a[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int e = min(eb + t, e1 - 1);
+            j[t] = ci[e];
+            a[t] = av[e];
+        }
+        T x[U][V];
+#pragma unroll
+        for (int t = 0; t < U; ++t) g.template get<V>(j[t], c0, x[t]);
+#pragma unroll
+        for (int t = 0; t < U; ++t)
+            if (eb + t < e1) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += a[t] * x[t][v];
+            }
+    }
+}
+
+// out(i, .) = sum_j a_ij g(j, .); epi(i, c0, acc, dot).  Each block walks its
+// rows in chunks of `crows` rows; a chunk whose entries fit is first staged
+// in LDS (indices, values and row pointers, coalesced), so the group's
+// lanes read each entry from LDS; a longer chunk reads them from memory.
 template <class T, int K, bool DOT, class G, class E>
 __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const T *__restrict__ av, G g, E epi, double *partials,
-                                                  unsigned long long pmask) {
-    constexpr int RPP = kBlock / K;
-    constexpr int U = 8;
-    const int c = threadIdx.x % K, grp = threadIdx.x / K;
+                                                  unsigned long long pmask, int crows) {
+    using L = Lay<T, K>;
+    constexpr int V = L::V, LPR = L::LPR, RPP = L::RPP;
+    __shared__ int32_t s_ci[kStage];
+    __shared__ T s_av[kStage];
+    __shared__ int32_t s_rp[kChunkRowsMax + 1];
+    const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+    const int c0 = lane * V;
+    g.prep(c0);
+    epi.prep(c0);
     int r0, r1;
     block_rows(n, r0, r1);
-    double dot = 0.0;
-    for (int i = r0 + grp; i < r1; i += RPP) {
-        const int e0 = rp[i], e1 = rp[i + 1];
-        T acc = 0;
-        for (int eb = e0; eb < e1; eb += U) {
-            int j[U];
-            T a[U], x[U];
+    double dot[V];
 #pragma unroll
-            for (int t = 0; t < U; ++t) {
-                const int e = min(eb + t, e1 - 1);
-                j[t] = ci[e];
-                a[t] = av[e];
+    for (int v = 0; v < V; ++v) dot[v] = 0.0;
+    for (int a = r0; a < r1; a += crows) {
+        const int b = min(a + crows, r1);
+        const int E0 = rp[a], E1 = rp[b];
+        if (E1 - E0 <= kStage) {
+            __syncthreads();  // the previous chunk is done with the stage
+            for (int t = threadIdx.x; t < E1 - E0; t += kBlock) {
+                s_ci[t] = ci[E0 + t];
+                s_av[t] = av[E0 + t];
             }
-#pragma unroll
-            for (int t = 0; t < U; ++t) x[t] = g(j[t], c);
-#pragma unroll
-            for (int t = 0; t < U; ++t)
-                if (eb + t < e1) acc += a[t] * x[t];
+            for (int t = threadIdx.x; t <= b - a; t += kBlock) s_rp[t] = rp[a + t] - E0;
+            __syncthreads();
+            for (int i = a + grp; i < b; i += RPP) {
+                T acc[V];
+                row_acc<T, V>(s_rp[i - a], s_rp[i - a + 1], s_ci, s_av, g, c0, acc);
+                epi.template fin<V>(i, c0, acc, dot);
+            }
+        } else {
+            for (int i = a + grp; i < b; i += RPP) {
+                T acc[V];
+                row_acc<T, V>(rp[i], rp[i + 1], ci, av, g, c0, acc);
+                epi.template fin<V>(i, c0, acc, dot);
+            }
         }
-        epi(i, c, acc, dot);
     }
-    if (DOT) block_col_sum<K>(dot, partials, pmask);
+    if constexpr (DOT) block_col_sum_v<K, V>(dot, partials, pmask);
+}
+
+// rows per chunk of a matrix with `nnz` entries in `nr` rows
+template <class T, int K>
+int chunk_rows(int64_t nr, int64_t nnz) {
+    constexpr int RPP = Lay<T, K>::RPP;
+    const double mean = nr > 0 ? std::max(1.0, (double)nnz / (double)nr) : 1.0;
+    int r = (int)(0.75 * kStage / mean) / RPP * RPP;
+    r = std::min(r, kChunkRowsMax / RPP * RPP);
+    return std::max(r, RPP);
 }
 
 template <class T, int K, class TX = T>
 struct MGather {
+    static constexpr int kU = 8;
+    __device__ void prep(int) {}
     const TX *x;
-    __device__ T operator()(int j, int c) const { return (T)x[(size_t)j * K + c]; }
+    template <int V>
+    __device__ void get(int j, int c0, T (&o)[V]) const {
+        TX u[V];
+        vload<TX, V>(x + (size_t)j * K + c0, u);
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = (T)u[v];
+    }
 };
 
 template <class T, int K, class TY>
 struct MEPre {  // S = wd Y, R = Y - (A wd) Y  (values pre-scaled by wd)
+    __device__ void prep(int) {}
     const T *wd;
     const TY *y;
     T *s, *r;
-    __device__ void operator()(int i, int c, T acc, double &) const {
-        const size_t o = (size_t)i * K + c;
-        const T yi = (T)y[o];
-        s[o] = wd[i] * yi;
-        r[o] = yi - acc;
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        TY yv[V];
+        vload<TY, V>(y + o, yv);
+        const T w = wd[i];
+        T sv[V], rv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T yi = (T)yv[v];
+            sv[v] = w * yi;
+            rv[v] = yi - acc[v];
+        }
+        vstore<T, V>(s + o, sv);
+        vstore<T, V>(r + o, rv);
     }
 };
 template <class T, int K, class TY, class TZ>
 struct MEPost {  // Z = S + wd (Y - A S); dot += Y Z
+    __device__ void prep(int) {}
     const T *wd;
     const TY *y;
     const T *s;
     TZ *z;
-    __device__ void operator()(int i, int c, T acc, double &dot) const {
-        const size_t o = (size_t)i * K + c;
-        const T zi = s[o] + wd[i] * ((T)y[o] - acc);
-        const TZ zo = (TZ)zi;
-        z[o] = zo;
-        dot += (double)y[o] * (double)zo;
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], double (&dot)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        TY yv[V];
+        T sv[V];
+        vload<TY, V>(y + o, yv);
+        vload<T, V>(s + o, sv);
+        const T w = wd[i];
+        TZ zv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const T zi = sv[v] + w * ((T)yv[v] - acc[v]);
+            zv[v] = (TZ)zi;
+            dot[v] += (double)yv[v] * (double)zv[v];
+        }
+        vstore<TZ, V>(z + o, zv);
     }
 };
 template <class T, int K, class TY>
 struct MEResid {
+    __device__ void prep(int) {}
     const TY *y;
     T *r;
-    __device__ void operator()(int i, int c, T acc, double &) const {
-        const size_t o = (size_t)i * K + c;
-        r[o] = (T)y[o] - acc;
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        TY yv[V];
+        vload<TY, V>(y + o, yv);
+        T rv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) rv[v] = (T)yv[v] - acc[v];
+        vstore<T, V>(r + o, rv);
     }
 };
 template <class T, int K, bool ADD>
 struct MESpmv {
+    __device__ void prep(int) {}
     T *out;
-    __device__ void operator()(int i, int c, T acc, double &) const {
-        const size_t o = (size_t)i * K + c;
-        out[o] = ADD ? out[o] + acc : acc;
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        T ov[V];
+        if (ADD) {
+            vload<T, V>(out + o, ov);
+#pragma unroll
+            for (int v = 0; v < V; ++v) ov[v] = ov[v] + acc[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) ov[v] = acc[v];
+        }
+        vstore<T, V>(out + o, ov);
     }
 };
+constexpr int kVMax = 4;
 template <int K>
-struct MGDir {  // P_new = Z + beta_c P_old, on the fly
+struct MGDir {  // P_new = Z + beta_c P_old, on the fly (two gathers: four entries at a time)
+    static constexpr int kU = 4;
     const double *z, *p;
     const double *beta;
-    __device__ double operator()(int j, int c) const {
-        const size_t o = (size_t)j * K + c;
-        return z[o] + beta[c] * p[o];
+    double bt[kVMax];
+    __device__ void prep(int c0) {
+        for (int v = 0; v < kVMax; ++v) bt[v] = c0 + v < K ? beta[c0 + v] : 0.0;
+    }
+    template <int V>
+    __device__ void get(int j, int c0, double (&o)[V]) const {
+        double zv[V], pv[V];
+        vload<double, V>(z + (size_t)j * K + c0, zv);
+        vload<double, V>(p + (size_t)j * K + c0, pv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = zv[v] + bt[v] * pv[v];
     }
 };
 template <int K>
@@ -202,24 +378,46 @@ struct MEDir {
     const double *z, *pold;
     const double *beta;
     double *pnew, *q;
-    __device__ void operator()(int i, int c, double acc, double &dot) const {
-        const size_t o = (size_t)i * K + c;
-        const double pi = z[o] + beta[c] * pold[o];
-        pnew[o] = pi;
-        q[o] = acc;
-        dot += pi * acc;
+    double bt[kVMax];
+    __device__ void prep(int c0) {
+        for (int v = 0; v < kVMax; ++v) bt[v] = c0 + v < K ? beta[c0 + v] : 0.0;
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const double (&acc)[V], double (&dot)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        double zv[V], pv[V], pn[V];
+        vload<double, V>(z + o, zv);
+        vload<double, V>(pold + o, pv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            pn[v] = zv[v] + bt[v] * pv[v];
+            dot[v] += pn[v] * acc[v];
+        }
+        vstore<double, V>(pnew + o, pn);
+        vstore<double, V>(q + o, acc);
     }
 };
 template <int K>
 struct MERes {  // d = B - A X; dot += d^2; R = d for the columns of `mask`
+    __device__ void prep(int) {}
     const double *b;
     double *out;
+    float *out32;  // FP32 copy of R (mixed precision) or null
     unsigned long long mask;
-    __device__ void operator()(int i, int c, double acc, double &dot) const {
-        const size_t o = (size_t)i * K + c;
-        const double d = b[o] - acc;
-        if (out && ((mask >> c) & 1ull)) out[o] = d;
-        dot += d * d;
+    template <int V>
+    __device__ void fin(int i, int c0, const double (&acc)[V], double (&dot)[V]) const {
+        const size_t o = (size_t)i * K + c0;
+        double bv[V];
+        vload<double, V>(b + o, bv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const double d = bv[v] - acc[v];
+            if (out && ((mask >> (c0 + v)) & 1ull)) {
+                out[o + v] = d;
+                if (out32) out32[o + v] = (float)d;
+            }
+            dot[v] += d * d;
+        }
     }
 };
 
@@ -229,7 +427,7 @@ struct MERes {  // d = B - A X; dot += d^2; R = d for the columns of `mask`
 // partials of ||b||^2 for them.
 template <int K>
 __global__ void __launch_bounds__(kBlock) mk_start(int n, SlotMap q, const double *__restrict__ B, int ldb,
-                                                   double *X, double *R, double *B0, double *P0, double *P1,
+                                                   double *X, double *R, float *R32, double *B0, double *P0, double *P1,
                                                    double rtol, int max_iter, double *pr2, MState *st) {
     constexpr int RPP = kBlock / K;
     const int c = threadIdx.x % K, grp = threadIdx.x / K;
@@ -244,6 +442,7 @@ __global__ void __launch_bounds__(kBlock) mk_start(int n, SlotMap q, const doubl
             const double bi = B[(size_t)i * ldb + qc];
             X[o] = 0.0;
             R[o] = bi;
+            if (R32) R32[o] = (float)bi;
             B0[o] = bi;
             P0[o] = 0.0;
             P1[o] = 0.0;
@@ -385,7 +584,8 @@ __global__ void __launch_bounds__(kRed) mk_fin_pq(const double *ppq, int nb, MSt
 // X += alpha P, R -= alpha Q for running columns; partials of ||R||^2
 template <int K>
 __global__ void __launch_bounds__(kBlock) mk_update(int n, const double *__restrict__ P, const double *__restrict__ Q,
-                                                    double *X, double *R, double *pr2, const MState *st) {
+                                                    double *X, double *R, float *R32, double *pr2,
+                                                    const MState *st) {
     constexpr int RPP = kBlock / K;
     const int c = threadIdx.x % K, grp = threadIdx.x / K;
     int r0, r1;
@@ -400,6 +600,7 @@ __global__ void __launch_bounds__(kBlock) mk_update(int n, const double *__restr
             X[o] = X[o] + a * P[o];
             ri = ri - a * Q[o];
             R[o] = ri;
+            if (R32) R32[o] = (float)ri;
         }
         acc += ri * ri;
     }
@@ -480,10 +681,9 @@ struct Engine {
     bool mixed = false;
     Pool pool;
     double *X = nullptr, *R = nullptr, *Bk = nullptr, *Z = nullptr, *P[2] = {nullptr, nullptr}, *Q = nullptr;
+    float *R32 = nullptr;  // FP32 copy of R kept by the PCG kernels (mixed precision)
     struct Lv {
         void *y = nullptr, *s = nullptr, *r = nullptr, *z = nullptr, *t = nullptr;
-        int grid = 8;   // row-kernel grid of A_l
-        int gridP = 8, gridR = 8;
     };
     std::vector<Lv> lv;
     double *pr2 = nullptr, *prz = nullptr, *ppq = nullptr, *ptmp = nullptr, *sc = nullptr;
@@ -504,12 +704,49 @@ struct Engine {
 
 namespace {
 
+int device_cus() {
+    static const int n = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                     hipSuccess)
+            v = 256;
+        return std::max(v, 8);
+    }();
+    return n;
+}
+
+// Grid of a block-row kernel on nr rows: one block per RPP rows, at most
+// the blocks the device holds at once (so the balanced row ranges all run
+// in one wave), a multiple of 8 (the XCD-aware block numbering).
+template <class T, int K, bool DOT, class G, class Ep>
+int rows_grid(int nr) {
+    static const int occ = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mk_rows<T, K, DOT, G, Ep>, kBlock, 0) != hipSuccess) b = 1;
+        return std::max(b, 1);
+    }();
+    constexpr int RPP = Lay<T, K>::RPP;
+    const int need = (nr + RPP - 1) / RPP;
+    const int cap = std::min(device_cus() * occ, kMGridMax) / 8 * 8;
+    return std::max(8, std::min((need + 7) / 8 * 8, std::max(cap, 8)));
+}
+
+// Launch on matrix M (values av) and return the grid used (forced_grid > 0:
+// that grid, for partial sums that must line up with another kernel's).
 template <class T, int K, class G, class Ep>
-void launch_mrows_any(int n, const int32_t *rp, const int32_t *ci, const T *av, int grid, hipStream_t s,
-                      const G &g, const Ep &e, double *partials, bool dot, unsigned long long pmask = ~0ull) {
-    if (dot) mk_rows<T, K, true><<<grid, kBlock, 0, s>>>(n, rp, ci, av, g, e, partials, pmask);
-    else mk_rows<T, K, false><<<grid, kBlock, 0, s>>>(n, rp, ci, av, g, e, partials, pmask);
+int launch_mrows_any(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials, bool dot,
+                     unsigned long long pmask = ~0ull, int forced_grid = 0) {
+    const int crows = chunk_rows<T, K>(M.nr, M.nnz);
+    int grid;
+    if (dot) {
+        grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, true, G, Ep>(M.nr);
+        mk_rows<T, K, true><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
+    } else {
+        grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, false, G, Ep>(M.nr);
+        mk_rows<T, K, false><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
+    }
     HIPC(hipGetLastError());
+    return grid;
 }
 
 template <class T>
@@ -534,47 +771,53 @@ const float *vawd<float>(const Level &L) { return L.awd32; }
 // One V-cycle on the K-column block R -> Z (level-0 post-smoothing writes
 // the per-column r.z partials when dot).
 template <class T, int K>
-void mvcycle(Engine &E, bool dot, hipStream_t s) {
+int mvcycle(Engine &E, bool dot, hipStream_t s) {
     Hier &h = *E.h;
     const int L = h.nlev - 1;
     if (L == 0) {  // one level: direct solve, then the r.z partials
         mk_coarse<double, K><<<(h.nL + kBlock / K - 1) / (kBlock / K), kBlock, 0, s>>>(h.nL, h.cinv, E.R, E.Z);
         if (dot) mk_dot<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.R, E.Z, E.prz);
         HIPC(hipGetLastError());
-        return;
+        return E.nb_vec;
     }
     auto Tp = [](void *p) { return static_cast<T *>(p); };
     T *sv[CAMG_MAX_LEVELS] = {};
+    int g0 = 0;  // grid of the level-0 post-smoothing kernel (its r.z partials)
     for (int l = 0; l < L; ++l) {
         Level &Lv = h.lev[l];
         Engine::Lv &B = E.lv[l];
         const int nl = Lv.A.nr;
         T *s0 = Tp(B.s), *t0 = Tp(B.t), *r0 = Tp(B.r);
-        if (l == 0)
-            launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vawd<T>(Lv), B.grid, s, MGather<T, K, double>{E.R},
-                                   MEPre<T, K, double>{vwd<T>(Lv), E.R, s0, r0}, nullptr, false);
+        if (l == 0) {
+            if constexpr (sizeof(T) == 4)  // the FP32 copy of R holds exactly the values (T) R
+                launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K, float>{E.R32},
+                                       MEPre<T, K, float>{vwd<T>(Lv), E.R32, s0, r0}, nullptr, false);
+            else
+                launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K, double>{E.R},
+                                       MEPre<T, K, double>{vwd<T>(Lv), E.R, s0, r0}, nullptr, false);
+        }
         else
-            launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vawd<T>(Lv), B.grid, s, MGather<T, K>{Tp(B.y)},
+            launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K>{Tp(B.y)},
                                    MEPre<T, K, T>{vwd<T>(Lv), Tp(B.y), s0, r0}, nullptr, false);
         for (int it = 1; it < h.prm.nu_pre; ++it) {
             if (l == 0)
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false);
             else
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false);
             std::swap(s0, t0);
         }
         if (h.prm.nu_pre > 1) {
             if (l == 0)
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEResid<T, K, double>{E.R, r0}, nullptr, false);
             else
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEResid<T, K, T>{Tp(B.y), r0}, nullptr, false);
         }
         sv[l] = s0;
-        launch_mrows_any<T, K>(Lv.R.nr, Lv.R.rp, Lv.R.ci, vvals<T>(Lv.R), B.gridR, s, MGather<T, K>{r0},
+        launch_mrows_any<T, K>(Lv.R, vvals<T>(Lv.R), s, MGather<T, K>{r0},
                                MESpmv<T, K, false>{Tp(E.lv[l + 1].y)}, nullptr, false);
     }
     mk_coarse<T, K><<<(h.nL + kBlock / K - 1) / (kBlock / K), kBlock, 0, s>>>(h.nL, h.cinv, Tp(E.lv[L].y),
@@ -584,26 +827,27 @@ void mvcycle(Engine &E, bool dot, hipStream_t s) {
         Level &Lv = h.lev[l];
         Engine::Lv &B = E.lv[l];
         const int nl = Lv.A.nr;
-        launch_mrows_any<T, K>(Lv.P.nr, Lv.P.rp, Lv.P.ci, vvals<T>(Lv.P), B.gridP, s, MGather<T, K>{Tp(E.lv[l + 1].z)},
+        launch_mrows_any<T, K>(Lv.P, vvals<T>(Lv.P), s, MGather<T, K>{Tp(E.lv[l + 1].z)},
                                MESpmv<T, K, true>{sv[l]}, nullptr, false);
         T *s0 = sv[l];
         T *t0 = (s0 == Tp(B.s)) ? Tp(B.t) : Tp(B.s);
         for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
             if (l == 0)
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false);
             else
-                launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+                launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                        MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false);
             std::swap(s0, t0);
         }
         if (l == 0)
-            launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
-                                   MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0, E.Z}, E.prz, dot);
+            g0 = launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
+                                        MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0, E.Z}, E.prz, dot);
         else
-            launch_mrows_any<T, K>(nl, Lv.A.rp, Lv.A.ci, vvals<T>(Lv.A), B.grid, s, MGather<T, K>{s0},
+            launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                    MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, Tp(B.z)}, nullptr, false);
     }
+    return g0;
 }
 
 template <int K>
@@ -612,16 +856,14 @@ void miteration(Engine &E, int par, hipStream_t s) {
     const Csr &A = h.lev[0].A;
     mk_check<K><<<1, kRed, 0, s>>>(E.pr2, E.nb_vec, E.st, E.hist, E.cap, E.hflag_dev);
     HIPC(hipGetLastError());
-    if (E.mixed) mvcycle<float, K>(E, true, s);
-    else mvcycle<double, K>(E, true, s);
-    // the r.z partials come from a kernel on the n_0 rows: lv[0].grid == nb_vec blocks
-    mk_fin_rz<K><<<1, kRed, 0, s>>>(E.prz, E.nb_vec, E.st);
+    const int nrz = E.mixed ? mvcycle<float, K>(E, true, s) : mvcycle<double, K>(E, true, s);
+    mk_fin_rz<K><<<1, kRed, 0, s>>>(E.prz, nrz, E.st);
     const double *beta =
         reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
-    launch_mrows_any<double, K>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s, MGDir<K>{E.Z, E.P[par], beta},
-                                MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true);
-    mk_fin_pq<K><<<1, kRed, 0, s>>>(E.ppq, E.lv[0].grid, E.st);
-    mk_update<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.P[1 - par], E.Q, E.X, E.R, E.pr2, E.st);
+    const int npq = launch_mrows_any<double, K>(A, A.v, s, MGDir<K>{E.Z, E.P[par], beta},
+                                                MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true);
+    mk_fin_pq<K><<<1, kRed, 0, s>>>(E.ppq, npq, E.st);
+    mk_update<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.P[1 - par], E.Q, E.X, E.R, E.R32, E.pr2, E.st);
     HIPC(hipGetLastError());
 }
 
@@ -690,7 +932,7 @@ Engine::~Engine() {
 int64_t engine_footprint(const Hier &h, int K) {
     const int64_t n = h.lev[0].A.nr;
     const bool mixed = h.prm.precision == CAMG_MIXED_FP32;
-    int64_t b = 7 * n * K * 8;  // X, R, B, Z, P0, P1, Q
+    int64_t b = 7 * n * K * 8 + (mixed ? 4 * n * K : 0);  // X, R, B, Z, P0, P1, Q (+ FP32 R)
     for (int l = 0; l < h.nlev; ++l) b += 5 * (int64_t)h.lev[l].A.nr * K * (mixed ? 4 : 8);
     b += 4 * (int64_t)kMGridMax * K * 8 + sizeof(MState);
     return b;
@@ -712,6 +954,7 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     E->P[0] = E->pool.alloc<double>(blk);
     E->P[1] = E->pool.alloc<double>(blk);
     E->Q = E->pool.alloc<double>(blk);
+    if (E->mixed) E->R32 = E->pool.alloc<float>(blk);
     const size_t vb = E->mixed ? 4 : 8;
     E->lv.resize(h.nlev);
     for (int l = 0; l < h.nlev; ++l) {
@@ -725,11 +968,6 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
         B.s = E->pool.raw(nb);
         B.t = E->pool.raw(nb);
         B.r = E->pool.raw(nb);
-        B.grid = mgrid(L.A.nr, K);
-        if (l < h.nlev - 1) {
-            B.gridP = mgrid(L.P.nr, K);
-            B.gridR = mgrid(L.R.nr, K);
-        }
     }
     E->nb_vec = mgrid(E->n, K);
     E->pr2 = E->pool.alloc<double>((size_t)kMGridMax * K);
@@ -744,6 +982,7 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     // are computed along but never read; their values never mix with others)
     HIPC(hipMemsetAsync(E->st, 0, sizeof(MState), s));
     for (double *p : {E->X, E->R, E->Bk, E->Z, E->P[0], E->P[1], E->Q}) HIPC(hipMemsetAsync(p, 0, blk * 8, s));
+    if (E->R32) HIPC(hipMemsetAsync(E->R32, 0, blk * 4, s));
     for (auto &B : E->lv)
         for (void *p : {B.y, B.s, B.t, B.r, B.z})
             if (p) HIPC(hipMemsetAsync(p, 0, (size_t)h.lev[&B - &E->lv[0]].A.nr * K * vb, s));
@@ -757,7 +996,7 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
 
 void engine_start_slots(Engine &E, const SlotMap &q, const double *B, int ldb, double rtol, int max_iter,
                         hipStream_t s) {
-    CAMG_K_SWITCH(E.K, (mk_start<KK><<<E.nb_vec, kBlock, 0, s>>>(E.n, q, B, ldb, E.X, E.R, E.Bk, E.P[0], E.P[1], rtol,
+    CAMG_K_SWITCH(E.K, (mk_start<KK><<<E.nb_vec, kBlock, 0, s>>>(E.n, q, B, ldb, E.X, E.R, E.R32, E.Bk, E.P[0], E.P[1], rtol,
                                                                   max_iter, E.pr2, E.st)));
     HIPC(hipGetLastError());
     E.hflag[0] = 1;
@@ -782,10 +1021,10 @@ void engine_launch(Engine &E, int iters, hipStream_t s) {
 void engine_snapshot(Engine &E, bool true_res, EngineSnap *snap, hipStream_t s) {
     if (true_res) {
         const Csr &A = E.h->lev[0].A;
-        CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s,
-                                                           MGather<double, KK>{E.X}, MERes<KK>{E.Bk, nullptr, 0ull},
-                                                           E.ptmp, true)));
-        CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, E.lv[0].grid, E.sc)));
+        int nb = 0;
+        CAMG_K_SWITCH(E.K, (nb = launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
+                                                                MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true)));
+        CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, nb, E.sc)));
     }
     CAMG_K_SWITCH(E.K, (mk_snap<KK><<<1, 64, 0, s>>>(E.st, true_res ? E.sc : nullptr, snap)));
     HIPC(hipGetLastError());
@@ -846,10 +1085,10 @@ void engine_slot_state(Engine &E, int32_t *iters, int32_t *done, int32_t *status
 // true ||b - A x|| / ||b|| of every slot (host array of K)
 void engine_true_res(Engine &E, double *rel, hipStream_t s) {
     const Csr &A = E.h->lev[0].A;
-    CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s, MGather<double, KK>{E.X},
-                                                       MERes<KK>{E.Bk, nullptr, 0ull}, E.ptmp, true)));
-    double *part = E.ptmp;
-    CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(part, E.lv[0].grid, E.sc)));
+    int nb = 0;
+    CAMG_K_SWITCH(E.K, (nb = launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
+                                                            MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true)));
+    CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, nb, E.sc)));
     HIPC(hipGetLastError());
     double t2[kMaxSlots];
     MState st;
@@ -889,8 +1128,8 @@ void engine_destroy(Engine *e) { delete e; }
 void engine_replace(Engine &E, unsigned long long mask, hipStream_t s) {
     if (!mask) return;
     const Csr &A = E.h->lev[0].A;
-    CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A.nr, A.rp, A.ci, A.v, E.lv[0].grid, s, MGather<double, KK>{E.X},
-                                                       MERes<KK>{E.Bk, E.R, mask}, E.pr2, true, mask)));
+    CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
+                                                       MERes<KK>{E.Bk, E.R, E.R32, mask}, E.pr2, true, mask, E.nb_vec)));
     CAMG_K_SWITCH(E.K, (mk_restart<KK><<<1, 64, 0, s>>>(E.st, mask)));
     HIPC(hipGetLastError());
     E.hflag[0] = 1;
