@@ -270,9 +270,14 @@ camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_
 /*
  * Options of a handle.  CAMG_OPT_GRAPH (default 1): run each PCG iteration
  * as a captured HIP graph (0: launch the kernels one by one; the results
- * are bitwise the same).
+ * are bitwise the same).  CAMG_OPT_AUTOTUNE (default 0): multi-RHS engines
+ * created on the handle afterwards (camg_solve_multi_dev, camg_engine_create,
+ * camg_server_add) time the candidate schedules of their row kernels on
+ * every matrix of the hierarchy (entries per unrolled step, LDS chunk, grid)
+ * and keep the fastest, cached per matrix signature for the process; the
+ * results are bitwise the same as untuned.
  */
-enum { CAMG_OPT_GRAPH = 1 };
+enum { CAMG_OPT_GRAPH = 1, CAMG_OPT_AUTOTUNE = 2 };
 camg_status camg_set_option(camg_handle h, int32_t option, int64_t value);
 
 /* Release the hierarchy and all its device memory.  NULL is ignored. */

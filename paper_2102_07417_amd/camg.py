@@ -31,6 +31,7 @@ EXPORTED = [
     "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy",
 ]
 OPT_GRAPH = 1
+OPT_AUTOTUNE = 2
 
 
 class camg_params(C.Structure):
@@ -490,6 +491,9 @@ class Solver:
 
     def vcycle_dev(self, d_y, d_z, stream=None):
         _check(camg_vcycle_dev(self.h, d_y, d_z, stream))
+
+    def set_option(self, option, value):
+        _check(camg_set_option(self.h, option, value))
 
     def solve_multi_dev(self, d_B, d_X, rtol=1e-8, hist_cap=0, stream=None):
         """d_B, d_X: n-by-k row-major float64 CUDA tensors."""

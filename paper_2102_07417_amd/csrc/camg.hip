@@ -902,6 +902,9 @@ camg_status camg_set_option(camg_handle hh, int32_t option, int64_t value) {
             h->use_graph = value != 0;
             h->graph_ok = false;
             break;
+        case CAMG_OPT_AUTOTUNE:
+            h->autotune = value != 0;
+            break;
         default: fail(CAMG_E_ARG, "unknown option");
         }
     });

@@ -128,6 +128,7 @@ struct Hier {
     // slot 0 the whole iteration, slots 1 and 2 the parts before and after
     // the level-0 post-smoothing (used while kernel timing is on)
     bool use_graph = true;
+    bool autotune = false;  // engines created on the handle tune their row schedules
     bool graph_ok = false;
     bool graph_prof = false;
     hipGraphExec_t gexec[3][2] = {};

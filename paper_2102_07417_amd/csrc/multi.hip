@@ -21,7 +21,10 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "devutil.hpp"
@@ -169,12 +172,11 @@ __device__ __forceinline__ void block_col_sum_v(const double (&d)[V], double *pa
 constexpr int kStage = 1024;  // CSR entries staged in LDS per chunk
 constexpr int kChunkRowsMax = 512;
 
-// One row: acc(c0 .. c0+V) = sum_j a_ij g(j, .).  Entries G::kU at a time,
+// One row: acc(c0 .. c0+V) = sum_j a_ij g(j, .).  Entries U at a time,
 // clamped to the row so all loads and gathers are unconditional and in
 // flight together; products added in CSR order, padding skipped.
-template <class T, int V, class CI, class AV, class G>
+template <class T, int V, int U, class CI, class AV, class G>
 __device__ __forceinline__ void row_acc(int e0, int e1, const CI *ci, const AV *av, const G &g, int c0, T (&acc)[V]) {
-    constexpr int U = G::kU;
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = T(0);
     for (int eb = e0; eb < e1; eb += U) {
@@ -202,7 +204,7 @@ __device__ __forceinline__ void row_acc(int e0, int e1, const CI *ci, const AV *
 // rows in chunks of `crows` rows; a chunk whose entries fit is first staged
 // in LDS (indices, values and row pointers, coalesced), so the group's
 // lanes read each entry from LDS; a longer chunk reads them from memory.
-template <class T, int K, bool DOT, class G, class E>
+template <class T, int K, bool DOT, int U, class G, class E>
 __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const T *__restrict__ av, G g, E epi, double *partials,
                                                   unsigned long long pmask, int crows) {
@@ -223,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restri
     for (int a = r0; a < r1; a += crows) {
         const int b = min(a + crows, r1);
         const int E0 = rp[a], E1 = rp[b];
-        if (E1 - E0 <= kStage) {
+        if (E1 - E0 <= kStage && b - a <= kChunkRowsMax) {
             __syncthreads();  // the previous chunk is done with the stage
             for (int t = threadIdx.x; t < E1 - E0; t += kBlock) {
                 s_ci[t] = ci[E0 + t];
@@ -233,13 +235,13 @@ __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restri
             __syncthreads();
             for (int i = a + grp; i < b; i += RPP) {
                 T acc[V];
-                row_acc<T, V>(s_rp[i - a], s_rp[i - a + 1], s_ci, s_av, g, c0, acc);
+                row_acc<T, V, U>(s_rp[i - a], s_rp[i - a + 1], s_ci, s_av, g, c0, acc);
                 epi.template fin<V>(i, c0, acc, dot);
             }
         } else {
             for (int i = a + grp; i < b; i += RPP) {
                 T acc[V];
-                row_acc<T, V>(rp[i], rp[i + 1], ci, av, g, c0, acc);
+                row_acc<T, V, U>(rp[i], rp[i + 1], ci, av, g, c0, acc);
                 epi.template fin<V>(i, c0, acc, dot);
             }
         }
@@ -674,6 +676,18 @@ int mgrid(int n, int K) {
 }  // namespace
 
 // ======================================================================= engine
+// Schedule of the block-row kernels on one matrix: entries per unrolled
+// step (0: the kernel's default), rows per LDS chunk (0: from the mean row
+// length; -1: entries read from memory), grid of the kernels without
+// partial sums (0: the occupancy rule).  Every schedule gives bitwise the
+// same results: rows and products are added in the same order, and the
+// grid (row partition) of a kernel producing partial sums never changes.
+struct RowSched {
+    int u = 0;
+    int crows = 0;
+    int grid = 0;
+};
+
 struct Engine {
     Hier *h = nullptr;
     int K = 0;
@@ -699,6 +713,11 @@ struct Engine {
     bool graph_ok = false;
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;
+    std::map<std::tuple<const void *, int, int>, RowSched> sched;  // (matrix, value bytes, kind)
+    RowSched rs(const Csr &M, int vbytes, int kind) const {
+        auto it = sched.find(std::make_tuple((const void *)&M, vbytes, kind));
+        return it == sched.end() ? RowSched{} : it->second;
+    }
     ~Engine();
 };
 
@@ -718,11 +737,12 @@ int device_cus() {
 // Grid of a block-row kernel on nr rows: one block per RPP rows, at most
 // the blocks the device holds at once (so the balanced row ranges all run
 // in one wave), a multiple of 8 (the XCD-aware block numbering).
-template <class T, int K, bool DOT, class G, class Ep>
+template <class T, int K, bool DOT, int U, class G, class Ep>
 int rows_grid(int nr) {
     static const int occ = [] {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mk_rows<T, K, DOT, G, Ep>, kBlock, 0) != hipSuccess) b = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mk_rows<T, K, DOT, U, G, Ep>, kBlock, 0) != hipSuccess)
+            b = 1;
         return std::max(b, 1);
     }();
     constexpr int RPP = Lay<T, K>::RPP;
@@ -731,22 +751,31 @@ int rows_grid(int nr) {
     return std::max(8, std::min((need + 7) / 8 * 8, std::max(cap, 8)));
 }
 
-// Launch on matrix M (values av) and return the grid used (forced_grid > 0:
-// that grid, for partial sums that must line up with another kernel's).
-template <class T, int K, class G, class Ep>
-int launch_mrows_any(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials, bool dot,
-                     unsigned long long pmask = ~0ull, int forced_grid = 0) {
-    const int crows = chunk_rows<T, K>(M.nr, M.nnz);
-    int grid;
-    if (dot) {
-        grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, true, G, Ep>(M.nr);
-        mk_rows<T, K, true><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
-    } else {
-        grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, false, G, Ep>(M.nr);
-        mk_rows<T, K, false><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
-    }
+template <class T, int K, bool DOT, int U, class G, class Ep>
+int launch_mrows_u(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials,
+                   unsigned long long pmask, int forced_grid, const RowSched &rs) {
+    int crows = rs.crows > 0 ? rs.crows : chunk_rows<T, K>(M.nr, M.nnz);
+    if (rs.crows < 0) crows = std::max(M.nr, 1);  // one chunk per block: entries read from memory
+    int grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, DOT, U, G, Ep>(M.nr);
+    if (!DOT && forced_grid <= 0 && rs.grid > 0) grid = rs.grid;
+    mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
     HIPC(hipGetLastError());
     return grid;
+}
+
+// Launch on matrix M (values av) with schedule rs and return the grid used
+// (forced_grid > 0: that grid, for partial sums that must line up with
+// another kernel's; kernels with partial sums never take a tuned grid).
+template <class T, int K, class G, class Ep>
+int launch_mrows_any(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials, bool dot,
+                     unsigned long long pmask = ~0ull, int forced_grid = 0, const RowSched &rs = RowSched{}) {
+    const int u = rs.u ? rs.u : G::kU;
+    if (dot) {
+        if (u == 4) return launch_mrows_u<T, K, true, 4>(M, av, s, g, e, partials, pmask, forced_grid, rs);
+        return launch_mrows_u<T, K, true, 8>(M, av, s, g, e, partials, pmask, forced_grid, rs);
+    }
+    if (u == 4) return launch_mrows_u<T, K, false, 4>(M, av, s, g, e, partials, pmask, forced_grid, rs);
+    return launch_mrows_u<T, K, false, 8>(M, av, s, g, e, partials, pmask, forced_grid, rs);
 }
 
 template <class T>
@@ -786,39 +815,38 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
     for (int l = 0; l < L; ++l) {
         Level &Lv = h.lev[l];
         Engine::Lv &B = E.lv[l];
-        const int nl = Lv.A.nr;
         T *s0 = Tp(B.s), *t0 = Tp(B.t), *r0 = Tp(B.r);
         if (l == 0) {
             if constexpr (sizeof(T) == 4)  // the FP32 copy of R holds exactly the values (T) R
                 launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K, float>{E.R32},
-                                       MEPre<T, K, float>{vwd<T>(Lv), E.R32, s0, r0}, nullptr, false);
+                                       MEPre<T, K, float>{vwd<T>(Lv), E.R32, s0, r0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             else
                 launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K, double>{E.R},
-                                       MEPre<T, K, double>{vwd<T>(Lv), E.R, s0, r0}, nullptr, false);
+                                       MEPre<T, K, double>{vwd<T>(Lv), E.R, s0, r0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
         }
         else
             launch_mrows_any<T, K>(Lv.A, vawd<T>(Lv), s, MGather<T, K>{Tp(B.y)},
-                                   MEPre<T, K, T>{vwd<T>(Lv), Tp(B.y), s0, r0}, nullptr, false);
+                                   MEPre<T, K, T>{vwd<T>(Lv), Tp(B.y), s0, r0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
         for (int it = 1; it < h.prm.nu_pre; ++it) {
             if (l == 0)
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false);
+                                       MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             else
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false);
+                                       MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             std::swap(s0, t0);
         }
         if (h.prm.nu_pre > 1) {
             if (l == 0)
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEResid<T, K, double>{E.R, r0}, nullptr, false);
+                                       MEResid<T, K, double>{E.R, r0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             else
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEResid<T, K, T>{Tp(B.y), r0}, nullptr, false);
+                                       MEResid<T, K, T>{Tp(B.y), r0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
         }
         sv[l] = s0;
         launch_mrows_any<T, K>(Lv.R, vvals<T>(Lv.R), s, MGather<T, K>{r0},
-                               MESpmv<T, K, false>{Tp(E.lv[l + 1].y)}, nullptr, false);
+                               MESpmv<T, K, false>{Tp(E.lv[l + 1].y)}, nullptr, false, ~0ull, 0, E.rs(Lv.R, (int)sizeof(T), 0));
     }
     mk_coarse<T, K><<<(h.nL + kBlock / K - 1) / (kBlock / K), kBlock, 0, s>>>(h.nL, h.cinv, Tp(E.lv[L].y),
                                                                               Tp(E.lv[L].z));
@@ -826,26 +854,25 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
     for (int l = L - 1; l >= 0; --l) {
         Level &Lv = h.lev[l];
         Engine::Lv &B = E.lv[l];
-        const int nl = Lv.A.nr;
         launch_mrows_any<T, K>(Lv.P, vvals<T>(Lv.P), s, MGather<T, K>{Tp(E.lv[l + 1].z)},
-                               MESpmv<T, K, true>{sv[l]}, nullptr, false);
+                               MESpmv<T, K, true>{sv[l]}, nullptr, false, ~0ull, 0, E.rs(Lv.P, (int)sizeof(T), 0));
         T *s0 = sv[l];
         T *t0 = (s0 == Tp(B.s)) ? Tp(B.t) : Tp(B.s);
         for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
             if (l == 0)
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false);
+                                       MEPost<T, K, double, T>{vwd<T>(Lv), E.R, s0, t0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             else
                 launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                       MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false);
+                                       MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             std::swap(s0, t0);
         }
         if (l == 0)
             g0 = launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                        MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0, E.Z}, E.prz, dot);
+                                        MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0, E.Z}, E.prz, dot, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
         else
             launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                   MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, Tp(B.z)}, nullptr, false);
+                                   MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, Tp(B.z)}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
     }
     return g0;
 }
@@ -861,7 +888,7 @@ void miteration(Engine &E, int par, hipStream_t s) {
     const double *beta =
         reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
     const int npq = launch_mrows_any<double, K>(A, A.v, s, MGDir<K>{E.Z, E.P[par], beta},
-                                                MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true);
+                                                MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true, ~0ull, 0, E.rs(A, 8, 1));
     mk_fin_pq<K><<<1, kRed, 0, s>>>(E.ppq, npq, E.st);
     mk_update<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.P[1 - par], E.Q, E.X, E.R, E.R32, E.pr2, E.st);
     HIPC(hipGetLastError());
@@ -919,6 +946,100 @@ void m_launch_iteration(Engine &E, hipStream_t s) {
     if (E.use_graph && E.graph_ok) HIPC(hipGraphLaunch(E.gexec[E.par], s));
     else CAMG_K_SWITCH(E.K, miteration<KK>(E, E.par, s));
     E.par ^= 1;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Picks, per matrix of the hierarchy, the block-row schedule (entries per
+// unrolled step, LDS chunk, grid) that runs fastest here, timing every
+// candidate with HIP events when the engine is created; the choice is
+// cached per matrix signature for the rest of the process.  Schedules never
+// change results, so a tuned engine computes bitwise what an untuned one
+// does.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int64_t, int, int, int>, RowSched> g_tune_cache;
+
+template <class T, int K, class G, class Ep>
+void tune_matrix(Engine &E, const Csr &M, const T *av, const G &g, const Ep &ep, double *partials, bool dot,
+                 int kind, hipStream_t s) {
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, M.nr, M.nc, M.nnz, K, (int)sizeof(T), kind);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            E.sched[std::make_tuple((const void *)&M, (int)sizeof(T), kind)] = it->second;
+            return;
+        }
+    }
+    constexpr int RPP = Lay<T, K>::RPP;
+    const int def = chunk_rows<T, K>(M.nr, M.nnz);
+    const int rule = launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot);  // warm; the rule grid
+    std::vector<RowSched> cand;
+    for (int u : {4, 8})
+        for (int cr : {0, -1, std::max(RPP, def / 2 / RPP * RPP)})
+            for (int gd : {0, std::max(8, rule / 2 / 8 * 8)}) {
+                if (gd != 0 && (dot || gd == rule)) continue;
+                cand.push_back(RowSched{u, cr, gd});
+            }
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } eg{e0, e1};
+    RowSched best{};
+    float best_ms = 1e30f;
+    for (const RowSched &c : cand) {
+        launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot, ~0ull, 0, c);
+        HIPC(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot, ~0ull, 0, c);
+        HIPC(hipEventRecord(e1, s));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    E.sched[std::make_tuple((const void *)&M, (int)sizeof(T), kind)] = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+}
+
+template <class T, int K>
+void autotune_t(Engine &E, hipStream_t s) {
+    Hier &h = *E.h;
+    const int L = h.nlev - 1;
+    auto Tp = [](void *p) { return static_cast<T *>(p); };
+    for (int l = 0; l < L; ++l) {
+        const Level &Lv = h.lev[l];
+        Engine::Lv &B = E.lv[l];
+        tune_matrix<T, K>(E, Lv.A, vvals<T>(Lv.A), MGather<T, K>{Tp(B.s)}, MESpmv<T, K, false>{Tp(B.t)}, nullptr,
+                          false, 0, s);
+        tune_matrix<T, K>(E, Lv.R, vvals<T>(Lv.R), MGather<T, K>{Tp(B.r)}, MESpmv<T, K, false>{Tp(E.lv[l + 1].y)},
+                          nullptr, false, 0, s);
+        tune_matrix<T, K>(E, Lv.P, vvals<T>(Lv.P), MGather<T, K>{Tp(E.lv[l + 1].z)}, MESpmv<T, K, false>{Tp(B.t)},
+                          nullptr, false, 0, s);
+    }
+    const Csr &A = h.lev[0].A;
+    if (sizeof(T) != 8 || L == 0)
+        tune_matrix<double, K>(E, A, A.v, MGather<double, K>{E.X}, MESpmv<double, K, false>{E.Q}, nullptr, false, 0,
+                               s);
+    const double *beta =
+        reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
+    tune_matrix<double, K>(E, A, A.v, MGDir<K>{E.Z, E.P[0], beta}, MEDir<K>{E.Z, E.P[0], beta, E.P[1], E.Q}, E.ptmp,
+                           true, 1, s);
+}
+
+void engine_autotune(Engine &E, hipStream_t s) {
+    if (E.mixed) {
+        CAMG_K_SWITCH(E.K, autotune_t<float, KK>(E, s));
+    } else {
+        CAMG_K_SWITCH(E.K, autotune_t<double, KK>(E, s));
+    }
 }
 
 }  // namespace
@@ -990,6 +1111,7 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     HIPC(hipHostMalloc((void **)&E->hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
     HIPC(hipHostGetDevicePointer((void **)&E->hflag_dev, E->hflag, 0));
     E->hflag[0] = 0;
+    if (h.autotune) engine_autotune(*E, s);
     HIPC(hipStreamSynchronize(s));
     return E.release();
 }
@@ -1023,7 +1145,8 @@ void engine_snapshot(Engine &E, bool true_res, EngineSnap *snap, hipStream_t s) 
         const Csr &A = E.h->lev[0].A;
         int nb = 0;
         CAMG_K_SWITCH(E.K, (nb = launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
-                                                                MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true)));
+                                                                MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true,
+                                                                ~0ull, 0, E.rs(A, 8, 0))));
         CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, nb, E.sc)));
     }
     CAMG_K_SWITCH(E.K, (mk_snap<KK><<<1, 64, 0, s>>>(E.st, true_res ? E.sc : nullptr, snap)));
@@ -1087,7 +1210,8 @@ void engine_true_res(Engine &E, double *rel, hipStream_t s) {
     const Csr &A = E.h->lev[0].A;
     int nb = 0;
     CAMG_K_SWITCH(E.K, (nb = launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
-                                                            MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true)));
+                                                            MERes<KK>{E.Bk, nullptr, nullptr, 0ull}, E.ptmp, true,
+                                                            ~0ull, 0, E.rs(A, 8, 0))));
     CAMG_K_SWITCH(E.K, (mk_sum<KK><<<1, kRed, 0, s>>>(E.ptmp, nb, E.sc)));
     HIPC(hipGetLastError());
     double t2[kMaxSlots];
@@ -1129,7 +1253,8 @@ void engine_replace(Engine &E, unsigned long long mask, hipStream_t s) {
     if (!mask) return;
     const Csr &A = E.h->lev[0].A;
     CAMG_K_SWITCH(E.K, (launch_mrows_any<double, KK>(A, A.v, s, MGather<double, KK>{E.X},
-                                                       MERes<KK>{E.Bk, E.R, E.R32, mask}, E.pr2, true, mask, E.nb_vec)));
+                                                       MERes<KK>{E.Bk, E.R, E.R32, mask}, E.pr2, true, mask, E.nb_vec,
+                                                       E.rs(A, 8, 0))));
     CAMG_K_SWITCH(E.K, (mk_restart<KK><<<1, 64, 0, s>>>(E.st, mask)));
     HIPC(hipGetLastError());
     E.hflag[0] = 1;

@@ -366,3 +366,21 @@ def test_engine_column_alone_equals_in_mix(camg):
     assert torch.equal(xa, xb)
     e.close()
     s.close()
+
+
+def test_multi_rhs_autotuned_schedules_are_bitwise_equal(camg):
+    """The autotuner only picks among schedules that add the same products in
+    the same order: tuned and untuned engines give identical bits."""
+    for prec in (camg.FP64, camg.MIXED_FP32):
+        A = PB.lognormal3d(20, 2.0)
+        B = torch.from_numpy(PB.rhs_block(A.n, 8)).to("cuda:0")
+        outs = []
+        for tune in (0, 1):
+            s = camg.Solver(A, precision=prec)
+            s.set_option(camg.OPT_AUTOTUNE, tune)
+            X = torch.zeros_like(B)
+            r = s.solve_multi_dev(B, X, rtol=1e-8)
+            assert r.status == camg.OK
+            outs.append(X)
+            s.close()
+        assert torch.equal(outs[0], outs[1])
