@@ -200,14 +200,19 @@ __device__ __forceinline__ void row_acc(int e0, int e1, const CI *ci, const AV *
     }
 }
 
-// out(i, .) = sum_j a_ij g(j, .); epi(i, c0, acc, dot).  Each block walks its
-// rows in chunks of `crows` rows; a chunk whose entries fit is first staged
-// in LDS (indices, values and row pointers, coalesced), so the group's
-// lanes read each entry from LDS; a longer chunk reads them from memory.
+// out(i, .) = sum_j a_ij g(j, .); epi(i, c0, acc, dot).  The rows are cut
+// into chunks of `crows` rows; each XCD takes a contiguous eighth of the
+// chunks and its blocks sweep it together, block j taking chunks j, j + B,
+// ... (B blocks per XCD), so the chunks in flight on an XCD are neighbours
+// and the rows they gather (a stencil's nearby rows) are shared through its
+// L2 instead of being fetched again from the memory-side cache.  With
+// `stage`, a chunk whose entries fit is first copied to LDS (indices,
+// values, row pointers, coalesced) and the group's lanes read the entries
+// there; otherwise they read them from memory.
 template <class T, int K, bool DOT, int U, class G, class E>
 __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const T *__restrict__ av, G g, E epi, double *partials,
-                                                  unsigned long long pmask, int crows) {
+                                                  unsigned long long pmask, int crows, int stage) {
     using L = Lay<T, K>;
     constexpr int V = L::V, LPR = L::LPR, RPP = L::RPP;
     __shared__ int32_t s_ci[kStage];
@@ -217,15 +222,16 @@ __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restri
     const int c0 = lane * V;
     g.prep(c0);
     epi.prep(c0);
-    int r0, r1;
-    block_rows(n, r0, r1);
+    const int nch = (n + crows - 1) / crows;
+    const int xcd = blockIdx.x & 7, bx = gridDim.x >> 3, jb = blockIdx.x >> 3;
+    const int ch0 = (int)((int64_t)xcd * nch / 8), ch1 = (int)((int64_t)(xcd + 1) * nch / 8);
     double dot[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[v] = 0.0;
-    for (int a = r0; a < r1; a += crows) {
-        const int b = min(a + crows, r1);
+    for (int ch = ch0 + jb; ch < ch1; ch += bx) {
+        const int a = ch * crows, b = min(a + crows, n);
         const int E0 = rp[a], E1 = rp[b];
-        if (E1 - E0 <= kStage && b - a <= kChunkRowsMax) {
+        if (stage && E1 - E0 <= kStage && b - a <= kChunkRowsMax) {
             __syncthreads();  // the previous chunk is done with the stage
             for (int t = threadIdx.x; t < E1 - E0; t += kBlock) {
                 s_ci[t] = ci[E0 + t];
@@ -677,15 +683,16 @@ int mgrid(int n, int K) {
 
 // ======================================================================= engine
 // Schedule of the block-row kernels on one matrix: entries per unrolled
-// step (0: the kernel's default), rows per LDS chunk (0: from the mean row
-// length; -1: entries read from memory), grid of the kernels without
-// partial sums (0: the occupancy rule).  Every schedule gives bitwise the
+// step (0: the kernel's default), rows per chunk (0: from the mean row
+// length), grid of the kernels without partial sums (0: the occupancy
+// rule), whether chunks are staged in LDS.  Every schedule gives bitwise the
 // same results: rows and products are added in the same order, and the
 // grid (row partition) of a kernel producing partial sums never changes.
 struct RowSched {
     int u = 0;
     int crows = 0;
     int grid = 0;
+    int stage = 1;
 };
 
 struct Engine {
@@ -734,19 +741,17 @@ int device_cus() {
     return n;
 }
 
-// Grid of a block-row kernel on nr rows: one block per RPP rows, at most
-// the blocks the device holds at once (so the balanced row ranges all run
-// in one wave), a multiple of 8 (the XCD-aware block numbering).
+// Grid of a block-row kernel on nr rows: one block per chunk, at most the
+// blocks the device holds at once, a multiple of 8 (one share per XCD).
 template <class T, int K, bool DOT, int U, class G, class Ep>
-int rows_grid(int nr) {
+int rows_grid(int nr, int crows) {
     static const int occ = [] {
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mk_rows<T, K, DOT, U, G, Ep>, kBlock, 0) != hipSuccess)
             b = 1;
         return std::max(b, 1);
     }();
-    constexpr int RPP = Lay<T, K>::RPP;
-    const int need = (nr + RPP - 1) / RPP;
+    const int need = (nr + crows - 1) / crows;  // chunks
     const int cap = std::min(device_cus() * occ, kMGridMax) / 8 * 8;
     return std::max(8, std::min((need + 7) / 8 * 8, std::max(cap, 8)));
 }
@@ -754,11 +759,11 @@ int rows_grid(int nr) {
 template <class T, int K, bool DOT, int U, class G, class Ep>
 int launch_mrows_u(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials,
                    unsigned long long pmask, int forced_grid, const RowSched &rs) {
-    int crows = rs.crows > 0 ? rs.crows : chunk_rows<T, K>(M.nr, M.nnz);
-    if (rs.crows < 0) crows = std::max(M.nr, 1);  // one chunk per block: entries read from memory
-    int grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, DOT, U, G, Ep>(M.nr);
+    const int crows = rs.crows > 0 ? rs.crows : chunk_rows<T, K>(M.nr, M.nnz);
+    int grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, DOT, U, G, Ep>(M.nr, crows);
     if (!DOT && forced_grid <= 0 && rs.grid > 0) grid = rs.grid;
-    mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows);
+    mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows,
+                                                  rs.stage ? 1 : 0);
     HIPC(hipGetLastError());
     return grid;
 }
@@ -977,11 +982,13 @@ void tune_matrix(Engine &E, const Csr &M, const T *av, const G &g, const Ep &ep,
     const int rule = launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot);  // warm; the rule grid
     std::vector<RowSched> cand;
     for (int u : {4, 8})
-        for (int cr : {0, -1, std::max(RPP, def / 2 / RPP * RPP)})
-            for (int gd : {0, std::max(8, rule / 2 / 8 * 8)}) {
-                if (gd != 0 && (dot || gd == rule)) continue;
-                cand.push_back(RowSched{u, cr, gd});
-            }
+        for (int cr : {def, std::max(RPP, def / 2 / RPP * RPP), RPP})
+            for (int st : {1, 0})
+                for (int gd : {0, std::max(8, rule / 2 / 8 * 8)}) {
+                    if (gd != 0 && (dot || gd == rule)) continue;
+                    if (!st && cr != def) continue;
+                    cand.push_back(RowSched{u, cr, gd, st});
+                }
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));
