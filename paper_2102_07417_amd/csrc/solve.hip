@@ -242,13 +242,6 @@ struct GVec {
 // The new search direction p = z + beta p_old, formed on the fly.  On the
 // first iteration (and after a restart) beta = 0 and p_old is finite, so
 // z + 0 * p_old is exactly z: no branch is needed.
-struct GDir {
-    static constexpr int kLoads = 2;
-    const double *z, *p;
-    double beta;
-    __device__ double operator()(int j) const { return z[j] + beta * p[j]; }
-};
-
 template <class T, class TY>
 struct EPre {  // s = wd y, r = y - A s
     const T *wd;
@@ -300,18 +293,16 @@ struct ESpmv {
     __device__ Pre load(int i) const { return Pre{ADD ? out[i] : T(0)}; }
     __device__ void finish(int i, T acc, const Pre &p, double &) const { out[i] = ADD ? p.o + acc : acc; }
 };
-struct EDir {  // p_new, q = A p_new, dot += p.q
-    const double *z, *pold;
-    double beta;
-    double *pnew, *q;
+struct EPQ {  // q = A p; dot += p.q
+    const double *p;
+    double *q;
     struct Pre {
         double pi;
     };
-    __device__ Pre load(int i) const { return Pre{z[i] + beta * pold[i]}; }
-    __device__ void finish(int i, double acc, const Pre &p, double &dot) const {
-        pnew[i] = p.pi;
+    __device__ Pre load(int i) const { return Pre{p[i]}; }
+    __device__ void finish(int i, double acc, const Pre &pr, double &dot) const {
         q[i] = acc;
-        dot += p.pi * acc;
+        dot += pr.pi * acc;
     }
 };
 struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
@@ -427,15 +418,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_check(const double *pr2, PcgStat
     }
 }
 
-// rho = sum of the post-smoothing partials; p_new = z + beta p_old;
-// q = A p_new; partials of p_new . q
-template <int LPR, bool TILE>
-__global__ void __launch_bounds__(kBlock) k_pcg_dir(MatArg<double> M, const double *__restrict__ z,
-                                                    const double *__restrict__ pold, double *__restrict__ pnew,
-                                                    double *__restrict__ q, const double *prz, double *ppq,
-                                                    PcgState *st) {
+// rho = sum of the post-smoothing partials, beta = rho / rho_old (0 on a
+// (re)start); p_new = z + beta p_old, streamed
+__global__ void __launch_bounds__(kBlock) k_pcg_pnew(int n, const double *__restrict__ z,
+                                                     const double *__restrict__ pold, double *__restrict__ pnew,
+                                                     const double *prz, PcgState *st) {
     if (st->done) return;
-    extern __shared__ double smem_d[];
     const double rho = sum_all(prz, st->n_rz);
     const bool first = st->iter == st->restart;
     const double beta = first ? 0.0 : rho / st->rho_old;
@@ -443,13 +431,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_dir(MatArg<double> M, const doub
         st->rho = rho;
         st->beta = beta;
     }
-    double dot = 0.0;
-    run_rows<double, LPR, TILE>(M, GDir{z, pold, beta}, EDir{z, pold, beta, pnew, q}, smem_d, dot);
-    const double b = block_sum<kBlock>(dot);
-    if (threadIdx.x == 0) {
-        ppq[blockIdx.x] = b;
-        if (blockIdx.x == 0) st->n_pq = gridDim.x;
-    }
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) pnew[i] = z[i] + beta * pold[i];
 }
 
 // sigma = sum of the p.q partials; breakdown test; alpha = rho / sigma;
@@ -665,16 +648,15 @@ void pcg_check(const double *pr2, PcgState *st, double *hist, int hist_cap, int3
     HIPC(hipGetLastError());
 }
 
+// New search direction and q = A p: p_new is streamed by one kernel, then
+// q = A p_new runs as a one-gather row kernel with the p.q partials (one
+// gathered vector instead of two in a fused kernel, whose second gather
+// costs more than the extra pass over z, p_old and p_new).
 int pcg_dir(const Csr &A, const RowCfg &c, const double *z, const double *pold, double *pnew, double *q,
             const double *prz, double *ppq, PcgState *st, hipStream_t s) {
-    const MatArg<double> M = mat_arg<double>(A, c);
-    const size_t smem = c.tile ? (size_t)(c.tile_nnz + 1) * sizeof(double) : 0;
-    if (c.tile) {
-        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, true><<<c.grid, kBlock, smem, s>>>(M, z, pold, pnew, q, prz, ppq, st)));
-    } else {
-        CAMG_LPR_SWITCH(c.lpr, (k_pcg_dir<L, false><<<c.grid, kBlock, 0, s>>>(M, z, pold, pnew, q, prz, ppq, st)));
-    }
+    k_pcg_pnew<<<vec_grid(A.nr), kBlock, 0, s>>>(A.nr, z, pold, pnew, prz, st);
     HIPC(hipGetLastError());
+    launch_rows<double, true>(A, c, GVec<double>{pnew}, EPQ{pnew, q}, ppq, &st->n_pq, st, s);
     return c.grid;
 }
 
