@@ -181,6 +181,17 @@ def main():
     copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
 
+    # host API on the same hierarchy: b copied in and x out over PCIe around the device solve
+    sh = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, max_iter=max_iter)
+    sh.solve(b)
+    th = []
+    for _ in range(max(1, min(args.steps, 3))):
+        t0 = time.perf_counter()
+        sh.solve(b)
+        th.append((time.perf_counter() - t0) * 1e3)
+    sh.close()
+    host_ms = statistics.median(th)
+
     info = fp64[-1]["info"]
     solve_ms = statistics.median(r["solve_ms"] for r in fp64)
     setup_ms = statistics.median(r["setup_ms"] for r in fp64)
@@ -213,7 +224,7 @@ def main():
                    "operator_complexity": round(info.operator_complexity, 4)},
         "fp64": {"solve_ms": round(solve_ms, 4), "setup_ms": round(setup_ms, 4), "iters": iters,
                  "ms_per_iter": round(per_iter_ms, 5), "true_relres": fp64[-1]["true_relres"],
-                 "vcycle_alg_bytes": vb},
+                 "vcycle_alg_bytes": vb, "host_api_solve_ms": round(host_ms, 4)},
         "roofline": {"bound": "hbm", "kernel": "level-0 post-smoothing (k_rows<EPost, DOT>)",
                      "achieved": round(k_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -646,30 +646,46 @@ __global__ void __launch_bounds__(kRed) mk_sum(const double *partials, int nb, d
     if (threadIdx.x < K) out[threadIdx.x] = tot[threadIdx.x];
 }
 
-// last level: Z = Ainv Y for a K-column block (FP64 arithmetic), K lanes
-// per row; eight loads in flight, products added in column order
+// last level: Z = Ainv Y for a K-column block, a dense FP64 product on the
+// matrix cores.  One wavefront per 16x16 tile of Z runs
+// v_mfma_f64_16x16x4f64 over the inner dimension in steps of 4: lane l holds
+// A(i0 + l%16, k0 + l/16) and Y(k0 + l/16, j0 + l%16), and its four results
+// r = 0..3 are rows i0 + l/16 + 4r of column j0 + l%16 (the layout measured
+// on gfx950).  Out-of-range rows, columns
+// and inner indices contribute zeros.  Column j of Z depends only on column
+// j of Y.
+typedef double mk_d4 __attribute__((ext_vector_type(4)));
 template <class T, int K>
 __global__ void __launch_bounds__(kBlock) mk_coarse(int n, const double *__restrict__ cinv, const T *__restrict__ y,
                                                     T *__restrict__ z) {
-    constexpr int RPP = kBlock / K;
-    const int c = threadIdx.x % K;
-    const int i = blockIdx.x * RPP + threadIdx.x / K;
-    if (i >= n) return;
-    const double *row = cinv + (size_t)i * n;
-    double acc = 0.0;
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {
-        double a[8], v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            a[t] = row[j + t];
-            v[t] = (double)y[(size_t)(j + t) * K + c];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc += a[t] * v[t];
+    constexpr int TJ = (K + 15) / 16;  // column tiles
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int tile = blockIdx.x * (kBlock / 64) + wave;
+    const int i0 = (tile / TJ) * 16, j0 = (tile % TJ) * 16;
+    if (i0 >= n) return;  // uniform over the wavefront
+    const int li = lane % 16, lk = lane / 16;
+    const int ia = i0 + li, jb = j0 + li;
+    const double *arow = cinv + (size_t)min(ia, n - 1) * n;
+    mk_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = (ia < n && k < n) ? arow[k] : 0.0;
+        const double bv = (k < n && jb < K) ? (double)y[(size_t)k * K + jb] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
     }
-    for (; j < n; ++j) acc += row[j] * (double)y[(size_t)j * K + c];
-    z[(size_t)i * K + c] = (T)acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+        if (i < n && jb < K) z[(size_t)i * K + jb] = (T)acc[r];
+    }
+}
+
+template <class T, int K>
+void launch_coarse(int n, const double *cinv, const T *y, T *z, hipStream_t s) {
+    const int tiles = ((n + 15) / 16) * ((K + 15) / 16);
+    mk_coarse<T, K><<<(tiles + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s>>>(n, cinv, y, z);
+    HIPC(hipGetLastError());
 }
 
 int mgrid(int n, int K) {
@@ -809,7 +825,7 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
     Hier &h = *E.h;
     const int L = h.nlev - 1;
     if (L == 0) {  // one level: direct solve, then the r.z partials
-        mk_coarse<double, K><<<(h.nL + kBlock / K - 1) / (kBlock / K), kBlock, 0, s>>>(h.nL, h.cinv, E.R, E.Z);
+        launch_coarse<double, K>(h.nL, h.cinv, E.R, E.Z, s);
         if (dot) mk_dot<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.R, E.Z, E.prz);
         HIPC(hipGetLastError());
         return E.nb_vec;
@@ -853,9 +869,7 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
         launch_mrows_any<T, K>(Lv.R, vvals<T>(Lv.R), s, MGather<T, K>{r0},
                                MESpmv<T, K, false>{Tp(E.lv[l + 1].y)}, nullptr, false, ~0ull, 0, E.rs(Lv.R, (int)sizeof(T), 0));
     }
-    mk_coarse<T, K><<<(h.nL + kBlock / K - 1) / (kBlock / K), kBlock, 0, s>>>(h.nL, h.cinv, Tp(E.lv[L].y),
-                                                                              Tp(E.lv[L].z));
-    HIPC(hipGetLastError());
+    launch_coarse<T, K>(h.nL, h.cinv, Tp(E.lv[L].y), Tp(E.lv[L].z), s);
     for (int l = L - 1; l >= 0; --l) {
         Level &Lv = h.lev[l];
         Engine::Lv &B = E.lv[l];

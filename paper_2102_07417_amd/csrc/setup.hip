@@ -429,12 +429,12 @@ __global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int32_t *fl
         for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) D[(int64_t)i * n + j] = D[(int64_t)i * n + j] / ljj;
         __syncthreads();
         // trailing update of the lower triangle: rows i > j, columns j < k <= i
-        const int m = n - j - 1;
-        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
-            const int a = (int)(t / m), b = (int)(t % m);
-            if (b > a) continue;
-            const int i = j + 1 + a, k = j + 1 + b;
-            D[(int64_t)i * n + k] = D[(int64_t)i * n + k] - D[(int64_t)i * n + j] * D[(int64_t)k * n + j];
+        // (one wavefront per row, lanes over the row's columns)
+        const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+        for (int i = j + 1 + wave; i < n; i += nw) {
+            const double lij = D[(int64_t)i * n + j];
+            for (int k = j + 1 + lane; k <= i; k += 64)
+                D[(int64_t)i * n + k] = D[(int64_t)i * n + k] - lij * D[(int64_t)k * n + j];
         }
         __syncthreads();
     }

@@ -25,7 +25,7 @@ def camg():
 
 SYSTEMS = [("poisson2d_40", lambda: PB.poisson2d(40), "fp64"),
            ("lognormal3d_14", lambda: PB.lognormal3d(14, 2.0), "mixed"),
-           ("elasticity_4", lambda: PB.elasticity3d(4, 0.3), "fp64")]
+           ("elasticity_6", lambda: PB.elasticity3d(6, 0.3), "fp64")]
 
 
 def _drain(srv, n, out=None, timeout=60.0):
