@@ -260,10 +260,12 @@ void camg_free_host(void *p);
  * Kernel timing for benchmarks: while enabled, every solve on the handle
  * brackets the level-0 post-smoothing kernel (the fine-level Jacobi step
  * z = s + omega D^{-1} (y - A s) fused with the r.z partial sums) with HIP
- * events on the solve's stream and accumulates the durations of the
- * launches that did work.  Each call returns (and resets) the totals
- * gathered since the previous call, then enables or disables timing.
- * total_ms and launches may be NULL.
+ * events on the solve's stream, on every enable-th PCG iteration (the last
+ * of each group of enable iterations), and accumulates the durations of the
+ * timed launches that did work.  Each call returns (and resets) the totals
+ * gathered since the previous call, then sets timing: enable = 0 off,
+ * enable = n >= 1 on, every n-th iteration.  total_ms and launches may be
+ * NULL.
  */
 camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_t *launches);
 

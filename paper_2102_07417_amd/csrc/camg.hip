@@ -481,28 +481,27 @@ void build_graphs(Hier &h) {
         HIPC(hipGraphInstantiate(&h.gexec[slot][par], h.graph[slot][par], nullptr, nullptr, 0));
     };
     for (int p = 0; p < 2; ++p) {
-        if (h.prof) {
+        capture(0, p, 0, 2);
+        if (h.prof) {  // timed iterations: the level-0 post-smoothing kernel between two events
             capture(1, p, 0, 0);
             capture(2, p, 2, 2);
-        } else {
-            capture(0, p, 0, 2);
         }
     }
     h.graph_ok = true;
     h.graph_prof = h.prof;
 }
 
-void launch_iteration(Hier &h, int par, hipStream_t s) {
+void launch_iteration(Hier &h, int par, bool timed, hipStream_t s) {
     const bool g = h.use_graph && h.graph_ok;
-    if (g && !h.prof) {
+    if (g && !timed) {
         HIPC(hipGraphLaunch(h.gexec[0][par], s));
         return;
     }
     if (g) HIPC(hipGraphLaunch(h.gexec[1][par], s));
     else enqueue_segment(h, par, 0, s);
-    if (h.prof) HIPC(hipEventRecord(h.pev[par][0], s));
+    if (timed) HIPC(hipEventRecord(h.pev[par][0], s));
     enqueue_segment(h, par, 1, s);
-    if (h.prof) HIPC(hipEventRecord(h.pev[par][1], s));
+    if (timed) HIPC(hipEventRecord(h.pev[par][1], s));
     if (g) HIPC(hipGraphLaunch(h.gexec[2][par], s));
     else enqueue_segment(h, par, 2, s);
 }
@@ -528,8 +527,10 @@ void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, 
         hipEvent_t *e;
         ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
     } eg{ev};
+    // with timing on, every prof_stride-th iteration is timed (the last of each stride)
+    auto timed = [&](int k) { return h.prof && (k % h.prof_stride) == h.prof_stride - 1; };
     auto collect = [&](int k) {
-        if (!h.prof) return;
+        if (!timed(k)) return;
         float ms = 0.f;
         HIPC(hipEventElapsedTime(&ms, h.pev[k & 1][0], h.pev[k & 1][1]));
         times.emplace_back(k, ms);
@@ -539,7 +540,7 @@ void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, 
     int last = -1;
     for (int k = k0; k < max_iter; ++k) {
         const int par = k & 1;
-        launch_iteration(h, par, s);
+        launch_iteration(h, par, timed(k), s);
         HIPC(hipEventRecord(ev[par], s));
         last = k;
         if (k > k0) {
@@ -885,11 +886,13 @@ camg_status camg_profile(camg_handle hh, int32_t enable, double *total_ms, int64
         if (launches) *launches = h->prof_launches;
         h->prof_ms = 0.0;
         h->prof_launches = 0;
+        if (enable < 0) fail(CAMG_E_ARG, "enable must be >= 0");
         const bool on = enable != 0;
         if (on && !h->pev[0][0])
             for (auto &pp : h->pev)
                 for (auto &e : pp) HIPC(hipEventCreate(&e));
         h->prof = on;
+        h->prof_stride = on ? enable : 1;
     });
 }
 

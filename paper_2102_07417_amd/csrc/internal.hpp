@@ -121,6 +121,7 @@ struct Hier {
     double setup_ms = 0.0;
     // optional timing of the level-0 post-smoothing kernel inside solves
     bool prof = false;
+    int prof_stride = 1;  // time every prof_stride-th iteration
     hipEvent_t pev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][start/end]
     double prof_ms = 0.0;
     int64_t prof_launches = 0;

@@ -26,7 +26,14 @@ namespace camg {
 
 namespace {
 
-constexpr int kTileW = 2048;      // largest nominal nonzeros per tile
+#ifndef CAMG_TILE_W
+#define CAMG_TILE_W 2048
+#endif
+#ifndef CAMG_TILE_ROWS
+#define CAMG_TILE_ROWS 128
+#endif
+constexpr int kTileW = CAMG_TILE_W;        // largest nominal nonzeros per tile
+constexpr int kTileRows = CAMG_TILE_ROWS;  // nominal rows per tile
 constexpr int kTileMaxRow = 4096; // longest row a tile can hold (LDS <= 8192 entries)
 
 template <class T>
@@ -321,7 +328,7 @@ struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
 
 // ------------------------------------------------------------------ kernels
 template <class T, int LPR, bool TILE, bool DOT, class G, class E>
-__global__ void __launch_bounds__(kBlock) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
                                                  const PcgState *st) {
     if (st && st->done) return;
     extern __shared__ double smem_d[];
@@ -525,8 +532,8 @@ RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
     const double mean = n > 0 ? std::max(1.0, (double)nnz / n) : 1.0;
     c.maxrow = maxrow;
     if (maxrow <= kTileMaxRow) {
-        // about kBlock rows per tile, at most kTileW nonzeros
-        int W = (int)std::min<double>(kTileW, std::max(256.0, kBlock * mean));
+        // about kTileRows rows per tile, at most kTileW nonzeros
+        int W = (int)std::min<double>(kTileW, std::max(256.0, kTileRows * mean));
         W = (W + 63) / 64 * 64;
         c.tile = true;
         c.W = W;

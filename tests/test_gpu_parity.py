@@ -273,6 +273,13 @@ def test_kernel_timing_hook(camg):
     r = s.solve(b)
     ms, launches = camg.camg_profile(s.h, 0)
     assert launches == r.iters and ms > 0
+    # every 4th iteration (k = 3, 7, ...), same solution bits as untimed solves
+    camg.camg_profile(s.h, 4)
+    r4 = s.solve(b)
+    ms4, launches4 = camg.camg_profile(s.h, 0)
+    assert launches4 == r4.iters // 4 and ms4 > 0
+    r0 = s.solve(b)
+    assert np.array_equal(r4.x, r0.x) and np.array_equal(r.x, r0.x)
     s.close()
 
 
