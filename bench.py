@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--batched", type=int, default=32,
                     help="right-hand sides of the batched (block) run on aniso3d_160; 0 skips it")
     ap.add_argument("--only-batched", action="store_true", help="print only the batched run")
+    ap.add_argument("--small-systems", type=int, default=256,
+                    help="independent 100x100 lognormal systems solved in one launch; 0 skips it")
     ap.add_argument("--serve", action="store_true",
                     help="print only the serving sweep (8 resident systems, Poisson arrivals)")
     ap.add_argument("--rates", default="5,10,20,50,100,200", help="request rates (1/s) of the serving sweep")
@@ -120,7 +122,10 @@ def main():
     camg.load()
     dev = torch.device("cuda:0")
     if args.only_batched:
-        print(json.dumps({"batched": batched_run(args.batched or 32, args.steps)}), flush=True)
+        out = {"batched": batched_run(args.batched or 32, args.steps)}
+        if args.small_systems:
+            out["small_systems"] = small_systems_run(args.small_systems)
+        print(json.dumps(out), flush=True)
         return
     if args.serve:
         print(json.dumps({"serving": serve_run([float(r) for r in args.rates.split(",")], args.serve_seconds)}),
@@ -240,6 +245,8 @@ def main():
                         "speedup_vs_fp64": round(solve_ms / m_ms, 4), "rel_err_vs_fp64_gpu": err}
     if args.batched:
         out["batched"] = batched_run(args.batched, max(1, min(args.steps, 3)))
+    if args.small_systems:
+        out["small_systems"] = small_systems_run(args.small_systems)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, x64, iters)
     print(json.dumps(out), flush=True)
@@ -322,6 +329,53 @@ def batched_run(k, steps):
             "block_mixed_max_rel_err_vs_sequential_fp64": emx,
             "block_mixed_autotuned_ms": round(bmt_ms, 3), "block_mixed_autotuned_speedup": round(seq_ms / bmt_ms, 3),
             "autotune_and_runs_s": round(tune_s, 2)}
+
+
+def small_systems_run(count, steps=3):
+    """count independent 2D lognormal(0, 2) systems on 100x100 cells (each
+    its own coefficient seed and right-hand side, n = 10,000), FP64, rtol
+    1e-8: one launch with a workgroup per system against solving them one
+    after another with the single-system path.  Hierarchies are set up
+    before the clock starts."""
+    import numpy as np
+    import torch
+
+    from paper_2102_07417_amd import camg, problems
+
+    dev = torch.device("cuda:0")
+    solvers, db, dx = [], [], []
+    for k in range(count):
+        A = problems.lognormal2d(100, 2.0, 5000 + k)
+        solvers.append(camg.Solver(A, max_iter=2000))
+        db.append(torch.from_numpy(problems.rhs(A.n, 9000 + k)).to(dev))
+        dx.append(torch.zeros_like(db[-1]))
+    camg.solve_batch_dev(solvers, db, dx)
+    tb = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rel, st = camg.solve_batch_dev(solvers, db, dx)
+        torch.cuda.synchronize()
+        tb.append((time.perf_counter() - t0) * 1e3)
+    xb = [x.clone() for x in dx]
+    for k in range(count):
+        solvers[k].solve_dev(db[k], dx[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for k in range(count):
+        its.append(solvers[k].solve_dev(db[k], dx[k]).iters)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    err = max(float(((xb[k] - dx[k]).norm() / dx[k].norm()).item()) for k in range(count))
+    for s in solvers:
+        s.close()
+    bms = statistics.median(tb)
+    return {"workload": "lognormal2d_100 x %d (independent seeds)" % count, "n_each": 10000, "systems": count,
+            "batch_ms": round(bms, 3), "sequential_ms": round(seq_ms, 3), "speedup": round(seq_ms / bms, 3),
+            "iters": [int(it.min()), int(it.max())], "sequential_iters": [min(its), max(its)],
+            "max_true_relres": float(rel.max()), "not_ok": int((st != camg.OK).sum()),
+            "max_rel_diff_vs_sequential": err, "systems_per_s": round(count / (bms * 1e-3), 1)}
 
 
 def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):

@@ -172,6 +172,22 @@ camg_status camg_engine_finish(camg_engine_t e, int32_t slot0, int32_t m, double
 camg_status camg_engine_destroy(camg_engine_t e);
 
 /*
+ * Many small systems at once: count systems (handles of one precision, one
+ * smoothing step each way, on one device, each listed once) are solved in
+ * one kernel launch, one workgroup per system running that system's whole
+ * PCG solve (every iteration and V-cycle level) with the same recurrence
+ * and stopping test as camg_solve_dev, x0 = 0, rtol shared.  d_b[k], d_x[k]
+ * are device vectors of system k; iters, true_relres and status are host
+ * arrays of count entries (each may be NULL); per-system outcomes are in
+ * status (CAMG_OK, CAMG_E_MAXIT, CAMG_E_BREAKDOWN) while the call returns
+ * CAMG_OK.  Meant for systems up to ~1e5 unknowns (one compute unit works
+ * through each system); larger ones are correct but slow.
+ */
+camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
+                                 double rtol, int32_t *iters, double *true_relres, int32_t *status,
+                                 void *hip_stream);
+
+/*
  * Server: resident hierarchies answering solve requests (the paper reuses
  * one hierarchy for many solves; here every system added keeps its
  * hierarchy and a slot engine on a stream of its own, so the systems' work

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcamg.so")
-SOURCES = ["setup.hip", "spgemm.hip", "solve.hip", "multi.hip", "serve.hip", "camg.hip"]
+SOURCES = ["setup.hip", "spgemm.hip", "solve.hip", "multi.hip", "serve.hip", "batch.hip", "camg.hip"]
 ARCH = os.environ.get("CAMG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -28,7 +28,7 @@ EXPORTED = [
     "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
     "camg_set_option", "camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
     "camg_engine_state", "camg_engine_finish", "camg_engine_destroy", "camg_server_create", "camg_server_add",
-    "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy",
+    "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy", "camg_solve_batch_dev",
 ]
 OPT_GRAPH = 1
 OPT_AUTOTUNE = 2
@@ -87,6 +87,8 @@ def load(path: str | None = None):
     L.camg_engine_state.argtypes = [vp, vp, vp, vp]
     L.camg_engine_finish.argtypes = [vp, i32, i32, vp, i32, vp]
     L.camg_engine_destroy.argtypes = [vp]
+    L.camg_solve_batch_dev.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+    L.camg_solve_batch_dev.restype = C.c_int
     L.camg_server_create.argtypes = [i64, C.POINTER(vp)]
     L.camg_server_add.argtypes = [vp, vp, i32, i32, vp]
     L.camg_server_submit.argtypes = [vp, i32, i32, vp, i32, vp, i32, dbl, i32, i64]
@@ -298,6 +300,21 @@ class Engine:
 def torch_float64():
     import torch
     return torch.float64
+
+
+def solve_batch_dev(solvers, d_bs, d_xs, rtol=1e-8, stream=None):
+    """Many small systems in one launch (one workgroup per system).  Returns
+    (iters, true_relres, status) arrays; raises on a call error."""
+    m = len(solvers)
+    hs = (C.c_void_p * m)(*[s.h for s in solvers])
+    bs = (C.c_void_p * m)(*[t.data_ptr() for t in d_bs])
+    xs = (C.c_void_p * m)(*[t.data_ptr() for t in d_xs])
+    it = np.zeros(m, np.int32)
+    rel = np.zeros(m)
+    st = np.zeros(m, np.int32)
+    _check(load().camg_solve_batch_dev(m, C.cast(hs, C.c_void_p), C.cast(bs, C.c_void_p), C.cast(xs, C.c_void_p),
+                                       float(rtol), _p(it), _p(rel), _p(st), _stream_ptr(stream)))
+    return it, rel, st
 
 
 class camg_completion(C.Structure):

@@ -1062,6 +1062,25 @@ camg_status camg_engine_destroy(camg_engine_t ce) {
     });
 }
 
+// ---------------------------------------------------------------- many small systems
+camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
+                                 double rtol, int32_t *iters, double *true_relres, int32_t *status,
+                                 void *hip_stream) {
+    return guarded([&] {
+        if (count < 1 || !hs || !d_b || !d_x) fail(CAMG_E_ARG, "count < 1 or null array");
+        if (!std::isfinite(rtol)) fail(CAMG_E_ARG, "rtol must be finite");
+        std::vector<Hier *> v(count);
+        std::vector<std::unique_ptr<BusyGuard>> guards;
+        for (int k = 0; k < count; ++k) {
+            v[k] = as_hier(hs[k]);
+            if (!d_b[k] || !d_x[k]) fail(CAMG_E_ARG, "null vector");
+            guards.emplace_back(new BusyGuard(v[k]));  // also rejects a handle listed twice
+        }
+        HIPC(hipSetDevice(v[0]->device));
+        solve_batch(v, d_b, d_x, rtol, iters, true_relres, status, (hipStream_t)hip_stream);
+    });
+}
+
 // ---------------------------------------------------------------- server API
 struct camg_server {
     Server *s = nullptr;

@@ -266,6 +266,10 @@ void engine_release_mask(Engine &E, unsigned long long mask, hipStream_t s);
 void engine_gather_x(Engine &E, const SlotMap &q, int k, double *out, hipStream_t s);
 int engine_n(const Engine &E);
 
+// ---------------------------------------------------------------- many small systems (batch.hip)
+void solve_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x, double rtol, int32_t *iters,
+                 double *true_relres, int32_t *status, hipStream_t s);
+
 // ---------------------------------------------------------------- server (serve.hip)
 struct Server;
 Server *server_create(int64_t budget);
