@@ -8,7 +8,9 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,23 +30,97 @@ void hip_check(hipError_t e, const char *what) {
     fail(CAMG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void *Pool::raw(size_t nbytes) {
+namespace {
+constexpr size_t kChunk = (size_t)16 << 20;     // packing chunk
+constexpr size_t kOwnBlock = (size_t)4 << 20;   // requests of this size or more get their own block
+constexpr size_t kCacheCap = (size_t)4 << 30;   // scratch cache per device
+std::mutex g_cache_mu;
+std::multimap<size_t, Pool::Block> g_cache;     // free scratch blocks by size
+size_t g_cache_bytes[64] = {};
+
+void drain_cache(int dev) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end();) {
+        if (it->second.device == dev) {
+            (void)hipFree(it->second.p);
+            g_cache_bytes[dev & 63] -= it->second.size;
+            it = g_cache.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+}  // namespace
+
+Pool::Block Pool::get(size_t size) {
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (scratch_) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        // smallest cached block that fits, if it is not much larger
+        for (auto it = g_cache.lower_bound(size); it != g_cache.end() && it->first <= 2 * size + kChunk; ++it)
+            if (it->second.device == dev) {
+                Block bl = it->second;
+                g_cache_bytes[dev & 63] -= bl.size;
+                g_cache.erase(it);
+                return bl;
+            }
+    }
     void *p = nullptr;
-    if (nbytes == 0) nbytes = 1;
-    nbytes = (nbytes + 255) & ~(size_t)255;
-    hipError_t e = hipMalloc(&p, nbytes);
+    hipError_t e = hipMalloc(&p, size);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        fail(CAMG_E_NOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+        drain_cache(dev);
+        e = hipMalloc(&p, size);
     }
-    ptrs.push_back(p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(CAMG_E_NOMEM, "device allocation of " + std::to_string(size) + " bytes failed");
+    }
+    return Block{p, size, dev};
+}
+
+void *Pool::raw(size_t nbytes) {
+    if (nbytes == 0) nbytes = 1;
+    nbytes = (nbytes + 255) & ~(size_t)255;
     bytes += (int64_t)nbytes;
-    return p;
+    if (nbytes <= left_) {
+        void *p = cur_;
+        cur_ += nbytes;
+        left_ -= nbytes;
+        return p;
+    }
+    if (nbytes >= kOwnBlock) {
+        blocks_.push_back(get(nbytes));
+        return blocks_.back().p;
+    }
+    blocks_.push_back(get(kChunk));
+    cur_ = static_cast<char *>(blocks_.back().p) + nbytes;
+    left_ = blocks_.back().size - nbytes;
+    return blocks_.back().p;
 }
 
 void Pool::release() {
-    for (void *p : ptrs) (void)hipFree(p);
-    ptrs.clear();
+    if (blocks_.empty()) return;
+    bool keep = scratch_;
+    if (keep && hipStreamSynchronize(stream_) != hipSuccess) {  // the stream's work on these blocks is done
+        (void)hipGetLastError();
+        keep = false;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (const Block &bl : blocks_) {
+            if (keep && g_cache_bytes[bl.device & 63] + bl.size <= kCacheCap) {
+                g_cache.emplace(bl.size, bl);
+                g_cache_bytes[bl.device & 63] += bl.size;
+            } else {
+                (void)hipFree(bl.p);
+            }
+        }
+    }
+    blocks_.clear();
+    cur_ = nullptr;
+    left_ = 0;
     bytes = 0;
 }
 
@@ -138,7 +214,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                      hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const camg_params &prm = h.prm;
-    Pool tmp;
+    Pool tmp(s);
     int64_t nnz;
     if (host_in) nnz = rp[n];
     else nnz = read1(rp + n, s);
@@ -169,7 +245,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         if (nl <= prm.max_coarse || l == prm.max_levels - 1) break;
         Level &L = h.lev[l];
         const int64_t nz = L.A.nnz;
-        Pool lt;  // per-level temporaries
+        Pool lt(s);  // per-level temporaries
         if (l > 0) {
             tpos = lt.alloc<int32_t>(std::max<int64_t>(nz, 1));
             transpose_positions(nl, L.A.rp, L.A.ci, tpos, s);
@@ -716,7 +792,7 @@ camg_status camg_solve(camg_handle hh, const double *b, double rtol, double *x, 
         BusyGuard g(h);
         HIPC(hipSetDevice(h->device));
         const int n = h->lev[0].A.nr;
-        Pool io;
+        Pool io((hipStream_t) nullptr);
         double *db = io.alloc<double>(n), *dx = io.alloc<double>(n);
         HIPC(hipMemcpy(db, b, sizeof(double) * n, hipMemcpyHostToDevice));
         ret = solve_dev(*h, db, rtol, dx, iters, hist, hist_cap, true_relres, nullptr);
@@ -815,8 +891,8 @@ camg_status camg_galerkin(int32_t n, const int32_t *a_rp, const int32_t *a_ci, c
     return guarded([&] {
         if (n < 1 || nc < 0 || !a_rp || !a_ci || !a_val || !p_rp || !p_ci || !p_val || !c_rp || !c_ci || !c_val)
             fail(CAMG_E_ARG, "bad argument");
-        Pool tmp, outp;
         hipStream_t s = nullptr;
+        Pool tmp(s), outp(s);
         auto up = [&](Csr &M, int nr, int ncol, const int32_t *rp, const int32_t *ci, const double *v) {
             M.nr = nr;
             M.nc = ncol;

@@ -26,13 +26,38 @@ void hip_check(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------- memory
 // Device allocations owned by a handle (or by a set-up scratch pool).
+// Device memory.  Requests are rounded to 256 bytes; small ones are packed
+// into 16 MB chunks, large ones get blocks of their own.  A scratch pool
+// (constructed with the stream its memory is used on) hands its blocks to a
+// per-device cache when released, after that stream has drained, and later
+// scratch pools take blocks from the cache instead of calling hipMalloc (a
+// hipFree waits for the whole device, a hipMalloc costs tens of
+// microseconds).  The cache keeps at most 4 GiB per device for the life of
+// the process.
 struct Pool {
-    std::vector<void *> ptrs;
-    int64_t bytes = 0;
+    Pool() = default;
+    explicit Pool(hipStream_t scratch_stream) : scratch_(true), stream_(scratch_stream) {}
+    Pool(const Pool &) = delete;
+    Pool &operator=(const Pool &) = delete;
     void *raw(size_t nbytes);
     template <class T> T *alloc(size_t count) { return static_cast<T *>(raw(count * sizeof(T))); }
     void release();
     ~Pool() { release(); }
+    int64_t bytes = 0;  // bytes handed out
+
+    struct Block {
+        void *p;
+        size_t size;
+        int device;
+    };
+
+  private:
+    Block get(size_t size);
+    std::vector<Block> blocks_;
+    char *cur_ = nullptr;
+    size_t left_ = 0;
+    bool scratch_ = false;
+    hipStream_t stream_ = nullptr;
 };
 
 // Column-index and value arrays carry this many elements of padding past

@@ -335,7 +335,7 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
                 goff.push_back(total);
                 total += ts;
             }
-        Pool g;
+        Pool g(s);
         int *scr = g.alloc<int>((size_t)total);
         int32_t *drows = g.alloc<int32_t>(grow.size());
         int32_t *dts = g.alloc<int32_t>(grow.size());
@@ -390,7 +390,7 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
             itot += 2 * (int64_t)ts + np;
             dtot += u;
         }
-        Pool g;
+        Pool g(s);
         const int m = (int)rows.size();
         int *iscr = g.alloc<int>((size_t)itot);
         double *dscr = g.alloc<double>((size_t)std::max<int64_t>(dtot, 1));
