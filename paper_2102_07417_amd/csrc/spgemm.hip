@@ -76,27 +76,79 @@ __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int n
     if (b >= 0) brows[(int64_t)b * stride + lbase[b] + off] = i;
 }
 
+// Visit the products of row i of X Y in ascending order of X's entries e:
+// for each e the lanes take the entries t of row k = X.ci[e] of Y and call
+// f(j = Y.ci[t], x = X.v[e], y = Y.v[t]); step e finishes (wavefront
+// barrier) before step e+1 starts.  The entries of X's row (column, value,
+// extent of Y's row) are loaded by all lanes at once, 64 at a time, and the
+// first 64 entries of the next Y row are loaded while the current one is
+// processed, so each step waits for at most one round of memory latency.
+template <class F>
+__device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrView &Y, int lane, F f) {
+    const int e0 = X.rp[i], e1 = X.rp[i + 1];
+    for (int cb = e0; cb < e1; cb += kWave) {
+        const int ne = min(kWave, e1 - cb);
+        int yb = 0, yc = 0;
+        double xv = 0.0;
+        if (lane < ne) {
+            const int k = X.ci[cb + lane];
+            xv = X.v[cb + lane];
+            yb = Y.rp[k];
+            yc = Y.rp[k + 1] - yb;
+        }
+        int b = __shfl(yb, 0, kWave), c = __shfl(yc, 0, kWave);
+        double x = __shfl(xv, 0, kWave);
+        int jc = 0;
+        double vc = 0.0;
+        if (lane < c) {
+            jc = Y.ci[b + lane];
+            vc = Y.v[b + lane];
+        }
+        for (int q = 0; q < ne; ++q) {
+            int bn = 0, cn = 0, jn = 0;
+            double xn = 0.0, vn = 0.0;
+            if (q + 1 < ne) {
+                bn = __shfl(yb, q + 1, kWave);
+                cn = __shfl(yc, q + 1, kWave);
+                xn = __shfl(xv, q + 1, kWave);
+                if (lane < cn) {
+                    jn = Y.ci[bn + lane];
+                    vn = Y.v[bn + lane];
+                }
+            }
+            if (lane < c) f(jc, x, vc);
+            for (int t = b + kWave + lane; t < b + c; t += kWave) f(Y.ci[t], x, Y.v[t]);
+            WAVE_SYNC();
+            b = bn;
+            c = cn;
+            x = xn;
+            jc = jn;
+            vc = vn;
+        }
+    }
+}
+
 // Insert the columns of row i of X Y into the table; returns the number of
 // new keys this lane inserted.  *overflow is set if a probe sequence wraps.
 __device__ __forceinline__ int insert_row(int i, const CsrView &X, const CsrView &Y, int *keys, int ts, int lane,
                                           bool &overflow) {
     int cnt = 0;
-    const int e1 = X.rp[i + 1];
-    for (int e = X.rp[i]; e < e1; ++e) {
-        const int k = X.ci[e];
-        const int t1 = Y.rp[k + 1];
-        for (int t = Y.rp[k] + lane; t < t1; t += kWave) {
-            const int j = Y.ci[t];
-            unsigned h = slot_of(j, ts);
-            for (int probe = 0;; ++probe) {
-                const int old = atomicCAS(&keys[h], kEmpty, j);
-                if (old == kEmpty) { ++cnt; break; }
-                if (old == j) break;
-                h = (h + 1) & (unsigned)(ts - 1);
-                if (probe >= ts) { overflow = true; break; }
+    for_products(i, X, Y, lane, [&](int j, double, double) {
+        unsigned h = slot_of(j, ts);
+        for (int probe = 0;; ++probe) {
+            const int old = atomicCAS(&keys[h], kEmpty, j);
+            if (old == kEmpty) {
+                ++cnt;
+                break;
+            }
+            if (old == j) break;
+            h = (h + 1) & (unsigned)(ts - 1);
+            if (probe >= ts) {
+                overflow = true;
+                break;
             }
         }
-    }
+    });
     return cnt;
 }
 
@@ -195,21 +247,15 @@ __device__ __forceinline__ void fill_row(int i, bool valid, const CsrView &X, co
             acc[p] = 0.0;
         }
         WAVE_SYNC();
-        // products in ascending inner index; lanes hold distinct columns
-        const int e1 = X.rp[i + 1];
-        for (int e = X.rp[i]; e < e1; ++e) {
-            const int k = X.ci[e];
-            const double x = X.v[e];
-            const int t1 = Y.rp[k + 1];
-            for (int t = Y.rp[k] + lane; t < t1; t += kWave) {
-                const int h = find_slot(keys, ts, Y.ci[t]);
-                if (h >= 0) {
-                    const int p = pos[h];
-                    acc[p] = acc[p] + x * Y.v[t];
-                }
+        // products in ascending inner index; within a step the lanes hold
+        // distinct columns
+        for_products(i, X, Y, lane, [&](int j, double x, double y) {
+            const int h = find_slot(keys, ts, j);
+            if (h >= 0) {
+                const int p = pos[h];
+                acc[p] = acc[p] + x * y;
             }
-            WAVE_SYNC();
-        }
+        });
         const int off = zrp[i];
         for (int p = lane; p < u; p += kWave) {
             zci[off + p] = cols[p];
