@@ -18,13 +18,14 @@ _lib = None
 
 OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -2, -3, -4, -5, -6
 F, U, CPT = -1, 0, 1
-X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS = range(10)
+X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS, X_G = range(11)
+SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
 
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("omega", C.c_double), ("max_levels", C.c_int32),
-                ("max_coarse", C.c_int32), ("max_iter", C.c_int32)]
+                ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32)]
 
 
 class CsrOut(C.Structure):
@@ -53,6 +54,8 @@ def lib():
         L.orc_cholesky.argtypes = [i32, vp]
         L.orc_chol_solve.argtypes = [i32, vp, vp, vp]
         L.orc_gershgorin_omega.argtypes = [i32, vp, vp, vp]; L.orc_gershgorin_omega.restype = dbl
+        L.orc_fsai.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
+        L.orc_fsai_omega.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), vp]
         L.orc_csr_free.argtypes = [C.POINTER(CsrOut)]
         L.orc_setup.argtypes = [i32, vp, vp, vp, C.POINTER(Params), C.POINTER(vp)]
         L.orc_num_levels.argtypes = [vp]
@@ -195,6 +198,25 @@ def gershgorin_omega(A) -> float:
     return float(lib().orc_gershgorin_omega(n, _p(rp), _p(ci), _p(v)))
 
 
+def fsai(A):
+    """Static FSAI factor G on the lower-triangular pattern of A (status, G)."""
+    o, keep = _to_out(*_csr_arrays(A))
+    r = CsrOut()
+    st = lib().orc_fsai(C.byref(o), C.byref(r))
+    if st != OK:
+        lib().orc_csr_free(C.byref(r))
+        return st, None
+    return st, _from_out(r)
+
+
+def fsai_omega(A, G) -> float:
+    oa, ka = _to_out(*_csr_arrays(A))
+    og, kg = _to_out(*_csr_arrays(G))
+    w = np.zeros(1)
+    assert lib().orc_fsai_omega(C.byref(oa), C.byref(og), _p(w)) == OK
+    return float(w[0])
+
+
 class Hierarchy:
     """Oracle AMG hierarchy (setup) plus V-cycle and PCG."""
 
@@ -262,6 +284,16 @@ class Hierarchy:
         a = np.zeros(self.sizes(l)[0])
         assert lib().orc_export(self.h, l, X_DINV, _p(a), None, None) == OK
         return a
+
+    def G(self, l):
+        """FSAI factor of level l (FSAI smoother only)."""
+        n, nnz, _, _ = self.sizes(l)
+        rp_a = self.A(l)[2]
+        ci_a = self.A(l)[3]
+        nnzg = int(sum(np.count_nonzero(ci_a[rp_a[i]:rp_a[i + 1]] <= i) for i in range(n)))
+        rp = np.zeros(n + 1, np.int32); ci = np.zeros(nnzg, np.int32); v = np.zeros(nnzg)
+        assert lib().orc_export(self.h, l, X_G, _p(rp), _p(ci), _p(v)) == OK
+        return (n, n, rp, ci, v)
 
     def omega(self, l):
         a = np.zeros(1)

@@ -35,6 +35,7 @@ void orc_params_default(orc_params *p) {
     p->max_levels = 25;
     p->max_coarse = 256;
     p->max_iter = 1000;
+    p->smoother = ORC_SMOOTH_JACOBI;
 }
 
 /* Position of column j in row i, or -1 (rows are sorted). */
@@ -421,10 +422,109 @@ double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, con
     return (4.0 / 3.0) / rho;
 }
 
+
+/*
+ * Factorised sparse approximate inverse smoother, M^{-1} = G^T G with G
+ * lower triangular (Section 2, eq. smo).  The paper builds G adaptively
+ * (aFSAI, from another paper); here G is the static factor of Kolotilina
+ * and Yeremin on the pattern of the lower triangle of A: for row i, with
+ * P_i = {j <= i : a_ij stored} in ascending order (i last), solve
+ * A(P_i, P_i) g = e_last by a dense Cholesky factorisation, forward and
+ * backward substitution, and set G(i, P_i) = g / sqrt(g_last), so that
+ * G A G^T has a unit diagonal.
+ */
+int orc_fsai(const orc_csr *A, orc_csr *G) {
+    int32_t n = A->nrows;
+    G->nrows = n; G->ncols = n;
+    G->rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    if (!G->rp) return ORC_E_NOMEM;
+    G->rp[0] = 0;
+    int32_t mmax = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t m = 0;
+        for (int32_t e = A->rp[i]; e < A->rp[i + 1]; ++e) if (A->ci[e] <= i) ++m;
+        G->rp[i + 1] = G->rp[i] + m;
+        if (m > mmax) mmax = m;
+    }
+    int32_t nnz = G->rp[n];
+    G->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    G->val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *M = (double *)malloc(sizeof(double) * (size_t)mmax * (size_t)mmax);
+    double *e = (double *)malloc(sizeof(double) * (size_t)mmax);
+    double *g = (double *)malloc(sizeof(double) * (size_t)mmax);
+    int st = ORC_OK;
+    if (!G->ci || !G->val || !M || !e || !g) st = ORC_E_NOMEM;
+    for (int32_t i = 0; i < n && st == ORC_OK; ++i) {
+        int32_t m = G->rp[i + 1] - G->rp[i];
+        const int32_t *idx = A->ci + A->rp[i];   /* the first m columns of row i are <= i */
+        for (int32_t r = 0; r < m; ++r)
+            for (int32_t c = 0; c < m; ++c) {
+                int32_t p = find_in_row(A->rp, A->ci, idx[r], idx[c]);
+                M[(size_t)r * m + c] = p >= 0 ? A->val[p] : 0.0;
+            }
+        if (m == 0 || idx[m - 1] != i || orc_cholesky(m, M) != 0) { st = ORC_E_NOT_SPD; break; }
+        for (int32_t r = 0; r < m; ++r) e[r] = r == m - 1 ? 1.0 : 0.0;
+        orc_chol_solve(m, M, e, g);
+        if (!(g[m - 1] > 0.0)) { st = ORC_E_NOT_SPD; break; }
+        double sd = sqrt(g[m - 1]);
+        for (int32_t r = 0; r < m; ++r) {
+            G->ci[G->rp[i] + r] = idx[r];
+            G->val[G->rp[i] + r] = g[r] / sd;
+        }
+    }
+    free(M); free(e); free(g);
+    return st;
+}
+
+/*
+ * Relaxation weight of the FSAI smoother S = I - omega G^T G A, which needs
+ * omega rho(G^T G A) < 2 (eq. smoother).  rho(G^T G A) = rho(M) for
+ * M = G A G^T, and rho(M) <= rho(|M|) <= max_i (|M| v)_i / v_i for every
+ * positive vector v (the Collatz-Wielandt bound of the non-negative matrix
+ * |M|).  The paper gives no value; the reading taken is
+ * omega = (4/3) / rho_hat with rho_hat the smallest of these bounds over
+ * v_0 = 1 and ten power steps v_{k+1} = |M| v_k / max_i (|M| v_k)_i, so
+ * omega rho <= 4/3 as for Jacobi (v_0 alone gives the Gershgorin bound).
+ * M is formed by the sparse product of this file (G A first, then
+ * (G A) G^T); products |M| v are summed in CSR order from 0.0.
+ */
+int orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega) {
+    orc_csr GT = {0, 0, NULL, NULL, NULL}, GA = {0, 0, NULL, NULL, NULL}, M = {0, 0, NULL, NULL, NULL};
+    int st = orc_transpose(G, &GT);
+    if (!st) st = orc_spgemm(G, A, &GA);
+    if (!st) st = orc_spgemm(&GA, &GT, &M);
+    int32_t n = M.nrows;
+    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!st && (!v || !w)) st = ORC_E_NOMEM;
+    if (!st) {
+        for (int32_t i = 0; i < n; ++i) v[i] = 1.0;
+        double best = 0.0;
+        for (int32_t k = 0; k <= 10; ++k) {
+            double bound = 0.0, wmax = 0.0;
+            for (int32_t i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int32_t e = M.rp[i]; e < M.rp[i + 1]; ++e) s = s + fabs(M.val[e]) * v[M.ci[e]];
+                w[i] = s;
+                double q = s / v[i];
+                if (q > bound) bound = q;
+                if (s > wmax) wmax = s;
+            }
+            if (k == 0 || bound < best) best = bound;
+            for (int32_t i = 0; i < n; ++i) v[i] = w[i] / wmax;
+        }
+        *omega = (4.0 / 3.0) / best;
+    }
+    free(v); free(w);
+    orc_csr_free(&GT); orc_csr_free(&GA); orc_csr_free(&M);
+    return st;
+}
+
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
     orc_csr A, P, R;
+    orc_csr G, GT;           /* FSAI smoother factor and its transpose (FSAI only) */
     uint8_t *strong;
     int32_t *stcnt;
     int8_t *cf;
@@ -460,6 +560,7 @@ void orc_destroy(orc_hier *h) {
     for (int32_t l = 0; l < ORC_MAXLEV; ++l) {
         orc_level *L = &h->lev[l];
         orc_csr_free(&L->A); orc_csr_free(&L->P); orc_csr_free(&L->R);
+        orc_csr_free(&L->G); orc_csr_free(&L->GT);
         free(L->strong); free(L->stcnt); free(L->cf); free(L->dinv);
     }
     free(h->L);
@@ -507,7 +608,16 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
             if (d < 0 || !(av[d] > 0.0)) { orc_destroy(h); return ORC_E_NOT_SPD; }
             L->dinv[i] = 1.0 / av[d];
         }
-        L->omega = h->prm.omega > 0.0 ? h->prm.omega : orc_gershgorin_omega(nl, arp, aci, av);
+        if (h->prm.smoother == ORC_SMOOTH_FSAI) {
+            st = orc_fsai(&L->A, &L->G);
+            if (!st) st = orc_transpose(&L->G, &L->GT);
+            double w = 0.0;
+            if (!st && !(h->prm.omega > 0.0)) st = orc_fsai_omega(&L->A, &L->G, &w);
+            if (st) { orc_destroy(h); return st; }
+            L->omega = h->prm.omega > 0.0 ? h->prm.omega : w;
+        } else {
+            L->omega = h->prm.omega > 0.0 ? h->prm.omega : orc_gershgorin_omega(nl, arp, aci, av);
+        }
         orc_strength(nl, arp, aci, av, h->prm.theta, L->strong, L->stcnt);
         st = orc_pmis(nl, arp, aci, L->strong, L->stcnt, h->prm.seed, l, L->cf, &L->rounds);
         if (st) { orc_destroy(h); return st; }
@@ -525,7 +635,7 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
     }
     /* last level: discard any coarsening data computed before a stall */
     orc_level *Lc = &h->lev[l];
-    orc_csr_free(&Lc->P); orc_csr_free(&Lc->R);
+    orc_csr_free(&Lc->P); orc_csr_free(&Lc->R); orc_csr_free(&Lc->G); orc_csr_free(&Lc->GT);
     h->nlev = l + 1;
     int32_t nL = Lc->A.nrows;
     if (nL > 8192) { orc_destroy(h); return ORC_E_COARSE; }
@@ -573,6 +683,7 @@ int orc_export(const orc_hier *h, int32_t l, int32_t what, void *a, void *b, voi
     case ORC_X_OMEGA: if (last) return ORC_E_ARG; memcpy(a, &L->omega, sizeof(double)); return ORC_OK;
     case ORC_X_STCNT: if (last) return ORC_E_ARG; memcpy(a, L->stcnt, sizeof(int32_t) * (size_t)n); return ORC_OK;
     case ORC_X_ROUNDS: if (last) return ORC_E_ARG; memcpy(a, &L->rounds, sizeof(int32_t)); return ORC_OK;
+    case ORC_X_G: if (last || !L->G.rp) return ORC_E_ARG; copy_out_csr(&L->G, a, b, c); return ORC_OK;
     case ORC_X_CHOL: if (!last) return ORC_E_ARG; memcpy(a, h->L, sizeof(double) * (size_t)n * (size_t)n); return ORC_OK;
     default: return ORC_E_ARG;
     }
@@ -588,42 +699,61 @@ static void spmv(const orc_csr *A, const double *s, double *t) {
 }
 
 /*
- * One V-cycle z = M_l y (Alg. AMG application in a V-cycle) with Jacobi
- * smoothing s <- s + omega D^{-1} (y - A s) (eq. smoother, M = D).
- * nu_pre steps from s = 0 (the first of them is s = omega D^{-1} y, since
- * A 0 = 0), residual, restriction by R = P^T, recursion, prolongation and
- * correction, nu_post steps.  On the last level, z = L^{-T} L^{-1} y.
- * The scaled inverse diagonal is formed as (omega * dinv_i).
+ * One V-cycle z = M_l y (Alg. AMG application in a V-cycle).  Smoothing is
+ * s <- s + omega M^{-1} (y - A s) (eq. smoother) with M = D (Jacobi; the
+ * scaled inverse diagonal formed as omega * dinv_i) or M^{-1} = G^T G
+ * (FSAI, eq. smo: u = G d, w = G^T u, s_i + omega * w_i).  nu_pre steps from
+ * s = 0 (the first of them is s = omega M^{-1} y, since A 0 = 0), residual,
+ * restriction by R = P^T, recursion, prolongation and correction, nu_post
+ * steps.  On the last level, z = L^{-T} L^{-1} y.
  */
-static void vcycle_level(const orc_hier *h, int32_t l, const double *y, double *z) {
-    const orc_level *L = &h->lev[l];
+static void smooth_step(const orc_level *L, int fsai, int first, const double *y, double *s, double *t,
+                        double *u, double *w) {
     int32_t n = L->A.nrows;
-    if (l == h->nlev - 1) { orc_chol_solve(n, h->L, y, z); return; }
-    int32_t nc = L->P.ncols;
-    double *s = z;   /* the smoothed iterate lives in the output */
-    double *t = (double *)malloc(sizeof(double) * (size_t)n);
-    double *yc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
-    double *dc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
-    for (int32_t i = 0; i < n; ++i) s[i] = 0.0;
-    for (int32_t it = 0; it < h->prm.nu_pre; ++it) {
-        if (it == 0) {
+    if (!fsai) {
+        if (first) {
             for (int32_t i = 0; i < n; ++i) s[i] = (L->omega * L->dinv[i]) * y[i];
         } else {
             spmv(&L->A, s, t);
             for (int32_t i = 0; i < n; ++i) s[i] = s[i] + (L->omega * L->dinv[i]) * (y[i] - t[i]);
         }
+        return;
     }
+    if (first) {
+        spmv(&L->G, y, u);
+        spmv(&L->GT, u, w);
+        for (int32_t i = 0; i < n; ++i) s[i] = L->omega * w[i];
+    } else {
+        spmv(&L->A, s, t);
+        for (int32_t i = 0; i < n; ++i) t[i] = y[i] - t[i];
+        spmv(&L->G, t, u);
+        spmv(&L->GT, u, w);
+        for (int32_t i = 0; i < n; ++i) s[i] = s[i] + L->omega * w[i];
+    }
+}
+
+static void vcycle_level(const orc_hier *h, int32_t l, const double *y, double *z) {
+    const orc_level *L = &h->lev[l];
+    int32_t n = L->A.nrows;
+    if (l == h->nlev - 1) { orc_chol_solve(n, h->L, y, z); return; }
+    int32_t nc = L->P.ncols;
+    int fsai = h->prm.smoother == ORC_SMOOTH_FSAI;
+    double *s = z;   /* the smoothed iterate lives in the output */
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    double *u = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *yc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double *dc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    for (int32_t i = 0; i < n; ++i) s[i] = 0.0;
+    for (int32_t it = 0; it < h->prm.nu_pre; ++it) smooth_step(L, fsai, it == 0, y, s, t, u, w);
     spmv(&L->A, s, t);
     for (int32_t i = 0; i < n; ++i) t[i] = y[i] - t[i];      /* r = y - A s */
     spmv(&L->R, t, yc);                                       /* y_{l+1} = P^T r */
     vcycle_level(h, l + 1, yc, dc);
     spmv(&L->P, dc, t);                                       /* d_l = P d_{l+1} */
     for (int32_t i = 0; i < n; ++i) s[i] = s[i] + t[i];
-    for (int32_t it = 0; it < h->prm.nu_post; ++it) {
-        spmv(&L->A, s, t);
-        for (int32_t i = 0; i < n; ++i) s[i] = s[i] + (L->omega * L->dinv[i]) * (y[i] - t[i]);
-    }
-    free(t); free(yc); free(dc);
+    for (int32_t it = 0; it < h->prm.nu_post; ++it) smooth_step(L, fsai, 0, y, s, t, u, w);
+    free(t); free(u); free(w); free(yc); free(dc);
 }
 
 void orc_vcycle(const orc_hier *h, const double *y, double *z) { vcycle_level(h, 0, y, z); }

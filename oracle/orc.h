@@ -45,7 +45,9 @@ typedef struct {
     int32_t  max_levels;
     int32_t  max_coarse;
     int32_t  max_iter;
+    int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D) or ORC_SMOOTH_FSAI (M^{-1} = G^T G) */
 } orc_params;
+enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
 
 void orc_params_default(orc_params *p);
 
@@ -64,6 +66,10 @@ int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
 int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */
 void orc_chol_solve(int32_t n, const double *L, const double *y, double *z);
 double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
+/* static FSAI factor G (lower triangular, pattern of the lower triangle of A) */
+int  orc_fsai(const orc_csr *A, orc_csr *G);
+/* omega = (4/3) / max_i sum_j |(G A G^T)_ij| */
+int  orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega);
 void orc_csr_free(orc_csr *m);
 void orc_free(void *p);
 
@@ -75,7 +81,7 @@ int  orc_num_levels(const orc_hier *h);
 /* sizes of level l: n, nnz(A), nnz(P) (0 on the coarsest), n of level l+1 (0 on the coarsest) */
 int  orc_level_sizes(const orc_hier *h, int32_t l, int32_t *n, int32_t *nnzA, int32_t *nnzP, int32_t *nc);
 enum { ORC_X_A = 0, ORC_X_P = 1, ORC_X_R = 2, ORC_X_CF = 3, ORC_X_STRONG = 4, ORC_X_DINV = 5,
-       ORC_X_OMEGA = 6, ORC_X_CHOL = 7, ORC_X_STCNT = 8, ORC_X_ROUNDS = 9 };
+       ORC_X_OMEGA = 6, ORC_X_CHOL = 7, ORC_X_STCNT = 8, ORC_X_ROUNDS = 9, ORC_X_G = 10 };
 int  orc_export(const orc_hier *h, int32_t l, int32_t what, void *a, void *b, void *c);
 /* z = M y : one V-cycle */
 void orc_vcycle(const orc_hier *h, const double *y, double *z);

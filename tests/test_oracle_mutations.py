@@ -1,5 +1,6 @@
 """Plant plausible mistakes in a copy of the oracle source and check that
-the pins in test_oracle.py catch every one of them (CPU only)."""
+the pins in test_oracle.py and test_oracle_fsai.py catch every one of
+them (CPU only)."""
 import os
 import subprocess
 import sys
@@ -39,13 +40,20 @@ MUTATIONS = [
      "for (int32_t i = 0; i < n; ++i) t[i] = t[i] - y[i];"),
     ("pcg_beta_sign", "p[i] = z[i] + beta * p[i];", "p[i] = z[i] - beta * p[i];"),
     ("pcg_stop_nonstrict", "if (rtol > 0.0 && rn < rtol * bn) break;", "if (rtol > 0.0 && rn <= 10 * rtol * bn) break;"),
+    ("fsai_no_scaling", "G->val[G->rp[i] + r] = g[r] / sd;", "G->val[G->rp[i] + r] = g[r];"),
+    ("fsai_scale_not_sqrt", "double sd = sqrt(g[m - 1]);", "double sd = g[m - 1];"),
+    ("fsai_wrong_unit_vector", "e[r] = r == m - 1 ? 1.0 : 0.0;", "e[r] = r == 0 ? 1.0 : 0.0;"),
+    ("fsai_G_twice", "spmv(&L->G, y, u);\n        spmv(&L->GT, u, w);", "spmv(&L->G, y, u);\n        spmv(&L->G, u, w);"),
+    ("fsai_omega_no_abs", "s = s + fabs(M.val[e]) * v[M.ci[e]];", "s = s + M.val[e] * v[M.ci[e]];"),
+    ("fsai_step_sign", "s[i] = s[i] + L->omega * w[i];", "s[i] = s[i] - L->omega * w[i];"),
 ]
 
 
 def _run_pins(libpath):
     env = dict(os.environ, CAMG_ORACLE_LIB=libpath)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                        os.path.join(ROOT, "tests", "test_oracle.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_fsai.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode
 
