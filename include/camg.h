@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 1
+#define CAMG_ABI_VERSION 2
 
 typedef struct camg_hier *camg_handle;
 
@@ -54,18 +54,25 @@ typedef enum {
 } camg_status;
 
 enum { CAMG_FP64 = 0, CAMG_MIXED_FP32 = 1 };
+/* Smoother (Section 2, eq. smoother): Jacobi (M = D, the default) or the
+ * factorised sparse approximate inverse M^{-1} = G^T G (eq. smo; here the
+ * static factor on the pattern of the lower triangle of A). */
+enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1 };
 
 /* Hierarchy and solver parameters. */
 typedef struct {
     double   theta;       /* strength threshold; default 0.25 */
     uint64_t seed;        /* PMIS random seed; level l, point i uses splitmix64 draw (l << 40) + i */
-    int32_t  nu_pre;      /* Jacobi steps before the coarse correction; default 1 */
-    int32_t  nu_post;     /* Jacobi steps after it; default 1 (equal values keep M symmetric) */
-    double   omega;       /* <= 0: (4/3) / max_i(sum_j |a_ij| / a_ii) per level; > 0: fixed */
+    int32_t  nu_pre;      /* smoothing steps before the coarse correction; default 1 */
+    int32_t  nu_post;     /* smoothing steps after it; default 1 (equal values keep M symmetric) */
+    double   omega;       /* <= 0: per level, Jacobi (4/3) / max_i(sum_j |a_ij| / a_ii), FSAI (4/3) / rho_hat
+                             with rho_hat the Collatz-Wielandt bound of |G A G^T| (10 power steps); > 0: fixed */
     int32_t  max_levels;  /* default 25 */
     int32_t  max_coarse;  /* a level with at most this many unknowns is solved directly; default 256 */
     int32_t  precision;   /* CAMG_FP64 or CAMG_MIXED_FP32 (FP32 V-cycle inside FP64 PCG) */
     int32_t  max_iter;    /* PCG iteration limit; default 1000 */
+    int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 128 entries
+                             on or below the diagonal per row, and runs on the single-system path only */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32
@@ -254,10 +261,12 @@ camg_status camg_level_sizes(camg_handle h, int32_t l, int32_t *n, int64_t *nnz_
  *   CAMG_X_CF: a = int8[n] (1 = C, -1 = F);   CAMG_X_STRONG: a = uint8[nnz(A_l)];
  *   CAMG_X_DINV: a = double[n] (1 / a_ii);    CAMG_X_OMEGA: a = double[1];
  *   CAMG_X_STCNT: a = int32[n] (|S_i^T|);      CAMG_X_COARSE_INV: a = double[n*n] (last level:
- *   the dense inverse applied by the coarse solve, row-major).
+ *   the dense inverse applied by the coarse solve, row-major);
+ *   CAMG_X_G (FSAI smoother): the factor G as CSR like CAMG_X_A; its nonzero count is the number
+ *   of entries of A_l on or below the diagonal.
  */
 enum { CAMG_X_A = 0, CAMG_X_P = 1, CAMG_X_R = 2, CAMG_X_CF = 3, CAMG_X_STRONG = 4, CAMG_X_DINV = 5,
-       CAMG_X_OMEGA = 6, CAMG_X_COARSE_INV = 7, CAMG_X_STCNT = 8 };
+       CAMG_X_OMEGA = 6, CAMG_X_COARSE_INV = 7, CAMG_X_STCNT = 8, CAMG_X_G = 9 };
 camg_status camg_export_level(camg_handle h, int32_t l, int32_t what, void *a, void *b, void *c);
 
 /*

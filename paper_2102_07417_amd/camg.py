@@ -19,7 +19,7 @@ LIBPATH = os.path.join(HERE, "libcamg.so")
 OK, E_MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM, E_DEVICE, E_BUSY = (
     0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
 FP64, MIXED_FP32 = 0, 1
-X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_COARSE_INV, X_STCNT = range(9)
+X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_COARSE_INV, X_STCNT, X_G = range(10)
 MAX_LEVELS = 32
 
 EXPORTED = [
@@ -31,13 +31,14 @@ EXPORTED = [
     "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy", "camg_solve_batch_dev",
 ]
 OPT_GRAPH = 1
+SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
 OPT_AUTOTUNE = 2
 
 
 class camg_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
-                ("precision", C.c_int32), ("max_iter", C.c_int32)]
+                ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32)]
 
 
 class camg_info_t(C.Structure):
@@ -464,6 +465,16 @@ class Solver:
 
     def R(self, l):
         return self._csr(l, X_R)
+
+    def G(self, l):
+        """FSAI factor of level l (the handle must use the FSAI smoother)."""
+        n, _, rp_a, ci_a, _ = self.A(l)
+        nnz = int(sum(np.count_nonzero(ci_a[rp_a[i]:rp_a[i + 1]] <= i) for i in range(n)))
+        rp = np.zeros(n + 1, np.int32)
+        ci = np.zeros(max(nnz, 1), np.int32)
+        v = np.zeros(max(nnz, 1))
+        _check(camg_export_level(self.h, l, X_G, rp, ci, v))
+        return (n, n, rp, ci[:nnz], v[:nnz])
 
     def _vec(self, l, what, dtype, size=None):
         n = self.sizes(l)[0]

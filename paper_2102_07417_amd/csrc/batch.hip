@@ -385,6 +385,7 @@ void solve_batch(std::vector<Hier *> &hs, const double *const *b, double *const 
         if (h->prm.precision != prec) fail(CAMG_E_ARG, "all handles of a batch must have the same precision");
         if (h->prm.nu_pre != 1 || h->prm.nu_post != 1)
             fail(CAMG_E_ARG, "the batched solver runs one smoothing step each way");
+        if (h->prm.smoother != CAMG_SMOOTH_JACOBI) fail(CAMG_E_ARG, "the batched solver runs the Jacobi smoother only");
         if (h->device != hs[0]->device) fail(CAMG_E_ARG, "all handles of a batch must live on one device");
     }
     std::vector<BOut> out;

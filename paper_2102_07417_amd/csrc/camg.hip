@@ -169,6 +169,7 @@ void check_params(const camg_params &p) {
     if (p.max_iter < 0) fail(CAMG_E_ARG, "max_iter must be >= 0");
     if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
+    if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI) fail(CAMG_E_ARG, "unknown smoother");
 }
 
 // ---------------------------------------------------------------- set-up
@@ -267,6 +268,48 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         scale_vec(nl, L.omega, L.dinv, L.wd, s);
         L.awd = h.pool.alloc<double>(padded(nz));
         scale_columns(L.A, L.wd, L.awd, s);
+        if (prm.smoother == CAMG_SMOOTH_FSAI) {
+            // FSAI factor on the lower pattern of A_l, its transpose, omega (eq. smo, eq. smoother)
+            int32_t *gcnt = lt.alloc<int32_t>(nl);
+            const int mmax = fsai_counts(nl, L.A.rp, L.A.ci, gcnt, lt, s);
+            int64_t *grp64 = lt.alloc<int64_t>((size_t)nl + 1);
+            scan_i32_to_i64(gcnt, grp64, nl, lt, s);
+            Csr &G = L.G;
+            G.nr = G.nc = nl;
+            G.nnz = read1(grp64 + nl, s);
+            G.rp = h.pool.alloc<int32_t>((size_t)nl + 1);
+            narrow_i64(grp64, G.rp, nl, s);
+            G.ci = h.pool.alloc<int32_t>(padded(G.nnz));
+            G.v = h.pool.alloc<double>(padded(G.nnz));
+            HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+            fsai_rows(L.A, G, mmax, flags, s);
+            int32_t gf[8];
+            HIPC(hipMemcpyAsync(gf, flags, sizeof(gf), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (gf[6]) fail(CAMG_E_ARG, "FSAI: a row has more than 128 entries on or below the diagonal");
+            if (gf[7]) fail(CAMG_E_NOT_SPD, "FSAI: a local matrix is not positive definite on level " +
+                                                std::to_string(l));
+            Csr &Gt = L.Gt;
+            Gt.nr = Gt.nc = nl;
+            Gt.nnz = G.nnz;
+            int32_t *gcc = lt.alloc<int32_t>(nl);
+            column_counts(G, gcc, s);
+            int64_t *gtrp64 = lt.alloc<int64_t>((size_t)nl + 1);
+            scan_i32_to_i64(gcc, gtrp64, nl, lt, s);
+            Gt.rp = h.pool.alloc<int32_t>((size_t)nl + 1);
+            narrow_i64(gtrp64, Gt.rp, nl, s);
+            Gt.ci = h.pool.alloc<int32_t>(padded(Gt.nnz));
+            Gt.v = h.pool.alloc<double>(padded(Gt.nnz));
+            transpose_csr(G, Gt, lt, s);
+            if (prm.omega > 0.0) {
+                L.omega = prm.omega;
+            } else {
+                Csr GA, M;
+                spgemm(G, L.A, GA, lt, lt, s);
+                spgemm(GA, Gt, M, lt, lt, s);
+                L.omega = (4.0 / 3.0) / cw_bound(M, lt, s);
+            }
+        }
         // strength and PMIS
         L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
         L.stcnt = h.pool.alloc<int32_t>(nl);
@@ -352,9 +395,14 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         Level &L = h.lev[l];
         const int nl = L.A.nr;
         L.cA = make_cfg(h, L.A, tmp, s);
+        const bool fsai = prm.smoother == CAMG_SMOOTH_FSAI && l < h.nlev - 1;
         if (l < h.nlev - 1) {
             L.cP = make_cfg(h, L.P, tmp, s);
             L.cR = make_cfg(h, L.R, tmp, s);
+        }
+        if (fsai) {
+            L.cG = make_cfg(h, L.G, tmp, s);
+            L.cGt = make_cfg(h, L.Gt, tmp, s);
         }
         if (!mixed) {
             if (l > 0) {
@@ -376,10 +424,14 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                 to_f32(nl, L.wd, L.wd32, s);
                 L.awd32 = h.pool.alloc<float>(padded(L.A.nnz));
                 to_f32(L.A.nnz, L.awd, L.awd32, s);
+                if (fsai) {
+                    alloc_f32_copy(h.pool, L.G, s);
+                    alloc_f32_copy(h.pool, L.Gt, s);
+                }
             }
         }
-        // extra buffer for more than one smoothing step
-        if (prm.nu_pre > 1 || prm.nu_post > 1) {
+        // extra buffer for more than one smoothing step (FSAI: for u = G d)
+        if (prm.nu_pre > 1 || prm.nu_post > 1 || fsai) {
             if (!mixed) L.t = h.pool.alloc<double>(nl);
             else L.t32 = h.pool.alloc<float>(nl);
         }
@@ -431,8 +483,46 @@ int32_t *st_count(PcgState *st, size_t off) { return reinterpret_cast<int32_t *>
 
 // Pre-smoothing (nu_pre steps from s = 0) and residual on level l.
 // Returns the buffer that holds s.
+// FSAI pre-smoothing (eq. smo): s = omega G^T G y, then nu_pre - 1 steps
+// s += omega G^T G (y - A s) in place, then r = y - A s.  u = G d lives in t,
+// d in r.
+template <class T, class TY>
+T *fsai_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
+    T *sv = VT<T>::s(L), *tv = VT<T>::t(L), *rv = VT<T>::r(L);
+    const T om = (T)L.omega;
+    vc_gmul<T, TY>(L.G, L.cG, y, tv, st, s);
+    vc_fsai_first<T>(L.Gt, L.cGt, om, tv, sv, st, s);
+    for (int it = 1; it < h.prm.nu_pre; ++it) {
+        vc_resid<T, TY>(L.A, L.cA, y, sv, rv, st, s);
+        vc_gmul<T, T>(L.G, L.cG, rv, tv, st, s);
+        vc_fsai_step<T, TY, T, false>(L.Gt, L.cGt, om, tv, sv, nullptr, sv, nullptr, nullptr, st, s);
+    }
+    vc_resid<T, TY>(L.A, L.cA, y, sv, rv, st, s);
+    return sv;
+}
+
+// FSAI post-smoothing: nu_post steps, the last one into z (with dot: the
+// partials of y.z into h.prz, their count into st->n_rz)
+template <class T, class TY, class TZ>
+void fsai_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
+    T *tv = VT<T>::t(L), *rv = VT<T>::r(L);
+    const T om = (T)L.omega;
+    for (int it = 0; it < h.prm.nu_post; ++it) {
+        vc_resid<T, TY>(L.A, L.cA, y, sv, rv, st, s);
+        vc_gmul<T, T>(L.G, L.cG, rv, tv, st, s);
+        if (it + 1 < h.prm.nu_post)
+            vc_fsai_step<T, TY, T, false>(L.Gt, L.cGt, om, tv, sv, nullptr, sv, nullptr, nullptr, st, s);
+        else if (dot)
+            vc_fsai_step<T, TY, TZ, true>(L.Gt, L.cGt, om, tv, sv, y, z, h.prz,
+                                           st_count(st, offsetof(PcgState, n_rz)), st, s);
+        else
+            vc_fsai_step<T, TY, TZ, false>(L.Gt, L.cGt, om, tv, sv, nullptr, z, nullptr, nullptr, st, s);
+    }
+}
+
 template <class T, class TY>
 T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
+    if (h.prm.smoother == CAMG_SMOOTH_FSAI) return fsai_pre<T, TY>(h, L, y, st, s);
     T *sv = VT<T>::s(L), *tv = VT<T>::t(L);
     vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), VT<T>::awd(L), y, sv, VT<T>::r(L), st, s);
     if (h.prm.nu_pre > 1) {
@@ -449,6 +539,10 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
 // the partials of y.z into h.prz and their count into st->n_rz.
 template <class T, class TY, class TZ>
 void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
+    if (h.prm.smoother == CAMG_SMOOTH_FSAI) {
+        fsai_post<T, TY, TZ>(h, L, y, sv, z, dot, st, s);
+        return;
+    }
     T *tv = VT<T>::t(L);
     for (int it = 0; it + 1 < h.prm.nu_post; ++it) {
         T *out = (tv == sv) ? VT<T>::s(L) : tv;
@@ -475,7 +569,7 @@ void vcycle_part(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, 
         return;
     }
     // the level-0 iterate ends up in s or t depending on nu_pre
-    T *s0 = (h.prm.nu_pre % 2 == 1) ? VT<T>::s(h.lev[0]) : VT<T>::t(h.lev[0]);
+    T *s0 = (h.prm.smoother == CAMG_SMOOTH_FSAI || h.prm.nu_pre % 2 == 1) ? VT<T>::s(h.lev[0]) : VT<T>::t(h.lev[0]);
     if (head) {
         T *sv[CAMG_MAX_LEVELS] = {};
         for (int l = 0; l < L; ++l) {
@@ -735,6 +829,7 @@ void camg_params_default(camg_params *p) {
     p->max_coarse = 256;
     p->precision = CAMG_FP64;
     p->max_iter = 1000;
+    p->smoother = CAMG_SMOOTH_JACOBI;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
@@ -876,6 +971,10 @@ camg_status camg_export_level(camg_handle hh, int32_t l, int32_t what, void *a, 
         case CAMG_X_DINV: HIPC(hipMemcpy(a, L.dinv, sizeof(double) * n, hipMemcpyDeviceToHost)); break;
         case CAMG_X_OMEGA: std::memcpy(a, &L.omega, sizeof(double)); break;
         case CAMG_X_STCNT: HIPC(hipMemcpy(a, L.stcnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost)); break;
+        case CAMG_X_G:
+            if (!L.G.rp) fail(CAMG_E_ARG, "the handle does not use the FSAI smoother");
+            copy_csr_out(L.G, a, b, c);
+            break;
         case CAMG_X_COARSE_INV:
             if (!last) fail(CAMG_E_ARG, "the dense inverse exists on the last level only");
             HIPC(hipMemcpy(a, h->cinv, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToHost));

@@ -110,6 +110,9 @@ struct Level {
     double *y = nullptr, *s = nullptr, *r = nullptr, *z = nullptr, *t = nullptr;
     float *y32 = nullptr, *s32 = nullptr, *r32 = nullptr, *z32 = nullptr, *t32 = nullptr;
     RowCfg cA, cP, cR;
+    // FSAI smoother (M^{-1} = G^T G), when selected
+    Csr G, Gt;
+    RowCfg cG, cGt;
 };
 
 // Scalars of one PCG recurrence, resident on the device.
@@ -197,7 +200,13 @@ void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *st
                   int32_t *cnt, hipStream_t s);
 void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
                  const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s);
-void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
+void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
+// FSAI smoother: counts of entries on or below the diagonal per row (returns
+// the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:
+// row too long, flags[7]: not SPD), the Collatz-Wielandt bound of |M|
+int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool &tmp, hipStream_t s);
+void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
+double cw_bound(const Csr &M, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
 void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
 void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax_bits, int32_t *flags, hipStream_t s);
@@ -238,6 +247,15 @@ template <class T>
 void vc_restrict(const Csr &R, const RowCfg &c, const T *r, T *yc, const PcgState *st, hipStream_t str);
 template <class T>
 void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState *st, hipStream_t str);
+// FSAI smoothing (M^{-1} = G^T G): u = G y; s = omega G^T u; z = s + omega G^T u
+// (z may be s; with DOT the partials of y.z)
+template <class T, class TY>
+void vc_gmul(const Csr &G, const RowCfg &c, const TY *y, T *u, const PcgState *st, hipStream_t str);
+template <class T>
+void vc_fsai_first(const Csr &Gt, const RowCfg &c, T omega, const T *u, T *s, const PcgState *st, hipStream_t str);
+template <class T, class TY, class TZ, bool DOT>
+void vc_fsai_step(const Csr &Gt, const RowCfg &c, T omega, const T *u, const T *s, const TY *y, TZ *z,
+                  double *partials, int32_t *nout, const PcgState *st, hipStream_t str);
 template <class T>
 void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *st, hipStream_t str);
 // partial sums of y.z; returns the number of partials

@@ -1082,6 +1082,7 @@ int64_t engine_footprint(const Hier &h, int K) {
 
 Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     if (K < 1 || K > kMaxSlots || (K & (K - 1))) fail(CAMG_E_ARG, "slot count must be a power of two in [1, 64]");
+    if (h.prm.smoother != CAMG_SMOOTH_JACOBI) fail(CAMG_E_ARG, "the multi-RHS engine runs the Jacobi smoother only");
     std::unique_ptr<Engine> E(new Engine());
     E->h = &h;
     E->K = K;

@@ -463,6 +463,159 @@ __global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, dou
     }
 }
 
+
+// ------------------------------------------------------------------ FSAI smoother
+// Static FSAI factor G (M^{-1} = G^T G, G lower triangular on the pattern of
+// the lower triangle of A): row i solves A(P_i, P_i) g = e_last with a dense
+// Cholesky factorisation and substitutions, then G(i, P_i) = g / sqrt(g_last).
+// The per-entry arithmetic (and its order) is the oracle's: the right-looking
+// factorisation applies to each entry the same subtractions, in the same
+// order of k, as a column-oriented one.
+
+// m_i = number of entries of row i on or below the diagonal; max m into *mmax
+__global__ void k_fsai_count(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, int32_t *mmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int m = 0;
+    if (i < n) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e) m += ci[e] <= i ? 1 : 0;
+        cnt[i] = m;
+    }
+    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)m);
+    if (threadIdx.x == 0) atomicMax(mmax, (int32_t)bm);
+}
+
+__device__ __forceinline__ double csr_lookup(const int32_t *rp, const int32_t *ci, const double *v, int i, int j) {
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo <= hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (ci[mid] == j) return v[mid];
+        if (ci[mid] < j) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return 0.0;
+}
+
+#define FSAI_SYNC()                                             \
+    do {                                                        \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                        \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+    } while (0)
+
+// one wavefront per row, the local matrix (m <= MAXM) in LDS
+template <int MAXM, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_fsai_rows(int n, const int32_t *__restrict__ arp,
+                                                        const int32_t *__restrict__ aci, const double *__restrict__ av,
+                                                        const int32_t *__restrict__ grp, int32_t *gci, double *gv,
+                                                        int32_t *flags) {
+    __shared__ double Ms[WPB][MAXM * MAXM];
+    __shared__ double ws[WPB][MAXM], zs[WPB][MAXM];
+    __shared__ int idx[WPB][MAXM];
+    __shared__ int bad[WPB];
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int i = blockIdx.x * WPB + w;
+    if (i >= n) return;  // the whole wavefront
+    const int m = grp[i + 1] - grp[i];
+    if (m < 1 || m > MAXM) {  // uniform over the wavefront
+        if (lane == 0) atomicOr(&flags[6], 1);
+        return;
+    }
+    double *M = Ms[w];
+    for (int r = lane; r < m; r += 64) idx[w][r] = aci[arp[i] + r];
+    if (lane == 0) bad[w] = 0;
+    FSAI_SYNC();
+    for (int t = lane; t < m * m; t += 64) {
+        const int r = t / m, c = t - (t / m) * m;
+        if (c <= r) M[r * m + c] = csr_lookup(arp, aci, av, idx[w][r], idx[w][c]);
+    }
+    FSAI_SYNC();
+    for (int k = 0; k < m; ++k) {
+        if (lane == 0) {
+            const double d = M[k * m + k];
+            if (!(d > 0.0)) bad[w] = 1;
+            else M[k * m + k] = sqrt(d);
+        }
+        FSAI_SYNC();
+        if (bad[w]) break;
+        const double lkk = M[k * m + k];
+        for (int r = k + 1 + lane; r < m; r += 64) M[r * m + k] = M[r * m + k] / lkk;
+        FSAI_SYNC();
+        const int q = m - k - 1;
+        for (int t = lane; t < q * q; t += 64) {
+            const int rr = t / q, cc = t - (t / q) * q;
+            if (cc <= rr) {
+                const int r = k + 1 + rr, c = k + 1 + cc;
+                M[r * m + c] = M[r * m + c] - M[r * m + k] * M[c * m + k];
+            }
+        }
+        FSAI_SYNC();
+    }
+    if (bad[w]) {
+        if (lane == 0) atomicOr(&flags[7], 1);
+        return;
+    }
+    if (lane == 0) {
+        double *wv = ws[w], *z = zs[w];
+        for (int r = 0; r < m; ++r) {
+            double t = r == m - 1 ? 1.0 : 0.0;
+            for (int k = 0; k < r; ++k) t = t - M[r * m + k] * wv[k];
+            wv[r] = t / M[r * m + r];
+        }
+        for (int r = m - 1; r >= 0; --r) {
+            double t = wv[r];
+            for (int k = r + 1; k < m; ++k) t = t - M[k * m + r] * z[k];
+            z[r] = t / M[r * m + r];
+        }
+        if (!(z[m - 1] > 0.0)) bad[w] = 1;
+    }
+    FSAI_SYNC();
+    if (bad[w]) {
+        if (lane == 0) atomicOr(&flags[7], 1);
+        return;
+    }
+    const double sd = sqrt(zs[w][m - 1]);
+    const int o = grp[i];
+    for (int r = lane; r < m; r += 64) {
+        gci[o + r] = idx[w][r];
+        gv[o + r] = zs[w][r] / sd;
+    }
+}
+
+// Collatz-Wielandt step on |M|: w = |M| v (CSR order), bound = max w_i / v_i,
+// wmax = max w_i (non-negative doubles compared through their bit patterns)
+__global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *v, double *w,
+                          unsigned long long *bmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double q = 0.0, s = 0.0;
+    if (i < n) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e) s = s + fabs(mv[e]) * v[ci[e]];
+        w[i] = s;
+        q = s / v[i];
+    }
+    const unsigned long long bq = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
+    const unsigned long long bs = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(s));
+    if (threadIdx.x == 0) {
+        atomicMax(&bmax[0], bq);
+        atomicMax(&bmax[1], bs);
+    }
+}
+
+// v = w / wmax; best = min(best, bound) (the first bound when k == 0)
+__global__ void k_cw_norm(int n, double *v, const double *w, const unsigned long long *bmax, double *best, int k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double wmax = __longlong_as_double((long long)bmax[1]);
+    if (i < n) v[i] = w[i] / wmax;
+    if (i == 0) {
+        const double bound = __longlong_as_double((long long)bmax[0]);
+        if (k == 0 || bound < *best) *best = bound;
+    }
+}
+
+__global__ void k_fill_d(int n, double *v, double x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = x;
+}
+
 __global__ void k_max_row(int n, const int32_t *rp, int32_t *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int len = i < n ? rp[i + 1] - rp[i] : 0;
@@ -596,6 +749,45 @@ void chol_inverse(int n, const double *L, double *X, hipStream_t s) {
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s) {
     k_tile_starts<<<nblocks(n + 1), kBlock, 0, s>>>(n, rp, W, ntiles, tstart);
     HIPC(hipGetLastError());
+}
+
+
+int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool &tmp, hipStream_t s) {
+    int32_t *d = tmp.alloc<int32_t>(1);
+    HIPC(hipMemsetAsync(d, 0, sizeof(int32_t), s));
+    k_fsai_count<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, cnt, d);
+    HIPC(hipGetLastError());
+    int32_t h = 0;
+    HIPC(hipMemcpyAsync(&h, d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return h;
+}
+
+void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
+    const int n = A.nr;
+    if (mmax <= 16) k_fsai_rows<16, 4><<<(n + 3) / 4, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 32) k_fsai_rows<32, 2><<<(n + 1) / 2, 128, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 64) k_fsai_rows<64, 1><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 128) k_fsai_rows<128, 1><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else fail(CAMG_E_ARG, "FSAI: a row has more than 128 entries on or below the diagonal");
+    HIPC(hipGetLastError());
+}
+
+double cw_bound(const Csr &M, Pool &tmp, hipStream_t s) {
+    const int n = M.nr;
+    double *v = tmp.alloc<double>(n), *w = tmp.alloc<double>(n), *best = tmp.alloc<double>(1);
+    unsigned long long *bmax = tmp.alloc<unsigned long long>(2 * 11);
+    HIPC(hipMemsetAsync(bmax, 0, sizeof(unsigned long long) * 2 * 11, s));
+    k_fill_d<<<nblocks(n), kBlock, 0, s>>>(n, v, 1.0);
+    for (int k = 0; k <= 10; ++k) {
+        k_cw_step<<<nblocks(n), kBlock, 0, s>>>(n, M.rp, M.ci, M.v, v, w, bmax + 2 * k);
+        k_cw_norm<<<nblocks(n), kBlock, 0, s>>>(n, v, w, bmax + 2 * k, best, k);
+    }
+    HIPC(hipGetLastError());
+    double hb = 0.0;
+    HIPC(hipMemcpyAsync(&hb, best, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return hb;
 }
 
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s) {

@@ -300,6 +300,30 @@ struct ESpmv {
     __device__ Pre load(int i) const { return Pre{ADD ? out[i] : T(0)}; }
     __device__ void finish(int i, T acc, const Pre &p, double &) const { out[i] = ADD ? p.o + acc : acc; }
 };
+template <class T>
+struct EScale {  // out = omega * (A x)  (first FSAI step: s = omega G^T u)
+    T omega;
+    T *out;
+    struct Pre {};
+    __device__ Pre load(int) const { return Pre{}; }
+    __device__ void finish(int i, T acc, const Pre &, double &) const { out[i] = omega * acc; }
+};
+template <class T, class TY, class TZ>
+struct EAddScaled {  // z = s + omega (A x); dot += y.z when y is given  (FSAI step; z may be s)
+    T omega;
+    const T *s;
+    const TY *y;
+    TZ *z;
+    struct Pre {
+        T si;
+    };
+    __device__ Pre load(int i) const { return Pre{s[i]}; }
+    __device__ void finish(int i, T acc, const Pre &p, double &dot) const {
+        const TZ zo = (TZ)(p.si + omega * acc);
+        z[i] = zo;
+        if (y) dot += (double)y[i] * (double)zo;
+    }
+};
 struct EPQ {  // q = A p; dot += p.q
     const double *p;
     double *q;
@@ -600,6 +624,22 @@ void vc_prolong(const Csr &P, const RowCfg &c, const T *d, T *s, const PcgState 
     launch_rows<T, false>(P, c, GVec<T>{d}, ESpmv<T, true>{s}, nullptr, nullptr, st, str);
 }
 
+template <class T, class TY>
+void vc_gmul(const Csr &G, const RowCfg &c, const TY *y, T *u, const PcgState *st, hipStream_t str) {
+    launch_rows<T, false>(G, c, GVec<T, TY>{y}, ESpmv<T, false>{u}, nullptr, nullptr, st, str);
+}
+
+template <class T>
+void vc_fsai_first(const Csr &Gt, const RowCfg &c, T omega, const T *u, T *s, const PcgState *st, hipStream_t str) {
+    launch_rows<T, false>(Gt, c, GVec<T>{u}, EScale<T>{omega, s}, nullptr, nullptr, st, str);
+}
+
+template <class T, class TY, class TZ, bool DOT>
+void vc_fsai_step(const Csr &Gt, const RowCfg &c, T omega, const T *u, const T *s, const TY *y, TZ *z,
+                  double *partials, int32_t *nout, const PcgState *st, hipStream_t str) {
+    launch_rows<T, DOT>(Gt, c, GVec<T>{u}, EAddScaled<T, TY, TZ>{omega, s, y, z}, partials, nout, st, str);
+}
+
 template <class T>
 void coarse_solve(int n, const double *cinv, const T *y, T *z, const PcgState *st, hipStream_t str) {
     k_coarse<T><<<(n + 3) / 4, kBlock, 0, str>>>(n, cinv, y, z, st);
@@ -631,6 +671,24 @@ template void vc_restrict<float>(const Csr &, const RowCfg &, const float *, flo
 template void vc_prolong<double>(const Csr &, const RowCfg &, const double *, double *, const PcgState *,
                                  hipStream_t);
 template void vc_prolong<float>(const Csr &, const RowCfg &, const float *, float *, const PcgState *, hipStream_t);
+template void vc_gmul<double, double>(const Csr &, const RowCfg &, const double *, double *, const PcgState *,
+                                      hipStream_t);
+template void vc_gmul<float, float>(const Csr &, const RowCfg &, const float *, float *, const PcgState *, hipStream_t);
+template void vc_gmul<float, double>(const Csr &, const RowCfg &, const double *, float *, const PcgState *,
+                                     hipStream_t);
+template void vc_fsai_first<double>(const Csr &, const RowCfg &, double, const double *, double *, const PcgState *,
+                                    hipStream_t);
+template void vc_fsai_first<float>(const Csr &, const RowCfg &, float, const float *, float *, const PcgState *,
+                                   hipStream_t);
+#define INST_FSTEP(T, TY, TZ, D)                                                                                  \
+    template void vc_fsai_step<T, TY, TZ, D>(const Csr &, const RowCfg &, T, const T *, const T *, const TY *, TZ *, \
+                                             double *, int32_t *, const PcgState *, hipStream_t);
+INST_FSTEP(double, double, double, false)
+INST_FSTEP(double, double, double, true)
+INST_FSTEP(float, float, float, false)
+INST_FSTEP(float, double, float, false)
+INST_FSTEP(float, double, double, false)
+INST_FSTEP(float, double, double, true)
 template void coarse_solve<double>(int, const double *, const double *, double *, const PcgState *, hipStream_t);
 template void coarse_solve<float>(int, const double *, const float *, float *, const PcgState *, hipStream_t);
 

@@ -45,14 +45,14 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 1
+    assert lib.camg_abi_version() == 2
     for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
     p = camg.camg_params()
     lib.camg_params_default(C.byref(p))
     assert p.theta == 0.25 and p.nu_pre == 1 and p.nu_post == 1 and p.max_coarse == 256 and p.max_levels == 25
-    assert p.precision == camg.FP64 and p.omega == 0.0
+    assert p.precision == camg.FP64 and p.omega == 0.0 and p.smoother == camg.SMOOTH_JACOBI
 
 
 def test_argument_errors_without_device(lib):
@@ -71,8 +71,8 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "camg.h"
 int main(void) {
-  printf("params %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
-         offsetof(camg_params, precision), offsetof(camg_params, max_iter));
+  printf("params %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
+         offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother));
   printf("info %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
          offsetof(camg_completion, latency_ms));
@@ -84,7 +84,7 @@ int main(void) {
     out = dict((l.split()[0], [int(v) for v in l.split()[1:]])
                for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     P = camg.camg_params
-    assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset]
+    assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset]
     I = camg.camg_info_t
     assert out["info"] == [C.sizeof(I), I.nnz_p.offset]
     Q = camg.camg_completion

@@ -391,3 +391,65 @@ def test_multi_rhs_autotuned_schedules_are_bitwise_equal(camg):
             outs.append(X)
             s.close()
         assert torch.equal(outs[0], outs[1])
+
+
+# ----------------------------------------------------------------- FSAI smoother
+FSAI_CASES = ["poisson2d_64", "lognormal3d_24", "aniso3d_20", "elasticity_6"]
+
+
+@pytest.mark.parametrize("name", FSAI_CASES)
+def test_fsai_hierarchy_vcycle_and_solve(camg, name):
+    print(f"[gpu] fsai {name}", flush=True)
+    A = CASES[name]()
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), max_coarse=40,
+                                smoother=camg.SMOOTH_FSAI)
+    o = O.Hierarchy(A, max_coarse=40, smoother=O.SMOOTH_FSAI)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev - 1):
+        gg, og = g.G(l), o.G(l)
+        assert np.array_equal(gg[2], og[2]) and np.array_equal(gg[3], og[3]), f"G_{l} pattern"
+        assert np.array_equal(gg[4], og[4]), f"G_{l} values"
+        assert g.omega(l) == o.omega(l), f"omega_{l}"
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        y = rng.standard_normal(A.n)
+        dz = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+        g.vcycle_dev(_dev(y), dz)
+        torch.cuda.synchronize()
+        zo = o.vcycle(y)
+        assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-12 * np.linalg.norm(zo)
+    b = PB.rhs(A.n)
+    r = g.solve(b)
+    ro = o.solve(b, 1e-8)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+
+
+def test_fsai_two_steps_and_mixed(camg):
+    A = PB.lognormal3d(20, 2.0)
+    b = PB.rhs(A.n)
+    g = camg.Solver(A, smoother=camg.SMOOTH_FSAI, nu_pre=2, nu_post=2)
+    o = O.Hierarchy(A, smoother=O.SMOOTH_FSAI, nu_pre=2, nu_post=2)
+    y = np.random.default_rng(4).standard_normal(A.n)
+    dz = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    g.vcycle_dev(_dev(y), dz)
+    torch.cuda.synchronize()
+    zo = o.vcycle(y)
+    assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-12 * np.linalg.norm(zo)
+    r, ro = g.solve(b), o.solve(b, 1e-8)
+    assert abs(r.iters - ro.iters) <= 1 and np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+    gm = camg.Solver(A, smoother=camg.SMOOTH_FSAI, precision=camg.MIXED_FP32)
+    rm = gm.solve(b)
+    ro1 = O.Hierarchy(A, smoother=O.SMOOTH_FSAI).solve(b, 1e-8)
+    assert rm.status == camg.OK and rm.true_relres < 1e-8 and rm.iters <= ro1.iters + 5
+    assert np.linalg.norm(rm.x - ro1.x) / np.linalg.norm(ro1.x) < 1e-6
+    # the block engine and the many-systems kernel run Jacobi only
+    B = torch.from_numpy(PB.rhs_block(A.n, 2)).to("cuda:0")
+    with pytest.raises(camg.CamgError):
+        gm.solve_multi_dev(B, torch.zeros_like(B))
+    db = _dev(b)
+    with pytest.raises(camg.CamgError):
+        camg.solve_batch_dev([gm], [db], [torch.zeros_like(db)])
+    gm.close()
