@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--workload", default="lognormal3d_128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-fsai", action="store_true", help="skip the FSAI-smoother solves")
     ap.add_argument("--batched", type=int, default=32,
                     help="right-hand sides of the batched (block) run on aniso3d_160; 0 skips it")
     ap.add_argument("--only-batched", action="store_true", help="print only the batched run")
@@ -141,10 +142,11 @@ def main():
     stream = torch.cuda.current_stream()
     max_iter = 5000
 
-    def one_step(precision, profile=False):
+    def one_step(precision, profile=False, smoother=0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=max_iter)
+        s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=max_iter,
+                                    smoother=smoother)
         t1 = time.perf_counter()
         if profile:  # time the level-0 post-smoothing kernel on every 8th iteration
             camg.camg_profile(s.h, PROFILE_STRIDE)
@@ -186,6 +188,16 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
+
+    # the FSAI smoother (M^{-1} = G^T G) on the same system, FP64 and mixed
+    fsai = {}
+    if not args.no_fsai:
+        for prec, key in ((camg.FP64, "fp64"), (camg.MIXED_FP32, "mixed")):
+            one_step(prec, smoother=camg.SMOOTH_FSAI)
+            rs = [one_step(prec, smoother=camg.SMOOTH_FSAI) for _ in range(max(1, min(args.steps, 3)))]
+            fsai[key] = {"solve_ms": round(statistics.median(r["solve_ms"] for r in rs), 4),
+                         "setup_ms": round(statistics.median(r["setup_ms"] for r in rs), 4),
+                         "iters": rs[-1]["iters"], "true_relres": rs[-1]["true_relres"]}
 
     # host API on the same hierarchy: b copied in and x out over PCIe around the device solve
     sh = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, max_iter=max_iter)
@@ -243,6 +255,8 @@ def main():
         out["mixed"] = {"solve_ms": round(m_ms, 4), "setup_ms": round(statistics.median(r["setup_ms"] for r in mixed), 4),
                         "iters": mixed[-1]["iters"], "true_relres": mixed[-1]["true_relres"],
                         "speedup_vs_fp64": round(solve_ms / m_ms, 4), "rel_err_vs_fp64_gpu": err}
+    if fsai:
+        out["fsai_smoother"] = fsai
     if args.batched:
         out["batched"] = batched_run(args.batched, max(1, min(args.steps, 3)))
     if args.small_systems:

@@ -71,7 +71,7 @@ typedef struct {
     int32_t  max_coarse;  /* a level with at most this many unknowns is solved directly; default 256 */
     int32_t  precision;   /* CAMG_FP64 or CAMG_MIXED_FP32 (FP32 V-cycle inside FP64 PCG) */
     int32_t  max_iter;    /* PCG iteration limit; default 1000 */
-    int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 128 entries
+    int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 192 entries
                              on or below the diagonal per row, and runs on the single-system path only */
 } camg_params;
 

@@ -286,7 +286,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             int32_t gf[8];
             HIPC(hipMemcpyAsync(gf, flags, sizeof(gf), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
-            if (gf[6]) fail(CAMG_E_ARG, "FSAI: a row has more than 128 entries on or below the diagonal");
+            if (gf[6]) fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
             if (gf[7]) fail(CAMG_E_NOT_SPD, "FSAI: a local matrix is not positive definite on level " +
                                                 std::to_string(l));
             Csr &Gt = L.Gt;

@@ -502,82 +502,107 @@ __device__ __forceinline__ double csr_lookup(const int32_t *rp, const int32_t *c
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
     } while (0)
 
-// one wavefront per row, the local matrix (m <= MAXM) in LDS
-template <int MAXM, int WPB>
-__global__ void __launch_bounds__(WPB * 64) k_fsai_rows(int n, const int32_t *__restrict__ arp,
-                                                        const int32_t *__restrict__ aci, const double *__restrict__ av,
-                                                        const int32_t *__restrict__ grp, int32_t *gci, double *gv,
-                                                        int32_t *flags) {
-    __shared__ double Ms[WPB][MAXM * MAXM];
-    __shared__ double ws[WPB][MAXM], zs[WPB][MAXM];
+// TPR threads (one wavefront, or a 256-thread workgroup for long rows) per
+// row; the lower triangle of the local matrix (m <= MAXM) packed row by row
+// in LDS: entry (r, c), c <= r, at r (r + 1) / 2 + c.  Both substitutions
+// go column by column (the oracle's order for every entry): unknown k is
+// divided by its pivot, then removed from the remaining equations in
+// parallel.
+template <int TPR>
+__device__ __forceinline__ void fsai_sync() {
+    if constexpr (TPR == 64) {
+        FSAI_SYNC();
+    } else {
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int tri_row(int t) {
+    int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    return r;
+}
+
+template <int MAXM, int WPB, int TPR>
+__global__ void __launch_bounds__(WPB * TPR) k_fsai_rows(int n, const int32_t *__restrict__ arp,
+                                                         const int32_t *__restrict__ aci,
+                                                         const double *__restrict__ av, const int32_t *__restrict__ grp,
+                                                         int32_t *gci, double *gv, int32_t *flags) {
+    static_assert(TPR == 64 || WPB == 1, "one row per workgroup when a row has more than one wavefront");
+    __shared__ double Ms[WPB][MAXM * (MAXM + 1) / 2];
+    __shared__ double es[WPB][MAXM], zs[WPB][MAXM];
     __shared__ int idx[WPB][MAXM];
     __shared__ int bad[WPB];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int w = threadIdx.x / TPR, lane = threadIdx.x % TPR;
     const int i = blockIdx.x * WPB + w;
-    if (i >= n) return;  // the whole wavefront
+    if (i >= n) return;  // the whole row group
     const int m = grp[i + 1] - grp[i];
-    if (m < 1 || m > MAXM) {  // uniform over the wavefront
+    if (m < 1 || m > MAXM) {  // uniform over the row group
         if (lane == 0) atomicOr(&flags[6], 1);
         return;
     }
-    double *M = Ms[w];
-    for (int r = lane; r < m; r += 64) idx[w][r] = aci[arp[i] + r];
-    if (lane == 0) bad[w] = 0;
-    FSAI_SYNC();
-    for (int t = lane; t < m * m; t += 64) {
-        const int r = t / m, c = t - (t / m) * m;
-        if (c <= r) M[r * m + c] = csr_lookup(arp, aci, av, idx[w][r], idx[w][c]);
+    double *M = Ms[w], *e = es[w], *z = zs[w];
+    auto at = [](int r, int c) { return r * (r + 1) / 2 + c; };
+    for (int r = lane; r < m; r += TPR) {
+        idx[w][r] = aci[arp[i] + r];
+        e[r] = r == m - 1 ? 1.0 : 0.0;
     }
-    FSAI_SYNC();
+    if (lane == 0) bad[w] = 0;
+    fsai_sync<TPR>();
+    const int tri = m * (m + 1) / 2;
+    for (int t = lane; t < tri; t += TPR) {
+        const int r = tri_row(t), c = t - r * (r + 1) / 2;
+        M[t] = csr_lookup(arp, aci, av, idx[w][r], idx[w][c]);
+    }
+    fsai_sync<TPR>();
+    // right-looking Cholesky
     for (int k = 0; k < m; ++k) {
         if (lane == 0) {
-            const double d = M[k * m + k];
+            const double d = M[at(k, k)];
             if (!(d > 0.0)) bad[w] = 1;
-            else M[k * m + k] = sqrt(d);
+            else M[at(k, k)] = sqrt(d);
         }
-        FSAI_SYNC();
+        fsai_sync<TPR>();
         if (bad[w]) break;
-        const double lkk = M[k * m + k];
-        for (int r = k + 1 + lane; r < m; r += 64) M[r * m + k] = M[r * m + k] / lkk;
-        FSAI_SYNC();
-        const int q = m - k - 1;
-        for (int t = lane; t < q * q; t += 64) {
-            const int rr = t / q, cc = t - (t / q) * q;
-            if (cc <= rr) {
-                const int r = k + 1 + rr, c = k + 1 + cc;
-                M[r * m + c] = M[r * m + c] - M[r * m + k] * M[c * m + k];
-            }
+        const double lkk = M[at(k, k)];
+        for (int r = k + 1 + lane; r < m; r += TPR) M[at(r, k)] = M[at(r, k)] / lkk;
+        fsai_sync<TPR>();
+        for (int t = at(k + 1, 0) + lane; t < tri; t += TPR) {
+            const int r = tri_row(t), c = t - r * (r + 1) / 2;
+            if (c > k) M[t] = M[t] - M[at(r, k)] * M[at(c, k)];
         }
-        FSAI_SYNC();
+        fsai_sync<TPR>();
     }
     if (bad[w]) {
         if (lane == 0) atomicOr(&flags[7], 1);
         return;
     }
-    if (lane == 0) {
-        double *wv = ws[w], *z = zs[w];
-        for (int r = 0; r < m; ++r) {
-            double t = r == m - 1 ? 1.0 : 0.0;
-            for (int k = 0; k < r; ++k) t = t - M[r * m + k] * wv[k];
-            wv[r] = t / M[r * m + r];
-        }
-        for (int r = m - 1; r >= 0; --r) {
-            double t = wv[r];
-            for (int k = r + 1; k < m; ++k) t = t - M[k * m + r] * z[k];
-            z[r] = t / M[r * m + r];
-        }
-        if (!(z[m - 1] > 0.0)) bad[w] = 1;
+    // forward: L w = e_last (w overwrites e)
+    for (int k = 0; k < m; ++k) {
+        if (lane == 0) e[k] = e[k] / M[at(k, k)];
+        fsai_sync<TPR>();
+        const double wk = e[k];
+        for (int r = k + 1 + lane; r < m; r += TPR) e[r] = e[r] - M[at(r, k)] * wk;
+        fsai_sync<TPR>();
     }
-    FSAI_SYNC();
-    if (bad[w]) {
+    // backward: L^T g = w
+    for (int k = m - 1; k >= 0; --k) {
+        if (lane == 0) z[k] = e[k] / M[at(k, k)];
+        fsai_sync<TPR>();
+        const double gk = z[k];
+        for (int r = lane; r < k; r += TPR) e[r] = e[r] - M[at(k, r)] * gk;
+        fsai_sync<TPR>();
+    }
+    if (!(z[m - 1] > 0.0)) {
         if (lane == 0) atomicOr(&flags[7], 1);
         return;
     }
-    const double sd = sqrt(zs[w][m - 1]);
+    const double sd = sqrt(z[m - 1]);
     const int o = grp[i];
-    for (int r = lane; r < m; r += 64) {
+    for (int r = lane; r < m; r += TPR) {
         gci[o + r] = idx[w][r];
-        gv[o + r] = zs[w][r] / sd;
+        gv[o + r] = z[r] / sd;
     }
 }
 
@@ -588,7 +613,16 @@ __global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const dou
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double q = 0.0, s = 0.0;
     if (i < n) {
-        for (int e = rp[i]; e < rp[i + 1]; ++e) s = s + fabs(mv[e]) * v[ci[e]];
+        const int e1 = rp[i + 1];
+        int e = rp[i];
+        for (; e + 8 <= e1; e += 8) {  // eight loads in flight, added in CSR order
+            double x[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) x[t] = fabs(mv[e + t]) * v[ci[e + t]];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s = s + x[t];
+        }
+        for (; e < e1; ++e) s = s + fabs(mv[e]) * v[ci[e]];
         w[i] = s;
         q = s / v[i];
     }
@@ -765,11 +799,12 @@ int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool 
 
 void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     const int n = A.nr;
-    if (mmax <= 16) k_fsai_rows<16, 4><<<(n + 3) / 4, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
-    else if (mmax <= 32) k_fsai_rows<32, 2><<<(n + 1) / 2, 128, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
-    else if (mmax <= 64) k_fsai_rows<64, 1><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
-    else if (mmax <= 128) k_fsai_rows<128, 1><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
-    else fail(CAMG_E_ARG, "FSAI: a row has more than 128 entries on or below the diagonal");
+    if (mmax <= 16) k_fsai_rows<16, 4, 64><<<(n + 3) / 4, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 32) k_fsai_rows<32, 4, 64><<<(n + 3) / 4, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 64) k_fsai_rows<64, 1, 64><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 128) k_fsai_rows<128, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= 192) k_fsai_rows<192, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
     HIPC(hipGetLastError());
 }
 
