@@ -95,22 +95,6 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     return t;
 }
 
-// Ticket for the "last block finishes the reduction" pattern.  Every block
-// calls it once after writing its partial; it returns true in exactly one
-// block, which then sees every other block's partial.
-__device__ __forceinline__ bool last_block(unsigned *counter) {
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
-}
-
 // Deterministic sum of partials[0..n) by one block of NT threads: thread t
 // adds t, t+NT, ... in order, then the fixed block tree.  Thread 0 gets it.
 template <int NT>

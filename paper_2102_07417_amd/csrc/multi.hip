@@ -362,46 +362,18 @@ struct MESpmv {
         vstore<T, V>(out + o, ov);
     }
 };
-constexpr int kVMax = 4;
 template <int K>
-struct MGDir {  // P_new = Z + beta_c P_old, on the fly (two gathers: four entries at a time)
-    static constexpr int kU = 4;
-    const double *z, *p;
-    const double *beta;
-    double bt[kVMax];
-    __device__ void prep(int c0) {
-        for (int v = 0; v < kVMax; ++v) bt[v] = c0 + v < K ? beta[c0 + v] : 0.0;
-    }
-    template <int V>
-    __device__ void get(int j, int c0, double (&o)[V]) const {
-        double zv[V], pv[V];
-        vload<double, V>(z + (size_t)j * K + c0, zv);
-        vload<double, V>(p + (size_t)j * K + c0, pv);
-#pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = zv[v] + bt[v] * pv[v];
-    }
-};
-template <int K>
-struct MEDir {
-    const double *z, *pold;
-    const double *beta;
-    double *pnew, *q;
-    double bt[kVMax];
-    __device__ void prep(int c0) {
-        for (int v = 0; v < kVMax; ++v) bt[v] = c0 + v < K ? beta[c0 + v] : 0.0;
-    }
+struct MEPQ {  // Q = A P; dot += P.Q (own row of P read back)
+    __device__ void prep(int) {}
+    const double *p;
+    double *q;
     template <int V>
     __device__ void fin(int i, int c0, const double (&acc)[V], double (&dot)[V]) const {
         const size_t o = (size_t)i * K + c0;
-        double zv[V], pv[V], pn[V];
-        vload<double, V>(z + o, zv);
-        vload<double, V>(pold + o, pv);
+        double pv[V];
+        vload<double, V>(p + o, pv);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            pn[v] = zv[v] + bt[v] * pv[v];
-            dot[v] += pn[v] * acc[v];
-        }
-        vstore<double, V>(pnew + o, pn);
+        for (int v = 0; v < V; ++v) dot[v] += pv[v] * acc[v];
         vstore<double, V>(q + o, acc);
     }
 };
@@ -615,6 +587,18 @@ __global__ void __launch_bounds__(kBlock) mk_update(int n, const double *__restr
     block_col_sum<K>(acc, pr2);
 }
 
+// P_new = Z + beta_c P_old for every column (beta_c = 0 for columns that
+// are not running, which leaves P_new = Z: finite and never used)
+template <int K, class TZ>
+__global__ void __launch_bounds__(kBlock) mk_pnew(int n, const TZ *__restrict__ Z, const double *__restrict__ Pold,
+                                                  double *__restrict__ Pnew, const MState *st) {
+    const int64_t tot = (int64_t)n * K;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < tot; t += (int64_t)gridDim.x * kBlock) {
+        const int c = (int)(t % K);
+        Pnew[t] = (double)Z[t] + st->beta[c] * Pold[t];
+    }
+}
+
 // partials of the per-column dot products Y.Z
 template <int K>
 __global__ void __launch_bounds__(kBlock) mk_dot(int n, const double *__restrict__ Y, const double *__restrict__ Z,
@@ -717,7 +701,9 @@ struct Engine {
     int n = 0;
     bool mixed = false;
     Pool pool;
-    double *X = nullptr, *R = nullptr, *Bk = nullptr, *Z = nullptr, *P[2] = {nullptr, nullptr}, *Q = nullptr;
+    double *X = nullptr, *R = nullptr, *Bk = nullptr, *P[2] = {nullptr, nullptr}, *Q = nullptr;
+    void *Zv = nullptr;    // preconditioned residual: FP32 when the V-cycle is (it holds FP32 values), else FP64
+    bool z32 = false;
     float *R32 = nullptr;  // FP32 copy of R kept by the PCG kernels (mixed precision)
     struct Lv {
         void *y = nullptr, *s = nullptr, *r = nullptr, *z = nullptr, *t = nullptr;
@@ -825,8 +811,9 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
     Hier &h = *E.h;
     const int L = h.nlev - 1;
     if (L == 0) {  // one level: direct solve, then the r.z partials
-        launch_coarse<double, K>(h.nL, h.cinv, E.R, E.Z, s);
-        if (dot) mk_dot<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.R, E.Z, E.prz);
+        double *Z = static_cast<double *>(E.Zv);  // one level: Z is FP64
+        launch_coarse<double, K>(h.nL, h.cinv, E.R, Z, s);
+        if (dot) mk_dot<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.R, Z, E.prz);
         HIPC(hipGetLastError());
         return E.nb_vec;
     }
@@ -887,8 +874,14 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
             std::swap(s0, t0);
         }
         if (l == 0)
-            g0 = launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
-                                        MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0, E.Z}, E.prz, dot, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
+            g0 = E.z32 ? launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
+                                                MEPost<T, K, double, float>{vwd<T>(Lv), E.R, s0,
+                                                                            static_cast<float *>(E.Zv)},
+                                                E.prz, dot, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0))
+                       : launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
+                                                MEPost<T, K, double, double>{vwd<T>(Lv), E.R, s0,
+                                                                             static_cast<double *>(E.Zv)},
+                                                E.prz, dot, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
         else
             launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                    MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, Tp(B.z)}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
@@ -904,10 +897,14 @@ void miteration(Engine &E, int par, hipStream_t s) {
     HIPC(hipGetLastError());
     const int nrz = E.mixed ? mvcycle<float, K>(E, true, s) : mvcycle<double, K>(E, true, s);
     mk_fin_rz<K><<<1, kRed, 0, s>>>(E.prz, nrz, E.st);
-    const double *beta =
-        reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
-    const int npq = launch_mrows_any<double, K>(A, A.v, s, MGDir<K>{E.Z, E.P[par], beta},
-                                                MEDir<K>{E.Z, E.P[par], beta, E.P[1 - par], E.Q}, E.ppq, true, ~0ull, 0, E.rs(A, 8, 1));
+    if (E.z32)
+        mk_pnew<K, float><<<E.nb_vec, kBlock, 0, s>>>(E.n, static_cast<const float *>(E.Zv), E.P[par], E.P[1 - par],
+                                                      E.st);
+    else
+        mk_pnew<K, double><<<E.nb_vec, kBlock, 0, s>>>(E.n, static_cast<const double *>(E.Zv), E.P[par],
+                                                       E.P[1 - par], E.st);
+    const int npq = launch_mrows_any<double, K>(A, A.v, s, MGather<double, K>{E.P[1 - par]},
+                                                MEPQ<K>{E.P[1 - par], E.Q}, E.ppq, true, ~0ull, 0, E.rs(A, 8, 1));
     mk_fin_pq<K><<<1, kRed, 0, s>>>(E.ppq, npq, E.st);
     mk_update<K><<<E.nb_vec, kBlock, 0, s>>>(E.n, E.P[1 - par], E.Q, E.X, E.R, E.R32, E.pr2, E.st);
     HIPC(hipGetLastError());
@@ -1049,10 +1046,8 @@ void autotune_t(Engine &E, hipStream_t s) {
     if (sizeof(T) != 8 || L == 0)
         tune_matrix<double, K>(E, A, A.v, MGather<double, K>{E.X}, MESpmv<double, K, false>{E.Q}, nullptr, false, 0,
                                s);
-    const double *beta =
-        reinterpret_cast<const double *>(reinterpret_cast<const char *>(E.st) + offsetof(MState, beta));
-    tune_matrix<double, K>(E, A, A.v, MGDir<K>{E.Z, E.P[0], beta}, MEDir<K>{E.Z, E.P[0], beta, E.P[1], E.Q}, E.ptmp,
-                           true, 1, s);
+    // the product q = A p (with its p.q partials) takes the FP64 A_0 schedule; tune it with its own epilogue
+    tune_matrix<double, K>(E, A, A.v, MGather<double, K>{E.P[0]}, MEPQ<K>{E.P[0], E.Q}, E.ptmp, true, 1, s);
 }
 
 void engine_autotune(Engine &E, hipStream_t s) {
@@ -1093,7 +1088,8 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     E->X = E->pool.alloc<double>(blk);
     E->R = E->pool.alloc<double>(blk);
     E->Bk = E->pool.alloc<double>(blk);
-    E->Z = E->pool.alloc<double>(blk);
+    E->z32 = E->mixed && h.nlev > 1;
+    E->Zv = E->pool.raw(blk * (E->z32 ? 4 : 8));
     E->P[0] = E->pool.alloc<double>(blk);
     E->P[1] = E->pool.alloc<double>(blk);
     E->Q = E->pool.alloc<double>(blk);
@@ -1124,7 +1120,8 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     // the PCG blocks start zeroed and every slot inactive (unused columns
     // are computed along but never read; their values never mix with others)
     HIPC(hipMemsetAsync(E->st, 0, sizeof(MState), s));
-    for (double *p : {E->X, E->R, E->Bk, E->Z, E->P[0], E->P[1], E->Q}) HIPC(hipMemsetAsync(p, 0, blk * 8, s));
+    for (double *p : {E->X, E->R, E->Bk, E->P[0], E->P[1], E->Q}) HIPC(hipMemsetAsync(p, 0, blk * 8, s));
+    HIPC(hipMemsetAsync(E->Zv, 0, blk * (E->z32 ? 4 : 8), s));
     if (E->R32) HIPC(hipMemsetAsync(E->R32, 0, blk * 4, s));
     for (auto &B : E->lv)
         for (void *p : {B.y, B.s, B.t, B.r, B.z})

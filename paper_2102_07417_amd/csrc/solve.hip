@@ -543,12 +543,6 @@ void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *
     HIPC(hipGetLastError());
 }
 
-int pow2_ceil(double x) {
-    int p = 1;
-    while (p < x && p < 64) p <<= 1;
-    return p;
-}
-
 }  // namespace
 
 RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
