@@ -20,12 +20,14 @@ OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -
 F, U, CPT = -1, 0, 1
 X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS, X_G = range(11)
 SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
+INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID = 0, 1, 2, 3
 
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("omega", C.c_double), ("max_levels", C.c_int32),
-                ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32)]
+                ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
+                ("interp", C.c_int32)]
 
 
 class CsrOut(C.Structure):
@@ -49,6 +51,7 @@ def lib():
         L.orc_pmis_rand.argtypes = [u64, i32, i32]; L.orc_pmis_rand.restype = u64
         L.orc_pmis.argtypes = [i32, vp, vp, vp, vp, u64, i32, vp, vp]
         L.orc_interp_direct.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(CsrOut)]
+        L.orc_interp.argtypes = [i32, vp, vp, vp, vp, vp, i32, C.POINTER(CsrOut)]
         L.orc_transpose.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_spgemm.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_cholesky.argtypes = [i32, vp]
@@ -152,6 +155,18 @@ def interp_direct(A, strong, cf):
     strong = np.ascontiguousarray(strong, np.uint8); cf = np.ascontiguousarray(cf, np.int8)
     o = CsrOut()
     st = lib().orc_interp_direct(n, _p(rp), _p(ci), _p(v), _p(strong), _p(cf), C.byref(o))
+    assert st == OK
+    return _from_out(o)
+
+
+def interp(A, strong, cf, variant):
+    """P for a given strength pattern and C/F split (INTERP_* variant)."""
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    strong = np.ascontiguousarray(strong, np.uint8); cf = np.ascontiguousarray(cf, np.int8)
+    o = CsrOut()
+    st = lib().orc_interp(n, _p(rp), _p(ci), _p(v), _p(strong), _p(cf), variant, C.byref(o))
     assert st == OK
     return _from_out(o)
 

@@ -36,6 +36,12 @@ void orc_params_default(orc_params *p) {
     p->max_coarse = 256;
     p->max_iter = 1000;
     p->smoother = ORC_SMOOTH_JACOBI;
+    p->interp = ORC_INTERP_DIRECT;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
 }
 
 /* Position of column j in row i, or -1 (rows are sorted). */
@@ -271,6 +277,184 @@ int orc_interp_direct(int32_t n, const int32_t *rp, const int32_t *ci, const dou
     return ORC_OK;
 }
 
+/*
+ * The paper's classical-AMG interpolations (Section 2, Interpolation), with
+ * the neighbour sets defined there for an F point i:
+ *   N_i   = off-diagonal neighbours of i (a_ij stored, j != i),
+ *   S_i   = strong neighbours (the strength flags of the level),
+ *   F_i^S = S_i n F,  C_i^S = S_i n C,  N_i^w = N_i \ (F_i^S u C_i^S),
+ * and the sign-filtered entry abar_kl = a_kl unless a_kl has the sign of
+ * a_kk, in which case it is 0.
+ *
+ * Classical (eq. clasInt, with the correction for PMIS coarsenings): the
+ * interpolatory set is C_i^S.  A strong F neighbour k whose filtered row
+ * has no entry on C_i^S (sum_{m in C_i^S} abar_km = 0) belongs to F_i^{S*}
+ * and is lumped into the diagonal together with N_i^w; every other k
+ * distributes a_ik over C_i^S in proportion to abar_kj.  The printed
+ * numerator lacks the direct coupling a_ij; it is restored here as in the
+ * extended+i formula and the Henson-Yang correction the paper follows, so
+ * that rows with zero sum interpolate constants exactly.
+ *
+ * Extended+i (eq. extpiInt): the set is C^_i = C_i^S u (union over k in
+ * F_i^S of C_k^S), k's share is spread over C^_i u {i}, the part that falls
+ * on i itself moves into the diagonal a~_ii, and weak neighbours outside
+ * C^_i are lumped.  A k whose filtered row has no entry on C^_i u {i} (its
+ * share cannot be spread) is lumped into the diagonal as well.
+ *
+ * Hybrid: the same formula on the smaller set C^h_i of Alg. extintset:
+ * start from C_i^S; F' = strong F neighbours with no strong connection to
+ * the set (k strongly depends on no point of it) that have at least one
+ * strong C neighbour; repeatedly add the candidate C point (a strong C
+ * neighbour of some point of F') that covers the most points of F', the
+ * smallest index on ties, and drop the points it covers from F'.  The loop
+ * ends when F' is empty.
+ *
+ * C rows are identity rows; an F row with an empty set is an empty row.
+ * Sums run in CSR order of row i, the set in ascending order.
+ */
+static double abar(const int32_t *rp, const int32_t *ci, const double *v, int32_t k, int32_t l) {
+    int32_t e = find_in_row(rp, ci, k, l);
+    if (e < 0) return 0.0;
+    int32_t d = find_in_row(rp, ci, k, k);
+    double akk = v[d], a = v[e];
+    int sa = (a > 0.0) - (a < 0.0), sd = (akk > 0.0) - (akk < 0.0);
+    return sa == sd ? 0.0 : a;
+}
+
+/* l in S_k: k strongly depends on l */
+static int depends(const int32_t *rp, const int32_t *ci, const uint8_t *strong, int32_t k, int32_t l) {
+    int32_t e = find_in_row(rp, ci, k, l);
+    return e >= 0 && strong[e];
+}
+
+static int is_strong_f(const int32_t *ci, const uint8_t *strong, const int8_t *cf, int32_t i, int32_t e) {
+    return ci[e] != i && strong[e] && cf[ci[e]] == ORC_F;
+}
+
+/* Interpolatory set of F point i, ascending, in set[0..*ns); mark[c] == i
+ * flags its members.  set, fp and mark hold n entries each. */
+static void interp_set(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                       int32_t variant, int32_t i, int32_t *set, int32_t *ns, int32_t *fp, int32_t *mark) {
+    (void)n;
+    int32_t m = 0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] != i && strong[e] && cf[ci[e]] == ORC_C) { set[m++] = ci[e]; mark[ci[e]] = i; }
+    if (variant == ORC_INTERP_EXTI) {
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (!is_strong_f(ci, strong, cf, i, e)) continue;
+            int32_t k = ci[e];
+            for (int32_t f = rp[k]; f < rp[k + 1]; ++f) {
+                int32_t c = ci[f];
+                if (c != k && strong[f] && cf[c] == ORC_C && mark[c] != i) { set[m++] = c; mark[c] = i; }
+            }
+        }
+    } else if (variant == ORC_INTERP_HYBRID) {
+        int32_t nf = 0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (!is_strong_f(ci, strong, cf, i, e)) continue;
+            int32_t k = ci[e], covered = 0, has_c = 0;
+            for (int32_t f = rp[k]; f < rp[k + 1]; ++f) {
+                int32_t c = ci[f];
+                if (c == k || !strong[f] || cf[c] != ORC_C) continue;
+                has_c = 1;
+                if (mark[c] == i) covered = 1;
+            }
+            if (has_c && !covered) fp[nf++] = k;
+        }
+        while (nf > 0) {
+            int32_t best = -1, bestdeg = 0;
+            for (int32_t a = 0; a < nf; ++a) {
+                int32_t k = fp[a];
+                for (int32_t f = rp[k]; f < rp[k + 1]; ++f) {
+                    int32_t c = ci[f];
+                    if (c == k || !strong[f] || cf[c] != ORC_C) continue;
+                    int32_t deg = 0;
+                    for (int32_t b = 0; b < nf; ++b) deg += depends(rp, ci, strong, fp[b], c);
+                    if (deg > bestdeg || (deg == bestdeg && c < best)) { best = c; bestdeg = deg; }
+                }
+            }
+            set[m++] = best;
+            mark[best] = i;
+            int32_t keep = 0;
+            for (int32_t a = 0; a < nf; ++a)
+                if (!depends(rp, ci, strong, fp[a], best)) fp[keep++] = fp[a];
+            nf = keep;
+        }
+    }
+    qsort(set, (size_t)m, sizeof(int32_t), cmp_i32);
+    *ns = m;
+}
+
+int orc_interp(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+               const int8_t *cf, int32_t variant, orc_csr *P) {
+    if (variant == ORC_INTERP_DIRECT) return orc_interp_direct(n, rp, ci, v, strong, cf, P);
+    if (variant != ORC_INTERP_CLASSICAL && variant != ORC_INTERP_EXTI && variant != ORC_INTERP_HYBRID)
+        return ORC_E_ARG;
+    int32_t *cmap = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *set = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *fp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *num = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *prp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *pci = NULL;
+    double *pv = NULL;
+    if (!cmap || !mark || !set || !fp || !num || !prp) goto nomem;
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i) { cmap[i] = nc; if (cf[i] == ORC_C) ++nc; mark[i] = -1; }
+    prp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t ns = 1;
+        if (cf[i] != ORC_C) interp_set(n, rp, ci, strong, cf, variant, i, set, &ns, fp, mark);
+        prp[i + 1] = prp[i] + ns;
+    }
+    int32_t nnz = prp[n];
+    pci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    pv = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!pci || !pv) goto nomem;
+    for (int32_t i = 0; i < n; ++i) mark[i] = -1;
+    int plus_i = variant != ORC_INTERP_CLASSICAL;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t o = prp[i];
+        if (cf[i] == ORC_C) { pci[o] = cmap[i]; pv[o] = 1.0; continue; }
+        int32_t ns = 0;
+        interp_set(n, rp, ci, strong, cf, variant, i, set, &ns, fp, mark);
+        if (ns == 0) continue;
+        for (int32_t t = 0; t < ns; ++t) {
+            int32_t e = find_in_row(rp, ci, i, set[t]);
+            num[t] = e >= 0 ? v[e] : 0.0;
+        }
+        double diag = v[find_in_row(rp, ci, i, i)];
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            int32_t k = ci[e];
+            if (k == i) continue;
+            if (is_strong_f(ci, strong, cf, i, e)) {
+                /* share of k, spread over the set (and i itself for extended+i and hybrid) */
+                double D = 0.0;
+                for (int32_t t = 0; t < ns; ++t) {
+                    if (plus_i && i < set[t] && (t == 0 || set[t - 1] < i)) D = D + abar(rp, ci, v, k, i);
+                    D = D + abar(rp, ci, v, k, set[t]);
+                }
+                if (plus_i && set[ns - 1] < i) D = D + abar(rp, ci, v, k, i);
+                if (D == 0.0) { diag = diag + v[e]; continue; }
+                for (int32_t t = 0; t < ns; ++t) num[t] = num[t] + (v[e] * abar(rp, ci, v, k, set[t])) / D;
+                if (plus_i) diag = diag + (v[e] * abar(rp, ci, v, k, i)) / D;
+            } else if (mark[k] != i) {
+                diag = diag + v[e];  /* weak neighbour outside the set */
+            }
+        }
+        for (int32_t t = 0; t < ns; ++t) {
+            pci[o + t] = cmap[set[t]];
+            pv[o + t] = -num[t] / diag;
+        }
+    }
+    free(cmap); free(mark); free(set); free(fp); free(num);
+    P->nrows = n; P->ncols = nc; P->rp = prp; P->ci = pci; P->val = pv;
+    return ORC_OK;
+nomem:
+    free(cmap); free(mark); free(set); free(fp); free(num); free(prp); free(pci); free(pv);
+    return ORC_E_NOMEM;
+}
+
 /* X^T by counting sort on the column index; rows of the result list their
  * columns in ascending order.  The restriction is R = P^T (eq. AcDef). */
 int orc_transpose(const orc_csr *X, orc_csr *XT) {
@@ -295,10 +479,6 @@ int orc_transpose(const orc_csr *X, orc_csr *XT) {
     return ORC_OK;
 }
 
-static int cmp_i32(const void *a, const void *b) {
-    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-    return (x > y) - (x < y);
-}
 
 /*
  * Z = X Y, row by row with a dense accumulator (Gustavson).  The pattern is
@@ -582,8 +762,9 @@ void orc_destroy(orc_hier *h) {
  *     (the paper's "small enough for a direct factorisation", read as a
  *     size threshold); it is also the last one when coarsening stalls
  *     (no C point, or every point C);
- *   - otherwise: Jacobi smoother (D^{-1}, omega), strength, PMIS, direct
- *     interpolation, R = P^T, A_{l+1} = R (A_l P)  (eq. AcDef);
+ *   - otherwise: smoother set-up, strength, PMIS, interpolation (direct by
+ *     default, or one of the paper's three), R = P^T, A_{l+1} = R (A_l P)
+ *     (eq. AcDef);
  *   - the last level is factorised densely (more than 8192 unknowns there
  *     is reported as a stalled coarsening).
  */
@@ -633,7 +814,7 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
         int32_t nc = 0;
         for (int32_t i = 0; i < nl; ++i) if (L->cf[i] == ORC_C) ++nc;
         if (nc == 0 || nc == nl) break;
-        st = orc_interp_direct(nl, arp, aci, av, L->strong, L->cf, &L->P);
+        st = orc_interp(nl, arp, aci, av, L->strong, L->cf, h->prm.interp, &L->P);
         if (!st) st = orc_transpose(&L->P, &L->R);
         orc_csr AP = {0, 0, NULL, NULL, NULL};
         if (!st) st = orc_spgemm(&L->A, &L->P, &AP);

@@ -46,8 +46,10 @@ typedef struct {
     int32_t  max_coarse;
     int32_t  max_iter;
     int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D) or ORC_SMOOTH_FSAI (M^{-1} = G^T G) */
+    int32_t  interp;      /* ORC_INTERP_* */
 } orc_params;
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
+enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3 };
 
 void orc_params_default(orc_params *p);
 
@@ -61,6 +63,9 @@ int  orc_pmis(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *st
               const int32_t *st_count, uint64_t seed, int32_t level, int8_t *cf, int32_t *rounds);
 int  orc_interp_direct(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
                        const uint8_t *strong, const int8_t *cf, orc_csr *P);
+/* classical (a_ij restored), extended+i or hybrid interpolation for a given C/F split */
+int  orc_interp(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                const uint8_t *strong, const int8_t *cf, int32_t variant, orc_csr *P);
 int  orc_transpose(const orc_csr *X, orc_csr *XT);
 int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
 int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */

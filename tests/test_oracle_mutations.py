@@ -1,5 +1,6 @@
 """Plant plausible mistakes in a copy of the oracle source and check that
-the pins in test_oracle.py and test_oracle_fsai.py catch every one of
+the pins in test_oracle.py, test_oracle_fsai.py and test_oracle_interp.py
+catch every one of
 them (CPU only)."""
 import os
 import subprocess
@@ -46,14 +47,43 @@ MUTATIONS = [
     ("fsai_G_twice", "spmv(&L->G, y, u);\n        spmv(&L->GT, u, w);", "spmv(&L->G, y, u);\n        spmv(&L->G, u, w);"),
     ("fsai_omega_no_abs", "s = s + fabs(M.val[e]) * v[M.ci[e]];", "s = s + M.val[e] * v[M.ci[e]];"),
     ("fsai_step_sign", "s[i] = s[i] + L->omega * w[i];", "s[i] = s[i] - L->omega * w[i];"),
+    ("ext_no_direct_coupling", "num[t] = e >= 0 ? v[e] : 0.0;", "num[t] = 0.0; (void)e;"),
+    ("ext_no_sign_filter", "return sa == sd ? 0.0 : a;", "(void)sa; (void)sd; return a;"),
+    ("ext_weak_in_set_lumped", "} else if (mark[k] != i) {", "} else if (!(strong[e] && cf[k] == ORC_C)) {"),
+    ("ext_no_plus_i_diagonal", "if (plus_i) diag = diag + (v[e] * abar(rp, ci, v, k, i)) / D;", ";"),
+    ("ext_denominator_without_i", "if (plus_i && set[ns - 1] < i) D = D + abar(rp, ci, v, k, i);", ";"),
+    ("ext_union_takes_weak", "if (c != k && strong[f] && cf[c] == ORC_C && mark[c] != i)",
+     "if (c != k && cf[c] == ORC_C && mark[c] != i)"),
+    ("classical_fstar_dropped", "if (D == 0.0) { diag = diag + v[e]; continue; }", "if (D == 0.0) continue;"),
+    ("ext_weight_sign", "pv[o + t] = -num[t] / diag;", "pv[o + t] = num[t] / diag;"),
+    ("hybrid_tie_largest", "(deg == bestdeg && c < best)", "(deg == bestdeg && c > best)"),
+    ("hybrid_degree_ignored", "for (int32_t b = 0; b < nf; ++b) deg += depends(rp, ci, strong, fp[b], c);",
+     "deg = 1;"),
+    ("hybrid_no_cover_update", "if (!depends(rp, ci, strong, fp[a], best)) fp[keep++] = fp[a];",
+     "if (fp[a] != best) fp[keep++] = fp[a];"),
 ]
 
 
-def _run_pins(libpath):
-    env = dict(os.environ, CAMG_ORACLE_LIB=libpath)
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_fsai.py")],
+PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py"]
+
+
+def _first_file(name):
+    """The pin file that targets the mutated step runs first, so that with
+    -x a caught mutation stops early; every pin file still runs."""
+    if name.startswith("fsai"):
+        return "test_oracle_fsai.py"
+    if name.startswith(("ext_", "hybrid_", "classical_")):
+        return "test_oracle_interp.py"
+    return "test_oracle.py"
+
+
+def _run_pins(libpath, name):
+    env = dict(os.environ, CAMG_ORACLE_LIB=libpath, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               MKL_NUM_THREADS="1")
+    first = _first_file(name)
+    files = [first] + [f for f in PIN_FILES if f != first]
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
+                       + [os.path.join(ROOT, "tests", f) for f in files],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode
 
@@ -69,4 +99,4 @@ def test_mutation_is_caught(name, old, new, tmp_path):
     lib = tmp_path / "liborc_mut.so"
     subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
                            "-I", hdr, "-o", str(lib), str(cfile), "-lm"])
-    assert _run_pins(str(lib)) != 0, f"the pins did not catch mutation {name}"
+    assert _run_pins(str(lib), name) != 0, f"the pins did not catch mutation {name}"
