@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 2
+#define CAMG_ABI_VERSION 3
 
 typedef struct camg_hier *camg_handle;
 
@@ -58,6 +58,17 @@ enum { CAMG_FP64 = 0, CAMG_MIXED_FP32 = 1 };
  * factorised sparse approximate inverse M^{-1} = G^T G (eq. smo; here the
  * static factor on the pattern of the lower triangle of A). */
 enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1 };
+/* Interpolation (Section 2, Interpolation).  DIRECT: distance-one direct
+ * formula over C_i^S (the default).  CLASSICAL: eq. clasInt with the
+ * correction for strong F neighbours that share no C point (they are
+ * lumped into the diagonal), keeping the direct coupling a_ij in the
+ * numerator.  EXTI: extended+i, eq. extpiInt, over C_i^S plus the strong C
+ * neighbours of the strong F neighbours.  HYBRID: the same formula over the
+ * smaller set of Alg. extintset (C_i^S plus, greedily, the C points that
+ * cover the most strong F neighbours without a C point in the set; the
+ * smallest index on ties).  Rows have at most 2048 candidate C points
+ * (CAMG_E_ARG otherwise). */
+enum { CAMG_INTERP_DIRECT = 0, CAMG_INTERP_CLASSICAL = 1, CAMG_INTERP_EXTI = 2, CAMG_INTERP_HYBRID = 3 };
 
 /* Hierarchy and solver parameters. */
 typedef struct {
@@ -73,6 +84,7 @@ typedef struct {
     int32_t  max_iter;    /* PCG iteration limit; default 1000 */
     int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 192 entries
                              on or below the diagonal per row, and runs on the single-system path only */
+    int32_t  interp;      /* CAMG_INTERP_DIRECT (default), _CLASSICAL, _EXTI or _HYBRID */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32

@@ -32,13 +32,15 @@ EXPORTED = [
 ]
 OPT_GRAPH = 1
 SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
+INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID = 0, 1, 2, 3
 OPT_AUTOTUNE = 2
 
 
 class camg_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
-                ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32)]
+                ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
+                ("interp", C.c_int32)]
 
 
 class camg_info_t(C.Structure):

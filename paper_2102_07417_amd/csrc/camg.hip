@@ -170,6 +170,7 @@ void check_params(const camg_params &p) {
     if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
     if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI) fail(CAMG_E_ARG, "unknown smoother");
+    if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_HYBRID) fail(CAMG_E_ARG, "unknown interpolation");
 }
 
 // ---------------------------------------------------------------- set-up
@@ -334,20 +335,40 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         scan_i32_to_i64(isc, cmap, nl, lt, s);
         const int64_t nc = read1(cmap + nl, s);
         if (nc == 0 || nc == nl) break;  // coarsening stalled: this is the last level
-        // direct interpolation P = [W; I]
+        // interpolation P = [W; I]: direct, or the paper's classical,
+        // extended+i or hybrid formula
         Csr &P = L.P;
         P.nr = nl;
         P.nc = (int32_t)nc;
         int32_t *pcnt = lt.alloc<int32_t>(nl);
-        interp_count(nl, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
+        int32_t *bnd = nullptr, *xflags = nullptr;
+        int bmax = 0;
+        if (prm.interp == CAMG_INTERP_DIRECT) {
+            interp_count(nl, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
+        } else {
+            bnd = lt.alloc<int32_t>(nl);
+            xflags = lt.alloc<int32_t>(2);
+            HIPC(hipMemsetAsync(xflags, 0, 2 * sizeof(int32_t), s));
+            bmax = xi_bounds(nl, L.A, L.strong, L.cf, prm.interp, bnd, lt, s);
+            xi_count(nl, L.A, L.strong, L.cf, prm.interp, bnd, bmax, pcnt, xflags, s);
+        }
         int64_t *prp64 = lt.alloc<int64_t>((size_t)nl + 1);
         scan_i32_to_i64(pcnt, prp64, nl, lt, s);
         P.nnz = read1(prp64 + nl, s);
+        if (P.nnz > INT32_MAX) fail(CAMG_E_ARG, "interpolation has 2^31 or more entries");
         P.rp = h.pool.alloc<int32_t>((size_t)nl + 1);
         narrow_i64(prp64, P.rp, nl, s);
         P.ci = h.pool.alloc<int32_t>(padded(P.nnz));
         P.v = h.pool.alloc<double>(padded(P.nnz));
-        interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
+        if (prm.interp == CAMG_INTERP_DIRECT) {
+            interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
+        } else {
+            xi_fill(nl, L.A, L.strong, L.cf, prm.interp, bnd, bmax, cmap, P.rp, P.ci, P.v, xflags, s);
+            int32_t hf[2];
+            HIPC(hipMemcpyAsync(hf, xflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (hf[0] || hf[1]) fail(CAMG_E_DEVICE, "interpolation: inconsistent candidate lists");
+        }
         // R = P^T
         Csr &R = L.R;
         R.nr = P.nc;
@@ -830,6 +851,7 @@ void camg_params_default(camg_params *p) {
     p->precision = CAMG_FP64;
     p->max_iter = 1000;
     p->smoother = CAMG_SMOOTH_JACOBI;
+    p->interp = CAMG_INTERP_DIRECT;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,

@@ -200,6 +200,16 @@ void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *st
                   int32_t *cnt, hipStream_t s);
 void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
                  const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s);
+// The paper's classical, extended+i and hybrid interpolations
+// (variant = CAMG_INTERP_*): per-row bound of the candidate list (returns
+// the largest), set sizes (cnt) and the rows of P.  flags[0]: candidate
+// list overflow; flags[1]: count and fill passes disagree.
+int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, Pool &tmp,
+              hipStream_t s);
+void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
+              int32_t *cnt, int32_t *flags, hipStream_t s);
+void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
+             const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, int32_t *flags, hipStream_t s);
 void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 // FSAI smoother: counts of entries on or below the diagonal per row (returns
 // the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:

@@ -1,5 +1,5 @@
 // Hierarchy set-up kernels (Alg. "AMG Set-up" of the paper): input checks,
-// strength of connection, PMIS rounds, direct interpolation, transpose,
+// strength of connection, PMIS rounds, interpolation, transpose,
 // Jacobi weights and the dense last-level factorisation.
 //
 // Every kernel that produces a value the CPU reference also produces does
@@ -606,6 +606,365 @@ __global__ void __launch_bounds__(WPB * TPR) k_fsai_rows(int n, const int32_t *_
     }
 }
 
+// ---------------------------------------------------------------- the paper's interpolations
+// Classical (direct coupling a_ij kept in the numerator), extended+i and
+// hybrid (Section 2, Interpolation; Alg. extintset).  One row group (a
+// wavefront, or a 256-thread workgroup for rows with many candidates)
+// builds the interpolatory set of an F row in LDS: candidates are appended,
+// then sorted and deduplicated by rank counting.  The weights follow the
+// CPU reference's order: the shares of the strong F neighbours are added in
+// CSR order of row i, each spread over the set with the sign-filtered
+// entries abar_kl of row k (abar_kl = 0 when a_kl has the sign of a_kk), so
+// P matches the reference bit for bit.
+constexpr int kXiClassical = 1, kXiExt = 2, kXiHybrid = 3;
+constexpr int kXiCapWave = 256, kXiCapGroup = 2048;  // candidate capacity of a wavefront / workgroup
+
+// strong C neighbours of every row
+__global__ void k_xi_cs(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                        int32_t *cs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (ci[e] != i && strong[e] && cf[ci[e]] == kC) ++c;
+    cs[i] = c;
+}
+
+// upper bound of the candidate list of an F row: |C_i^S|, plus the
+// |C_k^S| of its strong F neighbours for the two distance-two variants
+__global__ void k_xi_bound(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                           const int32_t *cs, int variant, int32_t *bnd, unsigned long long *bmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    long long b = 0;
+    if (i < n && cf[i] != kC) {
+        b = cs[i];
+        if (variant != kXiClassical)
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                const int k = ci[e];
+                if (k != i && strong[e] && cf[k] == kF) b += cs[k];
+            }
+    }
+    if (i < n) bnd[i] = (int32_t)(b < INT32_MAX ? b : INT32_MAX);
+    const unsigned long long m = block_max_u64<kBlock>((unsigned long long)b);
+    if (threadIdx.x == 0) atomicMax(bmax, m);
+}
+
+// C rows (identity) and F rows without candidates (empty)
+template <bool FILL>
+__global__ void k_xi_simple(int n, const int8_t *cf, const int32_t *bnd, const int64_t *cmap, int32_t *cnt,
+                            const int32_t *prp, int32_t *pci, double *pv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == kC) {
+        if constexpr (FILL) {
+            pci[prp[i]] = (int32_t)cmap[i];
+            pv[prp[i]] = 1.0;
+        } else {
+            cnt[i] = 1;
+        }
+    } else if (bnd[i] == 0) {
+        if constexpr (!FILL) cnt[i] = 0;
+    }
+}
+
+template <int CAP, int TPR>
+struct XiLds {
+    int cand[CAP], src[CAP], aux[CAP], pos[CAP], S[CAP], Q[CAP], rem[CAP];
+    double num[CAP];
+    double red[TPR / 64];
+    int redi[TPR / 64];
+    unsigned long long redu[TPR / 64];
+    double diag;
+    int cnt;
+};
+
+template <int TPR>
+__device__ __forceinline__ double xi_sum(double x, double *red, int lane) {
+    x = wave_sum(x);
+    if constexpr (TPR == 64) {
+        return x;
+    } else {
+        __syncthreads();
+        if ((lane & 63) == 0) red[lane >> 6] = x;
+        __syncthreads();
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < TPR / 64; ++w) t += red[w];
+        __syncthreads();
+        return t;
+    }
+}
+
+template <int TPR>
+__device__ __forceinline__ int xi_sum_i(int x, int *red, int lane) {
+    x = wave_sum_i(x);
+    if constexpr (TPR == 64) {
+        return x;
+    } else {
+        __syncthreads();
+        if ((lane & 63) == 0) red[lane >> 6] = x;
+        __syncthreads();
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < TPR / 64; ++w) t += red[w];
+        __syncthreads();
+        return t;
+    }
+}
+
+template <int TPR>
+__device__ __forceinline__ unsigned long long xi_max(unsigned long long x, unsigned long long *red, int lane) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o, kWave);
+        x = y > x ? y : x;
+    }
+    if constexpr (TPR == 64) {
+        return x;
+    } else {
+        __syncthreads();
+        if ((lane & 63) == 0) red[lane >> 6] = x;
+        __syncthreads();
+        unsigned long long t = 0;
+#pragma unroll
+        for (int w = 0; w < TPR / 64; ++w) t = red[w] > t ? red[w] : t;
+        __syncthreads();
+        return t;
+    }
+}
+
+// position of c in the ascending S[0, U) or -1
+__device__ __forceinline__ int xi_find(const int *S, int U, int c) {
+    int lo = 0, hi = U - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = S[mid];
+        if (x == c) return mid;
+        if (x < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+// out[0, U) = the distinct values of in[0, T) in ascending order;
+// pos[t] = the place of in[t] in out.  Returns U (all lanes).
+template <int TPR>
+__device__ int xi_sort_unique(const int *in, int T, int *out, int *pos, int *first, int *red, int lane) {
+    for (int t = lane; t < T; t += TPR) {
+        const int x = in[t];
+        int f = 1;
+        for (int u = 0; u < t; ++u)
+            if (in[u] == x) {
+                f = 0;
+                break;
+            }
+        first[t] = f;
+    }
+    fsai_sync<TPR>();
+    int mine = 0;
+    for (int t = lane; t < T; t += TPR) {
+        const int x = in[t];
+        int r = 0;
+        for (int u = 0; u < T; ++u) r += (first[u] && in[u] < x) ? 1 : 0;
+        pos[t] = r;
+        if (first[t]) {
+            out[r] = x;
+            ++mine;
+        }
+    }
+    fsai_sync<TPR>();
+    return xi_sum_i<TPR>(mine, red, lane);
+}
+
+// strong C neighbours of row k appended to cand (with source b when hybrid)
+template <int CAP, int TPR>
+__device__ __forceinline__ void xi_append(XiLds<CAP, TPR> &G, const int32_t *rp, const int32_t *ci,
+                                          const uint8_t *strong, const int8_t *cf, int k, int b, int lane) {
+    for (int f = rp[k] + lane; f < rp[k + 1]; f += TPR) {
+        const int c = ci[f];
+        if (c != k && strong[f] && cf[c] == kC) {
+            const int t = atomicAdd(&G.cnt, 1);
+            if (t < CAP) {
+                G.cand[t] = c;
+                G.src[t] = b;
+            }
+        }
+    }
+}
+
+// flags[0]: candidate list longer than the row group's capacity;
+// flags[1]: the fill pass found another set size than the count pass
+template <int CAP, int WPB, int TPR, bool FILL>
+__global__ void __launch_bounds__(WPB * TPR)
+    k_xi_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
+              const uint8_t *__restrict__ strong, const int8_t *__restrict__ cf, const int32_t *__restrict__ bnd,
+              int lo, int hi, int variant, const int64_t *__restrict__ cmap, int32_t *cnt,
+              const int32_t *__restrict__ prp, int32_t *pci, double *pv, int32_t *flags) {
+    static_assert(TPR == 64 || WPB == 1, "one row per workgroup when a row has more than one wavefront");
+    __shared__ XiLds<CAP, TPR> Ls[WPB];
+    const int w = threadIdx.x / TPR, lane = threadIdx.x % TPR;
+    const int i = blockIdx.x * WPB + w;
+    if (i >= n || cf[i] == kC) return;  // uniform over the row group
+    const int bi = bnd[i];
+    if (bi < lo || bi > hi) return;
+    XiLds<CAP, TPR> &G = Ls[w];
+    const int e0 = rp[i], e1 = rp[i + 1];
+    // C_i^S, and for extended+i the strong C neighbours of the strong F neighbours
+    if (lane == 0) G.cnt = 0;
+    fsai_sync<TPR>();
+    xi_append<CAP, TPR>(G, rp, ci, strong, cf, i, 0, lane);
+    if (variant == kXiExt)
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k != i && strong[e] && cf[k] == kF) xi_append<CAP, TPR>(G, rp, ci, strong, cf, k, 0, lane);
+        }
+    fsai_sync<TPR>();
+    const int T = G.cnt;
+    if (T > CAP) {
+        if (lane == 0) atomicOr(&flags[0], 1);
+        return;
+    }
+    int U = xi_sort_unique<TPR>(G.cand, T, G.S, G.pos, G.aux, G.redi, lane);
+    if (variant == kXiHybrid) {
+        // Alg. extintset: F' = strong F neighbours with a strong C neighbour
+        // but none in C_i^S; candidates = their strong C neighbours
+        const int s0 = U;
+        int nf = 0;
+        if (lane == 0) G.cnt = 0;
+        fsai_sync<TPR>();
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k == i || !strong[e] || cf[k] != kF) continue;
+            int hasc = 0, cov = 0;
+            for (int f = rp[k] + lane; f < rp[k + 1]; f += TPR) {
+                const int c = ci[f];
+                if (c != k && strong[f] && cf[c] == kC) {
+                    hasc = 1;
+                    if (xi_find(G.S, s0, c) >= 0) cov = 1;
+                }
+            }
+            hasc = xi_sum_i<TPR>(hasc, G.redi, lane);
+            cov = xi_sum_i<TPR>(cov, G.redi, lane);
+            if (hasc == 0 || cov != 0) continue;
+            xi_append<CAP, TPR>(G, rp, ci, strong, cf, k, nf, lane);
+            if (lane == 0 && nf < CAP) G.rem[nf] = 1;
+            ++nf;
+        }
+        fsai_sync<TPR>();
+        const int T2 = G.cnt;
+        if (T2 > CAP || s0 + nf > CAP) {
+            if (lane == 0) atomicOr(&flags[0], 1);
+            return;
+        }
+        if (nf > 0) {
+            const int U2 = xi_sort_unique<TPR>(G.cand, T2, G.Q, G.pos, G.aux, G.redi, lane);
+            int np = 0;
+            for (;;) {
+                // degree of each candidate over the points of F' still uncovered
+                for (int u = lane; u < U2; u += TPR) G.aux[u] = 0;
+                fsai_sync<TPR>();
+                for (int t = lane; t < T2; t += TPR)
+                    if (G.rem[G.src[t]]) atomicAdd(&G.aux[G.pos[t]], 1);
+                fsai_sync<TPR>();
+                unsigned long long key = 0;
+                for (int u = lane; u < U2; u += TPR) {
+                    const int d = G.aux[u];
+                    const unsigned long long kk =
+                        d > 0 ? ((unsigned long long)d << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)G.Q[u])
+                              : 0ull;
+                    key = kk > key ? kk : key;
+                }
+                key = xi_max<TPR>(key, G.redu, lane);
+                if (key == 0) break;
+                // most points covered, smallest index on ties
+                const int cstar = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+                if (lane == 0) G.S[s0 + np] = cstar;
+                ++np;
+                for (int t = lane; t < T2; t += TPR)
+                    if (G.cand[t] == cstar) G.rem[G.src[t]] = 0;
+                fsai_sync<TPR>();
+            }
+            U = s0 + np;
+            fsai_sync<TPR>();
+            xi_sort_unique<TPR>(G.S, U, G.cand, G.pos, G.aux, G.redi, lane);
+            for (int u = lane; u < U; u += TPR) G.S[u] = G.cand[u];
+            fsai_sync<TPR>();
+        }
+    }
+    if constexpr (!FILL) {
+        if (lane == 0) cnt[i] = U;
+        return;
+    } else {
+        const int o = prp[i];
+        if (prp[i + 1] - o != U) {
+            if (lane == 0) atomicOr(&flags[1], 1);
+            return;
+        }
+        const bool plus_i = variant != kXiClassical;
+        for (int u = lane; u < U; u += TPR) G.num[u] = 0.0;
+        fsai_sync<TPR>();
+        for (int e = e0 + lane; e < e1; e += TPR) {
+            const int c = ci[e];
+            if (c == i) {
+                G.diag = v[e];
+            } else {
+                const int p = xi_find(G.S, U, c);
+                if (p >= 0) G.num[p] = v[e];
+            }
+        }
+        fsai_sync<TPR>();
+        double diag = G.diag;
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k == i) continue;
+            const double a = v[e];
+            if (strong[e] && cf[k] == kF) {
+                // share of k, spread over the set (and i itself unless classical)
+                const int f0 = rp[k], f1 = rp[k + 1];
+                const double akk = csr_lookup(rp, ci, v, k, k);
+                const int sd = (akk > 0.0) - (akk < 0.0);
+                // denominator: every lane walks row k in CSR (= ascending
+                // column) order, the CPU reference's order over the set
+                double D = 0.0;
+                for (int f = f0; f < f1; ++f) {
+                    const int l = ci[f];
+                    const double x = v[f];
+                    const int sx = (x > 0.0) - (x < 0.0);
+                    const double ab = sx == sd ? 0.0 : x;
+                    if ((plus_i && l == i) || xi_find(G.S, U, l) >= 0) D = D + ab;
+                }
+                if (D == 0.0) {
+                    diag = diag + a;
+                    continue;
+                }
+                double dt = 0.0;
+                for (int f = f0 + lane; f < f1; f += TPR) {
+                    const int l = ci[f];
+                    const double x = v[f];
+                    const int sx = (x > 0.0) - (x < 0.0);
+                    const double ab = sx == sd ? 0.0 : x;
+                    if (l == i) {
+                        if (plus_i) dt = (a * ab) / D;
+                    } else {
+                        const int p = xi_find(G.S, U, l);
+                        if (p >= 0) G.num[p] = G.num[p] + (a * ab) / D;
+                    }
+                }
+                dt = xi_sum<TPR>(dt, G.red, lane);
+                if (plus_i) diag = diag + dt;
+                fsai_sync<TPR>();
+            } else if (xi_find(G.S, U, k) < 0) {
+                diag = diag + a;  // weak neighbour outside the set
+            }
+        }
+        fsai_sync<TPR>();
+        for (int u = lane; u < U; u += TPR) {
+            pci[o + u] = (int32_t)cmap[G.S[u]];
+            pv[o + u] = -G.num[u] / diag;
+        }
+    }
+}
+
 // Collatz-Wielandt step on |M|: w = |M| v (CSR order), bound = max w_i / v_i,
 // wmax = max w_i (non-negative doubles compared through their bit patterns)
 __global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *v, double *w,
@@ -806,6 +1165,45 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     else if (mmax <= 192) k_fsai_rows<192, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
     HIPC(hipGetLastError());
+}
+
+int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, Pool &tmp,
+              hipStream_t s) {
+    int32_t *cs = tmp.alloc<int32_t>(n);
+    unsigned long long *d = tmp.alloc<unsigned long long>(1);
+    HIPC(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
+    k_xi_cs<<<nblocks(n), kBlock, 0, s>>>(n, A.rp, A.ci, strong, cf, cs);
+    k_xi_bound<<<nblocks(n), kBlock, 0, s>>>(n, A.rp, A.ci, strong, cf, cs, variant, bnd, d);
+    HIPC(hipGetLastError());
+    unsigned long long h = 0;
+    HIPC(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    return h > (unsigned long long)INT32_MAX ? INT32_MAX : (int)h;
+}
+
+template <bool FILL>
+static void xi_launch(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd,
+                      int bmax, const int64_t *cmap, int32_t *cnt, const int32_t *prp, int32_t *pci, double *pv,
+                      int32_t *flags, hipStream_t s) {
+    k_xi_simple<FILL><<<nblocks(n), kBlock, 0, s>>>(n, cf, bnd, cmap, cnt, prp, pci, pv);
+    if (bmax >= 1)
+        k_xi_rows<kXiCapWave, 4, 64, FILL><<<(n + 3) / 4, 256, 0, s>>>(
+            n, A.rp, A.ci, A.v, strong, cf, bnd, 1, kXiCapWave, variant, cmap, cnt, prp, pci, pv, flags);
+    if (bmax > kXiCapWave)
+        k_xi_rows<kXiCapGroup, 1, 256, FILL><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, strong, cf, bnd, kXiCapWave + 1,
+                                                                kXiCapGroup, variant, cmap, cnt, prp, pci, pv, flags);
+    HIPC(hipGetLastError());
+}
+
+void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
+              int32_t *cnt, int32_t *flags, hipStream_t s) {
+    if (bmax > kXiCapGroup) fail(CAMG_E_ARG, "interpolation: a row has more than 2048 candidate coarse points");
+    xi_launch<false>(n, A, strong, cf, variant, bnd, bmax, nullptr, cnt, nullptr, nullptr, nullptr, flags, s);
+}
+
+void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
+             const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, int32_t *flags, hipStream_t s) {
+    xi_launch<true>(n, A, strong, cf, variant, bnd, bmax, cmap, nullptr, prp, pci, pv, flags, s);
 }
 
 double cw_bound(const Csr &M, Pool &tmp, hipStream_t s) {

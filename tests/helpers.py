@@ -46,3 +46,22 @@ def rows_sorted(A):
         if np.any(np.diff(seg) <= 0):
             return False
     return True
+
+
+def wide_stencil_2d(g, r):
+    """Graph Laplacian (+ identity) of a g x g grid where every point is
+    coupled with weight -1 to all points within Chebyshev distance r: rows
+    with up to (2r + 1)^2 entries, every coupling strong.  Used to give
+    interpolation long candidate lists."""
+    idx = np.arange(g * g).reshape(g, g)
+    M = np.zeros((g * g, g * g))
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            if dx == 0 and dy == 0:
+                continue
+            ys, xs = np.meshgrid(np.arange(g), np.arange(g), indexing="ij")
+            yy, xx = ys + dy, xs + dx
+            ok = (yy >= 0) & (yy < g) & (xx >= 0) & (xx < g)
+            M[idx[ys[ok], xs[ok]], idx[yy[ok], xx[ok]]] = -1.0
+    M[np.arange(g * g), np.arange(g * g)] = -M.sum(1) + 1.0
+    return from_dense(M)

@@ -7,6 +7,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2102_07417_amd import camg
@@ -45,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 2
+    assert lib.camg_abi_version() == 3
     for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -53,6 +54,7 @@ def test_pure_host_calls(lib):
     lib.camg_params_default(C.byref(p))
     assert p.theta == 0.25 and p.nu_pre == 1 and p.nu_post == 1 and p.max_coarse == 256 and p.max_levels == 25
     assert p.precision == camg.FP64 and p.omega == 0.0 and p.smoother == camg.SMOOTH_JACOBI
+    assert p.interp == camg.INTERP_DIRECT
 
 
 def test_argument_errors_without_device(lib):
@@ -64,6 +66,22 @@ def test_argument_errors_without_device(lib):
     assert len(lib.camg_last_error()) >= 0
 
 
+@pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 2), ("theta", 1.5),
+                                         ("precision", 3)])
+def test_bad_parameters_rejected_without_device(lib, field, value):
+    # parameters are checked before the device is touched
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    v = np.array([2.0])
+    p = camg.camg_params()
+    lib.camg_params_default(C.byref(p))
+    setattr(p, field, value)
+    h = C.c_void_p()
+    st = lib.camg_setup(1, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                        v.ctypes.data_as(C.c_void_p), C.byref(p), C.byref(h))
+    assert st == camg.E_ARG and not h.value
+
+
 def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text(r'''
@@ -71,8 +89,9 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "camg.h"
 int main(void) {
-  printf("params %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
-         offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother));
+  printf("params %zu %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
+         offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother),
+         offsetof(camg_params, interp));
   printf("info %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
          offsetof(camg_completion, latency_ms));
@@ -84,7 +103,8 @@ int main(void) {
     out = dict((l.split()[0], [int(v) for v in l.split()[1:]])
                for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     P = camg.camg_params
-    assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset]
+    assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset,
+                             P.interp.offset]
     I = camg.camg_info_t
     assert out["info"] == [C.sizeof(I), I.nnz_p.offset]
     Q = camg.camg_completion
