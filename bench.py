@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-fsai", action="store_true", help="skip the FSAI-smoother solves")
+    ap.add_argument("--no-interp", action="store_true",
+                    help="skip the classical / extended+i / hybrid interpolation solves")
     ap.add_argument("--batched", type=int, default=32,
                     help="right-hand sides of the batched (block) run on aniso3d_160; 0 skips it")
     ap.add_argument("--only-batched", action="store_true", help="print only the batched run")
@@ -108,6 +110,9 @@ def main():
                     help="print only the serving sweep (8 resident systems, Poisson arrivals)")
     ap.add_argument("--rates", default="5,10,20,50,100,200", help="request rates (1/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per rate")
+    ap.add_argument("--poi65m", type=str, default="", metavar="GRID[,GRID...]",
+                    help="only run the context case: 7-point Poisson on GRID^3 (404 is the paper's poi65m size) "
+                         "with Jacobi + extended+i, as the paper's Chr-jac set-up, and with direct interpolation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -132,6 +137,10 @@ def main():
         print(json.dumps({"serving": serve_run([float(r) for r in args.rates.split(",")], args.serve_seconds)}),
               flush=True)
         return
+    if args.poi65m:
+        for grid in [int(g) for g in args.poi65m.split(",")]:
+            print(json.dumps({"poisson_context": poisson_context_run(grid)}), flush=True)
+        return
     A = problems.workload(args.workload)
     b = problems.rhs(A.n)
     rp = torch.from_numpy(A.row_ptr).to(dev)
@@ -142,11 +151,11 @@ def main():
     stream = torch.cuda.current_stream()
     max_iter = 5000
 
-    def one_step(precision, profile=False, smoother=0):
+    def one_step(precision, profile=False, smoother=0, interp=0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=max_iter,
-                                    smoother=smoother)
+                                    smoother=smoother, interp=interp)
         t1 = time.perf_counter()
         if profile:  # time the level-0 post-smoothing kernel on every 8th iteration
             camg.camg_profile(s.h, PROFILE_STRIDE)
@@ -198,6 +207,21 @@ def main():
             fsai[key] = {"solve_ms": round(statistics.median(r["solve_ms"] for r in rs), 4),
                          "setup_ms": round(statistics.median(r["setup_ms"] for r in rs), 4),
                          "iters": rs[-1]["iters"], "true_relres": rs[-1]["true_relres"]}
+
+    # the paper's interpolations on the same system (Jacobi, FP64), as in its
+    # comparison of prolongations: complexities, iterations, set-up and solve
+    interps = {}
+    if not args.no_interp:
+        for var, key in ((camg.INTERP_CLASSICAL, "classical"), (camg.INTERP_EXTI, "extended_i"),
+                         (camg.INTERP_HYBRID, "hybrid")):
+            one_step(camg.FP64, interp=var)
+            rs = [one_step(camg.FP64, interp=var) for _ in range(max(1, min(args.steps, 3)))]
+            inf = rs[-1]["info"]
+            interps[key] = {"solve_ms": round(statistics.median(r["solve_ms"] for r in rs), 4),
+                            "setup_ms": round(statistics.median(r["setup_ms"] for r in rs), 4),
+                            "iters": rs[-1]["iters"], "true_relres": rs[-1]["true_relres"],
+                            "levels": inf.levels, "grid_complexity": round(inf.grid_complexity, 4),
+                            "operator_complexity": round(inf.operator_complexity, 4)}
 
     # host API on the same hierarchy: b copied in and x out over PCIe around the device solve
     sh = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, max_iter=max_iter)
@@ -257,6 +281,8 @@ def main():
                         "speedup_vs_fp64": round(solve_ms / m_ms, 4), "rel_err_vs_fp64_gpu": err}
     if fsai:
         out["fsai_smoother"] = fsai
+    if interps:
+        out["interpolations"] = interps
     if args.batched:
         out["batched"] = batched_run(args.batched, max(1, min(args.steps, 3)))
     if args.small_systems:
@@ -482,6 +508,61 @@ def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
               f"{out['rates'][-1]['solves_per_s']} solves/s", file=sys.stderr, flush=True)
     for _, _, s, _ in systems:
         s.close()
+    return out
+
+
+def poisson_context_run(grid):
+    """7-point Poisson on grid^3 (404^3 = the paper's poi65m: n = 65,939,264,
+    nnz = 460,595,552), assembled on the GPU, b ~ U[-1, 1] drawn on the
+    GPU.  Set-up and FP64 / mixed solve to rtol 1e-8 with Jacobi and
+    extended+i interpolation (the paper's Chr-jac configuration), then with
+    direct interpolation.  Each configuration runs once untimed, then once
+    timed."""
+    import torch
+
+    from paper_2102_07417_amd import camg, problems
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    n, rp, ci, va = problems.poisson3d_torch(grid, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    g = torch.Generator(device=dev)
+    g.manual_seed(7417)
+    db = torch.rand(n, dtype=torch.float64, device=dev, generator=g) * 2.0 - 1.0
+    dx = torch.zeros_like(db)
+    stream = torch.cuda.current_stream()
+    print(f"[poisson {grid}^3] n={n} nnz={int(rp[-1])} assembled in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    def run(interp, precision):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = camg.Solver.from_device(n, rp, ci, va, stream=stream, interp=interp, precision=precision)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dx.zero_()
+        r = s.solve_dev(db, dx, rtol=1e-8, stream=stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        inf = s.info
+        s.close()
+        return {"setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4), "iters": r.iters, "status": r.status,
+                "true_relres": r.true_relres, "ms_per_iter": round((t2 - t1) * 1e3 / max(r.iters, 1), 3),
+                "levels": inf.levels, "grid_complexity": round(inf.grid_complexity, 4),
+                "operator_complexity": round(inf.operator_complexity, 4),
+                "device_gb": round(inf.device_bytes / 1e9, 2),
+                "setup_phase_ms": {k: round(inf.setup_phase_ms[i], 2) for i, k in enumerate(camg.SETUP_PHASES)}}
+
+    out = {"grid": grid, "n": n, "nnz": int(rp[-1]), "assembly_s": round(gen_s, 2)}
+    for key, interp, prec in (("extended_i_fp64", camg.INTERP_EXTI, camg.FP64),
+                              ("extended_i_mixed", camg.INTERP_EXTI, camg.MIXED_FP32),
+                              ("direct_fp64", camg.INTERP_DIRECT, camg.FP64)):
+        run(interp, prec)
+        out[key] = run(interp, prec)
+        print(f"[poisson {grid}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
+    out["paper_chr_jac_poi65m"] = {"iters": 16, "setup_s": 3.81, "solve_s": 1.65, "cores": 384,
+                                   "hardware": "IBM POWER9 (Marconi100)", "grid_complexity": 1.327,
+                                   "operator_complexity": 4.036}
     return out
 
 

@@ -85,6 +85,9 @@ typedef struct {
     int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 192 entries
                              on or below the diagonal per row, and runs on the single-system path only */
     int32_t  interp;      /* CAMG_INTERP_DIRECT (default), _CLASSICAL, _EXTI or _HYBRID */
+    int64_t  rap_chunk;   /* Galerkin product R (A P): when A P has more products than this, it is formed in
+                             windows of coarse rows of at most this many products (bounds the set-up's scratch
+                             memory and keeps A P under 2^31 entries); 0: 2^30.  Results are bitwise the same */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32
@@ -101,6 +104,10 @@ typedef struct {
     int64_t device_bytes;                 /* device memory held by the handle */
     double  setup_ms;                     /* wall time of the set-up call */
     int32_t precision;
+    double  setup_phase_ms[8];            /* set-up wall time by phase, summed over levels: input copy and
+                                             checks, smoother weights, strength + PMIS + coarse numbering,
+                                             interpolation, R = P^T, Galerkin product, last-level factorisation,
+                                             launch shapes and solve buffers */
 } camg_info_t;
 
 int32_t     camg_abi_version(void);

@@ -40,7 +40,7 @@ class camg_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
-                ("interp", C.c_int32)]
+                ("interp", C.c_int32), ("rap_chunk", C.c_int64)]
 
 
 class camg_info_t(C.Structure):
@@ -48,7 +48,9 @@ class camg_info_t(C.Structure):
                 ("nnz_p", C.c_int64 * MAX_LEVELS), ("pmis_rounds", C.c_int32 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("grid_complexity", C.c_double),
                 ("operator_complexity", C.c_double), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("setup_phase_ms", C.c_double * 8)]
+SETUP_PHASES = ["input", "smoother", "strength_pmis", "interpolation", "transpose", "galerkin", "last_level",
+                "solve_prep"]
 
 
 _lib = None

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -171,6 +172,7 @@ void check_params(const camg_params &p) {
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
     if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI) fail(CAMG_E_ARG, "unknown smoother");
     if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_HYBRID) fail(CAMG_E_ARG, "unknown interpolation");
+    if (p.rap_chunk < 0) fail(CAMG_E_ARG, "rap_chunk must be >= 0");
 }
 
 // ---------------------------------------------------------------- set-up
@@ -217,6 +219,25 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     const auto t0 = std::chrono::steady_clock::now();
     const camg_params &prm = h.prm;
     Pool tmp(s);
+    // wall time per phase, taken at the stream synchronisations that end
+    // them; with CAMG_LOG_SETUP set in the environment each phase is also
+    // printed to stderr as it ends
+    static const char *const kPhase[8] = {"input", "smoother", "strength+pmis", "interpolation",
+                                          "transpose", "galerkin", "last level", "solve buffers"};
+    static const bool log_setup = std::getenv("CAMG_LOG_SETUP") != nullptr;
+    auto tp = t0;
+    int cur_level = 0;
+    auto phase = [&](int k) {
+        HIPC(hipStreamSynchronize(s));
+        const auto t = std::chrono::steady_clock::now();
+        const double dt = std::chrono::duration<double, std::milli>(t - tp).count();
+        h.phase_ms[k] += dt;
+        tp = t;
+        if (log_setup) {
+            std::fprintf(stderr, "[camg setup] level %d %s %.1f ms\n", cur_level, kPhase[k], dt);
+            std::fflush(stderr);
+        }
+    };
     int64_t nnz;
     if (host_in) nnz = rp[n];
     else nnz = read1(rp + n, s);
@@ -238,11 +259,13 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     }
     int32_t *tpos = tmp.alloc<int32_t>(std::max<int64_t>(nnz, 1));
     validate_input(h, n, nnz, h.lev[0].A, tpos, tmp, s);
+    phase(0);
 
     int32_t *flags = tmp.alloc<int32_t>(8);
     unsigned long long *qmax = tmp.alloc<unsigned long long>(1);
     int32_t *und = tmp.alloc<int32_t>(1);
     for (int l = 0;; ++l) {
+        cur_level = l;
         const int nl = h.lev[l].A.nr;
         if (nl <= prm.max_coarse || l == prm.max_levels - 1) break;
         Level &L = h.lev[l];
@@ -311,6 +334,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                 L.omega = (4.0 / 3.0) / cw_bound(M, lt, s);
             }
         }
+        phase(1);
         // strength and PMIS
         L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
         L.stcnt = h.pool.alloc<int32_t>(nl);
@@ -335,6 +359,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         scan_i32_to_i64(isc, cmap, nl, lt, s);
         const int64_t nc = read1(cmap + nl, s);
         if (nc == 0 || nc == nl) break;  // coarsening stalled: this is the last level
+        phase(2);
         // interpolation P = [W; I]: direct, or the paper's classical,
         // extended+i or hybrid formula
         Csr &P = L.P;
@@ -369,6 +394,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             HIPC(hipStreamSynchronize(s));
             if (hf[0] || hf[1]) fail(CAMG_E_DEVICE, "interpolation: inconsistent candidate lists");
         }
+        phase(3);
         // R = P^T
         Csr &R = L.R;
         R.nr = P.nc;
@@ -383,10 +409,11 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         R.ci = h.pool.alloc<int32_t>(padded(R.nnz));
         R.v = h.pool.alloc<double>(padded(R.nnz));
         transpose_csr(P, R, lt, s);
+        phase(4);
         // Galerkin product A_{l+1} = R (A P)  (eq. AcDef)
-        Csr AP, Ac;
-        spgemm(L.A, P, AP, lt, lt, s);
-        spgemm(R, AP, Ac, h.pool, lt, s);
+        Csr Ac;
+        galerkin(L.A, P, R, Ac, prm.rap_chunk, h.pool, lt, s);
+        phase(5);
         HIPC(hipStreamSynchronize(s));
         lt.release();
         Level next;
@@ -410,6 +437,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         h.cinv = h.pool.alloc<double>((size_t)h.nL * h.nL);
         chol_inverse(h.nL, D, h.cinv, s);
     }
+    phase(6);
     // launch shapes, work vectors, mixed-precision copies
     const bool mixed = prm.precision == CAMG_MIXED_FP32;
     for (int l = 0; l < h.nlev; ++l) {
@@ -473,6 +501,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     HIPC(hipHostMalloc((void **)&h.hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
     HIPC(hipHostGetDevicePointer((void **)&h.hflag_dev, h.hflag, 0));
     HIPC(hipStreamSynchronize(s));
+    phase(7);
     h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -852,6 +881,7 @@ void camg_params_default(camg_params *p) {
     p->max_iter = 1000;
     p->smoother = CAMG_SMOOTH_JACOBI;
     p->interp = CAMG_INTERP_DIRECT;
+    p->rap_chunk = 0;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
@@ -951,6 +981,7 @@ camg_status camg_info(camg_handle hh, camg_info_t *info) {
         info->device_bytes = h->pool.bytes;
         info->setup_ms = h->setup_ms;
         info->precision = h->prm.precision;
+        for (int k = 0; k < 8; ++k) info->setup_phase_ms[k] = h->phase_ms[k];
     });
 }
 

@@ -117,7 +117,7 @@ __device__ __forceinline__ int find_col(const int32_t *ci, int lo, int hi, int j
     // position of j in the sorted ci[lo, hi) or -1
     hi -= 1;
     while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
+        int mid = lo + ((hi - lo) >> 1);
         int c = ci[mid];
         if (c == j) return mid;
         if (c < j) lo = mid + 1; else hi = mid - 1;

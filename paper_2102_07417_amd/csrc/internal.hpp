@@ -147,6 +147,7 @@ struct Hier {
     int32_t *hflag_dev = nullptr;
     std::atomic<int> busy{0};
     double setup_ms = 0.0;
+    double phase_ms[8] = {};  // set-up time per phase (camg_info_t.setup_phase_ms)
     // optional timing of the level-0 post-smoothing kernel inside solves
     bool prof = false;
     int prof_stride = 1;  // time every prof_stride-th iteration
@@ -234,6 +235,10 @@ void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, h
 // entry the products are added in ascending order of the inner index.
 // Z's arrays are allocated from `out`.
 void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_t s);
+// A_c = R (A P); A P is formed in windows of at most `chunk` products
+// (0: 2^30) when it would be larger; bitwise the same either way.
+void galerkin(const Csr &A, const Csr &P, const Csr &R, Csr &Ac, int64_t chunk, Pool &out, Pool &tmp,
+              hipStream_t s);
 
 // ---------------------------------------------------------------- solve (solve.hip)
 RowCfg choose_cfg(int n, int64_t nnz, int maxrow);

@@ -16,6 +16,15 @@ namespace {
 
 inline int nblocks(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
 
+// wavefront-scope barrier: LDS writes of the wavefront are visible to all its lanes
+#define FSAI_SYNC()                                             \
+    do {                                                        \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                        \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+    } while (0)
+
+
 // ---------------------------------------------------------------- scan
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -338,12 +347,17 @@ __global__ void k_transpose_fill(int nr, const int32_t *rp, const int32_t *ci, c
     }
 }
 
-// rows of the transpose come out of k_transpose_fill in arbitrary order:
-// insertion sort each row by column (rows are short)
+// rows of the transpose come out of k_transpose_fill in arbitrary order and
+// are sorted by column: rows of at most kSortShort entries by one thread
+// (insertion sort), rows of at most kSortWave by a wavefront, longer ones by
+// a workgroup (k_sort_rows_block); the longer two rank the entries
+constexpr int kSortShort = 32, kSortWave = 1024, kSortBlockLds = 8192;
+
 __global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr) return;
     const int e0 = rp[i], e1 = rp[i + 1];
+    if (e1 - e0 > kSortShort) return;
     for (int e = e0 + 1; e < e1; ++e) {
         const int c = ci[e];
         const double x = v[e];
@@ -355,6 +369,64 @@ __global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
         }
         ci[f + 1] = c;
         v[f + 1] = x;
+    }
+}
+
+// one wavefront per row of kSortShort < length <= kSortWave entries: the
+// row is staged in LDS and every entry moves to its rank (the columns of a
+// row are distinct)
+__global__ void __launch_bounds__(256) k_sort_rows_wave(int nr, const int32_t *rp, int32_t *ci, double *v) {
+    __shared__ int kc[4][kSortWave];
+    __shared__ double kv[4][kSortWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= nr) return;
+    const int e0 = rp[i], L = rp[i + 1] - e0;
+    if (L <= kSortShort || L > kSortWave) return;
+    for (int t = lane; t < L; t += kWave) {
+        kc[w][t] = ci[e0 + t];
+        kv[w][t] = v[e0 + t];
+    }
+    FSAI_SYNC();
+    for (int t = lane; t < L; t += kWave) {
+        const int c = kc[w][t];
+        int r = 0;
+        for (int u = 0; u < L; ++u) r += kc[w][u] < c ? 1 : 0;
+        ci[e0 + r] = c;
+        v[e0 + r] = kv[w][t];
+    }
+}
+
+// indices of the rows longer than minlen (in any order) and their number
+__global__ void k_long_rows(int nr, const int32_t *rp, int minlen, int32_t *list, int32_t *count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && rp[i + 1] - rp[i] > minlen) list[atomicAdd(count, 1)] = i;
+}
+
+// one workgroup per listed row: the unsorted row is read from a copy (sci,
+// sv) and every entry is written at its rank; the keys are staged in LDS
+// when they fit
+__global__ void __launch_bounds__(1024) k_sort_rows_block(const int32_t *list, const int32_t *rp,
+                                                          const int32_t *sci, const double *sv, int32_t *ci,
+                                                          double *v) {
+    __shared__ int kc[kSortBlockLds];
+    const int i = list[blockIdx.x];
+    const int e0 = rp[i], L = rp[i + 1] - e0;
+    const bool lds = L <= kSortBlockLds;
+    if (lds) {
+        for (int t = threadIdx.x; t < L; t += blockDim.x) kc[t] = sci[e0 + t];
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int c = sci[e0 + t];
+        int r = 0;
+        if (lds) {
+            for (int u = 0; u < L; ++u) r += kc[u] < c ? 1 : 0;
+        } else {
+            for (int u = 0; u < L; ++u) r += sci[e0 + u] < c ? 1 : 0;
+        }
+        ci[e0 + r] = c;
+        v[e0 + r] = sv[e0 + t];
     }
 }
 
@@ -494,13 +566,6 @@ __device__ __forceinline__ double csr_lookup(const int32_t *rp, const int32_t *c
     }
     return 0.0;
 }
-
-#define FSAI_SYNC()                                             \
-    do {                                                        \
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
-        __builtin_amdgcn_wave_barrier();                        \
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
-    } while (0)
 
 // TPR threads (one wavefront, or a 256-thread workgroup for long rows) per
 // row; the lower triangle of the local matrix (m <= MAXM) packed row by row
@@ -674,6 +739,7 @@ struct XiLds {
     double red[TPR / 64];
     int redi[TPR / 64];
     unsigned long long redu[TPR / 64];
+    double term[TPR];
     double diag;
     int cnt;
 };
@@ -737,7 +803,7 @@ __device__ __forceinline__ unsigned long long xi_max(unsigned long long x, unsig
 __device__ __forceinline__ int xi_find(const int *S, int U, int c) {
     int lo = 0, hi = U - 1;
     while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
+        const int mid = lo + ((hi - lo) >> 1);
         const int x = S[mid];
         if (x == c) return mid;
         if (x < c) lo = mid + 1;
@@ -923,15 +989,26 @@ __global__ void __launch_bounds__(WPB * TPR)
                 const int f0 = rp[k], f1 = rp[k + 1];
                 const double akk = csr_lookup(rp, ci, v, k, k);
                 const int sd = (akk > 0.0) - (akk < 0.0);
-                // denominator: every lane walks row k in CSR (= ascending
-                // column) order, the CPU reference's order over the set
+                // denominator: the terms of row k are formed in parallel and
+                // added in CSR (= ascending column) order, the CPU
+                // reference's order over the set (terms outside the set are
+                // +0.0 and change nothing)
                 double D = 0.0;
-                for (int f = f0; f < f1; ++f) {
-                    const int l = ci[f];
-                    const double x = v[f];
-                    const int sx = (x > 0.0) - (x < 0.0);
-                    const double ab = sx == sd ? 0.0 : x;
-                    if ((plus_i && l == i) || xi_find(G.S, U, l) >= 0) D = D + ab;
+                for (int fb = f0; fb < f1; fb += TPR) {
+                    const int f = fb + lane;
+                    double term = 0.0;
+                    if (f < f1) {
+                        const int l = ci[f];
+                        const double x = v[f];
+                        const int sx = (x > 0.0) - (x < 0.0);
+                        const double ab = sx == sd ? 0.0 : x;
+                        if ((plus_i && l == i) || xi_find(G.S, U, l) >= 0) term = ab;
+                    }
+                    G.term[lane] = term;
+                    fsai_sync<TPR>();
+                    const int m = min(TPR, f1 - fb);
+                    for (int q = 0; q < m; ++q) D = D + G.term[q];
+                    fsai_sync<TPR>();
                 }
                 if (D == 0.0) {
                     diag = diag + a;
@@ -1103,7 +1180,24 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s) {
     int32_t *fill = tmp.alloc<int32_t>((size_t)X.nc + 1);
     HIPC(hipMemcpyAsync(fill, XT.rp, sizeof(int32_t) * ((size_t)X.nc + 1), hipMemcpyDeviceToDevice, s));
     k_transpose_fill<<<nblocks(X.nr), kBlock, 0, s>>>(X.nr, X.rp, X.ci, X.v, fill, XT.ci, XT.v);
-    k_sort_rows<<<nblocks(X.nc), kBlock, 0, s>>>(X.nc, XT.rp, XT.ci, XT.v);
+    HIPC(hipGetLastError());
+    const int nc = X.nc;
+    int32_t *list = tmp.alloc<int32_t>(std::max(nc, 1)), *cnt = tmp.alloc<int32_t>(1);
+    HIPC(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+    k_long_rows<<<nblocks(nc), kBlock, 0, s>>>(nc, XT.rp, kSortWave, list, cnt);
+    HIPC(hipGetLastError());
+    int32_t nlong = 0;
+    HIPC(hipMemcpyAsync(&nlong, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (nlong > 0) {
+        int32_t *sci = tmp.alloc<int32_t>(padded(X.nnz));
+        double *sv = tmp.alloc<double>(padded(X.nnz));
+        HIPC(hipMemcpyAsync(sci, XT.ci, sizeof(int32_t) * X.nnz, hipMemcpyDeviceToDevice, s));
+        HIPC(hipMemcpyAsync(sv, XT.v, sizeof(double) * X.nnz, hipMemcpyDeviceToDevice, s));
+        k_sort_rows_block<<<nlong, 1024, 0, s>>>(list, XT.rp, sci, sv, XT.ci, XT.v);
+    }
+    k_sort_rows<<<nblocks(nc), kBlock, 0, s>>>(nc, XT.rp, XT.ci, XT.v);
+    k_sort_rows_wave<<<(nc + 3) / 4, 256, 0, s>>>(nc, XT.rp, XT.ci, XT.v);
     HIPC(hipGetLastError());
 }
 void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,

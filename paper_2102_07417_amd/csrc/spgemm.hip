@@ -14,7 +14,8 @@
 //      are therefore rounded exactly as a sequential row-by-row product
 //      with a dense accumulator rounds them.
 // Rows whose table would not fit in LDS use the same code on tables in a
-// global scratch buffer.
+// global scratch buffer.  galerkin() forms R (A P), in chunks of coarse rows
+// when A P would be large.
 #include <algorithm>
 #include <climits>
 #include <vector>
@@ -52,6 +53,31 @@ __global__ void k_row_products(int nr, CsrView X, CsrView Y, int64_t *prod) {
         p += Y.rp[k + 1] - Y.rp[k];
     }
     prod[i] = p;
+}
+
+// first and last column of every row (INT_MAX / -1 for an empty row)
+__global__ void k_row_span(int nr, const int32_t *rp, const int32_t *ci, int32_t *lo, int32_t *hi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const bool any = rp[i] < rp[i + 1];
+    lo[i] = any ? ci[rp[i]] : INT_MAX;
+    hi[i] = any ? ci[rp[i + 1] - 1] : -1;
+}
+
+// rows [c0, c0 + m) of X as a matrix of their own, columns shifted by -f0
+__global__ void k_slice_rows(int m, const int32_t *rp, int c0, int32_t *rp2) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r <= m) rp2[r] = rp[c0 + r] - rp[c0];
+}
+
+__global__ void k_shift_cols(int64_t ne, const int32_t *ci, int f0, int32_t *ci2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < ne) ci2[e] = ci[e] - f0;
+}
+
+__global__ void k_offset_rp(int m, const int32_t *rp, int64_t base, int32_t *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r <= m) out[r] = (int32_t)(rp[r] + base);
 }
 
 // bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is
@@ -453,6 +479,112 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
         HIPC(hipGetLastError());
         HIPC(hipStreamSynchronize(s));
     }
+}
+
+// A_c = R (A P) (eq. AcDef).  When the products of A P exceed `chunk`, the
+// coarse rows are taken in consecutive chunks: a chunk needs the rows of
+// A P between the smallest and the largest fine index its rows of R touch,
+// which are formed from the same rows of A; the chunk's rows of A_c are then
+// R_chunk times that window.  Every entry receives the same products in the
+// same order as in the unchunked product, so the result is bitwise the same;
+// only the temporary memory shrinks.
+void galerkin(const Csr &A, const Csr &P, const Csr &R, Csr &Ac, int64_t chunk, Pool &out, Pool &tmp,
+              hipStream_t s) {
+    const int64_t budget = chunk > 0 ? chunk : (int64_t)1 << 30;
+    const int nf = A.nr, ncr = R.nr;
+    int64_t *prod = tmp.alloc<int64_t>(std::max(nf, 1));
+    int64_t *pref = tmp.alloc<int64_t>((size_t)nf + 1);
+    CsrView av{A.rp, A.ci, A.v}, pv{P.rp, P.ci, P.v};
+    if (nf > 0) k_row_products<<<nblk(nf, kBlock), kBlock, 0, s>>>(nf, av, pv, prod);
+    HIPC(hipGetLastError());
+    scan_i64(prod, pref, nf, tmp, s);
+    int64_t total = 0;
+    HIPC(hipMemcpyAsync(&total, pref + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (total <= budget || ncr <= 1) {
+        Csr AP;
+        spgemm(A, P, AP, tmp, tmp, s);
+        spgemm(R, AP, Ac, out, tmp, s);
+        return;
+    }
+    // plan the chunks on the host
+    std::vector<int64_t> hpref((size_t)nf + 1);
+    std::vector<int32_t> lo(ncr), hi(ncr), rrp((size_t)ncr + 1);
+    {
+        int32_t *dlo = tmp.alloc<int32_t>(ncr), *dhi = tmp.alloc<int32_t>(ncr);
+        k_row_span<<<nblk(ncr, kBlock), kBlock, 0, s>>>(ncr, R.rp, R.ci, dlo, dhi);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(hpref.data(), pref, sizeof(int64_t) * hpref.size(), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(lo.data(), dlo, sizeof(int32_t) * ncr, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(hi.data(), dhi, sizeof(int32_t) * ncr, hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(rrp.data(), R.rp, sizeof(int32_t) * rrp.size(), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    }
+    struct Part {
+        int c0, c1, f0, f1;
+        Csr C;
+    };
+    std::vector<Part> parts;
+    for (int c0 = 0; c0 < ncr;) {
+        int f0 = lo[c0], f1 = hi[c0], c1 = c0 + 1;
+        while (c1 < ncr) {
+            const int a = std::min(f0, lo[c1]), b = std::max(f1, hi[c1]);
+            if (a <= b && hpref[b + 1] - hpref[a] > budget) break;
+            f0 = a;
+            f1 = b;
+            ++c1;
+        }
+        if (f0 > f1) f0 = f1 = 0;  // rows of R without entries
+        parts.push_back({c0, c1, f0, f1, Csr{}});
+        c0 = c1;
+    }
+    Pool keep(s);
+    int64_t nnz = 0;
+    for (Part &pt : parts) {
+        Pool g(s);
+        Csr Aw;  // rows f0..f1 of A (row pointers index A's arrays)
+        Aw.nr = pt.f1 - pt.f0 + 1;
+        Aw.nc = A.nc;
+        Aw.rp = A.rp + pt.f0;
+        Aw.ci = A.ci;
+        Aw.v = A.v;
+        Csr APw;
+        spgemm(Aw, P, APw, g, g, s);
+        const int m = pt.c1 - pt.c0;
+        const int64_t e0 = rrp[pt.c0], ne = (int64_t)rrp[pt.c1] - e0;
+        Csr Rc;
+        Rc.nr = m;
+        Rc.nc = Aw.nr;
+        Rc.nnz = ne;
+        Rc.rp = g.alloc<int32_t>((size_t)m + 1);
+        Rc.ci = g.alloc<int32_t>(padded(std::max<int64_t>(ne, 1)));
+        Rc.v = R.v + e0;
+        k_slice_rows<<<nblk(m + 1, kBlock), kBlock, 0, s>>>(m, R.rp, pt.c0, Rc.rp);
+        if (ne > 0) k_shift_cols<<<nblk(ne, kBlock), kBlock, 0, s>>>(ne, R.ci + e0, pt.f0, Rc.ci);
+        HIPC(hipGetLastError());
+        spgemm(Rc, APw, pt.C, keep, g, s);
+        HIPC(hipStreamSynchronize(s));
+        nnz += pt.C.nnz;
+    }
+    if (nnz > INT32_MAX) fail(CAMG_E_NOMEM, "Galerkin product has more than 2^31-1 nonzeros");
+    Ac.nr = ncr;
+    Ac.nc = P.nc;
+    Ac.nnz = nnz;
+    Ac.rp = out.alloc<int32_t>((size_t)ncr + 1);
+    Ac.ci = out.alloc<int32_t>(padded(nnz));
+    Ac.v = out.alloc<double>(padded(nnz));
+    int64_t base = 0;
+    for (const Part &pt : parts) {
+        const int m = pt.c1 - pt.c0;
+        k_offset_rp<<<nblk(m + 1, kBlock), kBlock, 0, s>>>(m, pt.C.rp, base, Ac.rp + pt.c0);
+        HIPC(hipGetLastError());
+        if (pt.C.nnz > 0) {
+            HIPC(hipMemcpyAsync(Ac.ci + base, pt.C.ci, sizeof(int32_t) * pt.C.nnz, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(Ac.v + base, pt.C.v, sizeof(double) * pt.C.nnz, hipMemcpyDeviceToDevice, s));
+        }
+        base += pt.C.nnz;
+    }
+    HIPC(hipStreamSynchronize(s));
 }
 
 }  // namespace camg

@@ -139,6 +139,44 @@ def poisson3d(nx: int, ny: int | None = None, nz: int | None = None) -> CSR:
     return _stencil_csr(shape, _OFF3, 6.0 * one, [-one] * 6)
 
 
+def poisson3d_torch(nx: int, ny: int | None = None, nz: int | None = None, device="cpu"):
+    """The matrix of ``poisson3d`` assembled with torch on ``device`` (for
+    grids whose host assembly would be slow, e.g. 404^3 with 4.6e8
+    nonzeros).  Returns (n, row_ptr int32, col_idx int32, val float64)
+    tensors equal to ``poisson3d``'s arrays."""
+    import torch
+
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    n = nx * ny * nz
+    i = torch.arange(n, dtype=torch.int64, device=device)
+    x = i % nx
+    y = (i // nx) % ny
+    z = i // (nx * ny)
+    one = torch.ones_like(i, dtype=torch.bool)
+    # neighbours in ascending column order: z-1, y-1, x-1, self, x+1, y+1, z+1
+    offs = [-nx * ny, -nx, -1, 0, 1, nx, nx * ny]
+    masks = [z > 0, y > 0, x > 0, one, x < nx - 1, y < ny - 1, z < nz - 1]
+    cnt = torch.zeros(n, dtype=torch.int32, device=device)
+    for m in masks:
+        cnt += m.to(torch.int32)
+    del x, y, z
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(cnt, 0, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    col_idx = torch.empty(nnz, dtype=torch.int32, device=device)
+    val = torch.empty(nnz, dtype=torch.float64, device=device)
+    pos = row_ptr[:-1].clone()
+    for o, m in zip(offs, masks):
+        rows = torch.nonzero(m).squeeze(1) if o != 0 else i
+        p = pos[rows]
+        col_idx[p] = (rows + o).to(torch.int32)
+        val[p] = 6.0 if o == 0 else -1.0
+        pos[rows] += 1
+        del rows, p
+    return n, row_ptr.to(torch.int32), col_idx, val
+
+
 def aniso3d(n: int, eps: float = 1e-3) -> CSR:
     """7-point anisotropic diffusion on n^3: x/y couplings -1, z couplings -eps,
     diagonal 4 + 2 eps (Dirichlet eliminated)."""

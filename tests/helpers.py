@@ -65,3 +65,31 @@ def wide_stencil_2d(g, r):
             M[idx[ys[ok], xs[ok]], idx[yy[ok], xx[ok]]] = -1.0
     M[np.arange(g * g), np.arange(g * g)] = -M.sum(1) + 1.0
     return from_dense(M)
+
+
+def hub_graph(g):
+    """A g x g 5-point grid plus one hub point coupled with weight -1 to
+    every grid point (diagonals: coupling count + 0.1, so the matrix is
+    strictly diagonally dominant).  Every grid point depends strongly on
+    the hub, so PMIS makes the hub the only C point and the restriction has
+    one row of g^2 entries.  Assembled sparse, in CSR order."""
+    n = g * g + 1
+    hub = g * g
+    rows = [[] for _ in range(n)]
+    for y in range(g):
+        for x in range(g):
+            i = y * g + x
+            for yy, xx in ((y - 1, x), (y, x - 1), (y, x + 1), (y + 1, x)):
+                if 0 <= yy < g and 0 <= xx < g:
+                    rows[i].append((yy * g + xx, -1.0))
+            rows[i].append((hub, -1.0))
+            rows[hub].append((i, -1.0))
+    rp = [0]
+    ci, v = [], []
+    for i in range(n):
+        ent = rows[i] + [(i, len(rows[i]) + 0.1)]
+        ent.sort()
+        ci += [c for c, _ in ent]
+        v += [a for _, a in ent]
+        rp.append(len(ci))
+    return (n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v, np.float64))

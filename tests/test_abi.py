@@ -67,7 +67,7 @@ def test_argument_errors_without_device(lib):
 
 
 @pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 2), ("theta", 1.5),
-                                         ("precision", 3)])
+                                         ("precision", 3), ("rap_chunk", -1)])
 def test_bad_parameters_rejected_without_device(lib, field, value):
     # parameters are checked before the device is touched
     rp = np.array([0, 1], np.int32)
@@ -89,10 +89,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "camg.h"
 int main(void) {
-  printf("params %zu %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
+  printf("params %zu %zu %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
          offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother),
-         offsetof(camg_params, interp));
-  printf("info %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p));
+         offsetof(camg_params, interp), offsetof(camg_params, rap_chunk));
+  printf("info %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
+         offsetof(camg_info_t, setup_phase_ms));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
          offsetof(camg_completion, latency_ms));
   return 0;
@@ -104,8 +105,8 @@ int main(void) {
                for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     P = camg.camg_params
     assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset,
-                             P.interp.offset]
+                             P.interp.offset, P.rap_chunk.offset]
     I = camg.camg_info_t
-    assert out["info"] == [C.sizeof(I), I.nnz_p.offset]
+    assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset]
     Q = camg.camg_completion
     assert out["completion"] == [C.sizeof(Q), Q.true_relres.offset, Q.latency_ms.offset]

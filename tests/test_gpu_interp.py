@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2102_07417_amd import problems as PB
-from tests.helpers import wide_stencil_2d
+from tests.helpers import hub_graph, wide_stencil_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -167,3 +167,47 @@ def test_interp_full_size_lognormal_128(camg):
     rd = gd.solve_dev(db, torch.zeros_like(dx), rtol=1e-8)
     assert r.iters < rd.iters, (r.iters, rd.iters)
     gd.close()
+
+
+@pytest.mark.parametrize("variant", ["direct", "exti"])
+@pytest.mark.parametrize("name", ["lognormal3d_24", "elasticity_6", "poisson2d_ragged_37x23"])
+def test_chunked_galerkin_bit_exact(camg, name, variant):
+    """A tiny rap_chunk forces the Galerkin product into many windows of
+    coarse rows; every level must still equal the oracle's bit for bit."""
+    print(f"[gpu] chunked galerkin {name} {variant}", flush=True)
+    A = CASES[name]()
+    code = variant.upper()
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), max_coarse=40,
+                                interp=getattr(camg, "INTERP_" + code), rap_chunk=2000)
+    o = O.Hierarchy(A, max_coarse=40, interp=getattr(O, "INTERP_" + code))
+    assert g.nlev == o.nlev
+    for l in range(o.nlev):
+        ga, oa = g.A(l), o.A(l)
+        assert np.array_equal(ga[2], oa[2]) and np.array_equal(ga[3], oa[3]), f"A_{l} pattern"
+        assert np.array_equal(ga[4], oa[4]), f"A_{l} values"
+    g.close()
+
+
+@pytest.mark.parametrize("variant", ["direct", "exti"])
+@pytest.mark.parametrize("g", [40, 100])
+def test_transpose_long_rows(camg, g, variant):
+    """A hub point that every grid point interpolates from: R has one row
+    of g^2 + 1 entries (1601: sorted by a workgroup in LDS; 10001: from a global
+    copy).  The hierarchy must match the oracle bit for bit and the solve
+    must agree."""
+    print(f"[gpu] long transpose rows hub {g} {variant}", flush=True)
+    A = hub_graph(g)
+    n, rp, ci, v = _csr(A)
+    code = getattr(camg, "INTERP_" + variant.upper())
+    gs = camg.Solver.from_device(n, _dev(rp), _dev(ci), _dev(v), max_coarse=40, interp=code)
+    o = O.Hierarchy(A, max_coarse=40, interp=getattr(O, "INTERP_" + variant.upper()))
+    assert gs.nlev == o.nlev == 2
+    for what in ("P", "R"):
+        gp, op = getattr(gs, what)(0), getattr(o, what)(0)
+        assert np.array_equal(gp[2], op[2]) and np.array_equal(gp[3], op[3]) and np.array_equal(gp[4], op[4])
+    assert np.diff(gs.R(0)[2]).max() == g * g + 1   # the grid points and the hub itself
+    b = np.random.default_rng(g).uniform(-1.0, 1.0, n)
+    r, ro = gs.solve(b), o.solve(b, 1e-8)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    gs.close()

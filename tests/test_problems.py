@@ -82,3 +82,12 @@ def test_rhs_reproducible():
     assert np.array_equal(a, b) and a.min() >= -1 and a.max() <= 1
     B = PB.rhs_block(100, 3, 7)
     assert np.array_equal(B[:, 0], a) and np.array_equal(B[:, 2], PB.rhs(100, 9))
+
+
+def test_poisson3d_torch_matches_numpy():
+    for shape in [(5, 5, 5), (7, 4, 3), (1, 6, 2)]:
+        A = PB.poisson3d(*shape)
+        n, rp, ci, v = PB.poisson3d_torch(*shape)
+        assert n == A.n
+        assert np.array_equal(rp.numpy(), A.row_ptr) and np.array_equal(ci.numpy(), A.col_idx)
+        assert np.array_equal(v.numpy(), A.val)
