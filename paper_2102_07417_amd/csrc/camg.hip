@@ -374,7 +374,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             bnd = lt.alloc<int32_t>(nl);
             xflags = lt.alloc<int32_t>(2);
             HIPC(hipMemsetAsync(xflags, 0, 2 * sizeof(int32_t), s));
-            bmax = xi_bounds(nl, L.A, L.strong, L.cf, prm.interp, bnd, lt, s);
+            xi_bounds(nl, L.A, L.strong, L.cf, prm.interp, bnd, &bmax, lt, s);
             xi_count(nl, L.A, L.strong, L.cf, prm.interp, bnd, bmax, pcnt, xflags, s);
         }
         int64_t *prp64 = lt.alloc<int64_t>((size_t)nl + 1);

@@ -205,8 +205,10 @@ void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, c
 // (variant = CAMG_INTERP_*): per-row bound of the candidate list (returns
 // the largest), set sizes (cnt) and the rows of P.  flags[0]: candidate
 // list overflow; flags[1]: count and fill passes disagree.
-int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, Pool &tmp,
-              hipStream_t s);
+// (xi_bounds also gives the largest bound of the rows not handled one thread
+// per row; that one is passed to xi_count / xi_fill)
+int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, int *bmax_wave,
+              Pool &tmp, hipStream_t s);
 void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
               int32_t *cnt, int32_t *flags, hipStream_t s);
 void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,

@@ -682,7 +682,10 @@ __global__ void __launch_bounds__(WPB * TPR) k_fsai_rows(int n, const int32_t *_
 // entries abar_kl of row k (abar_kl = 0 when a_kl has the sign of a_kk), so
 // P matches the reference bit for bit.
 constexpr int kXiClassical = 1, kXiExt = 2, kXiHybrid = 3;
-constexpr int kXiCapWave = 256, kXiCapGroup = 2048;  // candidate capacity of a wavefront / workgroup
+// candidate capacity of a thread, a wavefront and a 256-thread workgroup (two tiers)
+constexpr int kXiCapThread = 32, kXiCapSmall = 128, kXiCapMid = 512, kXiCapGroup = 2048;
+// rows handled by one thread: at most kXiCapThread candidates and kXiThreadLen entries
+constexpr int kXiThreadLen = 16;
 
 // strong C neighbours of every row
 __global__ void k_xi_cs(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
@@ -699,6 +702,8 @@ __global__ void k_xi_cs(int n, const int32_t *rp, const int32_t *ci, const uint8
 // |C_k^S| of its strong F neighbours for the two distance-two variants
 __global__ void k_xi_bound(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
                            const int32_t *cs, int variant, int32_t *bnd, unsigned long long *bmax) {
+    // bmax[0]: largest bound; bmax[1]: largest bound of the rows that the
+    // thread-per-row kernel does not take
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     long long b = 0;
     if (i < n && cf[i] != kC) {
@@ -710,8 +715,13 @@ __global__ void k_xi_bound(int n, const int32_t *rp, const int32_t *ci, const ui
             }
     }
     if (i < n) bnd[i] = (int32_t)(b < INT32_MAX ? b : INT32_MAX);
+    const bool thread_row = i < n && b <= kXiCapThread && rp[i + 1] - rp[i] <= kXiThreadLen;
     const unsigned long long m = block_max_u64<kBlock>((unsigned long long)b);
-    if (threadIdx.x == 0) atomicMax(bmax, m);
+    const unsigned long long mw = block_max_u64<kBlock>(thread_row ? 0ull : (unsigned long long)b);
+    if (threadIdx.x == 0) {
+        atomicMax(bmax, m);
+        atomicMax(bmax + 1, mw);
+    }
 }
 
 // C rows (identity) and F rows without candidates (empty)
@@ -732,10 +742,33 @@ __global__ void k_xi_simple(int n, const int8_t *cf, const int32_t *bnd, const i
     }
 }
 
-template <int CAP, int TPR>
+template <int CAP, int CAPF, int TPR>
 struct XiLds {
-    int cand[CAP], src[CAP], aux[CAP], pos[CAP], S[CAP], Q[CAP], rem[CAP];
+    static_assert(16 * CAPF <= 24 * CAP, "the flattened rows overlay the candidate arrays");
+    // candidate lists while the set is built; the flattened rows of the
+    // fill pass afterwards: column of each entry, its place in the set (-1
+    // none, -2 the point i itself) and its sign-filtered value
+    union {
+        struct {
+            int cand[CAP], src[CAP], aux[CAP], pos[CAP], Q[CAP], rem[CAP];
+        };
+        struct {
+            double fab[CAPF];
+            int fl[CAPF], fp[CAPF];
+        };
+    };
+    int S[CAP];
     double num[CAP];
+    // one chunk (TPR entries) of row i: kind of each entry (0 diagonal, 1
+    // strong F neighbour, 2 other member of the set, 3 other), its column and
+    // value, and for strong F neighbours the start, length and diagonal of
+    // their row
+    int mk[TPR], mkind[TPR], mr0[TPR], mlen[TPR];
+    double ma[TPR], makk[TPR];
+    // a group of consecutive chunk entries whose strong F rows, laid end to
+    // end, fit CAPF entries: chunk position and offset of each such row
+    int gq[TPR], goff[TPR + 1], gb[TPR], hasc[TPR], cov[TPR];
+    double gD[TPR], gai[TPR];  // denominators of the group's rows, their sign-filtered entry at i
     double red[TPR / 64];
     int redi[TPR / 64];
     unsigned long long redu[TPR / 64];
@@ -812,39 +845,111 @@ __device__ __forceinline__ int xi_find(const int *S, int U, int c) {
     return -1;
 }
 
-// out[0, U) = the distinct values of in[0, T) in ascending order;
-// pos[t] = the place of in[t] in out.  Returns U (all lanes).
+// Exclusive scan of one int per lane over the row group; *total gets the sum.
 template <int TPR>
-__device__ int xi_sort_unique(const int *in, int T, int *out, int *pos, int *first, int *red, int lane) {
-    for (int t = lane; t < T; t += TPR) {
-        const int x = in[t];
-        int f = 1;
-        for (int u = 0; u < t; ++u)
-            if (in[u] == x) {
-                f = 0;
-                break;
-            }
-        first[t] = f;
+__device__ __forceinline__ int xi_scan_excl(int c, int *red, int lane, int *total) {
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if ((lane & 63) >= o) x += y;
     }
+    if constexpr (TPR == 64) {
+        *total = __shfl(x, 63, kWave);
+        return x - c;
+    } else {
+        __syncthreads();
+        if ((lane & 63) == 63) red[lane >> 6] = x;
+        __syncthreads();
+        int base = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < TPR / 64; ++w) {
+            if (w < (lane >> 6)) base += red[w];
+            tot += red[w];
+        }
+        __syncthreads();
+        *total = tot;
+        return base + x - c;
+    }
+}
+
+// The distinct values of key[0, T) in ascending order go to out[0, U);
+// pos[t] is the place of key[t] in out (when pos is given); returns U (all
+// lanes).  Short lists are ranked in place (key keeps its order; `first` is
+// scratch); longer ones are bitonic-sorted in place first (key, and tag
+// with it when given, then hold the sorted order) and deduplicated with a
+// scan.  key must have room for the next power of two of T entries.
+template <int TPR>
+__device__ int xi_sort_unique(int *key, int *tag, int T, int *out, int *pos, int *first, int *red, int lane) {
+    if (T <= 64) {
+        for (int t = lane; t < T; t += TPR) {
+            const int x = key[t];
+            int f = 1;
+            for (int u = 0; u < t; ++u)
+                if (key[u] == x) {
+                    f = 0;
+                    break;
+                }
+            first[t] = f;
+        }
+        fsai_sync<TPR>();
+        int mine = 0;
+        for (int t = lane; t < T; t += TPR) {
+            const int x = key[t];
+            int r = 0;
+            for (int u = 0; u < T; ++u) r += (first[u] && key[u] < x) ? 1 : 0;
+            if (pos) pos[t] = r;
+            if (first[t]) {
+                out[r] = x;
+                ++mine;
+            }
+        }
+        fsai_sync<TPR>();
+        return xi_sum_i<TPR>(mine, red, lane);
+    }
+    int np = 64;
+    while (np < T) np <<= 1;
+    for (int t = T + lane; t < np; t += TPR) key[t] = INT_MAX;
     fsai_sync<TPR>();
-    int mine = 0;
-    for (int t = lane; t < T; t += TPR) {
-        const int x = in[t];
-        int r = 0;
-        for (int u = 0; u < T; ++u) r += (first[u] && in[u] < x) ? 1 : 0;
-        pos[t] = r;
-        if (first[t]) {
-            out[r] = x;
-            ++mine;
+    for (int kk = 2; kk <= np; kk <<= 1) {
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int t = lane; t < np; t += TPR) {
+                const int u = t ^ jj;
+                if (u > t) {
+                    const int x = key[t], y = key[u];
+                    const bool up = (t & kk) == 0;
+                    if (up ? (x > y) : (x < y)) {
+                        key[t] = y;
+                        key[u] = x;
+                        if (tag) {
+                            const int g = tag[t];
+                            tag[t] = tag[u];
+                            tag[u] = g;
+                        }
+                    }
+                }
+            }
+            fsai_sync<TPR>();
         }
     }
+    // contiguous segments per lane: count the first entries of each value,
+    // scan, then place them
+    const int seg = (T + TPR - 1) / TPR, t0 = min(T, lane * seg), t1 = min(T, t0 + seg);
+    int c = 0;
+    for (int t = t0; t < t1; ++t) c += (t == 0 || key[t] != key[t - 1]) ? 1 : 0;
+    int U;
+    int run = xi_scan_excl<TPR>(c, red, lane, &U);
+    for (int t = t0; t < t1; ++t) {
+        if (t == 0 || key[t] != key[t - 1]) out[run++] = key[t];
+        if (pos) pos[t] = run - 1;
+    }
     fsai_sync<TPR>();
-    return xi_sum_i<TPR>(mine, red, lane);
+    return U;
 }
 
 // strong C neighbours of row k appended to cand (with source b when hybrid)
-template <int CAP, int TPR>
-__device__ __forceinline__ void xi_append(XiLds<CAP, TPR> &G, const int32_t *rp, const int32_t *ci,
+template <int CAP, int CAPF, int TPR>
+__device__ __forceinline__ void xi_append(XiLds<CAP, CAPF, TPR> &G, const int32_t *rp, const int32_t *ci,
                                           const uint8_t *strong, const int8_t *cf, int k, int b, int lane) {
     for (int f = rp[k] + lane; f < rp[k + 1]; f += TPR) {
         const int c = ci[f];
@@ -858,63 +963,412 @@ __device__ __forceinline__ void xi_append(XiLds<CAP, TPR> &G, const int32_t *rp,
     }
 }
 
+// metadata of entries [eb, eb + me) of row i (set membership tested when
+// U >= 0; values and the neighbours' diagonals loaded when vals)
+template <int CAP, int CAPF, int TPR>
+__device__ __forceinline__ void xi_meta(XiLds<CAP, CAPF, TPR> &G, int i, int eb, int me, const int32_t *rp,
+                                        const int32_t *ci, const double *v, const uint8_t *strong, const int8_t *cf,
+                                        int U, bool vals, int lane) {
+    if (lane < me) {
+        const int e = eb + lane, k = ci[e];
+        int kind = 3, r0 = 0, len = 0;
+        double akk = 0.0;
+        if (k == i) {
+            kind = 0;
+        } else if (strong[e] && cf[k] == kF) {
+            kind = 1;
+            r0 = rp[k];
+            len = rp[k + 1] - r0;
+            if (vals) akk = csr_lookup(rp, ci, v, k, k);
+        } else if (U >= 0 && xi_find(G.S, U, k) >= 0) {
+            kind = 2;
+        }
+        G.mk[lane] = k;
+        G.mkind[lane] = kind;
+        G.mr0[lane] = r0;
+        G.mlen[lane] = len;
+        G.makk[lane] = akk;
+        G.ma[lane] = vals ? v[e] : 0.0;
+    }
+    fsai_sync<TPR>();
+}
+
+// The group of chunk entries [q, qb) whose strong F rows fit CAPF entries
+// end to end: gq/goff list those rows (nk of them, tot entries).  nk == 0
+// with qb < me means entry qb alone is a longer row.
+template <int CAP, int CAPF, int TPR>
+__device__ __forceinline__ int xi_group(XiLds<CAP, CAPF, TPR> &G, int q, int me, int lane, int &nk, int &tot) {
+    int qb = q;
+    nk = 0;
+    tot = 0;
+    while (qb < me) {
+        if (G.mkind[qb] == 1) {
+            const int ln = G.mlen[qb];
+            if (tot + ln > CAPF) break;
+            if (lane == 0) {
+                G.gq[nk] = qb;
+                G.goff[nk] = tot;
+            }
+            ++nk;
+            tot += ln;
+        }
+        ++qb;
+    }
+    if (lane == 0) G.goff[nk] = tot;
+    fsai_sync<TPR>();
+    return qb;
+}
+
+// row of the group holding flattened entry t (the largest j with goff[j] <= t)
+__device__ __forceinline__ int xi_seg(const int *goff, int nk, int t) {
+    int lo = 0, hi = nk - 1;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo + 1) >> 1);
+        if (goff[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double xi_abar(double x, int sd) {
+    const int sx = (x > 0.0) - (x < 0.0);
+    return sx == sd ? 0.0 : x;
+}
+
+// share of one strong F neighbour k whose row is longer than CAPF: its
+// entries are read from global memory in chunks (same operations and order
+// as the grouped path); returns the new diagonal
+template <int CAP, int CAPF, int TPR>
+__device__ double xi_share_long(XiLds<CAP, CAPF, TPR> &G, int i, int k, double a, double akk, bool plus_i, int U,
+                                double diag, const int32_t *rp, const int32_t *ci, const double *v, int lane) {
+    const int f0 = rp[k], f1 = rp[k + 1];
+    const int sd = (akk > 0.0) - (akk < 0.0);
+    double D = 0.0;
+    for (int fb = f0; fb < f1; fb += TPR) {
+        const int f = fb + lane;
+        double term = 0.0;
+        if (f < f1) {
+            const int l = ci[f];
+            if ((plus_i && l == i) || xi_find(G.S, U, l) >= 0) term = xi_abar(v[f], sd);
+        }
+        G.term[lane] = term;
+        fsai_sync<TPR>();
+        const int m = min(TPR, f1 - fb);
+        for (int q = 0; q < m; ++q) D = D + G.term[q];
+        fsai_sync<TPR>();
+    }
+    if (D == 0.0) return diag + a;
+    double dt = 0.0;
+    for (int f = f0 + lane; f < f1; f += TPR) {
+        const int l = ci[f];
+        const double ab = xi_abar(v[f], sd);
+        if (l == i) {
+            if (plus_i) dt = (a * ab) / D;
+        } else {
+            const int p = xi_find(G.S, U, l);
+            if (p >= 0) G.num[p] = G.num[p] + (a * ab) / D;
+        }
+    }
+    dt = xi_sum<TPR>(dt, G.red, lane);
+    fsai_sync<TPR>();
+    return plus_i ? diag + dt : diag;
+}
+
+// Rows with at most MAXT candidates: one thread per row runs the CPU
+// reference's loops directly, with the set and the numerators in private
+// arrays (same operations, same order, so the same bits).
+__device__ __forceinline__ bool xi_depends(const int32_t *rp, const int32_t *ci, const uint8_t *strong, int k, int l) {
+    const int e = find_col(ci, rp[k], rp[k + 1], l);
+    return e >= 0 && strong[e];
+}
+
+template <int MAXT, bool FILL>
+__global__ void __launch_bounds__(256)
+    k_xi_thread(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
+                const uint8_t *__restrict__ strong, const int8_t *__restrict__ cf, const int32_t *__restrict__ bnd,
+                int variant, const int64_t *__restrict__ cmap, int32_t *cnt, const int32_t *__restrict__ prp,
+                int32_t *pci, double *pv, int32_t *flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || cf[i] == kC) return;
+    const int bi = bnd[i];
+    if (bi < 1 || bi > MAXT) return;
+    const int e0 = rp[i], e1 = rp[i + 1];
+    if (e1 - e0 > kXiThreadLen) return;
+    int set[MAXT];
+    int m = 0;
+    auto in_set = [&](int c) {
+        for (int t = 0; t < m; ++t)
+            if (set[t] == c) return true;
+        return false;
+    };
+    for (int e = e0; e < e1; ++e) {
+        const int c = ci[e];
+        if (c != i && strong[e] && cf[c] == kC) set[m++] = c;  // ascending
+    }
+    const int s0 = m;
+    if (variant == kXiExt) {
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k == i || !strong[e] || cf[k] != kF) continue;
+            for (int f = rp[k]; f < rp[k + 1]; ++f) {
+                const int c = ci[f];
+                if (c != k && strong[f] && cf[c] == kC && !in_set(c)) set[m++] = c;
+            }
+        }
+    } else if (variant == kXiHybrid) {
+        int fp[MAXT];
+        int nf = 0;
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k == i || !strong[e] || cf[k] != kF) continue;
+            bool has_c = false, covered = false;
+            for (int f = rp[k]; f < rp[k + 1]; ++f) {
+                const int c = ci[f];
+                if (c == k || !strong[f] || cf[c] != kC) continue;
+                has_c = true;
+                for (int t = 0; t < s0; ++t)
+                    if (set[t] == c) covered = true;
+            }
+            if (has_c && !covered) fp[nf++] = k;  // nf <= bound <= MAXT
+        }
+        while (nf > 0) {
+            int best = -1, bestdeg = 0;
+            for (int a = 0; a < nf; ++a) {
+                const int k = fp[a];
+                for (int f = rp[k]; f < rp[k + 1]; ++f) {
+                    const int c = ci[f];
+                    if (c == k || !strong[f] || cf[c] != kC) continue;
+                    int deg = 0;
+                    for (int b = 0; b < nf; ++b) deg += xi_depends(rp, ci, strong, fp[b], c) ? 1 : 0;
+                    if (deg > bestdeg || (deg == bestdeg && c < best)) {
+                        best = c;
+                        bestdeg = deg;
+                    }
+                }
+            }
+            set[m++] = best;
+            int keep = 0;
+            for (int a = 0; a < nf; ++a)
+                if (!xi_depends(rp, ci, strong, fp[a], best)) fp[keep++] = fp[a];
+            nf = keep;
+        }
+    }
+    // ascending order (insertion sort)
+    for (int t = 1; t < m; ++t) {
+        const int x = set[t];
+        int u = t - 1;
+        while (u >= 0 && set[u] > x) {
+            set[u + 1] = set[u];
+            --u;
+        }
+        set[u + 1] = x;
+    }
+    if constexpr (!FILL) {
+        cnt[i] = m;
+        return;
+    } else {
+        const int o = prp[i];
+        if (prp[i + 1] - o != m) {
+            atomicOr(&flags[1], 1);
+            return;
+        }
+        auto pos_of = [&](int c) {
+            int lo = 0, hi = m - 1;
+            while (lo <= hi) {
+                const int mid = lo + ((hi - lo) >> 1);
+                if (set[mid] == c) return mid;
+                if (set[mid] < c) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            return -1;
+        };
+        const bool plus_i = variant != kXiClassical;
+        double num[MAXT];
+        for (int t = 0; t < m; ++t) num[t] = 0.0;
+        double diag = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int c = ci[e];
+            if (c == i) diag = v[e];
+            else {
+                const int p = pos_of(c);
+                if (p >= 0) num[p] = v[e];
+            }
+        }
+        for (int e = e0; e < e1; ++e) {
+            const int k = ci[e];
+            if (k == i) continue;
+            const double a = v[e];
+            if (strong[e] && cf[k] == kF) {
+                const int f0 = rp[k], f1 = rp[k + 1];
+                const double akk = csr_lookup(rp, ci, v, k, k);
+                const int sd = (akk > 0.0) - (akk < 0.0);
+                double D = 0.0;
+                for (int f = f0; f < f1; ++f) {
+                    const int l = ci[f];
+                    if ((plus_i && l == i) || pos_of(l) >= 0) D = D + xi_abar(v[f], sd);
+                }
+                if (D == 0.0) {
+                    diag = diag + a;
+                    continue;
+                }
+                for (int f = f0; f < f1; ++f) {
+                    const int l = ci[f];
+                    const double ab = xi_abar(v[f], sd);
+                    if (l == i) {
+                        if (plus_i) diag = diag + (a * ab) / D;
+                    } else {
+                        const int p = pos_of(l);
+                        if (p >= 0) num[p] = num[p] + (a * ab) / D;
+                    }
+                }
+            } else if (pos_of(k) < 0) {
+                diag = diag + a;  // weak neighbour outside the set
+            }
+        }
+        for (int t = 0; t < m; ++t) {
+            pci[o + t] = (int32_t)cmap[set[t]];
+            pv[o + t] = -num[t] / diag;
+        }
+    }
+}
+
 // flags[0]: candidate list longer than the row group's capacity;
 // flags[1]: the fill pass found another set size than the count pass
-template <int CAP, int WPB, int TPR, bool FILL>
+template <int CAP, int CAPF, int WPB, int TPR, bool FILL>
 __global__ void __launch_bounds__(WPB * TPR)
     k_xi_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
               const uint8_t *__restrict__ strong, const int8_t *__restrict__ cf, const int32_t *__restrict__ bnd,
               int lo, int hi, int variant, const int64_t *__restrict__ cmap, int32_t *cnt,
               const int32_t *__restrict__ prp, int32_t *pci, double *pv, int32_t *flags) {
     static_assert(TPR == 64 || WPB == 1, "one row per workgroup when a row has more than one wavefront");
-    __shared__ XiLds<CAP, TPR> Ls[WPB];
+    __shared__ XiLds<CAP, CAPF, TPR> Ls[WPB];
     const int w = threadIdx.x / TPR, lane = threadIdx.x % TPR;
     const int i = blockIdx.x * WPB + w;
     if (i >= n || cf[i] == kC) return;  // uniform over the row group
     const int bi = bnd[i];
     if (bi < lo || bi > hi) return;
-    XiLds<CAP, TPR> &G = Ls[w];
     const int e0 = rp[i], e1 = rp[i + 1];
-    // C_i^S, and for extended+i the strong C neighbours of the strong F neighbours
+    if (bi <= kXiCapThread && e1 - e0 <= kXiThreadLen) return;  // one thread per row (k_xi_thread)
+    XiLds<CAP, CAPF, TPR> &G = Ls[w];
+    // C_i^S, and for extended+i the strong C neighbours of the strong F
+    // neighbours (their rows loaded end to end, a group at a time)
     if (lane == 0) G.cnt = 0;
     fsai_sync<TPR>();
-    xi_append<CAP, TPR>(G, rp, ci, strong, cf, i, 0, lane);
-    if (variant == kXiExt)
-        for (int e = e0; e < e1; ++e) {
-            const int k = ci[e];
-            if (k != i && strong[e] && cf[k] == kF) xi_append<CAP, TPR>(G, rp, ci, strong, cf, k, 0, lane);
+    xi_append<CAP, CAPF, TPR>(G, rp, ci, strong, cf, i, 0, lane);
+    if (variant == kXiExt) {
+        for (int eb = e0; eb < e1; eb += TPR) {
+            const int me = min(TPR, e1 - eb);
+            xi_meta<CAP, CAPF, TPR>(G, i, eb, me, rp, ci, v, strong, cf, -1, false, lane);
+            for (int q = 0; q < me;) {
+                int nk, tot;
+                const int qb = xi_group<CAP, CAPF, TPR>(G, q, me, lane, nk, tot);
+                if (nk == 0) {
+                    if (qb < me) xi_append<CAP, CAPF, TPR>(G, rp, ci, strong, cf, G.mk[qb], 0, lane);
+                    q = qb + 1;
+                    fsai_sync<TPR>();
+                    continue;
+                }
+                for (int t = lane; t < tot; t += TPR) {
+                    const int j = xi_seg(G.goff, nk, t), qq = G.gq[j];
+                    const int f = G.mr0[qq] + (t - G.goff[j]), k = G.mk[qq];
+                    const int c = ci[f];
+                    if (c != k && strong[f] && cf[c] == kC) {
+                        const int s2 = atomicAdd(&G.cnt, 1);
+                        if (s2 < CAP) G.cand[s2] = c;
+                    }
+                }
+                fsai_sync<TPR>();
+                q = qb;
+            }
         }
+    }
     fsai_sync<TPR>();
     const int T = G.cnt;
     if (T > CAP) {
         if (lane == 0) atomicOr(&flags[0], 1);
         return;
     }
-    int U = xi_sort_unique<TPR>(G.cand, T, G.S, G.pos, G.aux, G.redi, lane);
+    int U = xi_sort_unique<TPR>(G.cand, nullptr, T, G.S, nullptr, G.aux, G.redi, lane);
     if (variant == kXiHybrid) {
         // Alg. extintset: F' = strong F neighbours with a strong C neighbour
-        // but none in C_i^S; candidates = their strong C neighbours
+        // but none in C_i^S (numbered in CSR order); candidates = their
+        // strong C neighbours, tagged with the F' point they cover
         const int s0 = U;
         int nf = 0;
         if (lane == 0) G.cnt = 0;
         fsai_sync<TPR>();
-        for (int e = e0; e < e1; ++e) {
-            const int k = ci[e];
-            if (k == i || !strong[e] || cf[k] != kF) continue;
-            int hasc = 0, cov = 0;
-            for (int f = rp[k] + lane; f < rp[k + 1]; f += TPR) {
-                const int c = ci[f];
-                if (c != k && strong[f] && cf[c] == kC) {
-                    hasc = 1;
-                    if (xi_find(G.S, s0, c) >= 0) cov = 1;
+        for (int eb = e0; eb < e1; eb += TPR) {
+            const int me = min(TPR, e1 - eb);
+            xi_meta<CAP, CAPF, TPR>(G, i, eb, me, rp, ci, v, strong, cf, -1, false, lane);
+            for (int q = 0; q < me;) {
+                int nk, tot;
+                const int qb = xi_group<CAP, CAPF, TPR>(G, q, me, lane, nk, tot);
+                if (nk == 0) {
+                    if (qb < me) {  // one long row
+                        const int k = G.mk[qb];
+                        int hasc = 0, cov = 0;
+                        for (int f = rp[k] + lane; f < rp[k + 1]; f += TPR) {
+                            const int c = ci[f];
+                            if (c != k && strong[f] && cf[c] == kC) {
+                                hasc = 1;
+                                if (xi_find(G.S, s0, c) >= 0) cov = 1;
+                            }
+                        }
+                        hasc = xi_sum_i<TPR>(hasc, G.redi, lane);
+                        cov = xi_sum_i<TPR>(cov, G.redi, lane);
+                        if (hasc != 0 && cov == 0) {
+                            xi_append<CAP, CAPF, TPR>(G, rp, ci, strong, cf, k, nf, lane);
+                            if (lane == 0 && nf < CAP) G.rem[nf] = 1;
+                            ++nf;
+                        }
+                    }
+                    q = qb + 1;
+                    fsai_sync<TPR>();
+                    continue;
                 }
+                for (int j = lane; j < nk; j += TPR) {
+                    G.hasc[j] = 0;
+                    G.cov[j] = 0;
+                }
+                fsai_sync<TPR>();
+                for (int t = lane; t < tot; t += TPR) {
+                    const int j = xi_seg(G.goff, nk, t), qq = G.gq[j];
+                    const int f = G.mr0[qq] + (t - G.goff[j]), k = G.mk[qq];
+                    const int c = ci[f];
+                    if (c != k && strong[f] && cf[c] == kC) {
+                        G.hasc[j] = 1;
+                        if (xi_find(G.S, s0, c) >= 0) G.cov[j] = 1;
+                    }
+                }
+                fsai_sync<TPR>();
+                for (int j = 0; j < nk; ++j) {  // uniform: every lane numbers F' alike
+                    int b = -1;
+                    if (G.hasc[j] && !G.cov[j]) {
+                        b = nf;
+                        if (lane == 0 && nf < CAP) G.rem[nf] = 1;
+                        ++nf;
+                    }
+                    if (lane == 0) G.gb[j] = b;
+                }
+                fsai_sync<TPR>();
+                for (int t = lane; t < tot; t += TPR) {
+                    const int j = xi_seg(G.goff, nk, t);
+                    const int b = G.gb[j];
+                    if (b < 0) continue;
+                    const int qq = G.gq[j];
+                    const int f = G.mr0[qq] + (t - G.goff[j]), k = G.mk[qq];
+                    const int c = ci[f];
+                    if (c != k && strong[f] && cf[c] == kC) {
+                        const int s2 = atomicAdd(&G.cnt, 1);
+                        if (s2 < CAP) {
+                            G.cand[s2] = c;
+                            G.src[s2] = b;
+                        }
+                    }
+                }
+                fsai_sync<TPR>();
+                q = qb;
             }
-            hasc = xi_sum_i<TPR>(hasc, G.redi, lane);
-            cov = xi_sum_i<TPR>(cov, G.redi, lane);
-            if (hasc == 0 || cov != 0) continue;
-            xi_append<CAP, TPR>(G, rp, ci, strong, cf, k, nf, lane);
-            if (lane == 0 && nf < CAP) G.rem[nf] = 1;
-            ++nf;
         }
         fsai_sync<TPR>();
         const int T2 = G.cnt;
@@ -923,7 +1377,7 @@ __global__ void __launch_bounds__(WPB * TPR)
             return;
         }
         if (nf > 0) {
-            const int U2 = xi_sort_unique<TPR>(G.cand, T2, G.Q, G.pos, G.aux, G.redi, lane);
+            const int U2 = xi_sort_unique<TPR>(G.cand, G.src, T2, G.Q, G.pos, G.aux, G.redi, lane);
             int np = 0;
             for (;;) {
                 // degree of each candidate over the points of F' still uncovered
@@ -952,9 +1406,9 @@ __global__ void __launch_bounds__(WPB * TPR)
             }
             U = s0 + np;
             fsai_sync<TPR>();
-            xi_sort_unique<TPR>(G.S, U, G.cand, G.pos, G.aux, G.redi, lane);
-            for (int u = lane; u < U; u += TPR) G.S[u] = G.cand[u];
+            for (int u = lane; u < U; u += TPR) G.cand[u] = G.S[u];
             fsai_sync<TPR>();
+            xi_sort_unique<TPR>(G.cand, nullptr, U, G.S, nullptr, G.aux, G.redi, lane);
         }
     }
     if constexpr (!FILL) {
@@ -980,58 +1434,144 @@ __global__ void __launch_bounds__(WPB * TPR)
         }
         fsai_sync<TPR>();
         double diag = G.diag;
-        for (int e = e0; e < e1; ++e) {
-            const int k = ci[e];
-            if (k == i) continue;
-            const double a = v[e];
-            if (strong[e] && cf[k] == kF) {
-                // share of k, spread over the set (and i itself unless classical)
-                const int f0 = rp[k], f1 = rp[k + 1];
-                const double akk = csr_lookup(rp, ci, v, k, k);
-                const int sd = (akk > 0.0) - (akk < 0.0);
-                // denominator: the terms of row k are formed in parallel and
-                // added in CSR (= ascending column) order, the CPU
-                // reference's order over the set (terms outside the set are
-                // +0.0 and change nothing)
-                double D = 0.0;
-                for (int fb = f0; fb < f1; fb += TPR) {
-                    const int f = fb + lane;
-                    double term = 0.0;
-                    if (f < f1) {
-                        const int l = ci[f];
-                        const double x = v[f];
-                        const int sx = (x > 0.0) - (x < 0.0);
-                        const double ab = sx == sd ? 0.0 : x;
-                        if ((plus_i && l == i) || xi_find(G.S, U, l) >= 0) term = ab;
+        // row i in CSR order: weak neighbours outside the set go to the
+        // diagonal; each strong F neighbour k spreads a_ik over the set (and
+        // i itself unless classical) in proportion to the sign-filtered
+        // entries of its row, whose denominator is added in ascending column
+        // order -- the CPU reference's operations in its order.  The rows of
+        // a group of neighbours are loaded together; the sums run in LDS.
+        for (int eb = e0; eb < e1; eb += TPR) {
+            const int me = min(TPR, e1 - eb);
+            xi_meta<CAP, CAPF, TPR>(G, i, eb, me, rp, ci, v, strong, cf, U, true, lane);
+            for (int q = 0; q < me;) {
+                int nk, tot;
+                const int qb = xi_group<CAP, CAPF, TPR>(G, q, me, lane, nk, tot);
+                // four entries per lane at a time: their row lookups, loads
+                // and set searches run in lockstep so the latencies overlap
+                {
+                    int sstep = 1, gstep = 1;
+                    while (sstep * 2 <= U) sstep *= 2;
+                    while (gstep * 2 <= nk) gstep *= 2;
+                    for (int t0 = lane; t0 < tot; t0 += 4 * TPR) {
+                        int tt[4], f[4], l[4], jr[4], lo[4];
+                        double x[4], akk[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            tt[r] = t0 + r * TPR;
+                            jr[r] = 0;
+                        }
+                        // row of the group: the largest j with goff[j] <= t
+                        for (int st = gstep; st > 0; st >>= 1) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (jr[r] + st < nk && G.goff[jr[r] + st] <= tt[r]) jr[r] += st;
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const bool ok = tt[r] < tot;
+                            const int qq = G.gq[jr[r]];
+                            f[r] = ok ? G.mr0[qq] + (tt[r] - G.goff[jr[r]]) : G.mr0[qq];
+                            akk[r] = G.makk[qq];
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            l[r] = ci[f[r]];
+                            x[r] = v[f[r]];
+                            lo[r] = 0;
+                        }
+                        // lower bound of l in the set
+                        for (int st = sstep; st > 0; st >>= 1) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (lo[r] + st <= U && G.S[lo[r] + st - 1] < l[r]) lo[r] += st;
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if (tt[r] >= tot) continue;
+                            const int pp = (lo[r] < U && G.S[lo[r]] == l[r]) ? lo[r] : -1;
+                            G.fab[tt[r]] = xi_abar(x[r], (akk[r] > 0.0) - (akk[r] < 0.0));
+                            G.fl[tt[r]] = l[r];
+                            G.fp[tt[r]] = l[r] == i ? -2 : pp;
+                        }
                     }
-                    G.term[lane] = term;
-                    fsai_sync<TPR>();
-                    const int m = min(TPR, f1 - fb);
-                    for (int q = 0; q < m; ++q) D = D + G.term[q];
-                    fsai_sync<TPR>();
                 }
-                if (D == 0.0) {
-                    diag = diag + a;
-                    continue;
-                }
-                double dt = 0.0;
-                for (int f = f0 + lane; f < f1; f += TPR) {
-                    const int l = ci[f];
-                    const double x = v[f];
-                    const int sx = (x > 0.0) - (x < 0.0);
-                    const double ab = sx == sd ? 0.0 : x;
-                    if (l == i) {
-                        if (plus_i) dt = (a * ab) / D;
-                    } else {
-                        const int p = xi_find(G.S, U, l);
-                        if (p >= 0) G.num[p] = G.num[p] + (a * ab) / D;
-                    }
-                }
-                dt = xi_sum<TPR>(dt, G.red, lane);
-                if (plus_i) diag = diag + dt;
                 fsai_sync<TPR>();
-            } else if (xi_find(G.S, U, k) < 0) {
-                diag = diag + a;  // weak neighbour outside the set
+                // denominators of all the group's rows at once, one lane per
+                // row, each added in ascending column order
+                for (int jj = lane; jj < nk; jj += TPR) {
+                    const int off = G.goff[jj], ln = G.goff[jj + 1] - off;
+                    double D = 0.0, ai = 0.0;
+                    int u = 0;
+                    for (; u + 8 <= ln; u += 8) {
+                        int pb[8];
+                        double xb[8];
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) {
+                            pb[r] = G.fp[off + u + r];
+                            xb[r] = G.fab[off + u + r];
+                        }
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) {
+                            if (pb[r] >= 0 || (plus_i && pb[r] == -2)) D = D + xb[r];
+                            if (pb[r] == -2) ai = xb[r];
+                        }
+                    }
+                    for (; u < ln; ++u) {
+                        const int pu = G.fp[off + u];
+                        if (pu >= 0 || (plus_i && pu == -2)) D = D + G.fab[off + u];
+                        if (pu == -2) ai = G.fab[off + u];
+                    }
+                    G.gD[jj] = D;
+                    G.gai[jj] = ai;
+                }
+                fsai_sync<TPR>();
+                // each set entry adds the shares of the group's rows in CSR
+                // order of row i (its column found in each row's sorted
+                // columns); rows whose denominator is 0 give none
+                for (int pp = lane; pp < U; pp += TPR) {
+                    const int col = G.S[pp];
+                    double acc = G.num[pp];
+                    for (int jj = 0; jj < nk; ++jj) {
+                        const double D = G.gD[jj];
+                        if (D == 0.0) continue;
+                        const int off = G.goff[jj];
+                        int lo2 = off, hi2 = G.goff[jj + 1] - 1;
+                        while (lo2 <= hi2) {
+                            const int mid = lo2 + ((hi2 - lo2) >> 1);
+                            const int c2 = G.fl[mid];
+                            if (c2 == col) {
+                                acc = acc + (G.ma[G.gq[jj]] * G.fab[mid]) / D;
+                                break;
+                            }
+                            if (c2 < col) lo2 = mid + 1;
+                            else hi2 = mid - 1;
+                        }
+                    }
+                    G.num[pp] = acc;
+                }
+                // the diagonal, in CSR order of row i (every lane alike)
+                int j = 0;
+                for (int t = q; t < qb; ++t) {
+                    const int kind = G.mkind[t];
+                    const double a = G.ma[t];
+                    if (kind == 3) {
+                        diag = diag + a;  // weak neighbour outside the set
+                    } else if (kind == 1) {
+                        const double D = G.gD[j];
+                        if (D == 0.0) diag = diag + a;
+                        else if (plus_i) diag = diag + (a * G.gai[j]) / D;
+                        ++j;
+                    }
+                }
+                fsai_sync<TPR>();
+                if (nk == 0 && qb < me) {  // one row longer than CAPF
+                    diag = xi_share_long<CAP, CAPF, TPR>(G, i, G.mk[qb], G.ma[qb], G.makk[qb], plus_i, U, diag, rp,
+                                                         ci, v, lane);
+                    q = qb + 1;
+                } else {
+                    q = qb;
+                }
+                fsai_sync<TPR>();
             }
         }
         fsai_sync<TPR>();
@@ -1261,36 +1801,48 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     HIPC(hipGetLastError());
 }
 
-int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, Pool &tmp,
-              hipStream_t s) {
+int xi_bounds(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, int32_t *bnd, int *bmax_wave,
+              Pool &tmp, hipStream_t s) {
     int32_t *cs = tmp.alloc<int32_t>(n);
-    unsigned long long *d = tmp.alloc<unsigned long long>(1);
-    HIPC(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
+    unsigned long long *d = tmp.alloc<unsigned long long>(2);
+    HIPC(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), s));
     k_xi_cs<<<nblocks(n), kBlock, 0, s>>>(n, A.rp, A.ci, strong, cf, cs);
     k_xi_bound<<<nblocks(n), kBlock, 0, s>>>(n, A.rp, A.ci, strong, cf, cs, variant, bnd, d);
     HIPC(hipGetLastError());
-    unsigned long long h = 0;
-    HIPC(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+    unsigned long long h[2] = {0, 0};
+    HIPC(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    return h > (unsigned long long)INT32_MAX ? INT32_MAX : (int)h;
+    auto clamp = [](unsigned long long x) { return x > (unsigned long long)INT32_MAX ? INT32_MAX : (int)x; };
+    *bmax_wave = clamp(h[1]);
+    return clamp(h[0]);
 }
 
 template <bool FILL>
 static void xi_launch(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd,
                       int bmax, const int64_t *cmap, int32_t *cnt, const int32_t *prp, int32_t *pci, double *pv,
                       int32_t *flags, hipStream_t s) {
+    // bmax: largest bound of the rows the row-group kernels take (-1: none
+    // but those of the thread kernel)
     k_xi_simple<FILL><<<nblocks(n), kBlock, 0, s>>>(n, cf, bnd, cmap, cnt, prp, pci, pv);
+    k_xi_thread<kXiCapThread, FILL><<<nblocks(n), kBlock, 0, s>>>(n, A.rp, A.ci, A.v, strong, cf, bnd, variant,
+                                                                      cmap, cnt, prp, pci, pv, flags);
     if (bmax >= 1)
-        k_xi_rows<kXiCapWave, 4, 64, FILL><<<(n + 3) / 4, 256, 0, s>>>(
-            n, A.rp, A.ci, A.v, strong, cf, bnd, 1, kXiCapWave, variant, cmap, cnt, prp, pci, pv, flags);
-    if (bmax > kXiCapWave)
-        k_xi_rows<kXiCapGroup, 1, 256, FILL><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, strong, cf, bnd, kXiCapWave + 1,
-                                                                kXiCapGroup, variant, cmap, cnt, prp, pci, pv, flags);
+        k_xi_rows<kXiCapSmall, 3 * kXiCapSmall / 2, 4, 64, FILL><<<(n + 3) / 4, 256, 0, s>>>(
+            n, A.rp, A.ci, A.v, strong, cf, bnd, 1, kXiCapSmall, variant, cmap, cnt, prp, pci, pv, flags);
+    if (bmax > kXiCapSmall)
+        k_xi_rows<kXiCapMid, 3 * kXiCapMid / 2, 1, 256, FILL><<<n, 256, 0, s>>>(
+            n, A.rp, A.ci, A.v, strong, cf, bnd, kXiCapSmall + 1, kXiCapMid, variant, cmap, cnt, prp, pci, pv,
+            flags);
+    if (bmax > kXiCapMid)
+        k_xi_rows<kXiCapGroup, 3 * kXiCapGroup / 2, 1, 256, FILL><<<n, 256, 0, s>>>(
+            n, A.rp, A.ci, A.v, strong, cf, bnd, kXiCapMid + 1, kXiCapGroup, variant, cmap, cnt, prp, pci, pv,
+            flags);
     HIPC(hipGetLastError());
 }
 
 void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
               int32_t *cnt, int32_t *flags, hipStream_t s) {
+    // bmax: largest bound over the rows the row-group kernels take
     if (bmax > kXiCapGroup) fail(CAMG_E_ARG, "interpolation: a row has more than 2048 candidate coarse points");
     xi_launch<false>(n, A, strong, cf, variant, bnd, bmax, nullptr, cnt, nullptr, nullptr, nullptr, flags, s);
 }
