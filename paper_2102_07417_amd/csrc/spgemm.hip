@@ -83,14 +83,23 @@ __global__ void k_offset_rp(int m, const int32_t *rp, int64_t base, int32_t *out
 // bin b holds rows with value <= lim[b] (and > lim[b-1]); the last bin is
 // open.  Slots are taken per block: LDS counters first, then one global
 // atomic per block and bin.
+// Rows with at most kThrX entries of X and kThrP products are formed by one
+// thread each (k_sym_thread / k_fill_thread) and left out of the bins.
+constexpr int kThrX = 16;
+constexpr int64_t kThrP = 256;
+
+__device__ __forceinline__ bool thread_row(const CsrView &X, const int64_t *prod, int i) {
+    return X.rp[i + 1] - X.rp[i] <= kThrX && prod[i] <= kThrP;
+}
+
 __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int nb, const int64_t *lim, int32_t *bcnt,
-                           int32_t *brows, int stride) {
+                           int32_t *brows, int stride, CsrView X, const int64_t *prod) {
     __shared__ int lcnt[8], lbase[8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (threadIdx.x < 8) lcnt[threadIdx.x] = 0;
     __syncthreads();
     int b = -1, off = 0;
-    if (i < nr) {
+    if (i < nr && !thread_row(X, prod, i)) {
         const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
         b = 0;
         while (b < nb - 1 && x > lim[b]) ++b;
@@ -100,6 +109,47 @@ __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int n
     if (threadIdx.x < nb) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&bcnt[threadIdx.x], lcnt[threadIdx.x]) : 0;
     __syncthreads();
     if (b >= 0) brows[(int64_t)b * stride + lbase[b] + off] = i;
+}
+
+// One thread per short row: a merge of the rows of Y named by the row of X,
+// by column.  For each output column the contributing rows are visited in
+// ascending order of X's entries and their products added one at a time
+// from 0.0 -- the order of the wavefront kernels.
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_thread_rows(int nr, CsrView X, CsrView Y, const int64_t *prod, int32_t *cnt,
+                                                     const int32_t *zrp, int32_t *zci, double *zv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr || !thread_row(X, prod, i)) return;
+    const int e0 = X.rp[i], m = X.rp[i + 1] - e0;
+    int pos[kThrX], end[kThrX], head[kThrX];
+    double xv[kThrX];
+    for (int q = 0; q < m; ++q) {
+        const int k = X.ci[e0 + q];
+        pos[q] = Y.rp[k];
+        end[q] = Y.rp[k + 1];
+        head[q] = pos[q] < end[q] ? Y.ci[pos[q]] : INT_MAX;
+        xv[q] = X.v[e0 + q];
+    }
+    const int o = FILL ? zrp[i] : 0;
+    int c = 0;
+    for (;;) {
+        int j = INT_MAX;
+        for (int q = 0; q < m; ++q) j = head[q] < j ? head[q] : j;
+        if (j == INT_MAX) break;
+        double acc = 0.0;
+        for (int q = 0; q < m; ++q) {
+            if (head[q] != j) continue;
+            if (FILL) acc = acc + xv[q] * Y.v[pos[q]];
+            ++pos[q];
+            head[q] = pos[q] < end[q] ? Y.ci[pos[q]] : INT_MAX;
+        }
+        if (FILL) {
+            zci[o + c] = j;
+            zv[o + c] = acc;
+        }
+        ++c;
+    }
+    if (!FILL) cnt[i] = c;
 }
 
 // Visit the products of row i of X Y in ascending order of X's entries e:
@@ -372,7 +422,8 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     HIPC(hipMemcpyAsync(lim, sym_lim_h, sizeof(sym_lim_h), hipMemcpyHostToDevice, s));
     HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
     HIPC(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
-    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr);
+    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr, xv, prod);
+    k_thread_rows<false><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, cnt, nullptr, nullptr, nullptr);
     HIPC(hipGetLastError());
     int32_t hb[NB];
     HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
@@ -436,7 +487,8 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     const int64_t fill_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
     HIPC(hipMemcpyAsync(lim, fill_lim_h, sizeof(fill_lim_h), hipMemcpyHostToDevice, s));
     HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
-    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, lim, bcnt, brows, nr);
+    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, lim, bcnt, brows, nr, xv, prod);
+    k_thread_rows<true><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, nullptr, Z.rp, Z.ci, Z.v);
     HIPC(hipGetLastError());
     HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
