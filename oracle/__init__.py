@@ -20,14 +20,15 @@ OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -
 F, U, CPT = -1, 0, 1
 X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS, X_G = range(11)
 SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
-INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID = 0, 1, 2, 3
+INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 
 
 class Params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32),
                 ("nu_post", C.c_int32), ("omega", C.c_double), ("max_levels", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
-                ("interp", C.c_int32)]
+                ("interp", C.c_int32), ("bamg_lmin", C.c_int32), ("bamg_lmax", C.c_int32),
+                ("bamg_eps", C.c_double), ("bamg_mu", C.c_double)]
 
 
 class CsrOut(C.Structure):
@@ -52,6 +53,9 @@ def lib():
         L.orc_pmis.argtypes = [i32, vp, vp, vp, vp, u64, i32, vp, vp]
         L.orc_interp_direct.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(CsrOut)]
         L.orc_interp.argtypes = [i32, vp, vp, vp, vp, vp, i32, C.POINTER(CsrOut)]
+        L.orc_orthonormalize.argtypes = [i32, i32, vp]
+        L.orc_bamg.argtypes = [i32, vp, vp, vp, vp, i32, vp, i32, i32, dbl, dbl, C.POINTER(CsrOut)]
+        L.orc_setup_tv.argtypes = [i32, vp, vp, vp, i32, vp, C.POINTER(Params), C.POINTER(vp)]
         L.orc_transpose.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_spgemm.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_cholesky.argtypes = [i32, vp]
@@ -171,6 +175,29 @@ def interp(A, strong, cf, variant):
     return _from_out(o)
 
 
+def orthonormalize(V):
+    """Orthonormal basis of the test space V (n x nt), as the BAMG set-up forms it."""
+    V = np.array(V, dtype=np.float64, order="C", copy=True)
+    n, nt = V.shape
+    st = lib().orc_orthonormalize(n, nt, _p(V))
+    if st != OK:
+        raise OracleError(st)
+    return V
+
+
+def bamg(A, strong, cf, V, lmin=1, lmax=2, eps=1e-3, mu=10.0):
+    """BAMG prolongation for test space V (n x nt, used as given) and a C/F split."""
+    n, _, rp, ci, v = _csr_arrays(A)
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    strong = np.ascontiguousarray(strong, np.uint8); cf = np.ascontiguousarray(cf, np.int8)
+    V = np.ascontiguousarray(V, np.float64)
+    o = CsrOut()
+    st = lib().orc_bamg(n, _p(rp), _p(ci), _p(strong), _p(cf), V.shape[1], _p(V), lmin, lmax, eps, mu, C.byref(o))
+    if st != OK:
+        raise OracleError(st)
+    return _from_out(o)
+
+
 def transpose(X):
     o, keep = _to_out(*_csr_arrays(X))
     r = CsrOut()
@@ -235,15 +262,20 @@ def fsai_omega(A, G) -> float:
 class Hierarchy:
     """Oracle AMG hierarchy (setup) plus V-cycle and PCG."""
 
-    def __init__(self, A, **kw):
+    def __init__(self, A, V=None, **kw):
         n, _, rp, ci, v = _csr_arrays(A)
         self._keep = (np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
                       np.ascontiguousarray(v, np.float64))
         self.n = n
         self.params = params(**kw)
         h = C.c_void_p()
-        st = lib().orc_setup(n, _p(self._keep[0]), _p(self._keep[1]), _p(self._keep[2]),
-                             C.byref(self.params), C.byref(h))
+        if V is None:
+            st = lib().orc_setup(n, _p(self._keep[0]), _p(self._keep[1]), _p(self._keep[2]),
+                                 C.byref(self.params), C.byref(h))
+        else:
+            Vc = np.ascontiguousarray(V, np.float64)
+            st = lib().orc_setup_tv(n, _p(self._keep[0]), _p(self._keep[1]), _p(self._keep[2]), Vc.shape[1],
+                                    _p(Vc), C.byref(self.params), C.byref(h))
         self.status = st
         self.h = h if st == OK else None
         if st != OK:

@@ -37,6 +37,10 @@ void orc_params_default(orc_params *p) {
     p->max_iter = 1000;
     p->smoother = ORC_SMOOTH_JACOBI;
     p->interp = ORC_INTERP_DIRECT;
+    p->bamg_lmin = 1;
+    p->bamg_lmax = 2;
+    p->bamg_eps = 1e-3;
+    p->bamg_mu = 10.0;
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -455,6 +459,214 @@ nomem:
     return ORC_E_NOMEM;
 }
 
+/*
+ * BAMG prolongation (Section 2, Interpolation, eq. minBAMG and Alg. BAMG)
+ * for a given test space V (n x nt, row k = phi_k).
+ *
+ * Orthonormal basis of the test space: Cholesky-QR, G = V^T V (each entry
+ * summed over rows in index order), G = L L^T, V <- V L^{-T} row by row.
+ * A pivot at or below 1e-12 of the largest diagonal entry of G (a column
+ * whose independent part is below 1e-6 of the largest column) is an error.
+ */
+int orc_orthonormalize(int32_t n, int32_t nt, double *V) {
+    if (nt < 1 || nt > ORC_MAXNT) return ORC_E_ARG;
+    double G[ORC_MAXNT * ORC_MAXNT];
+    for (int32_t a = 0; a < nt; ++a)
+        for (int32_t b = 0; b <= a; ++b) {
+            double s = 0.0;
+            for (int32_t r = 0; r < n; ++r) s = s + V[(size_t)r * nt + a] * V[(size_t)r * nt + b];
+            G[a * nt + b] = s;
+        }
+    double gmax = 0.0;
+    for (int32_t a = 0; a < nt; ++a) gmax = G[a * nt + a] > gmax ? G[a * nt + a] : gmax;
+    /* G = L L^T (lower triangle, column by column) */
+    for (int32_t j = 0; j < nt; ++j) {
+        double d = G[j * nt + j];
+        for (int32_t k = 0; k < j; ++k) d = d - G[j * nt + k] * G[j * nt + k];
+        if (!(d > 1e-12 * gmax)) return ORC_E_ARG;  /* independent part below 1e-6 of the largest column */
+        double ljj = sqrt(d);
+        G[j * nt + j] = ljj;
+        for (int32_t i = j + 1; i < nt; ++i) {
+            double t = G[i * nt + j];
+            for (int32_t k = 0; k < j; ++k) t = t - G[i * nt + k] * G[j * nt + k];
+            G[i * nt + j] = t / ljj;
+        }
+    }
+    /* each row x of V becomes the solution y of L y = x */
+    for (int32_t r = 0; r < n; ++r) {
+        double *x = V + (size_t)r * nt;
+        for (int32_t a = 0; a < nt; ++a) {
+            double t = x[a];
+            for (int32_t k = 0; k < a; ++k) t = t - G[a * nt + k] * x[k];
+            x[a] = t / G[a * nt + a];
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * Interpolatory candidates of F point i at distance l: the C points reached
+ * from i by at most l steps along strong connections (k -> j for j in S_k),
+ * ascending.  mark (n entries, -1 outside a call) flags visited points,
+ * dist their distance; front lists them.
+ */
+static int32_t bamg_candidates(const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
+                               int32_t i, int32_t l, int32_t *mark, int32_t *dist, int32_t *front, int32_t *cand) {
+    int32_t nf = 1, nc = 0, head = 0;
+    front[0] = i;
+    mark[i] = i;
+    dist[i] = 0;
+    while (head < nf) {
+        int32_t k = front[head++];
+        if (dist[k] == l) continue;
+        for (int32_t e = rp[k]; e < rp[k + 1]; ++e) {
+            int32_t j = ci[e];
+            if (j == k || !strong[e] || mark[j] == i) continue;
+            mark[j] = i;
+            dist[j] = dist[k] + 1;
+            front[nf++] = j;
+            if (cf[j] == ORC_C) cand[nc++] = j;
+        }
+    }
+    for (int32_t t = 0; t < nf; ++t) mark[front[t]] = -1;
+    qsort(cand, (size_t)nc, sizeof(int32_t), cmp_i32);
+    return nc;
+}
+
+/*
+ * Weights of row i over the candidates cand[0..nc) (eq. minBAMG): a basis of
+ * the candidates' test-space rows is chosen greedily (maxvol by pivoted
+ * modified Gram-Schmidt: at each step the candidate whose residual row has
+ * the largest norm, the smallest index on ties, until nt are chosen or the
+ * largest residual is below 1e-10 of the largest row norm), phi_i is
+ * projected on the orthonormal q's (c_m = q_m . res, res -= c_m q_m), and
+ * R w = c is solved (R from the pivoted Gram-Schmidt).  Outputs the chosen
+ * candidates sel[0..r) (in choice order), w, the relative residual and
+ * ||w||.
+ */
+static int32_t bamg_weights(int32_t nt, const double *V, int32_t i, const int32_t *cand, int32_t nc, double *work,
+                            double *coef, int32_t *sel, double *w, double *relres, double *wnorm) {
+    double q[ORC_MAXNT][ORC_MAXNT], R[ORC_MAXNT][ORC_MAXNT], c[ORC_MAXNT], res[ORC_MAXNT];
+    uint8_t used[ORC_MAXCAND];
+    double n0 = 0.0;
+    for (int32_t t = 0; t < nc; ++t) {
+        used[t] = 0;
+        double s = 0.0;
+        for (int32_t a = 0; a < nt; ++a) {
+            work[t * nt + a] = V[(size_t)cand[t] * nt + a];
+            s = s + work[t * nt + a] * work[t * nt + a];
+        }
+        n0 = s > n0 ? s : n0;
+    }
+    int32_t r = 0;
+    while (r < nt) {
+        int32_t best = -1;
+        double bn = 0.0;
+        for (int32_t t = 0; t < nc; ++t) {
+            if (used[t]) continue;
+            double s = 0.0;
+            for (int32_t a = 0; a < nt; ++a) s = s + work[t * nt + a] * work[t * nt + a];
+            if (s > bn) { bn = s; best = t; }
+        }
+        if (best < 0 || !(bn > 1e-20 * n0)) break;
+        double nb = sqrt(bn);
+        for (int32_t a = 0; a < nt; ++a) q[r][a] = work[best * nt + a] / nb;
+        for (int32_t m = 0; m < r; ++m) R[m][r] = coef[best * nt + m];
+        R[r][r] = nb;
+        used[best] = 1;
+        sel[r] = best;
+        for (int32_t t = 0; t < nc; ++t) {
+            if (used[t]) continue;
+            double d = 0.0;
+            for (int32_t a = 0; a < nt; ++a) d = d + q[r][a] * work[t * nt + a];
+            coef[t * nt + r] = d;
+            for (int32_t a = 0; a < nt; ++a) work[t * nt + a] = work[t * nt + a] - d * q[r][a];
+        }
+        ++r;
+    }
+    double ni = 0.0;
+    for (int32_t a = 0; a < nt; ++a) {
+        res[a] = V[(size_t)i * nt + a];
+        ni = ni + res[a] * res[a];
+    }
+    for (int32_t m = 0; m < r; ++m) {
+        double d = 0.0;
+        for (int32_t a = 0; a < nt; ++a) d = d + q[m][a] * res[a];
+        c[m] = d;
+        for (int32_t a = 0; a < nt; ++a) res[a] = res[a] - d * q[m][a];
+    }
+    for (int32_t m = r - 1; m >= 0; --m) {
+        double t = c[m];
+        for (int32_t k = m + 1; k < r; ++k) t = t - R[m][k] * w[k];
+        w[m] = t / R[m][m];
+    }
+    double nr = 0.0, nw = 0.0;
+    for (int32_t a = 0; a < nt; ++a) nr = nr + res[a] * res[a];
+    for (int32_t m = 0; m < r; ++m) nw = nw + w[m] * w[m];
+    *relres = ni > 0.0 ? sqrt(nr) / sqrt(ni) : 0.0;
+    *wnorm = sqrt(nw);
+    return r;
+}
+
+/*
+ * Alg. BAMG over the F points (its printed loop over C points is read as
+ * over F points; C rows are identity rows): from l = lmin, take the
+ * candidates at distance <= l, their weights, and stop when the relative
+ * residual is <= eps and ||w|| <= mu, or at l = lmax.  The row lists the
+ * chosen candidates in ascending order; no candidate gives an empty row.
+ * More than ORC_MAXCAND candidates is an error.
+ */
+int orc_bamg(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf, int32_t nt,
+             const double *V, int32_t lmin, int32_t lmax, double eps, double mu, orc_csr *P) {
+    if (nt < 1 || nt > ORC_MAXNT || lmin < 1 || lmax < lmin) return ORC_E_ARG;
+    int32_t *cmap = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *front = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *work = (double *)malloc(sizeof(double) * (size_t)ORC_MAXCAND * nt);
+    double *coef = (double *)malloc(sizeof(double) * (size_t)ORC_MAXCAND * nt);
+    int32_t *prp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *pci = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n * nt + 1));
+    double *pv = (double *)malloc(sizeof(double) * ((size_t)n * nt + 1));
+    int st = ORC_OK;
+    if (!cmap || !mark || !dist || !front || !cand || !work || !coef || !prp || !pci || !pv) { st = ORC_E_NOMEM; goto done; }
+    int32_t nc0 = 0;
+    for (int32_t i = 0; i < n; ++i) { cmap[i] = nc0; if (cf[i] == ORC_C) ++nc0; mark[i] = -1; }
+    prp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t o = prp[i];
+        if (cf[i] == ORC_C) { pci[o] = cmap[i]; pv[o] = 1.0; prp[i + 1] = o + 1; continue; }
+        int32_t sel[ORC_MAXNT], r = 0, nc = 0;
+        double w[ORC_MAXNT], relres = 0.0, wn = 0.0;
+        for (int32_t l = lmin; l <= lmax; ++l) {
+            nc = bamg_candidates(rp, ci, strong, cf, i, l, mark, dist, front, cand);
+            if (nc > ORC_MAXCAND) { st = ORC_E_ARG; goto done; }
+            r = nc > 0 ? bamg_weights(nt, V, i, cand, nc, work, coef, sel, w, &relres, &wn) : 0;
+            if (relres <= eps && wn <= mu && r > 0) break;
+        }
+        /* ascending candidate order */
+        int32_t ord[ORC_MAXNT];
+        for (int32_t m = 0; m < r; ++m) ord[m] = m;
+        for (int32_t a = 1; a < r; ++a) {
+            int32_t x = ord[a], b = a - 1;
+            while (b >= 0 && cand[sel[ord[b]]] > cand[sel[x]]) { ord[b + 1] = ord[b]; --b; }
+            ord[b + 1] = x;
+        }
+        for (int32_t m = 0; m < r; ++m) {
+            pci[o + m] = cmap[cand[sel[ord[m]]]];
+            pv[o + m] = w[ord[m]];
+        }
+        prp[i + 1] = o + r;
+    }
+    P->nrows = n; P->ncols = nc0; P->rp = prp; P->ci = pci; P->val = pv;
+    prp = NULL; pci = NULL; pv = NULL;
+done:
+    free(cmap); free(mark); free(dist); free(front); free(cand); free(work); free(coef);
+    free(prp); free(pci); free(pv);
+    return st;
+}
+
 /* X^T by counting sort on the column index; rows of the result list their
  * columns in ascending order.  The restriction is R = P^T (eq. AcDef). */
 int orc_transpose(const orc_csr *X, orc_csr *XT) {
@@ -729,6 +941,7 @@ struct orc_hier {
     int32_t nlev;            /* levels 0..nlev-1; the last one is solved directly */
     orc_level lev[ORC_MAXLEV];
     double *L;               /* dense Cholesky factor of the last level */
+    double *tv;              /* BAMG: test space of the level being built */
 };
 
 static int copy_csr(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, orc_csr *o) {
@@ -753,6 +966,7 @@ void orc_destroy(orc_hier *h) {
         free(L->strong); free(L->stcnt); free(L->cf); free(L->dinv);
     }
     free(h->L);
+    free(h->tv);
     free(h);
 }
 
@@ -770,11 +984,30 @@ void orc_destroy(orc_hier *h) {
  */
 int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
               const orc_params *prm, orc_hier **out) {
+    return orc_setup_tv(n, rp, ci, v, 0, NULL, prm, out);
+}
+
+/* With BAMG interpolation the level-0 test space is V made orthonormal;
+ * level l+1 takes the rows of level l's test space at its C points (P is
+ * the identity there). */
+int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt, const double *V,
+                 const orc_params *prm, orc_hier **out) {
     *out = NULL;
     int st = orc_validate(n, rp, ci, v);
     if (st != ORC_OK) return st;
+    int bamg = prm && prm->interp == ORC_INTERP_BAMG;
+    if (bamg && (nt < 1 || nt > ORC_MAXNT || !V)) return ORC_E_ARG;
+    double *TV = NULL;
+    if (bamg) {
+        TV = (double *)malloc(sizeof(double) * (size_t)n * nt);
+        if (!TV) return ORC_E_NOMEM;
+        memcpy(TV, V, sizeof(double) * (size_t)n * nt);
+        st = orc_orthonormalize(n, nt, TV);
+        if (st) { free(TV); return st; }
+    }
     orc_hier *h = (orc_hier *)calloc(1, sizeof(orc_hier));
-    if (!h) return ORC_E_NOMEM;
+    if (!h) { free(TV); return ORC_E_NOMEM; }
+    h->tv = TV;
     if (prm) h->prm = *prm; else orc_params_default(&h->prm);
     if (h->prm.max_levels > ORC_MAXLEV) h->prm.max_levels = ORC_MAXLEV;
     if (h->prm.max_levels < 1) h->prm.max_levels = 1;
@@ -814,7 +1047,20 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
         int32_t nc = 0;
         for (int32_t i = 0; i < nl; ++i) if (L->cf[i] == ORC_C) ++nc;
         if (nc == 0 || nc == nl) break;
-        st = orc_interp(nl, arp, aci, av, L->strong, L->cf, h->prm.interp, &L->P);
+        if (bamg) {
+            st = orc_bamg(nl, arp, aci, L->strong, L->cf, nt, TV, h->prm.bamg_lmin, h->prm.bamg_lmax,
+                          h->prm.bamg_eps, h->prm.bamg_mu, &L->P);
+            if (!st) {  /* the next level's test space: rows at the C points */
+                int32_t c = 0;
+                for (int32_t i = 0; i < nl; ++i)
+                    if (L->cf[i] == ORC_C) {
+                        memmove(TV + (size_t)c * nt, TV + (size_t)i * nt, sizeof(double) * (size_t)nt);
+                        ++c;
+                    }
+            }
+        } else {
+            st = orc_interp(nl, arp, aci, av, L->strong, L->cf, h->prm.interp, &L->P);
+        }
         if (!st) st = orc_transpose(&L->P, &L->R);
         orc_csr AP = {0, 0, NULL, NULL, NULL};
         if (!st) st = orc_spgemm(&L->A, &L->P, &AP);

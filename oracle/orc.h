@@ -47,9 +47,14 @@ typedef struct {
     int32_t  max_iter;
     int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D) or ORC_SMOOTH_FSAI (M^{-1} = G^T G) */
     int32_t  interp;      /* ORC_INTERP_* */
+    int32_t  bamg_lmin, bamg_lmax;  /* BAMG: interpolation distances tried (1, 2) */
+    double   bamg_eps, bamg_mu;     /* BAMG: accept when relative residual <= eps and ||w|| <= mu */
 } orc_params;
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
-enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3 };
+enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3,
+       ORC_INTERP_BAMG = 4 };
+#define ORC_MAXNT 8        /* test vectors */
+#define ORC_MAXCAND 4096   /* BAMG candidates of one row */
 
 void orc_params_default(orc_params *p);
 
@@ -66,6 +71,11 @@ int  orc_interp_direct(int32_t n, const int32_t *rp, const int32_t *ci, const do
 /* classical (a_ij restored), extended+i or hybrid interpolation for a given C/F split */
 int  orc_interp(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
                 const uint8_t *strong, const int8_t *cf, int32_t variant, orc_csr *P);
+/* BAMG: orthonormal basis of a test space V (n x nt, row-major, in place) */
+int  orc_orthonormalize(int32_t n, int32_t nt, double *V);
+/* BAMG prolongation for test space V (n x nt) and a given C/F split */
+int  orc_bamg(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf, int32_t nt,
+              const double *V, int32_t lmin, int32_t lmax, double eps, double mu, orc_csr *P);
 int  orc_transpose(const orc_csr *X, orc_csr *XT);
 int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
 int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */
@@ -82,6 +92,9 @@ void orc_free(void *p);
 typedef struct orc_hier orc_hier;
 int  orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
                const orc_params *prm, orc_hier **out);
+/* the same with a test space V (n x nt, row-major; needed by ORC_INTERP_BAMG) */
+int  orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt, const double *V,
+                  const orc_params *prm, orc_hier **out);
 int  orc_num_levels(const orc_hier *h);
 /* sizes of level l: n, nnz(A), nnz(P) (0 on the coarsest), n of level l+1 (0 on the coarsest) */
 int  orc_level_sizes(const orc_hier *h, int32_t l, int32_t *n, int32_t *nnzA, int32_t *nnzP, int32_t *nc);

@@ -346,6 +346,25 @@ def elasticity3d(ne: int, nu: float = 0.3, seed: int = SEED_A) -> CSR:
     return CSR(n, row_ptr.astype(np.int32), col_idx, val)
 
 
+def elasticity_rigid_modes(ne: int) -> np.ndarray:
+    """The six rigid body modes of ``elasticity3d(ne)`` at its free dofs
+    (n x 6, row-major): translations along x, y, z, then rotations about z
+    (-y, x, 0), x (0, -z, y) and y (z, 0, -x), from the nodal coordinates
+    (node (ix, iy, iz) at (ix, iy, iz) / ne, iz = 1..ne; dofs interleaved)."""
+    nn = ne + 1
+    iz, iy, ix = np.meshgrid(np.arange(1, nn), np.arange(nn), np.arange(nn), indexing="ij")
+    x, y, z = (ix.ravel() / ne, iy.ravel() / ne, iz.ravel() / ne)
+    m = x.size
+    V = np.zeros((m, 3, 6))
+    V[:, 0, 0] = 1.0
+    V[:, 1, 1] = 1.0
+    V[:, 2, 2] = 1.0
+    V[:, 0, 3], V[:, 1, 3] = -y, x
+    V[:, 1, 4], V[:, 2, 4] = -z, y
+    V[:, 0, 5], V[:, 2, 5] = z, -x
+    return V.reshape(3 * m, 6)
+
+
 def rhs(n: int, seed: int = SEED_B) -> np.ndarray:
     """b ~ U[-1, 1] per entry, Philox(key=seed)."""
     return _rng(seed).uniform(-1.0, 1.0, n)

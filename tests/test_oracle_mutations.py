@@ -1,6 +1,6 @@
 """Plant plausible mistakes in a copy of the oracle source and check that
-the pins in test_oracle.py, test_oracle_fsai.py and test_oracle_interp.py
-catch every one of
+the pins in test_oracle.py, test_oracle_fsai.py, test_oracle_interp.py and
+test_oracle_bamg.py catch every one of
 them (CPU only)."""
 import os
 import subprocess
@@ -61,10 +61,21 @@ MUTATIONS = [
      "deg = 1;"),
     ("hybrid_no_cover_update", "if (!depends(rp, ci, strong, fp[a], best)) fp[keep++] = fp[a];",
      "if (fp[a] != best) fp[keep++] = fp[a];"),
+    ("bamg_tie_largest", "if (s > bn) { bn = s; best = t; }", "if (s >= bn && s > 0.0) { bn = s; best = t; }"),
+    ("bamg_no_orthogonalization", "for (int32_t a = 0; a < nt; ++a) work[t * nt + a] = work[t * nt + a] - d * q[r][a];",
+     "(void)d;"),
+    ("bamg_back_substitution_sign", "for (int32_t k = m + 1; k < r; ++k) t = t - R[m][k] * w[k];",
+     "for (int32_t k = m + 1; k < r; ++k) t = t + R[m][k] * w[k];"),
+    ("bamg_never_adapts", "if (relres <= eps && wn <= mu && r > 0) break;", "break;"),
+    ("bamg_residual_ignored", "*relres = ni > 0.0 ? sqrt(nr) / sqrt(ni) : 0.0;", "*relres = 0.0; (void)nr; (void)ni;"),
+    ("bamg_weak_paths", "if (j == k || !strong[e] || mark[j] == i) continue;", "if (j == k || mark[j] == i) continue;"),
+    ("bamg_orthonormalize_no_division", "x[a] = t / G[a * nt + a];", "x[a] = t;"),
+    ("bamg_coarse_space_not_injected",
+     "memmove(TV + (size_t)c * nt, TV + (size_t)i * nt, sizeof(double) * (size_t)nt);", "(void)i;"),
 ]
 
 
-PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py"]
+PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py", "test_oracle_bamg.py"]
 
 
 def _first_file(name):
@@ -74,6 +85,8 @@ def _first_file(name):
         return "test_oracle_fsai.py"
     if name.startswith(("ext_", "hybrid_", "classical_")):
         return "test_oracle_interp.py"
+    if name.startswith("bamg_"):
+        return "test_oracle_bamg.py"
     return "test_oracle.py"
 
 

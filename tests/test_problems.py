@@ -91,3 +91,17 @@ def test_poisson3d_torch_matches_numpy():
         assert n == A.n
         assert np.array_equal(rp.numpy(), A.row_ptr) and np.array_equal(ci.numpy(), A.col_idx)
         assert np.array_equal(v.numpy(), A.val)
+
+
+def test_elasticity_rigid_modes_in_kernel_away_from_clamp():
+    # K annihilates the rigid body modes on every row whose node is not
+    # coupled to the clamped z = 0 layer (z >= 2h)
+    ne = 3
+    A = PB.elasticity3d(ne)
+    V = PB.elasticity_rigid_modes(ne)
+    assert V.shape == (A.n, 6)
+    KV = A.to_scipy() @ V
+    nodes_per_layer = (ne + 1) ** 2
+    far = np.arange(A.n) // 3 >= nodes_per_layer   # nodes with z >= 2h
+    assert np.abs(KV[far]).max() < 1e-10 * np.abs(A.val).max()
+    assert np.abs(KV[~far]).max() > 1e-6
