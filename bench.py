@@ -110,6 +110,9 @@ def main():
                     help="print only the serving sweep (8 resident systems, Poisson arrivals)")
     ap.add_argument("--rates", default="5,10,20,50,100,200", help="request rates (1/s) of the serving sweep")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per rate")
+    ap.add_argument("--bamg", type=int, default=0, metavar="NE",
+                    help="only run elasticity on NE^3 elements (64: the 811,200-unknown mechanics case) with "
+                         "direct interpolation and with BAMG interpolation over the rigid body modes")
     ap.add_argument("--poi65m", type=str, default="", metavar="GRID[,GRID...]",
                     help="only run the context case: 7-point Poisson on GRID^3 (404 is the paper's poi65m size) "
                          "with Jacobi + extended+i, as the paper's Chr-jac set-up, and with direct interpolation")
@@ -136,6 +139,9 @@ def main():
     if args.serve:
         print(json.dumps({"serving": serve_run([float(r) for r in args.rates.split(",")], args.serve_seconds)}),
               flush=True)
+        return
+    if args.bamg:
+        print(json.dumps({"bamg_elasticity": bamg_run(args.bamg)}), flush=True)
         return
     if args.poi65m:
         for grid in [int(g) for g in args.poi65m.split(",")]:
@@ -508,6 +514,54 @@ def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
               f"{out['rates'][-1]['solves_per_s']} solves/s", file=sys.stderr, flush=True)
     for _, _, s, _ in systems:
         s.close()
+    return out
+
+
+def bamg_run(ne):
+    """Q1 elasticity on ne^3 elements (b ~ U[-1, 1]): set-up and solve to
+    rtol 1e-8 with direct interpolation, then with BAMG interpolation over
+    the six rigid body modes (FP64 and mixed).  Each configuration runs once
+    untimed, then once timed."""
+    import numpy as np
+    import torch
+
+    from paper_2102_07417_amd import camg, problems
+
+    dev = torch.device("cuda:0")
+    A = problems.elasticity3d(ne)
+    b = problems.rhs(A.n)
+    V = problems.elasticity_rigid_modes(ne)
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.val))
+    dV = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
+    db = torch.from_numpy(b).to(dev)
+    dx = torch.zeros_like(db)
+    stream = torch.cuda.current_stream()
+
+    def run(precision, bamg):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kw = dict(interp=camg.INTERP_BAMG, V=dV) if bamg else {}
+        s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=5000, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dx.zero_()
+        r = s.solve_dev(db, dx, rtol=1e-8, stream=stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        inf = s.info
+        s.close()
+        return {"setup_ms": round((t1 - t0) * 1e3, 3), "solve_ms": round((t2 - t1) * 1e3, 3), "iters": r.iters,
+                "status": r.status, "true_relres": r.true_relres, "levels": inf.levels,
+                "grid_complexity": round(inf.grid_complexity, 4),
+                "operator_complexity": round(inf.operator_complexity, 4),
+                "setup_phase_ms": {k: round(inf.setup_phase_ms[i], 2) for i, k in enumerate(camg.SETUP_PHASES)}}
+
+    out = {"ne": ne, "n": A.n, "nnz": A.nnz, "test_vectors": 6}
+    for key, prec, bamg in (("direct_fp64", camg.FP64, False), ("bamg_fp64", camg.FP64, True),
+                            ("direct_mixed", camg.MIXED_FP32, False), ("bamg_mixed", camg.MIXED_FP32, True)):
+        run(prec, bamg)
+        out[key] = run(prec, bamg)
+        print(f"[elasticity {ne}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 
 

@@ -68,7 +68,17 @@ enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1 };
  * cover the most strong F neighbours without a C point in the set; the
  * smallest index on ties).  Rows have at most 2048 candidate C points
  * (CAMG_E_ARG otherwise). */
-enum { CAMG_INTERP_DIRECT = 0, CAMG_INTERP_CLASSICAL = 1, CAMG_INTERP_EXTI = 2, CAMG_INTERP_HYBRID = 3 };
+enum { CAMG_INTERP_DIRECT = 0, CAMG_INTERP_CLASSICAL = 1, CAMG_INTERP_EXTI = 2, CAMG_INTERP_HYBRID = 3,
+       CAMG_INTERP_BAMG = 4 };
+/* CAMG_INTERP_BAMG (eq. minBAMG, Alg. BAMG; set up with camg_setup_tv): the
+ * weights of F point i least-squares fit its row of the test space from
+ * the rows of a basis of C points chosen greedily (largest residual norm,
+ * smallest index on ties; at most nt points) among the C points within
+ * strength-graph distance l; l grows from bamg_lmin while the relative
+ * residual exceeds bamg_eps or ||w|| exceeds bamg_mu, up to bamg_lmax (at
+ * most 2 here).  The test space is made orthonormal on level 0 and taken at
+ * the C points on coarser levels.  Rows have at most 128 candidates
+ * (CAMG_E_ARG otherwise). */
 
 /* Hierarchy and solver parameters. */
 typedef struct {
@@ -88,6 +98,10 @@ typedef struct {
     int64_t  rap_chunk;   /* Galerkin product R (A P): when A P has more products than this, it is formed in
                              windows of coarse rows of at most this many products (bounds the set-up's scratch
                              memory and keeps A P under 2^31 entries); 0: 2^30.  Results are bitwise the same */
+    int32_t  bamg_lmin;   /* BAMG: first interpolation distance tried; default 1 */
+    int32_t  bamg_lmax;   /* BAMG: last one (<= 2); default 2 */
+    double   bamg_eps;    /* BAMG: accept when the relative residual of the fit is <= eps (default 1e-3) */
+    double   bamg_mu;     /*       and the weights' 2-norm is <= mu (default 10) */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32
@@ -130,6 +144,20 @@ camg_status camg_setup(int32_t n, const int32_t *row_ptr, const int32_t *col_idx
                        const camg_params *params, camg_handle *out);
 camg_status camg_setup_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
                            const camg_params *params, void *hip_stream, camg_handle *out);
+/*
+ * The same with a test space for BAMG interpolation (Section 2, Unveiling
+ * the operator near kernel; eq. minBAMG): V is n x nt, row-major (row k =
+ * the test-space values at unknown k), 1 <= nt <= 8, linearly independent
+ * columns (CAMG_E_ARG otherwise), e.g. the rigid body modes of an
+ * elasticity problem.  V is borrowed for the call (host memory for
+ * camg_setup_tv, device memory for camg_setup_tv_dev).  With
+ * params->interp != CAMG_INTERP_BAMG, V is ignored.
+ */
+camg_status camg_setup_tv(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, int32_t nt,
+                          const double *V, const camg_params *params, camg_handle *out);
+camg_status camg_setup_tv_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
+                              int32_t nt, const double *d_V, const camg_params *params, void *hip_stream,
+                              camg_handle *out);
 
 /*
  * Solve A x = b by PCG preconditioned with one V-cycle per iteration

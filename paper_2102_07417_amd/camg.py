@@ -24,7 +24,7 @@ MAX_LEVELS = 32
 
 EXPORTED = [
     "camg_abi_version", "camg_status_str", "camg_last_error", "camg_params_default", "camg_setup",
-    "camg_setup_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
+    "camg_setup_dev", "camg_setup_tv", "camg_setup_tv_dev", "camg_solve", "camg_solve_dev", "camg_solve_multi_dev", "camg_vcycle_dev", "camg_info",
     "camg_level_sizes", "camg_export_level", "camg_galerkin", "camg_free_host", "camg_destroy", "camg_profile",
     "camg_set_option", "camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
     "camg_engine_state", "camg_engine_finish", "camg_engine_destroy", "camg_server_create", "camg_server_add",
@@ -32,7 +32,7 @@ EXPORTED = [
 ]
 OPT_GRAPH = 1
 SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
-INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID = 0, 1, 2, 3
+INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 OPT_AUTOTUNE = 2
 
 
@@ -40,7 +40,8 @@ class camg_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("seed", C.c_uint64), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
-                ("interp", C.c_int32), ("rap_chunk", C.c_int64)]
+                ("interp", C.c_int32), ("rap_chunk", C.c_int64), ("bamg_lmin", C.c_int32),
+                ("bamg_lmax", C.c_int32), ("bamg_eps", C.c_double), ("bamg_mu", C.c_double)]
 
 
 class camg_info_t(C.Structure):
@@ -72,6 +73,8 @@ def load(path: str | None = None):
     L.camg_params_default.argtypes = [C.POINTER(camg_params)]
     L.camg_setup.argtypes = [i32, vp, vp, vp, C.POINTER(camg_params), C.POINTER(vp)]
     L.camg_setup_dev.argtypes = [i32, vp, vp, vp, C.POINTER(camg_params), vp, C.POINTER(vp)]
+    L.camg_setup_tv.argtypes = [i32, vp, vp, vp, i32, vp, C.POINTER(camg_params), C.POINTER(vp)]
+    L.camg_setup_tv_dev.argtypes = [i32, vp, vp, vp, i32, vp, C.POINTER(camg_params), vp, C.POINTER(vp)]
     L.camg_solve.argtypes = [vp, vp, dbl, vp, vp, vp, i32, vp]
     L.camg_solve_dev.argtypes = [vp, vp, dbl, vp, vp, vp, i32, vp, vp]
     L.camg_solve_multi_dev.argtypes = [vp, i32, vp, dbl, vp, vp, vp, i32, vp, vp]
@@ -161,6 +164,25 @@ def camg_setup_dev(n, d_row_ptr, d_col_idx, d_val, prm=None, stream=None):
     st = load().camg_setup_dev(int(n), C.c_void_p(d_row_ptr.data_ptr()), C.c_void_p(d_col_idx.data_ptr()),
                                C.c_void_p(d_val.data_ptr()), C.byref(prm) if prm is not None else None,
                                _stream_ptr(stream), C.byref(h))
+    return st, h
+
+
+def camg_setup_tv(n, row_ptr, col_idx, val, V, prm=None):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    V = np.ascontiguousarray(V, np.float64)
+    h = C.c_void_p()
+    st = load().camg_setup_tv(int(n), _p(rp), _p(ci), _p(v), int(V.shape[1]), _p(V),
+                              C.byref(prm) if prm is not None else None, C.byref(h))
+    return st, h
+
+
+def camg_setup_tv_dev(n, d_row_ptr, d_col_idx, d_val, d_V, prm=None, stream=None):
+    h = C.c_void_p()
+    st = load().camg_setup_tv_dev(int(n), C.c_void_p(d_row_ptr.data_ptr()), C.c_void_p(d_col_idx.data_ptr()),
+                                  C.c_void_p(d_val.data_ptr()), int(d_V.shape[1]), C.c_void_p(d_V.data_ptr()),
+                                  C.byref(prm) if prm is not None else None, _stream_ptr(stream), C.byref(h))
     return st, h
 
 
@@ -410,22 +432,29 @@ class Solver:
     ``Solver(A)`` with A a problems.CSR (host arrays, copied to the device),
     or ``Solver.from_device(n, rp, ci, val)`` with torch CUDA tensors."""
 
-    def __init__(self, A=None, stream=None, _handle=None, **kw):
+    def __init__(self, A=None, stream=None, _handle=None, V=None, **kw):
         self.h = None
         if _handle is not None:
             self.h = _handle
         else:
             prm = params(**kw)
-            st, h = camg_setup(A.n, A.row_ptr, A.col_idx, A.val, prm)
+            if V is None:
+                st, h = camg_setup(A.n, A.row_ptr, A.col_idx, A.val, prm)
+            else:
+                st, h = camg_setup_tv(A.n, A.row_ptr, A.col_idx, A.val, V, prm)
             _check(st)
             self.h = h
         self.info = camg_info(self.h)
         self.n = self.info.n[0]
 
     @classmethod
-    def from_device(cls, n, d_rp, d_ci, d_val, stream=None, **kw):
+    def from_device(cls, n, d_rp, d_ci, d_val, stream=None, V=None, **kw):
+        """V: optional test space (torch CUDA tensor, n x nt float64) for BAMG."""
         prm = params(**kw)
-        st, h = camg_setup_dev(n, d_rp, d_ci, d_val, prm, stream)
+        if V is None:
+            st, h = camg_setup_dev(n, d_rp, d_ci, d_val, prm, stream)
+        else:
+            st, h = camg_setup_tv_dev(n, d_rp, d_ci, d_val, V, prm, stream)
         _check(st)
         return cls(_handle=h)
 

@@ -171,7 +171,10 @@ void check_params(const camg_params &p) {
     if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
     if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI) fail(CAMG_E_ARG, "unknown smoother");
-    if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_HYBRID) fail(CAMG_E_ARG, "unknown interpolation");
+    if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_BAMG) fail(CAMG_E_ARG, "unknown interpolation");
+    if (p.interp == CAMG_INTERP_BAMG &&
+        (p.bamg_lmin < 1 || p.bamg_lmax < p.bamg_lmin || p.bamg_lmax > 2 || std::isnan(p.bamg_eps) || std::isnan(p.bamg_mu)))
+        fail(CAMG_E_ARG, "BAMG: need 1 <= bamg_lmin <= bamg_lmax <= 2 and eps, mu not NaN");
     if (p.rap_chunk < 0) fail(CAMG_E_ARG, "rap_chunk must be >= 0");
 }
 
@@ -214,8 +217,8 @@ RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
     return c;
 }
 
-void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const double *v, bool host_in,
-                     hipStream_t s) {
+void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const double *v, int nt,
+                     const double *V, bool host_in, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const camg_params &prm = h.prm;
     Pool tmp(s);
@@ -259,6 +262,14 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     }
     int32_t *tpos = tmp.alloc<int32_t>(std::max<int64_t>(nnz, 1));
     validate_input(h, n, nnz, h.lev[0].A, tpos, tmp, s);
+    // BAMG: the level's test space (orthonormal basis of V on level 0)
+    double *tv = nullptr;
+    if (prm.interp == CAMG_INTERP_BAMG) {
+        tv = tmp.alloc<double>((size_t)n * nt);
+        HIPC(hipMemcpyAsync(tv, V, sizeof(double) * (size_t)n * nt,
+                            host_in ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        bamg_orthonormalize(n, nt, tv, tmp, s);
+    }
     phase(0);
 
     int32_t *flags = tmp.alloc<int32_t>(8);
@@ -360,16 +371,28 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         const int64_t nc = read1(cmap + nl, s);
         if (nc == 0 || nc == nl) break;  // coarsening stalled: this is the last level
         phase(2);
-        // interpolation P = [W; I]: direct, or the paper's classical,
-        // extended+i or hybrid formula
+        // interpolation P = [W; I]: direct, the paper's classical,
+        // extended+i or hybrid formula, or BAMG over the test space
         Csr &P = L.P;
         P.nr = nl;
         P.nc = (int32_t)nc;
         int32_t *pcnt = lt.alloc<int32_t>(nl);
-        int32_t *bnd = nullptr, *xflags = nullptr;
+        int32_t *bnd = nullptr, *xflags = nullptr, *btci = nullptr;
+        double *btv = nullptr;
         int bmax = 0;
         if (prm.interp == CAMG_INTERP_DIRECT) {
             interp_count(nl, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
+        } else if (prm.interp == CAMG_INTERP_BAMG) {
+            btci = lt.alloc<int32_t>((size_t)nl * nt);
+            btv = lt.alloc<double>((size_t)nl * nt);
+            xflags = lt.alloc<int32_t>(3);
+            HIPC(hipMemsetAsync(xflags, 0, 3 * sizeof(int32_t), s));
+            bamg_rows(nl, L.A, L.strong, L.cf, nt, tv, prm.bamg_lmin, prm.bamg_lmax, prm.bamg_eps, prm.bamg_mu, cmap,
+                      pcnt, btci, btv, xflags, s);
+            int32_t hf[3];
+            HIPC(hipMemcpyAsync(hf, xflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (hf[2]) fail(CAMG_E_ARG, "BAMG: a row has more than 128 candidate coarse points");
         } else {
             bnd = lt.alloc<int32_t>(nl);
             xflags = lt.alloc<int32_t>(2);
@@ -387,6 +410,12 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         P.v = h.pool.alloc<double>(padded(P.nnz));
         if (prm.interp == CAMG_INTERP_DIRECT) {
             interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
+        } else if (prm.interp == CAMG_INTERP_BAMG) {
+            bamg_compact(nl, nt, btci, btv, P, s);
+            // the next level's test space: the rows at the C points
+            double *tvc = tmp.alloc<double>((size_t)nc * nt);
+            bamg_gather_tv(nl, nt, L.cf, cmap, tv, tvc, s);
+            tv = tvc;
         } else {
             xi_fill(nl, L.A, L.strong, L.cf, prm.interp, bnd, bmax, cmap, P.rp, P.ci, P.v, xflags, s);
             int32_t hf[2];
@@ -882,10 +911,15 @@ void camg_params_default(camg_params *p) {
     p->smoother = CAMG_SMOOTH_JACOBI;
     p->interp = CAMG_INTERP_DIRECT;
     p->rap_chunk = 0;
+    p->bamg_lmin = 1;
+    p->bamg_lmax = 2;
+    p->bamg_eps = 1e-3;
+    p->bamg_mu = 10.0;
 }
 
-static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-                                const camg_params *params, void *stream, bool host_in, camg_handle *out) {
+static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt,
+                                const double *V, const camg_params *params, void *stream, bool host_in,
+                                camg_handle *out) {
     return guarded([&] {
         if (!out) fail(CAMG_E_ARG, "null output handle");
         *out = nullptr;
@@ -894,8 +928,10 @@ static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci,
         if (params) h->prm = *params;
         else camg_params_default(&h->prm);
         check_params(h->prm);
+        if (h->prm.interp == CAMG_INTERP_BAMG && (nt < 1 || nt > 8 || !V))
+            fail(CAMG_E_ARG, "BAMG interpolation needs a test space of 1 to 8 vectors (camg_setup_tv)");
         HIPC(hipGetDevice(&h->device));
-        build_hierarchy(*h, n, rp, ci, v, host_in, (hipStream_t)stream);
+        build_hierarchy(*h, n, rp, ci, v, nt, V, host_in, (hipStream_t)stream);
         *out = h.release();
     });
 }
@@ -907,12 +943,28 @@ camg_status camg_setup(int32_t n, const int32_t *row_ptr, const int32_t *col_idx
         if (out) *out = nullptr;
         return CAMG_E_CSR;
     }
-    return setup_common(n, row_ptr, col_idx, val, params, nullptr, true, out);
+    return setup_common(n, row_ptr, col_idx, val, 0, nullptr, params, nullptr, true, out);
 }
 
 camg_status camg_setup_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
                            const camg_params *params, void *hip_stream, camg_handle *out) {
-    return setup_common(n, d_row_ptr, d_col_idx, d_val, params, hip_stream, false, out);
+    return setup_common(n, d_row_ptr, d_col_idx, d_val, 0, nullptr, params, hip_stream, false, out);
+}
+
+camg_status camg_setup_tv(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, int32_t nt,
+                          const double *V, const camg_params *params, camg_handle *out) {
+    if (n >= 1 && row_ptr && (row_ptr[0] != 0 || row_ptr[n] < 0)) {
+        g_last_error = "row pointer is not 0-based";
+        if (out) *out = nullptr;
+        return CAMG_E_CSR;
+    }
+    return setup_common(n, row_ptr, col_idx, val, nt, V, params, nullptr, true, out);
+}
+
+camg_status camg_setup_tv_dev(int32_t n, const int32_t *d_row_ptr, const int32_t *d_col_idx, const double *d_val,
+                              int32_t nt, const double *d_V, const camg_params *params, void *hip_stream,
+                              camg_handle *out) {
+    return setup_common(n, d_row_ptr, d_col_idx, d_val, nt, d_V, params, hip_stream, false, out);
 }
 
 camg_status camg_solve_dev(camg_handle hh, const double *d_b, double rtol, double *d_x, int32_t *iters,

@@ -213,6 +213,15 @@ void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int 
               int32_t *cnt, int32_t *flags, hipStream_t s);
 void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
              const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, int32_t *flags, hipStream_t s);
+// BAMG prolongation: orthonormal basis of the test space (in place; nt <= 8),
+// packed rows (nt slots per row, counts in cnt; flags[2]: a row has too
+// many candidates), packed rows -> P (P.rp set), the next level's test space
+void bamg_orthonormalize(int n, int nt, double *V, Pool &tmp, hipStream_t s);
+void bamg_rows(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int nt, const double *V, int lmin,
+               int lmax, double eps, double mu, const int64_t *cmap, int32_t *cnt, int32_t *tci, double *tv,
+               int32_t *flags, hipStream_t s);
+void bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const Csr &P, hipStream_t s);
+void bamg_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc, hipStream_t s);
 void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 // FSAI smoother: counts of entries on or below the diagonal per row (returns
 // the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:

@@ -1582,6 +1582,260 @@ __global__ void __launch_bounds__(WPB * TPR)
     }
 }
 
+// ---------------------------------------------------------------- BAMG
+// BAMG prolongation (Section 2, Interpolation, eq. minBAMG and Alg. BAMG)
+// for a test space V (n x nt, row-major).  The CPU reference's operations in
+// its order: each candidate's sums run over the test-space components in
+// order, the greedy basis is the largest residual norm with the smallest
+// index on ties, and the small sequential steps (projection of phi_i, the
+// triangular solve) run on one lane.
+constexpr int kBamgNt = 8, kBamgRaw = 1024, kBamgCand = 128;
+
+// Gram matrix of V: one thread per entry (a, b), b <= a, rows in index order
+__global__ void k_gram(int n, int nt, const double *V, double *G) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt * nt) return;
+    const int a = t / nt, b = t % nt;
+    if (b > a) return;
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s = s + V[(size_t)r * nt + a] * V[(size_t)r * nt + b];
+    G[a * nt + b] = s;
+}
+
+struct BamgL {
+    double l[kBamgNt * kBamgNt];
+};
+
+// each row x of V becomes the solution y of L y = x
+__global__ void k_ortho_rows(int n, int nt, BamgL L, double *V) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double x[kBamgNt];
+    for (int a = 0; a < nt; ++a) x[a] = V[(size_t)r * nt + a];
+    for (int a = 0; a < nt; ++a) {
+        double t = x[a];
+        for (int k = 0; k < a; ++k) t = t - L.l[a * nt + k] * x[k];
+        x[a] = t / L.l[a * nt + a];
+    }
+    for (int a = 0; a < nt; ++a) V[(size_t)r * nt + a] = x[a];
+}
+
+struct BamgLds {
+    int raw[kBamgRaw], cand[kBamgRaw], first[64];
+    int used[kBamgCand];
+    double work[kBamgCand * kBamgNt], coef[kBamgCand * kBamgNt];
+    double q[kBamgNt * kBamgNt], R[kBamgNt * kBamgNt], w[kBamgNt];
+    int sel[kBamgNt];
+    int redi[1];
+    int cnt, r, best;
+    double relres, wn;
+};
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(x, o, kWave);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Greedy basis and weights of row i over G.cand[0..nc) (one wavefront);
+// sets G.r, G.sel, G.w, G.relres, G.wn.
+__device__ void bamg_weights(BamgLds &G, int nt, const double *__restrict__ V, int i, int nc, int lane) {
+    double n0l = 0.0;
+    for (int t = lane; t < nc; t += kWave) {
+        G.used[t] = 0;
+        double s = 0.0;
+        for (int a = 0; a < nt; ++a) {
+            const double x = V[(size_t)G.cand[t] * nt + a];
+            G.work[t * nt + a] = x;
+            s = s + x * x;
+        }
+        n0l = s > n0l ? s : n0l;
+    }
+    const double n0 = __longlong_as_double((long long)wave_max_u64((unsigned long long)__double_as_longlong(n0l)));
+    FSAI_SYNC();
+    int r = 0;
+    while (r < nt) {
+        // the unused candidate with the largest residual norm, smallest index on ties
+        double bl = 0.0;
+        int tl = INT_MAX;
+        for (int t = lane; t < nc; t += kWave) {
+            if (G.used[t]) continue;
+            double s = 0.0;
+            for (int a = 0; a < nt; ++a) s = s + G.work[t * nt + a] * G.work[t * nt + a];
+            if (s > bl) {
+                bl = s;
+                tl = t;
+            }
+        }
+        const unsigned long long mb = wave_max_u64((unsigned long long)__double_as_longlong(bl));
+        const double bn = __longlong_as_double((long long)mb);
+        const int best = wave_min_i((unsigned long long)__double_as_longlong(bl) == mb && bl > 0.0 ? tl : INT_MAX);
+        if (best == INT_MAX || !(bn > 1e-20 * n0)) break;
+        const double nb = sqrt(bn);
+        if (lane < nt) G.q[r * kBamgNt + lane] = G.work[best * nt + lane] / nb;
+        if (lane < r) G.R[lane * kBamgNt + r] = G.coef[best * nt + lane];
+        if (lane == 0) {
+            G.R[r * kBamgNt + r] = nb;
+            G.used[best] = 1;
+            G.sel[r] = best;
+        }
+        FSAI_SYNC();
+        for (int t = lane; t < nc; t += kWave) {
+            if (G.used[t]) continue;
+            double d = 0.0;
+            for (int a = 0; a < nt; ++a) d = d + G.q[r * kBamgNt + a] * G.work[t * nt + a];
+            G.coef[t * nt + r] = d;
+            for (int a = 0; a < nt; ++a) G.work[t * nt + a] = G.work[t * nt + a] - d * G.q[r * kBamgNt + a];
+        }
+        FSAI_SYNC();
+        ++r;
+    }
+    if (lane == 0) {
+        double res[kBamgNt], c[kBamgNt];
+        double ni = 0.0;
+        for (int a = 0; a < nt; ++a) {
+            res[a] = V[(size_t)i * nt + a];
+            ni = ni + res[a] * res[a];
+        }
+        for (int m = 0; m < r; ++m) {
+            double d = 0.0;
+            for (int a = 0; a < nt; ++a) d = d + G.q[m * kBamgNt + a] * res[a];
+            c[m] = d;
+            for (int a = 0; a < nt; ++a) res[a] = res[a] - d * G.q[m * kBamgNt + a];
+        }
+        for (int m = r - 1; m >= 0; --m) {
+            double t = c[m];
+            for (int k = m + 1; k < r; ++k) t = t - G.R[m * kBamgNt + k] * G.w[k];
+            G.w[m] = t / G.R[m * kBamgNt + m];
+        }
+        double nr = 0.0, nw = 0.0;
+        for (int a = 0; a < nt; ++a) nr = nr + res[a] * res[a];
+        for (int m = 0; m < r; ++m) nw = nw + G.w[m] * G.w[m];
+        G.relres = ni > 0.0 ? sqrt(nr) / sqrt(ni) : 0.0;
+        G.wn = sqrt(nw);
+        G.r = r;
+    }
+    FSAI_SYNC();
+}
+
+// One wavefront per row.  C rows: identity.  F rows: candidates at
+// distance <= l along strong connections (l <= 2), weights, until the
+// relative residual <= eps and ||w|| <= mu or l = lmax.  Row i's entries go
+// to tci/tv[i * nt ...], their count to cnt[i].  flags[2]: too many
+// candidates.
+__global__ void __launch_bounds__(64)
+    k_bamg_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                const uint8_t *__restrict__ strong, const int8_t *__restrict__ cf, int nt,
+                const double *__restrict__ V, int lmin, int lmax, double eps, double mu,
+                const int64_t *__restrict__ cmap, int32_t *cnt, int32_t *tci, double *tv, int32_t *flags) {
+    __shared__ BamgLds G;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == kC) {
+        if (lane == 0) {
+            cnt[i] = 1;
+            tci[(size_t)i * nt] = (int32_t)cmap[i];
+            tv[(size_t)i * nt] = 1.0;
+        }
+        return;
+    }
+    const int e0 = rp[i], e1 = rp[i + 1];
+    int r = 0, nc = 0;
+    double relres = 0.0, wn = 0.0;
+    for (int l = lmin; l <= lmax; ++l) {
+        if (lane == 0) G.cnt = 0;
+        FSAI_SYNC();
+        for (int e = e0 + lane; e < e1; e += kWave) {
+            const int j = ci[e];
+            if (j != i && strong[e] && cf[j] == kC) {
+                const int t = atomicAdd(&G.cnt, 1);
+                if (t < kBamgRaw) G.raw[t] = j;
+            }
+        }
+        if (l >= 2)
+            for (int e = e0; e < e1; ++e) {
+                const int j = ci[e];
+                if (j == i || !strong[e]) continue;
+                for (int f = rp[j] + lane; f < rp[j + 1]; f += kWave) {
+                    const int m = ci[f];
+                    if (m != j && m != i && strong[f] && cf[m] == kC) {
+                        const int t = atomicAdd(&G.cnt, 1);
+                        if (t < kBamgRaw) G.raw[t] = m;
+                    }
+                }
+            }
+        FSAI_SYNC();
+        const int T = G.cnt;
+        if (T > kBamgRaw) {
+            if (lane == 0) atomicOr(&flags[2], 1);
+            return;
+        }
+        nc = xi_sort_unique<kWave>(G.raw, nullptr, T, G.cand, nullptr, G.first, G.redi, lane);
+        if (nc > kBamgCand) {
+            if (lane == 0) atomicOr(&flags[2], 1);
+            return;
+        }
+        if (nc > 0) {
+            bamg_weights(G, nt, V, i, nc, lane);
+            r = G.r;
+            relres = G.relres;
+            wn = G.wn;
+        } else {
+            r = 0;
+        }
+        if (relres <= eps && wn <= mu && r > 0) break;
+    }
+    if (lane == 0) {
+        int ord[kBamgNt];
+        for (int m = 0; m < r; ++m) ord[m] = m;
+        for (int a = 1; a < r; ++a) {
+            const int x = ord[a];
+            int b = a - 1;
+            while (b >= 0 && G.cand[G.sel[ord[b]]] > G.cand[G.sel[x]]) {
+                ord[b + 1] = ord[b];
+                --b;
+            }
+            ord[b + 1] = x;
+        }
+        for (int m = 0; m < r; ++m) {
+            tci[(size_t)i * nt + m] = (int32_t)cmap[G.cand[G.sel[ord[m]]]];
+            tv[(size_t)i * nt + m] = G.w[ord[m]];
+        }
+        cnt[i] = r;
+    }
+}
+
+// packed rows (nt slots each) -> CSR rows
+__global__ void k_bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const int32_t *prp, int32_t *pci,
+                               double *pv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = prp[i], m = prp[i + 1] - o;
+    for (int k = 0; k < m; ++k) {
+        pci[o + k] = tci[(size_t)i * nt + k];
+        pv[o + k] = tv[(size_t)i * nt + k];
+    }
+}
+
+// next level's test space: the rows at the C points
+__global__ void k_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || cf[i] != kC) return;
+    for (int a = 0; a < nt; ++a) Vc[(size_t)cmap[i] * nt + a] = V[(size_t)i * nt + a];
+}
+
 // Collatz-Wielandt step on |M|: w = |M| v (CSR order), bound = max w_i / v_i,
 // wmax = max w_i (non-negative doubles compared through their bit patterns)
 __global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *v, double *w,
@@ -1850,6 +2104,53 @@ void xi_count(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int 
 void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int variant, const int32_t *bnd, int bmax,
              const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, int32_t *flags, hipStream_t s) {
     xi_launch<true>(n, A, strong, cf, variant, bnd, bmax, cmap, nullptr, prp, pci, pv, flags, s);
+}
+
+void bamg_orthonormalize(int n, int nt, double *V, Pool &tmp, hipStream_t s) {
+    if (nt < 1 || nt > kBamgNt) fail(CAMG_E_ARG, "test space: 1 to 8 vectors");
+    double *G = tmp.alloc<double>((size_t)nt * nt);
+    k_gram<<<1, 64, 0, s>>>(n, nt, V, G);
+    HIPC(hipGetLastError());
+    double g[kBamgNt * kBamgNt];
+    HIPC(hipMemcpyAsync(g, G, sizeof(double) * nt * nt, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    // G = L L^T, column by column (the CPU reference's operations)
+    double gmax = 0.0;
+    for (int a = 0; a < nt; ++a) gmax = g[a * nt + a] > gmax ? g[a * nt + a] : gmax;
+    for (int j = 0; j < nt; ++j) {
+        double d = g[j * nt + j];
+        for (int k = 0; k < j; ++k) d = d - g[j * nt + k] * g[j * nt + k];
+        if (!(d > 1e-12 * gmax)) fail(CAMG_E_ARG, "test space vectors are linearly dependent");
+        const double ljj = std::sqrt(d);
+        g[j * nt + j] = ljj;
+        for (int i = j + 1; i < nt; ++i) {
+            double t = g[i * nt + j];
+            for (int k = 0; k < j; ++k) t = t - g[i * nt + k] * g[j * nt + k];
+            g[i * nt + j] = t / ljj;
+        }
+    }
+    BamgL L;
+    for (int k = 0; k < nt * nt; ++k) L.l[k] = g[k];
+    k_ortho_rows<<<nblocks(n), kBlock, 0, s>>>(n, nt, L, V);
+    HIPC(hipGetLastError());
+}
+
+void bamg_rows(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int nt, const double *V, int lmin,
+               int lmax, double eps, double mu, const int64_t *cmap, int32_t *cnt, int32_t *tci, double *tv,
+               int32_t *flags, hipStream_t s) {
+    k_bamg_rows<<<n, kWave, 0, s>>>(n, A.rp, A.ci, strong, cf, nt, V, lmin, lmax, eps, mu, cmap, cnt, tci, tv,
+                                     flags);
+    HIPC(hipGetLastError());
+}
+
+void bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const Csr &P, hipStream_t s) {
+    k_bamg_compact<<<nblocks(n), kBlock, 0, s>>>(n, nt, tci, tv, P.rp, P.ci, P.v);
+    HIPC(hipGetLastError());
+}
+
+void bamg_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc, hipStream_t s) {
+    k_gather_tv<<<nblocks(n), kBlock, 0, s>>>(n, nt, cf, cmap, V, Vc);
+    HIPC(hipGetLastError());
 }
 
 double cw_bound(const Csr &M, Pool &tmp, hipStream_t s) {

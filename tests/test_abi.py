@@ -55,6 +55,7 @@ def test_pure_host_calls(lib):
     assert p.theta == 0.25 and p.nu_pre == 1 and p.nu_post == 1 and p.max_coarse == 256 and p.max_levels == 25
     assert p.precision == camg.FP64 and p.omega == 0.0 and p.smoother == camg.SMOOTH_JACOBI
     assert p.interp == camg.INTERP_DIRECT
+    assert p.bamg_lmin == 1 and p.bamg_lmax == 2 and p.bamg_eps == 1e-3 and p.bamg_mu == 10.0
 
 
 def test_argument_errors_without_device(lib):
@@ -67,7 +68,7 @@ def test_argument_errors_without_device(lib):
 
 
 @pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 2), ("theta", 1.5),
-                                         ("precision", 3), ("rap_chunk", -1)])
+                                         ("precision", 3), ("rap_chunk", -1), ("interp", 5)])
 def test_bad_parameters_rejected_without_device(lib, field, value):
     # parameters are checked before the device is touched
     rp = np.array([0, 1], np.int32)
@@ -92,6 +93,8 @@ int main(void) {
   printf("params %zu %zu %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
          offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother),
          offsetof(camg_params, interp), offsetof(camg_params, rap_chunk));
+  printf("bamg %zu %zu %zu\n", offsetof(camg_params, bamg_lmin), offsetof(camg_params, bamg_eps),
+         offsetof(camg_params, bamg_mu));
   printf("info %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
          offsetof(camg_info_t, setup_phase_ms));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
@@ -106,7 +109,26 @@ int main(void) {
     P = camg.camg_params
     assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset,
                              P.interp.offset, P.rap_chunk.offset]
+    assert out["bamg"] == [P.bamg_lmin.offset, P.bamg_eps.offset, P.bamg_mu.offset]
     I = camg.camg_info_t
     assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset]
     Q = camg.camg_completion
     assert out["completion"] == [C.sizeof(Q), Q.true_relres.offset, Q.latency_ms.offset]
+
+
+def test_bamg_setup_rejected_without_device(lib):
+    # BAMG without a test space, or with lmax above 2, is refused before any device work
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    v = np.array([2.0])
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    for kw in ({}, {"bamg_lmax": 3}):
+        p = camg.camg_params()
+        lib.camg_params_default(C.byref(p))
+        p.interp = camg.INTERP_BAMG
+        for k, val in kw.items():
+            setattr(p, k, val)
+        h = C.c_void_p()
+        assert lib.camg_setup(1, vp(rp), vp(ci), vp(v), C.byref(p), C.byref(h)) == camg.E_ARG
+        V = np.ones((1, 9))
+        assert lib.camg_setup_tv(1, vp(rp), vp(ci), vp(v), 9, vp(V), C.byref(p), C.byref(h)) == camg.E_ARG
