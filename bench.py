@@ -520,8 +520,9 @@ def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
 def bamg_run(ne):
     """Q1 elasticity on ne^3 elements (b ~ U[-1, 1]): set-up and solve to
     rtol 1e-8 with direct interpolation, then with BAMG interpolation over
-    the six rigid body modes (FP64 and mixed).  Each configuration runs once
-    untimed, then once timed."""
+    the six rigid body modes (FP64 and mixed; and mixed with the FSAI
+    smoother, the paper's pairing for mechanics).  Each configuration runs
+    once untimed, then once timed."""
     import numpy as np
     import torch
 
@@ -537,10 +538,11 @@ def bamg_run(ne):
     dx = torch.zeros_like(db)
     stream = torch.cuda.current_stream()
 
-    def run(precision, bamg):
+    def run(precision, bamg, smoother=0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         kw = dict(interp=camg.INTERP_BAMG, V=dV) if bamg else {}
+        kw["smoother"] = smoother
         s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=5000, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -557,10 +559,13 @@ def bamg_run(ne):
                 "setup_phase_ms": {k: round(inf.setup_phase_ms[i], 2) for i, k in enumerate(camg.SETUP_PHASES)}}
 
     out = {"ne": ne, "n": A.n, "nnz": A.nnz, "test_vectors": 6}
-    for key, prec, bamg in (("direct_fp64", camg.FP64, False), ("bamg_fp64", camg.FP64, True),
-                            ("direct_mixed", camg.MIXED_FP32, False), ("bamg_mixed", camg.MIXED_FP32, True)):
-        run(prec, bamg)
-        out[key] = run(prec, bamg)
+    for key, prec, bamg, sm in (("direct_fp64", camg.FP64, False, camg.SMOOTH_JACOBI),
+                                ("bamg_fp64", camg.FP64, True, camg.SMOOTH_JACOBI),
+                                ("direct_mixed", camg.MIXED_FP32, False, camg.SMOOTH_JACOBI),
+                                ("bamg_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
+                                ("bamg_fsai_mixed", camg.MIXED_FP32, True, camg.SMOOTH_FSAI)):
+        run(prec, bamg, sm)
+        out[key] = run(prec, bamg, sm)
         print(f"[elasticity {ne}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 
