@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("nu_post", C.c_int32), ("omega", C.c_double), ("max_levels", C.c_int32),
                 ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("bamg_lmin", C.c_int32), ("bamg_lmax", C.c_int32),
-                ("bamg_eps", C.c_double), ("bamg_mu", C.c_double)]
+                ("bamg_eps", C.c_double), ("bamg_mu", C.c_double), ("psmooth", C.c_int32),
+                ("pfilter", C.c_double)]
 
 
 class CsrOut(C.Structure):
@@ -55,6 +56,8 @@ def lib():
         L.orc_interp.argtypes = [i32, vp, vp, vp, vp, vp, i32, C.POINTER(CsrOut)]
         L.orc_orthonormalize.argtypes = [i32, i32, vp]
         L.orc_bamg.argtypes = [i32, vp, vp, vp, vp, i32, vp, i32, i32, dbl, dbl, C.POINTER(CsrOut)]
+        L.orc_psmooth.argtypes = [C.POINTER(CsrOut), vp, dbl, C.POINTER(CsrOut), C.POINTER(CsrOut)]
+        L.orc_pfilter.argtypes = [C.POINTER(CsrOut), dbl, i32, vp, C.POINTER(CsrOut)]
         L.orc_setup_tv.argtypes = [i32, vp, vp, vp, i32, vp, C.POINTER(Params), C.POINTER(vp)]
         L.orc_transpose.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_spgemm.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.POINTER(CsrOut)]
@@ -196,6 +199,27 @@ def bamg(A, strong, cf, V, lmin=1, lmax=2, eps=1e-3, mu=10.0):
     if st != OK:
         raise OracleError(st)
     return _from_out(o)
+
+
+def psmooth(A, dinv, omega, P):
+    """P - omega D^{-1} A P (union pattern)."""
+    oa, ka = _to_out(*_csr_arrays(A))
+    op, kp = _to_out(*_csr_arrays(P))
+    d = np.ascontiguousarray(dinv, np.float64)
+    r = CsrOut()
+    assert lib().orc_psmooth(C.byref(oa), _p(d), float(omega), C.byref(op), C.byref(r)) == OK
+    return _from_out(r)
+
+
+def pfilter(P, rho, W):
+    """Filtered P (rho of each row's absolute sum kept) compensated on W (nc x nt)."""
+    op, kp = _to_out(*_csr_arrays(P))
+    W = np.ascontiguousarray(W, np.float64)
+    if W.ndim == 1:
+        W = W[:, None]
+    r = CsrOut()
+    assert lib().orc_pfilter(C.byref(op), float(rho), W.shape[1], _p(W), C.byref(r)) == OK
+    return _from_out(r)
 
 
 def transpose(X):

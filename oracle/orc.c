@@ -41,6 +41,8 @@ void orc_params_default(orc_params *p) {
     p->bamg_lmax = 2;
     p->bamg_eps = 1e-3;
     p->bamg_mu = 10.0;
+    p->psmooth = 0;
+    p->pfilter = 1.0;
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -667,6 +669,154 @@ done:
     return st;
 }
 
+/*
+ * Prolongation smoothing (Section 2, Interpolation, end): one Jacobi step
+ * on the columns of P, Ps = P - omega D^{-1} (A P), with the level's Jacobi
+ * weight; row i holds the union of the patterns of P and A P (ascending),
+ * entry p - (omega dinv_i) ap with a missing entry read as 0.
+ */
+int orc_psmooth(const orc_csr *A, const double *dinv, double omega, const orc_csr *P, orc_csr *Ps) {
+    orc_csr AP = {0, 0, NULL, NULL, NULL};
+    int st = orc_spgemm(A, P, &AP);
+    if (st) return st;
+    int32_t n = P->nrows;
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t cap = P->rp[n] + AP.rp[n];
+    int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
+    double *val = (double *)malloc(sizeof(double) * (size_t)(cap > 0 ? cap : 1));
+    if (!rp || !ci || !val) { free(rp); free(ci); free(val); orc_csr_free(&AP); return ORC_E_NOMEM; }
+    int32_t o = 0;
+    rp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double s = omega * dinv[i];
+        int32_t a = P->rp[i], b = AP.rp[i];
+        while (a < P->rp[i + 1] || b < AP.rp[i + 1]) {
+            int32_t ja = a < P->rp[i + 1] ? P->ci[a] : INT32_MAX;
+            int32_t jb = b < AP.rp[i + 1] ? AP.ci[b] : INT32_MAX;
+            int32_t j = ja < jb ? ja : jb;
+            double pv = 0.0, av = 0.0;
+            if (ja == j) pv = P->val[a++];
+            if (jb == j) av = AP.val[b++];
+            ci[o] = j;
+            val[o] = pv - s * av;
+            ++o;
+        }
+        rp[i + 1] = o;
+    }
+    orc_csr_free(&AP);
+    Ps->nrows = n; Ps->ncols = P->ncols; Ps->rp = rp; Ps->ci = ci; Ps->val = val;
+    return ORC_OK;
+}
+
+/*
+ * Filtering of P with compensation (Section 2, Filtering, eq. action): per
+ * row, the entries are ranked by decreasing |p| (the smaller column first on
+ * ties) and the shortest leading set whose absolute sum (added in that
+ * order) reaches rho times the row's absolute sum is kept.  The dropped
+ * entries' action on the coarse test space W (nc x nt), r = sum over the
+ * dropped entries (ascending column) of p_j W_j, is moved onto the kept
+ * entries K by the minimum-norm correction d = B^T (B B^T + lambda I)^{-1} r,
+ * B = [W_k]_{k in K} (nt x |K|, kept entries in ascending column), lambda =
+ * 1e-12 trace(B B^T) / nt; the kept entries become p_k + d_k.  Then
+ * P~ W = P W up to the ridge term.  rho >= 1 keeps every row as it is.
+ */
+int orc_pfilter(const orc_csr *P, double rho, int32_t nt, const double *W, orc_csr *Pf) {
+    int32_t n = P->nrows, nnz = P->rp[n];
+    int32_t *rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    uint8_t *keep = (uint8_t *)malloc((size_t)(nnz > 0 ? nnz : 1));
+    if (!rp || !ci || !val || !ord || !keep) {
+        free(rp); free(ci); free(val); free(ord); free(keep);
+        return ORC_E_NOMEM;
+    }
+    int32_t o = 0;
+    rp[0] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t e0 = P->rp[i], m = P->rp[i + 1] - e0;
+        const int32_t *pc = P->ci + e0;
+        const double *pv = P->val + e0;
+        for (int32_t t = 0; t < m; ++t) keep[t] = 1;
+        if (rho < 1.0 && m > 1) {
+            /* rank by |p| descending, column ascending on ties (insertion sort) */
+            for (int32_t t = 0; t < m; ++t) {
+                int32_t x = t, u = t - 1;
+                while (u >= 0 && (fabs(pv[ord[u]]) < fabs(pv[x]) ||
+                                  (fabs(pv[ord[u]]) == fabs(pv[x]) && pc[ord[u]] > pc[x]))) {
+                    ord[u + 1] = ord[u];
+                    --u;
+                }
+                ord[u + 1] = x;
+            }
+            double tot = 0.0, run = 0.0;
+            for (int32_t t = 0; t < m; ++t) tot = tot + fabs(pv[ord[t]]);
+            int32_t nk = 0;
+            while (nk < m && run < rho * tot) run = run + fabs(pv[ord[nk++]]);
+            if (nk < 1) nk = 1;
+            for (int32_t t = 0; t < m; ++t) keep[t] = 0;
+            for (int32_t t = 0; t < nk; ++t) keep[ord[t]] = 1;
+        }
+        /* action of the dropped entries on W */
+        double r[ORC_MAXNT], G[ORC_MAXNT * ORC_MAXNT], y[ORC_MAXNT];
+        int32_t dropped = 0;
+        for (int32_t a = 0; a < nt; ++a) r[a] = 0.0;
+        for (int32_t t = 0; t < m; ++t)
+            if (!keep[t]) {
+                dropped = 1;
+                for (int32_t a = 0; a < nt; ++a) r[a] = r[a] + pv[t] * W[(size_t)pc[t] * nt + a];
+            }
+        if (dropped) {
+            for (int32_t a = 0; a < nt; ++a)
+                for (int32_t b = 0; b <= a; ++b) {
+                    double g = 0.0;
+                    for (int32_t t = 0; t < m; ++t)
+                        if (keep[t]) g = g + W[(size_t)pc[t] * nt + a] * W[(size_t)pc[t] * nt + b];
+                    G[a * nt + b] = g;
+                }
+            double tr = 0.0;
+            for (int32_t a = 0; a < nt; ++a) tr = tr + G[a * nt + a];
+            double lam = 1e-12 * tr / nt;
+            for (int32_t a = 0; a < nt; ++a) G[a * nt + a] = G[a * nt + a] + lam;
+            /* (B B^T + lambda I) y = r by Cholesky */
+            for (int32_t j = 0; j < nt; ++j) {
+                double d = G[j * nt + j];
+                for (int32_t k = 0; k < j; ++k) d = d - G[j * nt + k] * G[j * nt + k];
+                double ljj = sqrt(d > 0.0 ? d : 0.0);
+                G[j * nt + j] = ljj;
+                for (int32_t q = j + 1; q < nt; ++q) {
+                    double t = G[q * nt + j];
+                    for (int32_t k = 0; k < j; ++k) t = t - G[q * nt + k] * G[j * nt + k];
+                    G[q * nt + j] = ljj > 0.0 ? t / ljj : 0.0;
+                }
+            }
+            for (int32_t a = 0; a < nt; ++a) {
+                double t = r[a];
+                for (int32_t k = 0; k < a; ++k) t = t - G[a * nt + k] * y[k];
+                y[a] = G[a * nt + a] > 0.0 ? t / G[a * nt + a] : 0.0;
+            }
+            for (int32_t a = nt - 1; a >= 0; --a) {
+                double t = y[a];
+                for (int32_t k = a + 1; k < nt; ++k) t = t - G[k * nt + a] * y[k];
+                y[a] = G[a * nt + a] > 0.0 ? t / G[a * nt + a] : 0.0;
+            }
+        }
+        for (int32_t t = 0; t < m; ++t) {
+            if (!keep[t]) continue;
+            double d = 0.0;
+            if (dropped)
+                for (int32_t a = 0; a < nt; ++a) d = d + W[(size_t)pc[t] * nt + a] * y[a];
+            ci[o] = pc[t];
+            val[o] = pv[t] + d;
+            ++o;
+        }
+        rp[i + 1] = o;
+    }
+    free(ord); free(keep);
+    Pf->nrows = n; Pf->ncols = P->ncols; Pf->rp = rp; Pf->ci = ci; Pf->val = val;
+    return ORC_OK;
+}
+
 /* X^T by counting sort on the column index; rows of the result list their
  * columns in ascending order.  The restriction is R = P^T (eq. AcDef). */
 int orc_transpose(const orc_csr *X, orc_csr *XT) {
@@ -1060,6 +1210,29 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
             }
         } else {
             st = orc_interp(nl, arp, aci, av, L->strong, L->cf, h->prm.interp, &L->P);
+        }
+        if (!st && h->prm.psmooth) {  /* one Jacobi step on P with the Jacobi weight of the level */
+            double wj = h->prm.omega > 0.0 ? h->prm.omega : orc_gershgorin_omega(nl, arp, aci, av);
+            orc_csr Ps = {0, 0, NULL, NULL, NULL};
+            st = orc_psmooth(&L->A, L->dinv, wj, &L->P, &Ps);
+            if (!st) { orc_csr_free(&L->P); L->P = Ps; }
+        }
+        if (!st && h->prm.pfilter < 1.0) {  /* filter on the coarse test space (a unit vector without one) */
+            int32_t ncl = L->P.ncols;
+            double *ones = NULL;
+            const double *W = TV;
+            int32_t ntw = nt;
+            if (!bamg) {
+                ones = (double *)malloc(sizeof(double) * (size_t)(ncl > 0 ? ncl : 1));
+                if (!ones) { orc_destroy(h); return ORC_E_NOMEM; }
+                for (int32_t c = 0; c < ncl; ++c) ones[c] = 1.0;
+                W = ones;
+                ntw = 1;
+            }
+            orc_csr Pf = {0, 0, NULL, NULL, NULL};
+            st = orc_pfilter(&L->P, h->prm.pfilter, ntw, W, &Pf);
+            free(ones);
+            if (!st) { orc_csr_free(&L->P); L->P = Pf; }
         }
         if (!st) st = orc_transpose(&L->P, &L->R);
         orc_csr AP = {0, 0, NULL, NULL, NULL};

@@ -49,6 +49,8 @@ typedef struct {
     int32_t  interp;      /* ORC_INTERP_* */
     int32_t  bamg_lmin, bamg_lmax;  /* BAMG: interpolation distances tried (1, 2) */
     double   bamg_eps, bamg_mu;     /* BAMG: accept when relative residual <= eps and ||w|| <= mu */
+    int32_t  psmooth;     /* 1: one Jacobi step on P (P - omega D^{-1} A P) */
+    double   pfilter;     /* < 1: filter P, keeping this fraction of each row's absolute sum */
 } orc_params;
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
 enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3,
@@ -76,6 +78,9 @@ int  orc_orthonormalize(int32_t n, int32_t nt, double *V);
 /* BAMG prolongation for test space V (n x nt) and a given C/F split */
 int  orc_bamg(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf, int32_t nt,
               const double *V, int32_t lmin, int32_t lmax, double eps, double mu, orc_csr *P);
+/* prolongation smoothing P - omega D^{-1} A P, and filtering with compensation on W (nc x nt) */
+int  orc_psmooth(const orc_csr *A, const double *dinv, double omega, const orc_csr *P, orc_csr *Ps);
+int  orc_pfilter(const orc_csr *P, double rho, int32_t nt, const double *W, orc_csr *Pf);
 int  orc_transpose(const orc_csr *X, orc_csr *XT);
 int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
 int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */

@@ -198,3 +198,97 @@ def test_coarse_test_space_is_injected():
     P1 = O.bamg(h.A(1), h.strong(1), h.cf(1), V1)
     hp = h.P(1)
     assert all(np.array_equal(a, b) for a, b in zip(P1[2:], hp[2:]))
+
+
+# ----------------------------------------------------------------- prolongation smoothing and filtering
+def _int_laplacian_2d(g, rng):
+    """Grid Laplacian with integer weights 1..9; boundary rows get +1 on the
+    diagonal, so interior rows sum to exactly zero."""
+    n = g * g
+    M = np.zeros((n, n))
+    ids = np.arange(n).reshape(g, g)
+    for a, b in ((ids[:, :-1], ids[:, 1:]), (ids[:-1, :], ids[1:, :])):
+        w = rng.integers(1, 10, size=a.size).astype(float)
+        M[a.ravel(), b.ravel()] -= w
+        M[b.ravel(), a.ravel()] -= w
+    M[np.arange(n), np.arange(n)] = -M.sum(1)
+    interior = np.zeros((g, g), bool)
+    interior[1:-1, 1:-1] = True
+    M[np.arange(n), np.arange(n)] += (~interior.ravel()).astype(float)
+    return M, interior.ravel()
+
+
+def test_psmooth_keeps_constants_on_zero_sum_rows():
+    """P 1 = 1 and A 1 = 0 on a row give (P - w D^-1 A P) 1 = 1 there."""
+    M, interior = _int_laplacian_2d(12, np.random.default_rng(5))
+    A = from_dense(M)
+    s, cnt = O.strength(A)
+    cf, _ = O.pmis(A, s, cnt, 0, 0)
+    P = O.interp_direct(A, s, cf)
+    D = dense(P)
+    ok = np.isclose(D.sum(1), 1.0, rtol=0, atol=1e-14)          # rows interpolating constants exactly
+    n, _, rp, ci, _ = A
+    nb = np.array([ok[ci[rp[i]:rp[i + 1]]].all() for i in range(n)])
+    Ps = dense(O.psmooth(A, 1.0 / np.diag(M), 2.0 / 3.0, P))
+    rows = interior & nb
+    assert rows.sum() > 20
+    np.testing.assert_allclose(Ps[rows].sum(1), 1.0, rtol=0, atol=1e-13)
+    # omega = 0 leaves P unchanged (the pattern may grow by explicit zeros)
+    np.testing.assert_array_equal(dense(O.psmooth(A, 1.0 / np.diag(M), 0.0, P)), D)
+
+
+def test_pfilter_hand_example():
+    """Row (0.5, -0.3, 0.15, 0.05), rho = 0.8: the two largest reach 0.8 of
+    the absolute sum 1.0 and are kept; the dropped 0.2 of action on the unit
+    vector is split evenly by the minimum-norm correction: (0.6, -0.2)."""
+    P = (1, 4, np.array([0, 4], np.int32), np.array([0, 1, 2, 3], np.int32), np.array([0.5, -0.3, 0.15, 0.05]))
+    F = O.pfilter(P, 0.8, np.ones(4))
+    assert F[3].tolist() == [0, 1]
+    np.testing.assert_allclose(F[4], [0.6, -0.2], rtol=1e-11)
+    # rho = 1 keeps everything unchanged
+    F1 = O.pfilter(P, 1.0, np.ones(4))
+    assert F1[3].tolist() == [0, 1, 2, 3] and np.array_equal(F1[4], P[4])
+
+
+def test_pfilter_compensates_the_test_space():
+    """The filtered P keeps P's action on the coarse test space (eq. action),
+    up to the ridge term, wherever the kept columns span it."""
+    A = PB.elasticity3d(4)
+    V = PB.elasticity_rigid_modes(4)
+    s, cnt = O.strength(A)
+    cf, _ = O.pmis(A, s, cnt, 0, 0)
+    Q = O.orthonormalize(V)
+    P = O.bamg(A, s, cf, Q)
+    Ps = O.psmooth(A, 1.0 / np.diag(dense(A)), 0.6, P)
+    W = Q[cf == 1]
+    F = O.pfilter(Ps, 0.7, W)
+    Dp, Df = dense(Ps), dense(F)
+    assert F[3].size < 0.8 * Ps[3].size
+    checked = 0
+    for i in range(A.n):
+        kept = np.nonzero(Df[i])[0]
+        if len(kept) < W.shape[1] or np.linalg.matrix_rank(W[kept]) < W.shape[1]:
+            continue
+        np.testing.assert_allclose(Df[i] @ W, Dp[i] @ W, atol=1e-8 * np.abs(Dp[i] @ W).max() + 1e-12)
+        # the kept entries are the largest ones
+        drop = np.setdiff1d(np.nonzero(Dp[i])[0], kept)
+        if len(drop):
+            assert np.abs(Dp[i][drop]).max() <= np.abs(Dp[i][kept]).min()
+        checked += 1
+    assert checked > 20
+
+
+def test_smoothed_bamg_hierarchy():
+    A = PB.elasticity3d(2)
+    h = O.Hierarchy(A, V=PB.elasticity_rigid_modes(2), max_coarse=20, interp=O.INTERP_BAMG, psmooth=1, pfilter=0.8)
+    Ps = [dense(h.P(l)) for l in range(h.nlev - 1)]
+    om = [h.omega(l) for l in range(h.nlev - 1)]
+    M = _M_recursive(dense(A), Ps, om, 0)
+    Mo = np.stack([h.vcycle(e) for e in np.eye(A.n)], axis=1)
+    np.testing.assert_allclose(Mo, M, rtol=0, atol=1e-12 * np.abs(M).max())
+    A = PB.elasticity3d(10)
+    b = PB.rhs(A.n)
+    V = PB.elasticity_rigid_modes(10)
+    r0 = O.Hierarchy(A, V=V, interp=O.INTERP_BAMG).solve(b, 1e-8)
+    r1 = O.Hierarchy(A, V=V, interp=O.INTERP_BAMG, psmooth=1).solve(b, 1e-8)
+    assert r1.status == O.OK and r1.iters < r0.iters

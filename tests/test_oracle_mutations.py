@@ -70,6 +70,12 @@ MUTATIONS = [
     ("bamg_residual_ignored", "*relres = ni > 0.0 ? sqrt(nr) / sqrt(ni) : 0.0;", "*relres = 0.0; (void)nr; (void)ni;"),
     ("bamg_weak_paths", "if (j == k || !strong[e] || mark[j] == i) continue;", "if (j == k || mark[j] == i) continue;"),
     ("bamg_orthonormalize_no_division", "x[a] = t / G[a * nt + a];", "x[a] = t;"),
+    ("bamg_psmooth_sign", "val[o] = pv - s * av;", "val[o] = pv + s * av;"),
+    ("bamg_psmooth_no_scaling", "double s = omega * dinv[i];", "double s = omega; (void)dinv;"),
+    ("bamg_pfilter_keeps_smallest", "while (u >= 0 && (fabs(pv[ord[u]]) < fabs(pv[x]) ||",
+     "while (u >= 0 && (fabs(pv[ord[u]]) > fabs(pv[x]) ||"),
+    ("bamg_pfilter_no_compensation", "val[o] = pv[t] + d;", "val[o] = pv[t]; (void)d;"),
+    ("bamg_pfilter_compensation_sign", "val[o] = pv[t] + d;", "val[o] = pv[t] - d;"),
     ("bamg_coarse_space_not_injected",
      "memmove(TV + (size_t)c * nt, TV + (size_t)i * nt, sizeof(double) * (size_t)nt);", "(void)i;"),
 ]
