@@ -520,9 +520,11 @@ def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
 def bamg_run(ne):
     """Q1 elasticity on ne^3 elements (b ~ U[-1, 1]): set-up and solve to
     rtol 1e-8 with direct interpolation, then with BAMG interpolation over
-    the six rigid body modes (FP64 and mixed; and mixed with the FSAI
-    smoother, the paper's pairing for mechanics).  Each configuration runs
-    once untimed, then once timed."""
+    the six rigid body modes (FP64 and mixed; and mixed with the
+    prolongation smoothed and filtered to rho = 0.7).  Each configuration
+    runs once untimed, then once timed.  (The FSAI smoother is not paired
+    with BAMG here: BAMG's coarse levels have rows beyond its 192-entry
+    limit.)"""
     import numpy as np
     import torch
 
@@ -538,11 +540,12 @@ def bamg_run(ne):
     dx = torch.zeros_like(db)
     stream = torch.cuda.current_stream()
 
-    def run(precision, bamg, smoother=0):
+    def run(precision, bamg, smoother=0, **extra):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         kw = dict(interp=camg.INTERP_BAMG, V=dV) if bamg else {}
         kw["smoother"] = smoother
+        kw.update(extra)
         s = camg.Solver.from_device(A.n, rp, ci, va, stream=stream, precision=precision, max_iter=5000, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -563,9 +566,10 @@ def bamg_run(ne):
                                 ("bamg_fp64", camg.FP64, True, camg.SMOOTH_JACOBI),
                                 ("direct_mixed", camg.MIXED_FP32, False, camg.SMOOTH_JACOBI),
                                 ("bamg_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
-                                ("bamg_fsai_mixed", camg.MIXED_FP32, True, camg.SMOOTH_FSAI)):
-        run(prec, bamg, sm)
-        out[key] = run(prec, bamg, sm)
+                                ("bamg_psmooth_filter_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI)):
+        extra = {"psmooth": 1, "pfilter": 0.7} if "psmooth" in key else {}
+        run(prec, bamg, sm, **extra)
+        out[key] = run(prec, bamg, sm, **extra)
         print(f"[elasticity {ne}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 

@@ -102,6 +102,12 @@ typedef struct {
     int32_t  bamg_lmax;   /* BAMG: last one (<= 2); default 2 */
     double   bamg_eps;    /* BAMG: accept when the relative residual of the fit is <= eps (default 1e-3) */
     double   bamg_mu;     /*       and the weights' 2-norm is <= mu (default 10) */
+    int32_t  psmooth;     /* 1: smooth P by one Jacobi step, P - omega D^{-1} A P (omega: the level's Jacobi
+                             weight); default 0 */
+    double   pfilter;     /* < 1: filter P (Section 2, Filtering): per row keep the largest |p| up to this
+                             fraction of the row's absolute sum and move the dropped entries' action on the
+                             coarse test space (a unit vector without one) onto the kept entries by a
+                             minimum-norm correction; default 1 (off) */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32

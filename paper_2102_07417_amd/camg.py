@@ -41,7 +41,8 @@ class camg_params(C.Structure):
                 ("omega", C.c_double), ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("rap_chunk", C.c_int64), ("bamg_lmin", C.c_int32),
-                ("bamg_lmax", C.c_int32), ("bamg_eps", C.c_double), ("bamg_mu", C.c_double)]
+                ("bamg_lmax", C.c_int32), ("bamg_eps", C.c_double), ("bamg_mu", C.c_double),
+                ("psmooth", C.c_int32), ("pfilter", C.c_double)]
 
 
 class camg_info_t(C.Structure):

@@ -176,6 +176,8 @@ void check_params(const camg_params &p) {
         (p.bamg_lmin < 1 || p.bamg_lmax < p.bamg_lmin || p.bamg_lmax > 2 || std::isnan(p.bamg_eps) || std::isnan(p.bamg_mu)))
         fail(CAMG_E_ARG, "BAMG: need 1 <= bamg_lmin <= bamg_lmax <= 2 and eps, mu not NaN");
     if (p.rap_chunk < 0) fail(CAMG_E_ARG, "rap_chunk must be >= 0");
+    if (p.psmooth != 0 && p.psmooth != 1) fail(CAMG_E_ARG, "psmooth must be 0 or 1");
+    if (!(p.pfilter > 0.0)) fail(CAMG_E_ARG, "pfilter must be > 0");
 }
 
 // ---------------------------------------------------------------- set-up
@@ -300,6 +302,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         double rho;
         std::memcpy(&rho, &hq, sizeof(rho));
         L.omega = prm.omega > 0.0 ? prm.omega : (4.0 / 3.0) / rho;
+        const double w_jacobi = L.omega;  // also the weight of prolongation smoothing
         scale_vec(nl, L.omega, L.dinv, L.wd, s);
         L.awd = h.pool.alloc<double>(padded(nz));
         scale_columns(L.A, L.wd, L.awd, s);
@@ -422,6 +425,21 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             HIPC(hipMemcpyAsync(hf, xflags, sizeof(hf), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
             if (hf[0] || hf[1]) fail(CAMG_E_DEVICE, "interpolation: inconsistent candidate lists");
+        }
+        // prolongation smoothing and filtering (Section 2, Interpolation and
+        // Filtering); the filter keeps P's action on the coarse test space
+        // (a unit vector without one)
+        if (prm.psmooth) psmooth(L.A, L.dinv, w_jacobi, P, h.pool, lt, s);
+        if (prm.pfilter < 1.0) {
+            const double *W = tv;
+            int ntw = nt;
+            if (prm.interp != CAMG_INTERP_BAMG) {
+                double *ones = lt.alloc<double>(std::max<int64_t>(nc, 1));
+                fill_ones((int)nc, ones, s);
+                W = ones;
+                ntw = 1;
+            }
+            pfilter(P, prm.pfilter, ntw, W, h.pool, lt, s);
         }
         phase(3);
         // R = P^T
@@ -915,6 +933,8 @@ void camg_params_default(camg_params *p) {
     p->bamg_lmax = 2;
     p->bamg_eps = 1e-3;
     p->bamg_mu = 10.0;
+    p->psmooth = 0;
+    p->pfilter = 1.0;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt,

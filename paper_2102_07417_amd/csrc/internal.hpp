@@ -222,6 +222,12 @@ void bamg_rows(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int
                int32_t *flags, hipStream_t s);
 void bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const Csr &P, hipStream_t s);
 void bamg_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc, hipStream_t s);
+// Prolongation smoothing P <- P - omega D^{-1} (A P), and filtering of P
+// with compensation on the coarse test space W (n_c x nt); the new P is
+// allocated from `out`.
+void psmooth(const Csr &A, const double *dinv, double omega, Csr &P, Pool &out, Pool &tmp, hipStream_t s);
+void pfilter(Csr &P, double rho, int nt, const double *W, Pool &out, Pool &tmp, hipStream_t s);
+void fill_ones(int n, double *x, hipStream_t s);
 void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 // FSAI smoother: counts of entries on or below the diagonal per row (returns
 // the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:

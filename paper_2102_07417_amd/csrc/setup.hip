@@ -1836,6 +1836,166 @@ __global__ void k_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap
     for (int a = 0; a < nt; ++a) Vc[(size_t)cmap[i] * nt + a] = V[(size_t)i * nt + a];
 }
 
+// ---------------------------------------------------------------- P smoothing and filtering
+// Ps = P - omega D^{-1} (A P): one thread per row merges the rows of P and
+// A P (entry p - (omega dinv_i) ap, a missing entry read as 0).
+template <bool FILL>
+__global__ void k_psmooth(int n, const int32_t *prp, const int32_t *pci, const double *pv, const int32_t *arp,
+                          const int32_t *aci, const double *av, const double *dinv, double omega, int32_t *cnt,
+                          const int32_t *srp, int32_t *sci, double *sv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int a = prp[i], b = arp[i];
+    const int a1 = prp[i + 1], b1 = arp[i + 1];
+    const double sc = omega * dinv[i];
+    int o = FILL ? srp[i] : 0, c = 0;
+    while (a < a1 || b < b1) {
+        const int ja = a < a1 ? pci[a] : INT_MAX, jb = b < b1 ? aci[b] : INT_MAX;
+        const int j = ja < jb ? ja : jb;
+        double p = 0.0, q = 0.0;
+        if (ja == j) p = pv[a++];
+        if (jb == j) q = av[b++];
+        if (FILL) {
+            sci[o + c] = j;
+            sv[o + c] = p - sc * q;
+        }
+        ++c;
+    }
+    if (!FILL) cnt[i] = c;
+}
+
+// Filtering with compensation: one wavefront per row.  The entries are
+// ranked by decreasing |p| (smaller column first on ties) in LDS; lane 0
+// finds the kept prefix (absolute values added in rank order); the
+// dropped action r on W and the Gram matrix of the kept rows of W are sums
+// in ascending column order (one lane per component or pair); lane 0
+// solves (B B^T + lambda I) y = r; kept entries become p + W_k . y.
+constexpr int kFiltMax = 1024;
+
+__global__ void __launch_bounds__(64) k_pfilter(int n, const int32_t *rp, const int32_t *ci, const double *v, double rho,
+                                                int nt, const double *W, int32_t *cnt, int32_t *tci, double *tvv,
+                                                int32_t *flags) {
+    __shared__ int rk[kFiltMax];
+    __shared__ unsigned char keep[kFiltMax];
+    __shared__ double r[kBamgNt], G[kBamgNt * kBamgNt], y[kBamgNt];
+    __shared__ int dropped;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    if (i >= n) return;
+    const int e0 = rp[i], m = rp[i + 1] - e0;
+    if (m > kFiltMax) {
+        if (lane == 0) atomicOr(&flags[2], 1);
+        return;
+    }
+    for (int t = lane; t < m; t += kWave) keep[t] = 1;
+    if (lane == 0) dropped = 0;
+    FSAI_SYNC();
+    if (rho < 1.0 && m > 1) {
+        // rank of each entry in the (|p| desc, column asc) order
+        for (int t = lane; t < m; t += kWave) {
+            const double x = fabs(v[e0 + t]);
+            const int c = ci[e0 + t];
+            int k = 0;
+            for (int u = 0; u < m; ++u) {
+                const double yv = fabs(v[e0 + u]);
+                const int cu = ci[e0 + u];
+                k += (yv > x || (yv == x && cu < c)) ? 1 : 0;
+            }
+            rk[k] = t;
+        }
+        FSAI_SYNC();
+        if (lane == 0) {
+            double tot = 0.0, run = 0.0;
+            for (int k = 0; k < m; ++k) tot = tot + fabs(v[e0 + rk[k]]);
+            int nk = 0;
+            while (nk < m && run < rho * tot) run = run + fabs(v[e0 + rk[nk++]]);
+            if (nk < 1) nk = 1;
+            for (int t = 0; t < m; ++t) keep[t] = 0;
+            for (int k = 0; k < nk; ++k) keep[rk[k]] = 1;
+            dropped = nk < m ? 1 : 0;
+        }
+        FSAI_SYNC();
+    }
+    const int drop = dropped;
+    if (drop) {
+        if (lane < nt) {
+            double ra = 0.0;
+            for (int t = 0; t < m; ++t)
+                if (!keep[t]) ra = ra + v[e0 + t] * W[(size_t)ci[e0 + t] * nt + lane];
+            r[lane] = ra;
+        }
+        for (int pq = lane; pq < nt * nt; pq += kWave) {
+            const int a = pq / nt, b = pq % nt;
+            if (b > a) continue;
+            double g = 0.0;
+            for (int t = 0; t < m; ++t)
+                if (keep[t]) g = g + W[(size_t)ci[e0 + t] * nt + a] * W[(size_t)ci[e0 + t] * nt + b];
+            G[a * nt + b] = g;
+        }
+        FSAI_SYNC();
+        if (lane == 0) {
+            double tr = 0.0;
+            for (int a = 0; a < nt; ++a) tr = tr + G[a * nt + a];
+            const double lam = 1e-12 * tr / nt;
+            for (int a = 0; a < nt; ++a) G[a * nt + a] = G[a * nt + a] + lam;
+            for (int j = 0; j < nt; ++j) {
+                double d = G[j * nt + j];
+                for (int k = 0; k < j; ++k) d = d - G[j * nt + k] * G[j * nt + k];
+                const double ljj = sqrt(d > 0.0 ? d : 0.0);
+                G[j * nt + j] = ljj;
+                for (int q = j + 1; q < nt; ++q) {
+                    double t = G[q * nt + j];
+                    for (int k = 0; k < j; ++k) t = t - G[q * nt + k] * G[j * nt + k];
+                    G[q * nt + j] = ljj > 0.0 ? t / ljj : 0.0;
+                }
+            }
+            for (int a = 0; a < nt; ++a) {
+                double t = r[a];
+                for (int k = 0; k < a; ++k) t = t - G[a * nt + k] * y[k];
+                y[a] = G[a * nt + a] > 0.0 ? t / G[a * nt + a] : 0.0;
+            }
+            for (int a = nt - 1; a >= 0; --a) {
+                double t = y[a];
+                for (int k = a + 1; k < nt; ++k) t = t - G[k * nt + a] * y[k];
+                y[a] = G[a * nt + a] > 0.0 ? t / G[a * nt + a] : 0.0;
+            }
+        }
+        FSAI_SYNC();
+    }
+    // kept entries in ascending column order (their position: kept before them)
+    for (int t = lane; t < m; t += kWave) {
+        if (!keep[t]) continue;
+        int pos = 0;
+        for (int u = 0; u < t; ++u) pos += keep[u];
+        double d = 0.0;
+        if (drop)
+            for (int a = 0; a < nt; ++a) d = d + W[(size_t)ci[e0 + t] * nt + a] * y[a];
+        tci[e0 + pos] = ci[e0 + t];
+        tvv[e0 + pos] = v[e0 + t] + d;
+    }
+    if (lane == 0) {
+        int k = 0;
+        for (int t = 0; t < m; ++t) k += keep[t];
+        cnt[i] = k;
+    }
+}
+
+// rows of a temporary laid out like the source (row i at src_rp[i]) -> CSR
+__global__ void k_compact_rows(int n, const int32_t *src_rp, const int32_t *tci, const double *tv, const int32_t *rp,
+                               int32_t *ci, double *v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s0 = src_rp[i], o = rp[i], m = rp[i + 1] - o;
+    for (int k = 0; k < m; ++k) {
+        ci[o + k] = tci[s0 + k];
+        v[o + k] = tv[s0 + k];
+    }
+}
+
+__global__ void k_fill_ones(int n, double *x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 1.0;
+}
+
 // Collatz-Wielandt step on |M|: w = |M| v (CSR order), bound = max w_i / v_i,
 // wmax = max w_i (non-negative doubles compared through their bit patterns)
 __global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *v, double *w,
@@ -2150,6 +2310,70 @@ void bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const Csr
 
 void bamg_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc, hipStream_t s) {
     k_gather_tv<<<nblocks(n), kBlock, 0, s>>>(n, nt, cf, cmap, V, Vc);
+    HIPC(hipGetLastError());
+}
+
+void psmooth(const Csr &A, const double *dinv, double omega, Csr &P, Pool &out, Pool &tmp, hipStream_t s) {
+    Csr AP;
+    spgemm(A, P, AP, tmp, tmp, s);
+    const int n = P.nr;
+    int32_t *cnt = tmp.alloc<int32_t>(n);
+    k_psmooth<false><<<nblocks(n), kBlock, 0, s>>>(n, P.rp, P.ci, P.v, AP.rp, AP.ci, AP.v, dinv, omega, cnt, nullptr,
+                                                   nullptr, nullptr);
+    HIPC(hipGetLastError());
+    int64_t *rp64 = tmp.alloc<int64_t>((size_t)n + 1);
+    scan_i32_to_i64(cnt, rp64, n, tmp, s);
+    int64_t nnz = 0;
+    HIPC(hipMemcpyAsync(&nnz, rp64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (nnz > INT32_MAX) fail(CAMG_E_NOMEM, "smoothed prolongation has 2^31 or more entries");
+    Csr Ps;
+    Ps.nr = n;
+    Ps.nc = P.nc;
+    Ps.nnz = nnz;
+    Ps.rp = out.alloc<int32_t>((size_t)n + 1);
+    narrow_i64(rp64, Ps.rp, n, s);
+    Ps.ci = out.alloc<int32_t>(padded(nnz));
+    Ps.v = out.alloc<double>(padded(nnz));
+    k_psmooth<true><<<nblocks(n), kBlock, 0, s>>>(n, P.rp, P.ci, P.v, AP.rp, AP.ci, AP.v, dinv, omega, nullptr, Ps.rp,
+                                                  Ps.ci, Ps.v);
+    HIPC(hipGetLastError());
+    P = Ps;
+}
+
+void pfilter(Csr &P, double rho, int nt, const double *W, Pool &out, Pool &tmp, hipStream_t s) {
+    const int n = P.nr;
+    if (nt < 1 || nt > kBamgNt) fail(CAMG_E_ARG, "filter: 1 to 8 test vectors");
+    int32_t *cnt = tmp.alloc<int32_t>(n), *flags = tmp.alloc<int32_t>(3);
+    int32_t *tci = tmp.alloc<int32_t>(padded(P.nnz));
+    double *tvv = tmp.alloc<double>(padded(P.nnz));
+    HIPC(hipMemsetAsync(flags, 0, 3 * sizeof(int32_t), s));
+    k_pfilter<<<n, kWave, 0, s>>>(n, P.rp, P.ci, P.v, rho, nt, W, cnt, tci, tvv, flags);
+    HIPC(hipGetLastError());
+    int32_t hf[3];
+    HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (hf[2]) fail(CAMG_E_ARG, "filter: a row of P has more than 1024 entries");
+    int64_t *rp64 = tmp.alloc<int64_t>((size_t)n + 1);
+    scan_i32_to_i64(cnt, rp64, n, tmp, s);
+    Csr F;
+    F.nr = n;
+    F.nc = P.nc;
+    int64_t fnnz = 0;
+    HIPC(hipMemcpyAsync(&fnnz, rp64 + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    F.nnz = fnnz;
+    F.rp = out.alloc<int32_t>((size_t)n + 1);
+    narrow_i64(rp64, F.rp, n, s);
+    F.ci = out.alloc<int32_t>(padded(F.nnz));
+    F.v = out.alloc<double>(padded(F.nnz));
+    k_compact_rows<<<nblocks(n), kBlock, 0, s>>>(n, P.rp, tci, tvv, F.rp, F.ci, F.v);
+    HIPC(hipGetLastError());
+    P = F;
+}
+
+void fill_ones(int n, double *x, hipStream_t s) {
+    k_fill_ones<<<nblocks(n), kBlock, 0, s>>>(n, x);
     HIPC(hipGetLastError());
 }
 

@@ -37,6 +37,9 @@ CASES = {
     "elasticity_6_rbm_l1": (lambda: PB.elasticity3d(6), lambda: PB.elasticity_rigid_modes(6), {"bamg_lmax": 1}),
     "poisson2d_40_linear": (lambda: PB.poisson2d(40), lambda: _linear2d(40), {}),
     "lognormal3d_16_const": (lambda: PB.lognormal3d(16, 2.0), lambda: np.ones((16 ** 3, 1)), {}),
+    "elasticity_6_rbm_smoothed": (lambda: PB.elasticity3d(6), lambda: PB.elasticity_rigid_modes(6), {"psmooth": 1}),
+    "elasticity_6_rbm_filtered": (lambda: PB.elasticity3d(6), lambda: PB.elasticity_rigid_modes(6),
+                                  {"psmooth": 1, "pfilter": 0.7}),
 }
 
 
@@ -97,3 +100,38 @@ def test_bamg_rejects_dependent_test_space(camg):
     with pytest.raises(camg.CamgError) as e:
         camg.Solver(A, V=np.ones((A.n, 2)), interp=camg.INTERP_BAMG)
     assert e.value.status == camg.E_ARG
+
+
+@pytest.mark.parametrize("name,kw", [("poisson2d_48", {"psmooth": 1, "pfilter": 0.8}),
+                                     ("lognormal3d_16", {"psmooth": 1}),
+                                     ("lognormal3d_16_f", {"psmooth": 1, "pfilter": 0.8, "interp": 2})])
+def test_smoothed_prolongation_without_test_space(camg, name, kw):
+    """Smoothing and filtering of the classical prolongations (the filter
+    compensates on a unit vector): bit-exact hierarchies and solve parity."""
+    print(f"[gpu] smoothed P {name}", flush=True)
+    A = PB.poisson2d(48) if name.startswith("poisson") else PB.lognormal3d(16, 2.0)
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), max_coarse=40, **kw)
+    o = O.Hierarchy(A, max_coarse=40, **kw)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev - 1):
+        gp, op = g.P(l), o.P(l)
+        assert np.array_equal(gp[2], op[2]) and np.array_equal(gp[3], op[3]) and np.array_equal(gp[4], op[4])
+        ga, oa = g.A(l + 1), o.A(l + 1)
+        assert np.array_equal(ga[3], oa[3]) and np.array_equal(ga[4], oa[4])
+    b = PB.rhs(A.n)
+    r, ro = g.solve(b), o.solve(b, 1e-8)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+
+
+def test_over_filtered_prolongation_fails_like_the_oracle(camg):
+    """Filtering to 0.6 of each row can empty a coarse column: the coarse
+    operator then has a zero diagonal, which both sides report as not SPD."""
+    A = PB.lognormal3d(16, 2.0)
+    kw = {"psmooth": 1, "pfilter": 0.6, "interp": 2}
+    with pytest.raises(O.OracleError) as eo:
+        O.Hierarchy(A, max_coarse=40, **kw)
+    with pytest.raises(camg.CamgError) as eg:
+        camg.Solver(A, max_coarse=40, **kw)
+    assert eo.value.status == O.E_NOT_SPD and eg.value.status == camg.E_NOT_SPD
