@@ -29,7 +29,7 @@ class Params(C.Structure):
                 ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("bamg_lmin", C.c_int32), ("bamg_lmax", C.c_int32),
                 ("bamg_eps", C.c_double), ("bamg_mu", C.c_double), ("psmooth", C.c_int32),
-                ("pfilter", C.c_double)]
+                ("pfilter", C.c_double), ("srqm_iters", C.c_int32)]
 
 
 class CsrOut(C.Structure):
@@ -59,6 +59,8 @@ def lib():
         L.orc_psmooth.argtypes = [C.POINTER(CsrOut), vp, dbl, C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_pfilter.argtypes = [C.POINTER(CsrOut), dbl, i32, vp, C.POINTER(CsrOut)]
         L.orc_setup_tv.argtypes = [i32, vp, vp, vp, i32, vp, C.POINTER(Params), C.POINTER(vp)]
+        L.orc_symeig.argtypes = [i32, vp, vp, vp]
+        L.orc_srqm.argtypes = [C.POINTER(CsrOut), vp, C.POINTER(CsrOut), C.POINTER(CsrOut), i32, vp, i32, vp]
         L.orc_transpose.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_spgemm.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_cholesky.argtypes = [i32, vp]
@@ -220,6 +222,40 @@ def pfilter(P, rho, W):
     r = CsrOut()
     assert lib().orc_pfilter(C.byref(op), float(rho), W.shape[1], _p(W), C.byref(r)) == OK
     return _from_out(r)
+
+
+def symeig(Cm):
+    """Eigenvalues and eigenvectors (columns) of a symmetric matrix, m <= 16."""
+    Cm = np.array(Cm, dtype=np.float64, order="C", copy=True)
+    m = Cm.shape[0]
+    lam = np.zeros(m)
+    Q = np.zeros((m, m))
+    st = lib().orc_symeig(m, _p(Cm), _p(lam), _p(Q))
+    if st != OK:
+        raise OracleError(st)
+    return lam, Q
+
+
+def srqm(A, V, iters, dinv=None, G=None):
+    """SRQM refinement of an orthonormal test space V (n x nt) with the
+    preconditioner D^{-1} (dinv) or G^T G (G, a lower CSR).  Returns the new
+    V and the number of steps taken."""
+    oa, ka = _to_out(*_csr_arrays(A))
+    V = np.array(V, dtype=np.float64, order="C", copy=True)
+    n, nt = V.shape
+    done = np.zeros(1, np.int32)
+    if G is not None:
+        og, kg = _to_out(*_csr_arrays(G))
+        ot = CsrOut()
+        assert lib().orc_transpose(C.byref(og), C.byref(ot)) == OK
+        st = lib().orc_srqm(C.byref(oa), None, C.byref(og), C.byref(ot), nt, _p(V), iters, _p(done))
+        lib().orc_csr_free(C.byref(ot))
+    else:
+        d = np.ascontiguousarray(dinv, np.float64)
+        st = lib().orc_srqm(C.byref(oa), _p(d), None, None, nt, _p(V), iters, _p(done))
+    if st != OK:
+        raise OracleError(st)
+    return V, int(done[0])
 
 
 def transpose(X):

@@ -43,6 +43,7 @@ void orc_params_default(orc_params *p) {
     p->bamg_mu = 10.0;
     p->psmooth = 0;
     p->pfilter = 1.0;
+    p->srqm_iters = 0;
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -817,6 +818,213 @@ int orc_pfilter(const orc_csr *P, double rho, int32_t nt, const double *W, orc_c
     return ORC_OK;
 }
 
+/*
+ * Eigen-decomposition C = Q diag(lam) Q^T of a symmetric m x m matrix
+ * (row-major, overwritten) by the cyclic Jacobi method (Golub and Van Loan,
+ * Matrix Computations, the classical symmetric Schur rotation): pairs
+ * (p, q), p < q, are visited row by row; each rotation zeroes C[p][q] with
+ * tau = (c_qq - c_pp) / (2 c_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+ * c = 1 / sqrt(1 + t^2), s = t c, and updates the columns p, q of C, then
+ * its rows p, q, then the columns p, q of Q (Q starts as I).  Sweeps stop
+ * when the sum of squares above the diagonal is at most 1e-30 times the
+ * squared Frobenius norm of the input, or after 60 sweeps.  lam[i] = C[i][i]
+ * and column i of Q is its eigenvector.
+ */
+int orc_symeig(int32_t m, double *C, double *lam, double *Q) {
+    if (m < 1 || m > 2 * ORC_MAXNT) return ORC_E_ARG;
+    double tot = 0.0;
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t j = 0; j < m; ++j) tot = tot + C[i * m + j] * C[i * m + j];
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t j = 0; j < m; ++j) Q[i * m + j] = i == j ? 1.0 : 0.0;
+    for (int32_t sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int32_t p = 0; p < m; ++p)
+            for (int32_t q = p + 1; q < m; ++q) off = off + C[p * m + q] * C[p * m + q];
+        if (!(off > 1e-30 * tot)) break;
+        for (int32_t p = 0; p < m; ++p)
+            for (int32_t q = p + 1; q < m; ++q) {
+                const double apq = C[p * m + q];
+                if (apq == 0.0) continue;
+                const double tau = (C[q * m + q] - C[p * m + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                for (int32_t k = 0; k < m; ++k) {
+                    const double x = C[k * m + p], y = C[k * m + q];
+                    C[k * m + p] = c * x - s * y;
+                    C[k * m + q] = s * x + c * y;
+                }
+                for (int32_t k = 0; k < m; ++k) {
+                    const double x = C[p * m + k], y = C[q * m + k];
+                    C[p * m + k] = c * x - s * y;
+                    C[q * m + k] = s * x + c * y;
+                }
+                for (int32_t k = 0; k < m; ++k) {
+                    const double x = Q[k * m + p], y = Q[k * m + q];
+                    Q[k * m + p] = c * x - s * y;
+                    Q[k * m + q] = s * x + c * y;
+                }
+            }
+    }
+    for (int32_t i = 0; i < m; ++i) lam[i] = C[i * m + i];
+    return ORC_OK;
+}
+
+/* Y = A X for a block of k columns: row i of Y (stride ldy) is the sum, over
+ * the entries of row i of A in order, of a_ij times row j of X (stride ldx). */
+static void csr_block(const orc_csr *A, int32_t k, const double *X, int32_t ldx, double *Y, int32_t ldy) {
+    for (int32_t i = 0; i < A->nrows; ++i) {
+        for (int32_t a = 0; a < k; ++a) Y[(size_t)i * ldy + a] = 0.0;
+        for (int32_t e = A->rp[i]; e < A->rp[i + 1]; ++e) {
+            const double aij = A->val[e];
+            const double *x = X + (size_t)A->ci[e] * ldx;
+            for (int32_t a = 0; a < k; ++a) Y[(size_t)i * ldy + a] = Y[(size_t)i * ldy + a] + aij * x[a];
+        }
+    }
+}
+
+/*
+ * Test-space refinement by simultaneous Rayleigh quotient minimisation
+ * (Section 2, Unveiling the operator near kernel, eq. eigP), preconditioned
+ * with the level's smoother: M^{-1} = D^{-1} (Jacobi; G = NULL) or
+ * M^{-1} = G^T G (FSAI).  The paper fixes the method and the preconditioner,
+ * not the update; read as block preconditioned steepest descent with
+ * Rayleigh-Ritz (the trace of V^T A V is minimised over span[V, W]):
+ *
+ *   X = A V, T = V^T X, R = X - V T, W = M^{-1} R, S = [V W] (n x 2nt),
+ *   Gs = S^T S, Hs = S^T (A S)  (lower triangles, sums over rows in order),
+ *   Cholesky of Gs row by row, leaving out a column of S whose pivot is at
+ *   most 1e-12 times the largest diagonal of Gs (it adds no direction),
+ *   C = L^{-1} Hs L^{-T} on the kept columns, C = Q diag(lam) Q^T,
+ *   the nt smallest lam (the smaller index on ties), Z = L^{-T} Q_sel,
+ *   V = S_kept Z.
+ *
+ * V (n x nt, row-major, orthonormal on input) is updated in place for at
+ * most iters steps; a step in which every column of W is left out ends the
+ * iteration with V unchanged.  *done receives the number of steps taken.
+ */
+int orc_srqm(const orc_csr *A, const double *dinv, const orc_csr *G, const orc_csr *GT, int32_t nt, double *V,
+             int32_t iters, int32_t *done) {
+    *done = 0;
+    if (nt < 1 || nt > ORC_MAXNT || iters < 0) return ORC_E_ARG;
+    const int32_t n = A->nrows, m = 2 * nt;
+    double *S = (double *)malloc(sizeof(double) * ((size_t)n * m + 1));
+    double *AS = (double *)malloc(sizeof(double) * ((size_t)n * m + 1));
+    double *R = (double *)malloc(sizeof(double) * ((size_t)n * nt + 1));
+    double *Y = (double *)malloc(sizeof(double) * ((size_t)n * nt + 1));
+    if (!S || !AS || !R || !Y) { free(S); free(AS); free(R); free(Y); return ORC_E_NOMEM; }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t a = 0; a < nt; ++a) S[(size_t)i * m + a] = V[(size_t)i * nt + a];
+    double T[ORC_MAXNT * ORC_MAXNT];
+    double Gs[4 * ORC_MAXNT * ORC_MAXNT], Hs[4 * ORC_MAXNT * ORC_MAXNT], L[4 * ORC_MAXNT * ORC_MAXNT];
+    double Cm[4 * ORC_MAXNT * ORC_MAXNT], Q[4 * ORC_MAXNT * ORC_MAXNT], lam[2 * ORC_MAXNT];
+    double Z[2 * ORC_MAXNT * ORC_MAXNT];
+    int32_t K[2 * ORC_MAXNT];
+    for (int32_t it = 0; it < iters; ++it) {
+        /* X = A V into the first nt columns of AS */
+        csr_block(A, nt, S, m, AS, m);
+        /* T = V^T X, R = X - V T */
+        for (int32_t a = 0; a < nt; ++a)
+            for (int32_t b = 0; b < nt; ++b) {
+                double s = 0.0;
+                for (int32_t i = 0; i < n; ++i) s = s + S[(size_t)i * m + a] * AS[(size_t)i * m + b];
+                T[a * nt + b] = s;
+            }
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t b = 0; b < nt; ++b) {
+                double r = AS[(size_t)i * m + b];
+                for (int32_t a = 0; a < nt; ++a) r = r - S[(size_t)i * m + a] * T[a * nt + b];
+                R[(size_t)i * nt + b] = r;
+            }
+        /* W = M^{-1} R into the last nt columns of S */
+        if (G) {
+            csr_block(G, nt, R, nt, Y, nt);
+            csr_block(GT, nt, Y, nt, S + nt, m);
+        } else {
+            for (int32_t i = 0; i < n; ++i)
+                for (int32_t b = 0; b < nt; ++b) S[(size_t)i * m + nt + b] = dinv[i] * R[(size_t)i * nt + b];
+        }
+        csr_block(A, nt, S + nt, m, AS + nt, m);
+        /* Gram matrices of the subspace (lower triangles, mirrored) */
+        for (int32_t a = 0; a < m; ++a)
+            for (int32_t b = 0; b <= a; ++b) {
+                double g = 0.0, h = 0.0;
+                for (int32_t i = 0; i < n; ++i) g = g + S[(size_t)i * m + a] * S[(size_t)i * m + b];
+                for (int32_t i = 0; i < n; ++i) h = h + S[(size_t)i * m + a] * AS[(size_t)i * m + b];
+                Gs[a * m + b] = g; Gs[b * m + a] = g;
+                Hs[a * m + b] = h; Hs[b * m + a] = h;
+            }
+        /* Cholesky of Gs, row by row, leaving out dependent columns */
+        double gmax = 0.0;
+        for (int32_t a = 0; a < m; ++a) gmax = Gs[a * m + a] > gmax ? Gs[a * m + a] : gmax;
+        int32_t mk = 0;
+        for (int32_t j = 0; j < m; ++j) {
+            for (int32_t k = 0; k < mk; ++k) {
+                double t = Gs[j * m + K[k]];
+                for (int32_t q = 0; q < k; ++q) t = t - L[mk * m + q] * L[k * m + q];
+                L[mk * m + k] = t / L[k * m + k];
+            }
+            double d = Gs[j * m + j];
+            for (int32_t k = 0; k < mk; ++k) d = d - L[mk * m + k] * L[mk * m + k];
+            if (!(d > 1e-12 * gmax)) continue;
+            L[mk * m + mk] = sqrt(d);
+            K[mk] = j;
+            ++mk;
+        }
+        if (mk <= nt) break;  /* W adds nothing to span V */
+        /* C = L^{-1} Hs L^{-T}: first Cm = L^{-1} Hs (columns by forward
+         * substitution), then C = L^{-1} Cm^T, lower triangle mirrored */
+        for (int32_t c = 0; c < mk; ++c)
+            for (int32_t r = 0; r < mk; ++r) {
+                double t = Hs[K[r] * m + K[c]];
+                for (int32_t q = 0; q < r; ++q) t = t - L[r * m + q] * Cm[q * m + c];
+                Cm[r * m + c] = t / L[r * m + r];
+            }
+        for (int32_t c = 0; c < mk; ++c)
+            for (int32_t r = 0; r < mk; ++r) {
+                double t = Cm[c * m + r];
+                for (int32_t q = 0; q < r; ++q) t = t - L[r * m + q] * Q[q * mk + c];
+                Q[r * mk + c] = t / L[r * m + r];
+            }
+        for (int32_t r = 0; r < mk; ++r)
+            for (int32_t c = 0; c <= r; ++c) {
+                Cm[r * mk + c] = Q[r * mk + c];
+                Cm[c * mk + r] = Q[r * mk + c];
+            }
+        orc_symeig(mk, Cm, lam, Q);
+        /* the nt smallest Ritz values; Z = L^{-T} Q_sel by back substitution */
+        int32_t used[2 * ORC_MAXNT];
+        for (int32_t k = 0; k < mk; ++k) used[k] = 0;
+        for (int32_t b = 0; b < nt; ++b) {
+            int32_t best = -1;
+            for (int32_t k = 0; k < mk; ++k)
+                if (!used[k] && (best < 0 || lam[k] < lam[best])) best = k;
+            used[best] = 1;
+            for (int32_t r = mk - 1; r >= 0; --r) {
+                double t = Q[r * mk + best];
+                for (int32_t q = r + 1; q < mk; ++q) t = t - L[q * m + r] * Z[q * nt + b];
+                Z[r * nt + b] = t / L[r * m + r];
+            }
+        }
+        /* V = S_kept Z */
+        for (int32_t i = 0; i < n; ++i) {
+            double row[2 * ORC_MAXNT];
+            for (int32_t k = 0; k < mk; ++k) row[k] = S[(size_t)i * m + K[k]];
+            for (int32_t b = 0; b < nt; ++b) {
+                double t = 0.0;
+                for (int32_t k = 0; k < mk; ++k) t = t + row[k] * Z[k * nt + b];
+                S[(size_t)i * m + b] = t;
+            }
+        }
+        *done = it + 1;
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t a = 0; a < nt; ++a) V[(size_t)i * nt + a] = S[(size_t)i * m + a];
+    free(S); free(AS); free(R); free(Y);
+    return ORC_OK;
+}
+
 /* X^T by counting sort on the column index; rows of the result list their
  * columns in ascending order.  The restriction is R = P^T (eq. AcDef). */
 int orc_transpose(const orc_csr *X, orc_csr *XT) {
@@ -1147,6 +1355,7 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
     if (st != ORC_OK) return st;
     int bamg = prm && prm->interp == ORC_INTERP_BAMG;
     if (bamg && (nt < 1 || nt > ORC_MAXNT || !V)) return ORC_E_ARG;
+    if (prm && (prm->srqm_iters < 0 || prm->srqm_iters > 100 || (prm->srqm_iters > 0 && !bamg))) return ORC_E_ARG;
     double *TV = NULL;
     if (bamg) {
         TV = (double *)malloc(sizeof(double) * (size_t)n * nt);
@@ -1190,6 +1399,15 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
             L->omega = h->prm.omega > 0.0 ? h->prm.omega : w;
         } else {
             L->omega = h->prm.omega > 0.0 ? h->prm.omega : orc_gershgorin_omega(nl, arp, aci, av);
+        }
+        if (bamg && l == 0 && h->prm.srqm_iters > 0) {
+            /* refine the level-0 test space with the smoother just built,
+             * then take an orthonormal basis of it again */
+            int32_t done = 0;
+            const int fs = h->prm.smoother == ORC_SMOOTH_FSAI;
+            st = orc_srqm(&L->A, L->dinv, fs ? &L->G : NULL, fs ? &L->GT : NULL, nt, TV, h->prm.srqm_iters, &done);
+            if (!st) st = orc_orthonormalize(nl, nt, TV);
+            if (st) { orc_destroy(h); return st; }
         }
         orc_strength(nl, arp, aci, av, h->prm.theta, L->strong, L->stcnt);
         st = orc_pmis(nl, arp, aci, L->strong, L->stcnt, h->prm.seed, l, L->cf, &L->rounds);

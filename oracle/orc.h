@@ -51,6 +51,7 @@ typedef struct {
     double   bamg_eps, bamg_mu;     /* BAMG: accept when relative residual <= eps and ||w|| <= mu */
     int32_t  psmooth;     /* 1: one Jacobi step on P (P - omega D^{-1} A P) */
     double   pfilter;     /* < 1: filter P, keeping this fraction of each row's absolute sum */
+    int32_t  srqm_iters;  /* BAMG: SRQM steps refining the level-0 test space (0: none) */
 } orc_params;
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
 enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3,
@@ -81,6 +82,11 @@ int  orc_bamg(int32_t n, const int32_t *rp, const int32_t *ci, const uint8_t *st
 /* prolongation smoothing P - omega D^{-1} A P, and filtering with compensation on W (nc x nt) */
 int  orc_psmooth(const orc_csr *A, const double *dinv, double omega, const orc_csr *P, orc_csr *Ps);
 int  orc_pfilter(const orc_csr *P, double rho, int32_t nt, const double *W, orc_csr *Pf);
+/* eigen-decomposition of a symmetric m x m matrix (m <= 2 ORC_MAXNT; C overwritten) by cyclic Jacobi */
+int  orc_symeig(int32_t m, double *C, double *lam, double *Q);
+/* SRQM refinement of an orthonormal test space V (n x nt, in place) with M^{-1} = D^{-1}, or G^T G if G */
+int  orc_srqm(const orc_csr *A, const double *dinv, const orc_csr *G, const orc_csr *GT, int32_t nt, double *V,
+              int32_t iters, int32_t *done);
 int  orc_transpose(const orc_csr *X, orc_csr *XT);
 int  orc_spgemm(const orc_csr *X, const orc_csr *Y, orc_csr *Z);
 int  orc_cholesky(int32_t n, double *a);      /* in: dense SPD row-major; out: L in the lower triangle */

@@ -1,7 +1,7 @@
 """Plant plausible mistakes in a copy of the oracle source and check that
-the pins in test_oracle.py, test_oracle_fsai.py, test_oracle_interp.py and
-test_oracle_bamg.py catch every one of
-them (CPU only)."""
+the pins in test_oracle.py, test_oracle_fsai.py, test_oracle_interp.py,
+test_oracle_bamg.py and test_oracle_srqm.py catch every one of them (CPU
+only)."""
 import os
 import subprocess
 import sys
@@ -78,10 +78,24 @@ MUTATIONS = [
     ("bamg_pfilter_compensation_sign", "val[o] = pv[t] + d;", "val[o] = pv[t] - d;"),
     ("bamg_coarse_space_not_injected",
      "memmove(TV + (size_t)c * nt, TV + (size_t)i * nt, sizeof(double) * (size_t)nt);", "(void)i;"),
+    ("srqm_residual_sign", "for (int32_t a = 0; a < nt; ++a) r = r - S[(size_t)i * m + a] * T[a * nt + b];",
+     "for (int32_t a = 0; a < nt; ++a) r = r + S[(size_t)i * m + a] * T[a * nt + b];"),
+    ("srqm_no_preconditioner", "S[(size_t)i * m + nt + b] = dinv[i] * R[(size_t)i * nt + b];",
+     "S[(size_t)i * m + nt + b] = R[(size_t)i * nt + b];"),
+    ("srqm_largest_ritz_values", "if (!used[k] && (best < 0 || lam[k] < lam[best])) best = k;",
+     "if (!used[k] && (best < 0 || lam[k] > lam[best])) best = k;"),
+    ("srqm_back_substitution_no_division", "Z[r * nt + b] = t / L[r * m + r];", "Z[r * nt + b] = t;"),
+    ("srqm_gram_wrong_operand",
+     "for (int32_t i = 0; i < n; ++i) h = h + S[(size_t)i * m + a] * AS[(size_t)i * m + b];",
+     "for (int32_t i = 0; i < n; ++i) h = h + S[(size_t)i * m + a] * S[(size_t)i * m + b];"),
+    ("srqm_keeps_dependent_columns", "if (!(d > 1e-12 * gmax)) continue;", "if (!(d > 0.0)) continue;"),
+    ("srqm_symeig_rotation_sign", "const double s = t * c;", "const double s = -t * c;"),
+    ("srqm_fsai_G_twice", "csr_block(GT, nt, Y, nt, S + nt, m);", "csr_block(G, nt, Y, nt, S + nt, m);"),
 ]
 
 
-PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py", "test_oracle_bamg.py"]
+PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py", "test_oracle_bamg.py",
+             "test_oracle_srqm.py"]
 
 
 def _first_file(name):
@@ -93,6 +107,8 @@ def _first_file(name):
         return "test_oracle_interp.py"
     if name.startswith("bamg_"):
         return "test_oracle_bamg.py"
+    if name.startswith("srqm_"):
+        return "test_oracle_srqm.py"
     return "test_oracle.py"
 
 
