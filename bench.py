@@ -520,9 +520,10 @@ def serve_run(rates, seconds, budget_gb=32.0, slots=16, seed=2021):
 def bamg_run(ne):
     """Q1 elasticity on ne^3 elements (b ~ U[-1, 1]): set-up and solve to
     rtol 1e-8 with direct interpolation, then with BAMG interpolation over
-    the six rigid body modes (FP64 and mixed; and mixed with the
-    prolongation smoothed and filtered to rho = 0.7).  Each configuration
-    runs once untimed, then once timed.  (The FSAI smoother is not paired
+    the six rigid body modes (FP64 and mixed; mixed with the prolongation
+    smoothed and filtered to rho = 0.7; mixed with 3 SRQM steps on the
+    modes), then from six random vectors with and without 10 SRQM steps.
+    Each configuration runs once untimed, then once timed.  (The FSAI smoother is not paired
     with BAMG here: BAMG's coarse levels have rows beyond its 192-entry
     limit.)"""
     import numpy as np
@@ -566,10 +567,20 @@ def bamg_run(ne):
                                 ("bamg_fp64", camg.FP64, True, camg.SMOOTH_JACOBI),
                                 ("direct_mixed", camg.MIXED_FP32, False, camg.SMOOTH_JACOBI),
                                 ("bamg_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
-                                ("bamg_psmooth_filter_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI)):
+                                ("bamg_psmooth_filter_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
+                                ("bamg_srqm3_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI)):
         extra = {"psmooth": 1, "pfilter": 0.7} if "psmooth" in key else {}
+        if "srqm" in key:
+            extra["srqm_iters"] = 3
         run(prec, bamg, sm, **extra)
         out[key] = run(prec, bamg, sm, **extra)
+        print(f"[elasticity {ne}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
+    # without a known near kernel: six seeded N(0, 1) vectors, as given and
+    # after 10 SRQM steps
+    dV.copy_(torch.from_numpy(np.random.default_rng(0).standard_normal((A.n, 6))).to(dev))
+    for key, k in (("bamg_random_mixed", 0), ("bamg_random_srqm10_mixed", 10)):
+        run(camg.MIXED_FP32, True, camg.SMOOTH_JACOBI, srqm_iters=k)
+        out[key] = run(camg.MIXED_FP32, True, camg.SMOOTH_JACOBI, srqm_iters=k)
         print(f"[elasticity {ne}^3] {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 

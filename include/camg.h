@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 3
+#define CAMG_ABI_VERSION 4
 
 typedef struct camg_hier *camg_handle;
 
@@ -79,6 +79,15 @@ enum { CAMG_INTERP_DIRECT = 0, CAMG_INTERP_CLASSICAL = 1, CAMG_INTERP_EXTI = 2, 
  * most 2 here).  The test space is made orthonormal on level 0 and taken at
  * the C points on coarser levels.  Rows have at most 128 candidates
  * (CAMG_E_ARG otherwise). */
+/* SRQM refinement (Section 2, the passage on unveiling the near kernel, eq.
+ * eigP), camg_params.srqm_iters > 0, BAMG only: after the level-0 smoother is
+ * built, each step takes the orthonormal test space V, the residual
+ * R = A V - V (V^T A V) and W = M^{-1} R (M^{-1} = D^{-1} for Jacobi, G^T G for
+ * FSAI), and replaces V by the nt Ritz vectors of A with the smallest Ritz
+ * values on span[V, W] (columns of W that add no direction, pivot <= 1e-12 of
+ * the largest Gram diagonal, are left out; a step where all are left out ends
+ * the refinement).  The result is made orthonormal again.  The small dense
+ * eigenproblem (at most 16 x 16) is solved on the device by cyclic Jacobi. */
 
 /* Hierarchy and solver parameters. */
 typedef struct {
@@ -108,6 +117,8 @@ typedef struct {
                              fraction of the row's absolute sum and move the dropped entries' action on the
                              coarse test space (a unit vector without one) onto the kept entries by a
                              minimum-norm correction; default 1 (off) */
+    int32_t  srqm_iters;  /* BAMG: steps of simultaneous Rayleigh quotient minimisation refining the level-0
+                             test space before it is used (0 to 100; default 0); see camg_setup_tv */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32

@@ -42,7 +42,7 @@ class camg_params(C.Structure):
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("rap_chunk", C.c_int64), ("bamg_lmin", C.c_int32),
                 ("bamg_lmax", C.c_int32), ("bamg_eps", C.c_double), ("bamg_mu", C.c_double),
-                ("psmooth", C.c_int32), ("pfilter", C.c_double)]
+                ("psmooth", C.c_int32), ("pfilter", C.c_double), ("srqm_iters", C.c_int32)]
 
 
 class camg_info_t(C.Structure):

@@ -178,6 +178,9 @@ void check_params(const camg_params &p) {
     if (p.rap_chunk < 0) fail(CAMG_E_ARG, "rap_chunk must be >= 0");
     if (p.psmooth != 0 && p.psmooth != 1) fail(CAMG_E_ARG, "psmooth must be 0 or 1");
     if (!(p.pfilter > 0.0)) fail(CAMG_E_ARG, "pfilter must be > 0");
+    if (p.srqm_iters < 0 || p.srqm_iters > 100) fail(CAMG_E_ARG, "srqm_iters must lie in [0, 100]");
+    if (p.srqm_iters > 0 && p.interp != CAMG_INTERP_BAMG)
+        fail(CAMG_E_ARG, "srqm_iters refines the BAMG test space: it needs CAMG_INTERP_BAMG");
 }
 
 // ---------------------------------------------------------------- set-up
@@ -347,6 +350,13 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
                 spgemm(GA, Gt, M, lt, lt, s);
                 L.omega = (4.0 / 3.0) / cw_bound(M, lt, s);
             }
+        }
+        if (prm.interp == CAMG_INTERP_BAMG && l == 0 && prm.srqm_iters > 0) {
+            // refine the level-0 test space with the smoother just built
+            // (counted in the smoother phase), then make it orthonormal again
+            const bool fs = prm.smoother == CAMG_SMOOTH_FSAI;
+            srqm(L.A, L.dinv, fs ? &L.G : nullptr, fs ? &L.Gt : nullptr, nt, tv, prm.srqm_iters, lt, s);
+            bamg_orthonormalize(nl, nt, tv, lt, s);
         }
         phase(1);
         // strength and PMIS
@@ -935,6 +945,7 @@ void camg_params_default(camg_params *p) {
     p->bamg_mu = 10.0;
     p->psmooth = 0;
     p->pfilter = 1.0;
+    p->srqm_iters = 0;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt,

@@ -222,6 +222,10 @@ void bamg_rows(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int
                int32_t *flags, hipStream_t s);
 void bamg_compact(int n, int nt, const int32_t *tci, const double *tv, const Csr &P, hipStream_t s);
 void bamg_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap, const double *V, double *Vc, hipStream_t s);
+// SRQM refinement of the orthonormal test space V (n x nt, in place) with
+// M^{-1} = D^{-1} (G null) or G^T G; at most iters steps
+void srqm(const Csr &A, const double *dinv, const Csr *G, const Csr *Gt, int nt, double *V, int iters, Pool &tmp,
+          hipStream_t s);
 // Prolongation smoothing P <- P - omega D^{-1} (A P), and filtering of P
 // with compensation on the coarse test space W (n_c x nt); the new P is
 // allocated from `out`.

@@ -1591,17 +1591,6 @@ __global__ void __launch_bounds__(WPB * TPR)
 // triangular solve) run on one lane.
 constexpr int kBamgNt = 8, kBamgRaw = 1024, kBamgCand = 128;
 
-// Gram matrix of V: one thread per entry (a, b), b <= a, rows in index order
-__global__ void k_gram(int n, int nt, const double *V, double *G) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt * nt) return;
-    const int a = t / nt, b = t % nt;
-    if (b > a) return;
-    double s = 0.0;
-    for (int r = 0; r < n; ++r) s = s + V[(size_t)r * nt + a] * V[(size_t)r * nt + b];
-    G[a * nt + b] = s;
-}
-
 struct BamgL {
     double l[kBamgNt * kBamgNt];
 };
@@ -1834,6 +1823,328 @@ __global__ void k_gather_tv(int n, int nt, const int8_t *cf, const int64_t *cmap
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || cf[i] != kC) return;
     for (int a = 0; a < nt; ++a) Vc[(size_t)cmap[i] * nt + a] = V[(size_t)i * nt + a];
+}
+
+// ---------------------------------------------------------------- SRQM
+// Test-space refinement by simultaneous Rayleigh quotient minimisation
+// (Section 2, near-kernel passage, eq. eigP) with the smoother as
+// preconditioner: V <- the nt lowest Ritz vectors of A on span[V, M^{-1} R],
+// R = A V - V (V^T A V).  Every sum runs in the CPU reference's order (rows
+// of a Gram matrix in index order, the entries of a CSR row in order), so
+// the refined space is bitwise the reference's.
+
+constexpr int kSrqmM = 2 * kBamgNt;  // columns of the subspace [V W]
+
+// Y (row stride ldy) = A X (row stride ldx) for k <= 8 columns, one thread per
+// (row, column): the k threads of a row share its entries' loads and read
+// neighbouring X values, and each sum runs over the row's entries in order
+__global__ void k_csr_block(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const double *__restrict__ v, int k, const double *__restrict__ X, int ldx,
+                            double *__restrict__ Y, int ldy) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)n * k) return;
+    const int i = (int)(t / k), a = (int)(t % k);
+    double acc = 0.0;
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e) acc = acc + v[e] * X[(size_t)ci[e] * ldx + a];
+    Y[(size_t)i * ldy + a] = acc;
+}
+
+// Gram products G[a * ldg + b] = sum over the rows r = 0..n-1, in order, of
+// X[r ldx + a] Y[r ldy + b] (a < ma, b < mb, ma, mb <= 16; only b <= a when
+// lower).  The order is fixed, so each sum is one thread's, and the chain of
+// n dependent FP64 adds bounds the kernel (about 15 ns per row); the workgroup
+// stages 240-row tiles of X and Y in LDS column by column (a padded stride
+// keeps 16-byte reads of different columns in different banks), and the
+// next tile's loads are in flight while the threads add the current one.
+// blockIdx.x selects (Y, G) or (Y2, G2): two products share a launch.
+constexpr int kGramRows = 240, kGramThreads = 1024, kGramCols = 16, kGramLd = kGramRows + 2;
+constexpr int kGramLoads = (kGramRows * kGramCols + kGramThreads - 1) / kGramThreads;  // per thread and tile
+
+__global__ void __launch_bounds__(kGramThreads)
+    k_gram_tiled(int n, int ma, int mb, int lower, const double *__restrict__ X, int ldx, const double *Y,
+                 const double *Y2, int ldy, double *G, double *G2, int ldg) {
+    __shared__ __align__(16) double xs[kGramCols * kGramLd];
+    __shared__ __align__(16) double ys[kGramCols * kGramLd];
+    if (blockIdx.x == 1) {
+        Y = Y2;
+        G = G2;
+    }
+    const int tid = threadIdx.x;
+    int a = -1, b = 0;
+    const int npairs = lower ? ma * (ma + 1) / 2 : ma * mb;
+    if (tid < npairs) {
+        if (lower) {  // pairs (0,0), (1,0), (1,1), (2,0), ...
+            int t = tid;
+            a = 0;
+            while (t > a) {
+                t -= a + 1;
+                ++a;
+            }
+            b = t;
+        } else {
+            a = tid / mb;
+            b = tid % mb;
+        }
+    }
+    // this thread's tile elements: row and column within the tile, the same
+    // for every tile
+    int xr_[kGramLoads], xc_[kGramLoads], yr_[kGramLoads], yc_[kGramLoads];
+#pragma unroll
+    for (int k = 0; k < kGramLoads; ++k) {
+        const int e = tid + k * kGramThreads;
+        xr_[k] = e / ma;
+        xc_[k] = e % ma;
+        yr_[k] = e / mb;
+        yc_[k] = e % mb;
+    }
+    // every thread loads (rows past the matrix are clamped to its last row
+    // and not stored), so the loads issue back to back
+    double px[kGramLoads], py[kGramLoads];
+    auto load = [&](int r0) {
+#pragma unroll
+        for (int k = 0; k < kGramLoads; ++k) {
+            px[k] = X[(size_t)min(r0 + xr_[k], n - 1) * ldx + xc_[k]];
+            py[k] = Y[(size_t)min(r0 + yr_[k], n - 1) * ldy + yc_[k]];
+        }
+    };
+    auto stage = [&](int rows) {
+#pragma unroll
+        for (int k = 0; k < kGramLoads; ++k) {
+            if (xr_[k] < rows) xs[xc_[k] * kGramLd + xr_[k]] = px[k];
+            if (yr_[k] < rows) ys[yc_[k] * kGramLd + yr_[k]] = py[k];
+        }
+    };
+    double s = 0.0;
+    auto add_tile = [&](int rows) {
+        if (a < 0) return;
+        // 16 rows' products are formed first (independent of each other, two
+        // rows per 16-byte read), then added in row order
+        const double *xr = xs + a * kGramLd, *yr = ys + b * kGramLd;
+        const double2 *x2 = reinterpret_cast<const double2 *>(xr);
+        const double2 *y2 = reinterpret_cast<const double2 *>(yr);
+        int r = 0;
+        for (; r + 16 <= rows; r += 16) {
+            double pv[16];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double2 xv = x2[(r >> 1) + u], yv = y2[(r >> 1) + u];
+                pv[2 * u] = xv.x * yv.x;
+                pv[2 * u + 1] = xv.y * yv.y;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s = s + pv[u];
+        }
+        for (; r < rows; ++r) s = s + xr[r] * yr[r];
+    };
+    if (n > 0) load(0);
+    for (int r0 = 0; r0 < n; r0 += kGramRows) {
+        const int rows = min(kGramRows, n - r0);
+        stage(rows);
+        __syncthreads();
+        if (r0 + kGramRows < n) load(r0 + kGramRows);
+        add_tile(rows);
+        __syncthreads();
+    }
+    if (a >= 0) G[a * ldg + b] = s;
+}
+
+// R = X - V T per row (V, X: the first nt columns of S and AS, stride m);
+// out (stride ldo) = dinv[r] R (Jacobi) or R (dinv null)
+__global__ void k_srqm_resid(int n, int nt, int m, const double *__restrict__ S, const double *__restrict__ AS,
+                             const double *__restrict__ T, const double *__restrict__ dinv, double *__restrict__ out,
+                             int ldo) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double vr[kBamgNt];
+#pragma unroll
+    for (int a = 0; a < kBamgNt; ++a) vr[a] = a < nt ? S[(size_t)i * m + a] : 0.0;
+    const double d = dinv ? dinv[i] : 1.0;
+#pragma unroll
+    for (int b = 0; b < kBamgNt; ++b) {
+        if (b >= nt) break;
+        double r = AS[(size_t)i * m + b];
+#pragma unroll
+        for (int a = 0; a < kBamgNt; ++a)
+            if (a < nt) r = r - vr[a] * T[a * nt + b];
+        out[(size_t)i * ldo + b] = dinv ? d * r : r;
+    }
+}
+
+// The Rayleigh-Ritz step on the Gram matrices Gs = S^T S and Hs = S^T A S
+// (lower triangles, m = 2 nt), one wavefront:
+//   up-looking Cholesky of Gs leaving out columns with pivot <= 1e-12 of the
+//   largest diagonal (lane 0); C = L^{-1} Hs L^{-T} (a lane per column);
+//   cyclic Jacobi on C (a lane per row / column of each rotation); the nt
+//   smallest eigenvalues (smaller index on ties) and Z = L^{-T} Q_sel (a lane
+//   per column).  Out: kept columns K[0..mk), Z (mk x nt), mk (*mko).
+__global__ void __launch_bounds__(kWave) k_srqm_rr(int nt, const double *__restrict__ Gs,
+                                                   const double *__restrict__ Hs, int32_t *__restrict__ Ko,
+                                                   double *__restrict__ Zo, int32_t *__restrict__ mko) {
+    constexpr int M = kSrqmM;
+    __shared__ double g[M * M], h[M * M], L[M * M], Cm[M * M], C[M * M], Q[M * M], lam[M];
+    __shared__ int K[M], sel[kBamgNt];
+    __shared__ int mk_s, go;
+    __shared__ double tot_s;
+    const int lane = threadIdx.x;
+    const int m = 2 * nt;
+    for (int t = lane; t < m * m; t += kWave) {
+        const int a = t / m, b = t % m;
+        const int lo = a >= b ? a * m + b : b * m + a;  // the lower-triangle entry
+        g[t] = Gs[lo];
+        h[t] = Hs[lo];
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double gmax = 0.0;
+        for (int a = 0; a < m; ++a) gmax = g[a * m + a] > gmax ? g[a * m + a] : gmax;
+        int mk = 0;
+        for (int j = 0; j < m; ++j) {
+            for (int k = 0; k < mk; ++k) {
+                double t = g[j * m + K[k]];
+                for (int q = 0; q < k; ++q) t = t - L[mk * M + q] * L[k * M + q];
+                L[mk * M + k] = t / L[k * M + k];
+            }
+            double d = g[j * m + j];
+            for (int k = 0; k < mk; ++k) d = d - L[mk * M + k] * L[mk * M + k];
+            if (!(d > 1e-12 * gmax)) continue;
+            L[mk * M + mk] = sqrt(d);
+            K[mk] = j;
+            ++mk;
+        }
+        mk_s = mk;
+        *mko = mk;
+        for (int k = 0; k < mk; ++k) Ko[k] = K[k];
+    }
+    __syncthreads();
+    const int mk = mk_s;
+    if (mk <= nt) return;  // W adds no direction: the caller stops
+    // Cm = L^{-1} H' (H' = Hs on the kept columns), one column per lane
+    if (lane < mk) {
+        const int c = lane;
+        for (int r = 0; r < mk; ++r) {
+            double t = h[K[r] * m + K[c]];
+            for (int q = 0; q < r; ++q) t = t - L[r * M + q] * Cm[q * M + c];
+            Cm[r * M + c] = t / L[r * M + r];
+        }
+    }
+    __syncthreads();
+    // Q = L^{-1} Cm^T (temporary), one column per lane
+    if (lane < mk) {
+        const int c = lane;
+        for (int r = 0; r < mk; ++r) {
+            double t = Cm[c * M + r];
+            for (int q = 0; q < r; ++q) t = t - L[r * M + q] * Q[q * M + c];
+            Q[r * M + c] = t / L[r * M + r];
+        }
+    }
+    __syncthreads();
+    for (int t = lane; t < mk * mk; t += kWave) {
+        const int r = t / mk, c = t % mk;
+        C[r * M + c] = r >= c ? Q[r * M + c] : Q[c * M + r];
+    }
+    __syncthreads();
+    for (int t = lane; t < mk * mk; t += kWave) {
+        const int r = t / mk, c = t % mk;
+        Q[r * M + c] = r == c ? 1.0 : 0.0;
+    }
+    if (lane == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < mk; ++i)
+            for (int j = 0; j < mk; ++j) tot = tot + C[i * M + j] * C[i * M + j];
+        tot_s = tot;
+    }
+    __syncthreads();
+    // cyclic Jacobi (Golub and Van Loan's symmetric Schur rotation)
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (lane == 0) {
+            double off = 0.0;
+            for (int p = 0; p < mk; ++p)
+                for (int q = p + 1; q < mk; ++q) off = off + C[p * M + q] * C[p * M + q];
+            go = off > 1e-30 * tot_s;
+        }
+        __syncthreads();
+        if (!go) break;
+        for (int p = 0; p < mk; ++p)
+            for (int q = p + 1; q < mk; ++q) {
+                const double apq = C[p * M + q];
+                if (apq == 0.0) continue;  // uniform: every lane reads the same value
+                const double tau = (C[q * M + q] - C[p * M + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                __syncthreads();
+                if (lane < mk) {
+                    const int k = lane;
+                    const double x = C[k * M + p], y = C[k * M + q];
+                    C[k * M + p] = c * x - s * y;
+                    C[k * M + q] = s * x + c * y;
+                }
+                __syncthreads();
+                if (lane < mk) {
+                    const int k = lane;
+                    const double x = C[p * M + k], y = C[q * M + k];
+                    C[p * M + k] = c * x - s * y;
+                    C[q * M + k] = s * x + c * y;
+                    const double u = Q[k * M + p], w = Q[k * M + q];
+                    Q[k * M + p] = c * u - s * w;
+                    Q[k * M + q] = s * u + c * w;
+                }
+                __syncthreads();
+            }
+    }
+    if (lane == 0) {
+        for (int i = 0; i < mk; ++i) lam[i] = C[i * M + i];
+        bool used[M];
+        for (int k = 0; k < mk; ++k) used[k] = false;
+        for (int b = 0; b < nt; ++b) {
+            int best = -1;
+            for (int k = 0; k < mk; ++k)
+                if (!used[k] && (best < 0 || lam[k] < lam[best])) best = k;
+            used[best] = true;
+            sel[b] = best;
+        }
+    }
+    __syncthreads();
+    // Z = L^{-T} Q_sel, one column per lane (back substitution)
+    if (lane < nt) {
+        const int b = lane, best = sel[b];
+        double z[M];
+        for (int r = mk - 1; r >= 0; --r) {
+            double t = Q[r * M + best];
+            for (int q = r + 1; q < mk; ++q) t = t - L[q * M + r] * z[q];
+            z[r] = t / L[r * M + r];
+        }
+        for (int r = 0; r < mk; ++r) Zo[r * nt + b] = z[r];
+    }
+}
+
+// V = S_kept Z per row, written over the first nt columns of S
+__global__ void k_srqm_combine(int n, int nt, int m, const int32_t *__restrict__ K, const int32_t *__restrict__ mkp,
+                               const double *__restrict__ Z, double *__restrict__ S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int mk = *mkp;
+    double row[kSrqmM];
+#pragma unroll
+    for (int k = 0; k < kSrqmM; ++k) row[k] = k < mk ? S[(size_t)i * m + K[k]] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kBamgNt; ++b) {
+        if (b >= nt) break;
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSrqmM; ++k)
+            if (k < mk) t = t + row[k] * Z[k * nt + b];
+        S[(size_t)i * m + b] = t;
+    }
+}
+
+// Y (stride ldy, k columns) = X (stride ldx)
+__global__ void k_copy_block(int n, int k, const double *__restrict__ X, int ldx, double *__restrict__ Y, int ldy) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)n * k) return;
+    const size_t r = t / k, a = t % k;
+    Y[r * ldy + a] = X[r * ldx + a];
 }
 
 // ---------------------------------------------------------------- P smoothing and filtering
@@ -2269,7 +2580,7 @@ void xi_fill(int n, const Csr &A, const uint8_t *strong, const int8_t *cf, int v
 void bamg_orthonormalize(int n, int nt, double *V, Pool &tmp, hipStream_t s) {
     if (nt < 1 || nt > kBamgNt) fail(CAMG_E_ARG, "test space: 1 to 8 vectors");
     double *G = tmp.alloc<double>((size_t)nt * nt);
-    k_gram<<<1, 64, 0, s>>>(n, nt, V, G);
+    k_gram_tiled<<<1, kGramThreads, 0, s>>>(n, nt, nt, 1, V, nt, V, nullptr, nt, G, nullptr, nt);
     HIPC(hipGetLastError());
     double g[kBamgNt * kBamgNt];
     HIPC(hipMemcpyAsync(g, G, sizeof(double) * nt * nt, hipMemcpyDeviceToHost, s));
@@ -2405,4 +2716,41 @@ int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s) {
     return h;
 }
 
+
+void srqm(const Csr &A, const double *dinv, const Csr *G, const Csr *Gt, int nt, double *V, int iters, Pool &tmp,
+          hipStream_t s) {
+    const int n = A.nr, m = 2 * nt;
+    if (nt < 1 || nt > kBamgNt) fail(CAMG_E_ARG, "SRQM: 1 to 8 test vectors");
+    double *S = tmp.alloc<double>((size_t)n * m), *AS = tmp.alloc<double>((size_t)n * m);
+    double *R = G ? tmp.alloc<double>((size_t)n * nt) : nullptr;
+    double *Y = G ? tmp.alloc<double>((size_t)n * nt) : nullptr;
+    double *T = tmp.alloc<double>(kBamgNt * kBamgNt);
+    double *Gs = tmp.alloc<double>(kSrqmM * kSrqmM), *Hs = tmp.alloc<double>(kSrqmM * kSrqmM);
+    double *Z = tmp.alloc<double>(kSrqmM * kBamgNt);
+    int32_t *K = tmp.alloc<int32_t>(kSrqmM + 1);  // kept columns, then their count
+    const unsigned nb = (unsigned)(((size_t)n * nt + kBlock - 1) / kBlock);  // blocks for n x nt threads
+    k_copy_block<<<nb, kBlock, 0, s>>>(n, nt, V, nt, S, m);
+    for (int it = 0; it < iters; ++it) {
+        k_csr_block<<<nb, kBlock, 0, s>>>(n, A.rp, A.ci, A.v, nt, S, m, AS, m);
+        k_gram_tiled<<<1, kGramThreads, 0, s>>>(n, nt, nt, 0, S, m, AS, nullptr, m, T, nullptr, nt);
+        if (G) {
+            k_srqm_resid<<<nblocks(n), kBlock, 0, s>>>(n, nt, m, S, AS, T, nullptr, R, nt);
+            k_csr_block<<<nb, kBlock, 0, s>>>(n, G->rp, G->ci, G->v, nt, R, nt, Y, nt);
+            k_csr_block<<<nb, kBlock, 0, s>>>(n, Gt->rp, Gt->ci, Gt->v, nt, Y, nt, S + nt, m);
+        } else {
+            k_srqm_resid<<<nblocks(n), kBlock, 0, s>>>(n, nt, m, S, AS, T, dinv, S + nt, m);
+        }
+        k_csr_block<<<nb, kBlock, 0, s>>>(n, A.rp, A.ci, A.v, nt, S + nt, m, AS + nt, m);
+        k_gram_tiled<<<2, kGramThreads, 0, s>>>(n, m, m, 1, S, m, S, AS, m, Gs, Hs, m);
+        k_srqm_rr<<<1, kWave, 0, s>>>(nt, Gs, Hs, K, Z, K + kSrqmM);
+        HIPC(hipGetLastError());
+        int32_t mk = 0;
+        HIPC(hipMemcpyAsync(&mk, K + kSrqmM, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        if (mk <= nt) break;  // W adds no direction: V stays
+        k_srqm_combine<<<nblocks(n), kBlock, 0, s>>>(n, nt, m, K, K + kSrqmM, Z, S);
+    }
+    k_copy_block<<<nb, kBlock, 0, s>>>(n, nt, S, m, V, nt);
+    HIPC(hipGetLastError());
+}
 }  // namespace camg

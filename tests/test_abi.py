@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 3
+    assert lib.camg_abi_version() == 4
     for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -69,7 +69,8 @@ def test_argument_errors_without_device(lib):
 
 @pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 2), ("theta", 1.5),
                                          ("precision", 3), ("rap_chunk", -1), ("interp", 5),
-                                         ("psmooth", 2), ("pfilter", 0.0)])
+                                         ("psmooth", 2), ("pfilter", 0.0), ("srqm_iters", -1),
+                                         ("srqm_iters", 101), ("srqm_iters", 1)])
 def test_bad_parameters_rejected_without_device(lib, field, value):
     # parameters are checked before the device is touched
     rp = np.array([0, 1], np.int32)
@@ -94,8 +95,9 @@ int main(void) {
   printf("params %zu %zu %zu %zu %zu %zu %zu\n", sizeof(camg_params), offsetof(camg_params, omega),
          offsetof(camg_params, precision), offsetof(camg_params, max_iter), offsetof(camg_params, smoother),
          offsetof(camg_params, interp), offsetof(camg_params, rap_chunk));
-  printf("bamg %zu %zu %zu %zu %zu\n", offsetof(camg_params, bamg_lmin), offsetof(camg_params, bamg_eps),
-         offsetof(camg_params, bamg_mu), offsetof(camg_params, psmooth), offsetof(camg_params, pfilter));
+  printf("bamg %zu %zu %zu %zu %zu %zu\n", offsetof(camg_params, bamg_lmin), offsetof(camg_params, bamg_eps),
+         offsetof(camg_params, bamg_mu), offsetof(camg_params, psmooth), offsetof(camg_params, pfilter),
+         offsetof(camg_params, srqm_iters));
   printf("info %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
          offsetof(camg_info_t, setup_phase_ms));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
@@ -111,7 +113,7 @@ int main(void) {
     assert out["params"] == [C.sizeof(P), P.omega.offset, P.precision.offset, P.max_iter.offset, P.smoother.offset,
                              P.interp.offset, P.rap_chunk.offset]
     assert out["bamg"] == [P.bamg_lmin.offset, P.bamg_eps.offset, P.bamg_mu.offset, P.psmooth.offset,
-                           P.pfilter.offset]
+                           P.pfilter.offset, P.srqm_iters.offset]
     I = camg.camg_info_t
     assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset]
     Q = camg.camg_completion
