@@ -1904,8 +1904,8 @@ __global__ void __launch_bounds__(kGramThreads)
     auto load = [&](int r0) {
 #pragma unroll
         for (int k = 0; k < kGramLoads; ++k) {
-            px[k] = X[(size_t)min(r0 + xr_[k], n - 1) * ldx + xc_[k]];
-            py[k] = Y[(size_t)min(r0 + yr_[k], n - 1) * ldy + yc_[k]];
+            px[k] = X[(size_t)min((int64_t)r0 + xr_[k], (int64_t)n - 1) * ldx + xc_[k]];
+            py[k] = Y[(size_t)min((int64_t)r0 + yr_[k], (int64_t)n - 1) * ldy + yc_[k]];
         }
     };
     auto stage = [&](int rows) {
