@@ -776,9 +776,17 @@ void launch_iteration(Hier &h, int par, bool timed, hipStream_t s) {
     }
     if (g) HIPC(hipGraphLaunch(h.gexec[1][par], s));
     else enqueue_segment(h, par, 0, s);
-    if (timed) HIPC(hipEventRecord(h.pev[par][0], s));
+    // with Jacobi the segment is the one post-smoothing kernel, whose launch
+    // records the events itself; the two FSAI kernels sit between stream events
+    const bool one = h.prm.smoother == CAMG_SMOOTH_JACOBI;
+    if (timed && one) time_next_row_launch(h.pev[par][0], h.pev[par][1]);
+    if (timed && !one) HIPC(hipEventRecord(h.pev[par][0], s));
     enqueue_segment(h, par, 1, s);
-    if (timed) HIPC(hipEventRecord(h.pev[par][1], s));
+    if (timed && one && cancel_row_launch_timing()) {  // no row kernel in the segment
+        HIPC(hipEventRecord(h.pev[par][0], s));
+        HIPC(hipEventRecord(h.pev[par][1], s));
+    }
+    if (timed && !one) HIPC(hipEventRecord(h.pev[par][1], s));
     if (g) HIPC(hipGraphLaunch(h.gexec[2][par], s));
     else enqueue_segment(h, par, 2, s);
 }

@@ -262,6 +262,11 @@ void galerkin(const Csr &A, const Csr &P, const Csr &R, Csr &Ac, int64_t chunk, 
               hipStream_t s);
 
 // ---------------------------------------------------------------- solve (solve.hip)
+// the next row-kernel launch of the calling host thread records `start` and
+// `stop` at the beginning and end of its execution (hipExtLaunchKernelGGL)
+void time_next_row_launch(hipEvent_t start, hipEvent_t stop);
+// drops a request no launch has taken yet; true if there was one
+bool cancel_row_launch_timing();
 RowCfg choose_cfg(int n, int64_t nnz, int maxrow);
 
 // V-cycle building blocks.  T: value type of the level (double, or float

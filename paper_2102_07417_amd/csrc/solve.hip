@@ -19,6 +19,8 @@
 // adds the partials in index order in every block that needs the total.
 // Scalars of the recurrence stay in device memory; once the stopping test
 // passes, every later kernel sees `done` and returns at once.
+#include <hip/hip_ext.h>
+
 #include "devutil.hpp"
 #include "internal.hpp"
 
@@ -530,11 +532,29 @@ __global__ void __launch_bounds__(kBlock) k_sum_to(const double *partials, int n
     default: { constexpr int L = 64; __VA_ARGS__; } break; \
     }
 
+// events that the next row-kernel launch of this host thread records at its
+// own start and end (set by time_next_row_launch, cleared by that launch)
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
 template <class T, bool DOT, class G, class E>
 void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *partials, int32_t *nout,
                  const PcgState *st, hipStream_t s, const T *values = nullptr) {
     const MatArg<T> M = mat_arg<T>(A, c, values);
     const size_t smem = c.tile ? (size_t)(c.tile_nnz + 1) * sizeof(T) : 0;
+    if (t_ev_start) {  // timed launch: the events bracket the kernel's execution
+        hipEvent_t a = t_ev_start, b = t_ev_stop;
+        t_ev_start = t_ev_stop = nullptr;
+        if (c.tile) {
+            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, true, DOT, G, E>, dim3(c.grid), dim3(kBlock),
+                                                          (uint32_t)smem, s, a, b, 0, M, g, e, partials, nout, st)));
+        } else {
+            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, false, DOT, G, E>, dim3(c.grid),
+                                                          dim3(kBlock), 0u, s, a, b, 0, M, g, e, partials, nout,
+                                                          st)));
+        }
+        HIPC(hipGetLastError());
+        return;
+    }
     if (c.tile) {
         CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
     } else {
@@ -544,6 +564,17 @@ void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *
 }
 
 }  // namespace
+
+void time_next_row_launch(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool cancel_row_launch_timing() {
+    const bool pending = t_ev_start != nullptr;
+    t_ev_start = t_ev_stop = nullptr;
+    return pending;
+}
 
 RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
     RowCfg c;

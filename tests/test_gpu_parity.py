@@ -281,6 +281,20 @@ def test_kernel_timing_hook(camg):
     r0 = s.solve(b)
     assert np.array_equal(r4.x, r0.x) and np.array_equal(r.x, r0.x)
     s.close()
+    # a one-level hierarchy has no post-smoothing kernel to time, and the FSAI
+    # post-smoothing (two kernels) is timed between stream events
+    A1 = PB.lognormal3d(12, 2.0)
+    for A2, kw in ((A1, {"max_coarse": 5000}), (A, {"smoother": camg.SMOOTH_FSAI})):
+        b2 = PB.rhs(A2.n)
+        s = camg.Solver(A2, **kw)
+        assert s.nlev == (1 if "max_coarse" in kw else s.nlev)
+        camg.camg_profile(s.h, 1)
+        r = s.solve(b2)
+        ms, launches = camg.camg_profile(s.h, 0)
+        assert r.status == camg.OK and launches == r.iters and ms >= 0.0, kw
+        if "smoother" in kw:
+            assert ms > 0.0
+        s.close()
 
 
 # ----------------------------------------------------------------- multi-RHS
