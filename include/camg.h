@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 4
+#define CAMG_ABI_VERSION 5
 
 typedef struct camg_hier *camg_handle;
 
@@ -139,6 +139,8 @@ typedef struct {
                                              checks, smoother weights, strength + PMIS + coarse numbering,
                                              interpolation, R = P^T, Galerkin product, last-level factorisation,
                                              launch shapes and solve buffers */
+    int32_t compact_cols;                 /* bit 5 l + k set when matrix k of level l (A, P, R, G, G^T) has
+                                             16-bit column differences for the row kernels (levels 0..5) */
 } camg_info_t;
 
 int32_t     camg_abi_version(void);
@@ -366,9 +368,13 @@ camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_
  * camg_server_add) time the candidate schedules of their row kernels on
  * every matrix of the hierarchy (entries per unrolled step, LDS chunk, grid)
  * and keep the fastest, cached per matrix signature for the process; the
- * results are bitwise the same as untuned.
+ * results are bitwise the same as untuned.  CAMG_OPT_COMPACT_COLS (default
+ * 1): the single-system row kernels read each tiled matrix's columns as a
+ * per-tile base plus 16-bit differences where every tile spans fewer than
+ * 65536 columns (10 bytes per FP64 nonzero instead of 12); 0 reads the int32
+ * columns; the results are bitwise the same.
  */
-enum { CAMG_OPT_GRAPH = 1, CAMG_OPT_AUTOTUNE = 2 };
+enum { CAMG_OPT_GRAPH = 1, CAMG_OPT_AUTOTUNE = 2, CAMG_OPT_COMPACT_COLS = 3 };
 camg_status camg_set_option(camg_handle h, int32_t option, int64_t value);
 
 /* Release the hierarchy and all its device memory.  NULL is ignored. */

@@ -34,6 +34,7 @@ OPT_GRAPH = 1
 SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
 INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 OPT_AUTOTUNE = 2
+OPT_COMPACT_COLS = 3
 
 
 class camg_params(C.Structure):
@@ -50,7 +51,8 @@ class camg_info_t(C.Structure):
                 ("nnz_p", C.c_int64 * MAX_LEVELS), ("pmis_rounds", C.c_int32 * MAX_LEVELS),
                 ("omega", C.c_double * MAX_LEVELS), ("grid_complexity", C.c_double),
                 ("operator_complexity", C.c_double), ("device_bytes", C.c_int64), ("setup_ms", C.c_double),
-                ("precision", C.c_int32), ("setup_phase_ms", C.c_double * 8)]
+                ("precision", C.c_int32), ("setup_phase_ms", C.c_double * 8),
+                ("compact_cols", C.c_int32)]
 SETUP_PHASES = ["input", "smoother", "strength_pmis", "interpolation", "transpose", "galerkin", "last_level",
                 "solve_prep"]
 

@@ -218,6 +218,17 @@ RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
     if (c.tile) {
         c.tstart = h.pool.alloc<int32_t>((size_t)c.ntiles + 1);
         tile_starts(M.nr, M.rp, c.W, c.ntiles, c.tstart, s);
+        // 16-bit column differences per tile: 10 bytes per FP64 nonzero
+        // instead of 12 (6 instead of 8 in FP32) where the tiles allow them
+        int32_t *tb = tmp.alloc<int32_t>((size_t)c.ntiles);
+        uint16_t *of = tmp.alloc<uint16_t>(padded(M.nnz));
+        if (tile_offsets(c.ntiles, c.tstart, M.rp, M.ci, tb, of, tmp, s)) {
+            c.tbase = h.pool.alloc<int32_t>((size_t)c.ntiles);
+            c.off = h.pool.alloc<uint16_t>(padded(M.nnz));
+            HIPC(hipMemcpyAsync(c.tbase, tb, sizeof(int32_t) * (size_t)c.ntiles, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(c.off, of, sizeof(uint16_t) * padded(M.nnz), hipMemcpyDeviceToDevice, s));
+            c.use_off = h.compact_cols;
+        }
     }
     return c;
 }
@@ -1073,6 +1084,13 @@ camg_status camg_info(camg_handle hh, camg_info_t *info) {
         info->setup_ms = h->setup_ms;
         info->precision = h->prm.precision;
         for (int k = 0; k < 8; ++k) info->setup_phase_ms[k] = h->phase_ms[k];
+        info->compact_cols = 0;
+        for (int l = 0; l < h->nlev && l < 6; ++l) {
+            const Level &L = h->lev[l];
+            const RowCfg *cs[5] = {&L.cA, &L.cP, &L.cR, &L.cG, &L.cGt};
+            for (int k = 0; k < 5; ++k)
+                if (cs[k]->off) info->compact_cols |= 1 << (5 * l + k);
+        }
     });
 }
 
@@ -1226,6 +1244,12 @@ camg_status camg_set_option(camg_handle hh, int32_t option, int64_t value) {
             break;
         case CAMG_OPT_AUTOTUNE:
             h->autotune = value != 0;
+            break;
+        case CAMG_OPT_COMPACT_COLS:
+            h->compact_cols = value != 0;
+            for (Level &L : h->lev)
+                for (RowCfg *c : {&L.cA, &L.cP, &L.cR, &L.cG, &L.cGt}) c->use_off = h->compact_cols && c->off;
+            h->graph_ok = false;  // captured launches hold the old arguments
             break;
         default: fail(CAMG_E_ARG, "unknown option");
         }

@@ -91,6 +91,12 @@ struct RowCfg {
     int tpb = 0;          // consecutive tiles per block
     int maxrow = 0;
     int32_t *tstart = nullptr;  // device: first row of each tile
+    // compact column indices (tile mode, when every tile spans fewer than
+    // 65536 columns): column = tbase[tile] + off[nonzero]; use_off switches
+    // the row kernels between them and the int32 columns (the same results)
+    int32_t *tbase = nullptr;
+    uint16_t *off = nullptr;
+    bool use_off = false;
 };
 
 struct Level {
@@ -159,6 +165,7 @@ struct Hier {
     // the level-0 post-smoothing (used while kernel timing is on)
     bool use_graph = true;
     bool autotune = false;  // engines created on the handle tune their row schedules
+    bool compact_cols = true;  // row kernels read the 16-bit column differences where built
     bool graph_ok = false;
     bool graph_prof = false;
     hipGraphExec_t gexec[3][2] = {};
@@ -250,6 +257,11 @@ void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s);
+// per tile the smallest column (tbase) and 16-bit column differences (off,
+// nnz + padding entries); false, with off untouched, when a tile spans 65536
+// columns or more
+bool tile_offsets(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase,
+                  uint16_t *off, Pool &tmp, hipStream_t s);
 
 // ---------------------------------------------------------------- SpGEMM (spgemm.hip)
 // Z = X Y with the full symbolic pattern, rows sorted; for every output

@@ -44,6 +44,8 @@ struct MatArg {
     const int32_t *__restrict__ ci;
     const T *__restrict__ v;
     const int32_t *__restrict__ tstart;  // tile mode: first row of each tile (ntiles + 1)
+    const int32_t *__restrict__ tbase;   // tile mode with compact columns: smallest column per tile
+    const uint16_t *__restrict__ off;    //   and column - tbase per nonzero (null: use ci)
     int n;
     int rpt;     // vector mode: rows per block
     int ntiles;  // tile mode
@@ -60,7 +62,8 @@ const float *vals<float>(const Csr &A) { return A.v32; }
 
 template <class T>
 MatArg<T> mat_arg(const Csr &A, const RowCfg &c, const T *v = nullptr) {
-    return MatArg<T>{A.rp, A.ci, v ? v : vals<T>(A), c.tstart, A.nr, c.rpt, c.ntiles, c.tpb, c.tile_nnz};
+    return MatArg<T>{A.rp,        A.ci,  v ? v : vals<T>(A), c.tstart, c.use_off ? c.tbase : nullptr,
+                     c.use_off ? c.off : nullptr, A.nr, c.rpt, c.ntiles, c.tpb, c.tile_nnz};
 }
 
 // Sum of partials[0..n) in index order, result in every thread of the block.
@@ -75,6 +78,7 @@ __device__ __forceinline__ double sum_all(const double *partials, int n) {
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned short v4us __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -89,22 +93,36 @@ __device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
     o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
 }
 
+// Four column indices of the nonzeros idx .. idx+3 (idx a multiple of 4):
+// the int32 columns, or the tile's base plus 16-bit differences.
+template <bool OFF, class T>
+__device__ __forceinline__ v4i cols4(const MatArg<T> &M, int idx, int base) {
+    if constexpr (OFF) {
+        const v4us o = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
+        return v4i{base + (int)o.x, base + (int)o.y, base + (int)o.z, base + (int)o.w};
+    } else {
+        (void)base;
+        return __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
+    }
+}
+
 // Phase 1 of a tile: prod[e - e0] = a_e * g(col_e) for e in [e0, e0 + m).
-// Column indices and values are streamed as aligned 16-byte vectors from
-// e0 rounded down to a multiple of 4 (the arrays carry 8 elements of
-// padding, so the last vector stays inside the allocation).  Entries outside
-// the tile gather column 0 instead and store into the spare LDS slot
-// prod[junk] (no branch anywhere, so all the loads stay in flight).
-template <class T, class G>
-__device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m) {
+// Column indices (int32, or 16-bit differences to the tile's base column)
+// and values are streamed as aligned vectors of four from e0 rounded down to
+// a multiple of 4 (the arrays carry 8 elements of padding, so the last
+// vector stays inside the allocation).  Entries outside the tile gather
+// column 0 instead and store into the spare LDS slot prod[junk] (no branch
+// anywhere, so all the loads stay in flight).
+template <bool OFF, class T, class G>
+__device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m, int base) {
     const int junk = M.junk;
     const int a0 = e0 & ~3;
     const int span = e0 + m - a0;
     constexpr int STEP = 4 * kBlock;
     int k = 4 * threadIdx.x;
     for (; k + STEP < span; k += 2 * STEP) {
-        const v4i c0 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k));
-        const v4i c1 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k + STEP));
+        const v4i c0 = cols4<OFF>(M, a0 + k, base);
+        const v4i c1 = cols4<OFF>(M, a0 + k + STEP, base);
         T v0[4], v1[4];
         load4(M.v + a0 + k, v0);
         load4(M.v + a0 + k + STEP, v1);
@@ -125,7 +143,7 @@ __device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *p
         }
     }
     for (; k < span; k += STEP) {
-        const v4i c0 = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + a0 + k));
+        const v4i c0 = cols4<OFF>(M, a0 + k, base);
         T v0[4];
         load4(M.v + a0 + k, v0);
         const int cc[4] = {c0.x, c0.y, c0.z, c0.w};
@@ -197,7 +215,8 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
                 if (sl == 0) pre = epi.load(i);
             }
             if constexpr (G::kLoads > 1) stream_tile_scalar(M, g, prod, e0, m);
-            else stream_tile(M, g, prod, e0, m);
+            else if (M.off) stream_tile<true>(M, g, prod, e0, m, M.tbase[t]);
+            else stream_tile<false>(M, g, prod, e0, m, 0);
             __syncthreads();
             {
                 T acc = 0;

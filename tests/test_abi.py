@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 4
+    assert lib.camg_abi_version() == 5
     for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -98,8 +98,8 @@ int main(void) {
   printf("bamg %zu %zu %zu %zu %zu %zu\n", offsetof(camg_params, bamg_lmin), offsetof(camg_params, bamg_eps),
          offsetof(camg_params, bamg_mu), offsetof(camg_params, psmooth), offsetof(camg_params, pfilter),
          offsetof(camg_params, srqm_iters));
-  printf("info %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
-         offsetof(camg_info_t, setup_phase_ms));
+  printf("info %zu %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
+         offsetof(camg_info_t, setup_phase_ms), offsetof(camg_info_t, compact_cols));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
          offsetof(camg_completion, latency_ms));
   return 0;
@@ -115,7 +115,7 @@ int main(void) {
     assert out["bamg"] == [P.bamg_lmin.offset, P.bamg_eps.offset, P.bamg_mu.offset, P.psmooth.offset,
                            P.pfilter.offset, P.srqm_iters.offset]
     I = camg.camg_info_t
-    assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset]
+    assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset, I.compact_cols.offset]
     Q = camg.camg_completion
     assert out["completion"] == [C.sizeof(Q), Q.true_relres.offset, Q.latency_ms.offset]
 

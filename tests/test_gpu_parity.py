@@ -467,3 +467,59 @@ def test_fsai_two_steps_and_mixed(camg):
     with pytest.raises(camg.CamgError):
         camg.solve_batch_dev([gm], [db], [torch.zeros_like(db)])
     gm.close()
+
+
+# ----------------------------------------------------------------- compact columns
+def _far_coupled_chain(n=100_000, far=70_000):
+    """1D Laplacian plus a weak coupling of i and i + far for every 1000th i:
+    the tiles holding those rows span more than 65536 columns."""
+    import scipy.sparse as sp
+    main = 2.2 * np.ones(n)
+    A = sp.diags([-np.ones(n - 1), main, -np.ones(n - 1)], [-1, 0, 1], format="lil")
+    for i in range(0, n - far, 1000):
+        A[i, i + far] = -0.1
+        A[i + far, i] = -0.1
+    A = A.tocsr()
+    A.sort_indices()
+    return PB.CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("name,kw", [("lognormal3d_24", {}), ("lognormal3d_24", {"precision": 1}),
+                                     ("lognormal3d_24", {"smoother": 1}), ("elasticity_6", {})])
+def test_compact_columns_bitwise(camg, name, kw):
+    """Row kernels reading 16-bit column differences give bitwise the
+    iterates of the int32 columns (same products, same sums)."""
+    print(f"[gpu] compact columns {name} {kw}", flush=True)
+    A = CASES[name]()
+    b = PB.rhs(A.n)
+    s = camg.Solver(A, **kw)
+    assert s.info.compact_cols & 1, "A_0 should carry compact columns"
+    r1 = s.solve(b)
+    y = np.random.default_rng(5).standard_normal(A.n)
+    z1 = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    s.vcycle_dev(_dev(y), z1)
+    s.set_option(camg.OPT_COMPACT_COLS, 0)
+    r0 = s.solve(b)
+    z0 = torch.zeros_like(z1)
+    s.vcycle_dev(_dev(y), z0)
+    torch.cuda.synchronize()
+    assert r1.iters == r0.iters and np.array_equal(r1.x, r0.x)
+    assert torch.equal(z1, z0)
+    s.set_option(camg.OPT_COMPACT_COLS, 1)
+    r2 = s.solve(b)
+    assert np.array_equal(r2.x, r1.x)
+    s.close()
+
+
+def test_wide_tiles_keep_int32_columns(camg):
+    print("[gpu] compact columns: wide tiles", flush=True)
+    A = _far_coupled_chain()
+    b = PB.rhs(A.n)
+    s = camg.Solver(A, max_iter=3000)
+    assert not (s.info.compact_cols & 1)
+    r = s.solve(b)
+    o = O.Hierarchy(A, max_iter=3000)
+    ro = o.solve(b, 1e-8, max_iter=3000)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    s.close()
