@@ -66,6 +66,14 @@ def post0_bytes(n, nnz, fp32=False):
     return 4 * (n + 1) + 12 * nnz + 32 * n
 
 
+def post0_stored_bytes(n, nnz, compact):
+    """Bytes the level-0 post-smoothing kernel actually reads and writes when
+    A_0's column indices are stored as 16-bit differences to a base column
+    per tile (2 bytes per nonzero instead of 4; the per-tile bases, a few
+    tens of KB, are left out)."""
+    return post0_bytes(n, nnz) - (2 * nnz if compact else 0)
+
+
 def committed_traffic():
     """HBM bytes per launch of the level-0 post-smoothing kernel from the
     committed rocprofv3 counter summary, or None when the kernel sources have
@@ -249,6 +257,8 @@ def main():
     launches = sum(r["prof"][1] for r in fp64)
     k_ms = tot_ms / max(launches, 1)
     k_bytes = post0_bytes(A.n, A.nnz)
+    compact = bool(fp64[-1]["info"].compact_cols & 1)
+    k_stored = post0_stored_bytes(A.n, A.nnz, compact)
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9 if launches else 0.0
     traffic = committed_traffic() if args.workload == "lognormal3d_128" else None
     vb = vcycle_bytes(info)
@@ -277,7 +287,9 @@ def main():
                      "achieved": round(k_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": k_bytes, "avg_launch_us": round(k_ms * 1e3, 3),
-                     "launches": launches, "copy_kernel_gbs": round(copy_gbs, 1)},
+                     "launches": launches, "copy_kernel_gbs": round(copy_gbs, 1),
+                     "compact_cols": compact, "stored_bytes_per_launch": k_stored,
+                     "stored_gbs": round(k_stored / (k_ms * 1e-3) / 1e9, 2) if launches else 0.0},
     }
     if mixed:
         m_ms = statistics.median(r["solve_ms"] for r in mixed)
