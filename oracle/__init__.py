@@ -19,7 +19,7 @@ _lib = None
 OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -2, -3, -4, -5, -6
 F, U, CPT = -1, 0, 1
 X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS, X_G = range(11)
-SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
+SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI = 0, 1, 2
 INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 
 
@@ -391,6 +391,14 @@ class Hierarchy:
         a = np.zeros(self.sizes(l)[0])
         assert lib().orc_export(self.h, l, X_DINV, _p(a), None, None) == OK
         return a
+
+    def has_G(self, l):
+        """Whether level l smooths with FSAI (its factor can be exported)."""
+        try:
+            self.G(l)
+            return True
+        except AssertionError:
+            return False
 
     def G(self, l):
         """FSAI factor of level l (FSAI smoother only)."""

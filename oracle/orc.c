@@ -1183,6 +1183,17 @@ double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, con
  * backward substitution (column-oriented), and set
  * G(i, P_i) = g / sqrt(g_last), so that G A G^T has a unit diagonal.
  */
+/* the largest number of entries on or below the diagonal in a row of A */
+static int32_t lower_row_max(const orc_csr *A) {
+    int32_t mmax = 0;
+    for (int32_t i = 0; i < A->nrows; ++i) {
+        int32_t m = 0;
+        for (int32_t e = A->rp[i]; e < A->rp[i + 1]; ++e) if (A->ci[e] <= i) ++m;
+        if (m > mmax) mmax = m;
+    }
+    return mmax;
+}
+
 int orc_fsai(const orc_csr *A, orc_csr *G) {
     int32_t n = A->nrows;
     G->nrows = n; G->ncols = n;
@@ -1390,7 +1401,12 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
             if (d < 0 || !(av[d] > 0.0)) { orc_destroy(h); return ORC_E_NOT_SPD; }
             L->dinv[i] = 1.0 / av[d];
         }
-        if (h->prm.smoother == ORC_SMOOTH_FSAI) {
+        /* FSAI on this level: always with ORC_SMOOTH_FSAI; with
+         * ORC_SMOOTH_FSAI_JACOBI when no row has more than ORC_FSAI_MAXROW
+         * entries on or below the diagonal (Jacobi otherwise) */
+        const int use_fsai = h->prm.smoother == ORC_SMOOTH_FSAI ||
+                             (h->prm.smoother == ORC_SMOOTH_FSAI_JACOBI && lower_row_max(&L->A) <= ORC_FSAI_MAXROW);
+        if (use_fsai) {
             st = orc_fsai(&L->A, &L->G);
             if (!st) st = orc_transpose(&L->G, &L->GT);
             double w = 0.0;
@@ -1404,7 +1420,7 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
             /* refine the level-0 test space with the smoother just built,
              * then take an orthonormal basis of it again */
             int32_t done = 0;
-            const int fs = h->prm.smoother == ORC_SMOOTH_FSAI;
+            const int fs = L->G.rp != NULL;
             st = orc_srqm(&L->A, L->dinv, fs ? &L->G : NULL, fs ? &L->GT : NULL, nt, TV, h->prm.srqm_iters, &done);
             if (!st) st = orc_orthonormalize(nl, nt, TV);
             if (st) { orc_destroy(h); return st; }
@@ -1564,7 +1580,7 @@ static void vcycle_level(const orc_hier *h, int32_t l, const double *y, double *
     int32_t n = L->A.nrows;
     if (l == h->nlev - 1) { orc_chol_solve(n, h->L, y, z); return; }
     int32_t nc = L->P.ncols;
-    int fsai = h->prm.smoother == ORC_SMOOTH_FSAI;
+    int fsai = L->G.rp != NULL;  /* this level's smoother */
     double *s = z;   /* the smoothed iterate lives in the output */
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     double *u = (double *)malloc(sizeof(double) * (size_t)n);

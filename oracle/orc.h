@@ -45,7 +45,8 @@ typedef struct {
     int32_t  max_levels;
     int32_t  max_coarse;
     int32_t  max_iter;
-    int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D) or ORC_SMOOTH_FSAI (M^{-1} = G^T G) */
+    int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D), ORC_SMOOTH_FSAI (M^{-1} = G^T G) or
+                             ORC_SMOOTH_FSAI_JACOBI (FSAI per level where the rows are short enough) */
     int32_t  interp;      /* ORC_INTERP_* */
     int32_t  bamg_lmin, bamg_lmax;  /* BAMG: interpolation distances tried (1, 2) */
     double   bamg_eps, bamg_mu;     /* BAMG: accept when relative residual <= eps and ||w|| <= mu */
@@ -53,7 +54,9 @@ typedef struct {
     double   pfilter;     /* < 1: filter P, keeping this fraction of each row's absolute sum */
     int32_t  srqm_iters;  /* BAMG: SRQM steps refining the level-0 test space (0: none) */
 } orc_params;
-enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1 };
+enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1, ORC_SMOOTH_FSAI_JACOBI = 2 };
+#define ORC_FSAI_MAXROW 192  /* ORC_SMOOTH_FSAI_JACOBI: FSAI on levels whose rows have at most this many
+                                entries on or below the diagonal, Jacobi on the others */
 enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3,
        ORC_INTERP_BAMG = 4 };
 #define ORC_MAXNT 8        /* test vectors */

@@ -118,3 +118,82 @@ def test_fsai_pcg_converges_to_dense_solution(gen):
     Ad = dense(A)
     assert np.linalg.norm(b - Ad @ r.x) / np.linalg.norm(b) < 1.5e-8
     assert r.hist[-1] < 1e-8 * np.linalg.norm(b) <= r.hist[-2]
+
+
+# ----------------------------------------------------------------- FSAI where the rows fit, Jacobi elsewhere
+def _lower_max(Al):
+    n, _, rp, ci, _ = Al
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    return int(np.bincount(rows[ci <= rows], minlength=n).max())
+
+
+def test_fsai_jacobi_with_short_rows_is_fsai():
+    A = PB.lognormal3d(9, 2.0)
+    hf = O.Hierarchy(A, max_coarse=30, smoother=O.SMOOTH_FSAI)
+    hm = O.Hierarchy(A, max_coarse=30, smoother=O.SMOOTH_FSAI_JACOBI)
+    assert hf.nlev == hm.nlev >= 3
+    for l in range(hm.nlev - 1):
+        assert _lower_max(hm.A(l)) <= 192
+        np.testing.assert_array_equal(hm.G(l)[4], hf.G(l)[4])
+        assert hm.omega(l) == hf.omega(l)
+    y = np.random.default_rng(4).standard_normal(A.n)
+    assert np.array_equal(hm.vcycle(y), hf.vcycle(y))
+
+
+def test_fsai_jacobi_with_long_rows_is_jacobi():
+    """Every row of a radius-10 stencil has 221 entries on or below the
+    diagonal: that level keeps the Jacobi smoother and weight."""
+    from helpers import wide_stencil_2d
+    A = wide_stencil_2d(24, 10)
+    hj = O.Hierarchy(A, max_coarse=40)
+    hm = O.Hierarchy(A, max_coarse=40, smoother=O.SMOOTH_FSAI_JACOBI)
+    assert _lower_max(hm.A(0)) > 192 and not hm.has_G(0)
+    assert hm.omega(0) == hj.omega(0)
+    for l in range(hm.nlev - 1):
+        assert hm.has_G(l) == (_lower_max(hm.A(l)) <= 192)
+        if not hm.has_G(l):
+            assert hm.omega(l) == hj.omega(l)
+    if not any(hm.has_G(l) for l in range(hm.nlev - 1)):
+        y = np.random.default_rng(4).standard_normal(A[0])
+        assert np.array_equal(hm.vcycle(y), hj.vcycle(y))
+
+
+def _M_levels(Al, Ps, Minvs, omegas, l):
+    """Iteration-matrix recursion with each level's own smoother
+    S_l = I - omega_l Minv_l A_l (G^T G on FSAI levels, D^{-1} on Jacobi ones)."""
+    if l == len(Ps):
+        return np.linalg.inv(Al)
+    P = Ps[l]
+    Mc = _M_levels(P.T @ Al @ P, Ps, Minvs, omegas, l + 1)
+    n = Al.shape[0]
+    S = np.eye(n) - omegas[l] * Minvs[l] @ Al
+    E = S @ (np.eye(n) - P @ Mc @ P.T @ Al) @ S
+    return (np.eye(n) - E) @ np.linalg.inv(Al)
+
+
+def test_fsai_jacobi_mixed_levels_vcycle_matches_iteration_matrix():
+    """BAMG on 8^3 elasticity: level 1 has rows with 212 entries on or below
+    the diagonal (Jacobi), levels 0 and 2 smooth with FSAI."""
+    A, V = PB.elasticity3d(8), PB.elasticity_rigid_modes(8)
+    h = O.Hierarchy(A, V=V, interp=O.INTERP_BAMG, max_coarse=40, smoother=O.SMOOTH_FSAI_JACOBI)
+    kinds = [h.has_G(l) for l in range(h.nlev - 1)]
+    assert kinds[0] and not all(kinds), kinds
+    Ps, Minvs, om = [], [], []
+    for l in range(h.nlev - 1):
+        Ps.append(dense(h.P(l)))
+        Ad = dense(h.A(l))
+        if kinds[l]:
+            Gd = dense(h.G(l))
+            np.testing.assert_array_equal(Gd, dense(_G(h.A(l))))
+            Minvs.append(Gd.T @ Gd)
+        else:
+            Minvs.append(np.diag(1.0 / np.diag(Ad)))
+        om.append(h.omega(l))
+    M = _M_levels(dense(A), Ps, Minvs, om, 0)
+    Mo = np.stack([h.vcycle(e) for e in np.eye(A.n)], axis=1)
+    np.testing.assert_allclose(Mo, M, rtol=0, atol=1e-12 * np.abs(M).max())
+    np.testing.assert_allclose(Mo, Mo.T, rtol=0, atol=1e-12 * np.abs(Mo).max())
+    b = PB.rhs(A.n)
+    rj = O.Hierarchy(A, V=V, interp=O.INTERP_BAMG, max_coarse=40).solve(b, 1e-8, max_iter=2000)
+    rm = h.solve(b, 1e-8, max_iter=2000)
+    assert rm.status == O.OK and rm.iters < rj.iters

@@ -91,6 +91,9 @@ MUTATIONS = [
     ("srqm_keeps_dependent_columns", "if (!(d > 1e-12 * gmax)) continue;", "if (!(d > 0.0)) continue;"),
     ("srqm_symeig_rotation_sign", "const double s = t * c;", "const double s = -t * c;"),
     ("srqm_fsai_G_twice", "csr_block(GT, nt, Y, nt, S + nt, m);", "csr_block(G, nt, Y, nt, S + nt, m);"),
+    ("fsai_jacobi_threshold_flipped", "lower_row_max(&L->A) <= ORC_FSAI_MAXROW", "lower_row_max(&L->A) > ORC_FSAI_MAXROW"),
+    ("fsai_jacobi_smoother_from_params", "int fsai = L->G.rp != NULL;  /* this level's smoother */",
+     "int fsai = h->prm.smoother == ORC_SMOOTH_FSAI;"),
 ]
 
 
