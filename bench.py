@@ -534,10 +534,11 @@ def bamg_run(ne):
     rtol 1e-8 with direct interpolation, then with BAMG interpolation over
     the six rigid body modes (FP64 and mixed; mixed with the prolongation
     smoothed and filtered to rho = 0.7; mixed with 3 SRQM steps on the
-    modes), then from six random vectors with and without 10 SRQM steps.
-    Each configuration runs once untimed, then once timed.  (The FSAI smoother is not paired
-    with BAMG here: BAMG's coarse levels have rows beyond its 192-entry
-    limit.)"""
+    modes; direct and BAMG with the FSAI_JACOBI smoother: FSAI on the
+    levels whose rows have at most 192 entries on or below the diagonal,
+    Jacobi on BAMG's denser coarse levels), then from six random vectors
+    with and without 10 SRQM steps.  Each configuration runs once untimed,
+    then once timed."""
     import numpy as np
     import torch
 
@@ -580,7 +581,10 @@ def bamg_run(ne):
                                 ("direct_mixed", camg.MIXED_FP32, False, camg.SMOOTH_JACOBI),
                                 ("bamg_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
                                 ("bamg_psmooth_filter_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
-                                ("bamg_srqm3_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI)):
+                                ("bamg_srqm3_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
+                                ("direct_fsai_jacobi_mixed", camg.MIXED_FP32, False, camg.SMOOTH_FSAI_JACOBI),
+                                ("bamg_fsai_jacobi_fp64", camg.FP64, True, camg.SMOOTH_FSAI_JACOBI),
+                                ("bamg_fsai_jacobi_mixed", camg.MIXED_FP32, True, camg.SMOOTH_FSAI_JACOBI)):
         extra = {"psmooth": 1, "pfilter": 0.7} if "psmooth" in key else {}
         if "srqm" in key:
             extra["srqm_iters"] = 3

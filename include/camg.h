@@ -56,8 +56,11 @@ typedef enum {
 enum { CAMG_FP64 = 0, CAMG_MIXED_FP32 = 1 };
 /* Smoother (Section 2, eq. smoother): Jacobi (M = D, the default) or the
  * factorised sparse approximate inverse M^{-1} = G^T G (eq. smo; here the
- * static factor on the pattern of the lower triangle of A). */
-enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1 };
+ * static factor on the pattern of the lower triangle of A; every row of it
+ * must have at most 192 entries, CAMG_E_ARG otherwise).  FSAI_JACOBI: FSAI
+ * on each level whose rows have at most 192 entries on or below the
+ * diagonal and Jacobi on the others (e.g. the dense coarse levels of BAMG). */
+enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1, CAMG_SMOOTH_FSAI_JACOBI = 2 };
 /* Interpolation (Section 2, Interpolation).  DIRECT: distance-one direct
  * formula over C_i^S (the default).  CLASSICAL: eq. clasInt with the
  * correction for strong F neighbours that share no C point (they are

@@ -31,7 +31,7 @@ EXPORTED = [
     "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy", "camg_solve_batch_dev",
 ]
 OPT_GRAPH = 1
-SMOOTH_JACOBI, SMOOTH_FSAI = 0, 1
+SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI = 0, 1, 2
 INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 OPT_AUTOTUNE = 2
 OPT_COMPACT_COLS = 3

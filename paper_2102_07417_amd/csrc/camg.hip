@@ -170,7 +170,8 @@ void check_params(const camg_params &p) {
     if (p.max_iter < 0) fail(CAMG_E_ARG, "max_iter must be >= 0");
     if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
-    if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI) fail(CAMG_E_ARG, "unknown smoother");
+    if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI && p.smoother != CAMG_SMOOTH_FSAI_JACOBI)
+        fail(CAMG_E_ARG, "unknown smoother");
     if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_BAMG) fail(CAMG_E_ARG, "unknown interpolation");
     if (p.interp == CAMG_INTERP_BAMG &&
         (p.bamg_lmin < 1 || p.bamg_lmax < p.bamg_lmin || p.bamg_lmax > 2 || std::isnan(p.bamg_eps) || std::isnan(p.bamg_mu)))
@@ -320,10 +321,18 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         scale_vec(nl, L.omega, L.dinv, L.wd, s);
         L.awd = h.pool.alloc<double>(padded(nz));
         scale_columns(L.A, L.wd, L.awd, s);
-        if (prm.smoother == CAMG_SMOOTH_FSAI) {
+        // FSAI on this level: always with CAMG_SMOOTH_FSAI; with
+        // CAMG_SMOOTH_FSAI_JACOBI when no row has more than kFsaiMaxRow
+        // entries on or below the diagonal (Jacobi otherwise)
+        int32_t *gcnt = nullptr;
+        int mmax = 0;
+        if (prm.smoother != CAMG_SMOOTH_JACOBI) {
+            gcnt = lt.alloc<int32_t>(nl);
+            mmax = fsai_counts(nl, L.A.rp, L.A.ci, gcnt, lt, s);
+        }
+        L.fsai = prm.smoother == CAMG_SMOOTH_FSAI || (prm.smoother == CAMG_SMOOTH_FSAI_JACOBI && mmax <= kFsaiMaxRow);
+        if (L.fsai) {
             // FSAI factor on the lower pattern of A_l, its transpose, omega (eq. smo, eq. smoother)
-            int32_t *gcnt = lt.alloc<int32_t>(nl);
-            const int mmax = fsai_counts(nl, L.A.rp, L.A.ci, gcnt, lt, s);
             int64_t *grp64 = lt.alloc<int64_t>((size_t)nl + 1);
             scan_i32_to_i64(gcnt, grp64, nl, lt, s);
             Csr &G = L.G;
@@ -365,7 +374,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         if (prm.interp == CAMG_INTERP_BAMG && l == 0 && prm.srqm_iters > 0) {
             // refine the level-0 test space with the smoother just built
             // (counted in the smoother phase), then make it orthonormal again
-            const bool fs = prm.smoother == CAMG_SMOOTH_FSAI;
+            const bool fs = L.fsai;
             srqm(L.A, L.dinv, fs ? &L.G : nullptr, fs ? &L.Gt : nullptr, nt, tv, prm.srqm_iters, lt, s);
             bamg_orthonormalize(nl, nt, tv, lt, s);
         }
@@ -512,7 +521,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         Level &L = h.lev[l];
         const int nl = L.A.nr;
         L.cA = make_cfg(h, L.A, tmp, s);
-        const bool fsai = prm.smoother == CAMG_SMOOTH_FSAI && l < h.nlev - 1;
+        const bool fsai = L.fsai && l < h.nlev - 1;
         if (l < h.nlev - 1) {
             L.cP = make_cfg(h, L.P, tmp, s);
             L.cR = make_cfg(h, L.R, tmp, s);
@@ -640,7 +649,7 @@ void fsai_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState 
 
 template <class T, class TY>
 T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
-    if (h.prm.smoother == CAMG_SMOOTH_FSAI) return fsai_pre<T, TY>(h, L, y, st, s);
+    if (L.fsai) return fsai_pre<T, TY>(h, L, y, st, s);
     T *sv = VT<T>::s(L), *tv = VT<T>::t(L);
     vc_pre<T, TY>(L.A, L.cA, VT<T>::wd(L), VT<T>::awd(L), y, sv, VT<T>::r(L), st, s);
     if (h.prm.nu_pre > 1) {
@@ -657,7 +666,7 @@ T *smooth_pre(Hier &h, Level &L, const TY *y, PcgState *st, hipStream_t s) {
 // the partials of y.z into h.prz and their count into st->n_rz.
 template <class T, class TY, class TZ>
 void smooth_post(Hier &h, Level &L, const TY *y, T *sv, TZ *z, bool dot, PcgState *st, hipStream_t s) {
-    if (h.prm.smoother == CAMG_SMOOTH_FSAI) {
+    if (L.fsai) {
         fsai_post<T, TY, TZ>(h, L, y, sv, z, dot, st, s);
         return;
     }
@@ -687,7 +696,7 @@ void vcycle_part(Hier &h, const double *y0, double *z0, PcgState *st, bool dot, 
         return;
     }
     // the level-0 iterate ends up in s or t depending on nu_pre
-    T *s0 = (h.prm.smoother == CAMG_SMOOTH_FSAI || h.prm.nu_pre % 2 == 1) ? VT<T>::s(h.lev[0]) : VT<T>::t(h.lev[0]);
+    T *s0 = (h.lev[0].fsai || h.prm.nu_pre % 2 == 1) ? VT<T>::s(h.lev[0]) : VT<T>::t(h.lev[0]);
     if (head) {
         T *sv[CAMG_MAX_LEVELS] = {};
         for (int l = 0; l < L; ++l) {
@@ -789,7 +798,7 @@ void launch_iteration(Hier &h, int par, bool timed, hipStream_t s) {
     else enqueue_segment(h, par, 0, s);
     // with Jacobi the segment is the one post-smoothing kernel, whose launch
     // records the events itself; the two FSAI kernels sit between stream events
-    const bool one = h.prm.smoother == CAMG_SMOOTH_JACOBI;
+    const bool one = !h.lev[0].fsai;
     if (timed && one) time_next_row_launch(h.pev[par][0], h.pev[par][1]);
     if (timed && !one) HIPC(hipEventRecord(h.pev[par][0], s));
     enqueue_segment(h, par, 1, s);

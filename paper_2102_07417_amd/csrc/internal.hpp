@@ -111,6 +111,7 @@ struct Level {
     uint8_t *strong = nullptr;
     int32_t *stcnt = nullptr;
     int32_t rounds = 0;
+    bool fsai = false;  // this level smooths with FSAI (M^{-1} = G^T G), else Jacobi
     // V-cycle work vectors (y: right-hand side, s: smoothed iterate,
     // r: residual, z: result).  Level 0 borrows y and z from PCG.
     double *y = nullptr, *s = nullptr, *r = nullptr, *z = nullptr, *t = nullptr;
@@ -243,6 +244,8 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 // FSAI smoother: counts of entries on or below the diagonal per row (returns
 // the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:
 // row too long, flags[7]: not SPD), the Collatz-Wielandt bound of |M|
+// rows of the FSAI factor: at most this many entries on or below the diagonal
+constexpr int kFsaiMaxRow = 192;
 int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool &tmp, hipStream_t s);
 void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
 double cw_bound(const Csr &M, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)

@@ -2570,7 +2570,7 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     else if (mmax <= 32) k_fsai_rows<32, 4, 64><<<(n + 3) / 4, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else if (mmax <= 64) k_fsai_rows<64, 1, 64><<<n, 64, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else if (mmax <= 128) k_fsai_rows<128, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
-    else if (mmax <= 192) k_fsai_rows<192, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
+    else if (mmax <= kFsaiMaxRow) k_fsai_rows<kFsaiMaxRow, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
     HIPC(hipGetLastError());
 }

@@ -135,3 +135,51 @@ def test_over_filtered_prolongation_fails_like_the_oracle(camg):
     with pytest.raises(camg.CamgError) as eg:
         camg.Solver(A, max_coarse=40, **kw)
     assert eo.value.status == O.E_NOT_SPD and eg.value.status == camg.E_NOT_SPD
+
+
+def test_fsai_where_rows_fit_jacobi_elsewhere(camg):
+    """BAMG on 8^3 elasticity with the FSAI_JACOBI smoother: levels 0 and 2
+    smooth with FSAI, level 1 (212 entries on or below the diagonal in a
+    row) with Jacobi.  Hierarchy, factors and weights bit for bit; V-cycle,
+    FP64 and mixed solves as elsewhere."""
+    print("[gpu] BAMG + FSAI where rows fit", flush=True)
+    A, V = PB.elasticity3d(8), PB.elasticity_rigid_modes(8)
+    kw = dict(max_coarse=40, smoother=2)
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), V=_dev(V),
+                                interp=camg.INTERP_BAMG, **kw)
+    o = O.Hierarchy(A, V=V, interp=O.INTERP_BAMG, **kw)
+    assert g.nlev == o.nlev
+    kinds = [o.has_G(l) for l in range(o.nlev - 1)]
+    assert kinds[0] and not all(kinds), kinds
+    for l in range(o.nlev):
+        ga, oa = g.A(l), o.A(l)
+        assert np.array_equal(ga[3], oa[3]) and np.array_equal(ga[4], oa[4]), l
+        if l == o.nlev - 1:
+            break
+        gp, op = g.P(l), o.P(l)
+        assert np.array_equal(gp[3], op[3]) and np.array_equal(gp[4], op[4]), l
+        assert g.omega(l) == o.omega(l), l
+        if kinds[l]:
+            assert np.array_equal(g.G(l)[4], o.G(l)[4]), l
+        else:
+            with pytest.raises(camg.CamgError):
+                g.G(l)
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        y = rng.standard_normal(A.n)
+        dz = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+        g.vcycle_dev(_dev(y), dz)
+        torch.cuda.synchronize()
+        zo = o.vcycle(y)
+        assert np.linalg.norm(dz.cpu().numpy() - zo) / np.linalg.norm(zo) <= 1e-12
+    b = PB.rhs(A.n)
+    ro = o.solve(b, 1e-8, max_iter=3000)
+    r = g.solve(b)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1, (r.iters, ro.iters)
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+    gm = camg.Solver(A, V=V, interp=camg.INTERP_BAMG, precision=camg.MIXED_FP32, **kw)
+    rm = gm.solve(b)
+    assert rm.status == camg.OK and rm.true_relres < 1e-8
+    assert np.linalg.norm(rm.x - ro.x) / np.linalg.norm(ro.x) < 1e-6
+    gm.close()
