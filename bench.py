@@ -282,7 +282,8 @@ def main():
                    "operator_complexity": round(info.operator_complexity, 4)},
         "fp64": {"solve_ms": round(solve_ms, 4), "setup_ms": round(setup_ms, 4), "iters": iters,
                  "ms_per_iter": round(per_iter_ms, 5), "true_relres": fp64[-1]["true_relres"],
-                 "vcycle_alg_bytes": vb, "host_api_solve_ms": round(host_ms, 4)},
+                 "vcycle_alg_bytes": vb, "host_api_solve_ms": round(host_ms, 4),
+                 "setup_phase_ms": {k: round(info.setup_phase_ms[i], 2) for i, k in enumerate(camg.SETUP_PHASES)}},
         "roofline": {"bound": "hbm", "kernel": "level-0 post-smoothing (k_rows<EPost, DOT>)",
                      "achieved": round(k_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
