@@ -513,6 +513,99 @@ __global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int32_t *fl
     if (threadIdx.x == 0 && bad) atomicOr(&flags[5], 1);
 }
 
+// Blocked right-looking Cholesky for n <= kCholMfmaMax by one 512-thread
+// workgroup, in place (lower triangle).  Per 16-column panel: the diagonal
+// block is factorised in LDS (one barrier per column; two copies alternate,
+// so a step reads one while writing the other; padding beyond n is the
+// identity), the rows below solve against it (a thread per row), and the
+// trailing lower triangle is updated tile by tile on the matrix cores:
+// A_IJ -= L_I L_J^T over the panel's 16 columns with v_mfma_f64_16x16x4f64,
+// one wavefront per 16x16 tile (lane l supplies row/column l%16 at inner
+// index l/16 and receives rows l/16 + 4r of column l%16).
+constexpr int kCholMfmaMax = 256;
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(512) k_cholesky_mfma(int n, double *D, int32_t *flags) {
+    __shared__ double Lb[2][16][17];
+    __shared__ int bad;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    const int np = (n + 15) / 16;
+    for (int p = 0; p < np; ++p) {
+        const int c0 = 16 * p, cw = min(16, n - c0);
+        if (tid < 256) {
+            const int r = tid / 16, q = tid % 16;
+            Lb[0][r][q] = (r < cw && q < cw) ? D[(size_t)(c0 + r) * n + c0 + q] : (r == q ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        for (int c = 0; c < 16; ++c) {
+            const int cur = c & 1, nxt = cur ^ 1;
+            if (tid < 256) {
+                const int r = tid / 16, q = tid % 16;
+                double out = Lb[cur][r][q];
+                if (q >= c && q <= r) {
+                    const double d = Lb[cur][c][c];
+                    if (r == c && q == c && !(d > 0.0)) bad = 1;
+                    const double piv = sqrt(d);
+                    if (q == c) out = r == c ? piv : Lb[cur][r][c] / piv;
+                    else out = Lb[cur][r][q] - (Lb[cur][r][c] / piv) * (Lb[cur][q][c] / piv);
+                }
+                Lb[nxt][r][q] = out;
+            }
+            __syncthreads();
+        }
+        // 16 steps: the factor is back in copy 0
+        if (tid < 256) {
+            const int r = tid / 16, q = tid % 16;
+            if (r < cw && q <= r) D[(size_t)(c0 + r) * n + c0 + q] = Lb[0][r][q];
+        }
+        // rows below the block: x L11^T = a, column by column, in place
+        for (int i = c0 + 16 + tid; i < n; i += 512) {
+            double *x = D + (size_t)i * n + c0;
+            for (int c = 0; c < 16; ++c) {
+                double t = x[c];
+                for (int q = 0; q < c; ++q) t = t - x[q] * Lb[0][c][q];
+                x[c] = t / Lb[0][c][c];
+            }
+        }
+        __syncthreads();
+        // trailing update of the tiles (I, J), p < J <= I < np
+        const int side = np - p - 1;
+        const int ntile = side * (side + 1) / 2;
+        const int li = lane % 16, lk = lane / 16;
+        for (int t = wave; t < ntile; t += 8) {
+            int I = 0, tt = t;
+            while (tt > I) {
+                tt -= I + 1;
+                ++I;
+            }
+            const int i0 = 16 * (p + 1 + I), j0 = 16 * (p + 1 + tt);
+            chol_d4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + lk + 4 * r, j = j0 + li;
+                acc[r] = (i < n && j < n) ? D[(size_t)i * n + j] : 0.0;
+            }
+            const int ia = i0 + li, jb = j0 + li;
+#pragma unroll
+            for (int k0 = 0; k0 < 16; k0 += 4) {
+                const int k = c0 + k0 + lk;
+                const double a = ia < n ? -D[(size_t)ia * n + k] : 0.0;
+                const double b = jb < n ? D[(size_t)jb * n + k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + lk + 4 * r, j = j0 + li;
+                if (i < n && j <= i) D[(size_t)i * n + j] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && bad) atomicOr(&flags[5], 1);
+}
+
 // X = (L L^T)^{-1}: one wavefront per column j, forward then backward
 // substitution with the inner products split over the 64 lanes.
 __global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, double *X) {
@@ -2524,7 +2617,8 @@ void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v
     HIPC(hipGetLastError());
 }
 void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s) {
-    k_cholesky<<<1, 1024, 0, s>>>(n, D, flags);
+    if (n <= kCholMfmaMax) k_cholesky_mfma<<<1, 512, 0, s>>>(n, D, flags);
+    else k_cholesky<<<1, 1024, 0, s>>>(n, D, flags);
     HIPC(hipGetLastError());
 }
 void chol_inverse(int n, const double *L, double *X, hipStream_t s) {

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2102_07417_amd import problems as PB
-from tests.helpers import dense
+from tests.helpers import dense, from_dense
 
 pytestmark = pytest.mark.gpu
 
@@ -523,3 +523,37 @@ def test_wide_tiles_keep_int32_columns(camg):
     assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
     assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 100, 255, 256, 257, 400])
+def test_last_level_factor_sizes(camg, n):
+    """The last level's factorisation (blocked on the matrix cores up to 256
+    unknowns, unblocked above) across panel edges: its inverse against
+    numpy, and a one-level solve against a dense solve."""
+    rng = np.random.default_rng(n)
+    d = 2.0 + rng.random(n)
+    Ad = np.diag(d) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    if n > 20:  # a few long-range couplings so the factor is not banded
+        for i in range(0, n - 17, 7):
+            Ad[i, i + 17] = Ad[i + 17, i] = -0.3
+            Ad[i, i] += 0.3
+            Ad[i + 17, i + 17] += 0.3
+    def csr(M):
+        n_, _, rp, ci, v = from_dense(M)
+        return PB.CSR(n_, rp, ci, v)
+
+    s = camg.Solver(csr(Ad), max_coarse=1000)
+    assert s.nlev == 1
+    inv = np.linalg.inv(Ad)
+    np.testing.assert_allclose(s.coarse_inverse(), inv, rtol=0, atol=1e-12 * np.abs(inv).max())
+    b = PB.rhs(n)
+    r = s.solve(b)
+    assert r.status == camg.OK
+    np.testing.assert_allclose(r.x, np.linalg.solve(Ad, b), rtol=0, atol=1e-11 * np.abs(np.linalg.solve(Ad, b)).max())
+    s.close()
+    # an indefinite last level is refused by either factorisation
+    Ai = Ad.copy()
+    Ai[n // 2, n // 2] = -1.0
+    with pytest.raises(camg.CamgError) as e:
+        camg.Solver(csr(Ai), max_coarse=1000)
+    assert e.value.status == camg.E_NOT_SPD
