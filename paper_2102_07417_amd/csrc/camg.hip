@@ -221,13 +221,11 @@ RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
         tile_starts(M.nr, M.rp, c.W, c.ntiles, c.tstart, s);
         // 16-bit column differences per tile: 10 bytes per FP64 nonzero
         // instead of 12 (6 instead of 8 in FP32) where the tiles allow them
-        int32_t *tb = tmp.alloc<int32_t>((size_t)c.ntiles);
-        uint16_t *of = tmp.alloc<uint16_t>(padded(M.nnz));
-        if (tile_offsets(c.ntiles, c.tstart, M.rp, M.ci, tb, of, tmp, s)) {
-            c.tbase = h.pool.alloc<int32_t>((size_t)c.ntiles);
+        int32_t *tb = h.pool.alloc<int32_t>((size_t)c.ntiles);
+        if (tile_bases(c.ntiles, c.tstart, M.rp, M.ci, tb, tmp, s)) {
+            c.tbase = tb;
             c.off = h.pool.alloc<uint16_t>(padded(M.nnz));
-            HIPC(hipMemcpyAsync(c.tbase, tb, sizeof(int32_t) * (size_t)c.ntiles, hipMemcpyDeviceToDevice, s));
-            HIPC(hipMemcpyAsync(c.off, of, sizeof(uint16_t) * padded(M.nnz), hipMemcpyDeviceToDevice, s));
+            tile_diffs(c.ntiles, c.tstart, M.rp, M.ci, c.tbase, c.off, s);
             c.use_off = h.compact_cols;
         }
     }

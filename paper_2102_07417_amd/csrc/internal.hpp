@@ -260,11 +260,13 @@ void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s);
-// per tile the smallest column (tbase) and 16-bit column differences (off,
-// nnz + padding entries); false, with off untouched, when a tile spans 65536
-// columns or more
-bool tile_offsets(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase,
-                  uint16_t *off, Pool &tmp, hipStream_t s);
+// compact columns: tile_bases writes each tile's smallest column and tells
+// whether every tile spans fewer than 65536 columns; tile_diffs then writes
+// the 16-bit differences (nnz entries of off)
+bool tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
+                hipStream_t s);
+void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,
+                uint16_t *off, hipStream_t s);
 
 // ---------------------------------------------------------------- SpGEMM (spgemm.hip)
 // Z = X Y with the full symbolic pattern, rows sorted; for every output

@@ -2468,35 +2468,38 @@ __global__ void k_tile_starts(int n, const int32_t *rp, int W, int ntiles, int32
 
 
 // Compact column indices of a tiled matrix: tile t stores its smallest column
-// as tbase[t] and every nonzero as the 16-bit difference to it.  Pass 1
-// (write = false) finds the bases and sets flag[0] when a tile spans 65536
-// columns or more; pass 2 writes the differences.  One block per tile.
-__global__ void __launch_bounds__(kBlock) k_tile_offsets(int ntiles, const int32_t *__restrict__ tstart,
-                                                         const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ ci, int32_t *tbase,
-                                                         uint16_t *off, int32_t *flag, int write) {
-    __shared__ int base_s;
+// as tbase[t] and every nonzero as the 16-bit difference to it.  One block
+// per tile: k_tile_bases finds the bases and sets flag[0] when a tile spans
+// 65536 columns or more; k_tile_diffs writes the differences.
+__global__ void __launch_bounds__(kBlock) k_tile_bases(int ntiles, const int32_t *__restrict__ tstart,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, int32_t *tbase,
+                                                       int32_t *flag) {
     const int t = blockIdx.x;
     if (t >= ntiles) return;
     const int e0 = rp[tstart[t]], e1 = rp[tstart[t + 1]];
-    if (!write) {
-        int lo = INT32_MAX, hi = 0;
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
-            lo = min(lo, ci[e]);
-            hi = max(hi, ci[e]);
-        }
-        const unsigned long long mlo = block_max_u64<kBlock>((unsigned long long)(INT32_MAX - lo));
-        const unsigned long long mhi = block_max_u64<kBlock>((unsigned long long)hi);
-        if (threadIdx.x == 0) {
-            const int blo = INT32_MAX - (int)mlo, bhi = (int)mhi;
-            tbase[t] = e1 > e0 ? blo : 0;
-            if (e1 > e0 && bhi - blo > 65535) flag[0] = 1;
-        }
-        return;
+    int lo = INT32_MAX, hi = 0;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
+        lo = min(lo, ci[e]);
+        hi = max(hi, ci[e]);
     }
-    if (threadIdx.x == 0) base_s = tbase[t];
-    __syncthreads();
-    const int base = base_s;
+    const unsigned long long mlo = block_max_u64<kBlock>((unsigned long long)(INT32_MAX - lo));
+    const unsigned long long mhi = block_max_u64<kBlock>((unsigned long long)hi);
+    if (threadIdx.x == 0) {
+        const int blo = INT32_MAX - (int)mlo, bhi = (int)mhi;
+        tbase[t] = e1 > e0 ? blo : 0;
+        if (e1 > e0 && bhi - blo > 65535) flag[0] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_tile_diffs(int ntiles, const int32_t *__restrict__ tstart,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const int32_t *__restrict__ tbase, uint16_t *off) {
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int e0 = rp[tstart[t]], e1 = rp[tstart[t + 1]];
+    const int base = tbase[t];
     for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) off[e] = (uint16_t)(ci[e] - base);
 }
 }  // namespace
@@ -2630,20 +2633,23 @@ void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, h
     HIPC(hipGetLastError());
 }
 
-bool tile_offsets(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase,
-                  uint16_t *off, Pool &tmp, hipStream_t s) {
+bool tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
+                hipStream_t s) {
     if (ntiles <= 0) return false;
     int32_t *flag = tmp.alloc<int32_t>(1);
     HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    k_tile_offsets<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, off, flag, 0);
+    k_tile_bases<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, flag);
     HIPC(hipGetLastError());
     int32_t hf = 0;
     HIPC(hipMemcpyAsync(&hf, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    if (hf) return false;
-    k_tile_offsets<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, off, flag, 1);
+    return hf == 0;
+}
+
+void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,
+                uint16_t *off, hipStream_t s) {
+    k_tile_diffs<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, off);
     HIPC(hipGetLastError());
-    return true;
 }
 
 

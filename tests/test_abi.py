@@ -67,7 +67,7 @@ def test_argument_errors_without_device(lib):
     assert len(lib.camg_last_error()) >= 0
 
 
-@pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 2), ("theta", 1.5),
+@pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 3), ("theta", 1.5),
                                          ("precision", 3), ("rap_chunk", -1), ("interp", 5),
                                          ("psmooth", 2), ("pfilter", 0.0), ("srqm_iters", -1),
                                          ("srqm_iters", 101), ("srqm_iters", 1)])
