@@ -219,13 +219,16 @@ RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
     if (c.tile) {
         c.tstart = h.pool.alloc<int32_t>((size_t)c.ntiles + 1);
         tile_starts(M.nr, M.rp, c.W, c.ntiles, c.tstart, s);
-        // 16-bit column differences per tile: 10 bytes per FP64 nonzero
-        // instead of 12 (6 instead of 8 in FP32) where the tiles allow them
-        int32_t *tb = h.pool.alloc<int32_t>((size_t)c.ntiles);
-        if (tile_bases(c.ntiles, c.tstart, M.rp, M.ci, tb, tmp, s)) {
+        // 16-bit column words (window, offset) per tile: 10 bytes per FP64
+        // nonzero instead of 12 (6 instead of 8 in FP32) where the tiles allow
+        // them
+        int32_t *tb = h.pool.alloc<int32_t>((size_t)c.ntiles * kTileWins);
+        const int mode = tile_bases(c.ntiles, c.tstart, M.rp, M.ci, tb, tmp, s);
+        if (mode) {
             c.tbase = tb;
             c.off = h.pool.alloc<uint16_t>(padded(M.nnz));
-            tile_diffs(c.ntiles, c.tstart, M.rp, M.ci, c.tbase, c.off, s);
+            c.off_mode = mode;
+            tile_diffs(c.ntiles, c.tstart, M.rp, M.ci, c.tbase, c.off, mode, s);
             c.use_off = h.compact_cols;
         }
     }

@@ -91,11 +91,13 @@ struct RowCfg {
     int tpb = 0;          // consecutive tiles per block
     int maxrow = 0;
     int32_t *tstart = nullptr;  // device: first row of each tile
-    // compact column indices (tile mode, when every tile spans fewer than
-    // 65536 columns): column = tbase[tile] + off[nonzero]; use_off switches
-    // the row kernels between them and the int32 columns (the same results)
+    // compact column indices (tile mode, when kTileWins windows of 2^kWinBits
+    // columns cover every tile): column = tbase[tile * kTileWins + (off >>
+    // kWinBits)] + (off & (2^kWinBits - 1)); use_off switches the row kernels
+    // between them and the int32 columns (the same results)
     int32_t *tbase = nullptr;
     uint16_t *off = nullptr;
+    int off_mode = 0;  // 1: column = tbase[tile * kTileWins] + off; 2: windows as above
     bool use_off = false;
 };
 
@@ -260,13 +262,16 @@ void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s);
-// compact columns: tile_bases writes each tile's smallest column and tells
-// whether every tile spans fewer than 65536 columns; tile_diffs then writes
-// the 16-bit differences (nnz entries of off)
-bool tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
-                hipStream_t s);
+// compact columns: tile_bases places up to kTileWins windows of 2^kWinBits
+// columns per tile (tbase: ntiles * kTileWins, slot 0 = the tile's smallest
+// column) and returns 1 when one 65536-column span covers every tile, 2 when
+// the windows do, 0 otherwise; tile_diffs then writes the 16-bit words of
+// that mode
+constexpr int kTileWins = 8, kWinBits = 13;
+int tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
+               hipStream_t s);
 void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,
-                uint16_t *off, hipStream_t s);
+                uint16_t *off, int mode, hipStream_t s);
 
 // ---------------------------------------------------------------- SpGEMM (spgemm.hip)
 // Z = X Y with the full symbolic pattern, rows sorted; for every output

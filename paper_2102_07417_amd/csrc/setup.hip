@@ -2467,40 +2467,87 @@ __global__ void k_tile_starts(int n, const int32_t *rp, int W, int ntiles, int32
 }
 
 
-// Compact column indices of a tiled matrix: tile t stores its smallest column
-// as tbase[t] and every nonzero as the 16-bit difference to it.  One block
-// per tile: k_tile_bases finds the bases and sets flag[0] when a tile spans
-// 65536 columns or more; k_tile_diffs writes the differences.
+// Compact column indices of a tiled matrix: tile t keeps up to kTileWins
+// windows of 2^kWinBits columns, chosen greedily (window w starts at the
+// smallest column at or past the end of window w - 1), in tbase[t * kTileWins
+// ...]; a nonzero stores its window in the top bits of a 16-bit word and its
+// offset in the window in the low kWinBits bits.  When every tile spans fewer
+// than 65536 columns the words are simply column - (first window start), and
+// the kernels need no window table.  One block per tile: k_tile_bases places
+// the windows (unused slots repeat the last one), sets flag[0] when the tile
+// needs more and flag[1] when it spans 65536 columns or more; k_tile_diffs
+// writes the 16-bit words (single = 1: plain differences).
 __global__ void __launch_bounds__(kBlock) k_tile_bases(int ntiles, const int32_t *__restrict__ tstart,
                                                        const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, int32_t *tbase,
                                                        int32_t *flag) {
+    __shared__ int next_s;
     const int t = blockIdx.x;
     if (t >= ntiles) return;
     const int e0 = rp[tstart[t]], e1 = rp[tstart[t + 1]];
-    int lo = INT32_MAX, hi = 0;
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
-        lo = min(lo, ci[e]);
-        hi = max(hi, ci[e]);
+    {  // one 65536-column span from the smallest column?
+        int lo = INT32_MAX, hi = 0;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
+            lo = min(lo, ci[e]);
+            hi = max(hi, ci[e]);
+        }
+        const unsigned long long mlo = block_max_u64<kBlock>((unsigned long long)(INT32_MAX - lo));
+        const unsigned long long mhi = block_max_u64<kBlock>((unsigned long long)hi);
+        if (threadIdx.x == 0 && e1 > e0 && (int)mhi - (INT32_MAX - (int)mlo) > 65535) flag[1] = 1;
     }
-    const unsigned long long mlo = block_max_u64<kBlock>((unsigned long long)(INT32_MAX - lo));
-    const unsigned long long mhi = block_max_u64<kBlock>((unsigned long long)hi);
-    if (threadIdx.x == 0) {
-        const int blo = INT32_MAX - (int)mlo, bhi = (int)mhi;
-        tbase[t] = e1 > e0 ? blo : 0;
-        if (e1 > e0 && bhi - blo > 65535) flag[0] = 1;
+    int from = 0, last = 0;
+    for (int w = 0; w < kTileWins; ++w) {
+        int lo = INT32_MAX;
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock)
+            if (ci[e] >= from) lo = min(lo, ci[e]);
+        const unsigned long long m = block_max_u64<kBlock>((unsigned long long)(INT32_MAX - lo));
+        if (threadIdx.x == 0) next_s = INT32_MAX - (int)m;
+        __syncthreads();
+        const int start = next_s;
+        __syncthreads();
+        if (start == INT32_MAX) {  // every column is covered
+            for (int v = w + (int)threadIdx.x; v < kTileWins; v += kBlock) tbase[t * kTileWins + v] = last;
+            return;
+        }
+        if (threadIdx.x == 0) tbase[t * kTileWins + w] = start;
+        last = start;
+        from = start > INT32_MAX - (1 << kWinBits) ? INT32_MAX : start + (1 << kWinBits);
+    }
+    // columns past the last window: the tile needs more windows
+    int over = 0;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) over |= ci[e] >= from;
+    const unsigned long long any = block_max_u64<kBlock>((unsigned long long)over);
+    if (threadIdx.x == 0 && any) {
+        flag[0] = 1;
+        flag[1] = 1;
     }
 }
 
 __global__ void __launch_bounds__(kBlock) k_tile_diffs(int ntiles, const int32_t *__restrict__ tstart,
                                                        const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci,
-                                                       const int32_t *__restrict__ tbase, uint16_t *off) {
+                                                       const int32_t *__restrict__ tbase, uint16_t *off, int single) {
     const int t = blockIdx.x;
     if (t >= ntiles) return;
     const int e0 = rp[tstart[t]], e1 = rp[tstart[t + 1]];
-    const int base = tbase[t];
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) off[e] = (uint16_t)(ci[e] - base);
+    int w[kTileWins];
+#pragma unroll
+    for (int v = 0; v < kTileWins; ++v) w[v] = tbase[t * kTileWins + v];
+    if (single) {
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) off[e] = (uint16_t)(ci[e] - w[0]);
+        return;
+    }
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kBlock) {
+        const int c = ci[e];
+        int slot = 0, base = w[0];
+#pragma unroll
+        for (int v = 1; v < kTileWins; ++v)
+            if (c >= w[v] && w[v] > w[v - 1]) {
+                slot = v;
+                base = w[v];
+            }
+        off[e] = (uint16_t)((slot << kWinBits) | (c - base));
+    }
 }
 }  // namespace
 
@@ -2633,22 +2680,22 @@ void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, h
     HIPC(hipGetLastError());
 }
 
-bool tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
-                hipStream_t s) {
-    if (ntiles <= 0) return false;
-    int32_t *flag = tmp.alloc<int32_t>(1);
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+int tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
+               hipStream_t s) {  // tbase: ntiles * kTileWins
+    if (ntiles <= 0) return 0;
+    int32_t *flag = tmp.alloc<int32_t>(2);
+    HIPC(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
     k_tile_bases<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, flag);
     HIPC(hipGetLastError());
-    int32_t hf = 0;
-    HIPC(hipMemcpyAsync(&hf, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t hf[2] = {0, 0};
+    HIPC(hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    return hf == 0;
+    return hf[1] == 0 ? 1 : hf[0] == 0 ? 2 : 0;
 }
 
 void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,
-                uint16_t *off, hipStream_t s) {
-    k_tile_diffs<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, off);
+                uint16_t *off, int mode, hipStream_t s) {
+    k_tile_diffs<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, off, mode == 1);
     HIPC(hipGetLastError());
 }
 

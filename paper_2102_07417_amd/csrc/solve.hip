@@ -44,8 +44,9 @@ struct MatArg {
     const int32_t *__restrict__ ci;
     const T *__restrict__ v;
     const int32_t *__restrict__ tstart;  // tile mode: first row of each tile (ntiles + 1)
-    const int32_t *__restrict__ tbase;   // tile mode with compact columns: smallest column per tile
-    const uint16_t *__restrict__ off;    //   and column - tbase per nonzero (null: use ci)
+    const int32_t *__restrict__ tbase;   // tile mode with compact columns: kTileWins window starts per tile
+    const uint16_t *__restrict__ off;    //   and the 16-bit word per nonzero (null: use ci)
+    int off_mode;                        //   1: column = first start + word; 2: window in the top bits
     int n;
     int rpt;     // vector mode: rows per block
     int ntiles;  // tile mode
@@ -63,7 +64,7 @@ const float *vals<float>(const Csr &A) { return A.v32; }
 template <class T>
 MatArg<T> mat_arg(const Csr &A, const RowCfg &c, const T *v = nullptr) {
     return MatArg<T>{A.rp,        A.ci,  v ? v : vals<T>(A), c.tstart, c.use_off ? c.tbase : nullptr,
-                     c.use_off ? c.off : nullptr, A.nr, c.rpt, c.ntiles, c.tpb, c.tile_nnz};
+                     c.use_off ? c.off : nullptr, c.off_mode, A.nr, c.rpt, c.ntiles, c.tpb, c.tile_nnz};
 }
 
 // Sum of partials[0..n) in index order, result in every thread of the block.
@@ -94,15 +95,27 @@ __device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
 }
 
 // Four column indices of the nonzeros idx .. idx+3 (idx a multiple of 4):
-// the int32 columns, or the tile's base plus 16-bit differences.
-template <bool OFF, class T>
-__device__ __forceinline__ v4i cols4(const MatArg<T> &M, int idx, int base) {
-    if constexpr (OFF) {
-        const v4us o = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
-        return v4i{base + (int)o.x, base + (int)o.y, base + (int)o.z, base + (int)o.w};
-    } else {
+// MODE 0 the int32 columns; MODE 1 the tile's smallest column plus the
+// 16-bit word; MODE 2 the start of the window named by the word's top bits
+// (from LDS, wins) plus its low bits.
+__device__ __forceinline__ int decode_col(const int *wins, unsigned o) {
+    return wins[o >> kWinBits] + (int)(o & ((1u << kWinBits) - 1));
+}
+template <int MODE, class T>
+__device__ __forceinline__ v4i cols4(const MatArg<T> &M, int idx, const int *wins, int base) {
+    if constexpr (MODE == 0) {
+        (void)wins;
         (void)base;
         return __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
+    } else {
+        const v4us o = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
+        if constexpr (MODE == 1) {
+            (void)wins;
+            return v4i{base + (int)o.x, base + (int)o.y, base + (int)o.z, base + (int)o.w};
+        } else {
+            (void)base;
+            return v4i{decode_col(wins, o.x), decode_col(wins, o.y), decode_col(wins, o.z), decode_col(wins, o.w)};
+        }
     }
 }
 
@@ -113,16 +126,17 @@ __device__ __forceinline__ v4i cols4(const MatArg<T> &M, int idx, int base) {
 // vector stays inside the allocation).  Entries outside the tile gather
 // column 0 instead and store into the spare LDS slot prod[junk] (no branch
 // anywhere, so all the loads stay in flight).
-template <bool OFF, class T, class G>
-__device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m, int base) {
+template <int MODE, class T, class G>
+__device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m,
+                                            const int *wins, int base) {
     const int junk = M.junk;
     const int a0 = e0 & ~3;
     const int span = e0 + m - a0;
     constexpr int STEP = 4 * kBlock;
     int k = 4 * threadIdx.x;
     for (; k + STEP < span; k += 2 * STEP) {
-        const v4i c0 = cols4<OFF>(M, a0 + k, base);
-        const v4i c1 = cols4<OFF>(M, a0 + k + STEP, base);
+        const v4i c0 = cols4<MODE>(M, a0 + k, wins, base);
+        const v4i c1 = cols4<MODE>(M, a0 + k + STEP, wins, base);
         T v0[4], v1[4];
         load4(M.v + a0 + k, v0);
         load4(M.v + a0 + k + STEP, v1);
@@ -143,7 +157,7 @@ __device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *p
         }
     }
     for (; k < span; k += STEP) {
-        const v4i c0 = cols4<OFF>(M, a0 + k, base);
+        const v4i c0 = cols4<MODE>(M, a0 + k, wins, base);
         T v0[4];
         load4(M.v + a0 + k, v0);
         const int cc[4] = {c0.x, c0.y, c0.z, c0.w};
@@ -192,19 +206,27 @@ __device__ __forceinline__ void stream_tile_scalar(const MatArg<T> &M, const G &
 // In tile mode the first row a lane group owns has its row pointers and its
 // epilogue operands loaded before phase 1, so those loads overlap the
 // streaming of the tile; phase 2 then only touches LDS and the output.
-template <class T, int LPR, bool TILE, class G, class E>
+// SHAPE 0: vector rows; 1: tiles with int32 or one-base compact columns;
+// 2: tiles with windowed compact columns (a separate kernel, so the other
+// shapes keep their register budget)
+template <class T, int LPR, int SHAPE, class G, class E>
 __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E &epi, T *prod, double &dot) {
     const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
     constexpr int RPP = kBlock / LPR;  // rows per pass
     using Pre = typename E::Pre;
-    if (TILE) {
+    if constexpr (SHAPE > 0) {
         const int b = xcd_block();
         const int t0 = (int)((int64_t)b * M.ntiles / gridDim.x);
         const int t1 = (int)((int64_t)(b + 1) * M.ntiles / gridDim.x);
+        __shared__ int wins[kTileWins];  // compact columns: this tile's window starts
         for (int t = t0; t < t1; ++t) {
             const int r0 = M.tstart[t], r1 = M.tstart[t + 1];
             if (r0 == r1) continue;
             const int e0 = M.rp[r0], m = M.rp[r1] - e0;
+            if constexpr (SHAPE == 2) {  // the previous tile's readers passed the barrier that ended it
+                if (threadIdx.x < kTileWins) wins[threadIdx.x] = M.tbase[(size_t)t * kTileWins + threadIdx.x];
+                __syncthreads();
+            }
             const int i = r0 + grp;
             const bool has = i < r1;
             int qa = 0, qz = 0;
@@ -215,8 +237,9 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
                 if (sl == 0) pre = epi.load(i);
             }
             if constexpr (G::kLoads > 1) stream_tile_scalar(M, g, prod, e0, m);
-            else if (M.off) stream_tile<true>(M, g, prod, e0, m, M.tbase[t]);
-            else stream_tile<false>(M, g, prod, e0, m, 0);
+            else if constexpr (SHAPE == 2) stream_tile<2>(M, g, prod, e0, m, wins, 0);
+            else if (M.off) stream_tile<1>(M, g, prod, e0, m, wins, M.tbase[(size_t)t * kTileWins]);
+            else stream_tile<0>(M, g, prod, e0, m, wins, 0);
             __syncthreads();
             {
                 T acc = 0;
@@ -372,14 +395,14 @@ struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
 };
 
 // ------------------------------------------------------------------ kernels
-template <class T, int LPR, bool TILE, bool DOT, class G, class E>
+template <class T, int LPR, int SHAPE, bool DOT, class G, class E>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
                                                  const PcgState *st) {
     if (st && st->done) return;
     extern __shared__ double smem_d[];
     T *prod = reinterpret_cast<T *>(smem_d);
     double dot = 0.0;
-    run_rows<T, LPR, TILE>(M, g, e, prod, dot);
+    run_rows<T, LPR, SHAPE>(M, g, e, prod, dot);
     if (DOT) {
         const double b = block_sum<kBlock>(dot);
         if (threadIdx.x == 0) {
@@ -560,24 +583,31 @@ void launch_rows(const Csr &A, const RowCfg &c, const G &g, const E &e, double *
                  const PcgState *st, hipStream_t s, const T *values = nullptr) {
     const MatArg<T> M = mat_arg<T>(A, c, values);
     const size_t smem = c.tile ? (size_t)(c.tile_nnz + 1) * sizeof(T) : 0;
+    const int shape = !c.tile ? 0 : (M.off && M.off_mode == 2) ? 2 : 1;
     if (t_ev_start) {  // timed launch: the events bracket the kernel's execution
         hipEvent_t a = t_ev_start, b = t_ev_stop;
         t_ev_start = t_ev_stop = nullptr;
-        if (c.tile) {
-            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, true, DOT, G, E>, dim3(c.grid), dim3(kBlock),
-                                                          (uint32_t)smem, s, a, b, 0, M, g, e, partials, nout, st)));
+        const dim3 gr(c.grid), bl(kBlock);
+        const uint32_t sm = (uint32_t)smem;
+        if (shape == 1) {
+            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, 1, DOT, G, E>, gr, bl, sm, s, a, b, 0, M, g, e,
+                                                          partials, nout, st)));
+        } else if (shape == 2) {
+            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, 2, DOT, G, E>, gr, bl, sm, s, a, b, 0, M, g, e,
+                                                          partials, nout, st)));
         } else {
-            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, false, DOT, G, E>, dim3(c.grid),
-                                                          dim3(kBlock), 0u, s, a, b, 0, M, g, e, partials, nout,
-                                                          st)));
+            CAMG_LPR_SWITCH(c.lpr, (hipExtLaunchKernelGGL(k_rows<T, L, 0, DOT, G, E>, gr, bl, sm, s, a, b, 0, M, g, e,
+                                                          partials, nout, st)));
         }
         HIPC(hipGetLastError());
         return;
     }
-    if (c.tile) {
-        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, true, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
+    if (shape == 1) {
+        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, 1, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
+    } else if (shape == 2) {
+        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, 2, DOT, G, E><<<c.grid, kBlock, smem, s>>>(M, g, e, partials, nout, st)));
     } else {
-        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, false, DOT, G, E><<<c.grid, kBlock, 0, s>>>(M, g, e, partials, nout, st)));
+        CAMG_LPR_SWITCH(c.lpr, (k_rows<T, L, 0, DOT, G, E><<<c.grid, kBlock, 0, s>>>(M, g, e, partials, nout, st)));
     }
     HIPC(hipGetLastError());
 }

@@ -470,18 +470,36 @@ def test_fsai_two_steps_and_mixed(camg):
 
 
 # ----------------------------------------------------------------- compact columns
-def _far_coupled_chain(n=100_000, far=70_000):
-    """1D Laplacian plus a weak coupling of i and i + far for every 1000th i:
-    the tiles holding those rows span more than 65536 columns."""
+def _far_coupled_chain(n=100_000, far=9_000, reach=9):
+    """1D Laplacian plus weak couplings of i with i + far, ..., i + reach*far
+    for every 1000th i: a tile holding such a row needs more than the eight
+    windows of 8192 columns that compact columns allow."""
     import scipy.sparse as sp
     main = 2.2 * np.ones(n)
     A = sp.diags([-np.ones(n - 1), main, -np.ones(n - 1)], [-1, 0, 1], format="lil")
-    for i in range(0, n - far, 1000):
-        A[i, i + far] = -0.1
-        A[i + far, i] = -0.1
+    for i in range(0, n - reach * far, 1000):
+        for k in range(1, reach + 1):
+            j = i + k * far
+            A[i, j] = A[j, i] = -0.1
+            A[i, i] += 0.1
+            A[j, j] += 0.1
     A = A.tocsr()
     A.sort_indices()
     return PB.CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def _poisson3d_box(nx, ny, nz):
+    """7-point Poisson on an nx x ny x nz box (Dirichlet), x fastest."""
+    import scipy.sparse as sp
+
+    def lap(m):
+        return sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])
+
+    Ix, Iy, Iz = sp.identity(nx), sp.identity(ny), sp.identity(nz)
+    A = (sp.kron(Iz, sp.kron(Iy, lap(nx))) + sp.kron(Iz, sp.kron(lap(ny), Ix)) + sp.kron(lap(nz), sp.kron(Iy, Ix)))
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    return PB.CSR(A.shape[0], A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
 
 
 @pytest.mark.parametrize("name,kw", [("lognormal3d_24", {}), ("lognormal3d_24", {"precision": 1}),
@@ -508,6 +526,26 @@ def test_compact_columns_bitwise(camg, name, kw):
     s.set_option(camg.OPT_COMPACT_COLS, 1)
     r2 = s.solve(b)
     assert np.array_equal(r2.x, r1.x)
+    s.close()
+
+
+def test_compact_columns_with_several_windows(camg):
+    """A 260 x 260 x 3 grid: its planes of 67,600 unknowns put each tile's
+    columns into three bands, beyond one 65536-column span; the windows of
+    the compact columns cover them, bitwise like the int32 columns and within
+    the oracle's tolerance."""
+    print("[gpu] compact columns: several windows", flush=True)
+    A = _poisson3d_box(260, 260, 3)
+    b = PB.rhs(A.n)
+    s = camg.Solver(A)
+    assert s.info.compact_cols & 1
+    r1 = s.solve(b)
+    s.set_option(camg.OPT_COMPACT_COLS, 0)
+    r0 = s.solve(b)
+    assert r1.iters == r0.iters and np.array_equal(r1.x, r0.x)
+    ro = O.Hierarchy(A).solve(b, 1e-8)
+    assert abs(r1.iters - ro.iters) <= 1
+    assert np.linalg.norm(r1.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
     s.close()
 
 
