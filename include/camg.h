@@ -372,10 +372,12 @@ camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_
  * every matrix of the hierarchy (entries per unrolled step, LDS chunk, grid)
  * and keep the fastest, cached per matrix signature for the process; the
  * results are bitwise the same as untuned.  CAMG_OPT_COMPACT_COLS (default
- * 1): the single-system row kernels read each tiled matrix's columns as a
- * per-tile base plus 16-bit differences where every tile spans fewer than
- * 65536 columns (10 bytes per FP64 nonzero instead of 12); 0 reads the int32
- * columns; the results are bitwise the same.
+ * 1): the single-system row kernels read each tiled matrix's columns as
+ * 16-bit words (the difference to the tile's smallest column when the tile
+ * spans fewer than 65536 columns, else a window of 8192 columns out of at
+ * most eight per tile and the offset in it) where every tile can be encoded
+ * (10 bytes per FP64 nonzero instead of 12); 0 reads the int32 columns; the
+ * results are bitwise the same.
  */
 enum { CAMG_OPT_GRAPH = 1, CAMG_OPT_AUTOTUNE = 2, CAMG_OPT_COMPACT_COLS = 3 };
 camg_status camg_set_option(camg_handle h, int32_t option, int64_t value);
