@@ -9,7 +9,8 @@
 //    loads, forms a_ij * g(x_j) for every nonzero (eight gathers in flight
 //    per thread) and parks the products in LDS; phase 2 lets `lpr` lanes per
 //    row add them up and runs the row's epilogue.  Used whenever the longest
-//    row fits the LDS reserve (every matrix of the workloads here).
+//    row fits the LDS reserve (every matrix of the workloads here).  FP32
+//    tiles of long rows load the next tile during phase 2.
 //  - vector: `lpr` lanes walk each row directly (rows too long for a tile).
 // Blocks are renumbered so that each XCD owns one contiguous slab of rows
 // (its L2 then serves the gathered vector entries those rows share).
@@ -201,6 +202,138 @@ __device__ __forceinline__ void stream_tile_scalar(const MatArg<T> &M, const G &
     for (; k < m; k += kBlock) prod[k] = M.v[e0 + k] * g(M.ci[e0 + k]);
 }
 
+// Phase 1 split in two for a pipelined tile loop: tile_fetch issues the
+// loads of the first two 4*kBlock-entry steps of a tile into registers (the
+// column words as stored, so nothing waits on them), tile_consume gathers,
+// multiplies and parks the products, then streams whatever lies beyond the
+// two steps as stream_tile does.  Entries past the tile read column 0 (or
+// the tile base) and land in prod[junk], as in stream_tile.
+template <int MODE, class T>
+struct TileRegs {
+    using C = std::conditional_t<MODE == 0, v4i, v4us>;
+    C c[2];
+    T v[2][4];
+};
+template <int MODE, class T>
+__device__ __forceinline__ void tile_fetch(const MatArg<T> &M, TileRegs<MODE, T> &R, int e0, int m) {
+    const int a0 = e0 & ~3, span = e0 + m - a0;
+    constexpr int STEP = 4 * kBlock;
+    const int k = 4 * threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (k + h * STEP < span) {
+            const int idx = a0 + k + h * STEP;
+            if constexpr (MODE == 0) R.c[h] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
+            else R.c[h] = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
+            load4(M.v + idx, R.v[h]);
+        } else {
+            R.c[h] = typename TileRegs<MODE, T>::C{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) R.v[h][u] = 0;
+        }
+    }
+}
+template <int MODE, class T, class G>
+__device__ __forceinline__ void tile_consume(const MatArg<T> &M, const G &g, T *prod, const TileRegs<MODE, T> &R,
+                                             int e0, int m, int base) {
+    const int junk = M.junk;
+    const int a0 = e0 & ~3;
+    const int span = e0 + m - a0;
+    constexpr int STEP = 4 * kBlock;
+    const int k = 4 * threadIdx.x;
+    int cc[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if constexpr (MODE == 0) cc[4 * h + u] = R.c[h][u];
+            else cc[4 * h + u] = base + (int)R.c[h][u];
+        }
+    }
+    const int qb = a0 + k - e0;
+    T gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int q = qb + (u & 3) + (u >> 2) * STEP;
+        gv[u] = g((q >= 0 && q < m) ? cc[u] : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int q = qb + (u & 3) + (u >> 2) * STEP;
+        prod[(q >= 0 && q < m) ? q : junk] = R.v[u >> 2][u & 3] * gv[u];
+    }
+    for (int kk = k + 2 * STEP; kk < span; kk += STEP) {
+        const v4i c0 = cols4<MODE>(M, a0 + kk, nullptr, base);
+        T v0[4];
+        load4(M.v + a0 + kk, v0);
+        const int c4[4] = {c0.x, c0.y, c0.z, c0.w};
+        const int q0 = a0 + kk - e0;
+        T g4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g4[u] = g((q0 + u >= 0 && q0 + u < m) ? c4[u] : 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) prod[(q0 + u >= 0 && q0 + u < m) ? q0 + u : junk] = v0[u] * g4[u];
+    }
+}
+
+// The tile loop of SHAPE 1 with the next tile's matrix loads issued before
+// the current tile's row sums, so they travel while phase 2 runs.  The
+// products and their order of summation are those of run_rows.
+template <class T, int LPR, int MODE, class G, class E>
+__device__ __forceinline__ void run_tiles_pipelined(const MatArg<T> &M, const G &g, const E &epi, T *prod,
+                                                    double &dot) {
+    const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
+    constexpr int RPP = kBlock / LPR;
+    using Pre = typename E::Pre;
+    const int b = xcd_block();
+    const int t0 = (int)((int64_t)b * M.ntiles / gridDim.x);
+    const int t1 = (int)((int64_t)(b + 1) * M.ntiles / gridDim.x);
+    if (t0 >= t1) return;
+    int r0 = M.tstart[t0], r1 = M.tstart[t0 + 1];
+    int e0 = M.rp[r0], m = M.rp[r1] - e0;
+    TileRegs<MODE, T> R;
+    tile_fetch<MODE>(M, R, e0, m);
+    for (int t = t0; t < t1; ++t) {
+        // the next tile's bounds, needed where its loads are issued
+        const int nr1 = t + 1 < t1 ? M.tstart[t + 2] : r1;
+        const int ne0 = M.rp[r1], nm = M.rp[nr1] - ne0;
+        const int base = MODE == 1 ? M.tbase[(size_t)t * kTileWins] : 0;
+        const int i = r0 + grp;
+        const bool has = i < r1;
+        int qa = 0, qz = 0;
+        Pre pre{};
+        if (has) {
+            qa = M.rp[i] - e0;
+            qz = M.rp[i + 1] - e0;
+            if (sl == 0) pre = epi.load(i);
+        }
+        tile_consume<MODE>(M, g, prod, R, e0, m, base);
+        __syncthreads();
+        if (t + 1 < t1) tile_fetch<MODE>(M, R, ne0, nm);
+        {
+            T acc = 0;
+            for (int q = qa + sl; q < qz; q += LPR) acc += prod[q];
+            acc = group_sum<LPR>(acc);
+            if (has && sl == 0) epi.finish(i, acc, pre, dot);
+        }
+        for (int ib = r0 + RPP; ib < r1; ib += RPP) {
+            const int i2 = ib + grp;
+            T acc = 0;
+            if (i2 < r1) {
+                const int a2 = M.rp[i2] - e0, z2 = M.rp[i2 + 1] - e0;
+                for (int q = a2 + sl; q < z2; q += LPR) acc += prod[q];
+            }
+            acc = group_sum<LPR>(acc);
+            if (i2 < r1 && sl == 0) epi.finish(i2, acc, epi.load(i2), dot);
+        }
+        __syncthreads();
+        r0 = r1;
+        r1 = nr1;
+        e0 = ne0;
+        m = nm;
+    }
+}
+
 // Walk this block's rows; for each row i call
 //   epi.finish(i, sum_j a_ij g(j), epi.load(i), dot).
 // In tile mode the first row a lane group owns has its row pointers and its
@@ -214,6 +347,15 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
     const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
     constexpr int RPP = kBlock / LPR;  // rows per pass
     using Pre = typename E::Pre;
+    // FP32 tiles of long rows (64 and more nonzeros on average): the next
+    // tile's loads overlap the current tile's row sums.  The FP64 kernels
+    // would spill at eight waves per SIMD, and short-row tiles measured no
+    // gain.
+    if constexpr (SHAPE == 1 && G::kLoads == 1 && sizeof(T) == 4 && LPR >= 8) {
+        if (M.off) run_tiles_pipelined<T, LPR, 1>(M, g, epi, prod, dot);
+        else run_tiles_pipelined<T, LPR, 0>(M, g, epi, prod, dot);
+        return;
+    }
     if constexpr (SHAPE > 0) {
         const int b = xcd_block();
         const int t0 = (int)((int64_t)b * M.ntiles / gridDim.x);

@@ -595,3 +595,63 @@ def test_last_level_factor_sizes(camg, n):
     with pytest.raises(camg.CamgError) as e:
         camg.Solver(csr(Ai), max_coarse=1000)
     assert e.value.status == camg.E_NOT_SPD
+
+
+def _band_with_hubs(n=20_000, half=40, hubs=(1_234, 9_876, 17_000), reach=3_000, seed=11):
+    """A symmetric band of 2*half + 1 entries per row (mean row length over
+    64, so the FP32 row kernels take the pipelined tile loop) plus a few hub
+    rows coupled to `reach` points each: those rows exceed one 2048-entry
+    tile, leaving empty tiles and tiles beyond two streaming steps.  Weakly
+    diagonally dominant with negative couplings, hence SPD."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for d in range(1, half + 1):
+        i = np.arange(n - d)
+        rows.append(i)
+        cols.append(i + d)
+    for h in hubs:
+        j = rng.choice(np.setdiff1d(np.arange(n), np.arange(h - half, h + half + 1)), reach, replace=False)
+        rows.append(np.minimum(h, j))
+        cols.append(np.maximum(h, j))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    w = -rng.uniform(0.5, 1.5, r.size)
+    U = sp.coo_matrix((w, (r, c)), shape=(n, n)).tocsr()
+    U.sum_duplicates()
+    A = U + U.T
+    A = A + sp.diags(1.05 * np.asarray(-A.sum(axis=1)).ravel())
+    A = A.tocsr()
+    A.sort_indices()
+    return PB.CSR(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def test_pipelined_fp32_tiles(camg):
+    """Mixed precision on long rows: the FP32 V-cycle within FP32 rounding of
+    the oracle's, compact and int32 column words bitwise alike, and the
+    solve to a true residual below 1e-8."""
+    print("[gpu] pipelined FP32 tiles: band with hubs", flush=True)
+    A = _band_with_hubs()
+    assert A.row_ptr[-1] / A.n >= 64 and np.diff(A.row_ptr).max() > 2048
+    b = PB.rhs(A.n)
+    o = O.Hierarchy(A, max_iter=3000)
+    s = camg.Solver(A, precision=camg.MIXED_FP32, max_iter=3000)
+    assert s.nlev == o.nlev and s.info.compact_cols & 1
+    y = np.random.default_rng(6).standard_normal(A.n)
+    zo = o.vcycle(y)
+    z1 = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    s.vcycle_dev(_dev(y), z1)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(z1.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"[gpu] FP32 V-cycle against the oracle: {err:.2e}", flush=True)
+    assert err <= 2e-5
+    r1 = s.solve(b)
+    assert r1.status == camg.OK and r1.true_relres < 1e-8
+    s.set_option(camg.OPT_COMPACT_COLS, 0)
+    z0 = torch.zeros_like(z1)
+    s.vcycle_dev(_dev(y), z0)
+    r0 = s.solve(b)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z0)
+    assert r0.iters == r1.iters and np.array_equal(r0.x, r1.x)
+    s.close()
