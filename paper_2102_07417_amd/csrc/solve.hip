@@ -298,21 +298,21 @@ __device__ __forceinline__ void run_tiles_pipelined(const MatArg<T> &M, const G 
         const int nr1 = t + 1 < t1 ? M.tstart[t + 2] : r1;
         const int ne0 = M.rp[r1], nm = M.rp[nr1] - ne0;
         const int base = MODE == 1 ? M.tbase[(size_t)t * kTileWins] : 0;
+        // every lane loads its row's bounds and epilogue operands (a valid
+        // row where it has none), so no branch sits between these loads and
+        // the gathers: the gathers then wait only for the prefetched words
         const int i = r0 + grp;
         const bool has = i < r1;
-        int qa = 0, qz = 0;
-        Pre pre{};
-        if (has) {
-            qa = M.rp[i] - e0;
-            qz = M.rp[i + 1] - e0;
-            if (sl == 0) pre = epi.load(i);
-        }
+        const int ic = has ? i : (r1 > 0 ? r1 - 1 : 0);
+        const int qa = M.rp[ic] - e0, qz = M.rp[ic + 1] - e0;
+        const Pre pre = epi.load(ic);
         tile_consume<MODE>(M, g, prod, R, e0, m, base);
         __syncthreads();
         if (t + 1 < t1) tile_fetch<MODE>(M, R, ne0, nm);
         {
             T acc = 0;
-            for (int q = qa + sl; q < qz; q += LPR) acc += prod[q];
+            if (has)
+                for (int q = qa + sl; q < qz; q += LPR) acc += prod[q];
             acc = group_sum<LPR>(acc);
             if (has && sl == 0) epi.finish(i, acc, pre, dot);
         }
