@@ -9,8 +9,8 @@
 //    loads, forms a_ij * g(x_j) for every nonzero (eight gathers in flight
 //    per thread) and parks the products in LDS; phase 2 lets `lpr` lanes per
 //    row add them up and runs the row's epilogue.  Used whenever the longest
-//    row fits the LDS reserve (every matrix of the workloads here).  FP32
-//    tiles of long rows load the next tile during phase 2.
+//    row fits the LDS reserve (every matrix of the workloads here).  Tiles
+//    of long rows load the next tile during phase 2.
 //  - vector: `lpr` lanes walk each row directly (rows too long for a tile).
 // Blocks are renumbered so that each XCD owns one contiguous slab of rows
 // (its L2 then serves the gathered vector entries those rows share).
@@ -347,11 +347,10 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
     const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
     constexpr int RPP = kBlock / LPR;  // rows per pass
     using Pre = typename E::Pre;
-    // FP32 tiles of long rows (64 and more nonzeros on average): the next
-    // tile's loads overlap the current tile's row sums.  The FP64 kernels
-    // would spill at eight waves per SIMD, and short-row tiles measured no
-    // gain.
-    if constexpr (SHAPE == 1 && G::kLoads == 1 && sizeof(T) == 4 && LPR >= 8) {
+    // Tiles of long rows (64 and more nonzeros on average): the next tile's
+    // loads overlap the current tile's row sums (short-row tiles measured no
+    // gain).
+    if constexpr (SHAPE == 1 && G::kLoads == 1 && LPR >= 8) {
         if (M.off) run_tiles_pipelined<T, LPR, 1>(M, g, epi, prod, dot);
         else run_tiles_pipelined<T, LPR, 0>(M, g, epi, prod, dot);
         return;
@@ -537,8 +536,13 @@ struct EResNorm {  // d = b - A x; dot += d^2; optionally store d
 };
 
 // ------------------------------------------------------------------ kernels
+// Waves per SIMD: eight, except for the pipelined FP64 tile loop, whose
+// prefetched values take 16 more registers; at eight waves it would spill,
+// at six it does not (and measured faster than the plain loop at eight).
+template <class T, int LPR, int SHAPE, class G>
+constexpr int kWaves = (sizeof(T) == 8 && SHAPE == 1 && LPR >= 8 && G::kLoads == 1) ? 6 : 8;
 template <class T, int LPR, int SHAPE, bool DOT, class G, class E>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves<T, LPR, SHAPE, G>, kWaves<T, LPR, SHAPE, G>))) k_rows(MatArg<T> M, G g, E e, double *partials, int32_t *nout,
                                                  const PcgState *st) {
     if (st && st->done) return;
     extern __shared__ double smem_d[];
