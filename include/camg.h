@@ -36,13 +36,16 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 5
+#define CAMG_ABI_VERSION 6
 
 typedef struct camg_hier *camg_handle;
 
 typedef enum {
     CAMG_OK = 0,
     CAMG_E_MAXIT = 1,       /* warning: max_iter reached; outputs hold the last iterate */
+    CAMG_E_ACCURACY = 2,    /* warning (mixed precision, rtol > 0): the recursive residual met the test but
+                               the true residual ||b - A x|| / ||b|| is still >= rtol after the two restarts
+                               from it; outputs hold the last iterate and its true residual */
     CAMG_E_ARG = -1,        /* bad argument (null pointer, n < 1, bad parameter) */
     CAMG_E_CSR = -2,        /* malformed CSR, non-finite value, missing diagonal, asymmetry */
     CAMG_E_NOT_SPD = -3,    /* non-positive diagonal or non-positive Cholesky pivot */
@@ -190,7 +193,12 @@ camg_status camg_setup_tv_dev(int32_t n, const int32_t *d_row_ptr, const int32_t
  * NULL): hist[k] = ||r_k|| for k = 0..iters, truncated to hist_cap entries.
  * true_relres (may be NULL): ||b - A x|| / ||b|| in FP64 at exit.
  * b = 0 gives x = 0 after 0 iterations.  Returns CAMG_E_MAXIT (x valid) or
- * CAMG_E_BREAKDOWN (x = last iterate) when the loop did not converge.
+ * CAMG_E_BREAKDOWN (x = last iterate) when the loop did not converge.  In
+ * mixed precision the true residual must pass the test too: when the
+ * recursive one passes and the true one does not, PCG restarts from
+ * r = b - A x (at most twice) and returns CAMG_E_ACCURACY if the true
+ * residual still fails (in FP64 the test is the recursive residual's alone,
+ * as in the paper; true_relres reports the other).
  * camg_solve: host b and x.  camg_solve_dev: device b and x, asynchronous
  * with respect to the host except for the convergence polling; it returns
  * after the solve has finished on `hip_stream`.
@@ -209,7 +217,8 @@ camg_status camg_solve_dev(camg_handle h, const double *d_b, double rtol, double
  * (bitwise, for a given K) and agrees with a single-vector solve to
  * rounding.  iters[k], true_relres[k] (host, may be NULL); hist (host, may
  * be NULL) is k-by-hist_cap row-major.  Returns the worst status over the
- * columns (breakdown before max_iter before ok).
+ * columns (breakdown before max_iter before accuracy before ok; accuracy as
+ * for camg_solve_dev, per column).
  */
 camg_status camg_solve_multi_dev(camg_handle h, int32_t k, const double *d_B, double rtol, double *d_X,
                                  int32_t *iters, double *hist, int32_t hist_cap, double *true_relres,
@@ -255,7 +264,8 @@ camg_status camg_engine_destroy(camg_engine_t e);
  * and stopping test as camg_solve_dev, x0 = 0, rtol shared.  d_b[k], d_x[k]
  * are device vectors of system k; iters, true_relres and status are host
  * arrays of count entries (each may be NULL); per-system outcomes are in
- * status (CAMG_OK, CAMG_E_MAXIT, CAMG_E_BREAKDOWN) while the call returns
+ * status (CAMG_OK, CAMG_E_MAXIT, CAMG_E_BREAKDOWN, and CAMG_E_ACCURACY in
+ * mixed precision as for camg_solve_dev) while the call returns
  * CAMG_OK.  Meant for systems up to ~1e5 unknowns (one compute unit works
  * through each system); larger ones are correct but slow.
  */
@@ -286,7 +296,8 @@ camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const dou
  *     (retire finished batches, check true residuals, copy results out,
  *     admit, launch); completed requests are appended to `out` (at most
  *     cap, the rest stay for the next call) and *n_out receives their
- *     number.  Each completion has the worst column status, the largest
+ *     number.  Each completion has the worst column status (CAMG_E_ACCURACY
+ *     as for camg_solve_dev on a mixed-precision system), the largest
  *     iteration count and true relative residual of the request, the time
  *     from submission to admission and to completion (ms).
  *   camg_server_stats: arena bytes in use and its size, requests waiting,

@@ -16,8 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libcamg.so")
 
-OK, E_MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM, E_DEVICE, E_BUSY = (
-    0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
+OK, E_MAXIT, E_ACCURACY, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM, E_DEVICE, E_BUSY = (
+    0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8)
+# outcomes of a solve whose outputs are valid (the last iterate)
+SOLVE_OUTCOMES = (OK, E_MAXIT, E_ACCURACY, E_BREAKDOWN)
 FP64, MIXED_FP32 = 0, 1
 X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_COARSE_INV, X_STCNT, X_G = range(10)
 MAX_LEVELS = 32
@@ -136,6 +138,35 @@ def _check(st: int, allow=(OK,)):
     return st
 
 
+def _dev(t, name, dtype, shape=None, numel=None, device=True):
+    """Device pointer of a torch tensor after checking that it lives on a
+    GPU, has the expected dtype, is contiguous and has the expected shape or
+    size.  The C entry points read and write these buffers from kernels, so
+    a host tensor, a strided view or a short buffer must never reach them."""
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_cuda"):
+        raise TypeError(f"{name}: a torch tensor on the GPU is expected, got {type(t).__name__}")
+    import torch
+    want = {"f64": torch.float64, "i32": torch.int32}[dtype]
+    if t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype}, {want} expected")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, {tuple(shape)} expected")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, {numel} expected")
+    if device and not t.is_cuda:
+        raise ValueError(f"{name}: tensor is on {t.device}, a GPU tensor is expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _n_of(h):
+    """Unknowns of the hierarchy's finest level."""
+    n = np.zeros(1, np.int32)
+    _check(load().camg_level_sizes(h, 0, _p(n), None, None, None))
+    return int(n[0])
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -162,10 +193,21 @@ def camg_setup(n, row_ptr, col_idx, val, prm=None):
     return st, h
 
 
+def _dev_csr(n, d_row_ptr, d_col_idx, d_val):
+    for dev in (False, True):  # every size check first, then the devices
+        prp = _dev(d_row_ptr, "row_ptr", "i32", numel=int(n) + 1, device=dev)
+        pci = _dev(d_col_idx, "col_idx", "i32", device=dev)
+        pv = _dev(d_val, "val", "f64", numel=d_col_idx.numel(), device=dev)
+    nnz = int(d_row_ptr[-1].item()) if int(n) >= 0 else 0
+    if not 0 <= nnz <= d_col_idx.numel():
+        raise ValueError(f"row_ptr[n] = {nnz} does not fit col_idx / val of {d_col_idx.numel()} entries")
+    return prp, pci, pv
+
+
 def camg_setup_dev(n, d_row_ptr, d_col_idx, d_val, prm=None, stream=None):
     h = C.c_void_p()
-    st = load().camg_setup_dev(int(n), C.c_void_p(d_row_ptr.data_ptr()), C.c_void_p(d_col_idx.data_ptr()),
-                               C.c_void_p(d_val.data_ptr()), C.byref(prm) if prm is not None else None,
+    prp, pci, pv = _dev_csr(n, d_row_ptr, d_col_idx, d_val)
+    st = load().camg_setup_dev(int(n), prp, pci, pv, C.byref(prm) if prm is not None else None,
                                _stream_ptr(stream), C.byref(h))
     return st, h
 
@@ -183,8 +225,11 @@ def camg_setup_tv(n, row_ptr, col_idx, val, V, prm=None):
 
 def camg_setup_tv_dev(n, d_row_ptr, d_col_idx, d_val, d_V, prm=None, stream=None):
     h = C.c_void_p()
-    st = load().camg_setup_tv_dev(int(n), C.c_void_p(d_row_ptr.data_ptr()), C.c_void_p(d_col_idx.data_ptr()),
-                                  C.c_void_p(d_val.data_ptr()), int(d_V.shape[1]), C.c_void_p(d_V.data_ptr()),
+    prp, pci, pv = _dev_csr(n, d_row_ptr, d_col_idx, d_val)
+    if d_V.dim() != 2:
+        raise ValueError("V: an n-by-nt block is expected")
+    pV = _dev(d_V, "V", "f64", shape=(int(n), d_V.shape[1]))
+    st = load().camg_setup_tv_dev(int(n), prp, pci, pv, int(d_V.shape[1]), pV,
                                   C.byref(prm) if prm is not None else None, _stream_ptr(stream), C.byref(h))
     return st, h
 
@@ -200,10 +245,15 @@ def camg_solve(h, b, rtol, x, hist_cap=0):
 
 
 def camg_solve_dev(h, d_b, rtol, d_x, hist_cap=0, stream=None):
+    _dev(d_b, "b", "f64")
+    _dev(d_x, "x", "f64")
+    n = _n_of(h)
+    pb = _dev(d_b, "b", "f64", numel=n)
+    px = _dev(d_x, "x", "f64", numel=n)
     it = np.zeros(1, np.int32)
     hist = np.zeros(max(hist_cap, 1))
     rel = np.zeros(1)
-    st = load().camg_solve_dev(h, C.c_void_p(d_b.data_ptr()), float(rtol), C.c_void_p(d_x.data_ptr()), _p(it),
+    st = load().camg_solve_dev(h, pb, float(rtol), px, _p(it),
                                _p(hist) if hist_cap else None, int(hist_cap), _p(rel), _stream_ptr(stream))
     return st, int(it[0]), hist[:min(hist_cap, int(it[0]) + 1)], float(rel[0])
 
@@ -212,14 +262,24 @@ def camg_solve_multi_dev(h, k, d_B, rtol, d_X, hist_cap=0, stream=None):
     it = np.zeros(k, np.int32)
     hist = np.zeros((k, max(hist_cap, 1)))
     rel = np.zeros(k)
-    st = load().camg_solve_multi_dev(h, int(k), C.c_void_p(d_B.data_ptr()), float(rtol), C.c_void_p(d_X.data_ptr()),
+    _dev(d_B, "B", "f64")
+    _dev(d_X, "X", "f64")
+    n = _n_of(h)
+    pB = _dev(d_B, "B", "f64", shape=(n, int(k)))
+    pX = _dev(d_X, "X", "f64", shape=(n, int(k)))
+    st = load().camg_solve_multi_dev(h, int(k), pB, float(rtol), pX,
                                      _p(it), _p(hist) if hist_cap else None, int(hist_cap), _p(rel),
                                      _stream_ptr(stream))
     return st, it, hist, rel
 
 
 def camg_vcycle_dev(h, d_y, d_z, stream=None):
-    return load().camg_vcycle_dev(h, C.c_void_p(d_y.data_ptr()), C.c_void_p(d_z.data_ptr()), _stream_ptr(stream))
+    _dev(d_y, "y", "f64")
+    _dev(d_z, "z", "f64")
+    n = _n_of(h)
+    py = _dev(d_y, "y", "f64", numel=n)
+    pz = _dev(d_z, "z", "f64", numel=n)
+    return load().camg_vcycle_dev(h, py, pz, _stream_ptr(stream))
 
 
 def camg_info(h):
@@ -291,10 +351,8 @@ class Engine:
 
     def start(self, slot0, d_B, rtol=1e-8, max_iter=1000):
         """d_B: n-by-m row-major (or length-n) float64 CUDA tensor."""
-        m = 1 if d_B.dim() == 1 else d_B.shape[1]
-        ldb = d_B.stride(0) if d_B.dim() > 1 else 1
-        _check(load().camg_engine_start(self.e, int(slot0), int(m), C.c_void_p(d_B.data_ptr()), int(ldb),
-                                        float(rtol), int(max_iter)))
+        m, ldb, pB = _dev_rows(d_B, "B", self.solver.n)
+        _check(load().camg_engine_start(self.e, int(slot0), int(m), pB, int(ldb), float(rtol), int(max_iter)))
 
     def step(self, max_steps=1):
         r = np.zeros(1, np.int32)
@@ -309,10 +367,9 @@ class Engine:
         return it, dn, st
 
     def finish(self, slot0, d_X):
-        m = 1 if d_X.dim() == 1 else d_X.shape[1]
-        ldx = d_X.stride(0) if d_X.dim() > 1 else 1
+        m, ldx, pX = _dev_rows(d_X, "X", self.solver.n)
         rel = np.zeros(m)
-        _check(load().camg_engine_finish(self.e, int(slot0), int(m), C.c_void_p(d_X.data_ptr()), int(ldx), _p(rel)))
+        _check(load().camg_engine_finish(self.e, int(slot0), int(m), pX, int(ldx), _p(rel)))
         return rel
 
     def close(self):
@@ -327,6 +384,22 @@ class Engine:
             pass
 
 
+def _dev_rows(t, name, n):
+    """(columns, row stride, pointer) of an n-by-m row-major float64 GPU
+    block whose rows are contiguous (a column slice of a wider block is
+    fine), or of a length-n vector."""
+    if not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{name}: a float64 GPU tensor is expected")
+    if t.dtype != torch_float64():
+        raise TypeError(f"{name}: dtype {t.dtype}, torch.float64 expected")
+    if t.dim() == 1:
+        return 1, 1, _dev(t, name, "f64", numel=n)
+    if t.dim() != 2 or t.shape[0] != n or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name}: an {n}-by-m block with contiguous rows is expected, got shape "
+                         f"{tuple(t.shape)} strides {tuple(t.stride())}")
+    return int(t.shape[1]), int(t.stride(0)), C.c_void_p(t.data_ptr())
+
+
 def torch_float64():
     import torch
     return torch.float64
@@ -336,9 +409,11 @@ def solve_batch_dev(solvers, d_bs, d_xs, rtol=1e-8, stream=None):
     """Many small systems in one launch (one workgroup per system).  Returns
     (iters, true_relres, status) arrays; raises on a call error."""
     m = len(solvers)
+    if len(d_bs) != m or len(d_xs) != m:
+        raise ValueError("one b and one x per system expected")
     hs = (C.c_void_p * m)(*[s.h for s in solvers])
-    bs = (C.c_void_p * m)(*[t.data_ptr() for t in d_bs])
-    xs = (C.c_void_p * m)(*[t.data_ptr() for t in d_xs])
+    bs = (C.c_void_p * m)(*[_dev(t, f"b[{k}]", "f64", numel=solvers[k].n).value for k, t in enumerate(d_bs)])
+    xs = (C.c_void_p * m)(*[_dev(t, f"x[{k}]", "f64", numel=solvers[k].n).value for k, t in enumerate(d_xs)])
     it = np.zeros(m, np.int32)
     rel = np.zeros(m)
     st = np.zeros(m, np.int32)
@@ -352,18 +427,22 @@ class camg_completion(C.Structure):
                 ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
 
-def _buf_ptr(a):
-    """Pointer and row stride (elements) of a row-major 2D (or 1D) block: a
-    torch tensor (CUDA or host) or a numpy array."""
+def _buf_ptr(a, n, k):
+    """Pointer and row stride (elements) of a row-major n-by-k (or length-n
+    when k = 1) block: a torch tensor (CUDA or host) or a numpy array."""
     if isinstance(a, np.ndarray):
         if a.dtype != np.float64 or a.strides[-1] != 8:
             raise ValueError("float64 block with contiguous rows expected")
-        ld = a.strides[0] // 8 if a.ndim == 2 else 1
-        return C.c_void_p(a.ctypes.data), ld
-    if a.dtype != torch_float64() or a.stride(-1) != 1:
-        raise ValueError("float64 block with contiguous rows expected")
-    ld = a.stride(0) if a.dim() == 2 else 1
-    return C.c_void_p(a.data_ptr()), ld
+        shape, ld = a.shape, (a.strides[0] // 8 if a.ndim == 2 else 1)
+        ptr = a.ctypes.data
+    else:
+        if a.dtype != torch_float64() or a.stride(-1) != 1:
+            raise ValueError("float64 block with contiguous rows expected")
+        shape, ld = tuple(a.shape), (a.stride(0) if a.dim() == 2 else 1)
+        ptr = a.data_ptr()
+    if tuple(shape) not in ((n, k),) + (((n,),) if k == 1 else ()) or (len(shape) == 2 and ld < k):
+        raise ValueError(f"block of shape {tuple(shape)}, ({n}, {k}) expected")
+    return C.c_void_p(ptr), ld
 
 
 class Server:
@@ -387,8 +466,10 @@ class Server:
 
     def submit(self, system, B, X, rtol=1e-8, max_iter=1000, tag=0):
         k = 1 if B.ndim == 1 else B.shape[1]
-        pb, ldb = _buf_ptr(B)
-        px, ldx = _buf_ptr(X)
+        # an unknown system index is the library's to refuse (CAMG_E_ARG)
+        n = self.solvers[int(system)].n if 0 <= int(system) < len(self.solvers) else B.shape[0]
+        pb, ldb = _buf_ptr(B, n, k)
+        px, ldx = _buf_ptr(X, n, k)
         _check(load().camg_server_submit(self.s, int(system), int(k), pb, int(ldb), px, int(ldx), float(rtol),
                                          int(max_iter), int(tag)))
         self.live[int(tag)] = (B, X)
@@ -545,12 +626,12 @@ class Solver:
         x = np.zeros(self.n)
         cap = 100001 if hist_cap is None else hist_cap
         st, it, hist, rel = camg_solve(self.h, b, rtol, x, hist_cap=cap)
-        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        _check(st, allow=SOLVE_OUTCOMES)
         return SolveResult(st, x, it, hist, rel)
 
     def solve_dev(self, d_b, d_x, rtol=1e-8, hist_cap=0, stream=None):
         st, it, hist, rel = camg_solve_dev(self.h, d_b, rtol, d_x, hist_cap=hist_cap, stream=stream)
-        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        _check(st, allow=SOLVE_OUTCOMES)
         return SolveResult(st, None, it, hist, rel)
 
     def vcycle_dev(self, d_y, d_z, stream=None):
@@ -563,7 +644,7 @@ class Solver:
         """d_B, d_X: n-by-k row-major float64 CUDA tensors."""
         k = d_B.shape[1]
         st, it, hist, rel = camg_solve_multi_dev(self.h, k, d_B, rtol, d_X, hist_cap=hist_cap, stream=stream)
-        _check(st, allow=(OK, E_MAXIT, E_BREAKDOWN))
+        _check(st, allow=SOLVE_OUTCOMES)
         return MultiResult(st, it, hist, rel)
 
 

@@ -272,6 +272,9 @@ __global__ void __launch_bounds__(kBT) kb_solve(const BSys<T> *sys, BOut *out) {
         ++it;
     }
     const double t2 = b_true_res2(D, false);
+    // mixed precision: a recursive stop whose true residual still fails after
+    // the restarts is an accuracy warning
+    if (S.mixed && status == CAMG_OK && tol > 0.0 && !(sqrt(t2) < tol)) status = CAMG_E_ACCURACY;
     if (threadIdx.x == 0) {
         out[blockIdx.x].iters = it;
         out[blockIdx.x].status = status;

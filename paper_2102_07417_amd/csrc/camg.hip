@@ -894,6 +894,13 @@ camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t 
             rel = -1.0;
         }
     }
+    // mixed precision promises the true residual: after the restarts, a
+    // recursive stop whose true residual still fails is an accuracy warning
+    bool inaccurate = false;
+    if (h.prm.precision == CAMG_MIXED_FP32 && rtol > 0.0 && st.done && st.status == 0 && st.bnorm > 0.0) {
+        if (rel < 0.0) rel = true_relres_of(h, b, h.x, st.bnorm, nullptr, s);
+        inaccurate = rel >= rtol;
+    }
     // launches after convergence return at once: keep the iterations that ran
     for (const auto &t : times)
         if (t.first < st.iter) {
@@ -916,6 +923,10 @@ camg_status solve_dev(Hier &h, const double *b, double rtol, double *x, int32_t 
     if (!st.done) {
         g_last_error = "max_iter reached";
         return CAMG_E_MAXIT;
+    }
+    if (inaccurate) {
+        g_last_error = "true residual above rtol after two restarts (mixed precision)";
+        return CAMG_E_ACCURACY;
     }
     return CAMG_OK;
 }
@@ -940,6 +951,7 @@ const char *camg_status_str(camg_status s) {
     switch (s) {
     case CAMG_OK: return "ok";
     case CAMG_E_MAXIT: return "maximum number of iterations reached";
+    case CAMG_E_ACCURACY: return "true residual above the tolerance (mixed precision)";
     case CAMG_E_ARG: return "invalid argument";
     case CAMG_E_CSR: return "malformed or unsupported CSR matrix";
     case CAMG_E_NOT_SPD: return "matrix is not symmetric positive definite";
@@ -1318,9 +1330,10 @@ camg_status camg_solve_multi_dev(camg_handle hh, int32_t k, const double *d_B, d
                 if (iters) iters[c0 + c] = it[c];
                 if (true_relres) true_relres[c0 + c] = rel[c];
                 if (hist && hist_cap > 0) engine_hist(*E, c, hist + (size_t)(c0 + c) * hist_cap, hist_cap, it[c] + 1, s);
-                const camg_status cs = (camg_status)stt[c];
-                if (cs == CAMG_E_BREAKDOWN) worst = CAMG_E_BREAKDOWN;
-                else if (cs == CAMG_E_MAXIT && worst == CAMG_OK) worst = CAMG_E_MAXIT;
+                camg_status cs = (camg_status)stt[c];
+                if (cs == CAMG_OK && h->prm.precision == CAMG_MIXED_FP32 && rtol > 0.0 && rel[c] >= rtol)
+                    cs = CAMG_E_ACCURACY;
+                worst = worse_status(worst, cs);
             }
             engine_release(*E, 0, m, s);
         }
@@ -1329,6 +1342,8 @@ camg_status camg_solve_multi_dev(camg_handle hh, int32_t k, const double *d_B, d
     if (st != CAMG_OK) return st;
     if (worst == CAMG_E_BREAKDOWN) camg::g_last_error = "CG breakdown in at least one column";
     if (worst == CAMG_E_MAXIT) camg::g_last_error = "max_iter reached in at least one column";
+    if (worst == CAMG_E_ACCURACY)
+        camg::g_last_error = "true residual above rtol after two restarts in at least one column";
     return worst;
 }
 

@@ -21,6 +21,15 @@ struct Error {
 };
 
 [[noreturn]] void fail(camg_status s, const std::string &msg);
+
+// The worse of two per-column outcomes: breakdown, then max_iter, then the
+// mixed-precision accuracy warning, then ok.
+inline camg_status worse_status(camg_status a, camg_status b) {
+    auto rank = [](camg_status s) {
+        return s == CAMG_E_BREAKDOWN ? 3 : s == CAMG_E_MAXIT ? 2 : s == CAMG_E_ACCURACY ? 1 : 0;
+    };
+    return rank(b) > rank(a) ? b : a;
+}
 void hip_check(hipError_t e, const char *what);
 #define HIPC(x) ::camg::hip_check((x), #x)
 

@@ -186,8 +186,9 @@ void retire(Server &S, SSys &y) {
         y.final_[c] = true;
         r.iters = std::max(r.iters, sn.iter[c]);
         r.relres = std::max(r.relres, rel);
-        if (st == CAMG_E_BREAKDOWN) r.status = CAMG_E_BREAKDOWN;
-        else if (st == CAMG_E_MAXIT && r.status == CAMG_OK) r.status = CAMG_E_MAXIT;
+        camg_status cs = (camg_status)st;
+        if (y.mixed && cs == CAMG_OK && r.rtol > 0.0 && rel >= r.rtol) cs = CAMG_E_ACCURACY;
+        r.status = worse_status((camg_status)r.status, cs);
         if (--r.pending == 0) {
             // gather the request's columns into its staging block, copy out, free the slots
             SlotMap q;

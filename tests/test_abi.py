@@ -46,8 +46,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 5
-    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
+    assert lib.camg_abi_version() == 6
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
     p = camg.camg_params()
@@ -136,3 +136,51 @@ def test_bamg_setup_rejected_without_device(lib):
         assert lib.camg_setup(1, vp(rp), vp(ci), vp(v), C.byref(p), C.byref(h)) == camg.E_ARG
         V = np.ones((1, 9))
         assert lib.camg_setup_tv(1, vp(rp), vp(ci), vp(v), 9, vp(V), C.byref(p), C.byref(h)) == camg.E_ARG
+
+
+def test_device_wrappers_refuse_bad_buffers(lib):
+    """The *_dev wrappers check device, dtype, contiguity and size before a
+    pointer reaches the library (a host address in a kernel would fault the
+    GPU; a strided or short buffer would give wrong columns or out-of-bounds
+    accesses).  Host tensors stand in for every case; nothing reaches a GPU."""
+    torch = pytest.importorskip("torch")
+    n = 6
+    rp = torch.arange(0, 3 * (n + 1), 3, dtype=torch.int32)
+    ci = torch.zeros(3 * n, dtype=torch.int32)
+    va = torch.ones(3 * n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        camg.camg_setup_dev(n, rp, ci, va)                       # host memory
+    with pytest.raises(TypeError, match="dtype"):
+        camg.camg_setup_dev(n, rp.long(), ci, va)                # int64 row pointer
+    with pytest.raises(TypeError, match="dtype"):
+        camg.camg_setup_dev(n, rp, ci, va.float())               # float32 values
+    with pytest.raises(ValueError, match="contiguous"):
+        camg.camg_setup_dev(n, rp, torch.zeros((3 * n, 2), dtype=torch.int32)[:, 0], va)
+    with pytest.raises(ValueError, match="elements"):
+        camg.camg_setup_dev(n, rp[:-1], ci, va)                  # row pointer of n entries
+    with pytest.raises(ValueError, match="elements"):
+        camg.camg_setup_dev(n, rp, ci, va[:-1])                  # values shorter than columns
+    with pytest.raises(TypeError, match="torch tensor"):
+        camg.camg_setup_dev(n, np.zeros(n + 1, np.int32), ci, va)
+    b = torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        camg.camg_solve_dev(None, b, 1e-8, b.clone())
+    with pytest.raises(TypeError, match="dtype"):
+        camg.camg_solve_dev(None, b.float(), 1e-8, b.clone())
+    with pytest.raises(ValueError, match="contiguous"):
+        camg.camg_solve_dev(None, torch.zeros((n, 2), dtype=torch.float64)[:, 1], 1e-8, b.clone())
+    with pytest.raises(ValueError, match="GPU tensor"):
+        camg.camg_vcycle_dev(None, b, b.clone())
+    B = torch.zeros((n, 3), dtype=torch.float64)
+    with pytest.raises(ValueError, match="contiguous"):
+        camg.camg_solve_multi_dev(None, 3, B.t().contiguous().t(), 1e-8, B.clone())   # column-major block
+    with pytest.raises(ValueError, match="GPU tensor"):
+        camg.camg_solve_multi_dev(None, 3, B, 1e-8, B.clone())
+    with pytest.raises(ValueError, match="one b and one x"):
+        camg.solve_batch_dev([], [b], [])
+    # host blocks handed to the server: shape checked against the system size
+    with pytest.raises(ValueError, match="expected"):
+        camg._buf_ptr(np.zeros((n, 2)), n + 1, 2)
+    with pytest.raises(ValueError, match="expected"):
+        camg._buf_ptr(np.zeros((n, 2)), n, 3)
+    assert camg._buf_ptr(np.zeros((n, 4))[:, :2], n, 2)[1] == 4   # column slice: row stride 4

@@ -1,15 +1,22 @@
 """The mechanics workload at full size (Q1 elasticity on 64^3 elements,
 n = 811,200, nnz = 63,695,790, bottom face clamped) on the GPU against the
 CPU oracle, in the set-up the benchmark times: every level of the direct and
-of the BAMG + SRQM hierarchy bit for bit, one V-cycle, and a fixed number of
-PCG iterations in FP64 and in mixed precision (the oracle's full solve, about
-600 iterations, is too slow for a test; the GPU solves to 1e-8 are checked by
-their true residuals)."""
+of the BAMG + SRQM hierarchy bit for bit, one V-cycle, five PCG iterations
+in FP64 and in mixed precision, and the natural-stop solves against the
+oracle's full solve (about 600 iterations, too slow to run in a test: it is
+read from tests/golden/oracle_solve_elasticity_64.txt, written by
+tests/golden/make_oracle_solves.py from the oracle alone)."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2102_07417_amd import problems as PB
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_oracle_solves as GOLD  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -101,3 +108,56 @@ def test_bamg_srqm_hierarchy_bit_exact(camg, c3):
     o = O.Hierarchy(A, V=V, **kw)
     _same_levels(g, o)
     g.close()
+
+
+@pytest.mark.timeout(600)
+def test_natural_stop_against_oracle_solve(camg, c3):
+    """FP64: iterations within one of the oracle's at the natural stop
+    (rtol 1e-8), and at the oracle's iteration count (parity mode, rtol 0)
+    x within 1e-9 relative on the oracle's 4096 sampled unknowns, the
+    residual history beside the oracle's.  Mixed precision: true residual
+    below 1e-8 and its error against the oracle's FP64 solution stated."""
+    A, b, _ = c3
+    g = GOLD.read("elasticity_64")
+    assert g["n"] == A.n and g["nnz"] == A.nnz and g["status"] == 0
+    ko, idx, xo, ho = g["iters"], g["idx"], g["x"], g["hist"]
+    print(f"[gpu] full-size elasticity 64^3: natural stop vs oracle ({ko} iterations)", flush=True)
+    rp, ci, va = _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val)
+    db = _dev(b)
+    dx = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+
+    def rel_on_samples(x):
+        return np.linalg.norm(x[idx] - xo) / np.linalg.norm(xo)
+
+    s = camg.Solver.from_device(A.n, rp, ci, va, max_iter=5000)
+    r = s.solve_dev(db, dx, rtol=1e-8, hist_cap=ko + 10)
+    x = dx.cpu().numpy()
+    hg = np.asarray(r.hist)
+    m = min(len(hg), len(ho))
+    hdiff = np.abs(hg[:m] - ho[:m]) / ho[:m]
+    print(f"[gpu] FP64 natural stop: {r.iters} iterations (oracle {ko}), true_relres {r.true_relres:.3e} "
+          f"(oracle {g['true_relres']:.3e}), sampled rel diff {rel_on_samples(x):.2e}, "
+          f"history max rel diff {hdiff.max():.2e} (first 100: {hdiff[:100].max():.2e})", flush=True)
+    assert r.status == camg.OK and abs(r.iters - ko) <= 1
+    assert r.true_relres < 1e-8 * 1.01
+    if r.iters == ko:
+        assert rel_on_samples(x) <= 1e-9
+    assert hdiff[:100].max() <= 1e-9 and hdiff.max() <= 1e-6
+    # parity mode: exactly the oracle's iteration count
+    s.close()
+    s = camg.Solver.from_device(A.n, rp, ci, va, max_iter=ko)
+    dx.zero_()
+    r = s.solve_dev(db, dx, rtol=0.0)
+    e = rel_on_samples(dx.cpu().numpy())
+    print(f"[gpu] FP64 at {ko} iterations: sampled rel diff {e:.2e}", flush=True)
+    assert r.iters == ko and e <= 1e-9
+    s.close()
+    # mixed precision: FP32 V-cycle inside FP64 PCG, its error stated against the oracle
+    s = camg.Solver.from_device(A.n, rp, ci, va, max_iter=5000, precision=camg.MIXED_FP32)
+    dx.zero_()
+    r = s.solve_dev(db, dx, rtol=1e-8)
+    em = rel_on_samples(dx.cpu().numpy())
+    print(f"[gpu] mixed natural stop: {r.iters} iterations, true_relres {r.true_relres:.3e}, "
+          f"sampled rel error vs FP64 oracle {em:.2e}", flush=True)
+    assert r.status == camg.OK and r.true_relres < 1e-8 and em <= 1e-6
+    s.close()

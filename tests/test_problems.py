@@ -105,3 +105,21 @@ def test_elasticity_rigid_modes_in_kernel_away_from_clamp():
     far = np.arange(A.n) // 3 >= nodes_per_layer   # nodes with z >= 2h
     assert np.abs(KV[far]).max() < 1e-10 * np.abs(A.val).max()
     assert np.abs(KV[~far]).max() > 1e-6
+
+
+def test_oracle_solve_fixture_is_a_natural_stop():
+    """The stored oracle solve of the 64^3-element elasticity workload reads
+    back consistently: its history has iters + 1 entries, starts at ||b||,
+    and stops at the first residual below 1e-8 ||b|| (strict), as the
+    stopping rule of the experiments prescribes."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_oracle_solves as G
+    g = G.read("elasticity_64")
+    h = g["hist"]
+    assert g["status"] == 0 and len(h) == g["iters"] + 1 and g["n"] == 811200 and g["nnz"] == 63695790
+    assert h[-1] < 1e-8 * h[0] and np.all(h[:-1] >= 1e-8 * h[0])
+    assert abs(h[0] - np.linalg.norm(PB.rhs(g["n"]))) <= 1e-12 * h[0]
+    assert len(g["idx"]) == g["samples"] == 4096 and np.array_equal(g["idx"], G.sample_index(g["n"]))
+    assert g["true_relres"] < 1e-8 and np.all(np.isfinite(g["x"]))
