@@ -1180,7 +1180,7 @@ double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, con
  * and Yeremin on the pattern of the lower triangle of A: for row i, with
  * P_i = {j <= i : a_ij stored} in ascending order (i last), solve
  * A(P_i, P_i) g = e_last by a dense Cholesky factorisation, forward and
- * backward substitution (column-oriented), and set
+ * backward substitution (the dense routines of the last level), and set
  * G(i, P_i) = g / sqrt(g_last), so that G A G^T has a unit diagonal.
  */
 /* the largest number of entries on or below the diagonal in a row of A */
@@ -1224,17 +1224,10 @@ int orc_fsai(const orc_csr *A, orc_csr *G) {
                 M[(size_t)r * m + c] = p >= 0 ? A->val[p] : 0.0;
             }
         if (m == 0 || idx[m - 1] != i || orc_cholesky(m, M) != 0) { st = ORC_E_NOT_SPD; break; }
-        /* L L^T g = e_last, both substitutions column by column: once an
-         * unknown is known, it is removed from every later equation */
+        /* L L^T g = e_last by the last level's forward and backward
+         * substitutions */
         for (int32_t r = 0; r < m; ++r) e[r] = r == m - 1 ? 1.0 : 0.0;
-        for (int32_t k = 0; k < m; ++k) {
-            e[k] = e[k] / M[(size_t)k * m + k];
-            for (int32_t r = k + 1; r < m; ++r) e[r] = e[r] - M[(size_t)r * m + k] * e[k];
-        }
-        for (int32_t k = m - 1; k >= 0; --k) {
-            g[k] = e[k] / M[(size_t)k * m + k];
-            for (int32_t r = 0; r < k; ++r) e[r] = e[r] - M[(size_t)k * m + r] * g[k];
-        }
+        orc_chol_solve(m, M, e, g);
         if (!(g[m - 1] > 0.0)) { st = ORC_E_NOT_SPD; break; }
         double sd = sqrt(g[m - 1]);
         for (int32_t r = 0; r < m; ++r) {

@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 from paper_2102_07417_amd import problems as PB
+from tests.helpers import assert_fsai_close
 
 pytestmark = pytest.mark.gpu
 
@@ -140,8 +141,9 @@ def test_over_filtered_prolongation_fails_like_the_oracle(camg):
 def test_fsai_where_rows_fit_jacobi_elsewhere(camg):
     """BAMG on 8^3 elasticity with the FSAI_JACOBI smoother: levels 0 and 2
     smooth with FSAI, level 1 (212 entries on or below the diagonal in a
-    row) with Jacobi.  Hierarchy, factors and weights bit for bit; V-cycle,
-    FP64 and mixed solves as elsewhere."""
+    row) with Jacobi.  Hierarchy and Jacobi weights bit for bit; the FSAI
+    factors and their weights to rounding (the local solves substitute in
+    different orders); V-cycle, FP64 and mixed solves as elsewhere."""
     print("[gpu] BAMG + FSAI where rows fit", flush=True)
     A, V = PB.elasticity3d(8), PB.elasticity_rigid_modes(8)
     kw = dict(max_coarse=40, smoother=2)
@@ -158,10 +160,11 @@ def test_fsai_where_rows_fit_jacobi_elsewhere(camg):
             break
         gp, op = g.P(l), o.P(l)
         assert np.array_equal(gp[3], op[3]) and np.array_equal(gp[4], op[4]), l
-        assert g.omega(l) == o.omega(l), l
         if kinds[l]:
-            assert np.array_equal(g.G(l)[4], o.G(l)[4]), l
+            assert_fsai_close(g.G(l), o.G(l), f"_{l}")
+            assert abs(g.omega(l) - o.omega(l)) <= 1e-12 * o.omega(l), l
         else:
+            assert g.omega(l) == o.omega(l), l
             with pytest.raises(camg.CamgError):
                 g.G(l)
     rng = np.random.default_rng(2)
@@ -171,7 +174,7 @@ def test_fsai_where_rows_fit_jacobi_elsewhere(camg):
         g.vcycle_dev(_dev(y), dz)
         torch.cuda.synchronize()
         zo = o.vcycle(y)
-        assert np.linalg.norm(dz.cpu().numpy() - zo) / np.linalg.norm(zo) <= 1e-12
+        assert np.linalg.norm(dz.cpu().numpy() - zo) / np.linalg.norm(zo) <= 1e-10
     b = PB.rhs(A.n)
     ro = o.solve(b, 1e-8, max_iter=3000)
     r = g.solve(b)

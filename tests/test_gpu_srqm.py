@@ -47,6 +47,10 @@ CASES = {
     "elasticity_16_rbm_3": (lambda: PB.elasticity3d(16), lambda A: PB.elasticity_rigid_modes(16),
                             {"srqm_iters": 3}),
     "poisson2d_40_linear_3": (lambda: PB.poisson2d(40), lambda A: _linear2d(40), {"srqm_iters": 3}),
+    # FSAI on a 7-point matrix: the local systems' Cholesky factors couple
+    # the last unknown only, so the oracle's and the device's substitution
+    # orders add the same nonzero terms in the same order and level 0's G
+    # (the only one SRQM applies) is the same bit for bit
     "lognormal3d_16_const_fsai_5": (lambda: PB.lognormal3d(16, 2.0), lambda A: np.ones((A.n, 1)),
                                     {"srqm_iters": 5, "smoother": 1}),
     "lognormal3d_16_two_fsai_3": (lambda: PB.lognormal3d(16, 2.0),
