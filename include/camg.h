@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 6
+#define CAMG_ABI_VERSION 7
 
 typedef struct camg_hier *camg_handle;
 
@@ -272,6 +272,27 @@ camg_status camg_engine_destroy(camg_engine_t e);
 camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
                                  double rtol, int32_t *iters, double *true_relres, int32_t *status,
                                  void *hip_stream);
+
+/*
+ * The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * identical arguments, kernels, results and per-system outcomes as
+ * camg_solve_batch_dev, but the per-call device buffers (the systems'
+ * descriptors and their results) sit in a static device array of
+ * CAMG_NOALLOC_MAX_SYSTEMS entries (about 4.8 MB) that each GPU the library
+ * runs on holds until the process ends, instead of two allocations per
+ * call.  The call makes no device allocation and frees nothing; it still
+ * stages the descriptors through ordinary host memory and waits for the
+ * stream, like camg_solve_batch_dev.  count > CAMG_NOALLOC_MAX_SYSTEMS
+ * returns CAMG_E_ARG.  Every call on one GPU shares that GPU's array (the
+ * next call overwrites it; nothing in it needs clearing), so calls that
+ * overlap on one GPU (other host threads, other streams) race: serialise
+ * them.
+ */
+#define CAMG_NOALLOC_MAX_SYSTEMS 1024
+camg_status camg_solve_batch_noalloc_dev(int32_t count, const camg_handle *hs, const double *const *d_b,
+                                         double *const *d_x, double rtol, int32_t *iters, double *true_relres,
+                                         int32_t *status, void *hip_stream);
 
 /*
  * Server: resident hierarchies answering solve requests (the paper reuses

@@ -31,6 +31,7 @@ EXPORTED = [
     "camg_set_option", "camg_engine_footprint", "camg_engine_create", "camg_engine_start", "camg_engine_step",
     "camg_engine_state", "camg_engine_finish", "camg_engine_destroy", "camg_server_create", "camg_server_add",
     "camg_server_submit", "camg_server_poll", "camg_server_stats", "camg_server_destroy", "camg_solve_batch_dev",
+    "camg_solve_batch_noalloc_dev",
 ]
 OPT_GRAPH = 1
 SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI = 0, 1, 2
@@ -102,6 +103,8 @@ def load(path: str | None = None):
     L.camg_engine_destroy.argtypes = [vp]
     L.camg_solve_batch_dev.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
     L.camg_solve_batch_dev.restype = C.c_int
+    L.camg_solve_batch_noalloc_dev.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+    L.camg_solve_batch_noalloc_dev.restype = C.c_int
     L.camg_server_create.argtypes = [i64, C.POINTER(vp)]
     L.camg_server_add.argtypes = [vp, vp, i32, i32, vp]
     L.camg_server_submit.argtypes = [vp, i32, i32, vp, i32, vp, i32, dbl, i32, i64]
@@ -405,9 +408,14 @@ def torch_float64():
     return torch.float64
 
 
-def solve_batch_dev(solvers, d_bs, d_xs, rtol=1e-8, stream=None):
+NOALLOC_MAX_SYSTEMS = 1024
+
+
+def solve_batch_dev(solvers, d_bs, d_xs, rtol=1e-8, stream=None, no_alloc=False):
     """Many small systems in one launch (one workgroup per system).  Returns
-    (iters, true_relres, status) arrays; raises on a call error."""
+    (iters, true_relres, status) arrays; raises on a call error.  no_alloc:
+    call camg_solve_batch_noalloc_dev (per-call buffers in the library's
+    static device array, at most NOALLOC_MAX_SYSTEMS systems)."""
     m = len(solvers)
     if len(d_bs) != m or len(d_xs) != m:
         raise ValueError("one b and one x per system expected")
@@ -417,8 +425,9 @@ def solve_batch_dev(solvers, d_bs, d_xs, rtol=1e-8, stream=None):
     it = np.zeros(m, np.int32)
     rel = np.zeros(m)
     st = np.zeros(m, np.int32)
-    _check(load().camg_solve_batch_dev(m, C.cast(hs, C.c_void_p), C.cast(bs, C.c_void_p), C.cast(xs, C.c_void_p),
-                                       float(rtol), _p(it), _p(rel), _p(st), _stream_ptr(stream)))
+    fn = load().camg_solve_batch_noalloc_dev if no_alloc else load().camg_solve_batch_dev
+    _check(fn(m, C.cast(hs, C.c_void_p), C.cast(bs, C.c_void_p), C.cast(xs, C.c_void_p),
+              float(rtol), _p(it), _p(rel), _p(st), _stream_ptr(stream)))
     return it, rel, st
 
 

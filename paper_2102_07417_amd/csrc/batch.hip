@@ -16,6 +16,7 @@
 // works through each system.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "devutil.hpp"
@@ -353,12 +354,26 @@ BSys<T> describe(Hier &h, const double *b, double *x, double rtol) {
     return S;
 }
 
+// Descriptors in, results out, one launch: dsys holds m BSys<T>, dout m BOut
+// (device memory of the caller's choosing, left as the launch wrote it).
+template <class T>
+void launch_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x, double rtol, void *dsys,
+                  void *dout, std::vector<BOut> &out, hipStream_t s) {
+    const int m = (int)hs.size();
+    std::vector<BSys<T>> host(m);
+    for (int k = 0; k < m; ++k) host[k] = describe<T>(*hs[k], b[k], x[k], rtol);
+    HIPC(hipMemcpyAsync(dsys, host.data(), sizeof(BSys<T>) * m, hipMemcpyHostToDevice, s));
+    kb_solve<T><<<m, kBT, 0, s>>>(static_cast<const BSys<T> *>(dsys), static_cast<BOut *>(dout));
+    HIPC(hipGetLastError());
+    out.resize(m);
+    HIPC(hipMemcpyAsync(out.data(), dout, sizeof(BOut) * m, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+}
+
 template <class T>
 void run_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x, double rtol, std::vector<BOut> &out,
                hipStream_t s) {
     const int m = (int)hs.size();
-    std::vector<BSys<T>> host(m);
-    for (int k = 0; k < m; ++k) host[k] = describe<T>(*hs[k], b[k], x[k], rtol);
     void *dsys = nullptr, *dout = nullptr;
     HIPC(hipMalloc(&dsys, sizeof(BSys<T>) * m));
     struct Free {
@@ -369,20 +384,49 @@ void run_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x
         }
     } fr{&dsys, &dout};
     HIPC(hipMalloc(&dout, sizeof(BOut) * m));
-    HIPC(hipMemcpyAsync(dsys, host.data(), sizeof(BSys<T>) * m, hipMemcpyHostToDevice, s));
-    kb_solve<T><<<m, kBT, 0, s>>>(static_cast<const BSys<T> *>(dsys), static_cast<BOut *>(dout));
-    HIPC(hipGetLastError());
-    out.resize(m);
-    HIPC(hipMemcpyAsync(out.data(), dout, sizeof(BOut) * m, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
+    launch_batch<T>(hs, b, x, rtol, dsys, dout, out, s);
+}
+
+// ---- allocation-free variant: descriptors and results in a static device array
+//
+// Each GPU the library runs on holds one copy of `scratch` until the process
+// ends.  Its device address is taken once per device (with that device
+// current) and kept; host code never passes the array's own name to a
+// kernel or a copy.  The descriptors start at offset 0, the results at
+// kOutOff; a call overwrites every byte it reads back, so nothing has to
+// start at zero.
+constexpr size_t kDescBytes = sizeof(BSys<double>);
+static_assert(sizeof(BSys<float>) == kDescBytes, "descriptor sizes of both precisions are equal");
+constexpr size_t kOutOff = ((size_t)CAMG_NOALLOC_MAX_SYSTEMS * kDescBytes + 255) / 256 * 256;
+constexpr size_t kScratchBytes = kOutOff + ((size_t)CAMG_NOALLOC_MAX_SYSTEMS * sizeof(BOut) + 255) / 256 * 256;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the calling thread's current device must be dev
+void *scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) fail(CAMG_E_DEVICE, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) fail(CAMG_E_DEVICE, "hipGetSymbolAddress of the batch scratch array failed");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
 
 // Solve count systems, one workgroup each, in one launch (handles of one
-// precision, one smoothing step each way).
+// precision, one smoothing step each way).  no_alloc: the descriptors and
+// results live in the static scratch array of the current device instead of
+// two allocations of this call.
 void solve_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x, double rtol, int32_t *iters,
-                 double *true_relres, int32_t *status, hipStream_t s) {
+                 double *true_relres, int32_t *status, hipStream_t s, bool no_alloc) {
     const int prec = hs[0]->prm.precision;
     for (Hier *h : hs) {
         if (h->prm.precision != prec) fail(CAMG_E_ARG, "all handles of a batch must have the same precision");
@@ -392,8 +436,19 @@ void solve_batch(std::vector<Hier *> &hs, const double *const *b, double *const 
         if (h->device != hs[0]->device) fail(CAMG_E_ARG, "all handles of a batch must live on one device");
     }
     std::vector<BOut> out;
-    if (prec == CAMG_MIXED_FP32) run_batch<float>(hs, b, x, rtol, out, s);
-    else run_batch<double>(hs, b, x, rtol, out, s);
+    if (no_alloc) {
+        if (hs.size() > (size_t)CAMG_NOALLOC_MAX_SYSTEMS)
+            fail(CAMG_E_ARG, "more systems than the allocation-free batch holds (CAMG_NOALLOC_MAX_SYSTEMS)");
+        int dev = -1;
+        HIPC(hipGetDevice(&dev));
+        unsigned char *base = static_cast<unsigned char *>(scratch_ptr(dev));
+        if (prec == CAMG_MIXED_FP32) launch_batch<float>(hs, b, x, rtol, base, base + kOutOff, out, s);
+        else launch_batch<double>(hs, b, x, rtol, base, base + kOutOff, out, s);
+    } else if (prec == CAMG_MIXED_FP32) {
+        run_batch<float>(hs, b, x, rtol, out, s);
+    } else {
+        run_batch<double>(hs, b, x, rtol, out, s);
+    }
     for (size_t k = 0; k < hs.size(); ++k) {
         if (iters) iters[k] = out[k].iters;
         if (true_relres) true_relres[k] = out[k].true_rel;

@@ -1431,11 +1431,14 @@ camg_status camg_engine_destroy(camg_engine_t ce) {
 }
 
 // ---------------------------------------------------------------- many small systems
-camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
-                                 double rtol, int32_t *iters, double *true_relres, int32_t *status,
-                                 void *hip_stream) {
+namespace {
+camg_status batch_entry(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
+                        double rtol, int32_t *iters, double *true_relres, int32_t *status, void *hip_stream,
+                        bool no_alloc) {
     return guarded([&] {
         if (count < 1 || !hs || !d_b || !d_x) fail(CAMG_E_ARG, "count < 1 or null array");
+        if (no_alloc && count > CAMG_NOALLOC_MAX_SYSTEMS)
+            fail(CAMG_E_ARG, "more systems than the allocation-free batch holds (CAMG_NOALLOC_MAX_SYSTEMS)");
         if (!std::isfinite(rtol)) fail(CAMG_E_ARG, "rtol must be finite");
         std::vector<Hier *> v(count);
         std::vector<std::unique_ptr<BusyGuard>> guards;
@@ -1445,8 +1448,21 @@ camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const dou
             guards.emplace_back(new BusyGuard(v[k]));  // also rejects a handle listed twice
         }
         HIPC(hipSetDevice(v[0]->device));
-        solve_batch(v, d_b, d_x, rtol, iters, true_relres, status, (hipStream_t)hip_stream);
+        solve_batch(v, d_b, d_x, rtol, iters, true_relres, status, (hipStream_t)hip_stream, no_alloc);
     });
+}
+}  // namespace
+
+camg_status camg_solve_batch_dev(int32_t count, const camg_handle *hs, const double *const *d_b, double *const *d_x,
+                                 double rtol, int32_t *iters, double *true_relres, int32_t *status,
+                                 void *hip_stream) {
+    return batch_entry(count, hs, d_b, d_x, rtol, iters, true_relres, status, hip_stream, false);
+}
+
+camg_status camg_solve_batch_noalloc_dev(int32_t count, const camg_handle *hs, const double *const *d_b,
+                                         double *const *d_x, double rtol, int32_t *iters, double *true_relres,
+                                         int32_t *status, void *hip_stream) {
+    return batch_entry(count, hs, d_b, d_x, rtol, iters, true_relres, status, hip_stream, true);
 }
 
 // ---------------------------------------------------------------- server API

@@ -383,7 +383,7 @@ int engine_n(const Engine &E);
 
 // ---------------------------------------------------------------- many small systems (batch.hip)
 void solve_batch(std::vector<Hier *> &hs, const double *const *b, double *const *x, double rtol, int32_t *iters,
-                 double *true_relres, int32_t *status, hipStream_t s);
+                 double *true_relres, int32_t *status, hipStream_t s, bool no_alloc);
 
 // ---------------------------------------------------------------- server (serve.hip)
 struct Server;

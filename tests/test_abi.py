@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 6
+    assert lib.camg_abi_version() == 7
     for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -65,6 +65,20 @@ def test_argument_errors_without_device(lib):
     assert lib.camg_engine_destroy(None) == camg.OK
     assert lib.camg_server_destroy(None) == camg.OK
     assert len(lib.camg_last_error()) >= 0
+
+
+def test_noalloc_batch_limit_without_device(lib):
+    # more systems than the static array holds: refused before any handle or
+    # device is looked at
+    m = camg.NOALLOC_MAX_SYSTEMS + 1
+    hs = (C.c_void_p * m)()
+    ptrs = (C.c_void_p * m)()
+    st = lib.camg_solve_batch_noalloc_dev(m, C.cast(hs, C.c_void_p), C.cast(ptrs, C.c_void_p),
+                                          C.cast(ptrs, C.c_void_p), 1e-8, None, None, None, None)
+    assert st == camg.E_ARG and b"CAMG_NOALLOC_MAX_SYSTEMS" in lib.camg_last_error()
+    # the header's limit is the binding's
+    assert re.search(r"#define CAMG_NOALLOC_MAX_SYSTEMS (\d+)", open(HEADER).read()).group(1) == \
+        str(camg.NOALLOC_MAX_SYSTEMS)
 
 
 @pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 3), ("theta", 1.5),
