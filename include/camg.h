@@ -388,10 +388,13 @@ void camg_free_host(void *p);
  * z = s + omega D^{-1} (y - A s) fused with the r.z partial sums) with HIP
  * events on the solve's stream, on every enable-th PCG iteration (the last
  * of each group of enable iterations), and accumulates the durations of the
- * timed launches that did work.  Each call returns (and resets) the totals
- * gathered since the previous call, then sets timing: enable = 0 off,
- * enable = n >= 1 on, every n-th iteration.  total_ms and launches may be
- * NULL.
+ * timed launches that did work.  The multi-RHS engines of the handle
+ * (camg_solve_multi_dev, camg_engine_step) time their level-0 block
+ * post-smoothing kernel the same way, on every enable-th iteration they
+ * issue (those iterations run without the engine's graph).  Each call
+ * returns (and resets) the totals gathered since the previous call, then
+ * sets timing: enable = 0 off, enable = n >= 1 on, every n-th iteration.
+ * total_ms and launches may be NULL.
  */
 camg_status camg_profile(camg_handle h, int32_t enable, double *total_ms, int64_t *launches);
 

@@ -27,6 +27,8 @@
 #include <tuple>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "devutil.hpp"
 #include "internal.hpp"
 
@@ -722,6 +724,8 @@ struct Engine {
     bool graph_ok = false;
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;
+    int64_t iter_seq = 0;                       // iterations issued (strides of the kernel timing)
+    hipEvent_t tev[2] = {nullptr, nullptr};     // a timed level-0 post-smoothing launch
     std::map<std::tuple<const void *, int, int>, RowSched> sched;  // (matrix, value bytes, kind)
     RowSched rs(const Csr &M, int vbytes, int kind) const {
         auto it = sched.find(std::make_tuple((const void *)&M, vbytes, kind));
@@ -758,14 +762,33 @@ int rows_grid(int nr, int crows) {
     return std::max(8, std::min((need + 7) / 8 * 8, std::max(cap, 8)));
 }
 
+// events that the next block-row launch of this host thread records at its
+// own start and end (armed by mrows_time_next, cleared by that launch)
+thread_local hipEvent_t t_mev_start = nullptr, t_mev_stop = nullptr;
+// events of the level-0 post-smoothing launch of the iteration being issued
+// (set by a timed engine iteration, armed by the V-cycle right before it)
+thread_local hipEvent_t t_mpost_start = nullptr, t_mpost_stop = nullptr;
+
+void mrows_time_next(hipEvent_t a, hipEvent_t b) {
+    t_mev_start = a;
+    t_mev_stop = b;
+}
+
 template <class T, int K, bool DOT, int U, class G, class Ep>
 int launch_mrows_u(const Csr &M, const T *av, hipStream_t s, const G &g, const Ep &e, double *partials,
                    unsigned long long pmask, int forced_grid, const RowSched &rs) {
     const int crows = rs.crows > 0 ? rs.crows : chunk_rows<T, K>(M.nr, M.nnz);
     int grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, DOT, U, G, Ep>(M.nr, crows);
     if (!DOT && forced_grid <= 0 && rs.grid > 0) grid = rs.grid;
-    mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows,
-                                                  rs.stage ? 1 : 0);
+    if (t_mev_start) {  // timed launch: the events bracket the kernel's execution
+        hipEvent_t a = t_mev_start, b = t_mev_stop;
+        t_mev_start = t_mev_stop = nullptr;
+        hipExtLaunchKernelGGL(mk_rows<T, K, DOT, U, G, Ep>, dim3(grid), dim3(kBlock), 0, s, a, b, 0, M.nr, M.rp,
+                              M.ci, av, g, e, partials, pmask, crows, rs.stage ? 1 : 0);
+    } else {
+        mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows,
+                                                      rs.stage ? 1 : 0);
+    }
     HIPC(hipGetLastError());
     return grid;
 }
@@ -873,6 +896,10 @@ int mvcycle(Engine &E, bool dot, hipStream_t s) {
                                        MEPost<T, K, T, T>{vwd<T>(Lv), Tp(B.y), s0, t0}, nullptr, false, ~0ull, 0, E.rs(Lv.A, (int)sizeof(T), 0));
             std::swap(s0, t0);
         }
+        if (l == 0 && t_mpost_start) {  // a timed iteration: this launch records the events
+            mrows_time_next(t_mpost_start, t_mpost_stop);
+            t_mpost_start = t_mpost_stop = nullptr;
+        }
         if (l == 0)
             g0 = E.z32 ? launch_mrows_any<T, K>(Lv.A, vvals<T>(Lv.A), s, MGather<T, K>{s0},
                                                 MEPost<T, K, double, float>{vwd<T>(Lv), E.R, s0,
@@ -959,8 +986,35 @@ void m_launch_iteration(Engine &E, hipStream_t s) {
             E.use_graph = false;
         }
     }
-    if (E.use_graph && E.graph_ok) HIPC(hipGraphLaunch(E.gexec[E.par], s));
-    else CAMG_K_SWITCH(E.K, miteration<KK>(E, E.par, s));
+    // kernel timing on the handle: every prof_stride-th iteration runs
+    // without the graph, its level-0 post-smoothing launch bracketed by events
+    Hier &h = *E.h;
+    const bool timed = h.prof && (E.iter_seq % h.prof_stride) == h.prof_stride - 1 && E.h->nlev > 1;
+    ++E.iter_seq;
+    if (timed) {
+        if (!E.tev[0]) {
+            HIPC(hipEventCreate(&E.tev[0]));
+            HIPC(hipEventCreate(&E.tev[1]));
+        }
+        t_mpost_start = E.tev[0];
+        t_mpost_stop = E.tev[1];
+        try {
+            CAMG_K_SWITCH(E.K, miteration<KK>(E, E.par, s));
+        } catch (...) {
+            t_mpost_start = t_mpost_stop = nullptr;
+            t_mev_start = t_mev_stop = nullptr;
+            throw;
+        }
+        HIPC(hipEventSynchronize(E.tev[1]));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, E.tev[0], E.tev[1]));
+        h.prof_ms += ms;
+        h.prof_launches += 1;
+    } else if (E.use_graph && E.graph_ok) {
+        HIPC(hipGraphLaunch(E.gexec[E.par], s));
+    } else {
+        CAMG_K_SWITCH(E.K, miteration<KK>(E, E.par, s));
+    }
     E.par ^= 1;
 }
 
@@ -1062,6 +1116,8 @@ void engine_autotune(Engine &E, hipStream_t s) {
 
 Engine::~Engine() {
     m_destroy_graphs(*this);
+    for (hipEvent_t e : tev)
+        if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hflag) (void)hipHostFree(hflag);
 }
