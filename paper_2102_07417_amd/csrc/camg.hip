@@ -201,7 +201,7 @@ void validate_input(Hier &h, int n, int64_t nnz, const Csr &A, int32_t *tpos, Po
     if (hf[1]) fail(CAMG_E_CSR, "column index out of range or not strictly increasing within a row");
     if (hf[2]) fail(CAMG_E_CSR, "non-finite matrix value");
     if (hf[3]) fail(CAMG_E_CSR, "a diagonal entry is missing");
-    validate_sym(n, A.rp, A.ci, A.v, amax, flags, tpos, s);
+    validate_sym(n, nnz, A.rp, A.ci, A.v, amax, flags, tpos, s);
     HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (hf[4]) fail(CAMG_E_CSR, "matrix is not symmetric (pattern or values beyond 1e-12 max|a|)");
@@ -302,13 +302,13 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         Pool lt(s);  // per-level temporaries
         if (l > 0) {
             tpos = lt.alloc<int32_t>(std::max<int64_t>(nz, 1));
-            transpose_positions(nl, L.A.rp, L.A.ci, tpos, s);
+            transpose_positions(nl, nz, L.A.rp, L.A.ci, tpos, s);
         }
         // Jacobi weights (eq. smoother)
         L.dinv = h.pool.alloc<double>(nl);
         L.wd = h.pool.alloc<double>(nl);
         HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
-        diag_gershgorin(nl, L.A.rp, L.A.ci, L.A.v, L.dinv, qmax, flags, s);
+        diag_gershgorin(nl, nz, L.A.rp, L.A.ci, L.A.v, L.dinv, qmax, flags, s);
         int32_t hf[8];
         unsigned long long hq;
         HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -384,7 +384,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         L.strong = h.pool.alloc<uint8_t>(std::max<int64_t>(nz, 1));
         L.stcnt = h.pool.alloc<int32_t>(nl);
         L.cf = h.pool.alloc<int8_t>(nl);
-        strength(nl, L.A.rp, L.A.ci, L.A.v, tpos, prm.theta, L.strong, L.stcnt, s);
+        strength(nl, nz, L.A.rp, L.A.ci, L.A.v, tpos, prm.theta, L.strong, L.stcnt, s);
         uint64_t *u = lt.alloc<uint64_t>(nl);
         int8_t *newc = lt.alloc<int8_t>(nl);
         pmis_init(nl, L.stcnt, prm.seed, l, u, L.cf, und, s);

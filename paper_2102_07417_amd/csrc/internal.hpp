@@ -205,11 +205,11 @@ void narrow_i64(const int64_t *v64, int32_t *rp32, int n, hipStream_t s);
 void validate_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags, hipStream_t s);
 void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
                    unsigned long long *amax_bits, hipStream_t s);
-void validate_sym(int n, const int32_t *rp, const int32_t *ci, const double *v, const unsigned long long *amax_bits,
-                  int32_t *flags, int32_t *tpos, hipStream_t s);
-void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s);
-void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos, double theta,
-              uint8_t *strong, int32_t *stcnt, hipStream_t s);
+void validate_sym(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                  const unsigned long long *amax_bits, int32_t *flags, int32_t *tpos, hipStream_t s);
+void transpose_positions(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s);
+void strength(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos,
+              double theta, uint8_t *strong, int32_t *stcnt, hipStream_t s);
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
                int32_t *undecided, hipStream_t s);
 void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
@@ -261,7 +261,7 @@ int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool 
 void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
 double cw_bound(const Csr &M, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
 void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
-void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
+void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax_bits, int32_t *flags, hipStream_t s);
 void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t s);
 void scale_columns(const Csr &A, const double *wd, double *awd, hipStream_t s);

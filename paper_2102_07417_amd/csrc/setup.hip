@@ -3,10 +3,9 @@
 // Jacobi weights and the dense last-level factorisation.
 //
 // Every kernel that produces a value the CPU reference also produces does
-// the same floating-point operations in the same order (one thread per row,
-// CSR order, no fused multiply-add: the library is built with
-// -ffp-contract=off), so patterns and values of the hierarchy are
-// reproducible bit for bit.
+// the same floating-point operations in the same order (sums in CSR order,
+// no fused multiply-add: the library is built with -ffp-contract=off), so
+// patterns and values of the hierarchy are reproducible bit for bit.
 #include "devutil.hpp"
 #include "internal.hpp"
 
@@ -159,17 +158,33 @@ __global__ void k_val_rows(int n, const int32_t *rp, const int32_t *ci, const do
     if (threadIdx.x == 0) atomicMax(amax, bm);
 }
 
+// ---- per-row set-up work with G lanes per row (G a power of two <= 64):
+// lane sl of a row's group takes the row's entries sl, sl + G, ..., so the
+// group's loads are coalesced.  Whole groups run every loop and shuffle
+// (rows past n have empty bounds).  Maxima, integer counts and per-entry
+// values do not depend on the order of the lanes, and the one ordered sum
+// (Gershgorin) is formed in CSR order, so every result is the one a single
+// thread walking the row would give.
+template <int G>
+__device__ __forceinline__ int group_row(int n, int &sl) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    sl = (int)(t & (G - 1));
+    return (int)(t / G);
+}
+
 // tpos[e] = position of entry (j, i) in row j for entry e = (i, j); checks
 // structural and numerical symmetry when flags != nullptr.
-__global__ void k_tpos(int n, const int32_t *rp, const int32_t *ci, const double *v,
-                       const unsigned long long *amax, int32_t *flags, int32_t *tpos) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_tpos_g(int n, const int32_t *rp, const int32_t *ci, const double *v,
+                                                   const unsigned long long *amax, int32_t *flags, int32_t *tpos) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    if (i >= n) return;  // no shuffles below
     const double tol = flags ? 1e-12 * __longlong_as_double((long long)*amax) : 0.0;
     int bad = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        int j = ci[e];
-        int t = find_col(ci, rp[j], rp[j + 1], i);
+    for (int e = rp[i] + sl; e < rp[i + 1]; e += G) {
+        const int j = ci[e];
+        const int t = find_col(ci, rp[j], rp[j + 1], i);
         tpos[e] = t;
         if (t < 0) bad = 1;
         else if (flags && fabs(v[e] - v[t]) > tol) bad = 1;
@@ -180,20 +195,33 @@ __global__ void k_tpos(int n, const int32_t *rp, const int32_t *ci, const double
 // ---------------------------------------------------------------- strength
 // Classical strength with threshold: m_i = max_{k != i} (-a_ik);
 // j in S_i iff j != i, m_i > 0 and -a_ij >= theta * m_i (one rounded product).
-__global__ void k_strength(int n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
-                           uint8_t *strong) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_strength_g(int n, const int32_t *rp, const int32_t *ci, const double *v,
+                                                       double theta, uint8_t *strong) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
     int have = 0;
     double m = 0.0;
-    const int e0 = rp[i], e1 = rp[i + 1];
-    for (int e = e0; e < e1; ++e) {
+    for (int e = e0 + sl; e < e1; e += G) {
         if (ci[e] == i) continue;
-        double neg = -v[e];
-        if (!have || neg > m) { m = neg; have = 1; }
+        const double neg = -v[e];
+        if (!have || neg > m) {
+            m = neg;
+            have = 1;
+        }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {  // the group's maximum (and whether it has any entry)
+        const int oh = __shfl_xor(have, o, G);
+        const double om = __shfl_xor(m, o, G);
+        if (oh && (!have || om > m)) {
+            m = om;
+            have = 1;
+        }
     }
     const double thr = theta * m;
-    for (int e = e0; e < e1; ++e) {
+    for (int e = e0 + sl; e < e1; e += G) {
         const int j = ci[e];
         strong[e] = (j != i && have && m > 0.0 && -v[e] >= thr) ? 1 : 0;
     }
@@ -201,13 +229,95 @@ __global__ void k_strength(int n, const int32_t *rp, const int32_t *ci, const do
 
 // |S_i^T| = number of rows j with i in S_j = sum over row i of the strong
 // flags at the transposed positions (the pattern is symmetric)
-__global__ void k_stcount(int n, const int32_t *rp, const int32_t *tpos, const uint8_t *strong, int32_t *stcnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_stcount_g(int n, const int32_t *rp, const int32_t *tpos,
+                                                      const uint8_t *strong, int32_t *stcnt) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
     int c = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) c += strong[tpos[e]];
-    stcnt[i] = c;
+    for (int e = e0 + sl; e < e1; e += G) c += strong[tpos[e]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
+    if (i < n && sl == 0) stcnt[i] = c;
 }
+
+// Jacobi weight: dinv_i = 1 / a_ii and q_i = (sum_j |a_ij|) / a_ii (CSR
+// order); the max of q over rows is the Gershgorin bound of rho(D^{-1} A).
+// The group reads the row G entries at a time and every lane adds them up
+// one by one in CSR order from lane 0 to lane G-1 of each chunk, so s_i is
+// the sequential sum.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_diag_gersh_g(int n, const int32_t *rp, const int32_t *ci,
+                                                         const double *v, double *dinv, unsigned long long *qmax,
+                                                         int32_t *flags) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
+    double s = 0.0, d = 0.0;
+    int hd = 0;
+    for (int c = e0; c < e1; c += G) {
+        const int e = c + sl;
+        double a = 0.0;
+        if (e < e1) {
+            a = fabs(v[e]);
+            if (ci[e] == i) {
+                d = v[e];
+                hd = 1;
+            }
+        }
+        const int cnt = min(G, e1 - c);
+        for (int k = 0; k < cnt; ++k) s = s + __shfl(a, k, G);
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {  // the diagonal from the lane that read it
+        const int oh = __shfl_xor(hd, o, G);
+        const double od = __shfl_xor(d, o, G);
+        if (oh) {
+            d = od;
+            hd = 1;
+        }
+    }
+    double q = 0.0;
+    if (i < n && sl == 0) {
+        if (!(d > 0.0)) {
+            atomicOr(&flags[5], 1);
+            dinv[i] = 0.0;
+        } else {
+            dinv[i] = 1.0 / d;
+            q = s / d;
+        }
+    }
+    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
+    if (threadIdx.x == 0) atomicMax(qmax, bm);
+}
+
+// awd_e = a_e * wd_{col e}, one thread per nonzero
+__global__ void k_scale_entries(int64_t nnz, const int32_t *ci, const double *v, const double *wd, double *awd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) awd[e] = v[e] * wd[ci[e]];
+}
+
+// lanes per row for the group kernels: the smallest power of two covering
+// the mean row length, at most 64
+inline int group_lanes(int n, int64_t nnz) {
+    const double mean = n > 0 ? (double)nnz / n : 1.0;
+    int g = 1;
+    while (g < 64 && g < mean) g <<= 1;
+    return g;
+}
+inline int group_blocks(int n, int g) { return (int)(((int64_t)n * g + kBlock - 1) / kBlock); }
+
+#define CAMG_G_SWITCH(g, ...)                              \
+    switch (g) {                                           \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
+    default: { constexpr int G = 64; __VA_ARGS__; } break; \
+    }
 
 // ---------------------------------------------------------------- PMIS
 constexpr int8_t kF = -1, kU = 0, kC = 1;
@@ -431,40 +541,9 @@ __global__ void __launch_bounds__(1024) k_sort_rows_block(const int32_t *list, c
 }
 
 // ---------------------------------------------------------------- Jacobi weight
-// dinv_i = 1 / a_ii and q_i = (sum_j |a_ij|) / a_ii (CSR order); the max of
-// q over rows is the Gershgorin bound of rho(D^{-1} A).
-__global__ void k_diag_gersh(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
-                             unsigned long long *qmax, int32_t *flags) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double q = 0.0;
-    if (i < n) {
-        double s = 0.0, d = 0.0;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            s = s + fabs(v[e]);
-            if (ci[e] == i) d = v[e];
-        }
-        if (!(d > 0.0)) {
-            atomicOr(&flags[5], 1);
-            dinv[i] = 0.0;
-        } else {
-            dinv[i] = 1.0 / d;
-            q = s / d;
-        }
-    }
-    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
-    if (threadIdx.x == 0) atomicMax(qmax, bm);
-}
-
 __global__ void k_scale(int n, double omega, const double *dinv, double *wd) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) wd[i] = omega * dinv[i];
-}
-
-__global__ void k_scale_cols(int n, const int32_t *rp, const int32_t *ci, const double *v, const double *wd,
-                             double *awd) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) awd[e] = v[e] * wd[ci[e]];
 }
 
 __global__ void k_to_f32(int64_t n, const double *in, float *out) {
@@ -2568,19 +2647,22 @@ void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v,
     k_val_rows<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, flags, amax);
     HIPC(hipGetLastError());
 }
-void validate_sym(int n, const int32_t *rp, const int32_t *ci, const double *v, const unsigned long long *amax,
-                  int32_t *flags, int32_t *tpos, hipStream_t s) {
-    k_tpos<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, amax, flags, tpos);
+void validate_sym(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                  const unsigned long long *amax, int32_t *flags, int32_t *tpos, hipStream_t s) {
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_tpos_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, amax, flags, tpos)));
     HIPC(hipGetLastError());
 }
-void transpose_positions(int n, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s) {
-    k_tpos<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, nullptr, nullptr, nullptr, tpos);
+void transpose_positions(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s) {
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_tpos_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, nullptr, nullptr, nullptr, tpos)));
     HIPC(hipGetLastError());
 }
-void strength(int n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos, double theta,
-              uint8_t *strong, int32_t *stcnt, hipStream_t s) {
-    k_strength<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, theta, strong);
-    k_stcount<<<nblocks(n), kBlock, 0, s>>>(n, rp, tpos, strong, stcnt);
+void strength(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos,
+              double theta, uint8_t *strong, int32_t *stcnt, hipStream_t s) {
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_strength_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, theta, strong)));
+    CAMG_G_SWITCH(g, (k_stcount_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, tpos, strong, stcnt)));
     HIPC(hipGetLastError());
 }
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
@@ -2641,10 +2723,11 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s) {
     k_sort_rows_wave<<<(nc + 3) / 4, 256, 0, s>>>(nc, XT.rp, XT.ci, XT.v);
     HIPC(hipGetLastError());
 }
-void diag_gershgorin(int n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
+void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax, int32_t *flags, hipStream_t s) {
     HIPC(hipMemsetAsync(qmax, 0, sizeof(unsigned long long), s));
-    k_diag_gersh<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, dinv, qmax, flags);
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_diag_gersh_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, dinv, qmax, flags)));
     HIPC(hipGetLastError());
 }
 void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t s) {
@@ -2652,7 +2735,8 @@ void scale_vec(int n, double omega, const double *dinv, double *wd, hipStream_t 
     HIPC(hipGetLastError());
 }
 void scale_columns(const Csr &A, const double *wd, double *awd, hipStream_t s) {
-    k_scale_cols<<<nblocks(A.nr), kBlock, 0, s>>>(A.nr, A.rp, A.ci, A.v, wd, awd);
+    if (A.nnz > 0)
+        k_scale_entries<<<(int)((A.nnz + kBlock - 1) / kBlock), kBlock, 0, s>>>(A.nnz, A.ci, A.v, wd, awd);
     HIPC(hipGetLastError());
 }
 
