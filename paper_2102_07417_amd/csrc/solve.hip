@@ -38,6 +38,7 @@ namespace {
 constexpr int kTileW = CAMG_TILE_W;        // largest nominal nonzeros per tile
 constexpr int kTileRows = CAMG_TILE_ROWS;  // nominal rows per tile
 constexpr int kTileMaxRow = 4096; // longest row a tile can hold (LDS <= 8192 entries)
+constexpr int kTileWLong = 1664;   // nominal nonzeros per tile of the pipelined (long-row) loop
 
 template <class T>
 struct MatArg {
@@ -347,7 +348,7 @@ __device__ __forceinline__ void run_rows(const MatArg<T> &M, const G &g, const E
     const int sl = threadIdx.x & (LPR - 1), grp = threadIdx.x / LPR;
     constexpr int RPP = kBlock / LPR;  // rows per pass
     using Pre = typename E::Pre;
-    // Tiles of long rows (64 and more nonzeros on average): the next tile's
+    // Tiles of long rows (eight and more lanes per row): the next tile's
     // loads overlap the current tile's row sums (short-row tiles measured no
     // gain).
     if constexpr (SHAPE == 1 && G::kLoads == 1 && LPR >= 8) {
@@ -779,13 +780,21 @@ RowCfg choose_cfg(int n, int64_t nnz, int maxrow) {
         // about kTileRows rows per tile, at most kTileW nonzeros
         int W = (int)std::min<double>(kTileW, std::max(256.0, kTileRows * mean));
         W = (W + 63) / 64 * 64;
+        auto lanes = [&](int w) {
+            const double rows = w / mean;
+            int l = 1;
+            while (l * 2 <= 64 && l * 2 * rows <= kBlock) l *= 2;
+            return l;
+        };
+        // tiles of the pipelined loop (eight and more lanes per row) hold
+        // kTileWLong nominal nonzeros, so that a tile with its last row's
+        // overhang mostly stays within the two prefetched steps of
+        // 4 * kBlock entries
+        if (lanes(W) >= 8) W = std::min(W, kTileWLong);
         c.tile = true;
         c.W = W;
         c.tile_nnz = W + std::max(maxrow, 1);
-        const double rows = W / mean;
-        int l = 1;
-        while (l * 2 <= 64 && l * 2 * rows <= kBlock) l *= 2;
-        c.lpr = l;
+        c.lpr = lanes(W);
         c.ntiles = (int)std::max<int64_t>(1, (nnz + W - 1) / W);
         int g = std::min(c.ntiles, kMaxGrid);
         g = std::max(8, (g + 7) / 8 * 8);
