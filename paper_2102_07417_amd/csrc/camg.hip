@@ -56,7 +56,7 @@ void drain_cache(int dev) {
 Pool::Block Pool::get(size_t size) {
     int dev = 0;
     HIPC(hipGetDevice(&dev));
-    if (scratch_) {
+    {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         // smallest cached block that fits, if it is not much larger
         for (auto it = g_cache.lower_bound(size); it != g_cache.end() && it->first <= 2 * size + kChunk; ++it)
@@ -103,11 +103,22 @@ void *Pool::raw(size_t nbytes) {
 
 void Pool::release() {
     if (blocks_.empty()) return;
-    bool keep = scratch_;
-    if (keep && hipStreamSynchronize(stream_) != hipSuccess) {  // the stream's work on these blocks is done
-        (void)hipGetLastError();
-        keep = false;
+    bool keep = true;
+    if (scratch_) {
+        if (hipStreamSynchronize(stream_) != hipSuccess) keep = false;  // the stream's work on these blocks is done
+    } else {
+        // a handle's or an engine's blocks, which any stream may still use:
+        // wait for the devices they live on, as hipFree would
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) keep = false;
+        std::vector<int> devs;
+        for (const Block &bl : blocks_)
+            if (std::find(devs.begin(), devs.end(), bl.device) == devs.end()) devs.push_back(bl.device);
+        for (int d : devs)
+            if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess) keep = false;
+        if (cur >= 0) (void)hipSetDevice(cur);
     }
+    if (!keep) (void)hipGetLastError();
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         for (const Block &bl : blocks_) {

@@ -34,15 +34,17 @@ void hip_check(hipError_t e, const char *what);
 #define HIPC(x) ::camg::hip_check((x), #x)
 
 // ---------------------------------------------------------------- memory
-// Device allocations owned by a handle (or by a set-up scratch pool).
-// Device memory.  Requests are rounded to 256 bytes; small ones are packed
-// into 16 MB chunks, large ones get blocks of their own.  A scratch pool
-// (constructed with the stream its memory is used on) hands its blocks to a
-// per-device cache when released, after that stream has drained, and later
-// scratch pools take blocks from the cache instead of calling hipMalloc (a
-// hipFree waits for the whole device, a hipMalloc costs tens of
-// microseconds).  The cache keeps at most 4 GiB per device for the life of
-// the process.
+// Device allocations owned by a handle or an engine, or by a set-up scratch
+// pool.  Requests are rounded to 256 bytes; small ones are packed into 16 MB
+// chunks, large ones get blocks of their own.  A released pool hands its
+// blocks to a per-device cache (a scratch pool, constructed with the stream
+// its memory is used on, once that stream has drained; an owning pool once
+// the blocks' devices have drained, as hipFree would wait for them), and
+// later pools take blocks from the cache instead of calling hipMalloc, so
+// repeated set-ups and destructions cost no hipMalloc/hipFree (a hipMalloc
+// costs tens of microseconds, a hipFree waits for the whole device).  The
+// cache keeps at most 4 GiB per device for the life of the process; an
+// allocation that fails empties it and tries again.
 struct Pool {
     Pool() = default;
     explicit Pool(hipStream_t scratch_stream) : scratch_(true), stream_(scratch_stream) {}
