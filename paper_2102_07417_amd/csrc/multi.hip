@@ -172,6 +172,7 @@ __device__ __forceinline__ void block_col_sum_v(const double (&d)[V], double *pa
 }
 
 constexpr int kStage = 1024;  // CSR entries staged in LDS per chunk
+constexpr int64_t kSweepL2 = (int64_t)3 << 19;  // bytes of gathered block rows a stripe sweep may keep in an XCD's L2
 constexpr int kChunkRowsMax = 512;
 
 // One row: acc(c0 .. c0+V) = sum_j a_ij g(j, .).  Entries U at a time,
@@ -211,10 +212,20 @@ __device__ __forceinline__ void row_acc(int e0, int e1, const CI *ci, const AV *
 // `stage`, a chunk whose entries fit is first copied to LDS (indices,
 // values, row pointers, coalesced) and the group's lanes read the entries
 // there; otherwise they read them from memory.
+//
+// With pc > 0 the XCD's chunks are taken in stripes: its slab is read as
+// planes of pc chunks (pc chunks ~ the distance from a row to its farthest
+// neighbour, e.g. one plane of a 3D grid), each cut into stripes of wc
+// chunks, and the sweep goes stripe by stripe, plane by plane within a
+// stripe.  The block rows a chunk gathers from the planes before and after
+// it are then gathered again while they are still in the XCD's L2, instead
+// of a whole plane later (a plane of block rows exceeds the L2).  Every
+// chunk is taken once; only the order, and so which block adds a row's dot
+// terms, changes.
 template <class T, int K, bool DOT, int U, class G, class E>
 __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const T *__restrict__ av, G g, E epi, double *partials,
-                                                  unsigned long long pmask, int crows, int stage) {
+                                                  unsigned long long pmask, int crows, int stage, int pc, int wc) {
     using L = Lay<T, K>;
     constexpr int V = L::V, LPR = L::LPR, RPP = L::RPP;
     __shared__ int32_t s_ci[kStage];
@@ -230,7 +241,19 @@ __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restri
     double dot[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[v] = 0.0;
-    for (int ch = ch0 + jb; ch < ch1; ch += bx) {
+    const int m = ch1 - ch0;
+    const bool striped = pc > 0 && wc < pc;
+    const int zpl = striped ? (m + pc - 1) / pc : 1;  // planes of the slab
+    const int nst = striped ? (pc + wc - 1) / wc : 1;   // stripes of a plane
+    const int nq = striped ? nst * zpl * wc : m;
+    for (int q = jb; q < nq; q += bx) {
+        int ch = ch0 + q;
+        if (striped) {  // q -> (stripe, plane, offset in the stripe)
+            const int st = q / (zpl * wc), r = q - st * (zpl * wc);
+            const int z = r / wc, off = st * wc + (r - z * wc);
+            if (off >= pc || z * pc + off >= m) continue;
+            ch = ch0 + z * pc + off;
+        }
         const int a = ch * crows, b = min(a + crows, n);
         const int E0 = rp[a], E1 = rp[b];
         if (stage && E1 - E0 <= kStage && b - a <= kChunkRowsMax) {
@@ -270,6 +293,7 @@ int chunk_rows(int64_t nr, int64_t nnz) {
 template <class T, int K, class TX = T>
 struct MGather {
     static constexpr int kU = 8;
+    static constexpr int kRowBytes = K * (int)sizeof(TX);  // bytes of one gathered block row
     __device__ void prep(int) {}
     const TX *x;
     template <int V>
@@ -451,6 +475,17 @@ __global__ void __launch_bounds__(kBlock) mk_start(int n, SlotMap q, const doubl
             st->max_iter[c] = max_iter;
         }
     }
+}
+
+// largest |j - i| over the entries of a square CSR matrix with sorted rows
+// (first and last column of every row), as an unsigned maximum into *out
+__global__ void __launch_bounds__(kBlock) mk_band(int n, const int32_t *rp, const int32_t *ci,
+                                                  unsigned long long *out) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    int b = 0;
+    if (i < n && rp[i + 1] > rp[i]) b = max(i - ci[rp[i]], ci[rp[i + 1] - 1] - i);
+    const unsigned long long m = block_max_u64<kBlock>((unsigned long long)b);
+    if (threadIdx.x == 0) atomicMax(out, m);
 }
 
 // free the slots of `mask`
@@ -695,6 +730,7 @@ struct RowSched {
     int crows = 0;
     int grid = 0;
     int stage = 1;
+    int band = 0;  // largest |j - i| of the matrix (square matrices; 0: plain sweep)
 };
 
 struct Engine {
@@ -727,9 +763,16 @@ struct Engine {
     int64_t iter_seq = 0;                       // iterations issued (strides of the kernel timing)
     hipEvent_t tev[2] = {nullptr, nullptr};     // a timed level-0 post-smoothing launch
     std::map<std::tuple<const void *, int, int>, RowSched> sched;  // (matrix, value bytes, kind)
+    std::map<const void *, int> band;  // square matrices of the hierarchy: largest |j - i|
+    int band_of(const Csr &M) const {
+        auto it = band.find((const void *)&M);
+        return it == band.end() ? 0 : it->second;
+    }
     RowSched rs(const Csr &M, int vbytes, int kind) const {
         auto it = sched.find(std::make_tuple((const void *)&M, vbytes, kind));
-        return it == sched.end() ? RowSched{} : it->second;
+        RowSched r = it == sched.end() ? RowSched{} : it->second;
+        r.band = band_of(M);
+        return r;
     }
     ~Engine();
 };
@@ -780,14 +823,25 @@ int launch_mrows_u(const Csr &M, const T *av, hipStream_t s, const G &g, const E
     const int crows = rs.crows > 0 ? rs.crows : chunk_rows<T, K>(M.nr, M.nnz);
     int grid = forced_grid > 0 ? forced_grid : rows_grid<T, K, DOT, U, G, Ep>(M.nr, crows);
     if (!DOT && forced_grid <= 0 && rs.grid > 0) grid = rs.grid;
+    // stripes when the block rows of a band (a plane of a grid) outgrow the
+    // share of L2 they may take: five stripe-planes of gathered rows (the
+    // planes before and after the ones in flight) fit kSweepL2
+    int pc = 0, wc = 0;
+    if (rs.band > 0) {
+        const int64_t sw = std::max<int64_t>(crows, kSweepL2 / (5 * (int64_t)G::kRowBytes));  // rows per stripe
+        if (sw < rs.band) {
+            pc = (int)((rs.band + crows - 1) / crows);
+            wc = (int)std::max<int64_t>(1, sw / crows);
+        }
+    }
     if (t_mev_start) {  // timed launch: the events bracket the kernel's execution
         hipEvent_t a = t_mev_start, b = t_mev_stop;
         t_mev_start = t_mev_stop = nullptr;
         hipExtLaunchKernelGGL(mk_rows<T, K, DOT, U, G, Ep>, dim3(grid), dim3(kBlock), 0, s, a, b, 0, M.nr, M.rp,
-                              M.ci, av, g, e, partials, pmask, crows, rs.stage ? 1 : 0);
+                              M.ci, av, g, e, partials, pmask, crows, rs.stage ? 1 : 0, pc, wc);
     } else {
         mk_rows<T, K, DOT, U><<<grid, kBlock, 0, s>>>(M.nr, M.rp, M.ci, av, g, e, partials, pmask, crows,
-                                                      rs.stage ? 1 : 0);
+                                                      rs.stage ? 1 : 0, pc, wc);
     }
     HIPC(hipGetLastError());
     return grid;
@@ -1044,7 +1098,9 @@ void tune_matrix(Engine &E, const Csr &M, const T *av, const G &g, const Ep &ep,
     }
     constexpr int RPP = Lay<T, K>::RPP;
     const int def = chunk_rows<T, K>(M.nr, M.nnz);
-    const int rule = launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot);  // warm; the rule grid
+    RowSched plain{};
+    plain.band = E.band_of(M);  // candidates sweep in the order the runs use
+    const int rule = launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot, ~0ull, 0, plain);  // warm; the rule grid
     std::vector<RowSched> cand;
     for (int u : {4, 8})
         for (int cr : {def, std::max(RPP, def / 2 / RPP * RPP), RPP})
@@ -1052,7 +1108,7 @@ void tune_matrix(Engine &E, const Csr &M, const T *av, const G &g, const Ep &ep,
                 for (int gd : {0, std::max(8, rule / 2 / 8 * 8)}) {
                     if (gd != 0 && (dot || gd == rule)) continue;
                     if (!st && cr != def) continue;
-                    cand.push_back(RowSched{u, cr, gd, st});
+                    cand.push_back(RowSched{u, cr, gd, st, plain.band});
                 }
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
@@ -1186,6 +1242,20 @@ Engine *engine_create(Hier &h, int K, int cap, hipStream_t s) {
     HIPC(hipHostMalloc((void **)&E->hflag, 4 * sizeof(int32_t), hipHostMallocMapped));
     HIPC(hipHostGetDevicePointer((void **)&E->hflag_dev, E->hflag, 0));
     E->hflag[0] = 0;
+    // the band of every level's matrix, for the stripe order of the block sweeps
+    {
+        unsigned long long *dband = E->pool.alloc<unsigned long long>(h.nlev);
+        HIPC(hipMemsetAsync(dband, 0, sizeof(unsigned long long) * h.nlev, s));
+        for (int l = 0; l < h.nlev; ++l) {
+            const Csr &A = h.lev[l].A;
+            if (A.nr > 0) mk_band<<<(A.nr + kBlock - 1) / kBlock, kBlock, 0, s>>>(A.nr, A.rp, A.ci, dband + l);
+        }
+        HIPC(hipGetLastError());
+        std::vector<unsigned long long> hb(h.nlev);
+        HIPC(hipMemcpyAsync(hb.data(), dband, sizeof(unsigned long long) * h.nlev, hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        for (int l = 0; l < h.nlev; ++l) E->band[(const void *)&h.lev[l].A] = (int)hb[l];
+    }
     if (h.autotune) engine_autotune(*E, s);
     HIPC(hipStreamSynchronize(s));
     return E.release();
