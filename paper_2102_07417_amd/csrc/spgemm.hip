@@ -156,9 +156,12 @@ __global__ void __launch_bounds__(256) k_thread_rows(int nr, CsrView X, CsrView 
 // for each e the lanes take the entries t of row k = X.ci[e] of Y and call
 // f(j = Y.ci[t], x = X.v[e], y = Y.v[t]); step e finishes (wavefront
 // barrier) before step e+1 starts.  The entries of X's row (column, value,
-// extent of Y's row) are loaded by all lanes at once, 64 at a time, and the
-// first 64 entries of the next Y row are loaded while the current one is
-// processed, so each step waits for at most one round of memory latency.
+// extent of Y's row) are loaded by all lanes at once, 64 at a time.  The
+// first 64 entries of the Y rows are loaded kAhead steps at a time, the next
+// group's while the current group's steps run, so a step rarely waits for
+// memory (rows of Y with a few entries, as in the FSAI products, made every
+// step of a one-step-ahead pipeline wait for a full load).
+constexpr int kAhead = 4;
 template <class F>
 __device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrView &Y, int lane, F f) {
     const int e0 = X.rp[i], e1 = X.rp[i + 1];
@@ -172,34 +175,43 @@ __device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrV
             yb = Y.rp[k];
             yc = Y.rp[k + 1] - yb;
         }
-        int b = __shfl(yb, 0, kWave), c = __shfl(yc, 0, kWave);
-        double x = __shfl(xv, 0, kWave);
-        int jc = 0;
-        double vc = 0.0;
-        if (lane < c) {
-            jc = Y.ci[b + lane];
-            vc = Y.v[b + lane];
-        }
-        for (int q = 0; q < ne; ++q) {
-            int bn = 0, cn = 0, jn = 0;
-            double xn = 0.0, vn = 0.0;
-            if (q + 1 < ne) {
-                bn = __shfl(yb, q + 1, kWave);
-                cn = __shfl(yc, q + 1, kWave);
-                xn = __shfl(xv, q + 1, kWave);
-                if (lane < cn) {
-                    jn = Y.ci[bn + lane];
-                    vn = Y.v[bn + lane];
+        // the first kWave entries of Y's row for step q (q is the same on every lane)
+        auto head = [&](int q, int &j, double &v) {
+            j = 0;
+            v = 0.0;
+            if (q < ne) {
+                const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
+                if (lane < c) {
+                    j = Y.ci[b + lane];
+                    v = Y.v[b + lane];
                 }
             }
-            if (lane < c) f(jc, x, vc);
-            for (int t = b + kWave + lane; t < b + c; t += kWave) f(Y.ci[t], x, Y.v[t]);
-            WAVE_SYNC();
-            b = bn;
-            c = cn;
-            x = xn;
-            jc = jn;
-            vc = vn;
+        };
+        int jq[kAhead];
+        double vq[kAhead];
+#pragma unroll
+        for (int d = 0; d < kAhead; ++d) head(d, jq[d], vq[d]);
+        for (int q0 = 0; q0 < ne; q0 += kAhead) {
+            int jn[kAhead];
+            double vn[kAhead];
+#pragma unroll
+            for (int d = 0; d < kAhead; ++d) head(q0 + kAhead + d, jn[d], vn[d]);
+#pragma unroll
+            for (int d = 0; d < kAhead; ++d) {
+                const int q = q0 + d;
+                if (q < ne) {
+                    const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
+                    const double x = __shfl(xv, q, kWave);
+                    if (lane < c) f(jq[d], x, vq[d]);
+                    for (int t = b + kWave + lane; t < b + c; t += kWave) f(Y.ci[t], x, Y.v[t]);
+                    WAVE_SYNC();
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < kAhead; ++d) {
+                jq[d] = jn[d];
+                vq[d] = vn[d];
+            }
         }
     }
 }

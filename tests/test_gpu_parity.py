@@ -407,6 +407,43 @@ def test_multi_rhs_autotuned_schedules_are_bitwise_equal(camg):
         assert torch.equal(outs[0], outs[1])
 
 
+def test_multi_rhs_stripe_sweep(camg):
+    """Block sweeps in stripes: on a 32^3 Poisson grid a row's farthest
+    neighbour is a plane (1024 rows) away, and 64 FP64 columns make a block
+    row 512 bytes, so the planes' gathered rows outgrow the stripe budget
+    (1.5 MiB over five stripe-planes: 614 rows) and the level-0 sweeps run
+    stripe by stripe.  The columns match the oracle, and a column alone on a
+    64-slot engine equals the same column inside the 64-column block bit for
+    bit."""
+    print("[gpu] multi stripe sweep", flush=True)
+    A = PB.poisson3d(32)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    assert np.abs(A.col_idx - rows).max() == 1024
+    k = 64
+    B = PB.rhs_block(A.n, k)
+    s = camg.Solver(A, max_iter=3000)
+    dB = torch.from_numpy(B).to("cuda:0")
+    dX = torch.zeros_like(dB)
+    r = s.solve_multi_dev(dB, dX, rtol=1e-8)
+    assert r.status == camg.OK and np.all(r.true_relres < 1e-8 * 1.01)
+    X = dX.cpu().numpy()
+    o = O.Hierarchy(A, max_iter=3000)
+    for c in (0, 31, 63):
+        ro = o.solve(B[:, c], 1e-8, max_iter=3000)
+        assert abs(int(r.iters[c]) - ro.iters) <= 1, (c, r.iters[c], ro.iters)
+        assert np.linalg.norm(X[:, c] - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    e = camg.Engine(s, 64, hist_cap=200)
+    e.start(5, dB[:, 17].contiguous())
+    while e.step(8):
+        pass
+    xa = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    assert e.state()[0][5] == r.iters[17]
+    e.finish(5, xa)
+    assert torch.equal(xa, dX[:, 17].contiguous())
+    e.close()
+    s.close()
+
+
 # ----------------------------------------------------------------- FSAI smoother
 FSAI_CASES = ["poisson2d_64", "lognormal3d_24", "aniso3d_20", "elasticity_6"]
 
