@@ -227,6 +227,7 @@ def main():
                     help="right-hand sides of the batched (block) run on aniso3d_160; 0 skips it")
     ap.add_argument("--only-batched", action="store_true", help="print only the batched run")
     ap.add_argument("--only-c3", action="store_true", help="print only the elasticity case")
+    ap.add_argument("--c3-runs", type=int, default=2, help="timed solves per precision of the elasticity case")
     ap.add_argument("--small-systems", type=int, default=256,
                     help="independent 100x100 lognormal systems solved in one launch; 0 skips it")
     ap.add_argument("--serve", action="store_true",
@@ -256,7 +257,7 @@ def main():
     dev = torch.device("cuda:0")
     rates = [float(r) for r in args.rates.split(",")] if args.rates else SERVE_RATES
     if args.only_batched:
-        out = {"batched": batched_run(args.batched or 32, args.steps)}
+        out = {"copy_kernel_gbs": round(copy_kernel_gbs(dev), 1), "batched": batched_run(args.batched or 32, args.steps)}
         if args.small_systems:
             out["small_systems"] = small_systems_run(args.small_systems)
         print(json.dumps(out), flush=True)
@@ -276,8 +277,9 @@ def main():
     elas = None if (args.no_c3 or args.workload == "elasticity_64") else pool.submit(problems.workload,
                                                                                        "elasticity_64")
     if args.only_c3:
-        print(json.dumps({"c3": c3_run(elas.result() if elas else problems.workload("elasticity_64"),
-                                       args.no_cpu_baseline)}), flush=True)
+        print(json.dumps({"copy_kernel_gbs": round(copy_kernel_gbs(dev), 1),
+                          "c3": c3_run(elas.result() if elas else problems.workload("elasticity_64"),
+                                       args.no_cpu_baseline, runs=args.c3_runs)}), flush=True)
         return
 
     A = problems.workload(args.workload)
@@ -403,7 +405,7 @@ def main():
         out["c1"] = c1_run()
         log(f"c1: {out['c1']['solve_ms_median']} ms")
     if elas is not None:
-        out["c3"] = c3_run(elas.result(), args.no_cpu_baseline)
+        out["c3"] = c3_run(elas.result(), args.no_cpu_baseline, runs=args.c3_runs)
         log(f"c3: fp64 {out['c3']['fp64']['solve_ms']} ms, mixed {out['c3']['mixed']['solve_ms']} ms")
     pool.shutdown()
     if args.batched:
@@ -661,7 +663,7 @@ def small_systems_run(count, steps=3):
 
 
 # ====================================================================== c5
-SERVE_RATES = [20.0, 60.0]
+SERVE_RATES = [60.0, 120.0]
 
 
 def serve_run(rates, requests=1000, budget_gb=32.0, slots=16, seed=2021, interp=None):
