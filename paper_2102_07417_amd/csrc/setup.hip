@@ -307,6 +307,7 @@ inline int group_lanes(int n, int64_t nnz) {
     return g;
 }
 inline int group_blocks(int n, int g) { return (int)(((int64_t)n * g + kBlock - 1) / kBlock); }
+constexpr int kOrderedLanes = 8;  // most lanes per row of a group kernel with an ordered sum
 
 #define CAMG_G_SWITCH(g, ...)                              \
     switch (g) {                                           \
@@ -2726,7 +2727,9 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s) {
 void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax, int32_t *flags, hipStream_t s) {
     HIPC(hipMemsetAsync(qmax, 0, sizeof(unsigned long long), s));
-    const int g = group_lanes(n, nnz);
+    // the ordered sum is a chain as long as the row whatever G is, so fewer
+    // lanes per row keep more rows in flight per wavefront
+    const int g = std::min(group_lanes(n, nnz), kOrderedLanes);
     CAMG_G_SWITCH(g, (k_diag_gersh_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, dinv, qmax, flags)));
     HIPC(hipGetLastError());
 }
