@@ -19,7 +19,8 @@ _lib = None
 OK, MAXIT, E_ARG, E_CSR, E_NOT_SPD, E_BREAKDOWN, E_COARSE, E_NOMEM = 0, 1, -1, -2, -3, -4, -5, -6
 F, U, CPT = -1, 0, 1
 X_A, X_P, X_R, X_CF, X_STRONG, X_DINV, X_OMEGA, X_CHOL, X_STCNT, X_ROUNDS, X_G = range(11)
-SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI, SMOOTH_AFSAI = 0, 1, 2, 3
+AFSAI_MAXM, AFSAI_MAXCAND = 32, 2048
 INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 
 
@@ -29,7 +30,8 @@ class Params(C.Structure):
                 ("max_coarse", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("bamg_lmin", C.c_int32), ("bamg_lmax", C.c_int32),
                 ("bamg_eps", C.c_double), ("bamg_mu", C.c_double), ("psmooth", C.c_int32),
-                ("pfilter", C.c_double), ("srqm_iters", C.c_int32)]
+                ("pfilter", C.c_double), ("srqm_iters", C.c_int32), ("afsai_steps", C.c_int32),
+                ("afsai_step", C.c_int32), ("afsai_eps", C.c_double)]
 
 
 class CsrOut(C.Structure):
@@ -67,6 +69,7 @@ def lib():
         L.orc_chol_solve.argtypes = [i32, vp, vp, vp]
         L.orc_gershgorin_omega.argtypes = [i32, vp, vp, vp]; L.orc_gershgorin_omega.restype = dbl
         L.orc_fsai.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
+        L.orc_afsai.argtypes = [C.POINTER(CsrOut), i32, i32, dbl, C.POINTER(CsrOut), vp]
         L.orc_fsai_omega.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), vp]
         L.orc_csr_free.argtypes = [C.POINTER(CsrOut)]
         L.orc_setup.argtypes = [i32, vp, vp, vp, C.POINTER(Params), C.POINTER(vp)]
@@ -311,6 +314,18 @@ def fsai(A):
     return st, _from_out(r)
 
 
+def afsai(A, steps=10, step=2, eps=0.01):
+    """Adaptive FSAI factor (status, G, largest candidate set)."""
+    o, keep = _to_out(*_csr_arrays(A))
+    r = CsrOut()
+    mc = np.zeros(1, np.int32)
+    st = lib().orc_afsai(C.byref(o), steps, step, eps, C.byref(r), _p(mc))
+    if st != OK:
+        lib().orc_csr_free(C.byref(r))
+        return st, None, int(mc[0])
+    return st, _from_out(r), int(mc[0])
+
+
 def fsai_omega(A, G) -> float:
     oa, ka = _to_out(*_csr_arrays(A))
     og, kg = _to_out(*_csr_arrays(G))
@@ -402,12 +417,13 @@ class Hierarchy:
 
     def G(self, l):
         """FSAI factor of level l (FSAI smoother only)."""
-        n, nnz, _, _ = self.sizes(l)
-        rp_a = self.A(l)[2]
-        ci_a = self.A(l)[3]
-        nnzg = int(sum(np.count_nonzero(ci_a[rp_a[i]:rp_a[i + 1]] <= i) for i in range(n)))
-        rp = np.zeros(n + 1, np.int32); ci = np.zeros(nnzg, np.int32); v = np.zeros(nnzg)
+        n = self.sizes(l)[0]
+        rp = np.zeros(n + 1, np.int32)
+        assert lib().orc_export(self.h, l, X_G, _p(rp), None, None) == OK
+        nnzg = int(rp[n])
+        ci = np.zeros(max(nnzg, 1), np.int32); v = np.zeros(max(nnzg, 1))
         assert lib().orc_export(self.h, l, X_G, _p(rp), _p(ci), _p(v)) == OK
+        ci, v = ci[:nnzg], v[:nnzg]
         return (n, n, rp, ci, v)
 
     def omega(self, l):

@@ -44,6 +44,9 @@ void orc_params_default(orc_params *p) {
     p->psmooth = 0;
     p->pfilter = 1.0;
     p->srqm_iters = 0;
+    p->afsai_steps = 10;
+    p->afsai_step = 2;
+    p->afsai_eps = 0.01;
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -1240,6 +1243,143 @@ int orc_fsai(const orc_csr *A, orc_csr *G) {
 }
 
 /*
+ * Adaptive FSAI factor, the paper's default smoother (Section 2, eq. smo;
+ * the adaptive pattern search is that of the FSAI package the paper cites,
+ * JanFerSarGam15, in the reading below).  Row i of G minimises the Kaporin
+ * functional psi_i(g) = g^T A g over vectors with g_i = 1 supported on a
+ * pattern P_i of columns j <= i, and is then scaled by 1/sqrt(psi_i), so
+ * that G A G^T has a unit diagonal.  The pattern grows greedily from
+ * P_i = {i}; each pass:
+ *   1. solve A(P_i, P_i) y = e_last (P_i ascending, i last) by the dense
+ *      Cholesky factorisation and substitutions of the last level; the
+ *      minimiser is y / y_last and psi_i = 1 / y_last;
+ *   2. stop when `steps` growth steps have been taken, or, after a growth
+ *      step, when psi_i fell by no more than eps times its previous value;
+ *   3. the candidates are the columns j < i outside P_i stored in the rows
+ *      of A indexed by P_i; the gradient of psi_i with respect to g_j is
+ *      2 (A g)_j, which is proportional (factor 2 / y_last > 0) to
+ *      z_j = sum over the entries a_jc of row j with c in P_i of a_jc y_c,
+ *      summed in CSR order from 0.0;
+ *   4. add to P_i the `step` candidates with the largest |z_j| > 0 (the
+ *      smaller j first on ties); when no candidate has z_j != 0, stop.
+ * G(i, P_i) = y / sqrt(y_last), the same scaling as the static factor.
+ * steps = 0 gives G = D^{-1/2}.  *maxcand receives the largest candidate
+ * set of any row and pass (the hierarchy uses Jacobi on a level where it
+ * exceeds ORC_AFSAI_MAXCAND).
+ */
+int orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_csr *G, int32_t *maxcand) {
+    int32_t n = A->nrows;
+    if (steps < 0 || step < 1 || (int64_t)steps * step + 1 > ORC_AFSAI_MAXM || !(eps >= 0.0)) return ORC_E_ARG;
+    const int32_t mcap = steps * step + 1;
+    *maxcand = 0;
+    G->nrows = n; G->ncols = n;
+    G->rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *pci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)mcap);
+    double *pv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)mcap);
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));   /* place in P_i, or -1 */
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));  /* candidate stamp */
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    uint8_t *taken = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    double *M = (double *)malloc(sizeof(double) * (size_t)mcap * (size_t)mcap);
+    double *e = (double *)malloc(sizeof(double) * (size_t)mcap);
+    double *y = (double *)malloc(sizeof(double) * (size_t)mcap);
+    int32_t P[ORC_AFSAI_MAXM];
+    int st = ORC_OK;
+    if (!G->rp || !pci || !pv || !pos || !seen || !cand || !z || !taken || !M || !e || !y) st = ORC_E_NOMEM;
+    if (!st) {
+        G->rp[0] = 0;
+        for (int32_t j = 0; j < n; ++j) { pos[j] = -1; seen[j] = -1; }
+    }
+    int32_t stamp = 0;
+    for (int32_t i = 0; i < n && st == ORC_OK; ++i) {
+        int32_t m = 1;
+        P[0] = i;
+        double psi_prev = 0.0;
+        for (int32_t k = 0;; ++k) {
+            /* 1. local system on the current pattern */
+            for (int32_t r = 0; r < m; ++r)
+                for (int32_t c = 0; c < m; ++c) {
+                    int32_t p = find_in_row(A->rp, A->ci, P[r], P[c]);
+                    M[(size_t)r * m + c] = p >= 0 ? A->val[p] : 0.0;
+                }
+            if (orc_cholesky(m, M) != 0) { st = ORC_E_NOT_SPD; break; }
+            for (int32_t r = 0; r + 1 < m; ++r) e[r] = 0.0;
+            e[m - 1] = 1.0;
+            orc_chol_solve(m, M, e, y);
+            if (!(y[m - 1] > 0.0)) { st = ORC_E_NOT_SPD; break; }
+            const double psi = 1.0 / y[m - 1];
+            /* 2. stopping tests */
+            if (k == steps) break;
+            if (k > 0 && psi_prev - psi <= eps * psi_prev) break;
+            psi_prev = psi;
+            /* 3. candidates and gradient components */
+            for (int32_t r = 0; r < m; ++r) pos[P[r]] = r;
+            ++stamp;
+            int32_t nc = 0;
+            for (int32_t r = 0; r < m; ++r)
+                for (int32_t q = A->rp[P[r]]; q < A->rp[P[r] + 1]; ++q) {
+                    int32_t j = A->ci[q];
+                    if (j < i && pos[j] < 0 && seen[j] != stamp) { seen[j] = stamp; cand[nc++] = j; }
+                }
+            if (nc > *maxcand) *maxcand = nc;
+            for (int32_t t = 0; t < nc; ++t) {
+                int32_t j = cand[t];
+                double s = 0.0;
+                for (int32_t q = A->rp[j]; q < A->rp[j + 1]; ++q) {
+                    int32_t c = A->ci[q];
+                    if (pos[c] >= 0) s = s + A->val[q] * y[pos[c]];
+                }
+                z[t] = s;
+                taken[t] = 0;
+            }
+            for (int32_t r = 0; r < m; ++r) pos[P[r]] = -1;
+            /* 4. the `step` largest |z_j| join the pattern */
+            int32_t added = 0;
+            for (int32_t a = 0; a < step; ++a) {
+                int32_t best = -1;
+                for (int32_t t = 0; t < nc; ++t) {
+                    if (taken[t] || z[t] == 0.0) continue;
+                    if (best < 0 || fabs(z[t]) > fabs(z[best]) ||
+                        (fabs(z[t]) == fabs(z[best]) && cand[t] < cand[best])) best = t;
+                }
+                if (best < 0) break;
+                taken[best] = 1;
+                /* insert into the ascending pattern (i stays last) */
+                int32_t j = cand[best], r = m;
+                while (r > 0 && P[r - 1] > j) { P[r] = P[r - 1]; --r; }
+                P[r] = j;
+                ++m;
+                ++added;
+            }
+            if (added == 0) break;
+        }
+        if (st) break;
+        const double sd = sqrt(y[m - 1]);
+        for (int32_t r = 0; r < m; ++r) {
+            pci[(size_t)i * mcap + r] = P[r];
+            pv[(size_t)i * mcap + r] = y[r] / sd;
+        }
+        G->rp[i + 1] = G->rp[i] + m;
+    }
+    if (!st) {
+        int32_t nnz = G->rp[n];
+        G->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+        G->val = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+        if (!G->ci || !G->val) st = ORC_E_NOMEM;
+        for (int32_t i = 0; i < n && !st; ++i)
+            for (int32_t r = 0; r < G->rp[i + 1] - G->rp[i]; ++r) {
+                G->ci[G->rp[i] + r] = pci[(size_t)i * mcap + r];
+                G->val[G->rp[i] + r] = pv[(size_t)i * mcap + r];
+            }
+    } else {
+        G->ci = NULL; G->val = NULL;
+    }
+    free(pci); free(pv); free(pos); free(seen); free(cand); free(z); free(taken); free(M); free(e); free(y);
+    return st;
+}
+
+/*
  * Relaxation weight of the FSAI smoother S = I - omega G^T G A, which needs
  * omega rho(G^T G A) < 2 (eq. smoother).  rho(G^T G A) = rho(M) for
  * M = G A G^T, and rho(M) <= rho(|M|) <= max_i (|M| v)_i / v_i for every
@@ -1360,6 +1500,10 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
     int bamg = prm && prm->interp == ORC_INTERP_BAMG;
     if (bamg && (nt < 1 || nt > ORC_MAXNT || !V)) return ORC_E_ARG;
     if (prm && (prm->srqm_iters < 0 || prm->srqm_iters > 100 || (prm->srqm_iters > 0 && !bamg))) return ORC_E_ARG;
+    if (prm && prm->smoother == ORC_SMOOTH_AFSAI &&
+        (prm->afsai_steps < 0 || prm->afsai_step < 1 ||
+         (int64_t)prm->afsai_steps * prm->afsai_step + 1 > ORC_AFSAI_MAXM || !(prm->afsai_eps >= 0.0)))
+        return ORC_E_ARG;
     double *TV = NULL;
     if (bamg) {
         TV = (double *)malloc(sizeof(double) * (size_t)n * nt);
@@ -1397,10 +1541,18 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
         /* FSAI on this level: always with ORC_SMOOTH_FSAI; with
          * ORC_SMOOTH_FSAI_JACOBI when no row has more than ORC_FSAI_MAXROW
          * entries on or below the diagonal (Jacobi otherwise) */
-        const int use_fsai = h->prm.smoother == ORC_SMOOTH_FSAI ||
-                             (h->prm.smoother == ORC_SMOOTH_FSAI_JACOBI && lower_row_max(&L->A) <= ORC_FSAI_MAXROW);
+        int use_fsai = h->prm.smoother == ORC_SMOOTH_FSAI ||
+                       (h->prm.smoother == ORC_SMOOTH_FSAI_JACOBI && lower_row_max(&L->A) <= ORC_FSAI_MAXROW);
+        if (h->prm.smoother == ORC_SMOOTH_AFSAI) {
+            /* adaptive FSAI where every row's candidate set fits, Jacobi otherwise */
+            int32_t maxcand = 0;
+            st = orc_afsai(&L->A, h->prm.afsai_steps, h->prm.afsai_step, h->prm.afsai_eps, &L->G, &maxcand);
+            if (st) { orc_destroy(h); return st; }
+            use_fsai = maxcand <= ORC_AFSAI_MAXCAND;
+            if (!use_fsai) orc_csr_free(&L->G);
+        }
         if (use_fsai) {
-            st = orc_fsai(&L->A, &L->G);
+            if (h->prm.smoother != ORC_SMOOTH_AFSAI) st = orc_fsai(&L->A, &L->G);
             if (!st) st = orc_transpose(&L->G, &L->GT);
             double w = 0.0;
             if (!st && !(h->prm.omega > 0.0)) st = orc_fsai_omega(&L->A, &L->G, &w);

@@ -45,16 +45,22 @@ typedef struct {
     int32_t  max_levels;
     int32_t  max_coarse;
     int32_t  max_iter;
-    int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D), ORC_SMOOTH_FSAI (M^{-1} = G^T G) or
-                             ORC_SMOOTH_FSAI_JACOBI (FSAI per level where the rows are short enough) */
+    int32_t  smoother;    /* ORC_SMOOTH_JACOBI (M = D), ORC_SMOOTH_FSAI (M^{-1} = G^T G, static G),
+                             ORC_SMOOTH_FSAI_JACOBI (FSAI per level where the rows are short enough) or
+                             ORC_SMOOTH_AFSAI (M^{-1} = G^T G, adaptive G) */
     int32_t  interp;      /* ORC_INTERP_* */
     int32_t  bamg_lmin, bamg_lmax;  /* BAMG: interpolation distances tried (1, 2) */
     double   bamg_eps, bamg_mu;     /* BAMG: accept when relative residual <= eps and ||w|| <= mu */
     int32_t  psmooth;     /* 1: one Jacobi step on P (P - omega D^{-1} A P) */
     double   pfilter;     /* < 1: filter P, keeping this fraction of each row's absolute sum */
     int32_t  srqm_iters;  /* BAMG: SRQM steps refining the level-0 test space (0: none) */
+    int32_t  afsai_steps; /* ORC_SMOOTH_AFSAI: growth steps per row (steps * step + 1 <= ORC_AFSAI_MAXM) */
+    int32_t  afsai_step;  /*   entries added per step */
+    double   afsai_eps;   /*   stop a row when psi_i falls by no more than this fraction in a step */
 } orc_params;
-enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1, ORC_SMOOTH_FSAI_JACOBI = 2 };
+enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1, ORC_SMOOTH_FSAI_JACOBI = 2, ORC_SMOOTH_AFSAI = 3 };
+#define ORC_AFSAI_MAXM 32        /* entries of a row of the adaptive factor */
+#define ORC_AFSAI_MAXCAND 2048   /* ORC_SMOOTH_AFSAI: a level where a row's candidate set grows larger uses Jacobi */
 #define ORC_FSAI_MAXROW 192  /* ORC_SMOOTH_FSAI_JACOBI: FSAI on levels whose rows have at most this many
                                 entries on or below the diagonal, Jacobi on the others */
 enum { ORC_INTERP_DIRECT = 0, ORC_INTERP_CLASSICAL = 1, ORC_INTERP_EXTI = 2, ORC_INTERP_HYBRID = 3,
@@ -97,6 +103,8 @@ void orc_chol_solve(int32_t n, const double *L, const double *y, double *z);
 double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, const double *v);
 /* static FSAI factor G (lower triangular, pattern of the lower triangle of A) */
 int  orc_fsai(const orc_csr *A, orc_csr *G);
+/* adaptive FSAI factor (pattern grown greedily by the Kaporin gradient); *maxcand: largest candidate set */
+int  orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_csr *G, int32_t *maxcand);
 /* omega = (4/3) / max_i sum_j |(G A G^T)_ij| */
 int  orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega);
 void orc_csr_free(orc_csr *m);

@@ -1,7 +1,7 @@
 """Plant plausible mistakes in a copy of the oracle source and check that
-the pins in test_oracle.py, test_oracle_fsai.py, test_oracle_interp.py,
-test_oracle_bamg.py and test_oracle_srqm.py catch every one of them (CPU
-only)."""
+the pins in test_oracle.py, test_oracle_fsai.py, test_oracle_afsai.py,
+test_oracle_interp.py, test_oracle_bamg.py and test_oracle_srqm.py catch
+every one of them (CPU only)."""
 import os
 import subprocess
 import sys
@@ -92,13 +92,26 @@ MUTATIONS = [
     ("srqm_symeig_rotation_sign", "const double s = t * c;", "const double s = -t * c;"),
     ("srqm_fsai_G_twice", "csr_block(GT, nt, Y, nt, S + nt, m);", "csr_block(G, nt, Y, nt, S + nt, m);"),
     ("fsai_jacobi_threshold_flipped", "lower_row_max(&L->A) <= ORC_FSAI_MAXROW", "lower_row_max(&L->A) > ORC_FSAI_MAXROW"),
+    ("afsai_tie_largest", "(fabs(z[t]) == fabs(z[best]) && cand[t] < cand[best])",
+     "(fabs(z[t]) == fabs(z[best]) && cand[t] > cand[best])"),
+    ("afsai_signed_gradient", "fabs(z[t]) > fabs(z[best]) ||", "z[t] > z[best] ||"),
+    ("afsai_candidates_in_pattern", "if (j < i && pos[j] < 0 && seen[j] != stamp)",
+     "if (j < i && seen[j] != stamp)"),
+    ("afsai_gradient_wrong_entry", "if (pos[c] >= 0) s = s + A->val[q] * y[pos[c]];",
+     "if (pos[c] >= 0) s = s + A->val[q] * y[0];"),
+    ("afsai_stop_inverted", "if (k > 0 && psi_prev - psi <= eps * psi_prev) break;",
+     "if (k > 0 && psi_prev - psi > eps * psi_prev) break;"),
+    ("afsai_psi_not_kept", "            psi_prev = psi;\n", "            (void)psi_prev;\n"),
+    ("afsai_one_step_more", "if (k == steps) break;", "if (k == steps + 1) break;"),
+    ("afsai_no_scaling", "pv[(size_t)i * mcap + r] = y[r] / sd;", "pv[(size_t)i * mcap + r] = y[r];"),
+    ("afsai_fallback_flipped", "use_fsai = maxcand <= ORC_AFSAI_MAXCAND;", "use_fsai = maxcand > ORC_AFSAI_MAXCAND;"),
     ("fsai_jacobi_smoother_from_params", "int fsai = L->G.rp != NULL;  /* this level's smoother */",
      "int fsai = h->prm.smoother == ORC_SMOOTH_FSAI;"),
 ]
 
 
-PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_interp.py", "test_oracle_bamg.py",
-             "test_oracle_srqm.py"]
+PIN_FILES = ["test_oracle.py", "test_oracle_fsai.py", "test_oracle_afsai.py", "test_oracle_interp.py",
+             "test_oracle_bamg.py", "test_oracle_srqm.py"]
 
 
 def _first_file(name):
@@ -106,6 +119,8 @@ def _first_file(name):
     -x a caught mutation stops early; every pin file still runs."""
     if name.startswith("fsai"):
         return "test_oracle_fsai.py"
+    if name.startswith("afsai"):
+        return "test_oracle_afsai.py"
     if name.startswith(("ext_", "hybrid_", "classical_")):
         return "test_oracle_interp.py"
     if name.startswith("bamg_"):

@@ -14,8 +14,8 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_FILES = ["tests/test_oracle.py", "tests/test_oracle_fsai.py", "tests/test_oracle_interp.py",
-             "tests/test_oracle_bamg.py", "tests/test_oracle_srqm.py"]
+PIN_FILES = ["tests/test_oracle.py", "tests/test_oracle_fsai.py", "tests/test_oracle_afsai.py",
+             "tests/test_oracle_interp.py", "tests/test_oracle_bamg.py", "tests/test_oracle_srqm.py"]
 
 
 def _asan_runtime():
