@@ -70,6 +70,7 @@ def lib():
         L.orc_gershgorin_omega.argtypes = [i32, vp, vp, vp]; L.orc_gershgorin_omega.restype = dbl
         L.orc_fsai.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_afsai.argtypes = [C.POINTER(CsrOut), i32, i32, dbl, C.POINTER(CsrOut), vp]
+        L.orc_afsai_rows.argtypes = [C.POINTER(CsrOut), i32, i32, dbl, i32, vp, vp, vp, vp, vp]
         L.orc_fsai_omega.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), vp]
         L.orc_csr_free.argtypes = [C.POINTER(CsrOut)]
         L.orc_setup.argtypes = [i32, vp, vp, vp, C.POINTER(Params), C.POINTER(vp)]
@@ -324,6 +325,22 @@ def afsai(A, steps=10, step=2, eps=0.01):
         lib().orc_csr_free(C.byref(r))
         return st, None, int(mc[0])
     return st, _from_out(r), int(mc[0])
+
+
+def afsai_rows(A, rows, steps=10, step=2, eps=0.01):
+    """Rows `rows` of the adaptive FSAI factor: list of (columns, values)."""
+    o, keep = _to_out(*_csr_arrays(A))
+    sel = np.ascontiguousarray(rows, np.int32)
+    mcap = steps * step + 1
+    cols = np.zeros(max(len(sel), 1) * mcap, np.int32)
+    vals = np.zeros(max(len(sel), 1) * mcap)
+    cnt = np.zeros(max(len(sel), 1), np.int32)
+    mc = np.zeros(1, np.int32)
+    st = lib().orc_afsai_rows(C.byref(o), steps, step, eps, len(sel), _p(sel), _p(cols), _p(vals), _p(cnt), _p(mc))
+    if st != OK:
+        raise OracleError(st)
+    return [(cols[t * mcap:t * mcap + cnt[t]].copy(), vals[t * mcap:t * mcap + cnt[t]].copy())
+            for t in range(len(sel))]
 
 
 def fsai_omega(A, G) -> float:

@@ -1267,100 +1267,136 @@ int orc_fsai(const orc_csr *A, orc_csr *G) {
  * set of any row and pass (the hierarchy uses Jacobi on a level where it
  * exceeds ORC_AFSAI_MAXCAND).
  */
+typedef struct {
+    int32_t *pos;     /* place of a column in the pattern, or -1 */
+    int32_t *seen;    /* candidate stamp */
+    int32_t *cand;
+    double *z;
+    uint8_t *taken;
+    double *M, *e, *y;
+    int32_t stamp;
+} afsai_work;
+
+static void afsai_work_free(afsai_work *w) {
+    free(w->pos); free(w->seen); free(w->cand); free(w->z); free(w->taken); free(w->M); free(w->e); free(w->y);
+}
+
+static int afsai_work_init(afsai_work *w, int32_t n, int32_t mcap) {
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    w->pos = (int32_t *)malloc(sizeof(int32_t) * nn);
+    w->seen = (int32_t *)malloc(sizeof(int32_t) * nn);
+    w->cand = (int32_t *)malloc(sizeof(int32_t) * nn);
+    w->z = (double *)malloc(sizeof(double) * nn);
+    w->taken = (uint8_t *)malloc(nn);
+    w->M = (double *)malloc(sizeof(double) * (size_t)mcap * (size_t)mcap);
+    w->e = (double *)malloc(sizeof(double) * (size_t)mcap);
+    w->y = (double *)malloc(sizeof(double) * (size_t)mcap);
+    w->stamp = 0;
+    if (!w->pos || !w->seen || !w->cand || !w->z || !w->taken || !w->M || !w->e || !w->y) {
+        afsai_work_free(w);
+        return ORC_E_NOMEM;
+    }
+    for (int32_t j = 0; j < n; ++j) { w->pos[j] = -1; w->seen[j] = -1; }
+    return ORC_OK;
+}
+
+/* one row: its pattern P (ascending, i last) and values into P / val, the
+ * count into *mout; the largest candidate set into *maxcand */
+static int afsai_row(const orc_csr *A, int32_t i, int32_t steps, int32_t step, double eps, afsai_work *w,
+                     int32_t *P, double *val, int32_t *mout, int32_t *maxcand) {
+    double *M = w->M, *e = w->e, *y = w->y, *z = w->z;
+    int32_t *pos = w->pos, *seen = w->seen, *cand = w->cand;
+    uint8_t *taken = w->taken;
+    int32_t m = 1;
+    P[0] = i;
+    double psi_prev = 0.0;
+    for (int32_t k = 0;; ++k) {
+        /* 1. local system on the current pattern */
+        for (int32_t r = 0; r < m; ++r)
+            for (int32_t c = 0; c < m; ++c) {
+                int32_t p = find_in_row(A->rp, A->ci, P[r], P[c]);
+                M[(size_t)r * m + c] = p >= 0 ? A->val[p] : 0.0;
+            }
+        if (orc_cholesky(m, M) != 0) return ORC_E_NOT_SPD;
+        for (int32_t r = 0; r + 1 < m; ++r) e[r] = 0.0;
+        e[m - 1] = 1.0;
+        orc_chol_solve(m, M, e, y);
+        if (!(y[m - 1] > 0.0)) return ORC_E_NOT_SPD;
+        const double psi = 1.0 / y[m - 1];
+        /* 2. stopping tests */
+        if (k == steps) break;
+        if (k > 0 && psi_prev - psi <= eps * psi_prev) break;
+        psi_prev = psi;
+        /* 3. candidates and gradient components */
+        for (int32_t r = 0; r < m; ++r) pos[P[r]] = r;
+        ++w->stamp;
+        int32_t nc = 0;
+        for (int32_t r = 0; r < m; ++r)
+            for (int32_t q = A->rp[P[r]]; q < A->rp[P[r] + 1]; ++q) {
+                int32_t j = A->ci[q];
+                if (j < i && pos[j] < 0 && seen[j] != w->stamp) { seen[j] = w->stamp; cand[nc++] = j; }
+            }
+        if (nc > *maxcand) *maxcand = nc;
+        for (int32_t t = 0; t < nc; ++t) {
+            int32_t j = cand[t];
+            double s = 0.0;
+            for (int32_t q = A->rp[j]; q < A->rp[j + 1]; ++q) {
+                int32_t c = A->ci[q];
+                if (pos[c] >= 0) s = s + A->val[q] * y[pos[c]];
+            }
+            z[t] = s;
+            taken[t] = 0;
+        }
+        for (int32_t r = 0; r < m; ++r) pos[P[r]] = -1;
+        /* 4. the `step` largest |z_j| join the pattern */
+        int32_t added = 0;
+        for (int32_t a = 0; a < step; ++a) {
+            int32_t best = -1;
+            for (int32_t t = 0; t < nc; ++t) {
+                if (taken[t] || z[t] == 0.0) continue;
+                if (best < 0 || fabs(z[t]) > fabs(z[best]) ||
+                    (fabs(z[t]) == fabs(z[best]) && cand[t] < cand[best])) best = t;
+            }
+            if (best < 0) break;
+            taken[best] = 1;
+            /* insert into the ascending pattern (i stays last) */
+            int32_t j = cand[best], r = m;
+            while (r > 0 && P[r - 1] > j) { P[r] = P[r - 1]; --r; }
+            P[r] = j;
+            ++m;
+            ++added;
+        }
+        if (added == 0) break;
+    }
+    const double sd = sqrt(y[m - 1]);
+    for (int32_t r = 0; r < m; ++r) val[r] = y[r] / sd;
+    *mout = m;
+    return ORC_OK;
+}
+
+static int afsai_args_ok(int32_t steps, int32_t step, double eps) {
+    return !(steps < 0 || step < 1 || (int64_t)steps * step + 1 > ORC_AFSAI_MAXM || !(eps >= 0.0));
+}
+
 int orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_csr *G, int32_t *maxcand) {
     int32_t n = A->nrows;
-    if (steps < 0 || step < 1 || (int64_t)steps * step + 1 > ORC_AFSAI_MAXM || !(eps >= 0.0)) return ORC_E_ARG;
-    const int32_t mcap = steps * step + 1;
-    *maxcand = 0;
     G->nrows = n; G->ncols = n;
+    G->rp = NULL; G->ci = NULL; G->val = NULL;
+    *maxcand = 0;
+    if (!afsai_args_ok(steps, step, eps)) return ORC_E_ARG;
+    const int32_t mcap = steps * step + 1;
+    afsai_work w;
+    int st = afsai_work_init(&w, n, mcap);
+    if (st) return st;
     G->rp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
     int32_t *pci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)mcap);
     double *pv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)mcap);
-    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));   /* place in P_i, or -1 */
-    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));  /* candidate stamp */
-    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    uint8_t *taken = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
-    double *M = (double *)malloc(sizeof(double) * (size_t)mcap * (size_t)mcap);
-    double *e = (double *)malloc(sizeof(double) * (size_t)mcap);
-    double *y = (double *)malloc(sizeof(double) * (size_t)mcap);
-    int32_t P[ORC_AFSAI_MAXM];
-    int st = ORC_OK;
-    if (!G->rp || !pci || !pv || !pos || !seen || !cand || !z || !taken || !M || !e || !y) st = ORC_E_NOMEM;
-    if (!st) {
-        G->rp[0] = 0;
-        for (int32_t j = 0; j < n; ++j) { pos[j] = -1; seen[j] = -1; }
-    }
-    int32_t stamp = 0;
-    for (int32_t i = 0; i < n && st == ORC_OK; ++i) {
-        int32_t m = 1;
-        P[0] = i;
-        double psi_prev = 0.0;
-        for (int32_t k = 0;; ++k) {
-            /* 1. local system on the current pattern */
-            for (int32_t r = 0; r < m; ++r)
-                for (int32_t c = 0; c < m; ++c) {
-                    int32_t p = find_in_row(A->rp, A->ci, P[r], P[c]);
-                    M[(size_t)r * m + c] = p >= 0 ? A->val[p] : 0.0;
-                }
-            if (orc_cholesky(m, M) != 0) { st = ORC_E_NOT_SPD; break; }
-            for (int32_t r = 0; r + 1 < m; ++r) e[r] = 0.0;
-            e[m - 1] = 1.0;
-            orc_chol_solve(m, M, e, y);
-            if (!(y[m - 1] > 0.0)) { st = ORC_E_NOT_SPD; break; }
-            const double psi = 1.0 / y[m - 1];
-            /* 2. stopping tests */
-            if (k == steps) break;
-            if (k > 0 && psi_prev - psi <= eps * psi_prev) break;
-            psi_prev = psi;
-            /* 3. candidates and gradient components */
-            for (int32_t r = 0; r < m; ++r) pos[P[r]] = r;
-            ++stamp;
-            int32_t nc = 0;
-            for (int32_t r = 0; r < m; ++r)
-                for (int32_t q = A->rp[P[r]]; q < A->rp[P[r] + 1]; ++q) {
-                    int32_t j = A->ci[q];
-                    if (j < i && pos[j] < 0 && seen[j] != stamp) { seen[j] = stamp; cand[nc++] = j; }
-                }
-            if (nc > *maxcand) *maxcand = nc;
-            for (int32_t t = 0; t < nc; ++t) {
-                int32_t j = cand[t];
-                double s = 0.0;
-                for (int32_t q = A->rp[j]; q < A->rp[j + 1]; ++q) {
-                    int32_t c = A->ci[q];
-                    if (pos[c] >= 0) s = s + A->val[q] * y[pos[c]];
-                }
-                z[t] = s;
-                taken[t] = 0;
-            }
-            for (int32_t r = 0; r < m; ++r) pos[P[r]] = -1;
-            /* 4. the `step` largest |z_j| join the pattern */
-            int32_t added = 0;
-            for (int32_t a = 0; a < step; ++a) {
-                int32_t best = -1;
-                for (int32_t t = 0; t < nc; ++t) {
-                    if (taken[t] || z[t] == 0.0) continue;
-                    if (best < 0 || fabs(z[t]) > fabs(z[best]) ||
-                        (fabs(z[t]) == fabs(z[best]) && cand[t] < cand[best])) best = t;
-                }
-                if (best < 0) break;
-                taken[best] = 1;
-                /* insert into the ascending pattern (i stays last) */
-                int32_t j = cand[best], r = m;
-                while (r > 0 && P[r - 1] > j) { P[r] = P[r - 1]; --r; }
-                P[r] = j;
-                ++m;
-                ++added;
-            }
-            if (added == 0) break;
-        }
-        if (st) break;
-        const double sd = sqrt(y[m - 1]);
-        for (int32_t r = 0; r < m; ++r) {
-            pci[(size_t)i * mcap + r] = P[r];
-            pv[(size_t)i * mcap + r] = y[r] / sd;
-        }
-        G->rp[i + 1] = G->rp[i] + m;
+    if (!G->rp || !pci || !pv) st = ORC_E_NOMEM;
+    if (!st) G->rp[0] = 0;
+    for (int32_t i = 0; i < n && !st; ++i) {
+        int32_t m = 0;
+        st = afsai_row(A, i, steps, step, eps, &w, pci + (size_t)i * mcap, pv + (size_t)i * mcap, &m, maxcand);
+        if (!st) G->rp[i + 1] = G->rp[i] + m;
     }
     if (!st) {
         int32_t nnz = G->rp[n];
@@ -1372,10 +1408,29 @@ int orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_csr
                 G->ci[G->rp[i] + r] = pci[(size_t)i * mcap + r];
                 G->val[G->rp[i] + r] = pv[(size_t)i * mcap + r];
             }
-    } else {
-        G->ci = NULL; G->val = NULL;
     }
-    free(pci); free(pv); free(pos); free(seen); free(cand); free(z); free(taken); free(M); free(e); free(y);
+    free(pci); free(pv);
+    afsai_work_free(&w);
+    return st;
+}
+
+/* the rows sel[0..nsel) only (for sampled checks of large matrices):
+ * row t's pattern and values in cols / vals[t * (steps * step + 1) ...],
+ * its entry count in cnt[t] */
+int orc_afsai_rows(const orc_csr *A, int32_t steps, int32_t step, double eps, int32_t nsel, const int32_t *sel,
+                   int32_t *cols, double *vals, int32_t *cnt, int32_t *maxcand) {
+    *maxcand = 0;
+    if (!afsai_args_ok(steps, step, eps) || nsel < 0) return ORC_E_ARG;
+    const int32_t mcap = steps * step + 1;
+    for (int32_t t = 0; t < nsel; ++t)
+        if (sel[t] < 0 || sel[t] >= A->nrows) return ORC_E_ARG;
+    afsai_work w;
+    int st = afsai_work_init(&w, A->nrows, mcap);
+    if (st) return st;
+    for (int32_t t = 0; t < nsel && !st; ++t)
+        st = afsai_row(A, sel[t], steps, step, eps, &w, cols + (size_t)t * mcap, vals + (size_t)t * mcap, &cnt[t],
+                       maxcand);
+    afsai_work_free(&w);
     return st;
 }
 

@@ -105,6 +105,9 @@ double orc_gershgorin_omega(int32_t n, const int32_t *rp, const int32_t *ci, con
 int  orc_fsai(const orc_csr *A, orc_csr *G);
 /* adaptive FSAI factor (pattern grown greedily by the Kaporin gradient); *maxcand: largest candidate set */
 int  orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_csr *G, int32_t *maxcand);
+/* the same for the rows sel[0..nsel) only: row t in cols / vals[t * (steps * step + 1) ...], count in cnt[t] */
+int  orc_afsai_rows(const orc_csr *A, int32_t steps, int32_t step, double eps, int32_t nsel, const int32_t *sel,
+                    int32_t *cols, double *vals, int32_t *cnt, int32_t *maxcand);
 /* omega = (4/3) / max_i sum_j |(G A G^T)_ij| */
 int  orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega);
 void orc_csr_free(orc_csr *m);

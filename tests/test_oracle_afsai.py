@@ -267,3 +267,13 @@ def test_afsai_pcg_converges_faster_than_jacobi_on_elasticity():
     assert rj.status == O.OK and ra.status == O.OK
     assert np.linalg.norm(b - dense(A) @ ra.x) / np.linalg.norm(b) < 1.5e-8
     assert ra.iters < rj.iters
+
+
+def test_afsai_selected_rows_match_all_rows():
+    A = PB.elasticity3d(3)
+    G, _ = _aG(A, 6, 3, 0.005)
+    rows = [0, 1, 5, 17, A.n // 2, A.n - 1]
+    for (cols, vals), i in zip(O.afsai_rows(A, rows, 6, 3, 0.005), rows):
+        gc, gv = _rows(G)[i]
+        assert list(cols) == gc
+        np.testing.assert_array_equal(vals, gv)

@@ -95,15 +95,16 @@ MUTATIONS = [
     ("afsai_tie_largest", "(fabs(z[t]) == fabs(z[best]) && cand[t] < cand[best])",
      "(fabs(z[t]) == fabs(z[best]) && cand[t] > cand[best])"),
     ("afsai_signed_gradient", "fabs(z[t]) > fabs(z[best]) ||", "z[t] > z[best] ||"),
-    ("afsai_candidates_in_pattern", "if (j < i && pos[j] < 0 && seen[j] != stamp)",
-     "if (j < i && seen[j] != stamp)"),
+    ("afsai_candidates_in_pattern", "if (j < i && pos[j] < 0 && seen[j] != w->stamp)",
+     "if (j < i && seen[j] != w->stamp)"),
     ("afsai_gradient_wrong_entry", "if (pos[c] >= 0) s = s + A->val[q] * y[pos[c]];",
      "if (pos[c] >= 0) s = s + A->val[q] * y[0];"),
     ("afsai_stop_inverted", "if (k > 0 && psi_prev - psi <= eps * psi_prev) break;",
      "if (k > 0 && psi_prev - psi > eps * psi_prev) break;"),
-    ("afsai_psi_not_kept", "            psi_prev = psi;\n", "            (void)psi_prev;\n"),
+    ("afsai_psi_not_kept", "        psi_prev = psi;\n", "        (void)psi_prev;\n"),
     ("afsai_one_step_more", "if (k == steps) break;", "if (k == steps + 1) break;"),
-    ("afsai_no_scaling", "pv[(size_t)i * mcap + r] = y[r] / sd;", "pv[(size_t)i * mcap + r] = y[r];"),
+    ("afsai_no_scaling", "for (int32_t r = 0; r < m; ++r) val[r] = y[r] / sd;",
+     "for (int32_t r = 0; r < m; ++r) val[r] = y[r];"),
     ("afsai_fallback_flipped", "use_fsai = maxcand <= ORC_AFSAI_MAXCAND;", "use_fsai = maxcand > ORC_AFSAI_MAXCAND;"),
     ("fsai_jacobi_smoother_from_params", "int fsai = L->G.rp != NULL;  /* this level's smoother */",
      "int fsai = h->prm.smoother == ORC_SMOOTH_FSAI;"),
