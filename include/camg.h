@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CAMG_ABI_VERSION 7
+#define CAMG_ABI_VERSION 8
 
 typedef struct camg_hier *camg_handle;
 
@@ -62,8 +62,19 @@ enum { CAMG_FP64 = 0, CAMG_MIXED_FP32 = 1 };
  * static factor on the pattern of the lower triangle of A; every row of it
  * must have at most 192 entries, CAMG_E_ARG otherwise).  FSAI_JACOBI: FSAI
  * on each level whose rows have at most 192 entries on or below the
- * diagonal and Jacobi on the others (e.g. the dense coarse levels of BAMG). */
-enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1, CAMG_SMOOTH_FSAI_JACOBI = 2 };
+ * diagonal and Jacobi on the others (e.g. the dense coarse levels of BAMG).
+ * AFSAI: the adaptive factor, the paper's default smoother (eq. smo, with
+ * the pattern search of the FSAI package it cites): row i of G minimises
+ * psi_i(g) = g^T A g (g_i = 1) on a pattern grown from {i}; each step adds
+ * the afsai_step columns j < i, taken from the rows of A indexed by the
+ * pattern, with the largest |(A g)_j| (the Kaporin gradient; the smaller j
+ * on ties), for at most afsai_steps steps, and a row stops early once psi_i
+ * falls by no more than afsai_eps of its previous value in a step; the row
+ * is scaled so that G A G^T has a unit diagonal.  A level where a row's
+ * candidate set exceeds CAMG_AFSAI_MAXCAND columns uses Jacobi. */
+enum { CAMG_SMOOTH_JACOBI = 0, CAMG_SMOOTH_FSAI = 1, CAMG_SMOOTH_FSAI_JACOBI = 2, CAMG_SMOOTH_AFSAI = 3 };
+#define CAMG_AFSAI_MAXM 32        /* afsai_steps * afsai_step + 1 is at most this */
+#define CAMG_AFSAI_MAXCAND 2048
 /* Interpolation (Section 2, Interpolation).  DIRECT: distance-one direct
  * formula over C_i^S (the default).  CLASSICAL: eq. clasInt with the
  * correction for strong F neighbours that share no C point (they are
@@ -107,8 +118,9 @@ typedef struct {
     int32_t  max_coarse;  /* a level with at most this many unknowns is solved directly; default 256 */
     int32_t  precision;   /* CAMG_FP64 or CAMG_MIXED_FP32 (FP32 V-cycle inside FP64 PCG) */
     int32_t  max_iter;    /* PCG iteration limit; default 1000 */
-    int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default) or CAMG_SMOOTH_FSAI; FSAI needs at most 192 entries
-                             on or below the diagonal per row, and runs on the single-system path only */
+    int32_t  smoother;    /* CAMG_SMOOTH_JACOBI (default), _FSAI, _FSAI_JACOBI or _AFSAI; static FSAI needs at
+                             most 192 entries on or below the diagonal per row; the FSAI smoothers run on the
+                             single-system path only */
     int32_t  interp;      /* CAMG_INTERP_DIRECT (default), _CLASSICAL, _EXTI or _HYBRID */
     int64_t  rap_chunk;   /* Galerkin product R (A P): when A P has more products than this, it is formed in
                              windows of coarse rows of at most this many products (bounds the set-up's scratch
@@ -125,6 +137,10 @@ typedef struct {
                              minimum-norm correction; default 1 (off) */
     int32_t  srqm_iters;  /* BAMG: steps of simultaneous Rayleigh quotient minimisation refining the level-0
                              test space before it is used (0 to 100; default 0); see camg_setup_tv */
+    int32_t  afsai_steps; /* CAMG_SMOOTH_AFSAI: growth steps per row (default 10) */
+    int32_t  afsai_step;  /*   columns added per step (default 2); afsai_steps * afsai_step + 1 <= 32 */
+    double   afsai_eps;   /*   a row stops once psi_i falls by no more than this fraction in a step (>= 0;
+                               default 0.01) */
 } camg_params;
 
 #define CAMG_MAX_LEVELS 32
@@ -363,8 +379,8 @@ camg_status camg_level_sizes(camg_handle h, int32_t l, int32_t *n, int64_t *nnz_
  *   CAMG_X_DINV: a = double[n] (1 / a_ii);    CAMG_X_OMEGA: a = double[1];
  *   CAMG_X_STCNT: a = int32[n] (|S_i^T|);      CAMG_X_COARSE_INV: a = double[n*n] (last level:
  *   the dense inverse applied by the coarse solve, row-major);
- *   CAMG_X_G (FSAI smoother): the factor G as CSR like CAMG_X_A; its nonzero count is the number
- *   of entries of A_l on or below the diagonal.
+ *   CAMG_X_G (a level smoothed by FSAI or aFSAI): the factor G as CSR like CAMG_X_A; its nonzero
+ *   count is a[n] (export with b = c = NULL first to size them).
  */
 enum { CAMG_X_A = 0, CAMG_X_P = 1, CAMG_X_R = 2, CAMG_X_CF = 3, CAMG_X_STRONG = 4, CAMG_X_DINV = 5,
        CAMG_X_OMEGA = 6, CAMG_X_COARSE_INV = 7, CAMG_X_STCNT = 8, CAMG_X_G = 9 };

@@ -34,7 +34,8 @@ EXPORTED = [
     "camg_solve_batch_noalloc_dev",
 ]
 OPT_GRAPH = 1
-SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_FSAI, SMOOTH_FSAI_JACOBI, SMOOTH_AFSAI = 0, 1, 2, 3
+AFSAI_MAXM, AFSAI_MAXCAND = 32, 2048
 INTERP_DIRECT, INTERP_CLASSICAL, INTERP_EXTI, INTERP_HYBRID, INTERP_BAMG = 0, 1, 2, 3, 4
 OPT_AUTOTUNE = 2
 OPT_COMPACT_COLS = 3
@@ -46,7 +47,8 @@ class camg_params(C.Structure):
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("smoother", C.c_int32),
                 ("interp", C.c_int32), ("rap_chunk", C.c_int64), ("bamg_lmin", C.c_int32),
                 ("bamg_lmax", C.c_int32), ("bamg_eps", C.c_double), ("bamg_mu", C.c_double),
-                ("psmooth", C.c_int32), ("pfilter", C.c_double), ("srqm_iters", C.c_int32)]
+                ("psmooth", C.c_int32), ("pfilter", C.c_double), ("srqm_iters", C.c_int32),
+                ("afsai_steps", C.c_int32), ("afsai_step", C.c_int32), ("afsai_eps", C.c_double)]
 
 
 class camg_info_t(C.Structure):
@@ -593,10 +595,11 @@ class Solver:
         return self._csr(l, X_R)
 
     def G(self, l):
-        """FSAI factor of level l (the handle must use the FSAI smoother)."""
-        n, _, rp_a, ci_a, _ = self.A(l)
-        nnz = int(sum(np.count_nonzero(ci_a[rp_a[i]:rp_a[i + 1]] <= i) for i in range(n)))
+        """FSAI factor of level l (the level must smooth with FSAI or aFSAI)."""
+        n = self.sizes(l)[0]
         rp = np.zeros(n + 1, np.int32)
+        _check(camg_export_level(self.h, l, X_G, rp))
+        nnz = int(rp[n])
         ci = np.zeros(max(nnz, 1), np.int32)
         v = np.zeros(max(nnz, 1))
         _check(camg_export_level(self.h, l, X_G, rp, ci, v))

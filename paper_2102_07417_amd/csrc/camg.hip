@@ -181,8 +181,14 @@ void check_params(const camg_params &p) {
     if (p.max_iter < 0) fail(CAMG_E_ARG, "max_iter must be >= 0");
     if (p.precision != CAMG_FP64 && p.precision != CAMG_MIXED_FP32) fail(CAMG_E_ARG, "unknown precision");
     if (!std::isfinite(p.omega)) fail(CAMG_E_ARG, "omega must be finite");
-    if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI && p.smoother != CAMG_SMOOTH_FSAI_JACOBI)
+    if (p.smoother != CAMG_SMOOTH_JACOBI && p.smoother != CAMG_SMOOTH_FSAI && p.smoother != CAMG_SMOOTH_FSAI_JACOBI &&
+        p.smoother != CAMG_SMOOTH_AFSAI)
         fail(CAMG_E_ARG, "unknown smoother");
+    if (p.smoother == CAMG_SMOOTH_AFSAI &&
+        (p.afsai_steps < 0 || p.afsai_step < 1 || (int64_t)p.afsai_steps * p.afsai_step + 1 > CAMG_AFSAI_MAXM ||
+         !(p.afsai_eps >= 0.0)))
+        fail(CAMG_E_ARG, "aFSAI: need afsai_steps >= 0, afsai_step >= 1, afsai_steps * afsai_step + 1 <= 32 and "
+                         "afsai_eps >= 0");
     if (p.interp < CAMG_INTERP_DIRECT || p.interp > CAMG_INTERP_BAMG) fail(CAMG_E_ARG, "unknown interpolation");
     if (p.interp == CAMG_INTERP_BAMG &&
         (p.bamg_lmin < 1 || p.bamg_lmax < p.bamg_lmin || p.bamg_lmax > 2 || std::isnan(p.bamg_eps) || std::isnan(p.bamg_mu)))
@@ -338,13 +344,35 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         // entries on or below the diagonal (Jacobi otherwise)
         int32_t *gcnt = nullptr;
         int mmax = 0;
-        if (prm.smoother != CAMG_SMOOTH_JACOBI) {
+        if (prm.smoother == CAMG_SMOOTH_FSAI || prm.smoother == CAMG_SMOOTH_FSAI_JACOBI) {
             gcnt = lt.alloc<int32_t>(nl);
             mmax = fsai_counts(nl, L.A.rp, L.A.ci, gcnt, lt, s);
         }
         L.fsai = prm.smoother == CAMG_SMOOTH_FSAI || (prm.smoother == CAMG_SMOOTH_FSAI_JACOBI && mmax <= kFsaiMaxRow);
+        // adaptive FSAI: rows padded to mcap slots; Jacobi on a level where a
+        // candidate set outgrows the kernel's 2048 entries
+        const bool adaptive = prm.smoother == CAMG_SMOOTH_AFSAI;
+        const int mcap = adaptive ? prm.afsai_steps * prm.afsai_step + 1 : 0;
+        int32_t *apci = nullptr;
+        double *apv = nullptr;
+        if (adaptive) {
+            gcnt = lt.alloc<int32_t>(nl);
+            apci = lt.alloc<int32_t>((size_t)nl * mcap);
+            apv = lt.alloc<double>((size_t)nl * mcap);
+            const int maxrow = max_row_length(nl, L.A.rp, lt, s);
+            HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+            afsai_rows(L.A, maxrow, prm.afsai_steps, prm.afsai_step, prm.afsai_eps, gcnt, apci, apv, flags, s);
+            int32_t af[8];
+            HIPC(hipMemcpyAsync(af, flags, sizeof(af), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            if (af[4]) fail(CAMG_E_DEVICE, "aFSAI: candidate capacity of the launched tier exceeded");
+            if (af[7]) fail(CAMG_E_NOT_SPD, "aFSAI: a local matrix is not positive definite on level " +
+                                                std::to_string(l));
+            L.fsai = af[6] == 0;
+        }
         if (L.fsai) {
-            // FSAI factor on the lower pattern of A_l, its transpose, omega (eq. smo, eq. smoother)
+            // FSAI factor (static on the lower pattern of A_l, or the
+            // adaptive one), its transpose, omega (eq. smo, eq. smoother)
             int64_t *grp64 = lt.alloc<int64_t>((size_t)nl + 1);
             scan_i32_to_i64(gcnt, grp64, nl, lt, s);
             Csr &G = L.G;
@@ -354,14 +382,18 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             narrow_i64(grp64, G.rp, nl, s);
             G.ci = h.pool.alloc<int32_t>(padded(G.nnz));
             G.v = h.pool.alloc<double>(padded(G.nnz));
-            HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
-            fsai_rows(L.A, G, mmax, flags, s);
-            int32_t gf[8];
-            HIPC(hipMemcpyAsync(gf, flags, sizeof(gf), hipMemcpyDeviceToHost, s));
-            HIPC(hipStreamSynchronize(s));
-            if (gf[6]) fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
-            if (gf[7]) fail(CAMG_E_NOT_SPD, "FSAI: a local matrix is not positive definite on level " +
-                                                std::to_string(l));
+            if (adaptive) {
+                afsai_compact(G, mcap, apci, apv, s);
+            } else {
+                HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+                fsai_rows(L.A, G, mmax, flags, s);
+                int32_t gf[8];
+                HIPC(hipMemcpyAsync(gf, flags, sizeof(gf), hipMemcpyDeviceToHost, s));
+                HIPC(hipStreamSynchronize(s));
+                if (gf[6]) fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
+                if (gf[7]) fail(CAMG_E_NOT_SPD, "FSAI: a local matrix is not positive definite on level " +
+                                                    std::to_string(l));
+            }
             Csr &Gt = L.Gt;
             Gt.nr = Gt.nc = nl;
             Gt.nnz = G.nnz;
@@ -998,6 +1030,9 @@ void camg_params_default(camg_params *p) {
     p->psmooth = 0;
     p->pfilter = 1.0;
     p->srqm_iters = 0;
+    p->afsai_steps = 10;
+    p->afsai_step = 2;
+    p->afsai_eps = 0.01;
 }
 
 static camg_status setup_common(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nt,

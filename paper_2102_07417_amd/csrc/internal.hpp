@@ -261,6 +261,13 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 constexpr int kFsaiMaxRow = 192;
 int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool &tmp, hipStream_t s);
 void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
+// adaptive FSAI: rows padded to steps * step + 1 slots (pci / pv, counts in
+// cnt; flags[6]: a candidate set exceeded 2048 entries, the level takes
+// Jacobi; flags[7]: not SPD; flags[4]: internal capacity error), then
+// compacted into G (G.rp the scan of the counts)
+void afsai_rows(const Csr &A, int maxrow, int steps, int step, double eps, int32_t *cnt, int32_t *pci,
+                double *pv, int32_t *flags, hipStream_t s);
+void afsai_compact(const Csr &G, int mcap, const int32_t *pci, const double *pv, hipStream_t s);
 double cw_bound(const Csr &M, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
 void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
 void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,

@@ -714,8 +714,10 @@ __global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, dou
 // the lower triangle of A): row i solves A(P_i, P_i) g = e_last with a dense
 // Cholesky factorisation and substitutions, then G(i, P_i) = g / sqrt(g_last).
 // The per-entry arithmetic (and its order) is the oracle's: the right-looking
-// factorisation applies to each entry the same subtractions, in the same
-// order of k, as a column-oriented one.
+// factorisation and the column-by-column forward substitution apply to each
+// entry the same subtractions, in the same order of k, as the oracle's
+// row-oriented loops; the backward substitution runs row by row with
+// ascending k on one lane, as the oracle's does.
 
 // m_i = number of entries of row i on or below the diagonal; max m into *mmax
 __global__ void k_fsai_count(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, int32_t *mmax) {
@@ -741,11 +743,8 @@ __device__ __forceinline__ double csr_lookup(const int32_t *rp, const int32_t *c
 }
 
 // TPR threads (one wavefront, or a 256-thread workgroup for long rows) per
-// row; the lower triangle of the local matrix (m <= MAXM) packed row by row
-// in LDS: entry (r, c), c <= r, at r (r + 1) / 2 + c.  Both substitutions
-// go column by column (the oracle's order for every entry): unknown k is
-// divided by its pivot, then removed from the remaining equations in
-// parallel.
+// row; the lower triangle of the local matrix packed row by row in LDS:
+// entry (r, c), c <= r, at r (r + 1) / 2 + c.
 template <int TPR>
 __device__ __forceinline__ void fsai_sync() {
     if constexpr (TPR == 64) {
@@ -760,6 +759,58 @@ __device__ __forceinline__ int tri_row(int t) {
     while (r * (r + 1) / 2 > t) --r;
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
     return r;
+}
+
+__device__ __forceinline__ int tri_at(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// Right-looking Cholesky of the packed m x m matrix M in place; false (for
+// the whole row group) when a pivot is not positive.
+template <int TPR>
+__device__ bool fsai_factor(double *M, int m, int lane, int *bad) {
+    const int tri = m * (m + 1) / 2;
+    if (lane == 0) *bad = 0;
+    fsai_sync<TPR>();
+    for (int k = 0; k < m; ++k) {
+        if (lane == 0) {
+            const double d = M[tri_at(k, k)];
+            if (!(d > 0.0)) *bad = 1;
+            else M[tri_at(k, k)] = sqrt(d);
+        }
+        fsai_sync<TPR>();
+        if (*bad) return false;
+        const double lkk = M[tri_at(k, k)];
+        for (int r = k + 1 + lane; r < m; r += TPR) M[tri_at(r, k)] = M[tri_at(r, k)] / lkk;
+        fsai_sync<TPR>();
+        for (int t = tri_at(k + 1, 0) + lane; t < tri; t += TPR) {
+            const int r = tri_row(t), c = t - r * (r + 1) / 2;
+            if (c > k) M[t] = M[t] - M[tri_at(r, k)] * M[tri_at(c, k)];
+        }
+        fsai_sync<TPR>();
+    }
+    return true;
+}
+
+// y = (L L^T)^{-1} e_last for the factor in M: forward column by column
+// (e is overwritten), backward row by row with ascending k on lane 0.
+template <int TPR>
+__device__ void fsai_solve_last(const double *M, int m, double *e, double *y, int lane) {
+    for (int r = lane; r < m; r += TPR) e[r] = r == m - 1 ? 1.0 : 0.0;
+    fsai_sync<TPR>();
+    for (int k = 0; k < m; ++k) {
+        if (lane == 0) e[k] = e[k] / M[tri_at(k, k)];
+        fsai_sync<TPR>();
+        const double wk = e[k];
+        for (int r = k + 1 + lane; r < m; r += TPR) e[r] = e[r] - M[tri_at(r, k)] * wk;
+        fsai_sync<TPR>();
+    }
+    if (lane == 0) {
+        for (int r = m - 1; r >= 0; --r) {
+            double t = e[r];
+            for (int k = r + 1; k < m; ++k) t = t - M[tri_at(k, r)] * y[k];
+            y[r] = t / M[tri_at(r, r)];
+        }
+    }
+    fsai_sync<TPR>();
 }
 
 template <int MAXM, int WPB, int TPR>
@@ -781,12 +832,7 @@ __global__ void __launch_bounds__(WPB * TPR) k_fsai_rows(int n, const int32_t *_
         return;
     }
     double *M = Ms[w], *e = es[w], *z = zs[w];
-    auto at = [](int r, int c) { return r * (r + 1) / 2 + c; };
-    for (int r = lane; r < m; r += TPR) {
-        idx[w][r] = aci[arp[i] + r];
-        e[r] = r == m - 1 ? 1.0 : 0.0;
-    }
-    if (lane == 0) bad[w] = 0;
+    for (int r = lane; r < m; r += TPR) idx[w][r] = aci[arp[i] + r];
     fsai_sync<TPR>();
     const int tri = m * (m + 1) / 2;
     for (int t = lane; t < tri; t += TPR) {
@@ -794,44 +840,11 @@ __global__ void __launch_bounds__(WPB * TPR) k_fsai_rows(int n, const int32_t *_
         M[t] = csr_lookup(arp, aci, av, idx[w][r], idx[w][c]);
     }
     fsai_sync<TPR>();
-    // right-looking Cholesky
-    for (int k = 0; k < m; ++k) {
-        if (lane == 0) {
-            const double d = M[at(k, k)];
-            if (!(d > 0.0)) bad[w] = 1;
-            else M[at(k, k)] = sqrt(d);
-        }
-        fsai_sync<TPR>();
-        if (bad[w]) break;
-        const double lkk = M[at(k, k)];
-        for (int r = k + 1 + lane; r < m; r += TPR) M[at(r, k)] = M[at(r, k)] / lkk;
-        fsai_sync<TPR>();
-        for (int t = at(k + 1, 0) + lane; t < tri; t += TPR) {
-            const int r = tri_row(t), c = t - r * (r + 1) / 2;
-            if (c > k) M[t] = M[t] - M[at(r, k)] * M[at(c, k)];
-        }
-        fsai_sync<TPR>();
-    }
-    if (bad[w]) {
+    if (!fsai_factor<TPR>(M, m, lane, &bad[w])) {
         if (lane == 0) atomicOr(&flags[7], 1);
         return;
     }
-    // forward: L w = e_last (w overwrites e)
-    for (int k = 0; k < m; ++k) {
-        if (lane == 0) e[k] = e[k] / M[at(k, k)];
-        fsai_sync<TPR>();
-        const double wk = e[k];
-        for (int r = k + 1 + lane; r < m; r += TPR) e[r] = e[r] - M[at(r, k)] * wk;
-        fsai_sync<TPR>();
-    }
-    // backward: L^T g = w
-    for (int k = m - 1; k >= 0; --k) {
-        if (lane == 0) z[k] = e[k] / M[at(k, k)];
-        fsai_sync<TPR>();
-        const double gk = z[k];
-        for (int r = lane; r < k; r += TPR) e[r] = e[r] - M[at(k, r)] * gk;
-        fsai_sync<TPR>();
-    }
+    fsai_solve_last<TPR>(M, m, e, z, lane);
     if (!(z[m - 1] > 0.0)) {
         if (lane == 0) atomicOr(&flags[7], 1);
         return;
@@ -1043,6 +1056,226 @@ __device__ __forceinline__ int xi_scan_excl(int c, int *red, int lane, int *tota
         __syncthreads();
         *total = tot;
         return base + x - c;
+    }
+}
+
+// ------------------------------------------------------------------ adaptive FSAI
+// Row i of the adaptive factor minimises psi_i(g) = g^T A g (g_i = 1) over a
+// pattern P_i grown from {i} (Section 2, eq. smo; the pattern search of the
+// FSAI package the paper cites).  Each pass solves A(P, P) y = e_last
+// (psi = 1 / y_last); the row stops after `steps` growth steps or when psi
+// fell by no more than eps times its previous value; otherwise the `step`
+// candidates j < i (columns of the rows indexed by P, outside P) with the
+// largest |z_j|, z_j = sum over row j of a_jc y_c for c in P (the Kaporin
+// gradient up to a positive factor), join P, the smaller j first on ties.
+// G(i, P_i) = y / sqrt(y_last).  Every rounding is the oracle's: the local
+// solves as in k_fsai_rows, z_j summed along row j in CSR order.
+//
+// One wavefront per row.  The candidate set is kept sorted in LDS and
+// updated between passes (members that joined P leave it, the rows of the
+// new members are merged in), at most CAP entries: the largest tier
+// (kAfsaiMaxCand) raises flags[6] on overflow, and the level falls back to
+// Jacobi; a smaller tier is launched only where the bound
+// (steps * step + 1) * max row length rules overflow out (flags[4]
+// otherwise).  Rows are written padded (mcap slots each) with their counts.
+constexpr int kAfsaiMaxM = 32, kAfsaiMaxCand = 2048;
+
+// number of entries of the ascending S[0, len) below x
+__device__ __forceinline__ int afsai_below(const int *S, int len, int x) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int y = __shfl_xor(x, o, kWave);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+template <int MAXM, int CAP, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *__restrict__ arp,
+                                                         const int32_t *__restrict__ aci,
+                                                         const double *__restrict__ av, int steps, int step,
+                                                         double eps, int mcap, int32_t *__restrict__ cnt,
+                                                         int32_t *__restrict__ pci, double *__restrict__ pv,
+                                                         int32_t *flags) {
+    constexpr int Q = CAP / 64;
+    __shared__ double Ms[WPB][MAXM * (MAXM + 1) / 2];
+    __shared__ double es[WPB][MAXM], ys[WPB][MAXM];
+    __shared__ int Ps[WPB][MAXM], pends[WPB][MAXM];
+    __shared__ int cbuf[WPB][3][CAP];
+    __shared__ int bad[WPB];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * WPB + w;
+    if (i >= n) return;  // the whole wavefront
+    double *M = Ms[w], *e = es[w], *y = ys[w];
+    int *P = Ps[w], *pend = pends[w];
+    int *C = cbuf[w][0], *T = cbuf[w][1], *N = cbuf[w][2];
+    int m = 1, nC = 0, npend = 1;
+    if (lane == 0) {
+        P[0] = i;
+        pend[0] = i;
+    }
+    FSAI_SYNC();
+    double psi_prev = 0.0;
+    double zr[Q];
+    for (int k = 0;; ++k) {
+        // 1. local system A(P, P) y = e_last; row r of the local matrix from
+        //    row P[r] of A, matched against P[0..r]
+        const int tri = m * (m + 1) / 2;
+        for (int t = lane; t < tri; t += 64) M[t] = 0.0;
+        FSAI_SYNC();
+        if (lane < m) {
+            const int r = lane, row = P[r];
+            int c = 0;
+            for (int q = arp[row]; q < arp[row + 1] && c <= r; ++q) {
+                const int col = aci[q];
+                while (c <= r && P[c] < col) ++c;
+                if (c <= r && P[c] == col) M[tri_at(r, c)] = av[q];
+            }
+        }
+        FSAI_SYNC();
+        if (!fsai_factor<64>(M, m, lane, &bad[w])) {
+            if (lane == 0) atomicOr(&flags[7], 1);
+            return;
+        }
+        fsai_solve_last<64>(M, m, e, y, lane);
+        const double ylast = y[m - 1];
+        if (!(ylast > 0.0)) {
+            if (lane == 0) atomicOr(&flags[7], 1);
+            return;
+        }
+        // 2. stopping tests
+        const double psi = 1.0 / ylast;
+        if (k == steps) break;
+        if (k > 0 && psi_prev - psi <= eps * psi_prev) break;
+        psi_prev = psi;
+        // 3. candidate set: the new members leave it, their rows join it
+        if (k > 0) {
+            int nk = 0;
+            for (int b = 0; b < nC; b += 64) {
+                const int idx = b + lane;
+                const int c = idx < nC ? C[idx] : -1;
+                bool keep = idx < nC;
+                for (int a = 0; a < npend; ++a) keep = keep && pend[a] != c;
+                int tot;
+                const int off = xi_scan_excl<64>(keep ? 1 : 0, nullptr, lane, &tot);
+                if (keep) T[nk + off] = c;
+                nk += tot;
+            }
+            FSAI_SYNC();
+            int *sw = C; C = T; T = sw;
+            nC = nk;
+        }
+        for (int a = 0; a < npend; ++a) {
+            const int q = pend[a], rs = arp[q], re = arp[q + 1];
+            int nN = 0;
+            for (int b = rs; b < re; b += 64) {
+                if (aci[b] >= i) break;  // rows are sorted: nothing below i is left
+                const int ee = b + lane;
+                const int j = ee < re ? aci[ee] : INT_MAX;
+                const bool keep = j < i && xi_find(P, m, j) < 0 && xi_find(C, nC, j) < 0;
+                int tot;
+                const int off = xi_scan_excl<64>(keep ? 1 : 0, nullptr, lane, &tot);
+                if (nC + nN + tot > CAP) {
+                    if (lane == 0) atomicOr(&flags[CAP == kAfsaiMaxCand ? 6 : 4], 1);
+                    return;
+                }
+                if (keep) N[nN + off] = j;
+                nN += tot;
+            }
+            FSAI_SYNC();
+            if (nN > 0) {
+                for (int idx = lane; idx < nC; idx += 64) {
+                    const int c = C[idx];
+                    T[idx + afsai_below(N, nN, c)] = c;
+                }
+                for (int idx = lane; idx < nN; idx += 64) {
+                    const int x = N[idx];
+                    T[idx + afsai_below(C, nC, x)] = x;
+                }
+                FSAI_SYNC();
+                int *sw = C; C = T; T = sw;
+                nC += nN;
+            }
+        }
+        npend = 0;
+        // gradient components, one candidate per lane and slot
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int idx = lane + 64 * q;
+            double s = 0.0;
+            if (idx < nC) {
+                const int j = C[idx];
+                int pp = 0;
+                for (int t = arp[j]; t < arp[j + 1]; ++t) {
+                    const int col = aci[t];
+                    if (col > i) break;
+                    while (pp < m && P[pp] < col) ++pp;
+                    if (pp < m && P[pp] == col) s = s + av[t] * y[pp];
+                }
+            }
+            zr[q] = s;
+        }
+        // 4. the `step` largest |z_j| > 0 join P (smaller j on ties: C is ascending)
+        for (int a = 0; a < step; ++a) {
+            unsigned long long best = 0;
+            int bidx = INT_MAX;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(zr[q]));
+                if (bits > best) {
+                    best = bits;
+                    bidx = lane + 64 * q;
+                }
+            }
+            const unsigned long long top = xi_max<64>(best, nullptr, lane);
+            if (top == 0) break;
+            const int widx = wave_min_i(best == top ? bidx : INT_MAX);
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (lane + 64 * q == widx) zr[q] = 0.0;
+            if (lane == 0) {
+                const int j = C[widx];
+                int r = m;
+                while (r > 0 && P[r - 1] > j) {
+                    P[r] = P[r - 1];
+                    --r;
+                }
+                P[r] = j;
+                pend[npend] = j;
+            }
+            ++m;
+            ++npend;
+            FSAI_SYNC();
+        }
+        if (npend == 0) break;
+    }
+    const double sd = sqrt(y[m - 1]);
+    for (int r = lane; r < m; r += 64) {
+        pci[(int64_t)i * mcap + r] = P[r];
+        pv[(int64_t)i * mcap + r] = y[r] / sd;
+    }
+    if (lane == 0) cnt[i] = m;
+}
+
+// padded rows -> CSR (G.rp already the scan of the counts)
+__global__ void k_afsai_compact(int n, int mcap, const int32_t *pci, const double *pv, const int32_t *grp,
+                                int32_t *gci, double *gv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = grp[i], m = grp[i + 1] - o;
+    for (int r = 0; r < m; ++r) {
+        gci[o + r] = pci[(int64_t)i * mcap + r];
+        gv[o + r] = pv[(int64_t)i * mcap + r];
     }
 }
 
@@ -1798,15 +2031,6 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long y = __shfl_xor(x, o, kWave);
         x = y > x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int wave_min_i(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int y = __shfl_xor(x, o, kWave);
-        x = y < x ? y : x;
     }
     return x;
 }
@@ -2806,6 +3030,28 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     else if (mmax <= 128) k_fsai_rows<128, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else if (mmax <= kFsaiMaxRow) k_fsai_rows<kFsaiMaxRow, 1, 256><<<n, 256, 0, s>>>(n, A.rp, A.ci, A.v, G.rp, G.ci, G.v, flags);
     else fail(CAMG_E_ARG, "FSAI: a row has more than 192 entries on or below the diagonal");
+    HIPC(hipGetLastError());
+}
+
+void afsai_rows(const Csr &A, int maxrow, int steps, int step, double eps, int32_t *cnt, int32_t *pci,
+                double *pv, int32_t *flags, hipStream_t s) {
+    const int n = A.nr;
+    const int mcap = steps * step + 1;
+    if (steps < 0 || step < 1 || mcap > kAfsaiMaxM) fail(CAMG_E_ARG, "aFSAI: steps * step + 1 must be at most 32");
+    const int64_t bound = (int64_t)mcap * std::max(maxrow, 1);  // candidates of a row never exceed this
+#define AFSAI_LAUNCH(MM, CAP, WPB)                                                                            \
+    k_afsai_rows<MM, CAP, WPB><<<(n + (WPB) - 1) / (WPB), (WPB) * 64, 0, s>>>(n, A.rp, A.ci, A.v, steps, step, \
+                                                                               eps, mcap, cnt, pci, pv, flags)
+    if (mcap <= 16 && bound <= 256) AFSAI_LAUNCH(16, 256, 4);
+    else if (bound <= 256) AFSAI_LAUNCH(kAfsaiMaxM, 256, 4);
+    else if (bound <= 1024) AFSAI_LAUNCH(kAfsaiMaxM, 1024, 2);
+    else AFSAI_LAUNCH(kAfsaiMaxM, kAfsaiMaxCand, 1);
+#undef AFSAI_LAUNCH
+    HIPC(hipGetLastError());
+}
+
+void afsai_compact(const Csr &G, int mcap, const int32_t *pci, const double *pv, hipStream_t s) {
+    k_afsai_compact<<<nblocks(G.nr), kBlock, 0, s>>>(G.nr, mcap, pci, pv, G.rp, G.ci, G.v);
     HIPC(hipGetLastError());
 }
 

@@ -46,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_pure_host_calls(lib):
-    assert lib.camg_abi_version() == 7
+    assert lib.camg_abi_version() == 8
     for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.camg_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
@@ -81,7 +81,7 @@ def test_noalloc_batch_limit_without_device(lib):
         str(camg.NOALLOC_MAX_SYSTEMS)
 
 
-@pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 3), ("theta", 1.5),
+@pytest.mark.parametrize("field,value", [("interp", 4), ("interp", -1), ("smoother", 4), ("theta", 1.5),
                                          ("precision", 3), ("rap_chunk", -1), ("interp", 5),
                                          ("psmooth", 2), ("pfilter", 0.0), ("srqm_iters", -1),
                                          ("srqm_iters", 101), ("srqm_iters", 1)])
@@ -112,6 +112,8 @@ int main(void) {
   printf("bamg %zu %zu %zu %zu %zu %zu\n", offsetof(camg_params, bamg_lmin), offsetof(camg_params, bamg_eps),
          offsetof(camg_params, bamg_mu), offsetof(camg_params, psmooth), offsetof(camg_params, pfilter),
          offsetof(camg_params, srqm_iters));
+  printf("afsai %zu %zu %zu\n", offsetof(camg_params, afsai_steps), offsetof(camg_params, afsai_step),
+         offsetof(camg_params, afsai_eps));
   printf("info %zu %zu %zu %zu\n", sizeof(camg_info_t), offsetof(camg_info_t, nnz_p),
          offsetof(camg_info_t, setup_phase_ms), offsetof(camg_info_t, compact_cols));
   printf("completion %zu %zu %zu\n", sizeof(camg_completion), offsetof(camg_completion, true_relres),
@@ -128,6 +130,7 @@ int main(void) {
                              P.interp.offset, P.rap_chunk.offset]
     assert out["bamg"] == [P.bamg_lmin.offset, P.bamg_eps.offset, P.bamg_mu.offset, P.psmooth.offset,
                            P.pfilter.offset, P.srqm_iters.offset]
+    assert out["afsai"] == [P.afsai_steps.offset, P.afsai_step.offset, P.afsai_eps.offset]
     I = camg.camg_info_t
     assert out["info"] == [C.sizeof(I), I.nnz_p.offset, I.setup_phase_ms.offset, I.compact_cols.offset]
     Q = camg.camg_completion
@@ -150,6 +153,30 @@ def test_bamg_setup_rejected_without_device(lib):
         assert lib.camg_setup(1, vp(rp), vp(ci), vp(v), C.byref(p), C.byref(h)) == camg.E_ARG
         V = np.ones((1, 9))
         assert lib.camg_setup_tv(1, vp(rp), vp(ci), vp(v), 9, vp(V), C.byref(p), C.byref(h)) == camg.E_ARG
+
+
+def test_afsai_parameters_rejected_without_device(lib):
+    """Adaptive FSAI parameters outside their range are refused before any
+    device work: afsai_steps * afsai_step + 1 above 32, a negative step
+    count, no entries per step, a negative or NaN tolerance."""
+    rp = np.array([0, 1], np.int32)
+    ci = np.array([0], np.int32)
+    v = np.array([2.0])
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    for kw in ({"afsai_steps": 16, "afsai_step": 2}, {"afsai_steps": -1}, {"afsai_step": 0},
+               {"afsai_eps": -0.5}, {"afsai_eps": float("nan")}):
+        p = camg.camg_params()
+        lib.camg_params_default(C.byref(p))
+        assert (p.afsai_steps, p.afsai_step, p.afsai_eps) == (10, 2, 0.01)
+        p.smoother = camg.SMOOTH_AFSAI
+        for k, val in kw.items():
+            setattr(p, k, val)
+        h = C.c_void_p()
+        assert lib.camg_setup(1, vp(rp), vp(ci), vp(v), C.byref(p), C.byref(h)) == camg.E_ARG
+        assert b"aFSAI" in lib.camg_last_error()
+    hdr = open(HEADER).read()
+    assert int(re.search(r"#define CAMG_AFSAI_MAXM (\d+)", hdr).group(1)) == camg.AFSAI_MAXM
+    assert int(re.search(r"#define CAMG_AFSAI_MAXCAND (\d+)", hdr).group(1)) == camg.AFSAI_MAXCAND
 
 
 def test_device_wrappers_refuse_bad_buffers(lib):

@@ -1,0 +1,141 @@
+"""Adaptive FSAI smoother on the GPU against the oracle, through the C-ABI.
+
+The kernel repeats the oracle's roundings step for step (the local
+Cholesky factorisation and substitutions in the oracle's order, the
+gradient components summed along each row of A in CSR order), so the
+greedy choices coincide and every level's factor matches bit for bit.
+omega is compared to 1e-12 (its Collatz-Wielandt sums run in another
+order), V-cycles to 1e-10 and PCG solutions to 1e-9 with iteration counts
+within one.  The cases cover the four launch tiers of the kernel (pattern
+capacity 16 or 32, candidate capacity 256, 1024 or 2048), ties (constant
+coefficients), the stopping rule, and the level fallback to Jacobi."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2102_07417_amd import problems as PB
+from tests.helpers import from_dense
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def camg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_07417_amd import camg as m
+    m.load()
+    return m
+
+
+CASES = {
+    # name: (problem, afsai_steps, afsai_step, afsai_eps)
+    "ln3_16_s6x2": (lambda: PB.lognormal3d(16, 2.0), 6, 2, 0.01),      # pattern 13, bound 91: tier 16/256
+    "ln3_16_default": (lambda: PB.lognormal3d(16, 2.0), 10, 2, 0.01),  # pattern 21, bound 147: tier 32/256
+    "el_4_s2x2": (lambda: PB.elasticity3d(4), 2, 2, 0.0),              # bound 405: tier 32/1024
+    "el_4_default": (lambda: PB.elasticity3d(4), 10, 2, 0.01),         # bound 1701: tier 32/2048
+    "p2_48_ties": (lambda: PB.poisson2d(48), 3, 1, 0.0),               # exact ties everywhere
+    "an3_14_s8x3": (lambda: PB.aniso3d(14, 1e-3), 8, 3, 0.005),
+    "ln2_60_s15x2": (lambda: PB.lognormal2d(60, 2.0), 15, 2, 0.0),     # the largest pattern, 31
+}
+
+
+def _G_or_none(h, l):
+    try:
+        return h.G(l)
+    except Exception:
+        return None
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_afsai_hierarchy_bit_exact_vcycle_and_solve(camg, name):
+    gen, steps, step, eps = CASES[name]
+    print(f"[gpu] afsai {name}", flush=True)
+    A = gen()
+    kw = dict(max_coarse=40, afsai_steps=steps, afsai_step=step, afsai_eps=eps)
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), smoother=camg.SMOOTH_AFSAI,
+                                **kw)
+    o = O.Hierarchy(A, smoother=O.SMOOTH_AFSAI, **kw)
+    assert g.nlev == o.nlev
+    for l in range(o.nlev - 1):
+        gg, og = _G_or_none(g, l), _G_or_none(o, l)
+        assert (gg is None) == (og is None), f"level {l}: smoother choice"
+        if og is not None:
+            for a, b in zip(gg[2:], og[2:]):
+                np.testing.assert_array_equal(a, b, err_msg=f"G_{l}")
+        assert abs(g.omega(l) - o.omega(l)) <= 1e-12 * o.omega(l), f"omega_{l}"
+    y = np.random.default_rng(5).standard_normal(A.n)
+    dz = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    g.vcycle_dev(_dev(y), dz)
+    torch.cuda.synchronize()
+    zo = o.vcycle(y)
+    assert np.linalg.norm(dz.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+    b = PB.rhs(A.n)
+    r, ro = g.solve(b), o.solve(b, 1e-8)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+
+
+def test_afsai_mixed_precision(camg):
+    A = PB.elasticity3d(5)
+    b = PB.rhs(A.n)
+    g = camg.Solver(A, smoother=camg.SMOOTH_AFSAI, precision=camg.MIXED_FP32, max_coarse=40)
+    ro = O.Hierarchy(A, smoother=O.SMOOTH_AFSAI, max_coarse=40).solve(b, 1e-8)
+    r = g.solve(b)
+    assert r.status == camg.OK and r.true_relres < 1e-8 and r.iters <= ro.iters + 5
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) < 1e-6
+    g.close()
+
+
+def test_afsai_level_falls_back_to_jacobi(camg):
+    """Diagonal 4 with the last point coupled to all others: its candidate
+    set (every other point) exceeds 2048, so level 0 smooths with Jacobi on
+    both sides; the next levels are small and use the adaptive factor."""
+    n = O.AFSAI_MAXCAND + 52
+    M = 4.0 * np.eye(n)
+    M[-1, :-1] = M[:-1, -1] = -1.0
+    M[-1, -1] = 2.0 * n
+    _, _, rp, ci, v = from_dense(M)
+    kw = dict(max_coarse=50, afsai_steps=1, afsai_step=1, afsai_eps=0.0)
+    g = camg.Solver.from_device(n, _dev(rp), _dev(ci), _dev(v), smoother=camg.SMOOTH_AFSAI, **kw)
+    o = O.Hierarchy((n, n, rp, ci, v), smoother=O.SMOOTH_AFSAI, **kw)
+    assert _G_or_none(g, 0) is None and _G_or_none(o, 0) is None
+    assert g.omega(0) == o.omega(0)
+    b = PB.rhs(n)
+    r, ro = g.solve(b), o.solve(b, 1e-8)
+    assert r.status == camg.OK and abs(r.iters - ro.iters) <= 1
+    assert np.linalg.norm(r.x - ro.x) / np.linalg.norm(ro.x) <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("kw", [dict(afsai_steps=16, afsai_step=2), dict(afsai_step=0), dict(afsai_eps=-1.0)])
+def test_afsai_bad_parameters(camg, kw):
+    A = PB.poisson2d(30)
+    with pytest.raises(camg.CamgError):
+        camg.Solver(A, smoother=camg.SMOOTH_AFSAI, **kw)
+
+
+@pytest.mark.parametrize("workload,rows", [("lognormal3d_128", 3000), ("elasticity_64", 1500)])
+def test_afsai_fullsize_sampled_rows(camg, workload, rows):
+    """The full-size systems with the default parameters: level-0 rows of
+    the GPU factor, sampled (first, last and seeded random rows), equal the
+    oracle's rows computed one by one, bit for bit."""
+    print(f"[gpu] afsai full size {workload}", flush=True)
+    A = PB.workload(workload)
+    g = camg.Solver.from_device(A.n, _dev(A.row_ptr), _dev(A.col_idx), _dev(A.val), smoother=camg.SMOOTH_AFSAI)
+    n, _, rp, ci, v = g.G(0)
+    sel = np.unique(np.concatenate([[0, 1, A.n - 1], np.random.default_rng(9).integers(0, A.n, rows)]))
+    want = O.afsai_rows(A, sel)
+    for i, (cols, vals) in zip(sel, want):
+        np.testing.assert_array_equal(ci[rp[i]:rp[i + 1]], cols, err_msg=f"row {i}")
+        np.testing.assert_array_equal(v[rp[i]:rp[i + 1]], vals, err_msg=f"row {i}")
+    # density nnz(G) / nnz(A) as the paper states it for its matrices
+    print(f"[gpu] afsai {workload} density {rp[-1] / A.row_ptr[-1]:.3f}", flush=True)
+    g.close()
