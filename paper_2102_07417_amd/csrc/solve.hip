@@ -85,93 +85,120 @@ typedef unsigned short v4us __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Four consecutive values starting at a 16-byte aligned index.
-__device__ __forceinline__ void load4(const double *p, double (&o)[4]) {
-    const v2d a = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
-    const v2d b = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p + 2));
-    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
-}
-__device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
-    const v4f a = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
-    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+// Positions, from the start of a step of 4*kBlock nonzeros, of the four
+// nonzeros a thread takes.  FP32: four consecutive ones (one 16-byte load per
+// thread, so a wavefront's load covers one contiguous KiB).  FP64: two pairs
+// 2*kBlock apart, again one contiguous KiB per wavefront and load (four
+// consecutive doubles per thread would take two loads that each leave half
+// of every cache line they touch to the other; such loads measured 13 %
+// slower on 7-point rows).
+template <class T>
+__device__ __forceinline__ int quad_pos(int u) {
+    if constexpr (sizeof(T) == 4) return 4 * (int)threadIdx.x + u;
+    else return 2 * (int)threadIdx.x + (u & 1) + (u >> 1) * (2 * kBlock);
 }
 
-// Four column indices of the nonzeros idx .. idx+3 (idx a multiple of 4):
-// MODE 0 the int32 columns; MODE 1 the tile's smallest column plus the
-// 16-bit word; MODE 2 the start of the window named by the word's top bits
-// (from LDS, wins) plus its low bits.
+// The column words (as stored) and values of this thread's four nonzeros in
+// the step that starts s entries after a0 (a0 a multiple of 4).  A group that
+// starts at or past `span` reads the tile's first entries instead (inside the
+// arrays, no branch); the caller sends its products to the junk slot.  The
+// arrays carry 8 elements of padding, so a group that starts inside the span
+// stays inside the allocation.
+template <int MODE, class T>
+struct Quad {
+    using W = std::conditional_t<MODE == 0, int, unsigned short>;
+    W c[4];
+    T v[4];
+};
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef unsigned short v2us __attribute__((ext_vector_type(2)));
+template <int MODE, class T>
+__device__ __forceinline__ void fetch_quad(const MatArg<T> &M, int a0, int s, int span, Quad<MODE, T> &Q) {
+    if constexpr (sizeof(T) == 4) {
+        const int p = s + 4 * (int)threadIdx.x;
+        const int idx = a0 + (p < span ? p : 0);
+        const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(M.v + idx));
+        Q.v[0] = v.x; Q.v[1] = v.y; Q.v[2] = v.z; Q.v[3] = v.w;
+        if constexpr (MODE == 0) {
+            const v4i c = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
+            Q.c[0] = c.x; Q.c[1] = c.y; Q.c[2] = c.z; Q.c[3] = c.w;
+        } else {
+            const v4us c = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
+            Q.c[0] = c.x; Q.c[1] = c.y; Q.c[2] = c.z; Q.c[3] = c.w;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = s + 2 * (int)threadIdx.x + h * (2 * kBlock);
+            const int idx = a0 + (p < span ? p : 0);
+            const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(M.v + idx));
+            Q.v[2 * h] = v.x; Q.v[2 * h + 1] = v.y;
+            if constexpr (MODE == 0) {
+                const v2i c = __builtin_nontemporal_load(reinterpret_cast<const v2i *>(M.ci + idx));
+                Q.c[2 * h] = c.x; Q.c[2 * h + 1] = c.y;
+            } else {
+                const v2us c = __builtin_nontemporal_load(reinterpret_cast<const v2us *>(M.off + idx));
+                Q.c[2 * h] = c.x; Q.c[2 * h + 1] = c.y;
+            }
+        }
+    }
+}
+
+// Column of a stored word: MODE 0 the int32 column; MODE 1 the tile's
+// smallest column plus the 16-bit word; MODE 2 the start of the window named
+// by the word's top bits (from LDS, wins) plus its low bits.
 __device__ __forceinline__ int decode_col(const int *wins, unsigned o) {
     return wins[o >> kWinBits] + (int)(o & ((1u << kWinBits) - 1));
 }
-template <int MODE, class T>
-__device__ __forceinline__ v4i cols4(const MatArg<T> &M, int idx, const int *wins, int base) {
-    if constexpr (MODE == 0) {
-        (void)wins;
-        (void)base;
-        return __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
-    } else {
-        const v4us o = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
-        if constexpr (MODE == 1) {
-            (void)wins;
-            return v4i{base + (int)o.x, base + (int)o.y, base + (int)o.z, base + (int)o.w};
-        } else {
-            (void)base;
-            return v4i{decode_col(wins, o.x), decode_col(wins, o.y), decode_col(wins, o.z), decode_col(wins, o.w)};
+template <int MODE, class W>
+__device__ __forceinline__ int word_col(W w, const int *wins, int base) {
+    if constexpr (MODE == 0) return (int)w;
+    else if constexpr (MODE == 1) return base + (int)w;
+    else return decode_col(wins, w);
+}
+
+// prod[q] = a * g(col) for the four nonzeros of Q, q = position in the tile
+// (entries outside [0, m) gather column 0 and store into prod[junk]).
+template <int MODE, class T, class G>
+__device__ __forceinline__ void park_quads(const G &g, T *prod, const Quad<MODE, T> *Q, int nq, int qs, int m,
+                                           int junk, const int *wins, int base) {
+    T gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (u < 4 * nq) {
+            const int q = qs + (u >> 2) * (4 * kBlock) + quad_pos<T>(u & 3);
+            gv[u] = g((q >= 0 && q < m) ? word_col<MODE>(Q[u >> 2].c[u & 3], wins, base) : 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (u < 4 * nq) {
+            const int q = qs + (u >> 2) * (4 * kBlock) + quad_pos<T>(u & 3);
+            prod[(q >= 0 && q < m) ? q : junk] = Q[u >> 2].v[u & 3] * gv[u];
         }
     }
 }
 
-// Phase 1 of a tile: prod[e - e0] = a_e * g(col_e) for e in [e0, e0 + m).
-// Column indices (int32, or 16-bit differences to the tile's base column)
-// and values are streamed as aligned vectors of four from e0 rounded down to
-// a multiple of 4 (the arrays carry 8 elements of padding, so the last
-// vector stays inside the allocation).  Entries outside the tile gather
-// column 0 instead and store into the spare LDS slot prod[junk] (no branch
-// anywhere, so all the loads stay in flight).
+// Phase 1 of a tile: prod[e - e0] = a_e * g(col_e) for e in [e0, e0 + m),
+// streamed from e0 rounded down to a multiple of 4, two steps at a time
+// (eight gathers in flight per thread), with no branch around the loads.
 template <int MODE, class T, class G>
 __device__ __forceinline__ void stream_tile(const MatArg<T> &M, const G &g, T *prod, int e0, int m,
                                             const int *wins, int base) {
-    const int junk = M.junk;
     const int a0 = e0 & ~3;
     const int span = e0 + m - a0;
     constexpr int STEP = 4 * kBlock;
-    int k = 4 * threadIdx.x;
-    for (; k + STEP < span; k += 2 * STEP) {
-        const v4i c0 = cols4<MODE>(M, a0 + k, wins, base);
-        const v4i c1 = cols4<MODE>(M, a0 + k + STEP, wins, base);
-        T v0[4], v1[4];
-        load4(M.v + a0 + k, v0);
-        load4(M.v + a0 + k + STEP, v1);
-        const int cc[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        const int qb = a0 + k - e0;
-        T gv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = qb + (u & 3) + (u >> 2) * STEP;
-            const bool in = q >= 0 && q < m;
-            gv[u] = g(in ? cc[u] : 0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = qb + (u & 3) + (u >> 2) * STEP;
-            const T a = u < 4 ? v0[u & 3] : v1[u & 3];
-            prod[(q >= 0 && q < m) ? q : junk] = a * gv[u];
-        }
+    int s = 0;
+    for (; s + STEP < span; s += 2 * STEP) {
+        Quad<MODE, T> Q[2];
+        fetch_quad<MODE>(M, a0, s, span, Q[0]);
+        fetch_quad<MODE>(M, a0, s + STEP, span, Q[1]);
+        park_quads<MODE>(g, prod, Q, 2, a0 + s - e0, m, M.junk, wins, base);
     }
-    for (; k < span; k += STEP) {
-        const v4i c0 = cols4<MODE>(M, a0 + k, wins, base);
-        T v0[4];
-        load4(M.v + a0 + k, v0);
-        const int cc[4] = {c0.x, c0.y, c0.z, c0.w};
-        const int qb = a0 + k - e0;
-        T gv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool in = qb + u >= 0 && qb + u < m;
-            gv[u] = g(in ? cc[u] : 0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) prod[(qb + u >= 0 && qb + u < m) ? qb + u : junk] = v0[u] * gv[u];
+    if (s < span) {
+        Quad<MODE, T> Q[1];
+        fetch_quad<MODE>(M, a0, s, span, Q[0]);
+        park_quads<MODE>(g, prod, Q, 1, a0 + s - e0, m, M.junk, wins, base);
     }
 }
 
@@ -204,76 +231,31 @@ __device__ __forceinline__ void stream_tile_scalar(const MatArg<T> &M, const G &
 }
 
 // Phase 1 split in two for a pipelined tile loop: tile_fetch issues the
-// loads of the first two 4*kBlock-entry steps of a tile into registers (the
-// column words as stored, so nothing waits on them), tile_consume gathers,
-// multiplies and parks the products, then streams whatever lies beyond the
-// two steps as stream_tile does.  Entries past the tile read column 0 (or
-// the tile base) and land in prod[junk], as in stream_tile.
+// loads of the first two steps of a tile into registers (the column words as
+// stored, so nothing waits on them), tile_consume gathers, multiplies and
+// parks the products, then streams whatever lies beyond the two steps as
+// stream_tile does.
 template <int MODE, class T>
 struct TileRegs {
-    using C = std::conditional_t<MODE == 0, v4i, v4us>;
-    C c[2];
-    T v[2][4];
+    Quad<MODE, T> q[2];
 };
 template <int MODE, class T>
 __device__ __forceinline__ void tile_fetch(const MatArg<T> &M, TileRegs<MODE, T> &R, int e0, int m) {
     const int a0 = e0 & ~3, span = e0 + m - a0;
-    constexpr int STEP = 4 * kBlock;
-    const int k = 4 * threadIdx.x;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (k + h * STEP < span) {
-            const int idx = a0 + k + h * STEP;
-            if constexpr (MODE == 0) R.c[h] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(M.ci + idx));
-            else R.c[h] = __builtin_nontemporal_load(reinterpret_cast<const v4us *>(M.off + idx));
-            load4(M.v + idx, R.v[h]);
-        } else {
-            R.c[h] = typename TileRegs<MODE, T>::C{0, 0, 0, 0};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) R.v[h][u] = 0;
-        }
-    }
+    fetch_quad<MODE>(M, a0, 0, span, R.q[0]);
+    fetch_quad<MODE>(M, a0, 4 * kBlock, span, R.q[1]);
 }
 template <int MODE, class T, class G>
 __device__ __forceinline__ void tile_consume(const MatArg<T> &M, const G &g, T *prod, const TileRegs<MODE, T> &R,
                                              int e0, int m, int base) {
-    const int junk = M.junk;
     const int a0 = e0 & ~3;
     const int span = e0 + m - a0;
     constexpr int STEP = 4 * kBlock;
-    const int k = 4 * threadIdx.x;
-    int cc[8];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if constexpr (MODE == 0) cc[4 * h + u] = R.c[h][u];
-            else cc[4 * h + u] = base + (int)R.c[h][u];
-        }
-    }
-    const int qb = a0 + k - e0;
-    T gv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int q = qb + (u & 3) + (u >> 2) * STEP;
-        gv[u] = g((q >= 0 && q < m) ? cc[u] : 0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int q = qb + (u & 3) + (u >> 2) * STEP;
-        prod[(q >= 0 && q < m) ? q : junk] = R.v[u >> 2][u & 3] * gv[u];
-    }
-    for (int kk = k + 2 * STEP; kk < span; kk += STEP) {
-        const v4i c0 = cols4<MODE>(M, a0 + kk, nullptr, base);
-        T v0[4];
-        load4(M.v + a0 + kk, v0);
-        const int c4[4] = {c0.x, c0.y, c0.z, c0.w};
-        const int q0 = a0 + kk - e0;
-        T g4[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) g4[u] = g((q0 + u >= 0 && q0 + u < m) ? c4[u] : 0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) prod[(q0 + u >= 0 && q0 + u < m) ? q0 + u : junk] = v0[u] * g4[u];
+    park_quads<MODE>(g, prod, R.q, 2, a0 - e0, m, M.junk, nullptr, base);
+    for (int s = 2 * STEP; s < span; s += STEP) {
+        Quad<MODE, T> Q[1];
+        fetch_quad<MODE>(M, a0, s, span, Q[0]);
+        park_quads<MODE>(g, prod, Q, 1, a0 + s - e0, m, M.junk, nullptr, base);
     }
 }
 
