@@ -317,6 +317,17 @@ def main():
             rs = [one_step(prec, smoother=camg.SMOOTH_FSAI) for _ in range(max(1, min(args.steps, 3)))]
             fsai[key] = {"solve_ms": med(rs, "solve_ms"), "setup_ms": med(rs, "setup_ms"),
                          "iters": rs[-1]["iters"], "true_relres": rs[-1]["true_relres"]}
+        # the adaptive factor (the paper's smoother, eq. smo), alone and with
+        # extended+i interpolation (the paper's default set-up)
+        for interp, akey in ((camg.INTERP_DIRECT, "adaptive"), (camg.INTERP_EXTI, "adaptive_extended_i")):
+            fsai[akey] = {}
+            for prec, key in ((camg.FP64, "fp64"), (camg.MIXED_FP32, "mixed")):
+                one_step(prec, smoother=camg.SMOOTH_AFSAI, interp=interp)
+                rs = [one_step(prec, smoother=camg.SMOOTH_AFSAI, interp=interp) for _ in range(max(1, min(args.steps, 2)))]
+                fsai[akey][key] = {"solve_ms": med(rs, "solve_ms"), "setup_ms": med(rs, "setup_ms"),
+                                   "iters": rs[-1]["iters"], "true_relres": rs[-1]["true_relres"],
+                                   "smoother_setup_ms": round(rs[-1]["info"].setup_phase_ms[1], 2)}
+        fsai["adaptive"]["params"] = {"afsai_steps": 10, "afsai_step": 2, "afsai_eps": 0.01}
 
     # the paper's interpolations on the same system (Jacobi, FP64), as in its
     # comparison of prolongations: complexities, iterations, set-up and solve
@@ -512,6 +523,17 @@ def c3_run(A, no_oracle_check=False, runs=2):
             d["sampled_rel_err_vs_oracle"] = float(np.linalg.norm(xs - gold["x"]) / np.linalg.norm(gold["x"]))
         out[key] = d
     out["mixed"]["speedup_vs_fp64"] = round(out["fp64"]["solve_ms"] / out["mixed"]["solve_ms"], 4)
+    # the paper's smoother for its mechanical problems: adaptive FSAI (one run per precision)
+    out["adaptive_fsai"] = {}
+    for key, prec in (("fp64", camg.FP64), ("mixed", camg.MIXED_FP32)):
+        r = solve_once(camg, A, dA, db, dx, stream, prec, smoother=camg.SMOOTH_AFSAI)
+        d = {"setup_ms": round(r["setup_ms"], 2), "solve_ms": round(r["solve_ms"], 2), "iters": r["iters"],
+             "status": r["status"], "true_relres": r["true_relres"],
+             "smoother_setup_ms": round(r["info"].setup_phase_ms[1], 2)}
+        if gold is not None:
+            xs = dx.cpu().numpy()[gold["idx"]]
+            d["sampled_rel_err_vs_oracle_jacobi_solution"] = float(np.linalg.norm(xs - gold["x"]) / np.linalg.norm(gold["x"]))
+        out["adaptive_fsai"][key] = d
     return out
 
 
@@ -791,7 +813,8 @@ def bamg_run(ne):
     smoothed and filtered to rho = 0.7; mixed with 3 SRQM steps on the
     modes; direct and BAMG with the FSAI_JACOBI smoother: FSAI on the
     levels whose rows have at most 192 entries on or below the diagonal,
-    Jacobi on BAMG's denser coarse levels), then from six random vectors
+    Jacobi on BAMG's denser coarse levels; direct and BAMG with the
+    adaptive FSAI smoother), then from six random vectors
     with and without 10 SRQM steps.  Each configuration runs once untimed,
     then once timed."""
     import numpy as np
@@ -839,7 +862,10 @@ def bamg_run(ne):
                                 ("bamg_srqm3_mixed", camg.MIXED_FP32, True, camg.SMOOTH_JACOBI),
                                 ("direct_fsai_jacobi_mixed", camg.MIXED_FP32, False, camg.SMOOTH_FSAI_JACOBI),
                                 ("bamg_fsai_jacobi_fp64", camg.FP64, True, camg.SMOOTH_FSAI_JACOBI),
-                                ("bamg_fsai_jacobi_mixed", camg.MIXED_FP32, True, camg.SMOOTH_FSAI_JACOBI)):
+                                ("bamg_fsai_jacobi_mixed", camg.MIXED_FP32, True, camg.SMOOTH_FSAI_JACOBI),
+                                ("direct_afsai_mixed", camg.MIXED_FP32, False, camg.SMOOTH_AFSAI),
+                                ("bamg_afsai_fp64", camg.FP64, True, camg.SMOOTH_AFSAI),
+                                ("bamg_afsai_mixed", camg.MIXED_FP32, True, camg.SMOOTH_AFSAI)):
         extra = {"psmooth": 1, "pfilter": 0.7} if "psmooth" in key else {}
         if "srqm" in key:
             extra["srqm_iters"] = 3

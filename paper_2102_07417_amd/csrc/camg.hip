@@ -613,10 +613,10 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     h.p[0] = h.pool.alloc<double>(n0);
     h.p[1] = h.pool.alloc<double>(n0);
     h.q = h.pool.alloc<double>(n0);
-    h.pr2 = h.pool.alloc<double>(kMaxGrid);
-    h.prz = h.pool.alloc<double>(kMaxGrid);
-    h.ppq = h.pool.alloc<double>(kMaxGrid);
-    h.ptmp = h.pool.alloc<double>(kMaxGrid);
+    h.pr2 = h.pool.alloc<double>(kMaxPartials);
+    h.prz = h.pool.alloc<double>(kMaxPartials);
+    h.ppq = h.pool.alloc<double>(kMaxPartials);
+    h.ptmp = h.pool.alloc<double>(kMaxPartials);
     h.st = h.pool.alloc<PcgState>(1);
     h.sc = h.pool.alloc<double>(4);
     HIPC(hipHostMalloc((void **)&h.hflag, 4 * sizeof(int32_t), hipHostMallocMapped));

@@ -192,6 +192,7 @@ struct Hier {
 constexpr int kBlock = 256;          // threads per block for row kernels
 constexpr int kMaxSlots = 64;        // columns of a multi-RHS engine
 constexpr int kMaxGrid = 2048;       // cap on blocks of the reduction kernels
+constexpr int kMaxPartials = 8192;   // room for the per-block partials of any producing kernel
 
 // ---------------------------------------------------------------- scan (setup.hip)
 // out[0..n] = exclusive prefix sums of in[0..n-1]; out[n] = total.
