@@ -113,7 +113,8 @@ typedef struct {
     int32_t  nu_pre;      /* smoothing steps before the coarse correction; default 1 */
     int32_t  nu_post;     /* smoothing steps after it; default 1 (equal values keep M symmetric) */
     double   omega;       /* <= 0: per level, Jacobi (4/3) / max_i(sum_j |a_ij| / a_ii), FSAI (4/3) / rho_hat
-                             with rho_hat the Collatz-Wielandt bound of |G A G^T| (10 power steps); > 0: fixed */
+                             with rho_hat the Rayleigh quotient of G A G^T after 15 power steps from a vector
+                             drawn with seed + 1 (G, A, G^T applied in turn); > 0: fixed */
     int32_t  max_levels;  /* default 25 */
     int32_t  max_coarse;  /* a level with at most this many unknowns is solved directly; default 256 */
     int32_t  precision;   /* CAMG_FP64 or CAMG_MIXED_FP32 (FP32 V-cycle inside FP64 PCG) */

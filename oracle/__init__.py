@@ -71,7 +71,7 @@ def lib():
         L.orc_fsai.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut)]
         L.orc_afsai.argtypes = [C.POINTER(CsrOut), i32, i32, dbl, C.POINTER(CsrOut), vp]
         L.orc_afsai_rows.argtypes = [C.POINTER(CsrOut), i32, i32, dbl, i32, vp, vp, vp, vp, vp]
-        L.orc_fsai_omega.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), vp]
+        L.orc_fsai_omega.argtypes = [C.POINTER(CsrOut), C.POINTER(CsrOut), C.c_uint64, i32, vp]
         L.orc_csr_free.argtypes = [C.POINTER(CsrOut)]
         L.orc_setup.argtypes = [i32, vp, vp, vp, C.POINTER(Params), C.POINTER(vp)]
         L.orc_num_levels.argtypes = [vp]
@@ -343,11 +343,11 @@ def afsai_rows(A, rows, steps=10, step=2, eps=0.01):
             for t in range(len(sel))]
 
 
-def fsai_omega(A, G) -> float:
+def fsai_omega(A, G, seed=2021, level=0) -> float:
     oa, ka = _to_out(*_csr_arrays(A))
     og, kg = _to_out(*_csr_arrays(G))
     w = np.zeros(1)
-    assert lib().orc_fsai_omega(C.byref(oa), C.byref(og), _p(w)) == OK
+    assert lib().orc_fsai_omega(C.byref(oa), C.byref(og), seed, level, _p(w)) == OK
     return float(w[0])
 
 

@@ -1434,47 +1434,54 @@ int orc_afsai_rows(const orc_csr *A, int32_t steps, int32_t step, double eps, in
     return st;
 }
 
+static void spmv(const orc_csr *A, const double *s, double *t);
+
 /*
  * Relaxation weight of the FSAI smoother S = I - omega G^T G A, which needs
- * omega rho(G^T G A) < 2 (eq. smoother).  rho(G^T G A) = rho(M) for
- * M = G A G^T, and rho(M) <= rho(|M|) <= max_i (|M| v)_i / v_i for every
- * positive vector v (the Collatz-Wielandt bound of the non-negative matrix
- * |M|).  The paper gives no value; the reading taken is
- * omega = (4/3) / rho_hat with rho_hat the smallest of these bounds over
- * v_0 = 1 and ten power steps v_{k+1} = |M| v_k / max_i (|M| v_k)_i, so
- * omega rho <= 4/3 as for Jacobi (v_0 alone gives the Gershgorin bound).
- * M is formed by the sparse product of this file (G A first, then
- * (G A) G^T); products |M| v are summed in CSR order from 0.0.
+ * omega rho(G^T G A) < 2 (eq. smoother).  rho(G^T G A) = rho(M) for the
+ * symmetric positive definite M = G A G^T.  The paper gives no value; the
+ * reading taken is omega = (4/3) / rho_hat, rho_hat the Rayleigh quotient
+ * v^T M v / v^T v after ORC_FSAI_POWER_STEPS steps of the power method
+ * (v <- M v / ||M v||_2), M applied as G (A (G^T v)) (never formed), from
+ * v_0 with v_0[i] = 2 u_i - 1, u_i = the top 53 bits of splitmix64 draw
+ * ((level << 40) + i) of a generator seeded with seed + 1, over 2^53 (the
+ * PMIS stream with the next seed).  A Rayleigh quotient never exceeds
+ * lambda_max(M), so omega rho(M) >= 4/3; from a random start it comes
+ * within a few per cent of it in that many steps, so omega rho(M) stays
+ * far below 2.  Products in CSR order from 0.0, dot products in index order.
  */
-int orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega) {
-    orc_csr GT = {0, 0, NULL, NULL, NULL}, GA = {0, 0, NULL, NULL, NULL}, M = {0, 0, NULL, NULL, NULL};
+int orc_fsai_omega(const orc_csr *A, const orc_csr *G, uint64_t seed, int32_t level, double *omega) {
+    orc_csr GT = {0, 0, NULL, NULL, NULL};
     int st = orc_transpose(G, &GT);
-    if (!st) st = orc_spgemm(G, A, &GA);
-    if (!st) st = orc_spgemm(&GA, &GT, &M);
-    int32_t n = M.nrows;
-    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    if (!st && (!v || !w)) st = ORC_E_NOMEM;
+    const int32_t n = G->nrows;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    double *v = (double *)malloc(sizeof(double) * nn);
+    double *t = (double *)malloc(sizeof(double) * nn);
+    double *u = (double *)malloc(sizeof(double) * nn);
+    double *w = (double *)malloc(sizeof(double) * nn);
+    if (!st && (!v || !t || !u || !w)) st = ORC_E_NOMEM;
     if (!st) {
-        for (int32_t i = 0; i < n; ++i) v[i] = 1.0;
-        double best = 0.0;
-        for (int32_t k = 0; k <= 10; ++k) {
-            double bound = 0.0, wmax = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            v[i] = 2.0 * ((double)orc_pmis_rand(seed + 1u, level, i) * 0x1p-53) - 1.0;
+        double rq = 0.0;
+        for (int k = 0; k < ORC_FSAI_POWER_STEPS; ++k) {
+            spmv(&GT, v, t);  /* t = G^T v */
+            spmv(A, t, u);    /* u = A G^T v */
+            spmv(G, u, w);    /* w = G A G^T v */
+            double vv = 0.0, vw = 0.0, ww = 0.0;
             for (int32_t i = 0; i < n; ++i) {
-                double s = 0.0;
-                for (int32_t e = M.rp[i]; e < M.rp[i + 1]; ++e) s = s + fabs(M.val[e]) * v[M.ci[e]];
-                w[i] = s;
-                double q = s / v[i];
-                if (q > bound) bound = q;
-                if (s > wmax) wmax = s;
+                vv = vv + v[i] * v[i];
+                vw = vw + v[i] * w[i];
+                ww = ww + w[i] * w[i];
             }
-            if (k == 0 || bound < best) best = bound;
-            for (int32_t i = 0; i < n; ++i) v[i] = w[i] / wmax;
+            rq = vw / vv;
+            const double s = 1.0 / sqrt(ww);
+            for (int32_t i = 0; i < n; ++i) v[i] = w[i] * s;
         }
-        *omega = (4.0 / 3.0) / best;
+        *omega = (4.0 / 3.0) / rq;
     }
-    free(v); free(w);
-    orc_csr_free(&GT); orc_csr_free(&GA); orc_csr_free(&M);
+    free(v); free(t); free(u); free(w);
+    orc_csr_free(&GT);
     return st;
 }
 
@@ -1610,7 +1617,7 @@ int orc_setup_tv(int32_t n, const int32_t *rp, const int32_t *ci, const double *
             if (h->prm.smoother != ORC_SMOOTH_AFSAI) st = orc_fsai(&L->A, &L->G);
             if (!st) st = orc_transpose(&L->G, &L->GT);
             double w = 0.0;
-            if (!st && !(h->prm.omega > 0.0)) st = orc_fsai_omega(&L->A, &L->G, &w);
+            if (!st && !(h->prm.omega > 0.0)) st = orc_fsai_omega(&L->A, &L->G, h->prm.seed, l, &w);
             if (st) { orc_destroy(h); return st; }
             L->omega = h->prm.omega > 0.0 ? h->prm.omega : w;
         } else {

@@ -60,6 +60,7 @@ typedef struct {
 } orc_params;
 enum { ORC_SMOOTH_JACOBI = 0, ORC_SMOOTH_FSAI = 1, ORC_SMOOTH_FSAI_JACOBI = 2, ORC_SMOOTH_AFSAI = 3 };
 #define ORC_AFSAI_MAXM 32        /* entries of a row of the adaptive factor */
+#define ORC_FSAI_POWER_STEPS 15  /* power steps of the FSAI relaxation weight's estimate of rho(G A G^T) */
 #define ORC_AFSAI_MAXCAND 2048   /* ORC_SMOOTH_AFSAI: a level where a row's candidate set grows larger uses Jacobi */
 #define ORC_FSAI_MAXROW 192  /* ORC_SMOOTH_FSAI_JACOBI: FSAI on levels whose rows have at most this many
                                 entries on or below the diagonal, Jacobi on the others */
@@ -109,7 +110,7 @@ int  orc_afsai(const orc_csr *A, int32_t steps, int32_t step, double eps, orc_cs
 int  orc_afsai_rows(const orc_csr *A, int32_t steps, int32_t step, double eps, int32_t nsel, const int32_t *sel,
                     int32_t *cols, double *vals, int32_t *cnt, int32_t *maxcand);
 /* omega = (4/3) / max_i sum_j |(G A G^T)_ij| */
-int  orc_fsai_omega(const orc_csr *A, const orc_csr *G, double *omega);
+int  orc_fsai_omega(const orc_csr *A, const orc_csr *G, uint64_t seed, int32_t level, double *omega);
 void orc_csr_free(orc_csr *m);
 void orc_free(void *p);
 

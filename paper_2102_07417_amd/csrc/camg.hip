@@ -409,10 +409,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             if (prm.omega > 0.0) {
                 L.omega = prm.omega;
             } else {
-                Csr GA, M;
-                spgemm(G, L.A, GA, lt, lt, s);
-                spgemm(GA, Gt, M, lt, lt, s);
-                L.omega = (4.0 / 3.0) / cw_bound(M, lt, s);
+                L.omega = (4.0 / 3.0) / fsai_rayleigh(L.A, G, Gt, prm.seed, l, lt, s);
             }
         }
         if (prm.interp == CAMG_INTERP_BAMG && l == 0 && prm.srqm_iters > 0) {

@@ -257,7 +257,7 @@ void fill_ones(int n, double *x, hipStream_t s);
 void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s);
 // FSAI smoother: counts of entries on or below the diagonal per row (returns
 // the largest), the factor's rows (G.rp set, G.ci / G.v filled; flags[6]:
-// row too long, flags[7]: not SPD), the Collatz-Wielandt bound of |M|
+// row too long, flags[7]: not SPD), the power-method estimate of rho(G A G^T)
 // rows of the FSAI factor: at most this many entries on or below the diagonal
 constexpr int kFsaiMaxRow = 192;
 int fsai_counts(int n, const int32_t *rp, const int32_t *ci, int32_t *cnt, Pool &tmp, hipStream_t s);
@@ -269,7 +269,8 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
 void afsai_rows(const Csr &A, int maxrow, int steps, int step, double eps, int32_t *cnt, int32_t *pci,
                 double *pv, int32_t *flags, hipStream_t s);
 void afsai_compact(const Csr &G, int mcap, const int32_t *pci, const double *pv, hipStream_t s);
-double cw_bound(const Csr &M, Pool &tmp, hipStream_t s);  // XT arrays preallocated (rp, ci, v)
+double fsai_rayleigh(const Csr &A, const Csr &G, const Csr &Gt, uint64_t seed, int level, Pool &tmp,
+                     hipStream_t s);  // rho estimate of G A G^T for the FSAI weight
 void column_counts(const Csr &X, int32_t *cnt, hipStream_t s);
 void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,
                      unsigned long long *qmax_bits, int32_t *flags, hipStream_t s);

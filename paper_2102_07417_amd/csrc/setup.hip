@@ -2704,43 +2704,79 @@ __global__ void k_fill_ones(int n, double *x) {
     if (i < n) x[i] = 1.0;
 }
 
-// Collatz-Wielandt step on |M|: w = |M| v (CSR order), bound = max w_i / v_i,
-// wmax = max w_i (non-negative doubles compared through their bit patterns)
-__global__ void k_cw_step(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *v, double *w,
-                          unsigned long long *bmax) {
+// Relaxation weight of the FSAI smoother (eq. smoother, eq. smo): the
+// Rayleigh quotient of M = G A G^T after kFsaiPowerSteps power steps, M
+// applied as G (A (G^T v)).  Start: v_i = 2 u_i - 1, u_i the top 53 bits of
+// splitmix64 draw ((level << 40) + i) of a generator seeded with seed + 1,
+// over 2^53.  Products summed in CSR order from 0.0 (the oracle's order);
+// the dot products by a fixed tree.
+constexpr int kFsaiPowerSteps = 15;
+constexpr int kPwGrid = 1024;  // blocks of the dot-product kernel (partials per dot)
+
+__global__ void k_pw_start(int n, uint64_t seed, int level, double *v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double q = 0.0, s = 0.0;
     if (i < n) {
-        const int e1 = rp[i + 1];
-        int e = rp[i];
-        for (; e + 8 <= e1; e += 8) {  // eight loads in flight, added in CSR order
-            double x[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) x[t] = fabs(mv[e + t]) * v[ci[e + t]];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) s = s + x[t];
-        }
-        for (; e < e1; ++e) s = s + fabs(mv[e]) * v[ci[e]];
-        w[i] = s;
-        q = s / v[i];
-    }
-    const unsigned long long bq = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
-    const unsigned long long bs = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(s));
-    if (threadIdx.x == 0) {
-        atomicMax(&bmax[0], bq);
-        atomicMax(&bmax[1], bs);
+        const uint64_t c = ((uint64_t)(uint32_t)level << 40) + (uint64_t)(uint32_t)i;
+        v[i] = 2.0 * ((double)(splitmix64(seed + 1u, c) >> 11) * 0x1p-53) - 1.0;
     }
 }
 
-// v = w / wmax; best = min(best, bound) (the first bound when k == 0)
-__global__ void k_cw_norm(int n, double *v, const double *w, const unsigned long long *bmax, double *best, int k) {
+// y = M x, one thread per row, eight loads in flight, added in CSR order
+__global__ void k_pw_spmv(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *x, double *y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const double wmax = __longlong_as_double((long long)bmax[1]);
-    if (i < n) v[i] = w[i] / wmax;
-    if (i == 0) {
-        const double bound = __longlong_as_double((long long)bmax[0]);
-        if (k == 0 || bound < *best) *best = bound;
+    if (i >= n) return;
+    const int e1 = rp[i + 1];
+    int e = rp[i];
+    double s = 0.0;
+    for (; e + 8 <= e1; e += 8) {
+        double p[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) p[t] = mv[e + t] * x[ci[e + t]];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s = s + p[t];
     }
+    for (; e < e1; ++e) s = s + mv[e] * x[ci[e]];
+    y[i] = s;
+}
+
+// partials of v.v, v.w, w.w (block b: part[3 b + 0..2])
+__global__ void __launch_bounds__(kBlock) k_pw_dots(int n, const double *v, const double *w, double *part) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        a = a + v[i] * v[i];
+        b = b + v[i] * w[i];
+        c = c + w[i] * w[i];
+    }
+    a = block_sum<kBlock>(a);
+    b = block_sum<kBlock>(b);
+    c = block_sum<kBlock>(c);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// st[0] = v.w / v.v (the Rayleigh quotient), st[1] = 1 / ||w||
+__global__ void __launch_bounds__(kBlock) k_pw_fin(int nb, const double *part, double *st) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int t = threadIdx.x; t < nb; t += kBlock) {
+        a = a + part[3 * t];
+        b = b + part[3 * t + 1];
+        c = c + part[3 * t + 2];
+    }
+    a = block_sum<kBlock>(a);
+    b = block_sum<kBlock>(b);
+    c = block_sum<kBlock>(c);
+    if (threadIdx.x == 0) {
+        st[0] = b / a;
+        st[1] = 1.0 / sqrt(c);
+    }
+}
+
+__global__ void k_pw_scale(int n, const double *w, const double *st, double *v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = w[i] * st[1];
 }
 
 __global__ void k_fill_d(int n, double *v, double x) {
@@ -3217,21 +3253,27 @@ void fill_ones(int n, double *x, hipStream_t s) {
     HIPC(hipGetLastError());
 }
 
-double cw_bound(const Csr &M, Pool &tmp, hipStream_t s) {
-    const int n = M.nr;
-    double *v = tmp.alloc<double>(n), *w = tmp.alloc<double>(n), *best = tmp.alloc<double>(1);
-    unsigned long long *bmax = tmp.alloc<unsigned long long>(2 * 11);
-    HIPC(hipMemsetAsync(bmax, 0, sizeof(unsigned long long) * 2 * 11, s));
-    k_fill_d<<<nblocks(n), kBlock, 0, s>>>(n, v, 1.0);
-    for (int k = 0; k <= 10; ++k) {
-        k_cw_step<<<nblocks(n), kBlock, 0, s>>>(n, M.rp, M.ci, M.v, v, w, bmax + 2 * k);
-        k_cw_norm<<<nblocks(n), kBlock, 0, s>>>(n, v, w, bmax + 2 * k, best, k);
+double fsai_rayleigh(const Csr &A, const Csr &G, const Csr &Gt, uint64_t seed, int level, Pool &tmp,
+                     hipStream_t s) {
+    const int n = A.nr;
+    double *v = tmp.alloc<double>(n), *t = tmp.alloc<double>(n), *u = tmp.alloc<double>(n), *w = tmp.alloc<double>(n);
+    const int nb = std::max(1, std::min(kPwGrid, (n + kBlock - 1) / kBlock));
+    double *part = tmp.alloc<double>(3 * (size_t)nb), *st = tmp.alloc<double>(2);
+    const unsigned g = (unsigned)nblocks(n);
+    k_pw_start<<<g, kBlock, 0, s>>>(n, seed, level, v);
+    for (int k = 0; k < kFsaiPowerSteps; ++k) {
+        k_pw_spmv<<<g, kBlock, 0, s>>>(n, Gt.rp, Gt.ci, Gt.v, v, t);
+        k_pw_spmv<<<g, kBlock, 0, s>>>(n, A.rp, A.ci, A.v, t, u);
+        k_pw_spmv<<<g, kBlock, 0, s>>>(n, G.rp, G.ci, G.v, u, w);
+        k_pw_dots<<<nb, kBlock, 0, s>>>(n, v, w, part);
+        k_pw_fin<<<1, kBlock, 0, s>>>(nb, part, st);
+        k_pw_scale<<<g, kBlock, 0, s>>>(n, w, st, v);
     }
     HIPC(hipGetLastError());
-    double hb = 0.0;
-    HIPC(hipMemcpyAsync(&hb, best, sizeof(double), hipMemcpyDeviceToHost, s));
+    double rq = 0.0;
+    HIPC(hipMemcpyAsync(&rq, st, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
-    return hb;
+    return rq;
 }
 
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s) {

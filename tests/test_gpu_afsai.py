@@ -4,7 +4,7 @@ The kernel repeats the oracle's roundings step for step (the local
 Cholesky factorisation and substitutions in the oracle's order, the
 gradient components summed along each row of A in CSR order), so the
 greedy choices coincide and every level's factor matches bit for bit.
-omega is compared to 1e-12 (its Collatz-Wielandt sums run in another
+omega is compared to 1e-12 (its power steps sum the dot products in another
 order), V-cycles to 1e-10 and PCG solutions to 1e-9 with iteration counts
 within one.  The cases cover the four launch tiers of the kernel (pattern
 capacity 16 or 32, candidate capacity 256, 1024 or 2048), ties (constant

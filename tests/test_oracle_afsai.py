@@ -252,7 +252,7 @@ def test_afsai_vcycle_matches_iteration_matrix(gen, mc):
     om = [h.omega(l) for l in range(h.nlev - 1)]
     for l in range(h.nlev - 1):
         np.testing.assert_array_equal(Gs[l], dense(_aG(h.A(l), 4, 2, 0.01)[0]))
-        assert O.fsai_omega(h.A(l), h.G(l)) == om[l]
+        assert O.fsai_omega(h.A(l), h.G(l), h.params.seed, l) == om[l]
     M = _M_fsai(dense(A), Ps, Gs, om, 0, 1, 1)
     Mo = np.stack([h.vcycle(e) for e in np.eye(A.n)], axis=1)
     np.testing.assert_allclose(Mo, M, rtol=0, atol=1e-12 * np.abs(M).max())

@@ -45,7 +45,11 @@ MUTATIONS = [
     ("fsai_scale_not_sqrt", "double sd = sqrt(g[m - 1]);", "double sd = g[m - 1];"),
     ("fsai_wrong_unit_vector", "e[r] = r == m - 1 ? 1.0 : 0.0;", "e[r] = r == 0 ? 1.0 : 0.0;"),
     ("fsai_G_twice", "spmv(&L->G, y, u);\n        spmv(&L->GT, u, w);", "spmv(&L->G, y, u);\n        spmv(&L->G, u, w);"),
-    ("fsai_omega_no_abs", "s = s + fabs(M.val[e]) * v[M.ci[e]];", "s = s + M.val[e] * v[M.ci[e]];"),
+    ("fsai_omega_G_for_GT", "spmv(&GT, v, t);  /* t = G^T v */", "spmv(G, v, t);"),
+    ("fsai_omega_quotient", "rq = vw / vv;", "rq = ww / vw;"),
+    ("fsai_omega_fewer_steps", "for (int k = 0; k < ORC_FSAI_POWER_STEPS; ++k) {",
+     "for (int k = 0; k < ORC_FSAI_POWER_STEPS - 5; ++k) {"),
+    ("fsai_omega_pmis_seed", "orc_pmis_rand(seed + 1u, level, i)", "orc_pmis_rand(seed, level, i)"),
     ("fsai_step_sign", "s[i] = s[i] + L->omega * w[i];", "s[i] = s[i] - L->omega * w[i];"),
     ("ext_no_direct_coupling", "num[t] = e >= 0 ? v[e] : 0.0;", "num[t] = 0.0; (void)e;"),
     ("ext_no_sign_filter", "return sa == sd ? 0.0 : a;", "(void)sa; (void)sd; return a;"),
