@@ -213,6 +213,8 @@ void validate_sym(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, cons
 void transpose_positions(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, int32_t *tpos, hipStream_t s);
 void strength(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *tpos,
               double theta, uint8_t *strong, int32_t *stcnt, hipStream_t s);
+// PMIS: *undecided ends positive while undecided points remain, zero once
+// every point is C or F
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
                int32_t *undecided, hipStream_t s);
 void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,

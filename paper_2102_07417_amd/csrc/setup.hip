@@ -60,6 +60,22 @@ __device__ void block_exclusive_scan(int64_t (&v)[kScanItems], int64_t &total) {
     __syncthreads();
 }
 
+// Block results folded into one device word: the maximum only by a block
+// whose value exceeds what the word holds already (values only grow, so a
+// stale read costs an atomic at most), and "some point left" by the first
+// blocks that find the word at zero.  Either keeps the result exact while
+// most of the grid's blocks skip the atomic (one atomic per block on one
+// address serialises the grid).
+__device__ __forceinline__ void fold_max(unsigned long long *w, unsigned long long v) {
+    if (v > __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(w, v);
+}
+__device__ __forceinline__ void fold_max(int32_t *w, int32_t v) {
+    if (v > __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(w, v);
+}
+__device__ __forceinline__ void fold_any(int32_t *w, int32_t v) {
+    if (v > 0 && __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicAdd(w, v);
+}
+
 template <class T>
 __global__ void k_scan_tiles(const T *in, int n, int64_t *tile_sum) {
     int64_t v[kScanItems];
@@ -155,7 +171,7 @@ __global__ void k_val_rows(int n, const int32_t *rp, const int32_t *ci, const do
     if (!has_diag) atomicOr(&flags[3], 1);
     if (bad_diag) atomicOr(&flags[5], 1);
     const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(m));
-    if (threadIdx.x == 0) atomicMax(amax, bm);
+    if (threadIdx.x == 0) fold_max(amax, bm);
 }
 
 // ---- per-row set-up work with G lanes per row (G a power of two <= 64):
@@ -289,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_gersh_g(int n, const int32_t *r
         }
     }
     const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(q));
-    if (threadIdx.x == 0) atomicMax(qmax, bm);
+    if (threadIdx.x == 0) fold_max(qmax, bm);
 }
 
 // awd_e = a_e * wd_{col e}, one thread per nonzero
@@ -335,7 +351,7 @@ __global__ void k_pmis_init(int n, const int32_t *stcnt, uint64_t seed, int leve
         und = (s == kU);
     }
     const long long bu = block_sum_ll<kBlock>(und);
-    if (threadIdx.x == 0 && bu) atomicAdd(undecided, (int32_t)bu);
+    if (threadIdx.x == 0) fold_any(undecided, (int32_t)bu);
 }
 
 __device__ __forceinline__ bool key_gt(const int32_t *cnt, const uint64_t *u, int a, int b) {
@@ -384,7 +400,7 @@ __global__ void k_pmis_update(int n, const int32_t *rp, const int32_t *ci, const
         }
     }
     const long long bu = block_sum_ll<kBlock>(und);
-    if (threadIdx.x == 0 && bu) atomicAdd(undecided, (int32_t)bu);
+    if (threadIdx.x == 0) fold_any(undecided, (int32_t)bu);
 }
 
 __global__ void k_cf_flags(int n, const int8_t *cf, int32_t *isc) {
@@ -728,7 +744,7 @@ __global__ void k_fsai_count(int n, const int32_t *rp, const int32_t *ci, int32_
         cnt[i] = m;
     }
     const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)m);
-    if (threadIdx.x == 0) atomicMax(mmax, (int32_t)bm);
+    if (threadIdx.x == 0) fold_max(mmax, (int32_t)bm);
 }
 
 __device__ __forceinline__ double csr_lookup(const int32_t *rp, const int32_t *ci, const double *v, int i, int j) {
@@ -905,8 +921,8 @@ __global__ void k_xi_bound(int n, const int32_t *rp, const int32_t *ci, const ui
     const unsigned long long m = block_max_u64<kBlock>((unsigned long long)b);
     const unsigned long long mw = block_max_u64<kBlock>(thread_row ? 0ull : (unsigned long long)b);
     if (threadIdx.x == 0) {
-        atomicMax(bmax, m);
-        atomicMax(bmax + 1, mw);
+        fold_max(bmax, m);
+        fold_max(bmax + 1, mw);
     }
 }
 
@@ -2788,7 +2804,7 @@ __global__ void k_max_row(int n, const int32_t *rp, int32_t *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int len = i < n ? rp[i + 1] - rp[i] : 0;
     const unsigned long long m = block_max_u64<kBlock>((unsigned long long)len);
-    if (threadIdx.x == 0) atomicMax(out, (int32_t)m);
+    if (threadIdx.x == 0) fold_max(out, (int32_t)m);
 }
 
 // Tiles of the row kernels: tile t holds the rows whose first nonzero lies
