@@ -361,7 +361,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
             apv = lt.alloc<double>((size_t)nl * mcap);
             const int maxrow = max_row_length(nl, L.A.rp, lt, s);
             HIPC(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
-            afsai_rows(L.A, maxrow, prm.afsai_steps, prm.afsai_step, prm.afsai_eps, gcnt, apci, apv, flags, s);
+            afsai_rows(L.A, tpos, maxrow, prm.afsai_steps, prm.afsai_step, prm.afsai_eps, gcnt, apci, apv, flags, s);
             int32_t af[8];
             HIPC(hipMemcpyAsync(af, flags, sizeof(af), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));

@@ -267,9 +267,9 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s);
 // adaptive FSAI: rows padded to steps * step + 1 slots (pci / pv, counts in
 // cnt; flags[6]: a candidate set exceeded 2048 entries, the level takes
 // Jacobi; flags[7]: not SPD; flags[4]: internal capacity error), then
-// compacted into G (G.rp the scan of the counts)
-void afsai_rows(const Csr &A, int maxrow, int steps, int step, double eps, int32_t *cnt, int32_t *pci,
-                double *pv, int32_t *flags, hipStream_t s);
+// compacted into G (G.rp the scan of the counts); tpos: transpose positions of A
+void afsai_rows(const Csr &A, const int32_t *tpos, int maxrow, int steps, int step, double eps, int32_t *cnt,
+                int32_t *pci, double *pv, int32_t *flags, hipStream_t s);
 void afsai_compact(const Csr &G, int mcap, const int32_t *pci, const double *pv, hipStream_t s);
 double fsai_rayleigh(const Csr &A, const Csr &G, const Csr &Gt, uint64_t seed, int level, Pool &tmp,
                      hipStream_t s);  // rho estimate of G A G^T for the FSAI weight

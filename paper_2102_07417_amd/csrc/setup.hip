@@ -1119,12 +1119,14 @@ __device__ __forceinline__ int wave_min_i(int x) {
 template <int MAXM, int CAP, int WPB>
 __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *__restrict__ arp,
                                                          const int32_t *__restrict__ aci,
-                                                         const double *__restrict__ av, int steps, int step,
+                                                         const double *__restrict__ av,
+                                                         const int32_t *__restrict__ tpos, int steps, int step,
                                                          double eps, int mcap, int32_t *__restrict__ cnt,
                                                          int32_t *__restrict__ pci, double *__restrict__ pv,
                                                          int32_t *flags) {
     constexpr int Q = CAP / 64;
     __shared__ double Ms[WPB][MAXM * (MAXM + 1) / 2];
+    __shared__ double zs[WPB][CAP <= 256 ? 1 : CAP];  // scattered gradient (large candidate sets)
     __shared__ double es[WPB][MAXM], ys[WPB][MAXM];
     __shared__ int Ps[WPB][MAXM], pends[WPB][MAXM];
     __shared__ int cbuf[WPB][3][CAP];
@@ -1224,22 +1226,55 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
             }
         }
         npend = 0;
-        // gradient components, one candidate per lane and slot
+        // gradient components z_j = sum over c in P of a_jc y_c, each added
+        // in ascending c from 0.0 (the sum along row j of A in CSR order).
+        // Small candidate sets (short rows): each lane walks the rows of its
+        // candidates.  Large ones: the terms are scattered from the rows of
+        // the pattern instead (|P| rows rather than every candidate's): for
+        // c = P[0], P[1], ... in turn the lanes take the entries (c, j) of
+        // row c with j < i, and a candidate j adds a_jc (its own row's value,
+        // at the transpose position) times y_c -- the same terms in the same
+        // order, so both ways round alike.
+        if constexpr (CAP <= 256) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int idx = lane + 64 * q;
-            double s = 0.0;
-            if (idx < nC) {
-                const int j = C[idx];
-                int pp = 0;
-                for (int t = arp[j]; t < arp[j + 1]; ++t) {
-                    const int col = aci[t];
-                    if (col > i) break;
-                    while (pp < m && P[pp] < col) ++pp;
-                    if (pp < m && P[pp] == col) s = s + av[t] * y[pp];
+            for (int q = 0; q < Q; ++q) {
+                const int idx = lane + 64 * q;
+                double sz = 0.0;
+                if (idx < nC) {
+                    const int j = C[idx];
+                    int pp = 0;
+                    for (int t = arp[j]; t < arp[j + 1]; ++t) {
+                        const int col = aci[t];
+                        if (col > i) break;
+                        while (pp < m && P[pp] < col) ++pp;
+                        if (pp < m && P[pp] == col) sz = sz + av[t] * y[pp];
+                    }
                 }
+                zr[q] = sz;
             }
-            zr[q] = s;
+        } else {
+            double *z = zs[w];
+            for (int t = lane; t < nC; t += 64) z[t] = 0.0;
+            FSAI_SYNC();
+            for (int r = 0; r < m; ++r) {
+                const int c = P[r], ce = arp[c + 1];
+                const double yc = y[r];
+                for (int b = arp[c]; b < ce; b += 64) {
+                    if (aci[b] >= i) break;  // rows are sorted: nothing below i is left
+                    const int e = b + lane;
+                    const int j = e < ce ? aci[e] : INT_MAX;
+                    if (j < i) {
+                        const int slot = xi_find(C, nC, j);
+                        if (slot >= 0) z[slot] = z[slot] + av[tpos[e]] * yc;
+                    }
+                }
+                FSAI_SYNC();
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int idx = lane + 64 * q;
+                zr[q] = idx < nC ? z[idx] : 0.0;
+            }
         }
         // 4. the `step` largest |z_j| > 0 join P (smaller j on ties: C is ascending)
         for (int a = 0; a < step; ++a) {
@@ -3085,15 +3120,15 @@ void fsai_rows(const Csr &A, Csr &G, int mmax, int32_t *flags, hipStream_t s) {
     HIPC(hipGetLastError());
 }
 
-void afsai_rows(const Csr &A, int maxrow, int steps, int step, double eps, int32_t *cnt, int32_t *pci,
-                double *pv, int32_t *flags, hipStream_t s) {
+void afsai_rows(const Csr &A, const int32_t *tpos, int maxrow, int steps, int step, double eps, int32_t *cnt,
+                int32_t *pci, double *pv, int32_t *flags, hipStream_t s) {
     const int n = A.nr;
     const int mcap = steps * step + 1;
     if (steps < 0 || step < 1 || mcap > kAfsaiMaxM) fail(CAMG_E_ARG, "aFSAI: steps * step + 1 must be at most 32");
     const int64_t bound = (int64_t)mcap * std::max(maxrow, 1);  // candidates of a row never exceed this
 #define AFSAI_LAUNCH(MM, CAP, WPB)                                                                            \
-    k_afsai_rows<MM, CAP, WPB><<<(n + (WPB) - 1) / (WPB), (WPB) * 64, 0, s>>>(n, A.rp, A.ci, A.v, steps, step, \
-                                                                               eps, mcap, cnt, pci, pv, flags)
+    k_afsai_rows<MM, CAP, WPB><<<(n + (WPB) - 1) / (WPB), (WPB) * 64, 0, s>>>(n, A.rp, A.ci, A.v, tpos, steps, \
+                                                                               step, eps, mcap, cnt, pci, pv, flags)
     if (mcap <= 16 && bound <= 256) AFSAI_LAUNCH(16, 256, 4);
     else if (bound <= 256) AFSAI_LAUNCH(kAfsaiMaxM, 256, 4);
     else if (bound <= 1024) AFSAI_LAUNCH(kAfsaiMaxM, 1024, 2);
