@@ -265,15 +265,19 @@ __global__ void __launch_bounds__(kBlock) mk_rows(int n, const int32_t *__restri
             for (int t = threadIdx.x; t <= b - a; t += kBlock) s_rp[t] = rp[a + t] - E0;
             __syncthreads();
             for (int i = a + grp; i < b; i += RPP) {
+                typename E::template Pre<V> pre;
+                epi.template load<V>(i, c0, pre);
                 T acc[V];
                 row_acc<T, V, U>(s_rp[i - a], s_rp[i - a + 1], s_ci, s_av, g, c0, acc);
-                epi.template fin<V>(i, c0, acc, dot);
+                epi.template fin<V>(i, c0, acc, pre, dot);
             }
         } else {
             for (int i = a + grp; i < b; i += RPP) {
+                typename E::template Pre<V> pre;
+                epi.template load<V>(i, c0, pre);
                 T acc[V];
                 row_acc<T, V, U>(rp[i], rp[i + 1], ci, av, g, c0, acc);
-                epi.template fin<V>(i, c0, acc, dot);
+                epi.template fin<V>(i, c0, acc, pre, dot);
             }
         }
     }
@@ -305,6 +309,9 @@ struct MGather {
     }
 };
 
+// Epilogues: load(i, c0, pre) issues the row's epilogue reads, which the
+// row loop calls before the row's gathers so that both wait together;
+// fin(i, c0, acc, pre, dot) completes the row.
 template <class T, int K, class TY>
 struct MEPre {  // S = wd Y, R = Y - (A wd) Y  (values pre-scaled by wd)
     __device__ void prep(int) {}
@@ -312,16 +319,23 @@ struct MEPre {  // S = wd Y, R = Y - (A wd) Y  (values pre-scaled by wd)
     const TY *y;
     T *s, *r;
     template <int V>
-    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
+    struct Pre {
+        TY y[V];
+        T w;
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &p) const {
+        vload<TY, V>(y + (size_t)i * K + c0, p.y);
+        p.w = wd[i];
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], const Pre<V> &p, double (&)[V]) const {
         const size_t o = (size_t)i * K + c0;
-        TY yv[V];
-        vload<TY, V>(y + o, yv);
-        const T w = wd[i];
         T sv[V], rv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const T yi = (T)yv[v];
-            sv[v] = w * yi;
+            const T yi = (T)p.y[v];
+            sv[v] = p.w * yi;
             rv[v] = yi - acc[v];
         }
         vstore<T, V>(s + o, sv);
@@ -336,19 +350,27 @@ struct MEPost {  // Z = S + wd (Y - A S); dot += Y Z
     const T *s;
     TZ *z;
     template <int V>
-    __device__ void fin(int i, int c0, const T (&acc)[V], double (&dot)[V]) const {
+    struct Pre {
+        TY y[V];
+        T s[V];
+        T w;
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &p) const {
         const size_t o = (size_t)i * K + c0;
-        TY yv[V];
-        T sv[V];
-        vload<TY, V>(y + o, yv);
-        vload<T, V>(s + o, sv);
-        const T w = wd[i];
+        vload<TY, V>(y + o, p.y);
+        vload<T, V>(s + o, p.s);
+        p.w = wd[i];
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], const Pre<V> &p, double (&dot)[V]) const {
+        const size_t o = (size_t)i * K + c0;
         TZ zv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const T zi = sv[v] + w * ((T)yv[v] - acc[v]);
+            const T zi = p.s[v] + p.w * ((T)p.y[v] - acc[v]);
             zv[v] = (TZ)zi;
-            dot[v] += (double)yv[v] * (double)zv[v];
+            dot[v] += (double)p.y[v] * (double)zv[v];
         }
         vstore<TZ, V>(z + o, zv);
     }
@@ -359,14 +381,19 @@ struct MEResid {
     const TY *y;
     T *r;
     template <int V>
-    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
-        const size_t o = (size_t)i * K + c0;
-        TY yv[V];
-        vload<TY, V>(y + o, yv);
+    struct Pre {
+        TY y[V];
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &p) const {
+        vload<TY, V>(y + (size_t)i * K + c0, p.y);
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], const Pre<V> &p, double (&)[V]) const {
         T rv[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) rv[v] = (T)yv[v] - acc[v];
-        vstore<T, V>(r + o, rv);
+        for (int v = 0; v < V; ++v) rv[v] = (T)p.y[v] - acc[v];
+        vstore<T, V>(r + (size_t)i * K + c0, rv);
     }
 };
 template <class T, int K, bool ADD>
@@ -374,18 +401,19 @@ struct MESpmv {
     __device__ void prep(int) {}
     T *out;
     template <int V>
-    __device__ void fin(int i, int c0, const T (&acc)[V], double (&)[V]) const {
-        const size_t o = (size_t)i * K + c0;
+    struct Pre {
+        T o[V];
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &p) const {
+        if (ADD) vload<T, V>(out + (size_t)i * K + c0, p.o);
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const T (&acc)[V], const Pre<V> &p, double (&)[V]) const {
         T ov[V];
-        if (ADD) {
-            vload<T, V>(out + o, ov);
 #pragma unroll
-            for (int v = 0; v < V; ++v) ov[v] = ov[v] + acc[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) ov[v] = acc[v];
-        }
-        vstore<T, V>(out + o, ov);
+        for (int v = 0; v < V; ++v) ov[v] = ADD ? p.o[v] + acc[v] : acc[v];
+        vstore<T, V>(out + (size_t)i * K + c0, ov);
     }
 };
 template <int K>
@@ -394,13 +422,18 @@ struct MEPQ {  // Q = A P; dot += P.Q (own row of P read back)
     const double *p;
     double *q;
     template <int V>
-    __device__ void fin(int i, int c0, const double (&acc)[V], double (&dot)[V]) const {
-        const size_t o = (size_t)i * K + c0;
-        double pv[V];
-        vload<double, V>(p + o, pv);
+    struct Pre {
+        double p[V];
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &pr) const {
+        vload<double, V>(p + (size_t)i * K + c0, pr.p);
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const double (&acc)[V], const Pre<V> &pr, double (&dot)[V]) const {
 #pragma unroll
-        for (int v = 0; v < V; ++v) dot[v] += pv[v] * acc[v];
-        vstore<double, V>(q + o, acc);
+        for (int v = 0; v < V; ++v) dot[v] += pr.p[v] * acc[v];
+        vstore<double, V>(q + (size_t)i * K + c0, acc);
     }
 };
 template <int K>
@@ -411,13 +444,19 @@ struct MERes {  // d = B - A X; dot += d^2; R = d for the columns of `mask`
     float *out32;  // FP32 copy of R (mixed precision) or null
     unsigned long long mask;
     template <int V>
-    __device__ void fin(int i, int c0, const double (&acc)[V], double (&dot)[V]) const {
+    struct Pre {
+        double b[V];
+    };
+    template <int V>
+    __device__ void load(int i, int c0, Pre<V> &p) const {
+        vload<double, V>(b + (size_t)i * K + c0, p.b);
+    }
+    template <int V>
+    __device__ void fin(int i, int c0, const double (&acc)[V], const Pre<V> &p, double (&dot)[V]) const {
         const size_t o = (size_t)i * K + c0;
-        double bv[V];
-        vload<double, V>(b + o, bv);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const double d = bv[v] - acc[v];
+            const double d = p.b[v] - acc[v];
             if (out && ((mask >> (c0 + v)) & 1ull)) {
                 out[o + v] = d;
                 if (out32) out32[o + v] = (float)d;
