@@ -231,25 +231,46 @@ void alloc_f32_copy(Pool &pool, Csr &M, hipStream_t s) {
     to_f32(M.nnz, M.v, M.v32, s);
 }
 
-RowCfg make_cfg(Hier &h, const Csr &M, Pool &tmp, hipStream_t s) {
-    RowCfg c = choose_cfg(M.nr, M.nnz, max_row_length(M.nr, M.rp, tmp, s));
-    if (c.tile) {
+// Launch shapes of several matrices with two synchronisations in all (the
+// longest rows, then the tile-base modes) instead of two per matrix.
+void make_cfgs(Hier &h, const std::vector<std::pair<const Csr *, RowCfg *>> &ms, Pool &tmp, hipStream_t s) {
+    const int nm = (int)ms.size();
+    if (nm == 0) return;
+    int32_t *d = tmp.alloc<int32_t>(3 * (size_t)nm);  // longest row, then two flags per matrix
+    HIPC(hipMemsetAsync(d, 0, 3 * sizeof(int32_t) * (size_t)nm, s));
+    for (int k = 0; k < nm; ++k) max_row_length_async(ms[k].first->nr, ms[k].first->rp, d + k, s);
+    std::vector<int32_t> hd(3 * (size_t)nm);
+    HIPC(hipMemcpyAsync(hd.data(), d, sizeof(int32_t) * (size_t)nm, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::vector<int32_t *> tbs(nm, nullptr);
+    for (int k = 0; k < nm; ++k) {
+        const Csr &M = *ms[k].first;
+        RowCfg &c = *ms[k].second;
+        c = choose_cfg(M.nr, M.nnz, hd[k]);
+        if (!c.tile) continue;
         c.tstart = h.pool.alloc<int32_t>((size_t)c.ntiles + 1);
         tile_starts(M.nr, M.rp, c.W, c.ntiles, c.tstart, s);
-        // 16-bit column words (window, offset) per tile: 10 bytes per FP64
-        // nonzero instead of 12 (6 instead of 8 in FP32) where the tiles allow
-        // them
-        int32_t *tb = h.pool.alloc<int32_t>((size_t)c.ntiles * kTileWins);
-        const int mode = tile_bases(c.ntiles, c.tstart, M.rp, M.ci, tb, tmp, s);
-        if (mode) {
-            c.tbase = tb;
-            c.off = h.pool.alloc<uint16_t>(padded(M.nnz));
-            c.off_mode = mode;
-            tile_diffs(c.ntiles, c.tstart, M.rp, M.ci, c.tbase, c.off, mode, s);
-            c.use_off = h.compact_cols;
-        }
+        tbs[k] = h.pool.alloc<int32_t>((size_t)c.ntiles * kTileWins);
+        tile_bases_async(c.ntiles, c.tstart, M.rp, M.ci, tbs[k], d + nm + 2 * k, s);
     }
-    return c;
+    HIPC(hipMemcpyAsync(hd.data() + nm, d + nm, 2 * sizeof(int32_t) * (size_t)nm, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    for (int k = 0; k < nm; ++k) {
+        RowCfg &c = *ms[k].second;
+        if (!c.tile || c.ntiles <= 0) continue;
+        const int32_t *f = hd.data() + nm + 2 * k;
+        const int mode = f[1] == 0 ? 1 : f[0] == 0 ? 2 : 0;
+        if (!mode) continue;
+        // 16-bit column words (window, offset) per tile: 10 bytes per FP64
+        // nonzero instead of 12 (6 instead of 8 in FP32) where the tiles
+        // allow them
+        const Csr &M = *ms[k].first;
+        c.tbase = tbs[k];
+        c.off = h.pool.alloc<uint16_t>(padded(M.nnz));
+        c.off_mode = mode;
+        tile_diffs(c.ntiles, c.tstart, M.rp, M.ci, c.tbase, c.off, mode, s);
+        c.use_off = h.compact_cols;
+    }
 }
 
 void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const double *v, int nt,
@@ -309,7 +330,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
 
     int32_t *flags = tmp.alloc<int32_t>(8);
     unsigned long long *qmax = tmp.alloc<unsigned long long>(1);
-    int32_t *und = tmp.alloc<int32_t>(1);
+    int32_t *und = tmp.alloc<int32_t>(2);  // undecided-point flags of two PMIS rounds
     for (int l = 0;; ++l) {
         cur_level = l;
         const int nl = h.lev[l].A.nr;
@@ -430,10 +451,17 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         pmis_init(nl, L.stcnt, prm.seed, l, u, L.cf, und, s);
         int32_t hund = read1(und, s);
         int rounds = 0;
+        // two rounds per read-back of the flags (a round after the last one
+        // finds no undecided point and changes nothing); rounds counts those
+        // that started with undecided points
         while (hund > 0) {
             pmis_round(nl, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und, s);
-            ++rounds;
-            hund = read1(und, s);
+            pmis_round(nl, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und + 1, s);
+            int32_t hu[2];
+            HIPC(hipMemcpyAsync(hu, und, sizeof(hu), hipMemcpyDeviceToHost, s));
+            HIPC(hipStreamSynchronize(s));
+            rounds += hu[0] > 0 ? 2 : 1;
+            hund = hu[0] > 0 ? hu[1] : 0;
             if (rounds > nl + 1) fail(CAMG_E_DEVICE, "PMIS did not terminate");
         }
         L.rounds = rounds;
@@ -558,19 +586,26 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
     phase(6);
     // launch shapes, work vectors, mixed-precision copies
     const bool mixed = prm.precision == CAMG_MIXED_FP32;
+    {
+        std::vector<std::pair<const Csr *, RowCfg *>> ms;
+        for (int l = 0; l < h.nlev; ++l) {
+            Level &L = h.lev[l];
+            ms.push_back({&L.A, &L.cA});
+            if (l < h.nlev - 1) {
+                ms.push_back({&L.P, &L.cP});
+                ms.push_back({&L.R, &L.cR});
+            }
+            if (L.fsai && l < h.nlev - 1) {
+                ms.push_back({&L.G, &L.cG});
+                ms.push_back({&L.Gt, &L.cGt});
+            }
+        }
+        make_cfgs(h, ms, tmp, s);
+    }
     for (int l = 0; l < h.nlev; ++l) {
         Level &L = h.lev[l];
         const int nl = L.A.nr;
-        L.cA = make_cfg(h, L.A, tmp, s);
         const bool fsai = L.fsai && l < h.nlev - 1;
-        if (l < h.nlev - 1) {
-            L.cP = make_cfg(h, L.P, tmp, s);
-            L.cR = make_cfg(h, L.R, tmp, s);
-        }
-        if (fsai) {
-            L.cG = make_cfg(h, L.G, tmp, s);
-            L.cGt = make_cfg(h, L.Gt, tmp, s);
-        }
         if (!mixed) {
             if (l > 0) {
                 L.y = h.pool.alloc<double>(nl);

@@ -283,15 +283,19 @@ void dense_from_csr(int n, const int32_t *rp, const int32_t *ci, const double *v
 void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s);
 void chol_inverse(int n, const double *L, double *X, hipStream_t s);
 int max_row_length(int n, const int32_t *rp, Pool &tmp, hipStream_t s);
+// the same without a synchronisation: the longest row is folded into *out
+// (zeroed by the caller)
+void max_row_length_async(int n, const int32_t *rp, int32_t *out, hipStream_t s);
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s);
-// compact columns: tile_bases places up to kTileWins windows of 2^kWinBits
-// columns per tile (tbase: ntiles * kTileWins, slot 0 = the tile's smallest
-// column) and returns 1 when one 65536-column span covers every tile, 2 when
-// the windows do, 0 otherwise; tile_diffs then writes the 16-bit words of
-// that mode
+// compact columns: tile_bases_async places up to kTileWins windows of
+// 2^kWinBits columns per tile (tbase: ntiles * kTileWins, slot 0 = the
+// tile's smallest column) and leaves in flag[0..1] (zeroed by the caller)
+// what the host turns into the mode: flag[1] == 0, one 65536-column span
+// covers every tile (mode 1); else flag[0] == 0, the windows do (mode 2);
+// else neither (0); tile_diffs then writes the 16-bit words of that mode
 constexpr int kTileWins = 8, kWinBits = 13;
-int tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
-               hipStream_t s);
+void tile_bases_async(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase,
+                      int32_t *flag, hipStream_t s);
 void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,
                 uint16_t *off, int mode, hipStream_t s);
 

@@ -3078,17 +3078,15 @@ void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, h
     HIPC(hipGetLastError());
 }
 
-int tile_bases(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase, Pool &tmp,
-               hipStream_t s) {  // tbase: ntiles * kTileWins
-    if (ntiles <= 0) return 0;
-    int32_t *flag = tmp.alloc<int32_t>(2);
-    HIPC(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
-    k_tile_bases<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, flag);
+void max_row_length_async(int n, const int32_t *rp, int32_t *out, hipStream_t s) {
+    k_max_row<<<nblocks(n), kBlock, 0, s>>>(n, rp, out);
     HIPC(hipGetLastError());
-    int32_t hf[2] = {0, 0};
-    HIPC(hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    return hf[1] == 0 ? 1 : hf[0] == 0 ? 2 : 0;
+}
+
+void tile_bases_async(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, int32_t *tbase,
+                      int32_t *flag, hipStream_t s) {
+    if (ntiles > 0) k_tile_bases<<<ntiles, kBlock, 0, s>>>(ntiles, tstart, rp, ci, tbase, flag);
+    HIPC(hipGetLastError());
 }
 
 void tile_diffs(int ntiles, const int32_t *tstart, const int32_t *rp, const int32_t *ci, const int32_t *tbase,

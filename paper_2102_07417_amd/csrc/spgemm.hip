@@ -437,23 +437,44 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr, xv, prod);
     k_thread_rows<false><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, cnt, nullptr, nullptr, nullptr);
     HIPC(hipGetLastError());
-    int32_t hb[NB];
-    HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
+    int32_t hbs[NB];  // rows per symbolic bin
+    HIPC(hipMemcpyAsync(hbs, bcnt, sizeof(hbs), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
 
     // 2. symbolic
-    launch_symbolic<128, kWPB>(hb[0], brows + 0 * (size_t)nr, xv, yv, cnt, ovf, s);
-    launch_symbolic<512, kWPB>(hb[1], brows + 1 * (size_t)nr, xv, yv, cnt, ovf, s);
-    launch_symbolic<2048, kWPB>(hb[2], brows + 2 * (size_t)nr, xv, yv, cnt, ovf, s);
-    launch_symbolic<8192, kWPB>(hb[3], brows + 3 * (size_t)nr, xv, yv, cnt, ovf, s);
-    launch_symbolic<16384, 2>(hb[4], brows + 4 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<128, kWPB>(hbs[0], brows + 0 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<512, kWPB>(hbs[1], brows + 1 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<2048, kWPB>(hbs[2], brows + 2 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<8192, kWPB>(hbs[3], brows + 3 * (size_t)nr, xv, yv, cnt, ovf, s);
+    launch_symbolic<16384, 2>(hbs[4], brows + 4 * (size_t)nr, xv, yv, cnt, ovf, s);
+    // 3. row pointer, then the fill bins by exact row length; the overflow
+    // flag, the product's size and the bin counts come back in one
+    // read-back (the rare overflow path redoes the row pointer and bins)
+    const int64_t fill_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
+    int64_t *rp64 = tmp.alloc<int64_t>((size_t)nr + 1);
+    int32_t *bcnt2 = tmp.alloc<int32_t>(NB);
+    int32_t *brows2 = tmp.alloc<int32_t>((size_t)NB * nr);
+    int64_t *flim = tmp.alloc<int64_t>(NB);
+    HIPC(hipMemcpyAsync(flim, fill_lim_h, sizeof(fill_lim_h), hipMemcpyHostToDevice, s));
+    int64_t nnz = 0;
     int32_t hovf = 0;
-    HIPC(hipMemcpyAsync(&hovf, ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
+    int32_t hb[NB];  // rows per fill bin
+    auto rowptr_and_bins = [&]() {
+        scan_i32_to_i64(cnt, rp64, nr, tmp, s);
+        narrow_i64(rp64, Z.rp, nr, s);  // checked against 2^31 - 1 below, before use
+        HIPC(hipMemsetAsync(bcnt2, 0, sizeof(int32_t) * NB, s));
+        k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, flim, bcnt2, brows2, nr, xv, prod);
+        HIPC(hipGetLastError());
+        HIPC(hipMemcpyAsync(&nnz, rp64 + nr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(&hovf, ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPC(hipMemcpyAsync(hb, bcnt2, sizeof(hb), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+    };
+    rowptr_and_bins();
     if (hovf) {
         // rows whose distinct columns overflowed the largest LDS table: redo
         // them with global tables sized from their product bound
-        std::vector<int32_t> rows(hb[4]);
+        std::vector<int32_t> rows(hbs[4]);
         std::vector<int64_t> pr(nr);
         std::vector<int32_t> cn(nr);
         HIPC(hipMemcpy(rows.data(), brows + 4 * (size_t)nr, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost));
@@ -481,37 +502,25 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
         k_symbolic_glb<<<(int)grow.size(), 64, 0, s>>>((int)grow.size(), drows, doff, dts, xv, yv, scr, cnt, ovf);
         HIPC(hipGetLastError());
         HIPC(hipStreamSynchronize(s));
+        HIPC(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
+        rowptr_and_bins();
     }
-
-    // 3. row pointer
-    int64_t *rp64 = tmp.alloc<int64_t>((size_t)nr + 1);
-    scan_i32_to_i64(cnt, rp64, nr, tmp, s);
-    int64_t nnz = 0;
-    HIPC(hipMemcpyAsync(&nnz, rp64 + nr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
     if (nnz > INT32_MAX) fail(CAMG_E_NOMEM, "sparse product has more than 2^31-1 nonzeros");
-    narrow_i64(rp64, Z.rp, nr, s);
     Z.nnz = nnz;
     Z.ci = out.alloc<int32_t>(padded(nnz));
     Z.v = out.alloc<double>(padded(nnz));
 
-    // 4. fill bins by exact row length
-    const int64_t fill_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
-    HIPC(hipMemcpyAsync(lim, fill_lim_h, sizeof(fill_lim_h), hipMemcpyHostToDevice, s));
-    HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
-    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, lim, bcnt, brows, nr, xv, prod);
+    // 4. fill
     k_thread_rows<true><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, nullptr, Z.rp, Z.ci, Z.v);
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(hb, bcnt, sizeof(hb), hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
-    launch_fill<128, 64, kWPB>(hb[0], brows + 0 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
-    launch_fill<512, 256, kWPB>(hb[1], brows + 1 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
-    launch_fill<2048, 1024, kWPB>(hb[2], brows + 2 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
-    launch_fill<8192, 4096, 1>(hb[3], brows + 3 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<128, 64, kWPB>(hb[0], brows2 + 0 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<512, 256, kWPB>(hb[1], brows2 + 1 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<2048, 1024, kWPB>(hb[2], brows2 + 2 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
+    launch_fill<8192, 4096, 1>(hb[3], brows2 + 3 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
     if (hb[4] > 0) {
         std::vector<int32_t> rows(hb[4]);
         std::vector<int32_t> zrp(nr + 1);
-        HIPC(hipMemcpy(rows.data(), brows + 4 * (size_t)nr, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost));
+        HIPC(hipMemcpy(rows.data(), brows2 + 4 * (size_t)nr, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost));
         HIPC(hipMemcpy(zrp.data(), Z.rp, sizeof(int32_t) * (nr + 1), hipMemcpyDeviceToHost));
         std::vector<int32_t> gts;
         std::vector<int64_t> gio, gdo;

@@ -149,6 +149,43 @@ def test_galerkin_exact_integer(camg):
         assert np.array_equal(C[2], Co[2]) and np.array_equal(C[3], Co[3])
 
 
+def test_galerkin_rows_beyond_the_lds_tables(camg):
+    """A row of A P with more distinct columns than the largest LDS hash table
+    (16384 slots) and more entries than the largest LDS fill bin takes the
+    global-table symbolic and fill passes; the product still equals the
+    oracle's entry by entry (integer data, so exactly)."""
+    print("[gpu] galerkin with a 20001-column row", flush=True)
+    n = 20001
+    # arrow matrix: point 0 coupled to every other point
+    rp = np.zeros(n + 1, np.int32)
+    rp[1] = n
+    rp[2:] = n + 2 * np.arange(1, n)
+    ci = np.empty(rp[-1], np.int32)
+    v = np.empty(rp[-1])
+    ci[:n] = np.arange(n)
+    v[:n] = -1.0
+    v[0] = 2.0 * n
+    ci[n::2] = 0
+    ci[n + 1::2] = np.arange(1, n)
+    v[n::2] = -1.0
+    v[n + 1::2] = 4.0
+    A = (n, n, rp, ci, v)
+    # P: every point to itself, and points 1.. also to coarse point (i % 7)
+    prp = np.zeros(n + 1, np.int32)
+    pci, pv = [], []
+    for i in range(n):
+        cols = sorted({i % 7, 7 + i}) if i else [7]
+        pci += cols
+        pv += [1.0 if c >= 7 else 2.0 for c in cols]
+        prp[i + 1] = len(pci)
+    P = (n, n + 7, prp, np.array(pci, np.int32), np.array(pv))
+    C = camg.camg_galerkin(A, P)
+    Co = O.galerkin(A, P)
+    assert np.array_equal(C[2], Co[2]) and np.array_equal(C[3], Co[3])
+    assert np.array_equal(C[4], Co[4])
+    assert np.diff(C[2]).max() > 16384
+
+
 def test_single_level_and_tiny(camg):
     for A in [PB.poisson2d(1), PB.poisson2d(3), PB.poisson2d(16)]:
         b = PB.rhs(A.n)
