@@ -1126,10 +1126,11 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
                                                          int32_t *flags) {
     constexpr int Q = CAP / 64;
     __shared__ double Ms[WPB][MAXM * (MAXM + 1) / 2];
-    __shared__ double zs[WPB][CAP <= 256 ? 1 : CAP];  // scattered gradient (large candidate sets)
     __shared__ double es[WPB][MAXM], ys[WPB][MAXM];
     __shared__ int Ps[WPB][MAXM], pends[WPB][MAXM];
-    __shared__ int cbuf[WPB][3][CAP];
+    // candidates (C), then two work lists (T, N) that the scattered gradient
+    // of the large tiers reuses as CAP doubles once the candidates are merged
+    __shared__ __align__(16) int cbuf[WPB][3][CAP];
     __shared__ int bad[WPB];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * WPB + w;
@@ -1144,7 +1145,7 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
     }
     FSAI_SYNC();
     double psi_prev = 0.0;
-    double zr[Q];
+    double zr[CAP <= 256 ? Q : 1];  // the small tier's gradient, one candidate per lane and slot
     for (int k = 0;; ++k) {
         // 1. local system A(P, P) y = e_last; row r of the local matrix from
         //    row P[r] of A, matched against P[0..r]
@@ -1190,7 +1191,8 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
                 nk += tot;
             }
             FSAI_SYNC();
-            int *sw = C; C = T; T = sw;
+            for (int t = lane; t < nk; t += 64) C[t] = T[t];
+            FSAI_SYNC();
             nC = nk;
         }
         for (int a = 0; a < npend; ++a) {
@@ -1221,7 +1223,8 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
                     T[idx + afsai_below(C, nC, x)] = x;
                 }
                 FSAI_SYNC();
-                int *sw = C; C = T; T = sw;
+                for (int t = lane; t < nC + nN; t += 64) C[t] = T[t];
+                FSAI_SYNC();
                 nC += nN;
             }
         }
@@ -1253,7 +1256,7 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
                 zr[q] = sz;
             }
         } else {
-            double *z = zs[w];
+            double *z = reinterpret_cast<double *>(cbuf[w][1]);  // over T and N
             for (int t = lane; t < nC; t += 64) z[t] = 0.0;
             FSAI_SYNC();
             for (int r = 0; r < m; ++r) {
@@ -1270,30 +1273,40 @@ __global__ void __launch_bounds__(WPB * 64) k_afsai_rows(int n, const int32_t *_
                 }
                 FSAI_SYNC();
             }
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int idx = lane + 64 * q;
-                zr[q] = idx < nC ? z[idx] : 0.0;
-            }
         }
         // 4. the `step` largest |z_j| > 0 join P (smaller j on ties: C is ascending)
+        double *zl = reinterpret_cast<double *>(cbuf[w][1]);  // the large tiers' gradient
         for (int a = 0; a < step; ++a) {
             unsigned long long best = 0;
             int bidx = INT_MAX;
+            if constexpr (CAP <= 256) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(zr[q]));
-                if (bits > best) {
-                    best = bits;
-                    bidx = lane + 64 * q;
+                for (int q = 0; q < Q; ++q) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(zr[q]));
+                    if (bits > best) {
+                        best = bits;
+                        bidx = lane + 64 * q;
+                    }
+                }
+            } else {
+                for (int idx = lane; idx < nC; idx += 64) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(zl[idx]));
+                    if (bits > best) {
+                        best = bits;
+                        bidx = idx;
+                    }
                 }
             }
             const unsigned long long top = xi_max<64>(best, nullptr, lane);
             if (top == 0) break;
             const int widx = wave_min_i(best == top ? bidx : INT_MAX);
+            if constexpr (CAP <= 256) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (lane + 64 * q == widx) zr[q] = 0.0;
+                for (int q = 0; q < Q; ++q)
+                    if (lane + 64 * q == widx) zr[q] = 0.0;
+            } else if (lane == 0) {
+                zl[widx] = 0.0;
+            }
             if (lane == 0) {
                 const int j = C[widx];
                 int r = m;
