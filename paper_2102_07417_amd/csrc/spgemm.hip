@@ -85,21 +85,26 @@ __global__ void k_offset_rp(int m, const int32_t *rp, int64_t base, int32_t *out
 // atomic per block and bin.
 // Rows with at most kThrX entries of X and kThrP products are formed by one
 // thread each (k_sym_thread / k_fill_thread) and left out of the bins.
+// A thread's merge is a chain of dependent loads, hidden only when many
+// rows run at once: products of fewer rows than kThrMinRows give every row
+// a wavefront of the binned kernels instead (the same sums in the same
+// order either way).  `thrp` is kThrP, or -1 when no row is a thread row.
 constexpr int kThrX = 16;
 constexpr int64_t kThrP = 256;
+constexpr int kThrMinRows = 262144;
 
-__device__ __forceinline__ bool thread_row(const CsrView &X, const int64_t *prod, int i) {
-    return X.rp[i + 1] - X.rp[i] <= kThrX && prod[i] <= kThrP;
+__device__ __forceinline__ bool thread_row(const CsrView &X, const int64_t *prod, int i, int64_t thrp) {
+    return X.rp[i + 1] - X.rp[i] <= kThrX && prod[i] <= thrp;
 }
 
 __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int nb, const int64_t *lim, int32_t *bcnt,
-                           int32_t *brows, int stride, CsrView X, const int64_t *prod) {
+                           int32_t *brows, int stride, CsrView X, const int64_t *prod, int64_t thrp) {
     __shared__ int lcnt[8], lbase[8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (threadIdx.x < 8) lcnt[threadIdx.x] = 0;
     __syncthreads();
     int b = -1, off = 0;
-    if (i < nr && !thread_row(X, prod, i)) {
+    if (i < nr && !thread_row(X, prod, i, thrp)) {
         const int64_t x = val ? val[i] : (int64_t)(rpv[i + 1] - rpv[i]);
         b = 0;
         while (b < nb - 1 && x > lim[b]) ++b;
@@ -116,10 +121,10 @@ __global__ void k_bin_rows(int nr, const int64_t *val, const int32_t *rpv, int n
 // ascending order of X's entries and their products added one at a time
 // from 0.0 -- the order of the wavefront kernels.
 template <bool FILL>
-__global__ void __launch_bounds__(256) k_thread_rows(int nr, CsrView X, CsrView Y, const int64_t *prod, int32_t *cnt,
-                                                     const int32_t *zrp, int32_t *zci, double *zv) {
+__global__ void __launch_bounds__(256) k_thread_rows(int nr, CsrView X, CsrView Y, const int64_t *prod, int64_t thrp,
+                                                     int32_t *cnt, const int32_t *zrp, int32_t *zci, double *zv) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr || !thread_row(X, prod, i)) return;
+    if (i >= nr || !thread_row(X, prod, i, thrp)) return;
     const int e0 = X.rp[i], m = X.rp[i + 1] - e0;
     int pos[kThrX], end[kThrX], head[kThrX];
     double xv[kThrX];
@@ -434,8 +439,10 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     HIPC(hipMemcpyAsync(lim, sym_lim_h, sizeof(sym_lim_h), hipMemcpyHostToDevice, s));
     HIPC(hipMemsetAsync(bcnt, 0, sizeof(int32_t) * NB, s));
     HIPC(hipMemsetAsync(ovf, 0, sizeof(int32_t), s));
-    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr, xv, prod);
-    k_thread_rows<false><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, cnt, nullptr, nullptr, nullptr);
+    const int64_t thrp = nr >= kThrMinRows ? kThrP : -1;
+    k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, prod, nullptr, NB, lim, bcnt, brows, nr, xv, prod, thrp);
+    if (thrp >= 0)
+        k_thread_rows<false><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, thrp, cnt, nullptr, nullptr, nullptr);
     HIPC(hipGetLastError());
     int32_t hbs[NB];  // rows per symbolic bin
     HIPC(hipMemcpyAsync(hbs, bcnt, sizeof(hbs), hipMemcpyDeviceToHost, s));
@@ -463,7 +470,8 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
         scan_i32_to_i64(cnt, rp64, nr, tmp, s);
         narrow_i64(rp64, Z.rp, nr, s);  // checked against 2^31 - 1 below, before use
         HIPC(hipMemsetAsync(bcnt2, 0, sizeof(int32_t) * NB, s));
-        k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, flim, bcnt2, brows2, nr, xv, prod);
+        k_bin_rows<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, nullptr, Z.rp, NB, flim, bcnt2, brows2, nr, xv, prod,
+                                                       thrp);
         HIPC(hipGetLastError());
         HIPC(hipMemcpyAsync(&nnz, rp64 + nr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPC(hipMemcpyAsync(&hovf, ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -511,7 +519,8 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
     Z.v = out.alloc<double>(padded(nnz));
 
     // 4. fill
-    k_thread_rows<true><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, nullptr, Z.rp, Z.ci, Z.v);
+    if (thrp >= 0)
+        k_thread_rows<true><<<nblk(nr, 256), 256, 0, s>>>(nr, xv, yv, prod, thrp, nullptr, Z.rp, Z.ci, Z.v);
     HIPC(hipGetLastError());
     launch_fill<128, 64, kWPB>(hb[0], brows2 + 0 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
     launch_fill<512, 256, kWPB>(hb[1], brows2 + 1 * (size_t)nr, xv, yv, Z.rp, Z.ci, Z.v, s);
