@@ -212,7 +212,7 @@ void validate_input(Hier &h, int n, int64_t nnz, const Csr &A, int32_t *tpos, Po
     HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (hf[0]) fail(CAMG_E_CSR, "row pointer is not 0-based and non-decreasing up to nnz");
-    validate_rows(n, A.rp, A.ci, A.v, flags, amax, s);
+    validate_rows(n, nnz, A.rp, A.ci, A.v, flags, amax, s);
     HIPC(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     if (hf[1]) fail(CAMG_E_CSR, "column index out of range or not strictly increasing within a row");
@@ -455,8 +455,8 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         // finds no undecided point and changes nothing); rounds counts those
         // that started with undecided points
         while (hund > 0) {
-            pmis_round(nl, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und, s);
-            pmis_round(nl, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und + 1, s);
+            pmis_round(nl, nz, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und, s);
+            pmis_round(nl, nz, L.A.rp, L.A.ci, L.strong, tpos, L.stcnt, u, L.cf, newc, und + 1, s);
             int32_t hu[2];
             HIPC(hipMemcpyAsync(hu, und, sizeof(hu), hipMemcpyDeviceToHost, s));
             HIPC(hipStreamSynchronize(s));
@@ -483,7 +483,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         double *btv = nullptr;
         int bmax = 0;
         if (prm.interp == CAMG_INTERP_DIRECT) {
-            interp_count(nl, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
+            interp_count(nl, nz, L.A.rp, L.A.ci, L.strong, L.cf, pcnt, s);
         } else if (prm.interp == CAMG_INTERP_BAMG) {
             btci = lt.alloc<int32_t>((size_t)nl * nt);
             btv = lt.alloc<double>((size_t)nl * nt);
@@ -511,7 +511,7 @@ void build_hierarchy(Hier &h, int n, const int32_t *rp, const int32_t *ci, const
         P.ci = h.pool.alloc<int32_t>(padded(P.nnz));
         P.v = h.pool.alloc<double>(padded(P.nnz));
         if (prm.interp == CAMG_INTERP_DIRECT) {
-            interp_fill(nl, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
+            interp_fill(nl, nz, L.A.rp, L.A.ci, L.A.v, L.strong, L.cf, cmap, P.rp, P.ci, P.v, s);
         } else if (prm.interp == CAMG_INTERP_BAMG) {
             bamg_compact(nl, nt, btci, btv, P, s);
             // the next level's test space: the rows at the C points

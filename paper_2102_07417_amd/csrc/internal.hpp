@@ -206,7 +206,7 @@ void narrow_i64(const int64_t *v64, int32_t *rp32, int n, hipStream_t s);
 // flags[2]: non-finite value; flags[3]: diagonal missing; flags[4]: asymmetric;
 // flags[5]: non-positive diagonal.
 void validate_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags, hipStream_t s);
-void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
+void validate_rows(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
                    unsigned long long *amax_bits, hipStream_t s);
 void validate_sym(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
                   const unsigned long long *amax_bits, int32_t *flags, int32_t *tpos, hipStream_t s);
@@ -217,13 +217,13 @@ void strength(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const do
 // every point is C or F
 void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *u, int8_t *state,
                int32_t *undecided, hipStream_t s);
-void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
-                const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc, int32_t *undecided,
-                hipStream_t s);
+void pmis_round(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                const int32_t *tpos, const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc,
+                int32_t *undecided, hipStream_t s);
 void cf_flags(int n, const int8_t *cf, int32_t *isc, hipStream_t s);
-void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
-                  int32_t *cnt, hipStream_t s);
-void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+void interp_count(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                  const int8_t *cf, int32_t *cnt, hipStream_t s);
+void interp_fill(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
                  const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s);
 // The paper's classical, extended+i and hybrid interpolations
 // (variant = CAMG_INTERP_*): per-row bound of the candidate list (returns

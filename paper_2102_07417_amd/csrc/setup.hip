@@ -147,33 +147,6 @@ __global__ void k_val_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *fla
     if (i < n && rp[i + 1] < rp[i]) atomicOr(&flags[0], 1);
 }
 
-__global__ void k_val_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
-                           unsigned long long *amax) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int bad_col = 0, bad_val = 0, has_diag = 1, bad_diag = 0;
-    double m = 0.0;
-    if (i < n) {
-        has_diag = 0;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int c = ci[e];
-            if (c < 0 || c >= n || (e > rp[i] && c <= ci[e - 1])) bad_col = 1;
-            const double a = v[e];
-            if (!isfinite(a)) bad_val = 1;
-            else if (fabs(a) > m) m = fabs(a);
-            if (c == i) {
-                has_diag = 1;
-                if (!(a > 0.0)) bad_diag = 1;
-            }
-        }
-    }
-    if (bad_col) atomicOr(&flags[1], 1);
-    if (bad_val) atomicOr(&flags[2], 1);
-    if (!has_diag) atomicOr(&flags[3], 1);
-    if (bad_diag) atomicOr(&flags[5], 1);
-    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(m));
-    if (threadIdx.x == 0) fold_max(amax, bm);
-}
-
 // ---- per-row set-up work with G lanes per row (G a power of two <= 64):
 // lane sl of a row's group takes the row's entries sl, sl + G, ..., so the
 // group's loads are coalesced.  Whole groups run every loop and shuffle
@@ -186,6 +159,37 @@ __device__ __forceinline__ int group_row(int n, int &sl) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     sl = (int)(t & (G - 1));
     return (int)(t / G);
+}
+
+// Column range and order, finite values, a positive diagonal, and the
+// largest |a_ij| (for the symmetry tolerance), checked with G lanes per row.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_val_rows_g(int n, const int32_t *rp, const int32_t *ci, const double *v,
+                                                       int32_t *flags, unsigned long long *amax) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
+    int bad_col = 0, bad_val = 0, diag = 0, bad_diag = 0;
+    double m = 0.0;
+    for (int e = e0 + sl; e < e1; e += G) {
+        const int c = ci[e];
+        if (c < 0 || c >= n || (e > e0 && c <= ci[e - 1])) bad_col = 1;
+        const double a = v[e];
+        if (!isfinite(a)) bad_val = 1;
+        else if (fabs(a) > m) m = fabs(a);
+        if (c == i) {
+            diag = 1;
+            if (!(a > 0.0)) bad_diag = 1;
+        }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) diag |= __shfl_xor(diag, o, G);
+    if (bad_col) atomicOr(&flags[1], 1);
+    if (bad_val) atomicOr(&flags[2], 1);
+    if (i < n && sl == 0 && !diag) atomicOr(&flags[3], 1);
+    if (bad_diag) atomicOr(&flags[5], 1);
+    const unsigned long long bm = block_max_u64<kBlock>((unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) fold_max(amax, bm);
 }
 
 // tpos[e] = position of entry (j, i) in row j for entry e = (i, j); checks
@@ -362,45 +366,149 @@ __device__ __forceinline__ bool key_gt(const int32_t *cnt, const uint64_t *u, in
     return a > b;
 }
 
+// ---------------------------------------------------------------- PMIS rounds, G lanes per row
 // Selection: undecided i joins the new C set if its measure beats every
 // undecided neighbour in S_i u S_i^T (state as at the start of the round).
-__global__ void k_pmis_select(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
-                              const int32_t *tpos, const int32_t *stcnt, const uint64_t *u, const int8_t *state,
-                              int8_t *newc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int8_t sel = 0;
-    if (state[i] == kU) {
-        sel = 1;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int j = ci[e];
-            if (j == i || state[j] != kU) continue;
-            const int te = tpos[e];
-            if (!(strong[e] || (te >= 0 && strong[te]))) continue;
-            if (key_gt(stcnt, u, j, i)) { sel = 0; break; }
-        }
+// Whether some neighbour beats i does not depend on the order it is found in.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_pmis_select_g(int n, const int32_t *rp, const int32_t *ci,
+                                                          const uint8_t *strong, const int32_t *tpos,
+                                                          const int32_t *stcnt, const uint64_t *u,
+                                                          const int8_t *state, int8_t *newc) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const bool und = i < n && state[i] == kU;
+    const int e0 = und ? rp[i] : 0, e1 = und ? rp[i + 1] : 0;
+    int beaten = 0;
+    for (int e = e0 + sl; e < e1 && !beaten; e += G) {
+        const int j = ci[e];
+        if (j == i || state[j] != kU) continue;
+        const int te = tpos[e];
+        if (!(strong[e] || (te >= 0 && strong[te]))) continue;
+        if (key_gt(stcnt, u, j, i)) beaten = 1;
     }
-    newc[i] = sel;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) beaten |= __shfl_xor(beaten, o, G);
+    if (i < n && sl == 0) newc[i] = (und && !beaten) ? 1 : 0;
 }
 
 // Update: new C points become C; undecided points that depend strongly on
 // a new C point become F.
-__global__ void k_pmis_update(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
-                              const int8_t *newc, int8_t *state, int32_t *undecided) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int und = 0;
-    if (i < n && state[i] == kU) {
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_pmis_update_g(int n, const int32_t *rp, const int32_t *ci,
+                                                          const uint8_t *strong, const int8_t *newc, int8_t *state,
+                                                          int32_t *undecided) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const bool und = i < n && state[i] == kU;
+    const bool look = und && !newc[i];
+    const int e0 = look ? rp[i] : 0, e1 = look ? rp[i + 1] : 0;
+    int f = 0;
+    for (int e = e0 + sl; e < e1 && !f; e += G)
+        if (strong[e] && newc[ci[e]]) f = 1;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, G);
+    int left = 0;
+    if (und && sl == 0) {
         if (newc[i]) state[i] = kC;
-        else {
-            int f = 0;
-            for (int e = rp[i]; e < rp[i + 1]; ++e)
-                if (strong[e] && newc[ci[e]]) { f = 1; break; }
-            if (f) state[i] = kF;
-            else und = 1;
+        else if (f) state[i] = kF;
+        else left = 1;
+    }
+    const long long bu = block_sum_ll<kBlock>(left);
+    if (threadIdx.x == 0) fold_any(undecided, (int32_t)bu);
+}
+
+// ---------------------------------------------------------------- direct interpolation, G lanes per row
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_interp_count_g(int n, const int32_t *rp, const int32_t *ci,
+                                                           const uint8_t *strong, const int8_t *cf, int32_t *cnt) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const bool frow = i < n && cf[i] != kC;
+    const int e0 = frow ? rp[i] : 0, e1 = frow ? rp[i + 1] : 0;
+    int c = 0;
+    for (int e = e0 + sl; e < e1; e += G)
+        if (strong[e] && cf[ci[e]] == kC) ++c;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
+    if (i < n && sl == 0) cnt[i] = frow ? c : 1;
+}
+
+// C row: a single 1 at cmap(i).  F row: w_ij = -(alpha_i a_ij) / d_i over
+// C_i^S, d_i = a_ii + positive off-diagonals, alpha_i = (sum of negative
+// off-diagonals) / (sum over C_i^S of a_ij).  The lanes read G entries at a
+// time; every lane then adds the G terms in CSR order, so each of the three
+// sums is the chain a single thread walking the row would form, and the
+// weights go out in CSR order at ranks taken from a ballot.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_interp_fill_g(int n, const int32_t *rp, const int32_t *ci,
+                                                          const double *v, const uint8_t *strong, const int8_t *cf,
+                                                          const int64_t *cmap, const int32_t *prp, int32_t *pci,
+                                                          double *pv) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const bool isc = i < n && cf[i] == kC;
+    int o = i < n ? prp[i] : 0;
+    if (isc && sl == 0) {
+        pci[o] = (int32_t)cmap[i];
+        pv[o] = 1.0;
+    }
+    const bool frow = i < n && !isc && prp[i + 1] != o;
+    const int e0 = frow ? rp[i] : 0, e1 = frow ? rp[i + 1] : 0;
+    double d = 0.0;
+    int hd = 0;
+    for (int e = e0 + sl; e < e1; e += G)
+        if (ci[e] == i) {
+            d = v[e];
+            hd = 1;
+        }
+#pragma unroll
+    for (int q = G / 2; q > 0; q >>= 1) {  // the diagonal from the lane that read it
+        const int oh = __shfl_xor(hd, q, G);
+        const double od = __shfl_xor(d, q, G);
+        if (oh) {
+            d = od;
+            hd = 1;
         }
     }
-    const long long bu = block_sum_ll<kBlock>(und);
-    if (threadIdx.x == 0) fold_any(undecided, (int32_t)bu);
+    double num = 0.0, den = 0.0;
+    for (int c = e0; c < e1; c += G) {
+        const int e = c + sl;
+        double a = 0.0;
+        int kind = 0;  // bit 0: positive off-diagonal, bit 1: negative off-diagonal, bit 2: in C_i^S
+        if (e < e1) {
+            const int j = ci[e];
+            a = v[e];
+            if (j != i) kind = a > 0.0 ? 1 : (a < 0.0 ? 2 : 0);
+            if (strong[e] && cf[j] == kC) kind |= 4;
+        }
+        const int cnt = min(G, e1 - c);
+        for (int k = 0; k < cnt; ++k) {
+            const double ak = __shfl(a, k, G);
+            const int kk = __shfl(kind, k, G);
+            if (kk & 1) d = d + ak;
+            else if (kk & 2) num = num + ak;
+            if (kk & 4) den = den + ak;
+        }
+    }
+    const double alpha = num / den;
+    const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    for (int c = e0; c < e1; c += G) {
+        const int e = c + sl;
+        int j = 0, sc = 0;
+        if (e < e1) {
+            j = ci[e];
+            sc = strong[e] && cf[j] == kC;
+        }
+        const unsigned long long g = (__ballot(sc) >> gbase) & gmask;
+        if (sc) {
+            const int r = o + __popcll(g & ((1ull << sl) - 1));
+            pci[r] = (int32_t)cmap[j];
+            pv[r] = -(alpha * v[e]) / d;
+        }
+        o += __popcll(g);
+    }
 }
 
 __global__ void k_cf_flags(int n, const int8_t *cf, int32_t *isc) {
@@ -409,53 +517,6 @@ __global__ void k_cf_flags(int n, const int8_t *cf, int32_t *isc) {
 }
 
 // ---------------------------------------------------------------- direct interpolation
-__global__ void k_interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
-                               const int8_t *cf, int32_t *cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = 0;
-    if (cf[i] == kC) c = 1;
-    else
-        for (int e = rp[i]; e < rp[i + 1]; ++e)
-            if (strong[e] && cf[ci[e]] == kC) ++c;
-    cnt[i] = c;
-}
-
-// C row: a single 1 at cmap(i).  F row: w_ij = -(alpha_i a_ij) / d_i over
-// C_i^S, d_i = a_ii + positive off-diagonals, alpha_i = (sum of negative
-// off-diagonals) / (sum over C_i^S of a_ij); sums in CSR order.
-__global__ void k_interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
-                              const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int o = prp[i];
-    if (cf[i] == kC) {
-        pci[o] = (int32_t)cmap[i];
-        pv[o] = 1.0;
-        return;
-    }
-    if (prp[i + 1] == o) return;
-    const int e0 = rp[i], e1 = rp[i + 1];
-    double d = 0.0, num = 0.0, den = 0.0;
-    for (int e = e0; e < e1; ++e)
-        if (ci[e] == i) d = v[e];
-    for (int e = e0; e < e1; ++e) {
-        if (ci[e] == i) continue;
-        const double a = v[e];
-        if (a > 0.0) d = d + a;
-        else if (a < 0.0) num = num + a;
-    }
-    for (int e = e0; e < e1; ++e)
-        if (strong[e] && cf[ci[e]] == kC) den = den + v[e];
-    const double alpha = num / den;
-    for (int e = e0; e < e1; ++e)
-        if (strong[e] && cf[ci[e]] == kC) {
-            pci[o] = (int32_t)cmap[ci[e]];
-            pv[o] = -(alpha * v[e]) / d;
-            ++o;
-        }
-}
-
 // ---------------------------------------------------------------- transpose
 __global__ void k_col_count(int64_t nnz, const int32_t *ci, int32_t *cnt) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -475,16 +536,19 @@ __global__ void k_transpose_fill(int nr, const int32_t *rp, const int32_t *ci, c
 }
 
 // rows of the transpose come out of k_transpose_fill in arbitrary order and
-// are sorted by column: rows of at most kSortShort entries by one thread
+// are sorted by column: rows of at most `smax` entries by one thread
 // (insertion sort), rows of at most kSortWave by a wavefront, longer ones by
-// a workgroup (k_sort_rows_block); the longer two rank the entries
-constexpr int kSortShort = 32, kSortWave = 1024, kSortBlockLds = 8192;
+// a workgroup (k_sort_rows_block); the longer two rank the entries.  smax
+// is kSortShort when the transpose has at least kSortThreadRows rows, else
+// 1: a thread's sort is a chain of dependent loads, hidden only when many
+// rows run at once.
+constexpr int kSortShort = 32, kSortWave = 1024, kSortBlockLds = 8192, kSortThreadRows = 131072;
 
-__global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
+__global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v, int smax) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr) return;
     const int e0 = rp[i], e1 = rp[i + 1];
-    if (e1 - e0 > kSortShort) return;
+    if (e1 - e0 > smax) return;
     for (int e = e0 + 1; e < e1; ++e) {
         const int c = ci[e];
         const double x = v[e];
@@ -499,17 +563,17 @@ __global__ void k_sort_rows(int nr, const int32_t *rp, int32_t *ci, double *v) {
     }
 }
 
-// one wavefront per row of kSortShort < length <= kSortWave entries: the
+// one wavefront per row of smax < length <= kSortWave entries: the
 // row is staged in LDS and every entry moves to its rank (the columns of a
 // row are distinct)
-__global__ void __launch_bounds__(256) k_sort_rows_wave(int nr, const int32_t *rp, int32_t *ci, double *v) {
+__global__ void __launch_bounds__(256) k_sort_rows_wave(int nr, const int32_t *rp, int32_t *ci, double *v, int smax) {
     __shared__ int kc[4][kSortWave];
     __shared__ double kv[4][kSortWave];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int i = blockIdx.x * 4 + w;
     if (i >= nr) return;
     const int e0 = rp[i], L = rp[i + 1] - e0;
-    if (L <= kSortShort || L > kSortWave) return;
+    if (L <= smax || L > kSortWave) return;
     for (int t = lane; t < L; t += kWave) {
         kc[w][t] = ci[e0 + t];
         kv[w][t] = v[e0 + t];
@@ -2967,9 +3031,10 @@ void validate_rowptr(int n, int64_t nnz, const int32_t *rp, int32_t *flags, hipS
     k_val_rowptr<<<nblocks(n), kBlock, 0, s>>>(n, nnz, rp, flags);
     HIPC(hipGetLastError());
 }
-void validate_rows(int n, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
+void validate_rows(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, int32_t *flags,
                    unsigned long long *amax, hipStream_t s) {
-    k_val_rows<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, flags, amax);
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_val_rows_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, flags, amax)));
     HIPC(hipGetLastError());
 }
 void validate_sym(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
@@ -2996,26 +3061,39 @@ void pmis_init(int n, const int32_t *stcnt, uint64_t seed, int level, uint64_t *
     k_pmis_init<<<nblocks(n), kBlock, 0, s>>>(n, stcnt, seed, level, u, state, undecided);
     HIPC(hipGetLastError());
 }
-void pmis_round(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int32_t *tpos,
-                const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc, int32_t *undecided,
-                hipStream_t s) {
-    k_pmis_select<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, tpos, stcnt, u, state, newc);
+// Lanes per row of a PMIS round: about eight entries per lane.  Most rows
+// are decided after the first rounds and leave at once, so wider groups
+// mostly add wavefronts that do nothing (measured on strength + PMIS: one
+// lane per entry took 1.6x as long on 7-point rows, one lane per row 1.7x
+// as long on 81-entry rows).
+inline int pmis_lanes(int n, int64_t nnz) { return std::max(1, group_lanes(n, nnz) / 8); }
+void pmis_round(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                const int32_t *tpos, const int32_t *stcnt, const uint64_t *u, int8_t *state, int8_t *newc,
+                int32_t *undecided, hipStream_t s) {
+    const int g = pmis_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_pmis_select_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, strong, tpos, stcnt, u,
+                                                                                 state, newc)));
     HIPC(hipMemsetAsync(undecided, 0, sizeof(int32_t), s));
-    k_pmis_update<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, newc, state, undecided);
+    CAMG_G_SWITCH(g, (k_pmis_update_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, strong, newc, state,
+                                                                                 undecided)));
     HIPC(hipGetLastError());
 }
 void cf_flags(int n, const int8_t *cf, int32_t *isc, hipStream_t s) {
     k_cf_flags<<<nblocks(n), kBlock, 0, s>>>(n, cf, isc);
     HIPC(hipGetLastError());
 }
-void interp_count(int n, const int32_t *rp, const int32_t *ci, const uint8_t *strong, const int8_t *cf,
-                  int32_t *cnt, hipStream_t s) {
-    k_interp_count<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, strong, cf, cnt);
+void interp_count(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const uint8_t *strong,
+                  const int8_t *cf, int32_t *cnt, hipStream_t s) {
+    const int g = group_lanes(n, nnz);
+    CAMG_G_SWITCH(g, (k_interp_count_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, strong, cf, cnt)));
     HIPC(hipGetLastError());
 }
-void interp_fill(int n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
+void interp_fill(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *strong,
                  const int8_t *cf, const int64_t *cmap, const int32_t *prp, int32_t *pci, double *pv, hipStream_t s) {
-    k_interp_fill<<<nblocks(n), kBlock, 0, s>>>(n, rp, ci, v, strong, cf, cmap, prp, pci, pv);
+    // three ordered sums as long as the row whatever G is (see diag_gershgorin)
+    const int g = std::min(group_lanes(n, nnz), kOrderedLanes);
+    CAMG_G_SWITCH(g, (k_interp_fill_g<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, rp, ci, v, strong, cf, cmap, prp,
+                                                                                 pci, pv)));
     HIPC(hipGetLastError());
 }
 void column_counts(const Csr &X, int32_t *cnt, hipStream_t s) {
@@ -3044,8 +3122,9 @@ void transpose_csr(const Csr &X, Csr &XT, Pool &tmp, hipStream_t s) {
         HIPC(hipMemcpyAsync(sv, XT.v, sizeof(double) * X.nnz, hipMemcpyDeviceToDevice, s));
         k_sort_rows_block<<<nlong, 1024, 0, s>>>(list, XT.rp, sci, sv, XT.ci, XT.v);
     }
-    k_sort_rows<<<nblocks(nc), kBlock, 0, s>>>(nc, XT.rp, XT.ci, XT.v);
-    k_sort_rows_wave<<<(nc + 3) / 4, 256, 0, s>>>(nc, XT.rp, XT.ci, XT.v);
+    const int smax = nc >= kSortThreadRows ? kSortShort : 1;
+    if (smax > 1) k_sort_rows<<<nblocks(nc), kBlock, 0, s>>>(nc, XT.rp, XT.ci, XT.v, smax);
+    k_sort_rows_wave<<<(nc + 3) / 4, 256, 0, s>>>(nc, XT.rp, XT.ci, XT.v, smax);
     HIPC(hipGetLastError());
 }
 void diag_gershgorin(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, double *dinv,

@@ -44,15 +44,20 @@ struct CsrView {
     const double *v;
 };
 
+// prod[i] = number of products of row i of X Y, G lanes per row of X
+template <int G>
 __global__ void k_row_products(int nr, CsrView X, CsrView Y, int64_t *prod) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    int64_t p = 0;
-    for (int e = X.rp[i]; e < X.rp[i + 1]; ++e) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), sl = (int)(t & (G - 1));
+    const int e0 = i < nr ? X.rp[i] : 0, e1 = i < nr ? X.rp[i + 1] : 0;
+    long long p = 0;
+    for (int e = e0 + sl; e < e1; e += G) {
         const int k = X.ci[e];
         p += Y.rp[k + 1] - Y.rp[k];
     }
-    prod[i] = p;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) p += __shfl_xor(p, o, G);
+    if (i < nr && sl == 0) prod[i] = p;
 }
 
 // first and last column of every row (INT_MAX / -1 for an empty row)
@@ -388,6 +393,16 @@ __global__ void __launch_bounds__(64) k_fill_glb(int nrows, const int32_t *rows,
 
 inline int nblk(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// k_row_products with lanes per row matched to X's mean row length
+void row_products(int nr, int64_t nnz, const CsrView &X, const CsrView &Y, int64_t *prod, hipStream_t s) {
+    if (nr <= 0) return;
+    const double mean = (double)nnz / nr;
+    if (mean > 16) k_row_products<32><<<nblk((int64_t)nr * 32, kBlock), kBlock, 0, s>>>(nr, X, Y, prod);
+    else if (mean > 4) k_row_products<8><<<nblk((int64_t)nr * 8, kBlock), kBlock, 0, s>>>(nr, X, Y, prod);
+    else k_row_products<1><<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, X, Y, prod);
+    HIPC(hipGetLastError());
+}
+
 int next_pow2(int64_t x) {
     int64_t p = 1;
     while (p < x) p <<= 1;
@@ -426,8 +441,7 @@ void spgemm(const Csr &X, const Csr &Y, Csr &Z, Pool &out, Pool &tmp, hipStream_
 
     // 1. product bounds and symbolic bins
     int64_t *prod = tmp.alloc<int64_t>(nr);
-    k_row_products<<<nblk(nr, kBlock), kBlock, 0, s>>>(nr, xv, yv, prod);
-    HIPC(hipGetLastError());
+    row_products(nr, X.nnz, xv, yv, prod, s);
 
     constexpr int NB = 5;
     const int64_t sym_lim_h[NB] = {64, 256, 1024, 4096, INT64_MAX};
@@ -577,8 +591,7 @@ void galerkin(const Csr &A, const Csr &P, const Csr &R, Csr &Ac, int64_t chunk, 
     int64_t *prod = tmp.alloc<int64_t>(std::max(nf, 1));
     int64_t *pref = tmp.alloc<int64_t>((size_t)nf + 1);
     CsrView av{A.rp, A.ci, A.v}, pv{P.rp, P.ci, P.v};
-    if (nf > 0) k_row_products<<<nblk(nf, kBlock), kBlock, 0, s>>>(nf, av, pv, prod);
-    HIPC(hipGetLastError());
+    row_products(nf, A.nnz, av, pv, prod, s);
     scan_i64(prod, pref, nf, tmp, s);
     int64_t total = 0;
     HIPC(hipMemcpyAsync(&total, pref + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
