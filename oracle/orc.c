@@ -1537,9 +1537,9 @@ void orc_destroy(orc_hier *h) {
 /*
  * Hierarchy construction, Alg. AMG Set-up, level by level from A_0 = A:
  *   - level l is the last one when n_l <= max_coarse or l = max_levels - 1
- *     (the paper's "small enough for a direct factorisation", read as a
- *     size threshold); it is also the last one when coarsening stalls
- *     (no C point, or every point C);
+ *     (the paper stops where the level is small enough to factorise
+ *     directly, read as a size threshold); it is also the last one when
+ *     coarsening stalls (no C point, or every point C);
  *   - otherwise: smoother set-up, strength, PMIS, interpolation (direct by
  *     default, or one of the paper's three), R = P^T, A_{l+1} = R (A_l P)
  *     (eq. AcDef);
