@@ -223,6 +223,40 @@ def lognormal2d(n: int, sigma: float = 2.0, seed: int = SEED_A) -> CSR:
 
 
 # ---------------------------------------------------------------------------
+# Ragged rows: a graph Laplacian with power-law degrees
+# ---------------------------------------------------------------------------
+
+def powerlaw_graph(n: int, seed: int = SEED_A, max_degree: int = 200, shift: float = 1e-2) -> CSR:
+    """Weighted graph Laplacian plus ``shift`` on the diagonal, on n nodes
+    whose out-degrees follow a power law, so rows range from a couple of
+    entries to a few hundred in one matrix (an M-matrix, diagonally dominant,
+    SPD).  Draws, in order: u ~ U[0, 1) per node, target degree
+    d_i = min(max_degree, floor(2 / (u_i + 1e-9)^0.9)); the sum(d) targets of
+    the edges, integers in [0, n), node by node; after dropping self loops
+    and merging each undirected pair {i, j} into one edge (listed by
+    ascending (min, max)), one weight U[0.1, 1) per edge."""
+    g = _rng(seed)
+    u = g.random(n)
+    d = np.minimum(max_degree, np.floor(2.0 / (u + 1e-9) ** 0.9)).astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), d)
+    dst = g.integers(0, n, size=int(d.sum()), dtype=np.int64)
+    keep = src != dst
+    lo, hi = np.minimum(src[keep], dst[keep]), np.maximum(src[keep], dst[keep])
+    key = np.unique(lo * n + hi)
+    lo, hi = key // n, key % n
+    w = 0.1 + 0.9 * g.random(key.size)
+    deg = np.bincount(lo, weights=w, minlength=n) + np.bincount(hi, weights=w, minlength=n)
+    rows = np.concatenate([lo, hi, np.arange(n)])
+    cols = np.concatenate([hi, lo, np.arange(n)])
+    vals = np.concatenate([-w, -w, deg + shift])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return CSR(n, rp.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
 # 3D linear elasticity, trilinear (Q1) hexahedra
 # ---------------------------------------------------------------------------
 

@@ -35,6 +35,9 @@ CASES = {
     "aniso3d_20": lambda: PB.aniso3d(20, 1e-3),
     "elasticity_6": lambda: PB.elasticity3d(6),
     "lognormal2d_90": lambda: PB.lognormal2d(90, 2.0),
+    # rows of 2 to several hundred entries in one matrix: lane groups of the
+    # set-up kernels see ragged rows
+    "powerlaw_graph_3000": lambda: PB.powerlaw_graph(3000),
 }
 
 

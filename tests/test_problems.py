@@ -123,3 +123,17 @@ def test_oracle_solve_fixture_is_a_natural_stop():
     assert abs(h[0] - np.linalg.norm(PB.rhs(g["n"]))) <= 1e-12 * h[0]
     assert len(g["idx"]) == g["samples"] == 4096 and np.array_equal(g["idx"], G.sample_index(g["n"]))
     assert g["true_relres"] < 1e-8 and np.all(np.isfinite(g["x"]))
+
+
+def test_powerlaw_graph_ragged_spd():
+    A = PB.powerlaw_graph(600, seed=3)
+    _check(A)
+    lens = np.diff(A.row_ptr)
+    assert lens.min() <= 8 and lens.max() >= 100  # ragged: a few to hundreds per row
+    D = dense(A)
+    off = D - np.diag(np.diag(D))
+    assert np.all(off <= 0)
+    np.testing.assert_allclose(np.diag(D) + off.sum(1), 1e-2, rtol=0, atol=1e-12)  # zero row sums + shift
+    assert np.linalg.eigvalsh(D).min() > 0
+    B = PB.powerlaw_graph(600, seed=3)
+    assert np.array_equal(A.val, B.val) and np.array_equal(A.col_idx, B.col_idx)
