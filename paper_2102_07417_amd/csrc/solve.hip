@@ -631,12 +631,26 @@ __global__ void __launch_bounds__(kBlock) k_pcg_check(const double *pr2, PcgStat
     }
 }
 
+// The vector kernels below need a scalar that every block sums from the
+// partials of the kernel before (thousands of them); each thread first
+// issues the loads of its first kVecAhead elements, so their latency
+// overlaps that sum.  Elements are visited in the same order either way.
+constexpr int kVecAhead = 4;
+
 // rho = sum of the post-smoothing partials, beta = rho / rho_old (0 on a
 // (re)start); p_new = z + beta p_old, streamed
 __global__ void __launch_bounds__(kBlock) k_pcg_pnew(int n, const double *__restrict__ z,
                                                      const double *__restrict__ pold, double *__restrict__ pnew,
                                                      const double *prz, PcgState *st) {
     if (st->done) return;
+    const int stride = gridDim.x * kBlock, i0 = blockIdx.x * kBlock + threadIdx.x;
+    double za[kVecAhead], pa[kVecAhead];
+#pragma unroll
+    for (int u = 0; u < kVecAhead; ++u) {
+        const int i = i0 + u * stride;
+        za[u] = i < n ? z[i] : 0.0;
+        pa[u] = i < n ? pold[i] : 0.0;
+    }
     const double rho = sum_all(prz, st->n_rz);
     const bool first = st->iter == st->restart;
     const double beta = first ? 0.0 : rho / st->rho_old;
@@ -644,8 +658,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_pnew(int n, const double *__rest
         st->rho = rho;
         st->beta = beta;
     }
-    const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) pnew[i] = z[i] + beta * pold[i];
+#pragma unroll
+    for (int u = 0; u < kVecAhead; ++u) {
+        const int i = i0 + u * stride;
+        if (i < n) pnew[i] = za[u] + beta * pa[u];
+    }
+    for (int i = i0 + kVecAhead * stride; i < n; i += stride) pnew[i] = z[i] + beta * pold[i];
 }
 
 // sigma = sum of the p.q partials; breakdown test; alpha = rho / sigma;
@@ -655,6 +673,17 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int n, const double *__re
                                                        double *__restrict__ r, const double *ppq, double *pr2,
                                                        PcgState *st, int32_t *hflag) {
     if (st->done) return;
+    const int stride = gridDim.x * kBlock, i0 = xcd_block() * kBlock + threadIdx.x;
+    double xa[kVecAhead], pa[kVecAhead], ra[kVecAhead], qa[kVecAhead];
+#pragma unroll
+    for (int u = 0; u < kVecAhead; ++u) {
+        const int i = i0 + u * stride;
+        const bool in = i < n;
+        xa[u] = in ? x[i] : 0.0;
+        pa[u] = in ? p[i] : 0.0;
+        ra[u] = in ? r[i] : 0.0;
+        qa[u] = in ? q[i] : 0.0;
+    }
     const double sigma = sum_all(ppq, st->n_pq);
     const double rho = st->rho;
     if (!(sigma > 0.0) || !(rho > 0.0)) {
@@ -668,8 +697,17 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int n, const double *__re
     }
     const double alpha = rho / sigma;
     double acc = 0.0;
-    const int stride = gridDim.x * kBlock;
-    for (int i = xcd_block() * kBlock + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int u = 0; u < kVecAhead; ++u) {
+        const int i = i0 + u * stride;
+        if (i < n) {
+            x[i] = xa[u] + alpha * pa[u];
+            const double ri = ra[u] - alpha * qa[u];
+            r[i] = ri;
+            acc += ri * ri;
+        }
+    }
+    for (int i = i0 + kVecAhead * stride; i < n; i += stride) {
         x[i] = x[i] + alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
