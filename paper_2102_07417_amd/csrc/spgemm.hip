@@ -163,18 +163,26 @@ __global__ void __launch_bounds__(256) k_thread_rows(int nr, CsrView X, CsrView 
 }
 
 // Visit the products of row i of X Y in ascending order of X's entries e:
-// for each e the lanes take the entries t of row k = X.ci[e] of Y and call
-// f(j = Y.ci[t], x = X.v[e], y = Y.v[t]); step e finishes (wavefront
-// barrier) before step e+1 starts.  The entries of X's row (column, value,
-// extent of Y's row) are loaded by all lanes at once, 64 at a time.  The
-// first 64 entries of the Y rows are loaded kAhead steps at a time, the next
-// group's while the current group's steps run, so a step rarely waits for
-// memory (rows of Y with a few entries, as in the FSAI products, made every
-// step of a one-step-ahead pipeline wait for a full load).
+// for each e the lanes take the entries t of row k = X.ci[e] of Y; each
+// product (j = Y.ci[t], x = X.v[e], y = Y.v[t]) first goes through
+// tok = pre(j, x, y), the part whose order does not matter, then through
+// post(tok, x, y), and step e's post calls finish (wavefront barrier)
+// before step e+1's start (when ORDERED).  The entries of X's row (column,
+// value, extent of Y's row) are loaded by all lanes at once, 64 at a time.
+// Steps go in groups of four.  When each of a group's four Y rows has at
+// most 16 entries, lane 16 d + t takes entry t of the group's step d, the
+// pre calls of the four steps run at once and the post calls step by step;
+// otherwise the group's steps run one at a time, the lanes taking the first
+// 64 entries of the step's Y row (and the rest in further passes).  The
+// loads of the next group (one entry per lane when it is packed, else the
+// first 64 entries of each of its four Y rows) are issued while the current
+// group runs, so a step rarely waits for memory.
 constexpr int kAhead = 4;
-template <class F>
-__device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrView &Y, int lane, F f) {
+template <bool ORDERED, class Pre, class Post>
+__device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrView &Y, int lane, Pre pre,
+                                             Post post) {
     const int e0 = X.rp[i], e1 = X.rp[i + 1];
+    const int dl = lane >> 4, tl = lane & 15;  // packed groups: step and entry of this lane
     for (int cb = e0; cb < e1; cb += kWave) {
         const int ne = min(kWave, e1 - cb);
         int yb = 0, yc = 0;
@@ -185,38 +193,90 @@ __device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrV
             yb = Y.rp[k];
             yc = Y.rp[k + 1] - yb;
         }
-        // the first kWave entries of Y's row for step q (q is the same on every lane)
-        auto head = [&](int q, int &j, double &v) {
-            j = 0;
-            v = 0.0;
-            if (q < ne) {
-                const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
-                if (lane < c) {
-                    j = Y.ci[b + lane];
-                    v = Y.v[b + lane];
+        // whether the group of steps q0 .. q0+3 is packed (the same on every lane)
+        auto packed = [&](int q0) {
+            int m = 0;
+#pragma unroll
+            for (int d = 0; d < kAhead; ++d) {
+                const int q = q0 + d;
+                const int c = __shfl(yc, q & (kWave - 1), kWave);
+                if (q < ne) m = max(m, c);
+            }
+            return m <= 16;
+        };
+        // the loads of group q0: one entry per lane, or the first kWave
+        // entries of each step's Y row
+        auto load = [&](int q0, bool pk, int *jr, double *vr) {
+#pragma unroll
+            for (int d = 0; d < kAhead; ++d) {
+                jr[d] = 0;
+                vr[d] = 0.0;
+            }
+            if (pk) {
+                const int q = q0 + dl;
+                const int b = __shfl(yb, q & (kWave - 1), kWave), c = __shfl(yc, q & (kWave - 1), kWave);
+                if (q < ne && tl < c) {
+                    jr[0] = Y.ci[b + tl];
+                    vr[0] = Y.v[b + tl];
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < kAhead; ++d) {
+                    const int q = q0 + d;
+                    if (q < ne) {
+                        const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
+                        if (lane < c) {
+                            jr[d] = Y.ci[b + lane];
+                            vr[d] = Y.v[b + lane];
+                        }
+                    }
                 }
             }
         };
         int jq[kAhead];
         double vq[kAhead];
-#pragma unroll
-        for (int d = 0; d < kAhead; ++d) head(d, jq[d], vq[d]);
+        bool pk = packed(0);
+        load(0, pk, jq, vq);
         for (int q0 = 0; q0 < ne; q0 += kAhead) {
+            const bool more = q0 + kAhead < ne;
+            const bool pkn = more ? packed(q0 + kAhead) : false;
             int jn[kAhead];
             double vn[kAhead];
+            if (more) load(q0 + kAhead, pkn, jn, vn);
+            if (pk) {
+                const int q = q0 + dl;
+                const int c = __shfl(yc, q & (kWave - 1), kWave);
+                const double x = __shfl(xv, q & (kWave - 1), kWave);
+                const bool act = q < ne && tl < c;
+                int tok = 0;
+                if (act) tok = pre(jq[0], x, vq[0]);
+                if constexpr (ORDERED) {
 #pragma unroll
-            for (int d = 0; d < kAhead; ++d) head(q0 + kAhead + d, jn[d], vn[d]);
-#pragma unroll
-            for (int d = 0; d < kAhead; ++d) {
-                const int q = q0 + d;
-                if (q < ne) {
-                    const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
-                    const double x = __shfl(xv, q, kWave);
-                    if (lane < c) f(jq[d], x, vq[d]);
-                    for (int t = b + kWave + lane; t < b + c; t += kWave) f(Y.ci[t], x, Y.v[t]);
+                    for (int d = 0; d < kAhead; ++d) {
+                        if (act && dl == d) post(tok, x, vq[0]);
+                        WAVE_SYNC();
+                    }
+                } else {
                     WAVE_SYNC();
                 }
+            } else {
+#pragma unroll
+                for (int d = 0; d < kAhead; ++d) {
+                    const int q = q0 + d;
+                    if (q < ne) {
+                        const int b = __shfl(yb, q, kWave), c = __shfl(yc, q, kWave);
+                        const double x = __shfl(xv, q, kWave);
+                        if (lane < c) post(pre(jq[d], x, vq[d]), x, vq[d]);
+                        for (int t = b + kWave + lane; t < b + c; t += kWave) {
+                            const int j = Y.ci[t];
+                            const double y = Y.v[t];
+                            post(pre(j, x, y), x, y);
+                        }
+                        WAVE_SYNC();
+                    }
+                }
             }
+            pk = pkn;
 #pragma unroll
             for (int d = 0; d < kAhead; ++d) {
                 jq[d] = jn[d];
@@ -230,23 +290,29 @@ __device__ __forceinline__ void for_products(int i, const CsrView &X, const CsrV
 // new keys this lane inserted.  *overflow is set if a probe sequence wraps.
 __device__ __forceinline__ int insert_row(int i, const CsrView &X, const CsrView &Y, int *keys, int ts, int lane,
                                           bool &overflow) {
+    // the set of keys (and the count) does not depend on the order of the
+    // insertions, so no step waits for the one before
     int cnt = 0;
-    for_products(i, X, Y, lane, [&](int j, double, double) {
-        unsigned h = slot_of(j, ts);
-        for (int probe = 0;; ++probe) {
-            const int old = atomicCAS(&keys[h], kEmpty, j);
-            if (old == kEmpty) {
-                ++cnt;
-                break;
+    for_products<false>(
+        i, X, Y, lane,
+        [&](int j, double, double) {
+            unsigned h = slot_of(j, ts);
+            for (int probe = 0;; ++probe) {
+                const int old = atomicCAS(&keys[h], kEmpty, j);
+                if (old == kEmpty) {
+                    ++cnt;
+                    break;
+                }
+                if (old == j) break;
+                h = (h + 1) & (unsigned)(ts - 1);
+                if (probe >= ts) {
+                    overflow = true;
+                    break;
+                }
             }
-            if (old == j) break;
-            h = (h + 1) & (unsigned)(ts - 1);
-            if (probe >= ts) {
-                overflow = true;
-                break;
-            }
-        }
-    });
+            return 0;
+        },
+        [](int, double, double) {});
     return cnt;
 }
 
@@ -347,13 +413,15 @@ __device__ __forceinline__ void fill_row(int i, bool valid, const CsrView &X, co
         WAVE_SYNC();
         // products in ascending inner index; within a step the lanes hold
         // distinct columns
-        for_products(i, X, Y, lane, [&](int j, double x, double y) {
-            const int h = find_slot(keys, ts, j);
-            if (h >= 0) {
-                const int p = pos[h];
-                acc[p] = acc[p] + x * y;
-            }
-        });
+        for_products<true>(
+            i, X, Y, lane,
+            [&](int j, double, double) {
+                const int h = find_slot(keys, ts, j);
+                return h >= 0 ? pos[h] : -1;
+            },
+            [&](int p, double x, double y) {
+                if (p >= 0) acc[p] = acc[p] + x * y;
+            });
         const int off = zrp[i];
         for (int p = lane; p < u; p += kWave) {
             zci[off + p] = cols[p];
