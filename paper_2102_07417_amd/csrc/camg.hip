@@ -823,7 +823,7 @@ void enqueue_segment(Hier &h, int par, int seg, hipStream_t s) {
 }
 
 void destroy_graphs(Hier &h) {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         for (int p = 0; p < 2; ++p) {
             if (h.gexec[k][p]) (void)hipGraphExecDestroy(h.gexec[k][p]);
             if (h.graph[k][p]) (void)hipGraphDestroy(h.graph[k][p]);
@@ -835,15 +835,19 @@ void destroy_graphs(Hier &h) {
 
 // Capture graphs of the iteration (their kernel arguments only name buffers
 // the handle owns, so they stay valid across solves): without timing one
-// graph per parity; with timing, segments 0 and 2 as graphs, so that the
+// graph per parity, and one of two iterations (parity 0 then 1: the device
+// leaves a gap of some 13 us between two graph launches, paid once per two
+// iterations then); with timing, segments 0 and 2 as graphs, so that the
 // level-0 post-smoothing kernel can be launched between two stream events.
 void build_graphs(Hier &h) {
     destroy_graphs(h);
     if (!h.cap_stream) HIPC(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
-    auto capture = [&](int slot, int par, int s0, int s1) {
+    auto capture = [&](int slot, int par, int s0, int s1, bool two = false) {
         HIPC(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
         try {
             for (int seg = s0; seg <= s1; ++seg) enqueue_segment(h, par, seg, h.cap_stream);
+            if (two)
+                for (int seg = s0; seg <= s1; ++seg) enqueue_segment(h, 1 - par, seg, h.cap_stream);
         } catch (...) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(h.cap_stream, &g);
@@ -860,6 +864,7 @@ void build_graphs(Hier &h) {
             capture(2, p, 2, 2);
         }
     }
+    capture(3, 0, 0, 2, true);
     h.graph_ok = true;
     h.graph_prof = h.prof;
 }
@@ -919,21 +924,36 @@ void run_iterations(Hier &h, int k0, std::vector<std::pair<int, float>> &times, 
     volatile int32_t *flag = h.hflag;
     flag[0] = 0;
     int last = -1;
-    for (int k = k0; k < max_iter; ++k) {
+    // launches alternate between the two events; pk/pn: the first iteration
+    // and the number of iterations of the previous launch; iterations below
+    // `seen` have had their timings collected
+    int cur = 0, pk = -1, pn = 0, seen = k0;
+    for (int k = k0; k < max_iter;) {
         const int par = k & 1;
-        launch_iteration(h, par, timed(k), s);
-        HIPC(hipEventRecord(ev[par], s));
-        last = k;
-        if (k > k0) {
-            HIPC(hipEventSynchronize(ev[1 - par]));
-            collect(k - 1);
+        int nk = 1;
+        if (h.use_graph && h.graph_ok && par == 0 && k + 1 < max_iter && !timed(k) && !timed(k + 1)) {
+            HIPC(hipGraphLaunch(h.gexec[3][0], s));
+            nk = 2;
+        } else {
+            launch_iteration(h, par, timed(k), s);
+        }
+        HIPC(hipEventRecord(ev[cur], s));
+        last = k + nk - 1;
+        if (pk >= 0) {
+            HIPC(hipEventSynchronize(ev[1 - cur]));
+            for (int j = pk; j < pk + pn; ++j) collect(j);
+            seen = pk + pn;
             if (flag[0]) break;
         }
+        pk = k;
+        pn = nk;
+        cur = 1 - cur;
+        k += nk;
     }
     // the stopping test for the last residual formed
     pcg_check(h.pr2, h.st, h.dhist, h.dhist_cap, h.hflag_dev, s);
     HIPC(hipStreamSynchronize(s));
-    if (last >= 0) collect(last);
+    for (int j = seen; j <= last; ++j) collect(j);
 }
 
 double true_relres_of(Hier &h, const double *b, const double *x, double bnorm, double *r_out, hipStream_t s) {

@@ -182,8 +182,8 @@ struct Hier {
     bool compact_cols = true;  // row kernels read the 16-bit column differences where built
     bool graph_ok = false;
     bool graph_prof = false;
-    hipGraphExec_t gexec[3][2] = {};
-    hipGraph_t graph[3][2] = {};
+    hipGraphExec_t gexec[4][2] = {};  // [0] iteration, [1]/[2] its timed segments, [3][0] two iterations
+    hipGraph_t graph[4][2] = {};
     hipStream_t cap_stream = nullptr;
     // engines used by camg_solve_multi_dev, by slot count (owned)
     std::vector<struct Engine *> engines;
