@@ -766,26 +766,77 @@ __global__ void __launch_bounds__(512) k_cholesky_mfma(int n, double *D, int32_t
     if (tid == 0 && bad) atomicOr(&flags[5], 1);
 }
 
-// X = (L L^T)^{-1}: one wavefront per column j, forward then backward
-// substitution with the inner products split over the 64 lanes.
+// X = (L L^T)^{-1}: one wavefront per column j, whose vector lives in LDS.
+// Forward L y = e_j row by row from row j (y is zero above it), the inner
+// products split over the lanes; backward L^T x = y from the last row up,
+// each x_i then taken out of the rows above it with row i of L.  Both sweeps
+// read rows of L (contiguous), the next row's first kInvAhead * 64 entries
+// loaded while the current row is used, so a step waits for LDS and the
+// wavefront barrier rather than for memory.
+constexpr int kInvAhead = 4;
 __global__ void __launch_bounds__(64) k_chol_inverse(int n, const double *L, double *X) {
+    extern __shared__ double y[];  // n doubles
     const int j = blockIdx.x;
     const int lane = threadIdx.x;
     if (j >= n) return;
-    for (int i = 0; i < n; ++i) {
+    for (int k = lane; k < n; k += 64) y[k] = 0.0;
+    double cur[kInvAhead], nxt[kInvAhead];
+    // forward: entries k in [j, i) of row i
+    auto fwd_row = [&](int i, double *r) {
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) {
+            const int k = j + lane + 64 * m;
+            r[m] = (i < n && k < i) ? L[(int64_t)i * n + k] : 0.0;
+        }
+    };
+    fwd_row(j, cur);
+    double dcur = L[(int64_t)j * n + j];
+    __syncthreads();
+    for (int i = j; i < n; ++i) {
+        fwd_row(i + 1, nxt);
+        const double dnxt = i + 1 < n ? L[(int64_t)(i + 1) * n + i + 1] : 1.0;
         double t = 0.0;
-        for (int k = lane; k < i; k += 64) t += L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) {
+            const int k = j + lane + 64 * m;
+            if (k < i) t += cur[m] * y[k];
+        }
+        for (int k = j + lane + 64 * kInvAhead; k < i; k += 64) t += L[(int64_t)i * n + k] * y[k];
         t = wave_sum(t);
-        if (lane == 0) X[(int64_t)i * n + j] = ((i == j ? 1.0 : 0.0) - t) / L[(int64_t)i * n + i];
+        if (lane == 0) y[i] = ((i == j ? 1.0 : 0.0) - t) / dcur;
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) cur[m] = nxt[m];
+        dcur = dnxt;
     }
+    // backward: entries k in [0, i) of row i
+    auto bwd_row = [&](int i, double *r) {
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) {
+            const int k = lane + 64 * m;
+            r[m] = (i >= 0 && k < i) ? L[(int64_t)i * n + k] : 0.0;
+        }
+    };
+    bwd_row(n - 1, cur);
+    dcur = L[(int64_t)(n - 1) * n + n - 1];
     for (int i = n - 1; i >= 0; --i) {
-        double t = 0.0;
-        for (int k = i + 1 + lane; k < n; k += 64) t += L[(int64_t)k * n + i] * X[(int64_t)k * n + j];
-        t = wave_sum(t);
-        if (lane == 0) X[(int64_t)i * n + j] = (X[(int64_t)i * n + j] - t) / L[(int64_t)i * n + i];
+        bwd_row(i - 1, nxt);
+        const double dnxt = i > 0 ? L[(int64_t)(i - 1) * n + i - 1] : 1.0;
+        const double xi = y[i] / dcur;
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) {
+            const int k = lane + 64 * m;
+            if (k < i) y[k] = y[k] - cur[m] * xi;
+        }
+        for (int k = lane + 64 * kInvAhead; k < i; k += 64) y[k] = y[k] - L[(int64_t)i * n + k] * xi;
         __syncthreads();
+        if (lane == 0) y[i] = xi;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kInvAhead; ++m) cur[m] = nxt[m];
+        dcur = dnxt;
     }
+    for (int k = lane; k < n; k += 64) X[(int64_t)k * n + j] = y[k];
 }
 
 
@@ -3162,7 +3213,7 @@ void cholesky_dense(int n, double *D, int32_t *flags, hipStream_t s) {
     HIPC(hipGetLastError());
 }
 void chol_inverse(int n, const double *L, double *X, hipStream_t s) {
-    k_chol_inverse<<<n, 64, 0, s>>>(n, L, X);
+    k_chol_inverse<<<n, 64, sizeof(double) * (size_t)n, s>>>(n, L, X);
     HIPC(hipGetLastError());
 }
 void tile_starts(int n, const int32_t *rp, int W, int ntiles, int32_t *tstart, hipStream_t s) {
