@@ -2900,22 +2900,22 @@ __global__ void k_pw_start(int n, uint64_t seed, int level, double *v) {
     }
 }
 
-// y = M x, one thread per row, eight loads in flight, added in CSR order
-__global__ void k_pw_spmv(int n, const int32_t *rp, const int32_t *ci, const double *mv, const double *x, double *y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int e1 = rp[i + 1];
-    int e = rp[i];
+// y = M x with G lanes per row: the lanes form G products at a time, which
+// every lane then adds in CSR order (the sum a thread walking the row forms)
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_pw_spmv(int n, const int32_t *rp, const int32_t *ci, const double *mv,
+                                                    const double *x, double *y) {
+    int sl;
+    const int i = group_row<G>(n, sl);
+    const int e0 = i < n ? rp[i] : 0, e1 = i < n ? rp[i + 1] : 0;
     double s = 0.0;
-    for (; e + 8 <= e1; e += 8) {
-        double p[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) p[t] = mv[e + t] * x[ci[e + t]];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) s = s + p[t];
+    for (int c = e0; c < e1; c += G) {
+        const int e = c + sl;
+        const double p = e < e1 ? mv[e] * x[ci[e]] : 0.0;
+        const int cnt = min(G, e1 - c);
+        for (int k = 0; k < cnt; ++k) s = s + __shfl(p, k, G);
     }
-    for (; e < e1; ++e) s = s + mv[e] * x[ci[e]];
-    y[i] = s;
+    if (i < n && sl == 0) y[i] = s;
 }
 
 // partials of v.v, v.w, w.w (block b: part[3 b + 0..2])
@@ -3453,10 +3453,14 @@ double fsai_rayleigh(const Csr &A, const Csr &G, const Csr &Gt, uint64_t seed, i
     double *part = tmp.alloc<double>(3 * (size_t)nb), *st = tmp.alloc<double>(2);
     const unsigned g = (unsigned)nblocks(n);
     k_pw_start<<<g, kBlock, 0, s>>>(n, seed, level, v);
+    auto spmv = [&](const Csr &M, const double *x, double *y) {
+        const int gl = std::min(group_lanes(n, M.nnz), kOrderedLanes);
+        CAMG_G_SWITCH(gl, (k_pw_spmv<G><<<group_blocks(n, G), kBlock, 0, s>>>(n, M.rp, M.ci, M.v, x, y)));
+    };
     for (int k = 0; k < kFsaiPowerSteps; ++k) {
-        k_pw_spmv<<<g, kBlock, 0, s>>>(n, Gt.rp, Gt.ci, Gt.v, v, t);
-        k_pw_spmv<<<g, kBlock, 0, s>>>(n, A.rp, A.ci, A.v, t, u);
-        k_pw_spmv<<<g, kBlock, 0, s>>>(n, G.rp, G.ci, G.v, u, w);
+        spmv(Gt, v, t);
+        spmv(A, t, u);
+        spmv(G, u, w);
         k_pw_dots<<<nb, kBlock, 0, s>>>(n, v, w, part);
         k_pw_fin<<<1, kBlock, 0, s>>>(nb, part, st);
         k_pw_scale<<<g, kBlock, 0, s>>>(n, w, st, v);
