@@ -36,7 +36,12 @@ if ROOT not in sys.path:
 
 METRIC = "AMG-PCG solve time & V-cycle HBM GB/s at rtol 1e-8; FP64 vs mixed; p99 latency"
 HBM_PEAK_GBS = 8000.0
-PROFILE_STRIDE = 8
+# every PROFILE_STRIDE-th PCG iteration of a profiled solve is timed; such an
+# iteration is launched in three parts (two graphs, and the level-0 kernel
+# between events) instead of sharing a two-iteration graph, and each extra
+# launch leaves a gap of some 13 us, so one in 16 keeps the timing's cost
+# near 0.5 % of the solve while giving several timed launches per solve
+PROFILE_STRIDE = 16
 
 WORKLOADS = {
     "lognormal3d_128": "3D 7-point FV diffusion, 128^3 cells, lognormal(0,2) face coefficients, FP64 CSR, "
