@@ -285,6 +285,29 @@ def test_graph_replays_match_direct_launches(camg):
     s.close()
 
 
+def test_two_iteration_graphs_stop_at_max_iter(camg):
+    """Untimed iterations go two per graph launch: with rtol = 0 every
+    iteration count, odd or even, stops exactly at max_iter with the iterates
+    of direct launches, with and without the kernel timing that splits
+    every few iterations into single launches."""
+    A = PB.lognormal3d(16, 2.0)
+    b = PB.rhs(A.n, 3)
+    for m in [1, 2, 3, 4, 7, 8]:
+        for prof in [0, 4]:
+            s = camg.Solver(A, max_iter=m)
+            assert camg.camg_set_option(s.h, camg.OPT_GRAPH, 0) == camg.OK
+            d = s.solve(b, rtol=0.0)
+            assert camg.camg_set_option(s.h, camg.OPT_GRAPH, 1) == camg.OK
+            if prof:
+                camg.camg_profile(s.h, prof)
+            g = s.solve(b, rtol=0.0)
+            if prof:
+                camg.camg_profile(s.h, 0)
+            assert d.status == g.status == camg.E_MAXIT and d.iters == g.iters == m, (m, prof, d.iters, g.iters)
+            assert np.array_equal(d.x, g.x) and np.array_equal(d.hist, g.hist), (m, prof)
+            s.close()
+
+
 @pytest.mark.parametrize("name", ["lognormal3d_24", "elasticity_6", "aniso3d_20"])
 def test_mixed_precision_reaches_fp64_tolerance(camg, name):
     """FP32 V-cycle inside FP64 PCG: the true residual still drops below
