@@ -895,9 +895,11 @@ int launch_mrows_any(const Csr &M, const T *av, hipStream_t s, const G &g, const
     const int u = rs.u ? rs.u : G::kU;
     if (dot) {
         if (u == 4) return launch_mrows_u<T, K, true, 4>(M, av, s, g, e, partials, pmask, forced_grid, rs);
+        if (u == 7) return launch_mrows_u<T, K, true, 7>(M, av, s, g, e, partials, pmask, forced_grid, rs);
         return launch_mrows_u<T, K, true, 8>(M, av, s, g, e, partials, pmask, forced_grid, rs);
     }
     if (u == 4) return launch_mrows_u<T, K, false, 4>(M, av, s, g, e, partials, pmask, forced_grid, rs);
+    if (u == 7) return launch_mrows_u<T, K, false, 7>(M, av, s, g, e, partials, pmask, forced_grid, rs);
     return launch_mrows_u<T, K, false, 8>(M, av, s, g, e, partials, pmask, forced_grid, rs);
 }
 
@@ -1141,7 +1143,7 @@ void tune_matrix(Engine &E, const Csr &M, const T *av, const G &g, const Ep &ep,
     plain.band = E.band_of(M);  // candidates sweep in the order the runs use
     const int rule = launch_mrows_any<T, K>(M, av, s, g, ep, partials, dot, ~0ull, 0, plain);  // warm; the rule grid
     std::vector<RowSched> cand;
-    for (int u : {4, 8})
+    for (int u : {4, 7, 8})
         for (int cr : {def, std::max(RPP, def / 2 / RPP * RPP), RPP})
             for (int st : {1, 0})
                 for (int gd : {0, std::max(8, rule / 2 / 8 * 8)}) {
